@@ -1,0 +1,300 @@
+"""Seeded synthetic inputs for the black-oil Jacobian solve.
+
+This module produces *input data only*: grids, rock fields, reservoir states,
+well descriptions and fluid constants.  It contains none of the method's
+arithmetic (no properties, fluxes, Jacobians or solvers); both the FP64 CPU
+oracle and the HIP library consume what it produces, each through its own code.
+
+Randomness is counter based so that any cell's value can be regenerated on its
+own: u = (splitmix64(seed ^ (field_id << 48) ^ cell) >> 11 + 1/2) * 2^-53.
+SplitMix64 is Steele, Lea and Flood's public-domain mixer; normals come from
+the Box-Muller transform of two such uniforms.
+
+Workloads (the paper's SPE10 / CMG data are not available, so these stand in
+for them; the shapes follow the black-oil model of Section 2.1 with the
+7-point finite-difference discretisation of Section 3):
+
+The base state is 3000 psi, Sw 0.25, Sg 0.05, each with +-5% relative noise
+that is spatially correlated (seeded lattice every 8x8x4 cells, trilinear in
+between), so that neighbouring cells differ by at most a few per cent of the
+noise amplitude, as in a Newton iterate of a real run.
+
+* ``cfg 0``  20x20x5, log-normal k (ln 100 mD, sigma 1), injector and producer
+  in opposite corners, one Jacobian at the first Newton iterate.
+* ``cfg 1``  100x100x50, sinuous 1000 mD channels in a 10 mD log-normal
+  background, five-spot wells, a 10-system synthetic step sequence.
+* ``cfg 2``  200x200x50, log-normal k with sigma 2 and five 0.01 mD barrier
+  layers, five-spot wells, the same 10-system sequence.
+* ``tiny``   any small grid for pins and parity cases.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+__all__ = ["Well", "Case", "FLUID", "uniform", "normal", "make_case",
+           "tiny_case", "base_seed", "N_SYSTEMS"]
+
+N_SYSTEMS = 10
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def _splitmix64(x: np.ndarray) -> np.ndarray:
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform(seed: int, field_id: int, idx) -> np.ndarray:
+    """Counter-based U(0,1) (never exactly 0 or 1) for element ``idx`` of field ``field_id``."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    key = np.uint64(seed) ^ (np.uint64(field_id) << np.uint64(48))
+    z = _splitmix64(key ^ idx)
+    return ((z >> np.uint64(11)).astype(np.float64) + 0.5) * (2.0 ** -53)
+
+
+def normal(seed: int, field_id: int, idx) -> np.ndarray:
+    """Standard normal by Box-Muller from fields ``field_id`` and ``field_id + 1``."""
+    u1 = uniform(seed, field_id, idx)
+    u2 = uniform(seed, field_id + 1, idx)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+# Fluid and rock constants (field units).  The paper leaves these to the input
+# deck; the values are the ones every workload here uses.
+FLUID = dict(
+    p_ref=3000.0,                   # psi
+    Bw0=1.01, cw=3.0e-6,            # B_w = Bw0 (1 - cw (p - p_ref))       rb/STB
+    Bo0=1.25, co=1.0e-5,            # B_o                                  rb/STB
+    Bg0=0.95, cg=3.0e-4,            # B_g                                  rb/Mscf
+    Rs0=0.6, crs=2.0e-4,            # R_s = Rs0 (1 + crs (p - p_ref))      Mscf/STB
+    mu_w=0.5, mu_o=2.0, mu_g=0.02,  # cP
+    c_r=4.0e-6,                     # rock compressibility 1/psi
+    rho_wsc=62.4, rho_osc=53.0, rho_gsc=0.0458,  # lbm/ft3, lbm/ft3, lbm/scf
+    swc=0.2, sor=0.2, sorg=0.2, sgc=0.0,
+    nw=2, no=2, ng=2,               # Corey exponents (integers)
+    tcoef=0.001127,                 # Darcy constant, field units
+    rb_ft3=5.615,                   # ft3 per reservoir barrel
+    grav=1.0 / 144.0,               # psi per (lbm/ft3 * ft)
+)
+
+
+@dataclasses.dataclass
+class Well:
+    """A vertical well through cells (i, j, k_top..k_bot) (0-based)."""
+    i: int
+    j: int
+    k_top: int
+    k_bot: int
+    kind: str            # "inj" (water injector) or "prod"
+    control: str         # "bhp", or "wrat"/"orat"/"lrat" fixed rates
+    target: float        # BHP in psi, or rate in STB/day
+    rw: float = 0.25     # wellbore radius, ft
+    skin: float = 0.0
+
+
+@dataclasses.dataclass
+class Case:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    top_depth: float
+    kx: np.ndarray        # (N,) mD, cell g = i + nx*(j + ny*k)
+    ky: np.ndarray
+    kz: np.ndarray
+    phi0: np.ndarray      # porosity at p_ref
+    x_old: np.ndarray     # (3N,) interleaved (Po, Sw, Sg) per cell
+    x_new: np.ndarray
+    dt: float             # days
+    wells: List[Well]
+    fluid: dict
+    gravity: bool = True
+    inj_total_mobility: bool = True
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def base_seed(cfg: int) -> int:
+    return 1606000 + 100 * cfg
+
+
+# field ids
+_F_K, _F_PHI, _F_P, _F_SW, _F_SG, _F_CH = 1, 3, 4, 5, 6, 16
+
+
+def _cell_ijk(nx, ny, nz):
+    g = np.arange(nx * ny * nz, dtype=np.int64)
+    return g % nx, (g // nx) % ny, g // (nx * ny)
+
+
+NOISE_LATTICE = (8, 8, 4)
+
+
+def smooth_noise(seed, field_id, nx, ny, nz, lattice=NOISE_LATTICE) -> np.ndarray:
+    """Spatially correlated noise in [-1, 1]: i.i.d. U(-1,1) values on a coarse
+    lattice with spacing ``lattice`` cells, trilinearly interpolated to cell
+    centres."""
+    Lx, Ly, Lz = lattice
+    mx, my, mz = nx // Lx + 2, ny // Ly + 2, nz // Lz + 2
+    lat = (2.0 * uniform(seed, field_id, np.arange(mx * my * mz, dtype=np.uint64)) - 1.0).reshape(mz, my, mx)
+    i, j, k = _cell_ijk(nx, ny, nz)
+    fx, fy, fz = (i + 0.5) / Lx, (j + 0.5) / Ly, (k + 0.5) / Lz
+    ix, iy, iz = np.floor(fx).astype(np.int64), np.floor(fy).astype(np.int64), np.floor(fz).astype(np.int64)
+    tx, ty, tz = fx - ix, fy - iy, fz - iz
+    out = np.zeros(nx * ny * nz)
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                w = (tx if a else 1.0 - tx) * (ty if b else 1.0 - ty) * (tz if c else 1.0 - tz)
+                out += w * lat[iz + c, iy + b, ix + a]
+    return out
+
+
+def _noisy_state(seed, nx, ny, nz, p=3000.0, sw=0.25, sg=0.05, rel=0.05, noise="smooth"):
+    """Base state with relative noise of amplitude ``rel``.  ``smooth``: the
+    correlated field above (a physically plausible Newton state); ``iid``:
+    independent per cell."""
+    n = nx * ny * nz
+    x = np.empty(3 * n)
+    for q, (val, fid) in enumerate(((p, _F_P), (sw, _F_SW), (sg, _F_SG))):
+        if noise == "iid":
+            u = 2.0 * uniform(seed, fid, np.arange(n, dtype=np.uint64)) - 1.0
+        else:
+            u = smooth_noise(seed, fid, nx, ny, nz)
+        x[q::3] = val * (1.0 + rel * u)
+    return x
+
+
+def _porosity(seed, n, lo=0.15, hi=0.25):
+    return lo + (hi - lo) * uniform(seed, _F_PHI, np.arange(n, dtype=np.uint64))
+
+
+def _lognormal(seed, n, mean_ln, sigma):
+    return np.exp(mean_ln + sigma * normal(seed, _F_K, np.arange(n, dtype=np.uint64)))
+
+
+def _channels(seed, nx, ny, nz, kbg, nchan=12, kch=1000.0):
+    """Sinuous high-permeability channels: centreline y = y0 + a sin(2 pi x / lam + ph)."""
+    k = kbg.copy()
+    i, j, kk = _cell_ijk(nx, ny, nz)
+    for c in range(nchan):
+        u = uniform(seed, _F_CH + c, np.arange(8, dtype=np.uint64))
+        y0 = u[0] * ny
+        a = 5.0 + 10.0 * u[1]
+        lam = 30.0 + 50.0 * u[2]
+        ph = 2.0 * np.pi * u[3]
+        width = 3.0 + 3.0 * u[4]
+        thick = min(3 + int(6.0 * u[5]), 8, nz)
+        k0 = int((nz - thick + 1) * u[6])
+        yc = y0 + a * np.sin(2.0 * np.pi * (i + 0.5) / lam + ph)
+        inside = (np.abs(j + 0.5 - yc) <= 0.5 * width) & (kk >= k0) & (kk < k0 + thick)
+        k[inside] = kch
+    return k
+
+
+def _five_spot(nx, ny, nz, p_inj=3500.0, p_prod=2500.0):
+    wells = [Well(i, j, 0, nz - 1, "inj", "bhp", p_inj)
+             for (i, j) in ((0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1))]
+    wells.append(Well(nx // 2, ny // 2, 0, nz - 1, "prod", "bhp", p_prod))
+    return wells
+
+
+def _sequence_state(base, nx, ny, nz, dx, dy, wells, t):
+    """Smooth synthetic state at time t (days): pressure rises near injectors and
+    falls near the producer, a water front grows from the injectors."""
+    if t == 0.0:
+        return base.copy()
+    i, j, _ = _cell_ijk(nx, ny, nz)
+    xc, yc = (i + 0.5) * dx, (j + 0.5) * dy
+    L = 0.2 * nx * dx
+    inj = [w for w in wells if w.kind == "inj"]
+    prod = [w for w in wells if w.kind == "prod"]
+    d_inj = [np.hypot(xc - (w.i + 0.5) * dx, yc - (w.j + 0.5) * dy) for w in inj]
+    d_prod = [np.hypot(xc - (w.i + 0.5) * dx, yc - (w.j + 0.5) * dy) for w in prod]
+    shape = sum(np.exp(-d / L) for d in d_inj) - sum(np.exp(-d / L) for d in d_prod)
+    x = base.copy()
+    x[0::3] = base[0::3] + 300.0 * (1.0 - math.exp(-t / 10.0)) * shape
+    dmin = np.min(np.stack(d_inj), axis=0)
+    R = 0.3 * nx * dx * math.sqrt(t / 30.0)
+    sw0 = base[1::3]
+    x[1::3] = sw0 + (0.75 - sw0) * 0.5 * (1.0 - np.tanh((dmin - R) / (3.0 * dx)))
+    return x
+
+
+def make_case(cfg: int, system: int = 1) -> Case:
+    """The synthetic Jacobian-producing state of workload ``cfg`` (0, 1 or 2).
+
+    For cfg 0 the Jacobian is taken at the first Newton iterate
+    (x_new == x_old, dt = 1 day).  For cfg 1 and 2, ``system`` k = 1..10 takes
+    x_old = state(3(k-1) days) and x_new = state(3k days) with dt = 3 days.
+    """
+    dx, dy, dz, top = 50.0, 50.0, 10.0, 8000.0
+    if cfg == 0:
+        nx, ny, nz = 20, 20, 5
+        seed = base_seed(0)
+        n = nx * ny * nz
+        kx = _lognormal(seed, n, math.log(100.0), 1.0)
+        wells = [Well(0, 0, 0, nz - 1, "inj", "bhp", 3500.0),
+                 Well(nx - 1, ny - 1, 0, nz - 1, "prod", "bhp", 2500.0)]
+        x = _noisy_state(seed, nx, ny, nz)
+        return Case("cfg0", nx, ny, nz, dx, dy, dz, top, kx, kx.copy(), 0.1 * kx,
+                    _porosity(seed, n), x, x.copy(), 1.0, wells, dict(FLUID))
+    if cfg in (1, 2):
+        if not 1 <= system <= N_SYSTEMS:
+            raise ValueError("system must be in 1..10")
+        seed = base_seed(cfg)
+        if cfg == 1:
+            nx, ny, nz = 100, 100, 50
+            n = nx * ny * nz
+            kx = _channels(seed, nx, ny, nz, _lognormal(seed, n, math.log(10.0), 1.0))
+            kz = 0.1 * kx
+        else:
+            nx, ny, nz = 200, 200, 50
+            n = nx * ny * nz
+            kx = _lognormal(seed, n, math.log(100.0), 2.0)
+            kz = 0.1 * kx
+            layer = np.arange(n) // (nx * ny)
+            bar = np.isin(layer, (8, 17, 26, 35, 44))
+            kx[bar] = 0.01
+            kz[bar] = 0.01
+        wells = _five_spot(nx, ny, nz)
+        base = _noisy_state(seed, nx, ny, nz)
+        x_old = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * (system - 1))
+        x_new = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * system)
+        return Case(f"cfg{cfg}.{system}", nx, ny, nz, dx, dy, dz, top, kx, kx.copy(), kz,
+                    _porosity(seed, n), x_old, x_new, 3.0, wells, dict(FLUID))
+    raise ValueError(f"unknown workload {cfg}")
+
+
+def tiny_case(nx: int, ny: int, nz: int, seed: int = 7, *, sigma: float = 1.0,
+              noise: float = 0.05, noise_kind: str = "smooth", wells: Optional[List[Well]] = None,
+              dt: float = 1.0, step: float = 0.0, gravity: bool = True,
+              kz_ratio: float = 0.1) -> Case:
+    """A small seeded case.  ``step`` > 0 perturbs x_new away from x_old
+    (relative, uniform) so that accumulation terms are active."""
+    n = nx * ny * nz
+    kx = _lognormal(seed, n, math.log(100.0), sigma)
+    if wells is None:
+        wells = [Well(0, 0, 0, nz - 1, "inj", "bhp", 3500.0),
+                 Well(nx - 1, ny - 1, 0, nz - 1, "prod", "bhp", 2500.0)]
+    x_old = _noisy_state(seed, nx, ny, nz, rel=noise, noise=noise_kind)
+    x_new = x_old.copy()
+    if step > 0.0:
+        x_new = x_old * (1.0 + step * (2.0 * uniform(seed + 1, 30, np.arange(3 * n, dtype=np.uint64)) - 1.0))
+    return Case(f"tiny{nx}x{ny}x{nz}", nx, ny, nz, 50.0, 50.0, 10.0, 8000.0, kx, kx.copy(),
+                kz_ratio * kx, _porosity(seed, n), x_old, x_new, dt, wells, dict(FLUID),
+                gravity=gravity)

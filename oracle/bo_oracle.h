@@ -1,0 +1,174 @@
+/*
+ * FP64 CPU oracle for the fully implicit black-oil Jacobian solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow reference that
+ * the GPU library is checked against.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark load it; the product path never does.  It
+ * shares no code, header or table with the GPU library.
+ *
+ * What it computes (Liu, Shen, Wang, Yang, Chen, "Numerical Simulation of
+ * Multi-phase Flow in Porous Media on Parallel Computers"):
+ *   - the black-oil residual of Section 2.1 (three components, Darcy fluxes,
+ *     Peaceman wells of Section 2.3 with fixed bottom-hole pressure), discretised
+ *     by the 7-point finite-difference scheme of Section 3, and its analytic
+ *     Jacobian as 3x3 blocks;
+ *   - the quasi-IMPES decoupling operator of Section 3.2 and the pressure block;
+ *   - an aggregation AMG standing in for BoomerAMG on the pressure block;
+ *   - block ILU(0) (the RAS local solver of Section 3.2) and block Jacobi;
+ *   - the CPR two-stage preconditioner (PF) and Algorithm "CPR-FPF";
+ *   - restarted flexible GMRES (the Krylov method named in Section 3.3);
+ *   - dense LU with partial pivoting for exact solutions of tiny systems.
+ *
+ * Parity status per function is documented beside it.
+ *
+ * Conventions: cells are numbered g = i + nx*(j + ny*k); vectors are 3N long
+ * and interleave (Po, Sw, Sg) per cell; residual rows are ordered (oil, water,
+ * gas); 3x3 blocks are row-major (row = equation, column = unknown); BSR rows
+ * hold ascending column indices.  All arithmetic is IEEE double without
+ * contraction (built with -ffp-contract=off).
+ */
+#ifndef BO_ORACLE_H
+#define BO_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_OK = 0, OR_NOT_CONVERGED = 1, OR_ERR_ARG = -1, OR_ERR_ALLOC = -3,
+       OR_ERR_NONFINITE = -4, OR_ERR_SINGULAR_BLOCK = -5, OR_ERR_SINGULAR_COARSE = -6 };
+
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz, top_depth;
+    const double *kx, *ky, *kz, *phi0;      /* N each */
+    /* fluid and rock */
+    double p_ref, Bw0, cw, Bo0, co, Bg0, cg, Rs0, crs;
+    double mu_w, mu_o, mu_g, c_r;
+    double rho_wsc, rho_osc, rho_gsc;
+    double swc, sor, sorg, sgc;
+    int nw, no, ng;
+    double tcoef, rb_ft3, grav;
+    int gravity;               /* 0: potentials without the density term */
+    int inj_total_mobility;    /* 1: water injectors use the cell's total mobility */
+    /* wells: nwells entries each */
+    int nwells;
+    const int32_t *w_i, *w_j, *w_ktop, *w_kbot, *w_inj, *w_ctrl; /* ctrl 0 = fixed BHP */
+    const double *w_target, *w_rw, *w_skin;
+} or_problem;
+
+/* Relative permeabilities (Section 2.1; Stone II for oil).  out[0..5] =
+ * krw, krow, krg, krog, kro, and out[5] = dkro/dSw, out[6] = dkro/dSg. */
+void or_relperm(const or_problem *p, double sw, double sg, double *out);
+
+/* Geometry: transmissibility of the face between cells a and b (adjacent),
+ * pore volume of cell g at pressure pr, Peaceman well index of cell g. */
+double or_transmissibility(const or_problem *p, int a, int b);
+double or_pore_volume(const or_problem *p, int g, double pr);
+double or_well_index(const or_problem *p, int g, double rw, double skin);
+
+/* BSR pattern of the 7-point stencil: returns nnzb; fills rowptr (N+1) and
+ * colind (nnzb) when they are not NULL. */
+int or_pattern(const or_problem *p, int32_t *rowptr, int32_t *colind);
+
+/* Residual R (3N) of the discrete black-oil equations at x_new with old state
+ * x_old; when val != NULL also the analytic Jacobian dR/dx_new into the BSR
+ * values on the pattern of or_pattern.  Returns OR_OK or an error code. */
+int or_assemble(const or_problem *p, const double *x_old, const double *x_new, double dt,
+                double *R, const int32_t *rowptr, const int32_t *colind, double *val);
+
+/* Flux-only residual (no accumulation, no wells): used for conservation pins. */
+int or_flux_residual(const or_problem *p, const double *x, double *R);
+
+/* y = alpha*A*x + beta*y for a BSR matrix with bs x bs blocks (beta == 0 ignores y). */
+void or_bsr_spmv(int n, int bs, const int32_t *rowptr, const int32_t *colind, const double *val,
+                 double alpha, const double *x, double beta, double *y);
+
+/* Dense LU with partial pivoting: solves A x = b in place (A row-major n x n,
+ * b overwritten by x).  Returns OR_ERR_SINGULAR_BLOCK for a zero pivot. */
+int or_dense_solve(int n, double *A, double *b);
+
+/* Quasi-IMPES decoupling (Section 3.2).  Per cell the decoupled pressure row
+ * is c_i . (oil, water, gas rows) with c_i = s_i (1, -w_i), s_i = +-1 chosen so
+ * that the decoupled pressure diagonal is positive.  Outputs c (3N) and the
+ * pressure block App (values on the BSR pattern, nnzb doubles).
+ * mode OR_QI_DIAG: D_ps and D_ss are the pointwise diagonals of the cell's
+ *   blocks, w_i = (a_o,Sw / a_w,Sw, a_o,Sg / a_g,Sg);
+ * mode OR_QI_BLOCK: D_ss is the cell's 2x2 saturation block, w_i = a_ps a_ss^{-1}. */
+enum { OR_QI_DIAG = 0, OR_QI_BLOCK = 1 };
+int or_qi_decouple(int n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                   int mode, double *c, double *app);
+
+/* ---- CPR preconditioner and FGMRES ---------------------------------- */
+enum { OR_F_BJ = 0, OR_F_ILU_NATURAL = 1, OR_F_ILU_RB = 2, OR_F_ILU_TILED = 3 };
+enum { OR_SMOOTH_GS = 0, OR_SMOOTH_JACOBI = 1 };
+
+typedef struct {
+    int fpf;              /* 0: two-stage PF, 1: Algorithm CPR-FPF */
+    int ftype;            /* OR_F_* */
+    int tile_x, tile_y;   /* tiled ILU0 */
+    double theta;         /* strength threshold */
+    int coarse_max, max_levels;
+    int smoother;         /* OR_SMOOTH_* on level 0 (levels >= 1: damped Jacobi) */
+    int sweeps;           /* pre = post sweeps */
+    int use_amg;          /* 0: pressure stage skipped (F only) */
+    int qi_mode;          /* OR_QI_DIAG or OR_QI_BLOCK */
+} or_cpr_opts;
+
+typedef struct or_cpr or_cpr;
+
+/* Builds decoupling weights, the AMG hierarchy and the F-stage factors.  nx,ny,nz
+ * describe the grid (needed for red-black and tiled orderings, and for the
+ * level-0 smoother colouring). */
+int or_cpr_setup(const or_problem *p, int n, const int32_t *rowptr, const int32_t *colind,
+                 const double *val, const or_cpr_opts *o, or_cpr **out);
+void or_cpr_free(or_cpr *c);
+/* z = M^{-1} v (3N). */
+int or_cpr_apply(or_cpr *c, const double *v, double *z);
+/* Individual stages for parity tests. */
+int or_cpr_restrict(or_cpr *c, const double *v, double *rp);        /* rp_i = c_i . v_i (N) */
+int or_cpr_vcycle(or_cpr *c, const double *b, double *x);           /* one V-cycle, level 0 */
+int or_cpr_fstage(or_cpr *c, const double *r, double *x);           /* F(r) (3N) */
+
+/* Hierarchy introspection. */
+int or_amg_nlevels(or_cpr *c);
+/* n, nnz of level l matrix; nnz of P_l (0 for the coarsest); number of colours. */
+void or_amg_level_info(or_cpr *c, int l, int *n, int *nnz, int *pnnz, int *ncolors, double *omega);
+/* Copies level-l data out (any pointer may be NULL). */
+void or_amg_level_get(or_cpr *c, int l, int32_t *rowptr, int32_t *colind, double *val,
+                      int32_t *agg, int32_t *color, int32_t *prowptr, int32_t *pcolind, double *pval,
+                      int32_t *strong_rowptr, int32_t *strong_colind);
+/* MIS-2 members of level l (1 = aggregate root), n bytes. */
+void or_amg_level_roots(or_cpr *c, int l, uint8_t *root);
+/* Decoupling rows c (3N) and F-stage pivot inverses (N*9, for ILU: inverses of U_ii). */
+void or_cpr_get(or_cpr *c, double *cw, double *fpiv_inv);
+
+typedef struct {
+    int m, maxit;
+    double rtol;
+    int orth;             /* 0: modified Gram-Schmidt, 1: classical GS with one re-orthogonalisation */
+} or_fgmres_opts;
+
+typedef struct {
+    int iterations, restarts, converged;
+    double rel_residual;      /* true ||b - A x|| / ||b|| */
+    double est_residual;      /* last |g_{j+1}| / ||b|| */
+} or_fgmres_stats;
+
+/* Right-preconditioned flexible GMRES(m) on the BSR system (x in: x0, out: x).
+ * pc may be NULL (no preconditioner).  hist (optional, maxit+1) receives the
+ * estimated relative residual after each iteration. */
+int or_fgmres(int n, const int32_t *rowptr, const int32_t *colind, const double *val,
+              or_cpr *pc, const double *b, double *x, const or_fgmres_opts *o,
+              or_fgmres_stats *st, double *hist);
+
+/* FGMRES returning the Arnoldi quantities of its first cycle (for the
+ * Arnoldi-relation pin): Z (m x 3N), V ((m+1) x 3N), H ((m+1) x m, row-major,
+ * before rotations).  Runs exactly k <= m steps without restart. */
+int or_arnoldi(int n, const int32_t *rowptr, const int32_t *colind, const double *val,
+               or_cpr *pc, const double *b, int k, int orth, double *Z, double *V, double *H);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,30 @@
+/* Oracle (test infrastructure only): aggregation AMG hierarchy. */
+#ifndef OR_AMG_H
+#define OR_AMG_H
+#include <stdint.h>
+#include "or_internal.h"
+
+#define OR_MAXLEV 16
+#define OR_DENSE_MAX 2000
+
+typedef struct {
+    int nlev;
+    or_csr A[OR_MAXLEV];        /* level operators */
+    or_csr P[OR_MAXLEV];        /* prolongation level l+1 -> l */
+    or_csr R[OR_MAXLEV];        /* restriction P^T */
+    int32_t *agg[OR_MAXLEV];    /* aggregate of each node (-1: unaggregated) */
+    uint8_t *sf[OR_MAXLEV];     /* strength flag per entry of A[l] */
+    uint8_t *root[OR_MAXLEV];   /* MIS-2 members (aggregate roots) */
+    int32_t *color[OR_MAXLEV];  /* red-black colours, level 0 only */
+    int ncolor[OR_MAXLEV];
+    double omega[OR_MAXLEV];
+    double *dense;              /* coarsest matrix, row-major, when solved directly */
+    int coarse_direct;
+    int smoother, sweeps;
+} or_amg;
+
+int or_amg_setup(or_amg *h, const or_csr *A0, int nx, int ny, int nz, double theta,
+                 int coarse_max, int max_levels, int smoother, int sweeps);
+void or_amg_vcycle(const or_amg *h, const double *b, double *x);
+void or_amg_free(or_amg *h);
+#endif

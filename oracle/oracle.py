@@ -1,0 +1,374 @@
+"""ctypes wrapper of the FP64 CPU oracle (test infrastructure only).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg use this
+module.  It never imports the GPU library, and the GPU library never imports
+it.  Inputs come from :mod:`bo_casegen`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+OR_OK, OR_NOT_CONVERGED = 0, 1
+F_BJ, F_ILU_NATURAL, F_ILU_RB, F_ILU_TILED = 0, 1, 2, 3
+QI_DIAG, QI_BLOCK = 0, 1
+SMOOTH_GS, SMOOTH_JACOBI = 0, 1
+
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class OrProblem(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("top_depth", C.c_double),
+        ("kx", _dp), ("ky", _dp), ("kz", _dp), ("phi0", _dp),
+        ("p_ref", C.c_double), ("Bw0", C.c_double), ("cw", C.c_double), ("Bo0", C.c_double),
+        ("co", C.c_double), ("Bg0", C.c_double), ("cg", C.c_double), ("Rs0", C.c_double),
+        ("crs", C.c_double),
+        ("mu_w", C.c_double), ("mu_o", C.c_double), ("mu_g", C.c_double), ("c_r", C.c_double),
+        ("rho_wsc", C.c_double), ("rho_osc", C.c_double), ("rho_gsc", C.c_double),
+        ("swc", C.c_double), ("sor", C.c_double), ("sorg", C.c_double), ("sgc", C.c_double),
+        ("nw", C.c_int), ("no", C.c_int), ("ng", C.c_int),
+        ("tcoef", C.c_double), ("rb_ft3", C.c_double), ("grav", C.c_double),
+        ("gravity", C.c_int), ("inj_total_mobility", C.c_int),
+        ("nwells", C.c_int),
+        ("w_i", _ip), ("w_j", _ip), ("w_ktop", _ip), ("w_kbot", _ip), ("w_inj", _ip), ("w_ctrl", _ip),
+        ("w_target", _dp), ("w_rw", _dp), ("w_skin", _dp),
+    ]
+
+
+class CprOpts(C.Structure):
+    _fields_ = [("fpf", C.c_int), ("ftype", C.c_int), ("tile_x", C.c_int), ("tile_y", C.c_int),
+                ("theta", C.c_double), ("coarse_max", C.c_int), ("max_levels", C.c_int),
+                ("smoother", C.c_int), ("sweeps", C.c_int), ("use_amg", C.c_int), ("qi_mode", C.c_int)]
+
+
+class FgmresOpts(C.Structure):
+    _fields_ = [("m", C.c_int), ("maxit", C.c_int), ("rtol", C.c_double), ("orth", C.c_int)]
+
+
+class FgmresStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("rel_residual", C.c_double), ("est_residual", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b  # type: ignore
+        _b.build()
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER(OrProblem)
+    L.or_relperm.argtypes = [P, C.c_double, C.c_double, _f64p]
+    L.or_transmissibility.argtypes = [P, C.c_int, C.c_int]
+    L.or_transmissibility.restype = C.c_double
+    L.or_pore_volume.argtypes = [P, C.c_int, C.c_double]
+    L.or_pore_volume.restype = C.c_double
+    L.or_well_index.argtypes = [P, C.c_int, C.c_double, C.c_double]
+    L.or_well_index.restype = C.c_double
+    L.or_pattern.argtypes = [P, C.c_void_p, C.c_void_p]
+    L.or_assemble.argtypes = [P, _f64p, _f64p, C.c_double, _f64p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.or_flux_residual.argtypes = [P, _f64p, _f64p]
+    L.or_bsr_spmv.argtypes = [C.c_int, C.c_int, _i32p, _i32p, _f64p, C.c_double, _f64p, C.c_double, _f64p]
+    L.or_bsr_spmv.restype = None
+    L.or_dense_solve.argtypes = [C.c_int, _f64p, _f64p]
+    L.or_qi_decouple.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _f64p, _f64p]
+    L.or_cpr_setup.argtypes = [C.c_void_p, C.c_int, _i32p, _i32p, _f64p, C.POINTER(CprOpts), C.POINTER(C.c_void_p)]
+    L.or_cpr_free.argtypes = [C.c_void_p]
+    L.or_cpr_free.restype = None
+    for f in ("or_cpr_apply", "or_cpr_restrict", "or_cpr_vcycle", "or_cpr_fstage"):
+        getattr(L, f).argtypes = [C.c_void_p, _f64p, _f64p]
+    L.or_amg_nlevels.argtypes = [C.c_void_p]
+    L.or_amg_level_info.argtypes = [C.c_void_p, C.c_int] + [C.POINTER(C.c_int)] * 4 + [C.POINTER(C.c_double)]
+    L.or_amg_level_info.restype = None
+    L.or_amg_level_get.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 10
+    L.or_amg_level_get.restype = None
+    L.or_amg_level_roots.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
+    L.or_amg_level_roots.restype = None
+    L.or_cpr_get.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.or_cpr_get.restype = None
+    L.or_fgmres.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _f64p, _f64p,
+                            C.POINTER(FgmresOpts), C.POINTER(FgmresStats), C.c_void_p]
+    L.or_arnoldi.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _f64p, C.c_int, C.c_int,
+                             _f64p, _f64p, _f64p]
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class Problem:
+    """Keeps the numpy arrays of a case alive behind an ``OrProblem``."""
+
+    def __init__(self, case):
+        f = case.fluid
+        self.case = case
+        self._keep = []
+
+        def d(a):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            self._keep.append(a)
+            return _ptr(a, C.c_double)
+
+        def i(a):
+            a = np.ascontiguousarray(a, dtype=np.int32)
+            self._keep.append(a)
+            return _ptr(a, C.c_int32)
+
+        W = case.wells
+        s = OrProblem()
+        s.nx, s.ny, s.nz = case.nx, case.ny, case.nz
+        s.dx, s.dy, s.dz, s.top_depth = case.dx, case.dy, case.dz, case.top_depth
+        s.kx, s.ky, s.kz, s.phi0 = d(case.kx), d(case.ky), d(case.kz), d(case.phi0)
+        for k in ("p_ref", "Bw0", "cw", "Bo0", "co", "Bg0", "cg", "Rs0", "crs", "mu_w", "mu_o",
+                  "mu_g", "c_r", "rho_wsc", "rho_osc", "rho_gsc", "swc", "sor", "sorg", "sgc",
+                  "tcoef", "rb_ft3", "grav"):
+            setattr(s, k, float(f[k]))
+        s.nw, s.no, s.ng = int(f["nw"]), int(f["no"]), int(f["ng"])
+        s.gravity = int(case.gravity)
+        s.inj_total_mobility = int(case.inj_total_mobility)
+        s.nwells = len(W)
+        s.w_i = i([w.i for w in W] or [0])
+        s.w_j = i([w.j for w in W] or [0])
+        s.w_ktop = i([w.k_top for w in W] or [0])
+        s.w_kbot = i([w.k_bot for w in W] or [0])
+        s.w_inj = i([1 if w.kind == "inj" else 0 for w in W] or [0])
+        s.w_ctrl = i([0 if w.control == "bhp" else 1 for w in W] or [0])
+        s.w_target = d([w.target for w in W] or [0.0])
+        s.w_rw = d([w.rw for w in W] or [0.25])
+        s.w_skin = d([w.skin for w in W] or [0.0])
+        self.s = s
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def relperm(prob: Problem, sw: float, sg: float) -> dict:
+    out = np.zeros(9)
+    lib().or_relperm(prob.ref, sw, sg, out)
+    return dict(krw=out[0], krow=out[1], krg=out[2], krog=out[3], kro=out[4],
+                dkro_dsw=out[5], dkro_dsg=out[6], dkrw=out[7], dkrg=out[8])
+
+
+def transmissibility(prob: Problem, a: int, b: int) -> float:
+    return lib().or_transmissibility(prob.ref, a, b)
+
+
+def pore_volume(prob: Problem, g: int, p: float) -> float:
+    return lib().or_pore_volume(prob.ref, g, p)
+
+
+def well_index(prob: Problem, g: int, rw: float = 0.25, skin: float = 0.0) -> float:
+    return lib().or_well_index(prob.ref, g, rw, skin)
+
+
+def pattern(prob: Problem):
+    L = lib()
+    nnzb = L.or_pattern(prob.ref, None, None)
+    n = prob.case.n
+    rp = np.zeros(n + 1, np.int32)
+    ci = np.zeros(nnzb, np.int32)
+    L.or_pattern(prob.ref, rp.ctypes.data, ci.ctypes.data)
+    return rp, ci
+
+
+def residual(prob: Problem, x_old=None, x_new=None, dt=None) -> np.ndarray:
+    c = prob.case
+    x_old = np.ascontiguousarray(c.x_old if x_old is None else x_old, dtype=np.float64)
+    x_new = np.ascontiguousarray(c.x_new if x_new is None else x_new, dtype=np.float64)
+    R = np.zeros(3 * c.n)
+    st = lib().or_assemble(prob.ref, x_old, x_new, c.dt if dt is None else dt, R, None, None, None)
+    if st != OR_OK:
+        raise RuntimeError(f"or_assemble failed: {st}")
+    return R
+
+
+def jacobian(prob: Problem, x_old=None, x_new=None, dt=None):
+    """Returns (rowptr, colind, val (nnzb,3,3), R)."""
+    c = prob.case
+    x_old = np.ascontiguousarray(c.x_old if x_old is None else x_old, dtype=np.float64)
+    x_new = np.ascontiguousarray(c.x_new if x_new is None else x_new, dtype=np.float64)
+    rp, ci = pattern(prob)
+    val = np.zeros(9 * len(ci))
+    R = np.zeros(3 * c.n)
+    st = lib().or_assemble(prob.ref, x_old, x_new, c.dt if dt is None else dt, R,
+                           rp.ctypes.data, ci.ctypes.data, val.ctypes.data)
+    if st != OR_OK:
+        raise RuntimeError(f"or_assemble failed: {st}")
+    return rp, ci, val.reshape(-1, 3, 3), R
+
+
+def flux_residual(prob: Problem, x=None) -> np.ndarray:
+    c = prob.case
+    x = np.ascontiguousarray(c.x_new if x is None else x, dtype=np.float64)
+    R = np.zeros(3 * c.n)
+    lib().or_flux_residual(prob.ref, x, R)
+    return R
+
+
+def bsr_spmv(rp, ci, val, x, alpha=1.0, beta=0.0, y=None, bs=3) -> np.ndarray:
+    n = len(rp) - 1
+    y = np.zeros(bs * n) if y is None else np.array(y, dtype=np.float64, copy=True)
+    lib().or_bsr_spmv(n, bs, rp, ci, np.ascontiguousarray(val, dtype=np.float64).reshape(-1),
+                      alpha, np.ascontiguousarray(x, dtype=np.float64), beta, y)
+    return y
+
+
+def dense_solve(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    A = np.array(A, dtype=np.float64, order="C", copy=True)
+    x = np.array(b, dtype=np.float64, copy=True)
+    st = lib().or_dense_solve(A.shape[0], A, x)
+    if st != OR_OK:
+        raise RuntimeError("singular")
+    return x
+
+
+def qi_decouple(rp, ci, val, mode=1):
+    """Returns (c (3N), App (nnzb))."""
+    n = len(rp) - 1
+    w = np.zeros(3 * n)
+    app = np.zeros(len(ci))
+    st = lib().or_qi_decouple(n, rp, ci, np.ascontiguousarray(val, dtype=np.float64).reshape(-1), mode, w, app)
+    if st != OR_OK:
+        raise RuntimeError(f"or_qi_decouple failed: {st}")
+    return w, app
+
+
+def cpr_opts(fpf=0, ftype=F_ILU_TILED, tile=(8, 8), theta=0.08, coarse_max=256, max_levels=12,
+             smoother=SMOOTH_GS, sweeps=1, use_amg=1, qi_mode=QI_BLOCK) -> CprOpts:
+    return CprOpts(fpf, ftype, tile[0], tile[1], theta, coarse_max, max_levels, smoother,
+                   sweeps, use_amg, qi_mode)
+
+
+class Cpr:
+    """Oracle CPR preconditioner handle."""
+
+    def __init__(self, prob: Optional[Problem], rp, ci, val, opts: Optional[CprOpts] = None, **kw):
+        self.rp = np.ascontiguousarray(rp, dtype=np.int32)
+        self.ci = np.ascontiguousarray(ci, dtype=np.int32)
+        self.val = np.ascontiguousarray(val, dtype=np.float64).reshape(-1)
+        self.n = len(self.rp) - 1
+        self.opts = opts if opts is not None else cpr_opts(**kw)
+        h = C.c_void_p()
+        st = lib().or_cpr_setup(C.addressof(prob.s) if prob is not None else None, self.n,
+                                self.rp, self.ci, self.val, C.byref(self.opts), C.byref(h))
+        self.status = st
+        if st != OR_OK:
+            raise RuntimeError(f"or_cpr_setup failed: {st}")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().or_cpr_free(h)
+            self.h = None
+
+    def _call(self, f, v, m):
+        out = np.zeros(m)
+        st = getattr(lib(), f)(self.h, np.ascontiguousarray(v, dtype=np.float64), out)
+        if st != OR_OK:
+            raise RuntimeError(f"{f} failed: {st}")
+        return out
+
+    def apply(self, v):
+        return self._call("or_cpr_apply", v, 3 * self.n)
+
+    def restrict(self, v):
+        return self._call("or_cpr_restrict", v, self.n)
+
+    def vcycle(self, b):
+        return self._call("or_cpr_vcycle", b, self.n)
+
+    def fstage(self, r):
+        return self._call("or_cpr_fstage", r, 3 * self.n)
+
+    def weights(self):
+        w = np.zeros(3 * self.n)
+        lib().or_cpr_get(self.h, w.ctypes.data, None)
+        return w
+
+    def pivots(self):
+        p = np.zeros(9 * self.n)
+        lib().or_cpr_get(self.h, None, p.ctypes.data)
+        return p.reshape(-1, 3, 3)
+
+    def nlevels(self) -> int:
+        return lib().or_amg_nlevels(self.h)
+
+    def level(self, l: int) -> dict:
+        n, nnz, pnnz, nc = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        om = C.c_double()
+        lib().or_amg_level_info(self.h, l, C.byref(n), C.byref(nnz), C.byref(pnnz), C.byref(nc), C.byref(om))
+        n, nnz, pnnz = n.value, nnz.value, pnnz.value
+        rp = np.zeros(n + 1, np.int32); ci = np.zeros(nnz, np.int32); v = np.zeros(nnz)
+        agg = np.full(n, -2, np.int32); col = np.zeros(n, np.int32)
+        prp = np.zeros(n + 1, np.int32); pci = np.zeros(max(pnnz, 1), np.int32); pv = np.zeros(max(pnnz, 1))
+        srp = np.zeros(n + 1, np.int32); sci = np.zeros(max(nnz, 1), np.int32)
+        lib().or_amg_level_get(self.h, l, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, agg.ctypes.data,
+                               col.ctypes.data, prp.ctypes.data, pci.ctypes.data, pv.ctypes.data,
+                               srp.ctypes.data, sci.ctypes.data)
+        out = dict(n=n, nnz=nnz, rowptr=rp, colind=ci, val=v, color=col, ncolors=nc.value,
+                   omega=om.value, strong_rowptr=srp, strong_colind=sci[:srp[-1]])
+        if pnnz > 0:
+            root = np.zeros(n, np.uint8)
+            lib().or_amg_level_roots(self.h, l, root.ctypes.data)
+            out.update(agg=agg, p_rowptr=prp, p_colind=pci[:pnnz], p_val=pv[:pnnz], root=root.astype(bool))
+        return out
+
+
+def fgmres(rp, ci, val, b, pc: Optional[Cpr] = None, x0=None, m=30, maxit=1500, rtol=1e-6,
+           orth=1, history=False):
+    n = len(rp) - 1
+    x = np.zeros(3 * n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    o = FgmresOpts(m, maxit, rtol, orth)
+    st = FgmresStats()
+    hist = np.zeros(maxit + 1)
+    rc = lib().or_fgmres(n, np.ascontiguousarray(rp, np.int32), np.ascontiguousarray(ci, np.int32),
+                         np.ascontiguousarray(val, np.float64).reshape(-1), pc.h if pc else None,
+                         np.ascontiguousarray(b, np.float64), x, C.byref(o), C.byref(st),
+                         hist.ctypes.data if history else None)
+    info = dict(status=rc, iterations=st.iterations, restarts=st.restarts, converged=bool(st.converged),
+                rel_residual=st.rel_residual, est_residual=st.est_residual)
+    if history:
+        info["history"] = hist[: st.iterations + 1].copy()
+    return x, info
+
+
+def arnoldi(rp, ci, val, b, k, pc: Optional[Cpr] = None, orth=1):
+    n = len(rp) - 1
+    L = 3 * n
+    Z = np.zeros(k * L); V = np.zeros((k + 1) * L); H = np.zeros((k + 1) * k)
+    st = lib().or_arnoldi(n, np.ascontiguousarray(rp, np.int32), np.ascontiguousarray(ci, np.int32),
+                          np.ascontiguousarray(val, np.float64).reshape(-1), pc.h if pc else None,
+                          np.ascontiguousarray(b, np.float64), k, orth, Z, V, H)
+    if st != OR_OK:
+        raise RuntimeError("or_arnoldi failed")
+    return Z.reshape(k, L), V.reshape(k + 1, L), H.reshape(k + 1, k)
+
+
+def bsr_to_dense(rp, ci, val) -> np.ndarray:
+    n = len(rp) - 1
+    val = np.asarray(val).reshape(-1, 3, 3)
+    D = np.zeros((3 * n, 3 * n))
+    for i in range(n):
+        for e in range(rp[i], rp[i + 1]):
+            j = ci[e]
+            D[3 * i:3 * i + 3, 3 * j:3 * j + 3] = val[e]
+    return D
