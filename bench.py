@@ -1,0 +1,182 @@
+"""Benchmark: CPR-FGMRES time-to-solution on fully implicit black-oil Jacobians.
+
+One step = the whole hot path for one Newton system of the workload: Jacobian
+and right-hand side assembly (bo_jacobian_bsr), CPR setup (bo_cpr_setup) and
+the FGMRES(30) solve to a true relative residual of 1e-6 (bo_fgmres_solve).
+Steps cycle through the 10 systems of the synthetic step sequence; all inputs
+are resident in HBM before timing starts.
+
+Prints one JSON line with the time per system (`value`, seconds), the SpMV
+roofline figure (its average launch duration measured with HIP events on the
+library's stream) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CPR-FGMRES time-to-solution (s) at rel. residual 1e-6; BSR SpMV HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2))
+    ap.add_argument("--spmv-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import bo_casegen as cg
+    from paper_1606_00556_amd import bo as B
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    wl = args.workload
+    systems = [0] if wl == 0 else list(range(1, cg.N_SYSTEMS + 1))
+    log(args, f"[bench] generating workload {wl} ({len(systems)} systems)")
+    cases = [cg.make_case(wl, k) if wl else cg.make_case(0) for k in systems]
+    c0 = cases[0]
+    prob = B.problem_from_case(c0, dev)
+    states = [(torch.from_numpy(c.x_old).to(dev), torch.from_numpy(c.x_new).to(dev), c.dt) for c in cases]
+    n, nnzb = B.bo_jacobian_bsr_size(prob)
+    J = B.DeviceBsr(torch.empty(n + 1, dtype=torch.int32, device=dev),
+                    torch.empty(nnzb, dtype=torch.int32, device=dev),
+                    torch.empty(9 * nnzb, dtype=torch.float64, device=dev))
+    b = torch.empty(3 * n, dtype=torch.float64, device=dev)
+    x = torch.empty(3 * n, dtype=torch.float64, device=dev)
+    grid = (c0.nx, c0.ny, c0.nz)
+    copts = B.bo_cpr_default_opts()
+    fopts = B.bo_fgmres_default_opts()
+    torch.cuda.synchronize()
+
+    def step(i, record=None):
+        xo, xn, dt = states[i % len(states)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record is not None else None
+        if e: e[0].record(stream)
+        B.bo_jacobian_bsr(prob, xo, xn, dt, J, b)
+        if e: e[1].record(stream)
+        pc = B.bo_cpr_setup(J, grid, copts)
+        if e: e[2].record(stream)
+        x.zero_()
+        info = B.bo_fgmres_solve(pc, b, x, fopts)
+        if e: e[3].record(stream)
+        pc.close()
+        if not info["converged"]:
+            raise RuntimeError(f"system {i} did not converge: {info}")
+        if record is not None:
+            record.append((e, info))
+        return info
+
+    for w in range(args.warmup):
+        info = step(w)
+        log(args, f"[bench] warmup {w}: its={info['iterations']} rel={info['rel_residual']:.2e}")
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k, rec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = 1000.0 * (t1 - t0) / args.steps
+    asm_ms = sum(e[0].elapsed_time(e[1]) for e, _ in rec) / len(rec)
+    setup_ms = sum(e[1].elapsed_time(e[2]) for e, _ in rec) / len(rec)
+    solve_ms = sum(e[2].elapsed_time(e[3]) for e, _ in rec) / len(rec)
+    its = [inf["iterations"] for _, inf in rec]
+    log(args, f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step, assembly {asm_ms:.2f}, setup {setup_ms:.2f}, "
+              f"solve {solve_ms:.2f} ms, iterations {its}")
+
+    # SpMV roofline: algorithmic bytes = 72 B per stored block (3x3 FP64) +
+    # 24 B x read + 24 B y written per block row
+    pc = B.bo_cpr_setup(J, grid, copts)
+    xin = torch.randn(3 * n, dtype=torch.float64, device=dev)
+    yout = torch.empty_like(xin)
+    for _ in range(5):
+        B.bo_cpr_spmv(pc, 1.0, xin, 0.0, yout)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(args.spmv_reps):
+        B.bo_cpr_spmv(pc, 1.0, xin, 0.0, yout)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    spmv_us = 1000.0 * ev[0].elapsed_time(ev[1]) / args.spmv_reps
+    spmv_bytes = 72.0 * nnzb + 48.0 * n
+    spmv_gbs = spmv_bytes / (spmv_us * 1e-6) / 1e9
+    pc.close()
+    log(args, f"[bench] SpMV {spmv_us:.1f} us, {spmv_gbs:.0f} GB/s algorithmic ({spmv_bytes / 1e6:.1f} MB)")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args, cases[0])
+    out = {
+        "metric": METRIC,
+        "value": ms_per_step / 1000.0,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"cfg{wl}: {c0.nx}x{c0.ny}x{c0.nz} black-oil 3x3-block Jacobians "
+                         f"({n} cells, {3 * n} unknowns, {nnzb} blocks), "
+                         + ("10 systems of the synthetic 30-day step sequence" if wl else "one system")),
+            "solver": "FGMRES(30), CPR-PF: block quasi-IMPES, SA-AMG V(1,1) RB-GS/Jacobi, tiled BILU0 8x8",
+            "rtol": 1e-6,
+            "step": "bo_jacobian_bsr + bo_cpr_setup + bo_fgmres_solve",
+            "parallelism": "1 GPU",
+        },
+        "breakdown_ms": {"assembly": asm_ms, "setup": setup_ms, "solve": solve_ms},
+        "iterations": its,
+        "spmv": {"us": spmv_us, "GBs": spmv_gbs, "bytes": spmv_bytes},
+        "roofline": {"bound": "hbm", "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_slot_spmv"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(args, case):
+    """The FP64 oracle on the host: one system (assembly + setup + solve)."""
+    from oracle import oracle as O
+    log(args, "[bench] cpu baseline: oracle on one system")
+    t0 = time.perf_counter()
+    P = O.Problem(case)
+    rp, ci, val, R = O.jacobian(P)
+    pc = O.Cpr(P, rp, ci, val)
+    x, info = O.fgmres(rp, ci, val, -R, pc)
+    t1 = time.perf_counter()
+    log(args, f"[bench] cpu baseline: {t1 - t0:.2f} s, its={info['iterations']}")
+    return {"value": t1 - t0, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"{case.name}: one of the workload's systems, Jacobian + CPR setup + FGMRES solve, "
+                      f"single-threaded C oracle, {info['iterations']} iterations"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * bo: fully implicit black-oil Jacobian assembly and CPR-preconditioned
+ * flexible GMRES on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Liu, Shen, Wang, Yang, Chen, "Numerical Simulation of Multi-phase
+ * Flow in Porous Media on Parallel Computers"):
+ *   - Section 2.1: three-phase, three-component black-oil model (Darcy's law,
+ *     saturation and potential constraints, no-flow boundary, Stone II oil
+ *     relative permeability) with unknowns (Po, Sw, Sg) per cell;
+ *   - Section 2.3: Peaceman wells, fixed bottom-hole pressure control;
+ *   - Section 3: finite differences on a structured hexahedral grid (7-point);
+ *   - Section 3.2: block structure of the Jacobian, quasi-IMPES decoupling, and
+ *     the CPR-FPF preconditioner (RAS with ILU(0) subdomain solves, AMG on the
+ *     pressure block);
+ *   - Section 3.4: y = alpha A x + beta y, dot products and norms, and GMRES.
+ *
+ * Conventions shared by every entry point
+ *   - Cells are numbered g = i + nx*(j + ny*k), i fastest.
+ *   - Vectors have 3N doubles interleaving (Po, Sw, Sg) per cell.
+ *   - A BSR matrix has 3x3 blocks stored row-major (block row = equation
+ *     (oil, water, gas), block column = unknown (Po, Sw, Sg)); column indices
+ *     ascend within each block row.
+ *   - Every pointer is a DEVICE pointer unless its comment says [host].
+ *   - `stream` is a hipStream_t (NULL: the default stream); all device work is
+ *     enqueued on it.  Functions return after enqueueing unless stated.
+ *   - Every function returns a bo_status.  On an error nothing is guaranteed
+ *     about outputs, and bo_last_error() (per thread) describes the failure.
+ *   - The library never takes ownership of caller buffers.  Handles own their
+ *     device memory and release it in the matching destroy call.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently
+ *     on distinct streams.
+ */
+#ifndef BO_H
+#define BO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BO_OK = 0,
+    BO_NOT_CONVERGED = 1,         /* solver reached maxit; x holds the last iterate */
+    BO_ERR_INVALID_ARG = -1,
+    BO_ERR_HIP = -2,              /* a HIP runtime call failed */
+    BO_ERR_ALLOC = -3,
+    BO_ERR_NONFINITE = -4,        /* NaN/Inf in an input or during the iteration */
+    BO_ERR_SINGULAR_BLOCK = -5,   /* a 3x3 pivot block is singular */
+    BO_ERR_SINGULAR_COARSE = -6,  /* the coarsest AMG matrix is singular */
+    BO_ERR_UNSUPPORTED = -8       /* e.g. a matrix pattern that is not the grid's 7-point stencil */
+} bo_status;
+
+/* Thread-local description of the last error (never NULL). */
+const char *bo_last_error(void);
+/* Library version string. */
+const char *bo_version(void);
+
+/* Block sparse row matrix with 3x3 blocks. */
+typedef struct {
+    int32_t nbrows;     /* block rows (= cells) */
+    int32_t nnzb;       /* stored blocks */
+    int32_t *rowptr;    /* nbrows+1 */
+    int32_t *colind;    /* nnzb, ascending within each row */
+    double *val;        /* 9*nnzb, row-major blocks */
+} bo_bsr;
+
+/* Fluid and rock description (field units: psi, ft, mD, cP, days). */
+typedef struct {
+    double p_ref;                   /* reference pressure */
+    double Bw0, cw, Bo0, co, Bg0, cg;   /* B_a(p) = B_a0 (1 - c_a (p - p_ref)) */
+    double Rs0, crs;                /* R_s(p) = Rs0 (1 + crs (p - p_ref)), Mscf/STB */
+    double mu_w, mu_o, mu_g;        /* viscosities */
+    double c_r;                     /* rock compressibility, phi = phi0 (1 + c_r (p - p_ref)) */
+    double rho_wsc, rho_osc, rho_gsc;   /* surface densities, lbm/ft3 (gas: lbm/scf) */
+    double swc, sor, sorg, sgc;     /* Corey end points */
+    int32_t nw, no, ng;             /* Corey exponents (integers >= 1) */
+    double tcoef;                   /* Darcy unit constant (0.001127) */
+    double rb_ft3;                  /* ft3 per reservoir barrel (5.615) */
+    double grav;                    /* psi per (lbm/ft3 * ft) (1/144) */
+    int32_t gravity;                /* 0: potentials without the density term */
+    int32_t inj_total_mobility;     /* 1: water injectors use the cell's total mobility */
+} bo_fluid;
+
+/* A vertical well through cells (i, j, k_top..k_bot), 0-based. */
+typedef struct {
+    int32_t i, j, k_top, k_bot;
+    int32_t injector;   /* 1: water injector, 0: producer */
+    int32_t control;    /* 0: fixed bottom-hole pressure (Section 2.3); others unsupported */
+    double target;      /* bottom-hole pressure at the top perforation's depth, psi */
+    double rw, skin;    /* wellbore radius (ft) and skin */
+} bo_well;
+
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;          /* cell sizes, ft */
+    double top_depth;           /* depth of the grid top, ft (positive down) */
+    const double *kx, *ky, *kz; /* N permeabilities, mD */
+    const double *phi0;         /* N porosities at p_ref */
+    bo_fluid fluid;
+    int32_t nwells;
+    const bo_well *wells;       /* [host] nwells entries; no two perforations may share a cell */
+} bo_problem;
+
+/* ---- a1: Jacobian and right-hand side -------------------------------- */
+
+/* [host only] Sizes of the Jacobian of `p`: nbrows = N, nnzb = blocks of the
+ * 7-point pattern.  Fails with BO_ERR_INVALID_ARG when 9*nnzb overflows int32
+ * addressing assumptions are violated (N >= 2^31/7). */
+bo_status bo_jacobian_bsr_size(const bo_problem *p, int32_t *nbrows, int32_t *nnzb);
+
+/* Residual R of the discrete black-oil equations (Sections 2.1, 2.3, 3) at the
+ * Newton iterate x_new (3N) with old state x_old (3N) and time step dt (days),
+ * and its analytic Jacobian dR/dx_new.  Writes J's pattern and values into the
+ * caller-allocated J (rowptr N+1, colind nnzb, val 9*nnzb from
+ * bo_jacobian_bsr_size) and b = -R (3N), so that J dx = b is the Newton
+ * system.  Residual rows are per unit surface volume (STB/day for oil and water,
+ * Mscf/day for gas). */
+bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, const double *x_new, double dt,
+                          bo_bsr *J, double *b, void *stream);
+
+/* ---- Basic operations (Section 3.4) ---------------------------------- */
+
+/* y = alpha*A*x + beta*y on the BSR layout (beta == 0: y is not read). */
+bo_status bo_bsr_spmv(const bo_bsr *A, double alpha, const double *x, double beta, double *y,
+                      void *stream);
+
+/* ---- a2-a6: CPR preconditioner --------------------------------------- */
+
+enum { BO_F_BJ = 0, BO_F_ILU_TILED = 3 };          /* F stage: block Jacobi / tiled block ILU(0) */
+enum { BO_SMOOTH_GS = 0, BO_SMOOTH_JACOBI = 1 };   /* level-0 smoother */
+enum { BO_QI_DIAG = 0, BO_QI_BLOCK = 1 };          /* quasi-IMPES weights */
+enum { BO_PREC_FP64 = 0, BO_PREC_FP32 = 1, BO_PREC_FP32_BF16 = 2 };
+
+typedef struct {
+    int32_t fpf;            /* 0: two-stage P then F; 1: Algorithm CPR-FPF */
+    int32_t ftype;          /* BO_F_* */
+    int32_t tile_x, tile_y; /* ILU tiles: tile_x*tile_y columns of nz cells, tile_x*tile_y <= 64 */
+    double theta;           /* AMG strength threshold */
+    int32_t coarse_max;     /* coarsest level size bound (<= 1024) */
+    int32_t max_levels;     /* <= 16 */
+    int32_t smoother;       /* level 0: BO_SMOOTH_GS (red-black) or BO_SMOOTH_JACOBI; coarser: Jacobi */
+    int32_t sweeps;         /* pre- and post-smoothing sweeps */
+    int32_t use_amg;        /* 0: no pressure stage */
+    int32_t qi_mode;        /* BO_QI_* */
+    int32_t precision;      /* BO_PREC_*: storage/arithmetic of the AMG hierarchy and ILU factors */
+} bo_cpr_opts;
+
+/* Fills `o` [host] with the defaults: PF, tiled ILU0 8x8, theta 0.08,
+ * coarse_max 256, 12 levels, red-black GS, 1 sweep, AMG on, block QI, FP64. */
+void bo_cpr_default_opts(bo_cpr_opts *o);
+
+typedef struct bo_cpr bo_cpr;
+
+/* [host] grid of the matrix: the F stage tiles and the level-0 colours use it,
+ * and A's pattern must be the 7-point stencil of this grid. */
+typedef struct { int32_t nx, ny, nz; } bo_grid;
+
+/* Builds the CPR preconditioner of A (Section 3.2): quasi-IMPES weights and the
+ * decoupled pressure block, the AMG hierarchy on it, and the F-stage factors.
+ * Keeps a private copy of A's values in its own layout; A may be freed after
+ * return.  Synchronises `stream` (the hierarchy sizes are decided on the host). */
+bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
+                       bo_cpr **out, void *stream);
+void bo_cpr_destroy(bo_cpr *pc);
+
+/* z = M^{-1} v (3N each): PF or FPF as configured. */
+bo_status bo_cpr_apply(bo_cpr *pc, const double *v, double *z, void *stream);
+/* y = alpha*A*x + beta*y with the copy of A held by pc (the solver's SpMV). */
+bo_status bo_cpr_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, void *stream);
+/* Stages, for parity checks: rp (N) = Pi_r v; x (N) = one V-cycle on the
+ * pressure block for right-hand side b (N); x (3N) = F(r). */
+bo_status bo_cpr_restrict(bo_cpr *pc, const double *v, double *rp, void *stream);
+bo_status bo_cpr_vcycle(bo_cpr *pc, const double *b, double *x, void *stream);
+bo_status bo_cpr_fstage(bo_cpr *pc, const double *r, double *x, void *stream);
+
+/* [host] Hierarchy introspection.  Copies are synchronous; any output may be NULL.
+ * Level l holds n rows and nnz entries (CSR, ascending columns). */
+bo_status bo_cpr_levels(bo_cpr *pc, int32_t *nlevels);
+bo_status bo_cpr_level_info(bo_cpr *pc, int32_t l, int32_t *n, int32_t *nnz, int32_t *pnnz, double *omega);
+bo_status bo_cpr_level_copy(bo_cpr *pc, int32_t l, int32_t *rowptr, int32_t *colind, double *val,
+                            int32_t *agg, uint8_t *root, int32_t *prowptr, int32_t *pcolind, double *pval);
+/* [host] decoupling rows c (3N) */
+bo_status bo_cpr_copy_weights(bo_cpr *pc, double *c);
+
+/* ---- a7: flexible GMRES ---------------------------------------------- */
+
+typedef struct {
+    int32_t m;          /* restart length (1..64) */
+    int32_t maxit;      /* preconditioner applications allowed */
+    double rtol;        /* stop when ||b - A x|| <= rtol ||b|| (true residual) */
+    int32_t orth;       /* 0: modified Gram-Schmidt, 1: classical GS twice */
+} bo_fgmres_opts;
+
+void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, CGS2 */
+
+typedef struct {
+    int32_t iterations;     /* preconditioner applications */
+    int32_t restarts;
+    int32_t converged;
+    double rel_residual;    /* true ||b - A x|| / ||b|| at exit */
+    double est_residual;    /* last Arnoldi estimate |g_{j+1}| / ||b|| */
+} bo_solve_stats;
+
+/* Right-preconditioned FGMRES(m) on A x = b with the operator and
+ * preconditioner of pc (A captured at setup).  x holds the initial guess on
+ * entry and the solution on exit.  Synchronous: it reads one Arnoldi scalar
+ * column per iteration.  Returns BO_OK, BO_NOT_CONVERGED or an error. */
+bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, const bo_fgmres_opts *opts,
+                          bo_solve_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,346 @@
+"""ctypes binding of libbo (argument marshalling only; every step runs in the
+HIP kernels behind the C ABI declared in include/bo.h).
+
+Device buffers are torch tensors on a ROCm device; the current torch stream is
+passed as the HIP stream.  There is no CPU fallback: if libbo.so is missing or
+no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbo.so")
+
+BO_OK, BO_NOT_CONVERGED = 0, 1
+BO_ERR_INVALID_ARG, BO_ERR_HIP, BO_ERR_ALLOC, BO_ERR_NONFINITE = -1, -2, -3, -4
+BO_ERR_SINGULAR_BLOCK, BO_ERR_SINGULAR_COARSE, BO_ERR_UNSUPPORTED = -5, -6, -8
+BO_F_BJ, BO_F_ILU_TILED = 0, 3
+BO_SMOOTH_GS, BO_SMOOTH_JACOBI = 0, 1
+BO_QI_DIAG, BO_QI_BLOCK = 0, 1
+BO_PREC_FP64, BO_PREC_FP32, BO_PREC_FP32_BF16 = 0, 1, 2
+
+EXPORTS = [
+    "bo_last_error", "bo_version", "bo_jacobian_bsr_size", "bo_jacobian_bsr", "bo_bsr_spmv",
+    "bo_cpr_default_opts", "bo_cpr_setup", "bo_cpr_destroy", "bo_cpr_apply", "bo_cpr_spmv",
+    "bo_cpr_restrict", "bo_cpr_vcycle", "bo_cpr_fstage", "bo_cpr_levels", "bo_cpr_level_info",
+    "bo_cpr_level_copy", "bo_cpr_copy_weights", "bo_fgmres_default_opts", "bo_fgmres_solve",
+]
+
+
+class BoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bo status {status}: {msg}")
+        self.status = status
+
+
+class BoBsr(C.Structure):
+    _fields_ = [("nbrows", C.c_int32), ("nnzb", C.c_int32), ("rowptr", C.c_void_p),
+                ("colind", C.c_void_p), ("val", C.c_void_p)]
+
+
+class BoFluid(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("p_ref", "Bw0", "cw", "Bo0", "co", "Bg0", "cg", "Rs0", "crs",
+                                          "mu_w", "mu_o", "mu_g", "c_r", "rho_wsc", "rho_osc", "rho_gsc",
+                                          "swc", "sor", "sorg", "sgc")] + \
+              [("nw", C.c_int32), ("no", C.c_int32), ("ng", C.c_int32),
+               ("tcoef", C.c_double), ("rb_ft3", C.c_double), ("grav", C.c_double),
+               ("gravity", C.c_int32), ("inj_total_mobility", C.c_int32)]
+
+
+class BoWell(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("k_top", C.c_int32), ("k_bot", C.c_int32),
+                ("injector", C.c_int32), ("control", C.c_int32), ("target", C.c_double),
+                ("rw", C.c_double), ("skin", C.c_double)]
+
+
+class BoProblem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("top_depth", C.c_double),
+                ("kx", C.c_void_p), ("ky", C.c_void_p), ("kz", C.c_void_p), ("phi0", C.c_void_p),
+                ("fluid", BoFluid), ("nwells", C.c_int32), ("wells", C.POINTER(BoWell))]
+
+
+class BoCprOpts(C.Structure):
+    _fields_ = [("fpf", C.c_int32), ("ftype", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
+                ("theta", C.c_double), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
+                ("smoother", C.c_int32), ("sweeps", C.c_int32), ("use_amg", C.c_int32),
+                ("qi_mode", C.c_int32), ("precision", C.c_int32)]
+
+
+class BoGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32)]
+
+
+class BoFgmresOpts(C.Structure):
+    _fields_ = [("m", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("orth", C.c_int32)]
+
+
+class BoSolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("rel_residual", C.c_double), ("est_residual", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libbo.so (built by paper_1606_00556_amd/build.py); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise BoError(BO_ERR_HIP, f"{LIB_PATH} is not built: run __graft_entry__.build()")
+    # torch owns device memory and streams: load its HIP runtime first so that
+    # libbo binds to the same runtime instance (one per process)
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, st = C.c_void_p, C.c_int
+    L.bo_last_error.restype = C.c_char_p
+    L.bo_version.restype = C.c_char_p
+    L.bo_jacobian_bsr_size.argtypes = [C.POINTER(BoProblem), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.bo_jacobian_bsr.argtypes = [C.POINTER(BoProblem), vp, vp, C.c_double, C.POINTER(BoBsr), vp, vp]
+    L.bo_bsr_spmv.argtypes = [C.POINTER(BoBsr), C.c_double, vp, C.c_double, vp, vp]
+    L.bo_cpr_default_opts.argtypes = [C.POINTER(BoCprOpts)]
+    L.bo_cpr_default_opts.restype = None
+    L.bo_cpr_setup.argtypes = [C.POINTER(BoBsr), C.POINTER(BoGrid), C.POINTER(BoCprOpts), C.POINTER(vp), vp]
+    L.bo_cpr_destroy.argtypes = [vp]
+    L.bo_cpr_destroy.restype = None
+    for f in ("bo_cpr_apply", "bo_cpr_restrict", "bo_cpr_vcycle", "bo_cpr_fstage"):
+        getattr(L, f).argtypes = [vp, vp, vp, vp]
+    L.bo_cpr_spmv.argtypes = [vp, C.c_double, vp, C.c_double, vp, vp]
+    L.bo_cpr_levels.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.bo_cpr_level_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.bo_cpr_level_copy.argtypes = [vp, C.c_int32] + [vp] * 8
+    L.bo_cpr_copy_weights.argtypes = [vp, vp]
+    L.bo_fgmres_default_opts.argtypes = [C.POINTER(BoFgmresOpts)]
+    L.bo_fgmres_default_opts.restype = None
+    L.bo_fgmres_solve.argtypes = [vp, vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats), vp]
+    for f in EXPORTS:
+        if f not in ("bo_last_error", "bo_version", "bo_cpr_default_opts", "bo_cpr_destroy",
+                     "bo_fgmres_default_opts"):
+            getattr(L, f).restype = st
+    _lib = L
+    return L
+
+
+def _check(status: int, allowed=(BO_OK,)) -> int:
+    if status not in allowed:
+        raise BoError(status, lib().bo_last_error().decode())
+    return status
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+# ---- problem marshalling --------------------------------------------------------
+@dataclass
+class DeviceProblem:
+    """A bo_problem whose fields live in device tensors (kept alive here)."""
+    s: BoProblem
+    tensors: tuple
+    wells: object
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def problem_from_case(case, device="cuda") -> DeviceProblem:
+    import torch
+    f = case.fluid
+    fl = BoFluid(*[float(f[k]) for k in ("p_ref", "Bw0", "cw", "Bo0", "co", "Bg0", "cg", "Rs0", "crs",
+                                         "mu_w", "mu_o", "mu_g", "c_r", "rho_wsc", "rho_osc", "rho_gsc",
+                                         "swc", "sor", "sorg", "sgc")],
+                 int(f["nw"]), int(f["no"]), int(f["ng"]), float(f["tcoef"]), float(f["rb_ft3"]),
+                 float(f["grav"]), int(case.gravity), int(case.inj_total_mobility))
+    t = tuple(torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+              for a in (case.kx, case.ky, case.kz, case.phi0))
+    W = (BoWell * max(len(case.wells), 1))()
+    for q, w in enumerate(case.wells):
+        ctrl = {"bhp": 0, "wrat": 1, "orat": 2, "lrat": 3}[w.control]
+        W[q] = BoWell(w.i, w.j, w.k_top, w.k_bot, 1 if w.kind == "inj" else 0, ctrl, w.target, w.rw, w.skin)
+    s = BoProblem(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.top_depth,
+                  _ptr(t[0]), _ptr(t[1]), _ptr(t[2]), _ptr(t[3]), fl, len(case.wells),
+                  C.cast(W, C.POINTER(BoWell)))
+    return DeviceProblem(s, t, W)
+
+
+@dataclass
+class DeviceBsr:
+    """A bo_bsr over device tensors."""
+    rowptr: object
+    colind: object
+    val: object
+
+    @property
+    def s(self) -> BoBsr:
+        return BoBsr(self.rowptr.numel() - 1, self.colind.numel(), _ptr(self.rowptr), _ptr(self.colind),
+                     _ptr(self.val))
+
+
+# ---- entry points (same names as the C ABI) -----------------------------------------
+def bo_version() -> str:
+    return lib().bo_version().decode()
+
+
+def bo_jacobian_bsr_size(p: DeviceProblem):
+    n, nnzb = C.c_int32(), C.c_int32()
+    _check(lib().bo_jacobian_bsr_size(p.ref, C.byref(n), C.byref(nnzb)))
+    return n.value, nnzb.value
+
+
+def bo_jacobian_bsr(p: DeviceProblem, x_old, x_new, dt: float, J: Optional[DeviceBsr] = None, b=None,
+                    stream=None):
+    """Assembles J and b = -R.  Allocates J and b when they are not given."""
+    import torch
+    n, nnzb = bo_jacobian_bsr_size(p)
+    dev = x_new.device
+    if J is None:
+        J = DeviceBsr(torch.empty(n + 1, dtype=torch.int32, device=dev),
+                      torch.empty(nnzb, dtype=torch.int32, device=dev),
+                      torch.empty(9 * nnzb, dtype=torch.float64, device=dev))
+    if b is None:
+        b = torch.empty(3 * n, dtype=torch.float64, device=dev)
+    s = J.s
+    _check(lib().bo_jacobian_bsr(p.ref, _ptr(x_old), _ptr(x_new), float(dt), C.byref(s), _ptr(b),
+                                 _stream(stream)))
+    return J, b
+
+
+def bo_bsr_spmv(A: DeviceBsr, alpha: float, x, beta: float, y, stream=None):
+    s = A.s
+    _check(lib().bo_bsr_spmv(C.byref(s), alpha, _ptr(x), beta, _ptr(y), _stream(stream)))
+    return y
+
+
+def bo_cpr_default_opts(**overrides) -> BoCprOpts:
+    o = BoCprOpts()
+    lib().bo_cpr_default_opts(C.byref(o))
+    for k, v in overrides.items():
+        if k == "tile":
+            o.tile_x, o.tile_y = v
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def bo_fgmres_default_opts(**overrides) -> BoFgmresOpts:
+    o = BoFgmresOpts()
+    lib().bo_fgmres_default_opts(C.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+class Cpr:
+    """Owns a bo_cpr handle (bo_cpr_destroy on close / garbage collection)."""
+
+    def __init__(self, h: int, n: int):
+        self.h = C.c_void_p(h)
+        self.n = n
+
+    def close(self):
+        if self.h:
+            lib().bo_cpr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bo_cpr_setup(A: DeviceBsr, grid, opts: Optional[BoCprOpts] = None, stream=None) -> Cpr:
+    o = opts if opts is not None else bo_cpr_default_opts()
+    g = BoGrid(*grid)
+    h = C.c_void_p()
+    s = A.s
+    _check(lib().bo_cpr_setup(C.byref(s), C.byref(g), C.byref(o), C.byref(h), _stream(stream)))
+    return Cpr(h.value, s.nbrows)
+
+
+def bo_cpr_destroy(pc: Cpr):
+    pc.close()
+
+
+def bo_cpr_apply(pc: Cpr, v, z, stream=None):
+    _check(lib().bo_cpr_apply(pc.h, _ptr(v), _ptr(z), _stream(stream)))
+    return z
+
+
+def bo_cpr_spmv(pc: Cpr, alpha: float, x, beta: float, y, stream=None):
+    _check(lib().bo_cpr_spmv(pc.h, alpha, _ptr(x), beta, _ptr(y), _stream(stream)))
+    return y
+
+
+def bo_cpr_restrict(pc: Cpr, v, rp, stream=None):
+    _check(lib().bo_cpr_restrict(pc.h, _ptr(v), _ptr(rp), _stream(stream)))
+    return rp
+
+
+def bo_cpr_vcycle(pc: Cpr, b, x, stream=None):
+    _check(lib().bo_cpr_vcycle(pc.h, _ptr(b), _ptr(x), _stream(stream)))
+    return x
+
+
+def bo_cpr_fstage(pc: Cpr, r, x, stream=None):
+    _check(lib().bo_cpr_fstage(pc.h, _ptr(r), _ptr(x), _stream(stream)))
+    return x
+
+
+def bo_cpr_levels(pc: Cpr) -> int:
+    n = C.c_int32()
+    _check(lib().bo_cpr_levels(pc.h, C.byref(n)))
+    return n.value
+
+
+def bo_cpr_level_info(pc: Cpr, l: int) -> dict:
+    n, nnz, pnnz, om = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib().bo_cpr_level_info(pc.h, l, C.byref(n), C.byref(nnz), C.byref(pnnz), C.byref(om)))
+    return dict(n=n.value, nnz=nnz.value, pnnz=pnnz.value, omega=om.value)
+
+
+def bo_cpr_level_copy(pc: Cpr, l: int) -> dict:
+    """Host copies (numpy) of level l."""
+    import numpy as np
+    info = bo_cpr_level_info(pc, l)
+    n, nnz, pnnz = info["n"], info["nnz"], info["pnnz"]
+    rp = np.zeros(n + 1, np.int32); ci = np.zeros(max(nnz, 1), np.int32); v = np.zeros(max(nnz, 1))
+    agg = np.zeros(max(n, 1), np.int32); root = np.zeros(max(n, 1), np.uint8)
+    prp = np.zeros(n + 1, np.int32); pci = np.zeros(max(pnnz, 1), np.int32); pv = np.zeros(max(pnnz, 1))
+    _check(lib().bo_cpr_level_copy(pc.h, l, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, agg.ctypes.data,
+                                   root.ctypes.data, prp.ctypes.data, pci.ctypes.data, pv.ctypes.data))
+    out = dict(info, rowptr=rp, colind=ci[:nnz], val=v[:nnz])
+    if pnnz > 0:
+        out.update(agg=agg, root=root.astype(bool), p_rowptr=prp, p_colind=pci[:pnnz], p_val=pv[:pnnz])
+    return out
+
+
+def bo_cpr_copy_weights(pc: Cpr):
+    import numpy as np
+    c = np.zeros(3 * pc.n)
+    _check(lib().bo_cpr_copy_weights(pc.h, c.ctypes.data))
+    return c
+
+
+def bo_fgmres_solve(pc: Cpr, b, x, opts: Optional[BoFgmresOpts] = None, stream=None) -> dict:
+    o = opts if opts is not None else bo_fgmres_default_opts()
+    st = BoSolveStats()
+    rc = lib().bo_fgmres_solve(pc.h, _ptr(b), _ptr(x), C.byref(o), C.byref(st), _stream(stream))
+    _check(rc, allowed=(BO_OK, BO_NOT_CONVERGED))
+    return dict(status=rc, iterations=st.iterations, restarts=st.restarts, converged=bool(st.converged),
+                rel_residual=st.rel_residual, est_residual=st.est_residual)

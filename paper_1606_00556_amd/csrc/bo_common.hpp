@@ -1,0 +1,172 @@
+// Internal helpers of the bo HIP library (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <algorithm>
+#include <string>
+#include <vector>
+#include "../../include/bo.h"
+
+namespace bo {
+
+// ---- errors -----------------------------------------------------------------
+void set_error(const std::string &msg);
+bo_status fail(bo_status st, const std::string &msg);
+
+#define BO_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return ::bo::fail(BO_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define BO_TRY(expr)                       \
+    do {                                   \
+        bo_status s_ = (expr);             \
+        if (s_ != BO_OK) return s_;        \
+    } while (0)
+
+// ---- device memory ----------------------------------------------------------
+// Owned device buffer (freed in the destructor).
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    bo_status alloc(size_t count) {
+        if (count <= n && p) return BO_OK;
+        release();
+        size_t bytes = (count ? count : 1) * sizeof(T);
+        hipError_t e = hipMalloc((void **)&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(BO_ERR_ALLOC, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                          hipGetErrorString(e));
+        }
+        n = count;
+        return BO_OK;
+    }
+};
+
+// ---- launch geometry --------------------------------------------------------
+constexpr int kBlock = 256;
+inline unsigned grid_for(long long n, int block = kBlock) {
+    long long g = (n + block - 1) / block;
+    return (unsigned)(g > 0 ? g : 1);
+}
+
+// MI355X has 8 XCDs, each with its own L2; consecutive workgroups are dealt
+// round-robin to the XCDs.  Remapping the workgroup index so that each XCD
+// owns one contiguous range of rows keeps a row's stencil neighbours (rows +-
+// nx*ny away) in the same L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks) {
+    const unsigned nx = 8;
+    unsigned per = nblocks / nx, rem = nblocks % nx;
+    unsigned x = b % nx, q = b / nx;
+    // XCD x receives per (+1 if x < rem) blocks; its range starts at base(x)
+    unsigned base = x * per + (x < rem ? x : rem);
+    return base + q;
+}
+
+// ---- structured 7-point stencil ----------------------------------------------
+// Slot order = ascending column order of a block row: -z, -y, -x, diag, +x, +y, +z.
+enum { S_MZ = 0, S_MY = 1, S_MX = 2, S_D = 3, S_PX = 4, S_PY = 5, S_PZ = 6, NSLOT = 7 };
+
+struct Grid {
+    int nx, ny, nz;
+    long long n() const { return (long long)nx * ny * nz; }
+};
+
+// neighbour of cell g through slot s, or -1 outside the grid
+__device__ __forceinline__ int nbr_of(int g, int s, int nx, int ny, int nz) {
+    int nxy = nx * ny;
+    int i = g % nx, j = (g / nx) % ny, k = g / nxy;
+    switch (s) {
+    case S_MZ: return k > 0 ? g - nxy : -1;
+    case S_MY: return j > 0 ? g - nx : -1;
+    case S_MX: return i > 0 ? g - 1 : -1;
+    case S_D: return g;
+    case S_PX: return i < nx - 1 ? g + 1 : -1;
+    case S_PY: return j < ny - 1 ? g + nx : -1;
+    default: return k < nz - 1 ? g + nxy : -1;
+    }
+}
+
+// ---- small dense blocks ------------------------------------------------------
+// Inverse of a 3x3 block by Gauss-Jordan elimination with partial pivoting;
+// returns false for a pivot that is zero relative to the block's largest entry.
+__host__ __device__ inline bool inv3_gj(const double *A, double *Ainv) {
+    double M[3][6];
+    double amax = 0.0;
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            M[r][c] = A[3 * r + c];
+            M[r][3 + c] = (r == c) ? 1.0 : 0.0;
+            double a = fabs(A[3 * r + c]);
+            if (a > amax) amax = a;
+        }
+    if (!(amax > 0.0) || !(amax < INFINITY)) return false;
+    for (int k = 0; k < 3; k++) {
+        int piv = k;
+        for (int r = k + 1; r < 3; r++)
+            if (fabs(M[r][k]) > fabs(M[piv][k])) piv = r;
+        if (fabs(M[piv][k]) <= 1e-300 * amax) return false;
+        if (piv != k)
+            for (int c = 0; c < 6; c++) { double t = M[k][c]; M[k][c] = M[piv][c]; M[piv][c] = t; }
+        double d = M[k][k];
+        for (int c = 0; c < 6; c++) M[k][c] = M[k][c] / d;
+        for (int r = 0; r < 3; r++) {
+            if (r == k) continue;
+            double f = M[r][k];
+            for (int c = 0; c < 6; c++) M[r][c] = M[r][c] - f * M[k][c];
+        }
+    }
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) Ainv[3 * r + c] = M[r][3 + c];
+    return true;
+}
+
+// C = A B (3x3), sums from 0 in ascending inner index
+__host__ __device__ inline void mul3(const double *A, const double *B, double *C) {
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            double s = 0.0;
+            for (int k = 0; k < 3; k++) s = s + A[3 * r + k] * B[3 * k + c];
+            C[3 * r + c] = s;
+        }
+}
+
+// ---- deterministic reductions ------------------------------------------------
+// Sum of a double over a workgroup of kBlock threads in a fixed tree order.
+__device__ inline double block_sum(double v, double *sh) {
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w) sh[t] = sh[t] + sh[t + w];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ---- host-side scan / reductions (declared in bo_linalg.hip) -------------------
+// Exclusive prefix sum of n int32 counts into out (n+1 entries, out[n] = total);
+// returns the total on the host (synchronises the stream).
+bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s);
+
+}  // namespace bo

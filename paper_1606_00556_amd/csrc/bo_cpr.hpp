@@ -1,0 +1,71 @@
+// The CPR preconditioner handle (internal).
+#pragma once
+#include "bo_common.hpp"
+#include "bo_linalg.hpp"
+
+namespace bo {
+
+constexpr int kMaxLevels = 16;
+constexpr int kCoarseMaxLimit = 1024;
+
+// One level of the aggregation hierarchy: CSR operator (ascending columns),
+// and for every level but the coarsest the transfer operators to the next.
+struct Level {
+    int n = 0, nnz = 0;
+    DBuf<int32_t> rp, ci;
+    DBuf<double> v;
+    DBuf<int32_t> diagpos;
+    DBuf<double> dinv;
+    // transfer to level + 1
+    int nc = 0, pnnz = 0;
+    DBuf<int32_t> prp, pci, rrp, rci;
+    DBuf<double> pv, rv;
+    DBuf<int32_t> agg;
+    DBuf<uint8_t> root, sf;
+    double omega = 0.0;
+    // cycle work vectors
+    DBuf<double> x, b, r;
+    // single-precision copies (mixed form)
+    DBuf<float> v32, pv32, rv32, dinv32, x32, b32, r32;
+};
+
+struct Krylov {
+    int m = 0;
+    long long len = 0;
+    DBuf<double> V, Z;            // (m+1) x len, m x len
+    std::vector<const double *> vptr, zptr;   // host lists of the basis vectors
+    DBuf<double> h;               // device scalars of one Arnoldi step
+    DBuf<double> y;               // m coefficients for the update
+    double *host = nullptr;       // pinned: [0, 2m+3) fetched scalars, [2m+3, 3m+4) coefficients
+    ~Krylov() { if (host) (void)hipHostFree(host); }
+};
+
+}  // namespace bo
+
+struct bo_cpr {
+    bo::Grid g{};
+    int n = 0;                    // cells
+    bo_cpr_opts o{};
+    // operator (copy of A) in slot layout, 63 * N
+    bo::DBuf<double> A;
+    // decoupling rows, 3N
+    bo::DBuf<double> cw;
+    // level-0 pressure matrix in slot layout (7 * N) and the hierarchy
+    bo::DBuf<double> app;
+    bo::DBuf<float> app32;
+    int nlev = 0;
+    bo::Level lv[bo::kMaxLevels];
+    int coarse_n = 0;
+    bo::DBuf<double> cinv;        // dense inverse of the coarsest matrix
+    bo::DBuf<float> cinv32;
+    // F stage: inverse pivots (SoA 9 * N)
+    bo::DBuf<double> einv;
+    bo::DBuf<float> einv32;
+    bo::DBuf<uint16_t> einv16, A16;  // bf16 copies (mixed-bf16 form)
+    bo::DBuf<float> A32;          // fp32 copy of A's off-diagonal slots for the ILU apply
+    // work vectors
+    bo::DBuf<double> rp_, dp_, t3a, t3b, t3c, wf;
+    bo::DBuf<int32_t> flag;
+    bo::Reducer red;
+    bo::Krylov kr;
+};

@@ -1,0 +1,427 @@
+// Jacobian and residual of the fully implicit black-oil equations.
+//
+// Model: Section 2.1 (three components; Darcy fluxes; Phi = p - rho g depth;
+// S_o = 1 - S_w - S_g; zero capillary pressure; no-flow outer boundary; Stone
+// II oil relative permeability from Corey two-phase curves), Section 2.3
+// (Peaceman wells at fixed bottom-hole pressure), Section 3 (7-point finite
+// differences).  Equations are per unit surface volume (STB/day, Mscf/day);
+// the upstream cell of each phase potential carries the mobility, ties going
+// to the lower cell index; face densities are the mean of the two cells.
+//
+// Layout: one thread per cell gathers its own accumulation and its six faces
+// (in the order -z, -y, -x, +x, +y, +z) and writes its whole block row, so no
+// atomics are needed and every face flux is evaluated identically from both
+// sides (lower cell first).  A second kernel adds the well terms (one thread
+// per well; perforated cells are distinct).
+#include "bo_common.hpp"
+
+namespace bo {
+namespace {
+
+struct Fl {
+    double p_ref, Bw0, cw, Bo0, co, Bg0, cg, Rs0, crs, mu_w, mu_o, mu_g, c_r;
+    double rho_wsc, rho_osc, rho_gsc, swc, sor, sorg, sgc;
+    int nw, no, ng;
+    double tcoef, rb_ft3, grav;
+    int gravity, inj_total_mobility;
+};
+
+struct GridG {
+    int nx, ny, nz;
+    double dx, dy, dz, top;
+    const double *kx, *ky, *kz, *phi0;
+};
+
+struct Props {
+    double p, sw, sg, so;
+    double bw, dbw, bo, dbo, bg, dbg, rs, drs, phi, dphi;
+    double rw, drw, ro, dro, rg, drg;
+    double lw, lw_w;
+    double lo, lo_w, lo_g;
+    double lg, lg_g;
+};
+
+__device__ inline void recip_fvf(double B0, double c, double pref, double pr, double &b, double &db) {
+    double B = B0 * (1.0 - c * (pr - pref));
+    double dB = -B0 * c;
+    b = 1.0 / B;
+    db = -dB / (B * B);
+}
+
+__device__ inline double ipow(double x, int n) {
+    double r = 1.0;
+    for (int k = 0; k < n; k++) r = r * x;
+    return r;
+}
+
+// Corey: kr = clamp((s - lo)/span, 0, 1)^n
+__device__ inline void corey(double s, double lo, double span, int n, double &kr, double &dkr) {
+    double sn = (s - lo) / span;
+    if (sn <= 0.0) { kr = 0.0; dkr = 0.0; return; }
+    if (sn >= 1.0) { kr = 1.0; dkr = 0.0; return; }
+    kr = ipow(sn, n);
+    dkr = (double)n * ipow(sn, n - 1) / span;
+}
+
+__device__ inline void relperm(const Fl &f, double sw, double sg, double kr[9]) {
+    double krw, dkrw, krow, dkrow, krg, dkrg, krog, dkrog;
+    double spw = 1.0 - f.swc - f.sor;
+    double spg = 1.0 - f.swc - f.sorg - f.sgc;
+    corey(sw, f.swc, spw, f.nw, krw, dkrw);
+    corey(1.0 - sw, f.sor, spw, f.no, krow, dkrow);
+    dkrow = -dkrow;
+    corey(sg, f.sgc, spg, f.ng, krg, dkrg);
+    corey(1.0 - sg - f.swc, f.sorg, spg, f.no, krog, dkrog);
+    dkrog = -dkrog;
+    double krocw = 1.0;
+    double a = krow / krocw + krw, da_w = dkrow / krocw + dkrw;
+    double b = krog / krocw + krg, db_g = dkrog / krocw + dkrg;
+    double kro = krocw * (a * b - krw - krg);
+    double dkro_w = krocw * (da_w * b - dkrw);
+    double dkro_g = krocw * (a * db_g - dkrg);
+    if (kro <= 0.0) { kro = 0.0; dkro_w = 0.0; dkro_g = 0.0; }
+    kr[0] = krw; kr[1] = krow; kr[2] = krg; kr[3] = krog; kr[4] = kro;
+    kr[5] = dkro_w; kr[6] = dkro_g; kr[7] = dkrw; kr[8] = dkrg;
+}
+
+__device__ inline void props_of(const Fl &f, double phi0, const double *x, Props &c) {
+    double pr = x[0], sw = x[1], sg = x[2];
+    c.p = pr; c.sw = sw; c.sg = sg; c.so = 1.0 - sw - sg;
+    recip_fvf(f.Bw0, f.cw, f.p_ref, pr, c.bw, c.dbw);
+    recip_fvf(f.Bo0, f.co, f.p_ref, pr, c.bo, c.dbo);
+    recip_fvf(f.Bg0, f.cg, f.p_ref, pr, c.bg, c.dbg);
+    c.rs = f.Rs0 * (1.0 + f.crs * (pr - f.p_ref));
+    c.drs = f.Rs0 * f.crs;
+    c.phi = phi0 * (1.0 + f.c_r * (pr - f.p_ref));
+    c.dphi = phi0 * f.c_r;
+    double gps = 1000.0 * f.rho_gsc / f.rb_ft3;
+    c.rw = f.rho_wsc * c.bw;
+    c.drw = f.rho_wsc * c.dbw;
+    c.ro = (f.rho_osc + gps * c.rs) * c.bo;
+    c.dro = gps * c.drs * c.bo + (f.rho_osc + gps * c.rs) * c.dbo;
+    c.rg = gps * c.bg;
+    c.drg = gps * c.dbg;
+    double kr[9];
+    relperm(f, sw, sg, kr);
+    c.lw = kr[0] / f.mu_w; c.lw_w = kr[7] / f.mu_w;
+    c.lo = kr[4] / f.mu_o; c.lo_w = kr[5] / f.mu_o; c.lo_g = kr[6] / f.mu_o;
+    c.lg = kr[2] / f.mu_g; c.lg_g = kr[8] / f.mu_g;
+}
+
+__device__ inline void masses(const Props &c, double m[3], double dm[3][3], bool deriv) {
+    double so = c.so;
+    m[0] = c.phi * so * c.bo;
+    m[1] = c.phi * c.sw * c.bw;
+    m[2] = c.phi * (c.sg * c.bg + c.rs * so * c.bo);
+    if (!deriv) return;
+    dm[0][0] = c.dphi * so * c.bo + c.phi * so * c.dbo;
+    dm[0][1] = -c.phi * c.bo;
+    dm[0][2] = -c.phi * c.bo;
+    dm[1][0] = c.dphi * c.sw * c.bw + c.phi * c.sw * c.dbw;
+    dm[1][1] = c.phi * c.bw;
+    dm[1][2] = 0.0;
+    dm[2][0] = c.dphi * (c.sg * c.bg + c.rs * so * c.bo) +
+               c.phi * (c.sg * c.dbg + c.drs * so * c.bo + c.rs * so * c.dbo);
+    dm[2][1] = -c.phi * c.rs * c.bo;
+    dm[2][2] = c.phi * (c.bg - c.rs * c.bo);
+}
+
+// upwinded stream quantity: 0 oil, 1 water, 2 free gas, 3 dissolved gas
+__device__ inline void stream_q(const Props &c, int kind, double &M, double dM[3]) {
+    switch (kind) {
+    case 0:
+        M = c.lo * c.bo;
+        dM[0] = c.lo * c.dbo; dM[1] = c.lo_w * c.bo; dM[2] = c.lo_g * c.bo;
+        break;
+    case 1:
+        M = c.lw * c.bw;
+        dM[0] = c.lw * c.dbw; dM[1] = c.lw_w * c.bw; dM[2] = 0.0;
+        break;
+    case 2:
+        M = c.lg * c.bg;
+        dM[0] = c.lg * c.dbg; dM[1] = 0.0; dM[2] = c.lg_g * c.bg;
+        break;
+    default:
+        M = c.rs * c.lo * c.bo;
+        dM[0] = c.lo * (c.drs * c.bo + c.rs * c.dbo);
+        dM[1] = c.rs * c.lo_w * c.bo; dM[2] = c.rs * c.lo_g * c.bo;
+        break;
+    }
+}
+
+__device__ inline void density(const Props &c, int ph, double &rho, double &drho) {
+    if (ph == 0) { rho = c.ro; drho = c.dro; }
+    else if (ph == 1) { rho = c.rw; drho = c.drw; }
+    else { rho = c.rg; drho = c.drg; }
+}
+
+__device__ inline double depth_of(const GridG &g, int cell) {
+    int k = cell / (g.nx * g.ny);
+    return g.top + ((double)k + 0.5) * g.dz;
+}
+
+// face transmissibility between adjacent cells a < b through slot direction
+__device__ inline double trans(const GridG &g, const Fl &f, int a, int b) {
+    int d = b - a;
+    double area, len, ka, kb;
+    if (d == 1) { area = g.dy * g.dz; len = g.dx; ka = g.kx[a]; kb = g.kx[b]; }
+    else if (d == g.nx) { area = g.dx * g.dz; len = g.dy; ka = g.ky[a]; kb = g.ky[b]; }
+    else { area = g.dx * g.dy; len = g.dz; ka = g.kz[a]; kb = g.kz[b]; }
+    return f.tcoef * area / (len / (2.0 * ka) + len / (2.0 * kb));
+}
+
+__global__ void k_row_counts(int nx, int ny, int nz, int32_t *cnt) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = nx * ny * nz;
+    if (g >= n) return;
+    int c = 0;
+    for (int s = 0; s < NSLOT; s++) c += nbr_of(g, s, nx, ny, nz) >= 0;
+    cnt[g] = c;
+}
+
+__global__ void __launch_bounds__(kBlock) k_jac_cells(GridG G, Fl f, const double *__restrict__ xo,
+                                                       const double *__restrict__ xn, double acc,
+                                                       const int32_t *__restrict__ rowptr,
+                                                       int32_t *__restrict__ colind, double *__restrict__ val,
+                                                       double *__restrict__ b) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = G.nx * G.ny * G.nz;
+    if (g >= n) return;
+    Props c;
+    props_of(f, G.phi0[g], xn + 3 * (size_t)g, c);
+    double R[3], Jd[9];
+    {
+        Props co;
+        props_of(f, G.phi0[g], xo + 3 * (size_t)g, co);
+        double m1[3], dm1[3][3], m0[3], dd[3][3];
+        masses(c, m1, dm1, true);
+        masses(co, m0, dd, false);
+        for (int r = 0; r < 3; r++) R[r] = acc * (m1[r] - m0[r]);
+        for (int r = 0; r < 3; r++)
+            for (int s = 0; s < 3; s++) Jd[3 * r + s] = acc * dm1[r][s];
+    }
+    const double gg = f.gravity ? f.grav : 0.0;
+    const int row_of[4] = {0, 1, 2, 2};
+    const int phase_of[4] = {0, 1, 2, 0};
+    // faces in the order the lower-cell face loop visits them
+    const int order[6] = {S_MZ, S_MY, S_MX, S_PX, S_PY, S_PZ};
+    double Joff[6][9];
+    int nb_of[6];
+    for (int q = 0; q < 6; q++) {
+        int s = order[q];
+        int nb = nbr_of(g, s, G.nx, G.ny, G.nz);
+        nb_of[q] = nb;
+        for (int z = 0; z < 9; z++) Joff[q][z] = 0.0;
+        if (nb < 0) continue;
+        Props cn;
+        props_of(f, G.phi0[nb], xn + 3 * (size_t)nb, cn);
+        bool g_low = g < nb;
+        int l = g_low ? g : nb, h = g_low ? nb : g;
+        const Props &cl = g_low ? c : cn;
+        const Props &ch = g_low ? cn : c;
+        double T = trans(G, f, l, h);
+        double ddep = depth_of(G, l) - depth_of(G, h);
+        for (int st = 0; st < 4; st++) {
+            int ph = phase_of[st], row = row_of[st];
+            double rl, drl, rh, drh;
+            density(cl, ph, rl, drl);
+            density(ch, ph, rh, drh);
+            double rbar = 0.5 * (rl + rh);
+            double dphi = (cl.p - ch.p) - rbar * gg * ddep;
+            double dphi_pl = 1.0 - 0.5 * drl * gg * ddep;
+            double dphi_ph = -1.0 - 0.5 * drh * gg * ddep;
+            bool up_l = dphi >= 0.0;
+            double M, dM[3];
+            stream_q(up_l ? cl : ch, st, M, dM);
+            double F = T * M * dphi;
+            double dFl[3], dFh[3];
+            dFl[0] = T * M * dphi_pl;
+            dFh[0] = T * M * dphi_ph;
+            dFl[1] = dFl[2] = dFh[1] = dFh[2] = 0.0;
+            if (up_l) { for (int k = 0; k < 3; k++) dFl[k] = dFl[k] + T * dM[k] * dphi; }
+            else      { for (int k = 0; k < 3; k++) dFh[k] = dFh[k] + T * dM[k] * dphi; }
+            if (g_low) {
+                R[row] = R[row] + F;
+                for (int k = 0; k < 3; k++) {
+                    Jd[3 * row + k] = Jd[3 * row + k] + dFl[k];
+                    Joff[q][3 * row + k] = Joff[q][3 * row + k] + dFh[k];
+                }
+            } else {
+                R[row] = R[row] - F;
+                for (int k = 0; k < 3; k++) {
+                    Joff[q][3 * row + k] = Joff[q][3 * row + k] - dFl[k];
+                    Jd[3 * row + k] = Jd[3 * row + k] - dFh[k];
+                }
+            }
+        }
+    }
+    // write the block row in ascending column order: -z -y -x diag +x +y +z
+    int e = rowptr[g];
+    for (int q = 0; q < 3; q++) {
+        if (nb_of[q] < 0) continue;
+        colind[e] = nb_of[q];
+        for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Joff[q][z];
+        e++;
+    }
+    colind[e] = g;
+    for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Jd[z];
+    e++;
+    for (int q = 3; q < 6; q++) {
+        if (nb_of[q] < 0) continue;
+        colind[e] = nb_of[q];
+        for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Joff[q][z];
+        e++;
+    }
+    for (int r = 0; r < 3; r++) b[3 * (size_t)g + r] = -R[r];
+}
+
+// Peaceman well index of a perforated cell (Section 2.3)
+__device__ inline double well_index(const GridG &G, const Fl &f, int cell, double rw, double skin) {
+    double kx = G.kx[cell], ky = G.ky[cell];
+    double ryx = sqrt(ky / kx), rxy = sqrt(kx / ky);
+    double ro = 0.28 * sqrt(ryx * G.dx * G.dx + rxy * G.dy * G.dy) / (pow(ky / kx, 0.25) + pow(kx / ky, 0.25));
+    return f.tcoef * 2.0 * M_PI * sqrt(kx * ky) * G.dz / (log(ro / rw) + skin);
+}
+
+// One thread per well: subtract the source from R (b += q) and dq from the
+// diagonal block of each perforated cell.
+__global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nwells,
+                            const bo_well *__restrict__ wells, const int32_t *__restrict__ diag_pos,
+                            double *__restrict__ val, double *__restrict__ b) {
+    int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwells) return;
+    bo_well W = wells[w];
+    double gg = f.gravity ? f.grav : 0.0;
+    int top = W.i + G.nx * (W.j + G.ny * W.k_top);
+    double zh = depth_of(G, top);
+    for (int k = W.k_top; k <= W.k_bot; k++) {
+        int cell = W.i + G.nx * (W.j + G.ny * k);
+        Props c;
+        props_of(f, G.phi0[cell], xn + 3 * (size_t)cell, c);
+        double WI = well_index(G, f, cell, W.rw, W.skin);
+        double dz = zh - depth_of(G, cell);
+        double q[3] = {0.0, 0.0, 0.0}, dq[3][3];
+        for (int r = 0; r < 3; r++)
+            for (int s = 0; s < 3; s++) dq[r][s] = 0.0;
+        if (W.injector) {
+            double lt = c.lo + c.lw + c.lg;
+            double lt_w = c.lo_w + c.lw_w, lt_g = c.lo_g + c.lg_g;
+            if (!f.inj_total_mobility) { lt = c.lw; lt_w = c.lw_w; lt_g = 0.0; }
+            double dw = W.target - c.p - c.rw * gg * dz;
+            double dw_p = -1.0 - c.drw * gg * dz;
+            q[1] = WI * lt * c.bw * dw;
+            dq[1][0] = WI * lt * (c.dbw * dw + c.bw * dw_p);
+            dq[1][1] = WI * lt_w * c.bw * dw;
+            dq[1][2] = WI * lt_g * c.bw * dw;
+        } else {
+            double d_o = W.target - c.p - c.ro * gg * dz;
+            double d_w = W.target - c.p - c.rw * gg * dz;
+            double d_g = W.target - c.p - c.rg * gg * dz;
+            double do_p = -1.0 - c.dro * gg * dz;
+            double dw_p = -1.0 - c.drw * gg * dz;
+            double dg_p = -1.0 - c.drg * gg * dz;
+            q[0] = WI * c.lo * c.bo * d_o;
+            dq[0][0] = WI * c.lo * (c.dbo * d_o + c.bo * do_p);
+            dq[0][1] = WI * c.lo_w * c.bo * d_o;
+            dq[0][2] = WI * c.lo_g * c.bo * d_o;
+            q[1] = WI * c.lw * c.bw * d_w;
+            dq[1][0] = WI * c.lw * (c.dbw * d_w + c.bw * dw_p);
+            dq[1][1] = WI * c.lw_w * c.bw * d_w;
+            double qgf = WI * c.lg * c.bg * d_g;
+            q[2] = qgf + c.rs * q[0];
+            dq[2][0] = WI * c.lg * (c.dbg * d_g + c.bg * dg_p) + c.drs * q[0] + c.rs * dq[0][0];
+            dq[2][1] = c.rs * dq[0][1];
+            dq[2][2] = WI * c.lg_g * c.bg * d_g + c.rs * dq[0][2];
+        }
+        double *J = val + 9 * (size_t)diag_pos[cell];
+        for (int r = 0; r < 3; r++) {
+            b[3 * (size_t)cell + r] = b[3 * (size_t)cell + r] + q[r];
+            for (int s = 0; s < 3; s++) J[3 * r + s] = J[3 * r + s] - dq[r][s];
+        }
+    }
+}
+
+// position of the diagonal block of each row
+__global__ void k_diag_pos(int n, const int32_t *rowptr, const int32_t *colind, int32_t *pos) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    int p = -1;
+    for (int e = rowptr[g]; e < rowptr[g + 1]; e++)
+        if (colind[e] == g) p = e;
+    pos[g] = p;
+}
+
+}  // namespace
+}  // namespace bo
+
+using namespace bo;
+
+extern "C" bo_status bo_jacobian_bsr_size(const bo_problem *p, int32_t *nbrows, int32_t *nnzb) {
+    if (!p || !nbrows || !nnzb) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr_size: NULL argument");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(BO_ERR_INVALID_ARG, "grid dimensions must be >= 1");
+    long long n = (long long)p->nx * p->ny * p->nz;
+    long long faces = (long long)(p->nx - 1) * p->ny * p->nz + (long long)p->nx * (p->ny - 1) * p->nz +
+                      (long long)p->nx * p->ny * (p->nz - 1);
+    long long nnz = n + 2 * faces;
+    if (n >= (1LL << 31) / 7 || nnz >= (1LL << 31))
+        return fail(BO_ERR_INVALID_ARG, "grid too large for 32-bit block indices");
+    *nbrows = (int32_t)n;
+    *nnzb = (int32_t)nnz;
+    return BO_OK;
+}
+
+extern "C" bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, const double *x_new, double dt,
+                                     bo_bsr *J, double *b, void *stream) {
+    int32_t n, nnz;
+    BO_TRY(bo_jacobian_bsr_size(p, &n, &nnz));
+    if (!x_old || !x_new || !J || !b || !J->rowptr || !J->colind || !J->val)
+        return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL pointer");
+    if (!(dt > 0.0)) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: dt must be > 0");
+    if (!p->kx || !p->ky || !p->kz || !p->phi0) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL field");
+    if (p->nwells < 0 || (p->nwells > 0 && !p->wells)) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: wells");
+    // wells: validate on the host, no shared perforated cells
+    std::vector<long long> cells;
+    for (int w = 0; w < p->nwells; w++) {
+        const bo_well &W = p->wells[w];
+        if (W.control != 0) return fail(BO_ERR_UNSUPPORTED, "only fixed-BHP well control is supported");
+        if (W.i < 0 || W.i >= p->nx || W.j < 0 || W.j >= p->ny || W.k_top < 0 || W.k_bot >= p->nz ||
+            W.k_top > W.k_bot || !(W.rw > 0.0))
+            return fail(BO_ERR_INVALID_ARG, "well " + std::to_string(w) + " is outside the grid or malformed");
+        for (int k = W.k_top; k <= W.k_bot; k++) cells.push_back(W.i + (long long)p->nx * (W.j + (long long)p->ny * k));
+    }
+    std::vector<long long> sorted = cells;
+    std::sort(sorted.begin(), sorted.end());
+    for (size_t t = 1; t < sorted.size(); t++)
+        if (sorted[t] == sorted[t - 1]) return fail(BO_ERR_INVALID_ARG, "two perforations share a cell");
+    hipStream_t s = (hipStream_t)stream;
+    J->nbrows = n;
+    J->nnzb = nnz;
+    DBuf<int32_t> cnt;
+    BO_TRY(cnt.alloc(n));
+    k_row_counts<<<grid_for(n), kBlock, 0, s>>>(p->nx, p->ny, p->nz, cnt.p);
+    int32_t total = 0;
+    BO_TRY(scan_counts(cnt.p, J->rowptr, n, &total, s));
+    if (total != nnz) return fail(BO_ERR_HIP, "row count scan disagrees with the pattern size");
+    GridG G{p->nx, p->ny, p->nz, p->dx, p->dy, p->dz, p->top_depth, p->kx, p->ky, p->kz, p->phi0};
+    const bo_fluid &q = p->fluid;
+    Fl f{q.p_ref, q.Bw0, q.cw, q.Bo0, q.co, q.Bg0, q.cg, q.Rs0, q.crs, q.mu_w, q.mu_o, q.mu_g, q.c_r,
+         q.rho_wsc, q.rho_osc, q.rho_gsc, q.swc, q.sor, q.sorg, q.sgc, q.nw, q.no, q.ng,
+         q.tcoef, q.rb_ft3, q.grav, q.gravity, q.inj_total_mobility};
+    if (f.nw < 1 || f.no < 1 || f.ng < 1) return fail(BO_ERR_INVALID_ARG, "Corey exponents must be >= 1");
+    double acc = p->dx * p->dy * p->dz / (q.rb_ft3 * dt);
+    k_jac_cells<<<grid_for(n), kBlock, 0, s>>>(G, f, x_old, x_new, acc, J->rowptr, J->colind, J->val, b);
+    BO_HIP(hipGetLastError());
+    if (p->nwells > 0) {
+        DBuf<bo_well> dw;
+        DBuf<int32_t> dpos;
+        BO_TRY(dw.alloc(p->nwells));
+        BO_TRY(dpos.alloc(n));
+        BO_HIP(hipMemcpyAsync(dw.p, p->wells, sizeof(bo_well) * p->nwells, hipMemcpyHostToDevice, s));
+        k_diag_pos<<<grid_for(n), kBlock, 0, s>>>(n, J->rowptr, J->colind, dpos.p);
+        k_jac_wells<<<grid_for(p->nwells, 64), 64, 0, s>>>(G, f, x_new, p->nwells, dw.p, dpos.p, J->val, b);
+        BO_HIP(hipGetLastError());
+        // the temporaries are released when this call returns: wait for their users
+        BO_HIP(hipStreamSynchronize(s));
+    }
+    return BO_OK;
+}

@@ -1,0 +1,388 @@
+// Basic operations of Section 3.4 on the GPU: y = alpha A x + beta y (BSR and
+// the library's slot layout), y = alpha x + beta y, dot products and norms,
+// plus the prefix sums the setup phases need.
+//
+// Slot layout of a 7-point 3x3-block matrix: val[(s*9 + e)*N + i] holds entry
+// e (row-major in the block) of the block of row i in slot s (-z,-y,-x,diag,
+// +x,+y,+z).  Consecutive threads own consecutive rows, so every one of the 63
+// value streams is read fully coalesced; blocks outside the grid are zero and
+// are skipped.
+//
+// Reductions are deterministic: a fixed grid of workgroups writes per-group
+// partial sums in a fixed tree order, and the last group to finish (found with
+// an atomic ticket) adds the partials in index order.
+#include <algorithm>
+#include "bo_common.hpp"
+#include "bo_linalg.hpp"
+
+namespace bo {
+
+static thread_local std::string g_err = "no error";
+
+void set_error(const std::string &msg) { g_err = msg; }
+bo_status fail(bo_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+// ---- scan ------------------------------------------------------------------
+constexpr int kScanBlock = 1024;
+
+__global__ void k_block_sums(const int32_t *in, int n, int32_t *sums) {
+    __shared__ int32_t sh[kScanBlock];
+    int base = blockIdx.x * kScanBlock;
+    int t = threadIdx.x;
+    sh[t] = base + t < n ? in[base + t] : 0;
+    __syncthreads();
+    for (int w = kScanBlock / 2; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) sums[blockIdx.x] = sh[0];
+}
+
+// exclusive scan of `sums` (nb entries) in one workgroup, sequential chunks
+__global__ void k_scan_sums(int32_t *sums, int nb) {
+    __shared__ int32_t sh[kScanBlock];
+    __shared__ int32_t carry;
+    int t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += kScanBlock) {
+        int v = base + t < nb ? sums[base + t] : 0;
+        sh[t] = v;
+        __syncthreads();
+        for (int off = 1; off < kScanBlock; off <<= 1) {
+            int a = t >= off ? sh[t - off] : 0;
+            __syncthreads();
+            sh[t] += a;
+            __syncthreads();
+        }
+        if (base + t < nb) sums[base + t] = carry + sh[t] - v;
+        __syncthreads();
+        if (t == kScanBlock - 1) carry += sh[t];
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan_apply(const int32_t *in, int n, const int32_t *sums, int32_t *out) {
+    __shared__ int32_t sh[kScanBlock];
+    int base = blockIdx.x * kScanBlock;
+    int t = threadIdx.x;
+    int v = base + t < n ? in[base + t] : 0;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        int a = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    if (base + t < n) out[base + t] = sums[blockIdx.x] + sh[t] - v;
+    if (base + t == n - 1) out[n] = sums[blockIdx.x] + sh[t];
+}
+
+bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s) {
+    if (n <= 0) {
+        int32_t z = 0;
+        BO_HIP(hipMemcpyAsync(out, &z, sizeof z, hipMemcpyHostToDevice, s));
+        BO_HIP(hipStreamSynchronize(s));
+        if (total) *total = 0;
+        return BO_OK;
+    }
+    int nb = (n + kScanBlock - 1) / kScanBlock;
+    DBuf<int32_t> sums;
+    BO_TRY(sums.alloc(nb));
+    k_block_sums<<<nb, kScanBlock, 0, s>>>(counts, n, sums.p);
+    k_scan_sums<<<1, kScanBlock, 0, s>>>(sums.p, nb);
+    k_scan_apply<<<nb, kScanBlock, 0, s>>>(counts, n, sums.p, out);
+    BO_HIP(hipGetLastError());
+    int32_t tot = 0;
+    BO_HIP(hipMemcpyAsync(&tot, out + n, sizeof tot, hipMemcpyDeviceToHost, s));
+    BO_HIP(hipStreamSynchronize(s));
+    if (total) *total = tot;
+    return BO_OK;
+}
+
+// ---- BSR SpMV on the ABI layout ---------------------------------------------
+__global__ void k_bsr_spmv(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ v, double alpha, const double *__restrict__ x,
+                           double beta, double *__restrict__ y) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int e = rp[i]; e < rp[i + 1]; e++) {
+        const double *blk = v + 9 * (size_t)e;
+        const double *xj = x + 3 * (size_t)ci[e];
+        double x0 = xj[0], x1 = xj[1], x2 = xj[2];
+        for (int r = 0; r < 3; r++) {
+            s[r] = s[r] + blk[3 * r] * x0;
+            s[r] = s[r] + blk[3 * r + 1] * x1;
+            s[r] = s[r] + blk[3 * r + 2] * x2;
+        }
+    }
+    for (int r = 0; r < 3; r++) {
+        double yi = beta == 0.0 ? 0.0 : beta * y[3 * (size_t)i + r];
+        y[3 * (size_t)i + r] = alpha * s[r] + yi;
+    }
+}
+
+// ---- BSR -> slot layout -------------------------------------------------------
+__global__ void k_bsr_to_slots(int nx, int ny, int nz, const int32_t *__restrict__ rp,
+                               const int32_t *__restrict__ ci, const double *__restrict__ v,
+                               double *__restrict__ slots, int32_t *__restrict__ bad) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = nx * ny * nz;
+    if (i >= n) return;
+    size_t N = (size_t)n;
+    int e = rp[i], end = rp[i + 1];
+    for (int s = 0; s < NSLOT; s++) {
+        int nb = nbr_of(i, s, nx, ny, nz);
+        bool have = nb >= 0 && e < end && ci[e] == nb;
+        for (int z = 0; z < 9; z++) slots[((size_t)s * 9 + z) * N + i] = have ? v[9 * (size_t)e + z] : 0.0;
+        if (have) e++;
+        else if (nb >= 0) *bad = 1;  // a stencil neighbour is missing from the pattern
+    }
+    if (e != end) *bad = 1;          // entries outside the 7-point stencil
+}
+
+// y = alpha A x + beta y on the slot layout.  Each row sums its blocks in
+// ascending column order and each block's entries in ascending order.
+__global__ void __launch_bounds__(kBlock) k_slot_spmv(int nx, int ny, int nz, const double *__restrict__ A,
+                                                      double alpha, const double *__restrict__ x, double beta,
+                                                      double *__restrict__ y) {
+    int n = nx * ny * nz;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    size_t N = (size_t)n;
+    int nxy = nx * ny;
+    int ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
+                       ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NSLOT; s++) {
+        int j = nb[s];
+        if (j < 0) continue;
+        const double *a = A + (size_t)s * 9 * N + i;
+        double x0 = x[3 * (size_t)j], x1 = x[3 * (size_t)j + 1], x2 = x[3 * (size_t)j + 2];
+        s0 = s0 + a[0 * N] * x0; s0 = s0 + a[1 * N] * x1; s0 = s0 + a[2 * N] * x2;
+        s1 = s1 + a[3 * N] * x0; s1 = s1 + a[4 * N] * x1; s1 = s1 + a[5 * N] * x2;
+        s2 = s2 + a[6 * N] * x0; s2 = s2 + a[7 * N] * x1; s2 = s2 + a[8 * N] * x2;
+    }
+    double *yi = y + 3 * (size_t)i;
+    if (beta == 0.0) {
+        yi[0] = alpha * s0 + 0.0; yi[1] = alpha * s1 + 0.0; yi[2] = alpha * s2 + 0.0;
+    } else {
+        yi[0] = alpha * s0 + beta * yi[0];
+        yi[1] = alpha * s1 + beta * yi[1];
+        yi[2] = alpha * s2 + beta * yi[2];
+    }
+}
+
+// r = v - A (Pi_p dp): only column 0 of each block is needed.
+__global__ void __launch_bounds__(kBlock) k_slot_col0_residual(int nx, int ny, int nz,
+                                                               const double *__restrict__ A,
+                                                               const double *__restrict__ v,
+                                                               const double *__restrict__ dp,
+                                                               double *__restrict__ r) {
+    int n = nx * ny * nz;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    size_t N = (size_t)n;
+    int nxy = nx * ny;
+    int ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
+                       ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NSLOT; s++) {
+        int j = nb[s];
+        if (j < 0) continue;
+        const double *a = A + (size_t)s * 9 * N + i;
+        double p = dp[j];
+        s0 = s0 + a[0 * N] * p;
+        s1 = s1 + a[3 * N] * p;
+        s2 = s2 + a[6 * N] * p;
+    }
+    r[3 * (size_t)i] = v[3 * (size_t)i] - s0;
+    r[3 * (size_t)i + 1] = v[3 * (size_t)i + 1] - s1;
+    r[3 * (size_t)i + 2] = v[3 * (size_t)i + 2] - s2;
+}
+
+// ---- BLAS-1 -------------------------------------------------------------------
+__global__ void k_axpby(long long n, double a, const double *__restrict__ x, double b, double *__restrict__ y) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
+}
+
+__global__ void k_fill(long long n, double v, double *__restrict__ y) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+// Multi-dot: out[q] = sum_e x[e] * V[q][e] for q < nv (nv <= NV), in the
+// fixed partial-sum order described at the top of this file.
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_multidot(long long n, const double *__restrict__ x, VecList V, int nv,
+                                                     double *__restrict__ partial, unsigned *__restrict__ ticket,
+                                                     double *__restrict__ out) {
+    __shared__ double sh[kBlock];
+    __shared__ bool last;
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) acc[q] = 0.0;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        double xe = x[e];
+#pragma unroll
+        for (int q = 0; q < NV; q++)
+            if (q < nv) acc[q] = acc[q] + xe * V.p[q][e];
+    }
+    for (int q = 0; q < nv; q++) {
+        double s = block_sum(acc[q], sh);
+        if (threadIdx.x == 0) partial[(size_t)q * gridDim.x + blockIdx.x] = s;
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int q = 0; q < nv; q++) {
+        double s = 0.0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
+            s = s + ((volatile const double *)partial)[(size_t)q * gridDim.x + b];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) out[q] = s;
+    }
+    if (threadIdx.x == 0) *ticket = 0u;
+}
+
+// y = y + sign * sum_q h[q] * V[q]  (h on the device)
+__global__ void __launch_bounds__(kBlock) k_multiaxpy(long long n, VecList V, int nv,
+                                                      const double *__restrict__ h, double sign,
+                                                      double *__restrict__ y) {
+    __shared__ double hs[kMaxVecList];
+    if (threadIdx.x < nv) hs[threadIdx.x] = sign * h[threadIdx.x];
+    __syncthreads();
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        double s = 0.0;
+        for (int q = 0; q < nv; q++) s = s + hs[q] * V.p[q][e];
+        y[e] = y[e] + s;
+    }
+}
+
+__global__ void k_scale_copy(long long n, const double *__restrict__ inv, const double *__restrict__ x,
+                             double *__restrict__ y) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i] * inv[0];
+}
+
+// ---- host wrappers -------------------------------------------------------------
+bo_status slot_spmv(const Grid &g, const double *A, double alpha, const double *x, double beta, double *y,
+                    hipStream_t s) {
+    long long n = g.n();
+    k_slot_spmv<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, alpha, x, beta, y);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, const double *dp, double *r,
+                             hipStream_t s) {
+    long long n = g.n();
+    k_slot_col0_residual<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, v, dp, r);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
+                       hipStream_t s) {
+    long long n = g.n();
+    DBuf<int32_t> bad;
+    BO_TRY(bad.alloc(1));
+    BO_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+    k_bsr_to_slots<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, rp, ci, v, slots, bad.p);
+    BO_HIP(hipGetLastError());
+    int32_t h = 0;
+    BO_HIP(hipMemcpyAsync(&h, bad.p, sizeof h, hipMemcpyDeviceToHost, s));
+    BO_HIP(hipStreamSynchronize(s));
+    if (h) return fail(BO_ERR_UNSUPPORTED, "matrix pattern is not the 7-point stencil of the grid");
+    return BO_OK;
+}
+
+bo_status axpby(long long n, double a, const double *x, double b, double *y, hipStream_t s) {
+    k_axpby<<<grid_for(n), kBlock, 0, s>>>(n, a, x, b, y);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status fill(long long n, double v, double *y, hipStream_t s) {
+    k_fill<<<grid_for(n), kBlock, 0, s>>>(n, v, y);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status multiaxpy(long long n, const double *const *Vhost, int nv, const double *h, double sign, double *y,
+                    hipStream_t s) {
+    if (nv > kMaxVecList || nv < 1) return fail(BO_ERR_INVALID_ARG, "multiaxpy: 1..64 vectors");
+    VecList L{};
+    for (int q = 0; q < nv; q++) L.p[q] = Vhost[q];
+    long long blocks = std::min<long long>((n + kBlock - 1) / kBlock, 4096);
+    k_multiaxpy<<<(unsigned)std::max<long long>(blocks, 1), kBlock, 0, s>>>(n, L, nv, h, sign, y);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status scale_copy(long long n, const double *inv, const double *x, double *y, hipStream_t s) {
+    k_scale_copy<<<grid_for(n), kBlock, 0, s>>>(n, inv, x, y);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status Reducer::init() {
+    BO_TRY(partial.alloc((size_t)kRedBlocks * 16));
+    BO_TRY(ticket.alloc(1));
+    BO_HIP(hipMemset(ticket.p, 0, sizeof(unsigned)));
+    return BO_OK;
+}
+
+bo_status Reducer::multidot(long long n, const double *x, const double *const *Vhost, int nv, double *out,
+                            hipStream_t s) {
+    for (int q0 = 0; q0 < nv; q0 += 16) {
+        int c = std::min(16, nv - q0);
+        VecList L{};
+        for (int q = 0; q < c; q++) L.p[q] = Vhost[q0 + q];
+        k_multidot<16><<<kRedBlocks, kBlock, 0, s>>>(n, x, L, c, partial.p, ticket.p, out + q0);
+    }
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status Reducer::dot(long long n, const double *x, const double *y, double *out, hipStream_t s) {
+    VecList L{};
+    L.p[0] = y;
+    k_multidot<1><<<kRedBlocks, kBlock, 0, s>>>(n, x, L, 1, partial.p, ticket.p, out);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+}  // namespace bo
+
+using namespace bo;
+
+extern "C" const char *bo_last_error(void) { return g_err.c_str(); }
+extern "C" const char *bo_version(void) { return "bo 0.1 (gfx950)"; }
+
+extern "C" bo_status bo_bsr_spmv(const bo_bsr *A, double alpha, const double *x, double beta, double *y,
+                                 void *stream) {
+    if (!A || !x || !y || !A->rowptr || !A->colind || !A->val || A->nbrows < 0)
+        return fail(BO_ERR_INVALID_ARG, "bo_bsr_spmv: NULL argument");
+    if (A->nbrows == 0) return BO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    k_bsr_spmv<<<grid_for(A->nbrows), kBlock, 0, s>>>(A->nbrows, A->rowptr, A->colind, A->val, alpha, x, beta, y);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}

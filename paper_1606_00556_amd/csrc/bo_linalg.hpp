@@ -1,0 +1,39 @@
+// Host wrappers of the basic GPU operations (internal).
+#pragma once
+#include "bo_common.hpp"
+
+namespace bo {
+
+bo_status slot_spmv(const Grid &g, const double *A, double alpha, const double *x, double beta, double *y,
+                    hipStream_t s);
+bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, const double *dp, double *r,
+                             hipStream_t s);
+bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
+                       hipStream_t s);
+bo_status axpby(long long n, double a, const double *x, double b, double *y, hipStream_t s);
+bo_status fill(long long n, double v, double *y, hipStream_t s);
+constexpr int kMaxVecList = 64;
+// A list of device vectors passed to a kernel by value.
+struct VecList {
+    const double *p[kMaxVecList];
+};
+
+// y += sign * sum_q h[q] V[q]; Vhost: host array of nv device pointers, h on the device
+bo_status multiaxpy(long long n, const double *const *Vhost, int nv, const double *h, double sign, double *y,
+                    hipStream_t s);
+bo_status scale_copy(long long n, const double *inv, const double *x, double *y, hipStream_t s);
+
+constexpr int kRedBlocks = 1024;  // fixed reduction grid (determinism)
+
+// Deterministic dot products; results land in device memory.
+struct Reducer {
+    DBuf<double> partial;
+    DBuf<unsigned> ticket;
+    bo_status init();
+    // out[q] = <x, V[q]>, q < nv; Vhost is a host array of device pointers
+    bo_status multidot(long long n, const double *x, const double *const *Vhost, int nv, double *out,
+                       hipStream_t s);
+    bo_status dot(long long n, const double *x, const double *y, double *out, hipStream_t s);
+};
+
+}  // namespace bo

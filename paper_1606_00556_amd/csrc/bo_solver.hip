@@ -1,0 +1,382 @@
+// CPR preconditioner assembly and application, and flexible GMRES.
+//
+// CPR (Section 3.2): the two-stage form applies the pressure stage and then
+// the F stage to the remaining residual,
+//     x1 = Pi_p AMG(A_pp)^{-1} Pi_r v,   x = x1 + F(v - A x1);
+// Algorithm CPR-FPF adds an F stage in front:
+//     x = F(v); x += Pi_p AMG^{-1} Pi_r (v - A x); x += F(v - A x).
+// Pi_r is the quasi-IMPES restriction (c_i . v_i), Pi_p puts a pressure value
+// in the Po slot.  In the two-stage form v - A x1 needs only column 0 of each
+// block.
+//
+// FGMRES(m) (Krylov solver of Section 3.3, flexible variant so that the
+// preconditioner may change between iterations) runs on the original system,
+// right-preconditioned, so its implicit residual is the true residual.  The
+// Hessenberg column is formed on the device (deterministic reductions), read
+// back once per iteration, and the Givens rotations and the small triangular
+// solve run on the host.
+#include <cmath>
+#include <cstring>
+#include "bo_cpr.hpp"
+
+namespace bo {
+bo_status qi_decouple(bo_cpr *pc, hipStream_t s);
+bo_status qi_restrict(bo_cpr *pc, const double *v, double *rp, hipStream_t s);
+bo_status amg_setup(bo_cpr *pc, hipStream_t s);
+bo_status amg_vcycle(bo_cpr *pc, const double *b, double *x, hipStream_t s);
+bo_status fstage_setup(bo_cpr *pc, hipStream_t s);
+bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, double *wbuf, hipStream_t s);
+
+namespace {
+
+__global__ void k_check_finite(long long n, const double *__restrict__ v, int32_t *__restrict__ bad) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(v[i])) *bad = 1;
+}
+
+__global__ void k_add_p(long long n, const double *__restrict__ dp, double *__restrict__ z) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[3 * i] = z[3 * i] + dp[i];
+}
+
+}  // namespace
+
+bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
+    long long n = pc->n;
+    const Grid &g = pc->g;
+    if (!pc->o.fpf) {
+        if (pc->o.use_amg) {
+            BO_TRY(qi_restrict(pc, v, pc->rp_.p, s));
+            BO_TRY(amg_vcycle(pc, pc->rp_.p, pc->dp_.p, s));
+            BO_TRY(slot_col0_residual(g, pc->A.p, v, pc->dp_.p, pc->t3a.p, s));
+            return fstage_apply(pc, pc->t3a.p, pc->dp_.p, z, pc->wf.p, s);
+        }
+        return fstage_apply(pc, v, nullptr, z, pc->wf.p, s);
+    }
+    // FPF
+    BO_TRY(fstage_apply(pc, v, nullptr, z, pc->wf.p, s));
+    if (pc->o.use_amg) {
+        BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+        BO_TRY(slot_spmv(g, pc->A.p, -1.0, z, 1.0, pc->t3a.p, s));
+        BO_TRY(qi_restrict(pc, pc->t3a.p, pc->rp_.p, s));
+        BO_TRY(amg_vcycle(pc, pc->rp_.p, pc->dp_.p, s));
+        k_add_p<<<grid_for(n), kBlock, 0, s>>>(n, pc->dp_.p, z);
+        BO_HIP(hipGetLastError());
+    }
+    BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    BO_TRY(slot_spmv(g, pc->A.p, -1.0, z, 1.0, pc->t3a.p, s));
+    BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, pc->t3b.p, pc->wf.p, s));
+    return axpby(3 * n, 1.0, pc->t3b.p, 1.0, z, s);
+}
+
+}  // namespace bo
+
+using namespace bo;
+
+extern "C" void bo_cpr_default_opts(bo_cpr_opts *o) {
+    if (!o) return;
+    o->fpf = 0;
+    o->ftype = BO_F_ILU_TILED;
+    o->tile_x = 8;
+    o->tile_y = 8;
+    o->theta = 0.08;
+    o->coarse_max = 256;
+    o->max_levels = 12;
+    o->smoother = BO_SMOOTH_GS;
+    o->sweeps = 1;
+    o->use_amg = 1;
+    o->qi_mode = BO_QI_BLOCK;
+    o->precision = BO_PREC_FP64;
+}
+
+extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
+    if (!o) return;
+    o->m = 30;
+    o->maxit = 1500;
+    o->rtol = 1e-6;
+    o->orth = 1;
+}
+
+static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc,
+                            hipStream_t s) {
+    pc->g = Grid{grid->nx, grid->ny, grid->nz};
+    pc->n = (int)pc->g.n();
+    pc->o = *opts;
+    long long n = pc->n;
+    BO_TRY(pc->flag.alloc(1));
+    BO_TRY(pc->A.alloc(63 * n));
+    // inputs must be finite
+    BO_HIP(hipMemsetAsync(pc->flag.p, 0, sizeof(int32_t), s));
+    k_check_finite<<<grid_for(9LL * A->nnzb), kBlock, 0, s>>>(9LL * A->nnzb, A->val, pc->flag.p);
+    BO_HIP(hipGetLastError());
+    int32_t bad = 0;
+    BO_HIP(hipMemcpyAsync(&bad, pc->flag.p, sizeof bad, hipMemcpyDeviceToHost, s));
+    BO_HIP(hipStreamSynchronize(s));
+    if (bad) return fail(BO_ERR_NONFINITE, "bo_cpr_setup: the matrix holds NaN or Inf");
+    BO_TRY(bsr_to_slots(pc->g, A->rowptr, A->colind, A->val, pc->A.p, s));
+    BO_TRY(qi_decouple(pc, s));
+    if (pc->o.use_amg) BO_TRY(amg_setup(pc, s));
+    BO_TRY(fstage_setup(pc, s));
+    BO_TRY(pc->rp_.alloc(n));
+    BO_TRY(pc->dp_.alloc(n));
+    BO_TRY(pc->t3a.alloc(3 * n));
+    BO_TRY(pc->t3b.alloc(3 * n));
+    BO_TRY(pc->t3c.alloc(3 * n));
+    BO_TRY(pc->wf.alloc(3 * n));
+    BO_TRY(pc->red.init());
+    BO_HIP(hipStreamSynchronize(s));
+    return BO_OK;
+}
+
+extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
+                                  bo_cpr **out, void *stream) {
+    if (!out) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: out is NULL");
+    *out = nullptr;
+    if (!A || !grid || !opts || !A->rowptr || !A->colind || !A->val)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: NULL argument");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 ||
+        (long long)grid->nx * grid->ny * grid->nz != (long long)A->nbrows)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: grid does not match the matrix size");
+    if ((long long)A->nbrows * 7 >= (1LL << 31)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: matrix too large");
+    const bo_cpr_opts &o = *opts;
+    if (o.ftype != BO_F_BJ && o.ftype != BO_F_ILU_TILED)
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: F stage must be BO_F_BJ or BO_F_ILU_TILED");
+    if (o.ftype == BO_F_ILU_TILED && (o.tile_x < 1 || o.tile_y < 1 || o.tile_x * o.tile_y > 64))
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: tiles need 1 <= tile_x*tile_y <= 64");
+    if (o.use_amg && (o.coarse_max < 1 || o.coarse_max > kCoarseMaxLimit || !(o.theta >= 0.0) ||
+                      o.sweeps < 1 || o.sweeps > 8 || o.max_levels < 1))
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: AMG options out of range");
+    if (o.smoother != BO_SMOOTH_GS && o.smoother != BO_SMOOTH_JACOBI)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown smoother");
+    if (o.qi_mode != BO_QI_DIAG && o.qi_mode != BO_QI_BLOCK)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown quasi-IMPES mode");
+    if (o.precision != BO_PREC_FP64)
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: this precision is not available");
+    bo_cpr *pc = new (std::nothrow) bo_cpr();
+    if (!pc) return fail(BO_ERR_ALLOC, "bo_cpr_setup: out of host memory");
+    bo_status st = setup_impl(A, grid, opts, pc, (hipStream_t)stream);
+    if (st != BO_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        delete pc;
+        return st;
+    }
+    *out = pc;
+    return BO_OK;
+}
+
+extern "C" void bo_cpr_destroy(bo_cpr *pc) {
+    if (!pc) return;
+    (void)hipDeviceSynchronize();
+    delete pc;
+}
+
+extern "C" bo_status bo_cpr_apply(bo_cpr *pc, const double *v, double *z, void *stream) {
+    if (!pc || !v || !z) return fail(BO_ERR_INVALID_ARG, "bo_cpr_apply: NULL argument");
+    return cpr_apply(pc, v, z, (hipStream_t)stream);
+}
+
+extern "C" bo_status bo_cpr_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, void *stream) {
+    if (!pc || !x || !y) return fail(BO_ERR_INVALID_ARG, "bo_cpr_spmv: NULL argument");
+    return slot_spmv(pc->g, pc->A.p, alpha, x, beta, y, (hipStream_t)stream);
+}
+
+extern "C" bo_status bo_cpr_restrict(bo_cpr *pc, const double *v, double *rp, void *stream) {
+    if (!pc || !v || !rp) return fail(BO_ERR_INVALID_ARG, "bo_cpr_restrict: NULL argument");
+    return qi_restrict(pc, v, rp, (hipStream_t)stream);
+}
+
+extern "C" bo_status bo_cpr_vcycle(bo_cpr *pc, const double *b, double *x, void *stream) {
+    if (!pc || !b || !x) return fail(BO_ERR_INVALID_ARG, "bo_cpr_vcycle: NULL argument");
+    if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_vcycle: built without AMG");
+    return amg_vcycle(pc, b, x, (hipStream_t)stream);
+}
+
+extern "C" bo_status bo_cpr_fstage(bo_cpr *pc, const double *r, double *x, void *stream) {
+    if (!pc || !r || !x) return fail(BO_ERR_INVALID_ARG, "bo_cpr_fstage: NULL argument");
+    return fstage_apply(pc, r, nullptr, x, pc->wf.p, (hipStream_t)stream);
+}
+
+extern "C" bo_status bo_cpr_levels(bo_cpr *pc, int32_t *nlevels) {
+    if (!pc || !nlevels) return fail(BO_ERR_INVALID_ARG, "bo_cpr_levels: NULL argument");
+    *nlevels = pc->o.use_amg ? pc->nlev : 0;
+    return BO_OK;
+}
+
+extern "C" bo_status bo_cpr_level_info(bo_cpr *pc, int32_t l, int32_t *n, int32_t *nnz, int32_t *pnnz,
+                                       double *omega) {
+    if (!pc || l < 0 || l >= pc->nlev) return fail(BO_ERR_INVALID_ARG, "bo_cpr_level_info: bad level");
+    const Level &L = pc->lv[l];
+    bool last = l == pc->nlev - 1;
+    if (n) *n = L.n;
+    if (nnz) *nnz = L.nnz;
+    if (pnnz) *pnnz = last ? 0 : L.pnnz;
+    if (omega) *omega = last ? 0.0 : L.omega;
+    return BO_OK;
+}
+
+extern "C" bo_status bo_cpr_level_copy(bo_cpr *pc, int32_t l, int32_t *rowptr, int32_t *colind, double *val,
+                                       int32_t *agg, uint8_t *root, int32_t *prowptr, int32_t *pcolind,
+                                       double *pval) {
+    if (!pc || l < 0 || l >= pc->nlev) return fail(BO_ERR_INVALID_ARG, "bo_cpr_level_copy: bad level");
+    const Level &L = pc->lv[l];
+    bool last = l == pc->nlev - 1;
+    BO_HIP(hipDeviceSynchronize());
+    if (rowptr) BO_HIP(hipMemcpy(rowptr, L.rp.p, sizeof(int32_t) * (L.n + 1), hipMemcpyDeviceToHost));
+    if (colind) BO_HIP(hipMemcpy(colind, L.ci.p, sizeof(int32_t) * L.nnz, hipMemcpyDeviceToHost));
+    if (val) BO_HIP(hipMemcpy(val, L.v.p, sizeof(double) * L.nnz, hipMemcpyDeviceToHost));
+    if (!last) {
+        if (agg) BO_HIP(hipMemcpy(agg, L.agg.p, sizeof(int32_t) * L.n, hipMemcpyDeviceToHost));
+        if (root) BO_HIP(hipMemcpy(root, L.root.p, L.n, hipMemcpyDeviceToHost));
+        if (prowptr) BO_HIP(hipMemcpy(prowptr, L.prp.p, sizeof(int32_t) * (L.n + 1), hipMemcpyDeviceToHost));
+        if (pcolind) BO_HIP(hipMemcpy(pcolind, L.pci.p, sizeof(int32_t) * L.pnnz, hipMemcpyDeviceToHost));
+        if (pval) BO_HIP(hipMemcpy(pval, L.pv.p, sizeof(double) * L.pnnz, hipMemcpyDeviceToHost));
+    }
+    return BO_OK;
+}
+
+extern "C" bo_status bo_cpr_copy_weights(bo_cpr *pc, double *c) {
+    if (!pc || !c) return fail(BO_ERR_INVALID_ARG, "bo_cpr_copy_weights: NULL argument");
+    BO_HIP(hipDeviceSynchronize());
+    BO_HIP(hipMemcpy(c, pc->cw.p, sizeof(double) * 3 * pc->n, hipMemcpyDeviceToHost));
+    return BO_OK;
+}
+
+// ---- FGMRES ---------------------------------------------------------------------
+namespace {
+
+bo_status krylov_alloc(bo_cpr *pc, int m) {
+    Krylov &K = pc->kr;
+    long long len = 3LL * pc->n;
+    if (K.m == m && K.len == len) return BO_OK;
+    K.m = 0;
+    BO_TRY(K.V.alloc((size_t)(m + 1) * len));
+    BO_TRY(K.Z.alloc((size_t)m * len));
+    BO_TRY(K.h.alloc(2 * (m + 1) + 1));
+    BO_TRY(K.y.alloc(m + 1));
+    if (K.host) (void)hipHostFree(K.host);
+    K.host = nullptr;
+    BO_HIP(hipHostMalloc((void **)&K.host, sizeof(double) * (3 * m + 4), hipHostMallocDefault));
+    K.vptr.resize(m + 1);
+    K.zptr.resize(m);
+    for (int i = 0; i <= m; i++) K.vptr[i] = K.V.p + (size_t)i * len;
+    for (int i = 0; i < m; i++) K.zptr[i] = K.Z.p + (size_t)i * len;
+    K.m = m;
+    K.len = len;
+    return BO_OK;
+}
+
+}  // namespace
+
+extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, const bo_fgmres_opts *opts,
+                                     bo_solve_stats *stats, void *stream) {
+    if (!pc || !b || !x || !opts) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: NULL argument");
+    int m = opts->m;
+    if (m < 1 || m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || (opts->orth != 0 && opts->orth != 1))
+        return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
+    hipStream_t s = (hipStream_t)stream;
+    bo_solve_stats st{};
+    BO_TRY(krylov_alloc(pc, m));
+    Krylov &K = pc->kr;
+    const long long len = K.len;
+    const Grid &g = pc->g;
+    double *V = K.V.p, *Z = K.Z.p;
+    double *hd = K.h.p;                 // [0, m+1): h1, [m+1, 2m+2): h2, [2m+2]: |w|^2
+    double *hh = K.host;                // pinned copies of hd
+    double *yh = K.host + 2 * m + 3;    // pinned update coefficients
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1);
+    auto fetch = [&](int count) -> bo_status {
+        BO_HIP(hipMemcpyAsync(hh, hd, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+        BO_HIP(hipStreamSynchronize(s));
+        return BO_OK;
+    };
+    // ||b||
+    BO_TRY(pc->red.dot(len, b, b, hd, s));
+    BO_TRY(fetch(1));
+    double bnorm = std::sqrt(hh[0]);
+    if (!std::isfinite(bnorm)) {
+        if (stats) *stats = st;
+        return fail(BO_ERR_NONFINITE, "bo_fgmres_solve: right-hand side holds NaN or Inf");
+    }
+    if (bnorm == 0.0) {
+        BO_TRY(fill(len, 0.0, x, s));
+        BO_HIP(hipStreamSynchronize(s));
+        st.converged = 1;
+        if (stats) *stats = st;
+        return BO_OK;
+    }
+    double tol = opts->rtol * bnorm;
+    int its = 0;
+    bo_status status = BO_NOT_CONVERGED;
+    for (;;) {
+        // r = b - A x into V[0]
+        BO_HIP(hipMemcpyAsync(V, b, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
+        BO_TRY(slot_spmv(g, pc->A.p, -1.0, x, 1.0, V, s));
+        BO_TRY(pc->red.dot(len, V, V, hd, s));
+        BO_TRY(fetch(1));
+        double beta = std::sqrt(hh[0]);
+        st.rel_residual = beta / bnorm;
+        if (!std::isfinite(beta)) { status = fail(BO_ERR_NONFINITE, "bo_fgmres_solve: residual is not finite"); break; }
+        if (beta <= tol) { st.converged = 1; status = BO_OK; break; }
+        if (its >= opts->maxit) break;
+        if (its > 0) st.restarts++;
+        BO_TRY(axpby(len, 1.0 / beta, V, 0.0, V, s));
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; j++) {
+            double *vj = V + (size_t)j * len, *zj = Z + (size_t)j * len, *w = V + (size_t)(j + 1) * len;
+            BO_TRY(cpr_apply(pc, vj, zj, s));
+            its++;
+            BO_TRY(slot_spmv(g, pc->A.p, 1.0, zj, 0.0, w, s));
+            int nv = j + 1;
+            if (opts->orth == 1) {
+                BO_TRY(pc->red.multidot(len, w, K.vptr.data(), nv, hd, s));
+                BO_TRY(multiaxpy(len, K.vptr.data(), nv, hd, -1.0, w, s));
+                BO_TRY(pc->red.multidot(len, w, K.vptr.data(), nv, hd + (m + 1), s));
+                BO_TRY(multiaxpy(len, K.vptr.data(), nv, hd + (m + 1), -1.0, w, s));
+            } else {
+                for (int i = 0; i < nv; i++) {
+                    BO_TRY(pc->red.multidot(len, w, K.vptr.data() + i, 1, hd + i, s));
+                    BO_TRY(multiaxpy(len, K.vptr.data() + i, 1, hd + i, -1.0, w, s));
+                }
+            }
+            BO_TRY(pc->red.dot(len, w, w, hd + 2 * (m + 1), s));
+            BO_TRY(fetch(2 * (m + 1) + 1));
+            double hn = std::sqrt(hh[2 * (m + 1)]);
+            for (int i = 0; i <= j; i++)
+                H[(size_t)i * m + j] = opts->orth == 1 ? hh[i] + hh[m + 1 + i] : hh[i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            bool breakdown = !(hn > 1e-300);
+            if (!std::isfinite(hn)) { status = fail(BO_ERR_NONFINITE, "bo_fgmres_solve: NaN in the iteration"); goto done; }
+            if (!breakdown) BO_TRY(axpby(len, 1.0 / hn, w, 0.0, w, s));
+            for (int i = 0; i < j; i++) {
+                double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+            double den = std::hypot(a, bb);
+            cs[j] = a / den;
+            sn[j] = bb / den;
+            H[(size_t)j * m + j] = cs[j] * a + sn[j] * bb;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            k = j + 1;
+            st.est_residual = std::fabs(gv[j + 1]) / bnorm;
+            if (std::fabs(gv[j + 1]) <= tol || its >= opts->maxit || breakdown) break;
+        }
+        for (int i = k - 1; i >= 0; i--) {
+            double sum = gv[i];
+            for (int q = i + 1; q < k; q++) sum -= H[(size_t)i * m + q] * yh[q];
+            yh[i] = sum / H[(size_t)i * m + i];
+        }
+        BO_HIP(hipMemcpyAsync(K.y.p, yh, sizeof(double) * k, hipMemcpyHostToDevice, s));
+        BO_TRY(multiaxpy(len, K.zptr.data(), k, K.y.p, 1.0, x, s));
+    }
+done:
+    st.iterations = its;
+    BO_HIP(hipStreamSynchronize(s));
+    if (stats) *stats = st;
+    return status;
+}

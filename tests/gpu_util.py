@@ -1,0 +1,69 @@
+"""Helpers shared by the GPU parity tests: run the same seeded case through the
+oracle (CPU, FP64) and through the HIP library (via its C ABI binding)."""
+import numpy as np
+
+import bo_casegen as cg
+
+
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch.device("cuda:0")
+
+
+def to_dev(a, dtype=None):
+    import torch
+    a = np.ascontiguousarray(a)
+    t = torch.from_numpy(a)
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(torch_dev())
+
+
+def to_host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def oracle_system(O, case):
+    P = O.Problem(case)
+    rp, ci, val, R = O.jacobian(P)
+    return P, rp, ci, val, -R
+
+
+def device_bsr(B, rp, ci, val):
+    import torch
+    return B.DeviceBsr(to_dev(rp.astype(np.int32)), to_dev(ci.astype(np.int32)),
+                       to_dev(np.asarray(val, dtype=np.float64).reshape(-1)))
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def matching_opts(O, B, ftype="tiled", fpf=0, tile=(8, 8), coarse_max=256, smoother="gs", sweeps=1,
+                  use_amg=1, qi="block", theta=0.08):
+    """The same CPR configuration for the oracle and the library."""
+    oft = dict(tiled=O.F_ILU_TILED, bj=O.F_BJ)[ftype]
+    bft = dict(tiled=B.BO_F_ILU_TILED, bj=B.BO_F_BJ)[ftype]
+    osm = dict(gs=O.SMOOTH_GS, jacobi=O.SMOOTH_JACOBI)[smoother]
+    bsm = dict(gs=B.BO_SMOOTH_GS, jacobi=B.BO_SMOOTH_JACOBI)[smoother]
+    oqi = dict(block=O.QI_BLOCK, diag=O.QI_DIAG)[qi]
+    bqi = dict(block=B.BO_QI_BLOCK, diag=B.BO_QI_DIAG)[qi]
+    oo = O.cpr_opts(fpf=fpf, ftype=oft, tile=tile, theta=theta, coarse_max=coarse_max, smoother=osm,
+                    sweeps=sweeps, use_amg=use_amg, qi_mode=oqi)
+    bo = B.bo_cpr_default_opts(fpf=fpf, ftype=bft, tile=tile, theta=theta, coarse_max=coarse_max,
+                               smoother=bsm, sweeps=sweeps, use_amg=use_amg, qi_mode=bqi)
+    return oo, bo
+
+
+def ragged_case(seed=21):
+    """Spans several 8x8 tiles with ragged edges in x and y."""
+    return cg.tiny_case(19, 13, 6, seed=seed, step=0.01,
+                        wells=[cg.Well(0, 0, 0, 5, "inj", "bhp", 3500.0),
+                               cg.Well(18, 12, 0, 5, "prod", "bhp", 2500.0),
+                               cg.Well(9, 6, 1, 4, "prod", "bhp", 2600.0)])

@@ -1,0 +1,49 @@
+"""The C-ABI library loads and exports every entry point include/bo.h declares
+(CPU only: nothing is called that needs a GPU)."""
+import os
+import re
+import subprocess
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "bo.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bo_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_path_entry_points():
+    names = declared()
+    for f in ("bo_jacobian_bsr", "bo_cpr_setup", "bo_fgmres_solve", "bo_bsr_spmv", "bo_last_error"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1606_00556_amd import bo
+    lib = os.path.join(ROOT, "paper_1606_00556_amd", "libbo.so")
+    if not os.path.exists(lib):
+        from paper_1606_00556_amd import build
+        build.build()
+    out = subprocess.run(["nm", "-D", "--defined-only", lib], capture_output=True, text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if " T " in l)
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+    L = bo.lib()
+    for n in declared():
+        getattr(L, n)
+    assert set(bo.EXPORTS) == set(declared())
+
+
+def test_binding_reports_errors_without_gpu_work():
+    """Argument errors are caught on the host and reported through bo_last_error."""
+    import ctypes as C
+    from paper_1606_00556_amd import bo
+    L = bo.lib()
+    n, nnz = C.c_int32(), C.c_int32()
+    st = L.bo_jacobian_bsr_size(None, C.byref(n), C.byref(nnz))
+    assert st == bo.BO_ERR_INVALID_ARG
+    assert b"NULL" in L.bo_last_error()
+    o = bo.BoCprOpts()
+    L.bo_cpr_default_opts(C.byref(o))
+    assert o.tile_x == 8 and o.ftype == bo.BO_F_ILU_TILED and o.coarse_max == 256
