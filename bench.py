@@ -72,18 +72,24 @@ def main():
     fopts = B.bo_fgmres_default_opts()
     torch.cuda.synchronize()
 
+    # the preconditioner handle lives across systems, as in a Newton loop:
+    # bo_cpr_update rebuilds decoupling, AMG hierarchy and ILU factors from
+    # scratch for each new Jacobian and only reuses device memory
+    xo, xn, dt = states[0]
+    B.bo_jacobian_bsr(prob, xo, xn, dt, J, b)
+    pc = B.bo_cpr_setup(J, grid, copts)
+
     def step(i, record=None):
         xo, xn, dt = states[i % len(states)]
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record is not None else None
         if e: e[0].record(stream)
         B.bo_jacobian_bsr(prob, xo, xn, dt, J, b)
         if e: e[1].record(stream)
-        pc = B.bo_cpr_setup(J, grid, copts)
+        B.bo_cpr_update(pc, J)
         if e: e[2].record(stream)
         x.zero_()
         info = B.bo_fgmres_solve(pc, b, x, fopts)
         if e: e[3].record(stream)
-        pc.close()
         if not info["converged"]:
             raise RuntimeError(f"system {i} did not converge: {info}")
         if record is not None:
@@ -110,7 +116,6 @@ def main():
 
     # SpMV roofline: algorithmic bytes = 72 B per stored block (3x3 FP64) +
     # 24 B x read + 24 B y written per block row
-    pc = B.bo_cpr_setup(J, grid, copts)
     xin = torch.randn(3 * n, dtype=torch.float64, device=dev)
     yout = torch.empty_like(xin)
     for _ in range(5):
@@ -149,7 +154,7 @@ def main():
                          + ("10 systems of the synthetic 30-day step sequence" if wl else "one system")),
             "solver": "FGMRES(30), CPR-PF: block quasi-IMPES, SA-AMG V(1,1) RB-GS/Jacobi, tiled BILU0 8x8",
             "rtol": 1e-6,
-            "step": "bo_jacobian_bsr + bo_cpr_setup + bo_fgmres_solve",
+            "step": "bo_jacobian_bsr + bo_cpr_update (full rebuild, memory reused) + bo_fgmres_solve",
             "parallelism": "1 GPU",
         },
         "breakdown_ms": {"assembly": asm_ms, "setup": setup_ms, "solve": solve_ms},

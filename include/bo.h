@@ -161,6 +161,12 @@ typedef struct { int32_t nx, ny, nz; } bo_grid;
  * return.  Synchronises `stream` (the hierarchy sizes are decided on the host). */
 bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
                        bo_cpr **out, void *stream);
+/* Rebuilds pc for new values of a matrix with the same grid, pattern and
+ * options (a new Newton iterate): decoupling, AMG hierarchy and F-stage
+ * factors are recomputed from scratch; device memory of pc is reused when
+ * large enough.  On failure pc is unusable until a later update succeeds.
+ * Synchronises `stream`. */
+bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream);
 void bo_cpr_destroy(bo_cpr *pc);
 
 /* z = M^{-1} v (3N each): PF or FPF as configured. */

@@ -25,7 +25,7 @@ BO_PREC_FP64, BO_PREC_FP32, BO_PREC_FP32_BF16 = 0, 1, 2
 
 EXPORTS = [
     "bo_last_error", "bo_version", "bo_jacobian_bsr_size", "bo_jacobian_bsr", "bo_bsr_spmv",
-    "bo_cpr_default_opts", "bo_cpr_setup", "bo_cpr_destroy", "bo_cpr_apply", "bo_cpr_spmv",
+    "bo_cpr_default_opts", "bo_cpr_setup", "bo_cpr_update", "bo_cpr_destroy", "bo_cpr_apply", "bo_cpr_spmv",
     "bo_cpr_restrict", "bo_cpr_vcycle", "bo_cpr_fstage", "bo_cpr_levels", "bo_cpr_level_info",
     "bo_cpr_level_copy", "bo_cpr_copy_weights", "bo_fgmres_default_opts", "bo_fgmres_solve",
 ]
@@ -107,6 +107,7 @@ def lib():
     L.bo_cpr_default_opts.argtypes = [C.POINTER(BoCprOpts)]
     L.bo_cpr_default_opts.restype = None
     L.bo_cpr_setup.argtypes = [C.POINTER(BoBsr), C.POINTER(BoGrid), C.POINTER(BoCprOpts), C.POINTER(vp), vp]
+    L.bo_cpr_update.argtypes = [vp, C.POINTER(BoBsr), vp]
     L.bo_cpr_destroy.argtypes = [vp]
     L.bo_cpr_destroy.restype = None
     for f in ("bo_cpr_apply", "bo_cpr_restrict", "bo_cpr_vcycle", "bo_cpr_fstage"):
@@ -271,6 +272,12 @@ def bo_cpr_setup(A: DeviceBsr, grid, opts: Optional[BoCprOpts] = None, stream=No
     s = A.s
     _check(lib().bo_cpr_setup(C.byref(s), C.byref(g), C.byref(o), C.byref(h), _stream(stream)))
     return Cpr(h.value, s.nbrows)
+
+
+def bo_cpr_update(pc: Cpr, A: DeviceBsr, stream=None) -> Cpr:
+    s = A.s
+    _check(lib().bo_cpr_update(pc.h, C.byref(s), _stream(stream)))
+    return pc
 
 
 def bo_cpr_destroy(pc: Cpr):

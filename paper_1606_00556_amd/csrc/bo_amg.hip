@@ -147,6 +147,27 @@ __global__ void k_strength(int n, const int32_t *__restrict__ rp, const int32_t 
     }
 }
 
+// level-0 strength straight from the stencil layout: the transposed entry of
+// slot s of row i is slot 6-s of row j
+__global__ void k_strength_slots(int nx, int ny, int nz, const double *__restrict__ app,
+                                 const int32_t *__restrict__ rp, double t2, uint8_t *__restrict__ sf) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = nx * ny * nz;
+    if (i >= n) return;
+    size_t N = (size_t)n;
+    double aii = app[(size_t)S_D * N + i];
+    int e = rp[i];
+    for (int s = 0; s < NSLOT; s++) {
+        int j = nbr_of(i, s, nx, ny, nz);
+        if (j < 0) continue;
+        if (s == S_D) { sf[e++] = 0; continue; }
+        double ajj = app[(size_t)S_D * N + j];
+        double aij = app[(size_t)s * N + i], aji = app[(size_t)(NSLOT - 1 - s) * N + j];
+        double thr = t2 * fabs(aii * ajj);
+        sf[e++] = (aij * aij >= thr) || (aji * aji >= thr);
+    }
+}
+
 enum { UND = 0, IN = 1, OUT = 2, ISO = 3 };
 
 __global__ void k_mis_init(int n, const int32_t *__restrict__ rp, const uint8_t *__restrict__ sf,
@@ -283,26 +304,42 @@ __device__ __forceinline__ bool p_takes(int e, int i, const int32_t *ci, const u
     return (j == i || sf[e]) && agg[j] >= 0;
 }
 
+// Row data of the prolongator: the aggregate J of each entry that takes part
+// ({i} and the strong neighbours, aggregated) or -1, and its filtered value.
+constexpr int KP = 16;  // register fast path for rows of up to KP entries
+
 __global__ void k_p_count(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                           const uint8_t *__restrict__ sf, const int32_t *__restrict__ agg,
                           int32_t *__restrict__ cnt) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    int len = rp[i + 1] - rp[i];
     int c = 0;
-    for (int e = rp[i]; e < rp[i + 1]; e++) {
-        if (!p_takes(e, i, ci, sf, agg)) continue;
-        int J = agg[ci[e]];
-        bool first = true;
-        for (int f = rp[i]; f < e; f++)
-            if (p_takes(f, i, ci, sf, agg) && agg[ci[f]] == J) { first = false; break; }
-        c += first;
+    if (len > KP) return;  // long rows: k_p_long
+    {
+        int J[KP];
+#pragma unroll
+        for (int q = 0; q < KP; q++) {
+            J[q] = -1;
+            if (q < len) {
+                int e = rp[i] + q;
+                if (p_takes(e, i, ci, sf, agg)) J[q] = agg[ci[e]];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KP; q++) {
+            bool first = J[q] >= 0;
+#pragma unroll
+            for (int u = 0; u < q; u++) first = first && J[u] != J[q];
+            c += first;
+        }
     }
     cnt[i] = c;
 }
 
-// P row i: entries for each distinct aggregate J among {i} and its strong
-// neighbours, (agg(i)==J) - omega/aF_ii * sum_{agg(j)=J} aF_ij (sums in
-// ascending j), then sorted by J.
+// P row i: for each distinct aggregate J among {i} and its strong neighbours,
+// (agg(i)==J) - omega/aF_ii * sum_{agg(j)=J} aF_ij (sums in ascending j),
+// stored in ascending J.
 __global__ void k_p_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                          const double *__restrict__ v, const uint8_t *__restrict__ sf,
                          const int32_t *__restrict__ agg, const double *__restrict__ aF, double omega,
@@ -310,30 +347,110 @@ __global__ void k_p_fill(int n, const int32_t *__restrict__ rp, const int32_t *_
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double d = omega / aF[i];
-    int pos = prp[i];
-    for (int e = rp[i]; e < rp[i + 1]; e++) {
-        if (!p_takes(e, i, ci, sf, agg)) continue;
-        int J = agg[ci[e]];
-        bool first = true;
-        for (int f = rp[i]; f < e; f++)
-            if (p_takes(f, i, ci, sf, agg) && agg[ci[f]] == J) { first = false; break; }
-        if (!first) continue;
-        double s = 0.0;
-        for (int f = e; f < rp[i + 1]; f++)
-            if (p_takes(f, i, ci, sf, agg) && agg[ci[f]] == J) s = s + (ci[f] == i ? aF[i] : v[f]);
-        pci[pos] = J;
-        pv[pos] = (agg[i] == J ? 1.0 : 0.0) - d * s;
-        pos++;
+    int len = rp[i + 1] - rp[i];
+    int ai = agg[i];
+    if (len > KP) return;  // long rows: k_p_long
+    {
+        int J[KP];
+        double a[KP];
+#pragma unroll
+        for (int q = 0; q < KP; q++) {
+            J[q] = -1;
+            a[q] = 0.0;
+            if (q < len) {
+                int e = rp[i] + q;
+                if (p_takes(e, i, ci, sf, agg)) {
+                    J[q] = agg[ci[e]];
+                    a[q] = ci[e] == i ? aF[i] : v[e];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KP; q++) {
+            bool first = J[q] >= 0;
+#pragma unroll
+            for (int u = 0; u < q; u++) first = first && J[u] != J[q];
+            if (!first) continue;
+            double sum = 0.0;
+            int rank = 0;
+#pragma unroll
+            for (int u = 0; u < KP; u++) {
+                if (u >= q && J[u] == J[q]) sum = sum + a[u];
+                // distinct aggregates below J[q]: count first appearances
+                bool fu = J[u] >= 0 && J[u] < J[q];
+#pragma unroll
+                for (int w = 0; w < u; w++) fu = fu && J[w] != J[u];
+                rank += fu;
+            }
+            pci[prp[i] + rank] = J[q];
+            pv[prp[i] + rank] = (ai == J[q] ? 1.0 : 0.0) - d * sum;
+        }
     }
-    // insertion sort of the row by column
-    int b = prp[i], end = prp[i + 1];
-    for (int a = b + 1; a < end; a++) {
-        int c = pci[a];
-        double x = pv[a];
-        int q = a - 1;
-        while (q >= b && pci[q] > c) { pci[q + 1] = pci[q]; pv[q + 1] = pv[q]; q--; }
-        pci[q + 1] = c;
-        pv[q + 1] = x;
+}
+
+// Long rows of the prolongator (more than KP entries): one wavefront per row.
+// The row's (aggregate, filtered value) pairs are staged in LDS; an entry is
+// the first appearance of its aggregate if no earlier entry has it; the
+// entry's lane then sums the aggregate's values in ascending order and writes
+// the result at the aggregate's rank among the row's distinct aggregates.
+constexpr int KW = 512;
+constexpr int kPWaves = 4;
+
+__global__ void __launch_bounds__(64 * kPWaves) k_p_long(int n, const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                          const uint8_t *__restrict__ sf,
+                                                          const int32_t *__restrict__ agg,
+                                                          const double *__restrict__ aF, double omega,
+                                                          const int32_t *__restrict__ prp, int32_t *__restrict__ pci,
+                                                          double *__restrict__ pv, int32_t *__restrict__ cnt,
+                                                          int32_t *__restrict__ bad) {
+    __shared__ int J[kPWaves][KW];
+    __shared__ double A[kPWaves][KW];
+    __shared__ uint8_t first[kPWaves][KW];
+    int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    int i = blockIdx.x * kPWaves + wave;
+    if (i >= n) return;
+    int b = rp[i], len = rp[i + 1] - b;
+    if (len <= KP) return;  // handled by the register path
+    if (len > KW) { if (lane == 0) *bad = 1; return; }
+    for (int q = lane; q < len; q += 64) {
+        int e = b + q;
+        bool take = p_takes(e, i, ci, sf, agg);
+        J[wave][q] = take ? agg[ci[e]] : -1;
+        A[wave][q] = take ? (ci[e] == i ? aF[i] : v[e]) : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    int mycount = 0;
+    for (int q = lane; q < len; q += 64) {
+        int Jq = J[wave][q];
+        bool f = Jq >= 0;
+        for (int u = 0; u < q && f; u++) f = J[wave][u] != Jq;
+        first[wave][q] = f;
+        mycount += f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (cnt) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mycount += __shfl_xor(mycount, off, 64);
+        if (lane == 0) cnt[i] = mycount;
+        return;
+    }
+    double d = omega / aF[i];
+    int ai = agg[i];
+    for (int q = lane; q < len; q += 64) {
+        if (!first[wave][q]) continue;
+        int Jq = J[wave][q];
+        double sum = 0.0;
+        int rank = 0;
+        for (int u = 0; u < len; u++) {
+            int Ju = J[wave][u];
+            if (u >= q && Ju == Jq) sum = sum + A[wave][u];
+            rank += first[wave][u] && Ju < Jq;
+        }
+        pci[prp[i] + rank] = Jq;
+        pv[prp[i] + rank] = (ai == Jq ? 1.0 : 0.0) - d * sum;
     }
 }
 
@@ -356,11 +473,28 @@ __global__ void k_transpose_fill(int n, const int32_t *__restrict__ rp, const in
     }
 }
 
-__global__ void k_sort_rows(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ ci, double *__restrict__ v) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int b = rp[i], end = rp[i + 1];
-    for (int a = b + 1; a < end; a++) {
+// sorts every row by column: one wavefront per row; rows of up to 64 entries
+// are ranked across lanes (columns within a row are distinct)
+__global__ void __launch_bounds__(kBlock) k_sort_rows(int n, const int32_t *__restrict__ rp,
+                                                      int32_t *__restrict__ ci, double *__restrict__ v) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    int row = gid / 64, lane = gid % 64;
+    if (row >= n) return;
+    int b = rp[row], len = rp[row + 1] - b;
+    if (len <= 64) {
+        int c = lane < len ? ci[b + lane] : 0x7fffffff;
+        double x = lane < len ? v[b + lane] : 0.0;
+        int rank = 0;
+        for (int u = 0; u < 64; u++) {
+            int cu = __shfl(c, u, 64);
+            rank += cu < c;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < len) { ci[b + rank] = c; v[b + rank] = x; }
+        return;
+    }
+    if (lane != 0) return;
+    for (int a = b + 1; a < b + len; a++) {
         int c = ci[a];
         double x = v[a];
         int q = a - 1;
@@ -371,93 +505,99 @@ __global__ void k_sort_rows(int n, const int32_t *__restrict__ rp, int32_t *__re
 }
 
 // ---- row-wise sparse product C = A B ----------------------------------------------
-constexpr int kHash = 2048;            // LDS hash slots per wavefront
-constexpr int kWavesPerGroup = 4;
+// G lanes own one output row and an LDS hash of H slots (keys and values).
+// The row of A is walked in ascending order; for one entry a_ik the lanes
+// take the entries of row k of B in parallel.  Those have distinct columns,
+// so no two lanes touch one slot at the same time, and each output value is
+// accumulated in ascending k exactly as in a row-by-row Gustavson product.
+// The distinct columns are then compacted, ranked (sorted) and written.
 
-__device__ __forceinline__ unsigned hash_col(int c) { return ((unsigned)c * 2654435761u) & (kHash - 1); }
-
-// inserts the column set of row i of A*B into the wave's hash; returns the count
-__device__ int gather_cols(int i, const int32_t *arp, const int32_t *aci, const int32_t *brp, const int32_t *bci,
-                           int *tab, int *count, int lane) {
-    for (int e = arp[i]; e < arp[i + 1]; e++) {
-        int k = aci[e];
-        for (int f = brp[k] + lane; f < brp[k + 1]; f += 64) {
-            int c = bci[f];
-            unsigned h = hash_col(c);
-            for (int probe = 0; probe < kHash; probe++) {
-                int old = atomicCAS(&tab[h], -1, c);
-                if (old == -1) { atomicAdd(count, 1); break; }
-                if (old == c) break;
-                h = (h + 1) & (kHash - 1);
-            }
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    return *count;
+// products of each row (sum of the B row lengths it touches), max over rows
+__global__ void k_spgemm_bound(int n, const int32_t *__restrict__ arp, const int32_t *__restrict__ aci,
+                               const int32_t *__restrict__ brp, int32_t *__restrict__ mx) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    for (int e = arp[i]; e < arp[i + 1]; e++) c += brp[aci[e] + 1] - brp[aci[e]];
+    atomicMax(mx, c);
 }
 
-__global__ void __launch_bounds__(64 * kWavesPerGroup) k_spgemm_count(int n, const int32_t *__restrict__ arp,
-                                                                       const int32_t *__restrict__ aci,
-                                                                       const int32_t *__restrict__ brp,
-                                                                       const int32_t *__restrict__ bci,
-                                                                       int32_t *__restrict__ cnt,
-                                                                       int32_t *__restrict__ bad) {
-    __shared__ int tab[kWavesPerGroup][kHash];
-    __shared__ int count[kWavesPerGroup];
-    int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    int i = blockIdx.x * kWavesPerGroup + wave;
-    for (int t = lane; t < kHash; t += 64) tab[wave][t] = -1;
-    if (lane == 0) count[wave] = 0;
-    __syncthreads();
-    if (i < n) {
-        int c = gather_cols(i, arp, aci, brp, bci, tab[wave], &count[wave], lane);
-        if (lane == 0) {
-            cnt[i] = c;
-            if (c > kHash / 2) *bad = 1;
-        }
-    }
-}
-
-__global__ void __launch_bounds__(64 * kWavesPerGroup) k_spgemm_fill(int n, const int32_t *__restrict__ arp,
-                                                                      const int32_t *__restrict__ aci,
-                                                                      const double *__restrict__ av,
-                                                                      const int32_t *__restrict__ brp,
-                                                                      const int32_t *__restrict__ bci,
-                                                                      const double *__restrict__ bv,
-                                                                      const int32_t *__restrict__ crp,
-                                                                      int32_t *__restrict__ cci,
-                                                                      double *__restrict__ cv) {
-    __shared__ int tab[kWavesPerGroup][kHash];
-    __shared__ int count[kWavesPerGroup];
-    int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    int i = blockIdx.x * kWavesPerGroup + wave;
-    for (int t = lane; t < kHash; t += 64) tab[wave][t] = -1;
-    if (lane == 0) count[wave] = 0;
+template <int G, int H>
+__global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict__ arp,
+                                               const int32_t *__restrict__ aci, const double *__restrict__ av,
+                                               const int32_t *__restrict__ brp, const int32_t *__restrict__ bci,
+                                               const double *__restrict__ bv, int32_t *__restrict__ cnt,
+                                               const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
+                                               double *__restrict__ cv, int32_t *__restrict__ bad) {
+    constexpr int R = 256 / G;
+    __shared__ int key[R][H];
+    __shared__ double val[R][H];
+    __shared__ int nl[R];
+    int grp = threadIdx.x / G, sub = threadIdx.x % G;
+    int i = blockIdx.x * R + grp;
+    for (int t = sub; t < H; t += G) { key[grp][t] = -1; val[grp][t] = 0.0; }
+    if (sub == 0) nl[grp] = 0;
     __syncthreads();
     if (i >= n) return;
-    int total = gather_cols(i, arp, aci, brp, bci, tab[wave], &count[wave], lane);
-    int base = crp[i];
-    // rank of each distinct column = number of distinct columns below it
-    for (int t = lane; t < kHash; t += 64) {
-        int c = tab[wave][t];
-        if (c < 0) continue;
-        int rank = 0;
-        for (int u = 0; u < kHash; u++) {
-            int d = tab[wave][u];
-            rank += (d >= 0 && d < c);
+    const bool numeric = cci != nullptr;
+    for (int e = arp[i]; e < arp[i + 1]; e++) {
+        int k = aci[e];
+        double a = numeric ? av[e] : 0.0;
+        for (int f = brp[k] + sub; f < brp[k + 1]; f += G) {
+            int c = bci[f];
+            unsigned h = ((unsigned)c * 2654435761u) & (H - 1);
+            int slot = -1;
+            for (int probe = 0; probe < H; probe++) {
+                int old = atomicCAS(&key[grp][h], -1, c);
+                if (old == -1 || old == c) { slot = (int)h; break; }
+                h = (h + 1) & (H - 1);
+            }
+            if (slot < 0) { *bad = 1; continue; }
+            if (numeric) val[grp][slot] = val[grp][slot] + a * bv[f];
         }
-        // value: sum over the row of A in ascending order
-        double s = 0.0;
-        for (int e = arp[i]; e < arp[i + 1]; e++) {
-            int k = aci[e];
-            int q = find_col(bci, brp[k], brp[k + 1], c);
-            if (q >= 0) s = s + av[e] * bv[q];
-        }
-        cci[base + rank] = c;
-        cv[base + rank] = s;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
     }
-    (void)total;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    // compact the occupied slots into a dense list at the front of key/val:
+    // every lane first takes its slots into registers
+    constexpr int PER = H / G;
+    int kk[PER];
+    double vv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+        kk[u] = key[grp][sub + u * G];
+        vv[u] = numeric ? val[grp][sub + u * G] : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int u = 0; u < PER; u++)
+        if (kk[u] >= 0) {
+            int p = atomicAdd(&nl[grp], 1);
+            key[grp][p] = kk[u];
+            val[grp][p] = vv[u];
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    int L = nl[grp];
+    if (!numeric) {
+        if (sub == 0) {
+            cnt[i] = L;
+            if (L > H / 2) *bad = 1;
+        }
+        return;
+    }
+    // each distinct column goes to its rank among the row's columns
+    int base = crp[i];
+    for (int t = sub; t < L; t += G) {
+        int c = key[grp][t];
+        int rank = 0;
+        for (int u = 0; u < L; u++) rank += key[grp][u] < c;
+        cci[base + rank] = c;
+        cv[base + rank] = val[grp][t];
+    }
 }
 
 // ---- coarsest level: dense inverse ---------------------------------------------------
@@ -469,35 +609,36 @@ __global__ void k_dense_from_csr(int n, const int32_t *__restrict__ rp, const in
     for (int e = rp[i]; e < rp[i + 1]; e++) M[(size_t)i * 2 * n + ci[e]] = v[e];
 }
 
-// Gauss-Jordan with partial pivoting on [A | I] (n x 2n, row-major), one
-// workgroup; leaves A^{-1} in the right half.
+// Gauss-Jordan with partial pivoting on [A | I] (n x 2n, row-major, n <=
+// 1024), one workgroup of 1024 threads; leaves A^{-1} in the right half.
+// Per column: pivot = largest |a_rk| (ties: smallest row), swap, scale the
+// pivot row, then every thread owns columns c (coalesced across threads) and
+// eliminates them in all other rows with the multipliers cached in LDS.
 __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double *__restrict__ M, int32_t *__restrict__ bad) {
-    __shared__ double bestv[1024];
-    __shared__ int besti[1024];
+    __shared__ double f[1024];
+    __shared__ double wv[16];
+    __shared__ int wi[16];
     __shared__ int piv;
-    __shared__ double pivval;
-    int t = threadIdx.x, w = 2 * n;
+    int t = threadIdx.x, lane = t % 64, wave = t / 64;
+    int w = 2 * n;
     for (int k = 0; k < n; k++) {
-        double bv = -1.0;
-        int bi = n;
-        for (int r = k + t; r < n; r += blockDim.x) {
-            double a = fabs(M[(size_t)r * w + k]);
-            if (a > bv || (a == bv && r < bi)) { bv = a; bi = r; }
+        int r = k + t;
+        double bv = r < n ? fabs(M[(size_t)r * w + k]) : -1.0;
+        int bi = r < n ? r : n;
+        for (int off = 32; off > 0; off >>= 1) {
+            double ov = __shfl_xor(bv, off, 64);
+            int oi = __shfl_xor(bi, off, 64);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
         }
-        bestv[t] = bv;
-        besti[t] = bi;
+        if (lane == 0) { wv[wave] = bv; wi[wave] = bi; }
         __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (t < s) {
-                double o = bestv[t + s];
-                int oi = besti[t + s];
-                if (o > bestv[t] || (o == bestv[t] && oi < besti[t])) { bestv[t] = o; besti[t] = oi; }
-            }
-            __syncthreads();
-        }
         if (t == 0) {
-            piv = besti[0];
-            if (!(bestv[0] > 0.0)) *bad = 1;
+            double best = wv[0];
+            int bidx = wi[0];
+            for (int q = 1; q < 16; q++)
+                if (wv[q] > best || (wv[q] == best && wi[q] < bidx)) { best = wv[q]; bidx = wi[q]; }
+            piv = bidx;
+            if (!(best > 0.0)) *bad = 1;
         }
         __syncthreads();
         int p = piv;
@@ -508,21 +649,28 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double *__restrict
                 M[(size_t)p * w + c] = x;
             }
         __syncthreads();
-        if (t == 0) pivval = M[(size_t)k * w + k];
+        double d = M[(size_t)k * w + k];
         __syncthreads();
-        double d = pivval;
-        for (int c = t; c < w; c += blockDim.x) M[(size_t)k * w + c] = M[(size_t)k * w + c] / d;
+        for (int c = k + t; c < w; c += blockDim.x) M[(size_t)k * w + c] = M[(size_t)k * w + c] / d;
+        for (int rr = t; rr < n; rr += blockDim.x) f[rr] = rr == k ? 0.0 : M[(size_t)rr * w + k];
         __syncthreads();
-        for (int idx = t; idx < n * w; idx += blockDim.x) {
-            int r = idx / w, c = idx % w;
-            if (r == k) continue;
-            double f = M[(size_t)r * w + k];
-            if (c == k) continue;
-            M[(size_t)idx] = M[(size_t)idx] - f * M[(size_t)k * w + c];
+        // (row, column) pairs in a 2-D walk: columns fastest, no divisions
+        int ncol = w - (k + 1);
+        int rows_per = (int)blockDim.x / ncol;
+        if (rows_per >= 1) {
+            int rr0 = t / ncol, c = k + 1 + t % ncol;
+            if (rr0 < rows_per)
+                for (int rr = rr0; rr < n; rr += rows_per)
+                    if (rr != k) M[rr * w + c] = M[rr * w + c] - f[rr] * M[k * w + c];
+        } else {
+            for (int c = k + 1 + t; c < w; c += blockDim.x) {
+                double pk = M[k * w + c];
+                for (int rr = 0; rr < n; rr++)
+                    if (rr != k) M[rr * w + c] = M[rr * w + c] - f[rr] * pk;
+            }
         }
-        __syncthreads();
-        for (int r = t; r < n; r += blockDim.x)
-            if (r != k) M[(size_t)r * w + k] = 0.0;
+        for (int rr = t; rr < n; rr += blockDim.x)
+            if (rr != k) M[(size_t)rr * w + k] = 0.0;
         __syncthreads();
     }
 }
@@ -605,56 +753,52 @@ __global__ void __launch_bounds__(kBlock) k_resid_slots(int nx, int ny, int nz, 
     r[i] = b[i] - s;
 }
 
-// CSR: damped Jacobi sweep xo = xi + (2/3) (b - A xi) / a_ii
-__global__ void k_jacobi_csr(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                             const double *__restrict__ v, const int32_t *__restrict__ dpos,
-                             const double *__restrict__ b, const double *__restrict__ xi, double *__restrict__ xo) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// CSR row operations on coarse levels: G lanes per row (G a power of two
+// dividing 64) sum the row's products in strides of G and combine them with
+// cross-lane shuffles.
+enum { OP_MV = 0, OP_RESID = 1, OP_ADD = 2, OP_JACOBI = 3, OP_JACOBI0 = 4 };
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_csr_rowop(int n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                      const double *__restrict__ x, int op,
+                                                      const double *__restrict__ b,
+                                                      const int32_t *__restrict__ dpos, double *__restrict__ y) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    int row = gid / G, sub = gid % G;
+    if (row >= n) return;  // whole groups leave together
+    if (op == OP_JACOBI0) {
+        // one damped Jacobi sweep from a zero guess
+        if (sub == 0) y[row] = (2.0 / 3.0) * (b[row] / v[dpos[row]]);
+        return;
+    }
     double s = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; e++) s = s + v[e] * xi[ci[e]];
-    double d = v[dpos[i]];
-    xo[i] = xi[i] + (2.0 / 3.0) * ((b[i] - s) / d);
+    for (int e = rp[row] + sub; e < rp[row + 1]; e += G) s = s + v[e] * x[ci[e]];
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) s = s + __shfl_xor(s, off, G);
+    if (sub != 0) return;
+    switch (op) {
+    case OP_MV: y[row] = s; break;
+    case OP_RESID: y[row] = b[row] - s; break;
+    case OP_ADD: y[row] = y[row] + s; break;
+    default: {
+        double d = v[dpos[row]];
+        y[row] = x[row] + (2.0 / 3.0) * ((b[row] - s) / d);
+    }
+    }
 }
 
-// CSR: r = b - A x
-__global__ void k_resid_csr(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                            const double *__restrict__ v, const double *__restrict__ b,
-                            const double *__restrict__ x, double *__restrict__ r) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// dense y = M x, one wavefront per row
+__global__ void __launch_bounds__(kBlock) k_dense_mv(int n, const double *__restrict__ M,
+                                                     const double *__restrict__ x, double *__restrict__ y) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    int row = gid / 64, lane = gid % 64;
+    if (row >= n) return;
     double s = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; e++) s = s + v[e] * x[ci[e]];
-    r[i] = b[i] - s;
-}
-
-// CSR: y = A x
-__global__ void k_mv_csr(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                         const double *__restrict__ v, const double *__restrict__ x, double *__restrict__ y) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; e++) s = s + v[e] * x[ci[e]];
-    y[i] = s;
-}
-
-// CSR: x = x + P xc
-__global__ void k_prolong_add(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                              const double *__restrict__ v, const double *__restrict__ xc, double *__restrict__ x) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; e++) s = s + v[e] * xc[ci[e]];
-    x[i] = x[i] + s;
-}
-
-// dense y = M x (n <= 1024), one row per thread
-__global__ void k_dense_mv(int n, const double *__restrict__ M, const double *__restrict__ x, double *__restrict__ y) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int c = 0; c < n; c++) s = s + M[(size_t)i * n + c] * x[c];
-    y[i] = s;
+    for (int c = lane; c < n; c += 64) s = s + M[(size_t)row * n + c] * x[c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s = s + __shfl_xor(s, off, 64);
+    if (lane == 0) y[row] = s;
 }
 
 bo_status read_flag(int32_t *dflag, hipStream_t s, int32_t *out) {
@@ -664,6 +808,24 @@ bo_status read_flag(int32_t *dflag, hipStream_t s, int32_t *out) {
 }
 
 }  // namespace
+
+// y = op(A x) for a CSR matrix with nnz entries over n rows (see k_csr_rowop)
+static bo_status csr_rowop(int n, int nnz, const int32_t *rp, const int32_t *ci, const double *v, const double *x,
+                           int op, const double *b, const int32_t *dpos, double *y, hipStream_t s) {
+    double avg = n > 0 ? (double)nnz / n : 1.0;
+    long long threads;
+#define BO_ROWOP(G)                                                                                  \
+    threads = (long long)n * G;                                                                      \
+    k_csr_rowop<G><<<grid_for(threads), kBlock, 0, s>>>(n, rp, ci, v, x, op, b, dpos, y)
+    if (avg <= 6.0) { BO_ROWOP(4); }
+    else if (avg <= 12.0) { BO_ROWOP(8); }
+    else if (avg <= 24.0) { BO_ROWOP(16); }
+    else if (avg <= 48.0) { BO_ROWOP(32); }
+    else { BO_ROWOP(64); }
+#undef BO_ROWOP
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
 
 // ---- host: decoupling -------------------------------------------------------------
 bo_status qi_decouple(bo_cpr *pc, hipStream_t s) {
@@ -702,13 +864,30 @@ static bo_status level_diag(Level &L, int32_t *flag, hipStream_t s) {
 
 static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const double *av, const int32_t *brp,
                         const int32_t *bci, const double *bv, DBuf<int32_t> &crp, DBuf<int32_t> &cci,
-                        DBuf<double> &cv, int *cnnz, int32_t *flag, hipStream_t s) {
-    DBuf<int32_t> cnt;
+                        DBuf<double> &cv, int *cnnz, int32_t *flag, DBuf<int32_t> &cnt, hipStream_t s) {
     BO_TRY(cnt.alloc(n));
     BO_TRY(crp.alloc(n + 1));
     BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    unsigned groups = (unsigned)((n + kWavesPerGroup - 1) / kWavesPerGroup);
-    k_spgemm_count<<<groups, 64 * kWavesPerGroup, 0, s>>>(n, arp, aci, brp, bci, cnt.p, flag);
+    k_spgemm_bound<<<grid_for(n), kBlock, 0, s>>>(n, arp, aci, brp, flag);
+    int32_t bound = 0;
+    BO_TRY(read_flag(flag, s, &bound));
+    BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    // smallest hash holding twice the products of the longest row; lanes per
+    // row grow with the work per row
+    int sel;
+    if (bound <= 32) sel = 0;
+    else if (bound <= 128) sel = 1;
+    else if (bound <= 512) sel = 2;
+    else sel = 3;
+    auto launch = [&](int32_t *c, const int32_t *rp_, int32_t *ci_, double *v_) {
+        switch (sel) {
+        case 0: k_spgemm<8, 64><<<grid_for((long long)n * 8), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, rp_, ci_, v_, flag); break;
+        case 1: k_spgemm<16, 256><<<grid_for((long long)n * 16), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, rp_, ci_, v_, flag); break;
+        case 2: k_spgemm<64, 1024><<<grid_for((long long)n * 64), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, rp_, ci_, v_, flag); break;
+        default: k_spgemm<64, 2048><<<grid_for((long long)n * 64), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, rp_, ci_, v_, flag); break;
+        }
+    };
+    launch(cnt.p, nullptr, nullptr, nullptr);
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
     BO_TRY(read_flag(flag, s, &bad));
@@ -717,9 +896,10 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s));
     BO_TRY(cci.alloc(total));
     BO_TRY(cv.alloc(total));
-    k_spgemm_fill<<<groups, 64 * kWavesPerGroup, 0, s>>>(n, arp, aci, av, brp, bci, bv, crp.p, cci.p, cv.p);
+    launch(nullptr, crp.p, cci.p, cv.p);
     BO_HIP(hipGetLastError());
-    BO_HIP(hipStreamSynchronize(s));
+    BO_TRY(read_flag(flag, s, &bad));
+    if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: Galerkin product row exceeds the LDS hash capacity");
     *cnnz = total;
     return BO_OK;
 }
@@ -730,8 +910,9 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
     // level 0: CSR with the stencil pattern
     Level &L0 = pc->lv[0];
     L0.n = pc->n;
+    SetupWork &W = pc->sw;
     {
-        DBuf<int32_t> cnt;
+        DBuf<int32_t> &cnt = W.cnt;
         BO_TRY(cnt.alloc(L0.n));
         BO_TRY(L0.rp.alloc(L0.n + 1));
         k_stencil_counts<<<grid_for(L0.n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, cnt.p);
@@ -753,29 +934,38 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         BO_TRY(L.x.alloc(L.n));
         BO_TRY(L.b.alloc(L.n));
         BO_TRY(L.r.alloc(L.n));
+        BO_TRY(L.t.alloc(L.n));
         if (L.n <= o.coarse_max || l + 1 >= max_levels) break;
         int n = L.n;
         BO_TRY(L.sf.alloc(L.nnz));
-        k_strength<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, t2, L.sf.p);
+        if (l == 0)
+            k_strength_slots<<<grid_for(n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->app.p, L.rp.p, t2,
+                                                             L.sf.p);
+        else
+            k_strength<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, t2, L.sf.p);
         // MIS-2
-        DBuf<uint8_t> state, nw, d1;
-        DBuf<uint64_t> m1;
+        DBuf<uint8_t> &state = W.state, &nw = W.nw, &d1 = W.d1;
+        DBuf<uint64_t> &m1 = W.m1;
         BO_TRY(state.alloc(n)); BO_TRY(nw.alloc(n)); BO_TRY(d1.alloc(n)); BO_TRY(m1.alloc(n));
         k_mis_init<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.sf.p, state.p);
-        for (int round = 0;; round++) {
+        // rounds are checked for completion every second round: a round on a
+        // graph with no undecided node changes nothing
+        for (int round = 0;; round += 2) {
             if (round > 10000) return fail(BO_ERR_HIP, "AMG: MIS-2 did not terminate");
-            BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-            k_mis_m1<<<grid_for(n), kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p);
-            k_mis_m2<<<grid_for(n), kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p, nw.p);
-            k_mis_spread<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p);
-            k_mis_update<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p, state.p, flag);
+            for (int rep = 0; rep < 2; rep++) {
+                BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+                k_mis_m1<<<grid_for(n), kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p);
+                k_mis_m2<<<grid_for(n), kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p, nw.p);
+                k_mis_spread<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p);
+                k_mis_update<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p, state.p, flag);
+            }
             BO_HIP(hipGetLastError());
             int32_t any = 0;
             BO_TRY(read_flag(flag, s, &any));
             if (!any) break;
         }
         // aggregates
-        DBuf<int32_t> cnt, id, a1;
+        DBuf<int32_t> &cnt = W.cnt, &id = W.id, &a1 = W.a1;
         BO_TRY(cnt.alloc(n)); BO_TRY(id.alloc(n + 1)); BO_TRY(a1.alloc(n));
         BO_TRY(L.root.alloc(n));
         BO_TRY(L.agg.alloc(n));
@@ -792,8 +982,8 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         if (bad) return fail(BO_ERR_HIP, "AMG: a node could not be aggregated");
         L.nc = nc;
         // prolongator
-        DBuf<double> aF;
-        DBuf<unsigned long long> rho;
+        DBuf<double> &aF = W.aF;
+        DBuf<unsigned long long> &rho = W.rho;
         BO_TRY(aF.alloc(n)); BO_TRY(rho.alloc(1));
         BO_HIP(hipMemsetAsync(rho.p, 0, sizeof(unsigned long long), s));
         k_filter<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.sf.p, aF.p, rho.p);
@@ -804,7 +994,11 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         std::memcpy(&rhov, &rb, sizeof rhov);
         if (!(rhov > 0.0) || !(rhov < INFINITY)) return fail(BO_ERR_SINGULAR_COARSE, "AMG: bad smoother bound");
         L.omega = (4.0 / 3.0) / rhov;
+        BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
         k_p_count<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, L.agg.p, cnt.p);
+        k_p_long<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
+                                                                       aF.p, 0.0, nullptr, nullptr, nullptr,
+                                                                       cnt.p, flag);
         BO_TRY(L.prp.alloc(n + 1));
         int32_t pnnz = 0;
         BO_TRY(scan_counts(cnt.p, L.prp.p, n, &pnnz, s));
@@ -812,9 +1006,14 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         BO_TRY(L.pci.alloc(pnnz)); BO_TRY(L.pv.alloc(pnnz));
         k_p_fill<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, L.omega,
                                                 L.prp.p, L.pci.p, L.pv.p);
+        k_p_long<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
+                                                                       aF.p, L.omega, L.prp.p, L.pci.p, L.pv.p,
+                                                                       nullptr, flag);
         BO_HIP(hipGetLastError());
+        BO_TRY(read_flag(flag, s, &bad));
+        if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: prolongator row longer than the LDS staging limit");
         // R = P^T
-        DBuf<int32_t> rc, fp;
+        DBuf<int32_t> &rc = W.rc, &fp = W.fp;
         BO_TRY(rc.alloc(nc)); BO_TRY(fp.alloc(nc));
         BO_HIP(hipMemsetAsync(rc.p, 0, sizeof(int32_t) * nc, s));
         BO_HIP(hipMemsetAsync(fp.p, 0, sizeof(int32_t) * nc, s));
@@ -824,16 +1023,16 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         BO_TRY(scan_counts(rc.p, L.rrp.p, nc, &rn, s));
         BO_TRY(L.rci.alloc(pnnz)); BO_TRY(L.rv.alloc(pnnz));
         k_transpose_fill<<<grid_for(n), kBlock, 0, s>>>(n, L.prp.p, L.pci.p, L.pv.p, L.rrp.p, fp.p, L.rci.p, L.rv.p);
-        k_sort_rows<<<grid_for(nc), kBlock, 0, s>>>(nc, L.rrp.p, L.rci.p, L.rv.p);
+        k_sort_rows<<<grid_for((long long)nc * 64), kBlock, 0, s>>>(nc, L.rrp.p, L.rci.p, L.rv.p);
         BO_HIP(hipGetLastError());
         // A_c = R (A P)
-        DBuf<int32_t> aprp, apci;
-        DBuf<double> apv;
+        DBuf<int32_t> &aprp = W.aprp, &apci = W.apci;
+        DBuf<double> &apv = W.apv;
         int apnnz = 0;
-        BO_TRY(spgemm(n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p, aprp, apci, apv, &apnnz, flag, s));
+        BO_TRY(spgemm(n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p, aprp, apci, apv, &apnnz, flag, W.gcnt, s));
         Level &C = pc->lv[l + 1];
         C.n = nc;
-        BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, flag, s));
+        BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, flag, W.gcnt, s));
         BO_HIP(hipStreamSynchronize(s));
     }
     pc->nlev = l + 1;
@@ -844,7 +1043,7 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         return fail(BO_ERR_UNSUPPORTED, "AMG: coarsening stalled above the dense coarse-solve limit (" +
                                             std::to_string(nc) + " rows)");
     pc->coarse_n = nc;
-    DBuf<double> M;
+    DBuf<double> &M = W.dense;
     BO_TRY(M.alloc((size_t)nc * 2 * nc));
     BO_TRY(pc->cinv.alloc((size_t)nc * nc));
     k_dense_from_csr<<<grid_for(nc), kBlock, 0, s>>>(nc, Lc.rp.p, Lc.ci.p, Lc.v.p, M.p);
@@ -877,42 +1076,72 @@ static bo_status smooth0(bo_cpr *pc, const double *b, double *x, bool forward, h
     return BO_OK;
 }
 
-static bo_status smooth_c(Level &L, int sweeps, const double *b, double *x, hipStream_t s) {
-    for (int sw = 0; sw < sweeps; sw++) {
-        k_jacobi_csr<<<grid_for(L.n), kBlock, 0, s>>>(L.n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, b, x, L.r.p);
-        BO_HIP(hipMemcpyAsync(x, L.r.p, sizeof(double) * L.n, hipMemcpyDeviceToDevice, s));
+// coarse-level damped Jacobi; `x` holds the guess (NULL: zero) and the
+// result is returned in one of x / L.t
+static bo_status smooth_c(Level &L, int sweeps, const double *b, double *x, double **res, hipStream_t s) {
+    double *cur = x, *oth = L.t.p;
+    int first = 0;
+    if (!x) {
+        BO_TRY(csr_rowop(L.n, L.nnz, L.rp.p, L.ci.p, L.v.p, nullptr, OP_JACOBI0, b, L.diagpos.p, L.x.p, s));
+        cur = L.x.p;
+        oth = L.t.p;
+        first = 1;
     }
-    BO_HIP(hipGetLastError());
+    for (int sw = first; sw < sweeps; sw++) {
+        BO_TRY(csr_rowop(L.n, L.nnz, L.rp.p, L.ci.p, L.v.p, cur, OP_JACOBI, b, L.diagpos.p, oth, s));
+        std::swap(cur, oth);
+    }
+    *res = cur;
     return BO_OK;
 }
 
-static bo_status vcycle_rec(bo_cpr *pc, int l, const double *b, double *x, hipStream_t s) {
+// one V-cycle on level l for right-hand side b; returns the result pointer
+static bo_status vcycle_rec(bo_cpr *pc, int l, const double *b, double **res, hipStream_t s) {
     Level &L = pc->lv[l];
     if (l == pc->nlev - 1) {
-        k_dense_mv<<<grid_for(L.n), kBlock, 0, s>>>(L.n, pc->cinv.p, b, x);
+        k_dense_mv<<<grid_for((long long)L.n * 64), kBlock, 0, s>>>(L.n, pc->cinv.p, b, L.x.p);
         BO_HIP(hipGetLastError());
+        *res = L.x.p;
         return BO_OK;
     }
-    BO_TRY(fill(L.n, 0.0, x, s));
-    if (l == 0) BO_TRY(smooth0(pc, b, x, true, s));
-    else BO_TRY(smooth_c(L, pc->o.sweeps, b, x, s));
-    if (l == 0)
+    double *x;
+    if (l == 0) {
+        x = L.x.p;
+        BO_TRY(fill(L.n, 0.0, x, s));
+        BO_TRY(smooth0(pc, b, x, true, s));
         k_resid_slots<<<grid_for(L.n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->app.p, b, x, L.r.p);
-    else
-        k_resid_csr<<<grid_for(L.n), kBlock, 0, s>>>(L.n, L.rp.p, L.ci.p, L.v.p, b, x, L.r.p);
+    } else {
+        BO_TRY(smooth_c(L, pc->o.sweeps, b, nullptr, &x, s));
+        BO_TRY(csr_rowop(L.n, L.nnz, L.rp.p, L.ci.p, L.v.p, x, OP_RESID, b, nullptr, L.r.p, s));
+    }
     Level &C = pc->lv[l + 1];
-    k_mv_csr<<<grid_for(C.n), kBlock, 0, s>>>(C.n, L.rrp.p, L.rci.p, L.rv.p, L.r.p, C.b.p);
-    BO_HIP(hipGetLastError());
-    BO_TRY(vcycle_rec(pc, l + 1, C.b.p, C.x.p, s));
-    k_prolong_add<<<grid_for(L.n), kBlock, 0, s>>>(L.n, L.prp.p, L.pci.p, L.pv.p, C.x.p, x);
-    BO_HIP(hipGetLastError());
-    if (l == 0) BO_TRY(smooth0(pc, b, x, false, s));
-    else BO_TRY(smooth_c(L, pc->o.sweeps, b, x, s));
+    BO_TRY(csr_rowop(C.n, L.pnnz, L.rrp.p, L.rci.p, L.rv.p, L.r.p, OP_MV, nullptr, nullptr, C.b.p, s));
+    double *xc;
+    BO_TRY(vcycle_rec(pc, l + 1, C.b.p, &xc, s));
+    BO_TRY(csr_rowop(L.n, L.pnnz, L.prp.p, L.pci.p, L.pv.p, xc, OP_ADD, nullptr, nullptr, x, s));
+    if (l == 0) {
+        BO_TRY(smooth0(pc, b, x, false, s));
+        *res = x;
+    } else {
+        BO_TRY(smooth_c(L, pc->o.sweeps, b, x, res, s));
+    }
+    return BO_OK;
+}
+
+// one V-cycle for b; *res points at the result (a buffer of the hierarchy,
+// valid until the next cycle)
+bo_status amg_vcycle_ptr(bo_cpr *pc, const double *b, const double **res, hipStream_t s) {
+    double *r;
+    BO_TRY(vcycle_rec(pc, 0, b, &r, s));
+    *res = r;
     return BO_OK;
 }
 
 bo_status amg_vcycle(bo_cpr *pc, const double *b, double *x, hipStream_t s) {
-    return vcycle_rec(pc, 0, b, x, s);
+    const double *res;
+    BO_TRY(amg_vcycle_ptr(pc, b, &res, s));
+    if (res != x) BO_HIP(hipMemcpyAsync(x, res, sizeof(double) * pc->n, hipMemcpyDeviceToDevice, s));
+    return BO_OK;
 }
 
 }  // namespace bo

@@ -164,6 +164,14 @@ __device__ inline double block_sum(double v, double *sh) {
     return r;
 }
 
+// ---- process-lifetime scratch ------------------------------------------------------
+// Grow-only device buffers for temporaries of host wrappers that synchronise
+// the stream before returning (so a buffer is idle whenever a call starts);
+// steady-state calls then do not allocate, and hipFree does not synchronise
+// the device.  One set per host thread; never freed.
+enum ScratchSlot { SC_SCAN = 0, SC_FLAG, SC_JAC_CNT, SC_COUNT };
+bo_status scratch_get(int slot, size_t bytes, void **ptr);
+
 // ---- host-side scan / reductions (declared in bo_linalg.hip) -------------------
 // Exclusive prefix sum of n int32 counts into out (n+1 entries, out[n] = total);
 // returns the total on the host (synchronises the stream).

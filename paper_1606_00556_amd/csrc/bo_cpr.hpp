@@ -24,9 +24,20 @@ struct Level {
     DBuf<uint8_t> root, sf;
     double omega = 0.0;
     // cycle work vectors
-    DBuf<double> x, b, r;
+    DBuf<double> x, b, r, t;
     // single-precision copies (mixed form)
     DBuf<float> v32, pv32, rv32, dinv32, x32, b32, r32;
+};
+
+// setup temporaries kept with the handle, reused (grow-only) by later setups
+struct SetupWork {
+    DBuf<uint8_t> state, nw, d1;
+    DBuf<uint64_t> m1;
+    DBuf<int32_t> cnt, id, a1, rc, fp, gcnt;
+    DBuf<double> aF;
+    DBuf<unsigned long long> rho;
+    DBuf<int32_t> aprp, apci;
+    DBuf<double> apv, dense;
 };
 
 struct Krylov {
@@ -43,6 +54,7 @@ struct Krylov {
 }  // namespace bo
 
 struct bo_cpr {
+    bool broken = false;          // a failed bo_cpr_update leaves the handle unusable
     bo::Grid g{};
     int n = 0;                    // cells
     bo_cpr_opts o{};
@@ -58,14 +70,19 @@ struct bo_cpr {
     int coarse_n = 0;
     bo::DBuf<double> cinv;        // dense inverse of the coarsest matrix
     bo::DBuf<float> cinv32;
-    // F stage: inverse pivots (SoA 9 * N)
+    // F stage: block-Jacobi inverses (SoA 9 * N), or the tiled ILU factors in
+    // (tile, step, lane) order with the cell index of each slot and the
+    // forward-sweep result in the same order
     bo::DBuf<double> einv;
+    bo::DBuf<double> ilu, ilu_w;
+    bo::DBuf<int32_t> ilu_cell;
     bo::DBuf<float> einv32;
     bo::DBuf<uint16_t> einv16, A16;  // bf16 copies (mixed-bf16 form)
     bo::DBuf<float> A32;          // fp32 copy of A's off-diagonal slots for the ILU apply
     // work vectors
     bo::DBuf<double> rp_, dp_, t3a, t3b, t3c, wf;
     bo::DBuf<int32_t> flag;
+    bo::SetupWork sw;
     bo::Reducer red;
     bo::Krylov kr;
 };

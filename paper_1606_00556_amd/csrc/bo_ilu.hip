@@ -6,22 +6,29 @@
 // only modifies the diagonal blocks: E_i = A_ii - sum_{k<i} A_ik E_k^{-1} A_ki
 // over the lower neighbours k inside the tile (natural order: -z, -y, -x).
 // The solve is w_i = E_i^{-1}(r_i - sum_{k<i} A_ik w_k) followed by
-// x_i = w_i - E_i^{-1} sum_{j>i} A_ij x_j.  Inside a tile thread (a,b) owns
-// column (i0+a, j0+b) and at step s handles layer k = s - a - b, so each cell's
-// lower (upper) neighbours were finished one step earlier (later); their
-// values pass through a double-buffered LDS array.  The inverse pivots E^{-1}
-// are stored SoA (9 x N).  Block Jacobi (x_i = A_ii^{-1} r_i) is the
-// alternative F stage.
+// x_i = w_i - E_i^{-1} sum_{j>i} A_ij x_j.
+//
+// Schedule: lane t = a + tile_x*b of the tile's wavefront owns grid column
+// (i0+a, j0+b) and at step s handles layer k = s - a - b, so its -x, -y and
+// -z neighbours were handled one step earlier by lanes t-1, t-tile_x and t
+// itself; their values arrive through cross-lane shuffles (no LDS, no
+// barriers).  The factors are stored in the same (tile, step, lane) order,
+// field by field, so each step reads every field with one contiguous 512-byte
+// wavefront load, and the next step's fields are loaded before the current
+// step is computed.  Block Jacobi (x_i = A_ii^{-1} r_i) is the alternative F
+// stage.
 #include "bo_cpr.hpp"
 
 namespace bo {
 namespace {
 
-constexpr int kTileThreads = 64;
-
 struct TileGeom {
-    int nx, ny, nz, tx, ty, ntx;
+    int nx, ny, nz, tx, ty, ntx, nty, ns;
+    __host__ __device__ long long slots() const { return (long long)ntx * nty * ns * 64; }
 };
+
+// fields of the (tile, step, lane) factor layout
+enum { F_EINV = 0, F_LZ = 9, F_LY = 18, F_LX = 27, F_UX = 36, F_UY = 45, F_UZ = 54, F_NUM = 63 };
 
 __device__ __forceinline__ void load_blk(const double *__restrict__ A, int slot, size_t N, int g, double *o) {
     const double *p = A + (size_t)slot * 9 * N + g;
@@ -35,157 +42,195 @@ __device__ __forceinline__ void mv3(const double *A, const double *x, double *y)
     y[2] = A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
 }
 
-__global__ void __launch_bounds__(kTileThreads) k_ilu_factor(TileGeom T, const double *__restrict__ A,
-                                                             double *__restrict__ einv, int32_t *__restrict__ bad) {
-    __shared__ double Es[2][kTileThreads][9];
+template <int K>
+__device__ __forceinline__ void shfl_arr(const double *src, double *dst, int lane) {
+#pragma unroll
+    for (int z = 0; z < K; z++) dst[z] = __shfl(src[z], lane, 64);
+}
+
+// Factorisation: writes E^{-1}, the lower blocks (-z,-y,-x) and upper blocks
+// (+x,+y,+z) of each cell (zero where the neighbour lies outside the tile or
+// grid) into the (tile, step, lane) layout, and the cell index of each slot
+// (-1 for idle slots).  E^{-1} by Gauss-Jordan with partial pivoting.
+__global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__restrict__ A,
+                                                   double *__restrict__ F, int32_t *__restrict__ cell,
+                                                   int32_t *__restrict__ bad) {
     int t = threadIdx.x;
     int a = t % T.tx, b = t / T.tx;
-    int ti = blockIdx.x % T.ntx, tj = blockIdx.x / T.ntx;
+    int tile = blockIdx.x;
+    int ti = tile % T.ntx, tj = tile / T.ntx;
     int i = ti * T.tx + a, j = tj * T.ty + b;
     bool active = t < T.tx * T.ty && i < T.nx && j < T.ny;
+    bool has_mx = a > 0, has_my = b > 0;
+    bool has_px = a + 1 < T.tx && i + 1 < T.nx, has_py = b + 1 < T.ty && j + 1 < T.ny;
     size_t N = (size_t)T.nx * T.ny * T.nz;
+    size_t S = (size_t)T.slots();
     int nxy = T.nx * T.ny;
-    int steps = (T.tx - 1) + (T.ty - 1) + T.nz;
-    for (int s = 0; s < steps; s++) {
+    double Ep[9], Uxp[9], Uyp[9], Uzp[9];  // this lane's values from the previous step
+    for (int z = 0; z < 9; z++) Ep[z] = Uxp[z] = Uyp[z] = Uzp[z] = 0.0;
+    for (int s = 0; s < T.ns; s++) {
+        // neighbours' previous-step values (every lane takes part in the shuffles)
+        double Ex[9], Ey[9], Ux[9], Uy[9];
+        shfl_arr<9>(Ep, Ex, has_mx ? t - 1 : t);
+        shfl_arr<9>(Uxp, Ux, has_mx ? t - 1 : t);
+        shfl_arr<9>(Ep, Ey, has_my ? t - T.tx : t);
+        shfl_arr<9>(Uyp, Uy, has_my ? t - T.tx : t);
         int k = s - a - b;
-        int cur = s & 1, prv = cur ^ 1;
+        size_t q = ((size_t)tile * T.ns + s) * 64 + t;
         if (active && k >= 0 && k < T.nz) {
             int g = i + T.nx * (j + T.ny * k);
-            double E[9], L[9], U[9], Lk[9], tmp[9];
+            double E[9], L[9], Lk[9], tmp[9];
             load_blk(A, S_D, N, g, E);
-            // lower neighbours in ascending order: -z, -y, -x
+            // -z, -y, -x in ascending order
             if (k > 0) {
                 load_blk(A, S_MZ, N, g, L);
-                load_blk(A, S_PZ, N, g - nxy, U);
-                mul3(L, Es[prv][t], Lk);
-                mul3(Lk, U, tmp);
+                mul3(L, Ep, Lk); mul3(Lk, Uzp, tmp);
                 for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
+                for (int z = 0; z < 9; z++) F[(size_t)(F_LZ + z) * S + q] = L[z];
             }
-            if (b > 0) {
+            if (has_my) {
                 load_blk(A, S_MY, N, g, L);
-                load_blk(A, S_PY, N, g - T.nx, U);
-                mul3(L, Es[prv][t - T.tx], Lk);
-                mul3(Lk, U, tmp);
+                mul3(L, Ey, Lk); mul3(Lk, Uy, tmp);
                 for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
+                for (int z = 0; z < 9; z++) F[(size_t)(F_LY + z) * S + q] = L[z];
             }
-            if (a > 0) {
+            if (has_mx) {
                 load_blk(A, S_MX, N, g, L);
-                load_blk(A, S_PX, N, g - 1, U);
-                mul3(L, Es[prv][t - 1], Lk);
-                mul3(Lk, U, tmp);
+                mul3(L, Ex, Lk); mul3(Lk, Ux, tmp);
                 for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
+                for (int z = 0; z < 9; z++) F[(size_t)(F_LX + z) * S + q] = L[z];
             }
             double Ei[9];
             if (!inv3_gj(E, Ei)) {
                 *bad = 1;
                 for (int z = 0; z < 9; z++) Ei[z] = 0.0;
             }
+            for (int z = 0; z < 9; z++) { F[(size_t)(F_EINV + z) * S + q] = Ei[z]; Ep[z] = Ei[z]; }
+            // upper blocks: this row's +x, +y, +z (zero outside the tile)
+            if (has_px) load_blk(A, S_PX, N, g, Uxp); else for (int z = 0; z < 9; z++) Uxp[z] = 0.0;
+            if (has_py) load_blk(A, S_PY, N, g, Uyp); else for (int z = 0; z < 9; z++) Uyp[z] = 0.0;
+            if (k + 1 < T.nz) load_blk(A, S_PZ, N, g, Uzp); else for (int z = 0; z < 9; z++) Uzp[z] = 0.0;
             for (int z = 0; z < 9; z++) {
-                Es[cur][t][z] = Ei[z];
-                einv[(size_t)z * N + g] = Ei[z];
+                F[(size_t)(F_UX + z) * S + q] = Uxp[z];
+                F[(size_t)(F_UY + z) * S + q] = Uyp[z];
+                F[(size_t)(F_UZ + z) * S + q] = Uzp[z];
             }
+            cell[q] = g;
+            (void)nxy;
+        } else {
+            cell[q] = -1;
         }
-        __syncthreads();
     }
 }
 
-// forward sweep: w = (E + A_L)^{-1}-type solve, stored in w (3N)
-__global__ void __launch_bounds__(kTileThreads) k_ilu_forward(TileGeom T, const double *__restrict__ A,
-                                                              const double *__restrict__ einv,
-                                                              const double *__restrict__ r, double *__restrict__ w) {
-    __shared__ double Ws[2][kTileThreads][3];
-    int t = threadIdx.x;
-    int a = t % T.tx, b = t / T.tx;
-    int ti = blockIdx.x % T.ntx, tj = blockIdx.x / T.ntx;
-    int i = ti * T.tx + a, j = tj * T.ty + b;
-    bool active = t < T.tx * T.ty && i < T.nx && j < T.ny;
-    size_t N = (size_t)T.nx * T.ny * T.nz;
-    int steps = (T.tx - 1) + (T.ty - 1) + T.nz;
-    for (int s = 0; s < steps; s++) {
-        int k = s - a - b;
-        int cur = s & 1, prv = cur ^ 1;
-        if (active && k >= 0 && k < T.nz) {
-            int g = i + T.nx * (j + T.ny * k);
-            double v[3] = {r[3 * (size_t)g], r[3 * (size_t)g + 1], r[3 * (size_t)g + 2]};
-            double L[9], y[3];
-            if (k > 0) {
-                load_blk(A, S_MZ, N, g, L);
-                mv3(L, Ws[prv][t], y);
-                v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
-            }
-            if (b > 0) {
-                load_blk(A, S_MY, N, g, L);
-                mv3(L, Ws[prv][t - T.tx], y);
-                v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
-            }
-            if (a > 0) {
-                load_blk(A, S_MX, N, g, L);
-                mv3(L, Ws[prv][t - 1], y);
-                v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
-            }
-            double Ei[9], o[3];
-            for (int z = 0; z < 9; z++) Ei[z] = einv[(size_t)z * N + g];
-            mv3(Ei, v, o);
-            for (int c = 0; c < 3; c++) {
-                Ws[cur][t][c] = o[c];
-                w[3 * (size_t)g + c] = o[c];
-            }
-        }
-        __syncthreads();
+struct Fwd {
+    double e[9], lz[9], ly[9], lx[9];
+    int g;
+};
+
+__device__ __forceinline__ void load_fwd(const double *__restrict__ F, const int32_t *__restrict__ cell, size_t S,
+                                         size_t q, Fwd &f) {
+    f.g = cell[q];
+#pragma unroll
+    for (int z = 0; z < 9; z++) {
+        f.e[z] = F[(size_t)(F_EINV + z) * S + q];
+        f.lz[z] = F[(size_t)(F_LZ + z) * S + q];
+        f.ly[z] = F[(size_t)(F_LY + z) * S + q];
+        f.lx[z] = F[(size_t)(F_LX + z) * S + q];
     }
 }
 
-// backward sweep: x_i = w_i - E_i^{-1} sum_{upper} A_ij x_j; writes
-// out = x + (dp, 0, 0) when dp != NULL, else out = x.
-__global__ void __launch_bounds__(kTileThreads) k_ilu_backward(TileGeom T, const double *__restrict__ A,
-                                                               const double *__restrict__ einv,
-                                                               const double *__restrict__ w,
-                                                               const double *__restrict__ dp,
-                                                               double *__restrict__ out) {
-    __shared__ double Xs[2][kTileThreads][3];
+// forward sweep; w is stored in (tile, step, lane) order: wq[c * S + q]
+__global__ void __launch_bounds__(64) k_ilu_forward(TileGeom T, const double *__restrict__ F,
+                                                    const int32_t *__restrict__ cell, const double *__restrict__ r,
+                                                    double *__restrict__ wq) {
     int t = threadIdx.x;
     int a = t % T.tx, b = t / T.tx;
-    int ti = blockIdx.x % T.ntx, tj = blockIdx.x / T.ntx;
-    int i = ti * T.tx + a, j = tj * T.ty + b;
-    bool active = t < T.tx * T.ty && i < T.nx && j < T.ny;
-    bool has_px = a + 1 < T.tx && i + 1 < T.nx;
-    bool has_py = b + 1 < T.ty && j + 1 < T.ny;
-    size_t N = (size_t)T.nx * T.ny * T.nz;
-    int steps = (T.tx - 1) + (T.ty - 1) + T.nz;
-    for (int s = steps - 1; s >= 0; s--) {
-        int k = s - a - b;
-        int cur = s & 1, nxt = cur ^ 1;
-        if (active && k >= 0 && k < T.nz) {
-            int g = i + T.nx * (j + T.ny * k);
-            double acc[3] = {0.0, 0.0, 0.0};
-            double U[9], y[3];
-            if (has_px) {
-                load_blk(A, S_PX, N, g, U);
-                mv3(U, Xs[nxt][t + 1], y);
-                acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
-            }
-            if (has_py) {
-                load_blk(A, S_PY, N, g, U);
-                mv3(U, Xs[nxt][t + T.tx], y);
-                acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
-            }
-            if (k + 1 < T.nz) {
-                load_blk(A, S_PZ, N, g, U);
-                mv3(U, Xs[nxt][t], y);
-                acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
-            }
-            double Ei[9], c3[3];
-            for (int z = 0; z < 9; z++) Ei[z] = einv[(size_t)z * N + g];
-            mv3(Ei, acc, c3);
-            double x0 = w[3 * (size_t)g] - c3[0];
-            double x1 = w[3 * (size_t)g + 1] - c3[1];
-            double x2 = w[3 * (size_t)g + 2] - c3[2];
-            Xs[cur][t][0] = x0; Xs[cur][t][1] = x1; Xs[cur][t][2] = x2;
-            out[3 * (size_t)g] = dp ? dp[g] + x0 : x0;
-            out[3 * (size_t)g + 1] = x1;
-            out[3 * (size_t)g + 2] = x2;
+    int tile = blockIdx.x;
+    size_t S = (size_t)T.slots();
+    int lx = a > 0 ? t - 1 : t, ly = b > 0 ? t - T.tx : t;
+    double wp[3] = {0.0, 0.0, 0.0};
+    // two steps of factors in flight ahead of the one being computed
+    Fwd cur, n1, n2;
+    load_fwd(F, cell, S, ((size_t)tile * T.ns) * 64 + t, n1);
+    if (T.ns > 1) load_fwd(F, cell, S, ((size_t)tile * T.ns + 1) * 64 + t, n2);
+    for (int s = 0; s < T.ns; s++) {
+        cur = n1;
+        n1 = n2;
+        if (s + 2 < T.ns) load_fwd(F, cell, S, ((size_t)tile * T.ns + s + 2) * 64 + t, n2);
+        double wy[3], wx[3];
+        for (int c = 0; c < 3; c++) { wx[c] = __shfl(wp[c], lx, 64); wy[c] = __shfl(wp[c], ly, 64); }
+        if (cur.g >= 0) {
+            size_t g = (size_t)cur.g;
+            double v[3] = {r[3 * g], r[3 * g + 1], r[3 * g + 2]};
+            double y[3];
+            // zero blocks stand for missing neighbours
+            mv3(cur.lz, wp, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
+            mv3(cur.ly, wy, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
+            mv3(cur.lx, wx, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
+            mv3(cur.e, v, wp);
+            size_t q = ((size_t)tile * T.ns + s) * 64 + t;
+            wq[q] = wp[0]; wq[S + q] = wp[1]; wq[2 * S + q] = wp[2];
+        } else {
+            wp[0] = wp[1] = wp[2] = 0.0;
         }
-        __syncthreads();
+    }
+}
+
+struct Bwd {
+    double e[9], ux[9], uy[9], uz[9], w[3];
+    int g;
+};
+
+__device__ __forceinline__ void load_bwd(const double *__restrict__ F, const int32_t *__restrict__ cell,
+                                         const double *__restrict__ wq, size_t S, size_t q, Bwd &f) {
+    f.g = cell[q];
+#pragma unroll
+    for (int z = 0; z < 9; z++) {
+        f.e[z] = F[(size_t)(F_EINV + z) * S + q];
+        f.ux[z] = F[(size_t)(F_UX + z) * S + q];
+        f.uy[z] = F[(size_t)(F_UY + z) * S + q];
+        f.uz[z] = F[(size_t)(F_UZ + z) * S + q];
+    }
+    f.w[0] = wq[q]; f.w[1] = wq[S + q]; f.w[2] = wq[2 * S + q];
+}
+
+// backward sweep: x_i = w_i - E_i^{-1} sum_{upper} A_ij x_j, written in
+// natural order as out = x + (dp, 0, 0) (dp may be NULL)
+__global__ void __launch_bounds__(64) k_ilu_backward(TileGeom T, const double *__restrict__ F,
+                                                     const int32_t *__restrict__ cell, const double *__restrict__ wq,
+                                                     const double *__restrict__ dp, double *__restrict__ out) {
+    int t = threadIdx.x;
+    int a = t % T.tx, b = t / T.tx;
+    int tile = blockIdx.x;
+    size_t S = (size_t)T.slots();
+    int px = a + 1 < T.tx && t + 1 < 64 ? t + 1 : t;
+    int py = b + 1 < T.ty && t + T.tx < 64 ? t + T.tx : t;
+    double xp[3] = {0.0, 0.0, 0.0};
+    // the forward sweep must have finished this tile: wq is read ahead
+    Bwd cur, n1, n2;
+    load_bwd(F, cell, wq, S, ((size_t)tile * T.ns + T.ns - 1) * 64 + t, n1);
+    if (T.ns > 1) load_bwd(F, cell, wq, S, ((size_t)tile * T.ns + T.ns - 2) * 64 + t, n2);
+    for (int s = T.ns - 1; s >= 0; s--) {
+        cur = n1;
+        n1 = n2;
+        if (s >= 2) load_bwd(F, cell, wq, S, ((size_t)tile * T.ns + s - 2) * 64 + t, n2);
+        double xx[3], xy[3];
+        for (int c = 0; c < 3; c++) { xx[c] = __shfl(xp[c], px, 64); xy[c] = __shfl(xp[c], py, 64); }
+        if (cur.g >= 0) {
+            double acc[3], y[3];
+            mv3(cur.ux, xx, acc);
+            mv3(cur.uy, xy, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
+            mv3(cur.uz, xp, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
+            mv3(cur.e, acc, y);
+            xp[0] = cur.w[0] - y[0]; xp[1] = cur.w[1] - y[1]; xp[2] = cur.w[2] - y[2];
+            size_t g = (size_t)cur.g;
+            out[3 * g] = dp ? dp[g] + xp[0] : xp[0];
+            out[3 * g + 1] = xp[1];
+            out[3 * g + 2] = xp[2];
+        } else {
+            xp[0] = xp[1] = xp[2] = 0.0;
+        }
     }
 }
 
@@ -221,6 +266,8 @@ TileGeom geom(const bo_cpr *pc) {
     T.nx = pc->g.nx; T.ny = pc->g.ny; T.nz = pc->g.nz;
     T.tx = pc->o.tile_x; T.ty = pc->o.tile_y;
     T.ntx = (T.nx + T.tx - 1) / T.tx;
+    T.nty = (T.ny + T.ty - 1) / T.ty;
+    T.ns = (T.tx - 1) + (T.ty - 1) + T.nz;
     return T;
 }
 
@@ -228,14 +275,18 @@ TileGeom geom(const bo_cpr *pc) {
 
 bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
     long long n = pc->n;
-    BO_TRY(pc->einv.alloc(9 * n));
     BO_HIP(hipMemsetAsync(pc->flag.p, 0, sizeof(int32_t), s));
     if (pc->o.ftype == BO_F_BJ) {
+        BO_TRY(pc->einv.alloc(9 * n));
         k_bj_setup<<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, pc->einv.p, pc->flag.p);
     } else {
         TileGeom T = geom(pc);
-        int nty = (T.ny + T.ty - 1) / T.ty;
-        k_ilu_factor<<<T.ntx * nty, kTileThreads, 0, s>>>(T, pc->A.p, pc->einv.p, pc->flag.p);
+        size_t S = (size_t)T.slots();
+        BO_TRY(pc->ilu.alloc(S * F_NUM));
+        BO_TRY(pc->ilu_cell.alloc(S));
+        BO_TRY(pc->ilu_w.alloc(3 * S));
+        BO_HIP(hipMemsetAsync(pc->ilu.p, 0, sizeof(double) * S * F_NUM, s));
+        k_ilu_factor<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->A.p, pc->ilu.p, pc->ilu_cell.p, pc->flag.p);
     }
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
@@ -245,16 +296,16 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
     return BO_OK;
 }
 
-// out = F(r) (+ Pi_p dp when dp != NULL); wbuf is 3N scratch
+// out = F(r) (+ Pi_p dp when dp != NULL)
 bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, double *wbuf, hipStream_t s) {
+    (void)wbuf;
     long long n = pc->n;
     if (pc->o.ftype == BO_F_BJ) {
         k_bj_apply<<<grid_for(n), kBlock, 0, s>>>(n, pc->einv.p, r, dp, out);
     } else {
         TileGeom T = geom(pc);
-        int nty = (T.ny + T.ty - 1) / T.ty;
-        k_ilu_forward<<<T.ntx * nty, kTileThreads, 0, s>>>(T, pc->A.p, pc->einv.p, r, wbuf);
-        k_ilu_backward<<<T.ntx * nty, kTileThreads, 0, s>>>(T, pc->A.p, pc->einv.p, wbuf, dp, out);
+        k_ilu_forward<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->ilu.p, pc->ilu_cell.p, r, pc->ilu_w.p);
+        k_ilu_backward<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->ilu.p, pc->ilu_cell.p, pc->ilu_w.p, dp, out);
     }
     BO_HIP(hipGetLastError());
     return BO_OK;

@@ -283,14 +283,20 @@ __device__ inline double well_index(const GridG &G, const Fl &f, int cell, doubl
     return f.tcoef * 2.0 * M_PI * sqrt(kx * ky) * G.dz / (log(ro / rw) + skin);
 }
 
-// One thread per well: subtract the source from R (b += q) and dq from the
-// diagonal block of each perforated cell.
-__global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nwells,
-                            const bo_well *__restrict__ wells, const int32_t *__restrict__ diag_pos,
+constexpr int kWellChunk = 64;
+struct WellChunk {
+    bo_well w[kWellChunk];
+};
+
+// One thread per well (a chunk of up to 64 wells passed by value): subtract
+// the source from R (b += q) and dq from the diagonal block of each
+// perforated cell.
+__global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nwells, WellChunk wells,
+                            const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
                             double *__restrict__ val, double *__restrict__ b) {
     int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nwells) return;
-    bo_well W = wells[w];
+    bo_well W = wells.w[w];
     double gg = f.gravity ? f.grav : 0.0;
     int top = W.i + G.nx * (W.j + G.ny * W.k_top);
     double zh = depth_of(G, top);
@@ -333,22 +339,14 @@ __global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nw
             dq[2][1] = c.rs * dq[0][1];
             dq[2][2] = WI * c.lg_g * c.bg * d_g + c.rs * dq[0][2];
         }
-        double *J = val + 9 * (size_t)diag_pos[cell];
+        int dpos = rowptr[cell];
+        while (colind[dpos] != cell) dpos++;  // the diagonal is in the row by construction
+        double *J = val + 9 * (size_t)dpos;
         for (int r = 0; r < 3; r++) {
             b[3 * (size_t)cell + r] = b[3 * (size_t)cell + r] + q[r];
             for (int s = 0; s < 3; s++) J[3 * r + s] = J[3 * r + s] - dq[r][s];
         }
     }
-}
-
-// position of the diagonal block of each row
-__global__ void k_diag_pos(int n, const int32_t *rowptr, const int32_t *colind, int32_t *pos) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    int p = -1;
-    for (int e = rowptr[g]; e < rowptr[g + 1]; e++)
-        if (colind[e] == g) p = e;
-    pos[g] = p;
 }
 
 }  // namespace
@@ -396,11 +394,11 @@ extern "C" bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, c
     hipStream_t s = (hipStream_t)stream;
     J->nbrows = n;
     J->nnzb = nnz;
-    DBuf<int32_t> cnt;
-    BO_TRY(cnt.alloc(n));
-    k_row_counts<<<grid_for(n), kBlock, 0, s>>>(p->nx, p->ny, p->nz, cnt.p);
+    int32_t *cnt = nullptr;
+    BO_TRY(scratch_get(SC_JAC_CNT, sizeof(int32_t) * (size_t)n, (void **)&cnt));
+    k_row_counts<<<grid_for(n), kBlock, 0, s>>>(p->nx, p->ny, p->nz, cnt);
     int32_t total = 0;
-    BO_TRY(scan_counts(cnt.p, J->rowptr, n, &total, s));
+    BO_TRY(scan_counts(cnt, J->rowptr, n, &total, s));
     if (total != nnz) return fail(BO_ERR_HIP, "row count scan disagrees with the pattern size");
     GridG G{p->nx, p->ny, p->nz, p->dx, p->dy, p->dz, p->top_depth, p->kx, p->ky, p->kz, p->phi0};
     const bo_fluid &q = p->fluid;
@@ -411,17 +409,12 @@ extern "C" bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, c
     double acc = p->dx * p->dy * p->dz / (q.rb_ft3 * dt);
     k_jac_cells<<<grid_for(n), kBlock, 0, s>>>(G, f, x_old, x_new, acc, J->rowptr, J->colind, J->val, b);
     BO_HIP(hipGetLastError());
-    if (p->nwells > 0) {
-        DBuf<bo_well> dw;
-        DBuf<int32_t> dpos;
-        BO_TRY(dw.alloc(p->nwells));
-        BO_TRY(dpos.alloc(n));
-        BO_HIP(hipMemcpyAsync(dw.p, p->wells, sizeof(bo_well) * p->nwells, hipMemcpyHostToDevice, s));
-        k_diag_pos<<<grid_for(n), kBlock, 0, s>>>(n, J->rowptr, J->colind, dpos.p);
-        k_jac_wells<<<grid_for(p->nwells, 64), 64, 0, s>>>(G, f, x_new, p->nwells, dw.p, dpos.p, J->val, b);
+    for (int w0 = 0; w0 < p->nwells; w0 += kWellChunk) {
+        WellChunk ch{};
+        int cnt = std::min(kWellChunk, p->nwells - w0);
+        for (int q = 0; q < cnt; q++) ch.w[q] = p->wells[w0 + q];
+        k_jac_wells<<<1, kWellChunk, 0, s>>>(G, f, x_new, cnt, ch, J->rowptr, J->colind, J->val, b);
         BO_HIP(hipGetLastError());
-        // the temporaries are released when this call returns: wait for their users
-        BO_HIP(hipStreamSynchronize(s));
     }
     return BO_OK;
 }

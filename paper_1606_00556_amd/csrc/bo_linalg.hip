@@ -9,8 +9,8 @@
 // are skipped.
 //
 // Reductions are deterministic: a fixed grid of workgroups writes per-group
-// partial sums in a fixed tree order, and the last group to finish (found with
-// an atomic ticket) adds the partials in index order.
+// partial sums in a fixed tree order, and a second one-workgroup kernel adds
+// the partials in a fixed order (no device-scope fences in the hot loop).
 #include <algorithm>
 #include "bo_common.hpp"
 #include "bo_linalg.hpp"
@@ -23,6 +23,24 @@ void set_error(const std::string &msg) { g_err = msg; }
 bo_status fail(bo_status st, const std::string &msg) {
     g_err = msg;
     return st;
+}
+
+bo_status scratch_get(int slot, size_t bytes, void **ptr) {
+    static thread_local void *buf[SC_COUNT] = {};
+    static thread_local size_t cap[SC_COUNT] = {};
+    if (slot < 0 || slot >= SC_COUNT) return fail(BO_ERR_INVALID_ARG, "scratch slot");
+    if (bytes > cap[slot]) {
+        if (buf[slot]) (void)hipFree(buf[slot]);
+        buf[slot] = nullptr;
+        cap[slot] = 0;
+        size_t want = std::max<size_t>(bytes, 4096);
+        hipError_t e = hipMalloc(&buf[slot], want);
+        if (e != hipSuccess)
+            return fail(BO_ERR_ALLOC, std::string("scratch hipMalloc failed: ") + hipGetErrorString(e));
+        cap[slot] = want;
+    }
+    *ptr = buf[slot];
+    return BO_OK;
 }
 
 // ---- scan ------------------------------------------------------------------
@@ -91,11 +109,11 @@ bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total
         return BO_OK;
     }
     int nb = (n + kScanBlock - 1) / kScanBlock;
-    DBuf<int32_t> sums;
-    BO_TRY(sums.alloc(nb));
-    k_block_sums<<<nb, kScanBlock, 0, s>>>(counts, n, sums.p);
-    k_scan_sums<<<1, kScanBlock, 0, s>>>(sums.p, nb);
-    k_scan_apply<<<nb, kScanBlock, 0, s>>>(counts, n, sums.p, out);
+    int32_t *sums = nullptr;
+    BO_TRY(scratch_get(SC_SCAN, sizeof(int32_t) * nb, (void **)&sums));
+    k_block_sums<<<nb, kScanBlock, 0, s>>>(counts, n, sums);
+    k_scan_sums<<<1, kScanBlock, 0, s>>>(sums, nb);
+    k_scan_apply<<<nb, kScanBlock, 0, s>>>(counts, n, sums, out);
     BO_HIP(hipGetLastError());
     int32_t tot = 0;
     BO_HIP(hipMemcpyAsync(&tot, out + n, sizeof tot, hipMemcpyDeviceToHost, s));
@@ -222,14 +240,19 @@ __global__ void k_fill(long long n, double v, double *__restrict__ y) {
     if (i < n) y[i] = v;
 }
 
-// Multi-dot: out[q] = sum_e x[e] * V[q][e] for q < nv (nv <= NV), in the
-// fixed partial-sum order described at the top of this file.
+// wavefront sum by butterfly shuffles (fixed order)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Multi-dot, pass 1: each of the kRedBlocks workgroups writes the partial
+// sums of its grid-stride share, partial[q * nblocks + block] = sum x[e] V[q][e].
 template <int NV>
-__global__ void __launch_bounds__(kBlock) k_multidot(long long n, const double *__restrict__ x, VecList V, int nv,
-                                                     double *__restrict__ partial, unsigned *__restrict__ ticket,
-                                                     double *__restrict__ out) {
-    __shared__ double sh[kBlock];
-    __shared__ bool last;
+__global__ void __launch_bounds__(kBlock) k_multidot_partial(long long n, const double *__restrict__ x, VecList V,
+                                                             double *__restrict__ partial) {
+    __shared__ double sh[NV][kBlock / 64];
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; q++) acc[q] = 0.0;
@@ -237,27 +260,40 @@ __global__ void __launch_bounds__(kBlock) k_multidot(long long n, const double *
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
         double xe = x[e];
 #pragma unroll
-        for (int q = 0; q < NV; q++)
-            if (q < nv) acc[q] = acc[q] + xe * V.p[q][e];
+        for (int q = 0; q < NV; q++) acc[q] = acc[q] + xe * V.p[q][e];
     }
-    for (int q = 0; q < nv; q++) {
-        double s = block_sum(acc[q], sh);
-        if (threadIdx.x == 0) partial[(size_t)q * gridDim.x + blockIdx.x] = s;
+    int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        double w = wave_sum(acc[q]);
+        if (lane == 0) sh[q][wave] = w;
     }
-    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+    if (threadIdx.x < NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; w++) t = t + sh[threadIdx.x][w];
+        partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// pass 2 (one workgroup): out[q] = sum over the partials in a fixed order
+__global__ void __launch_bounds__(kBlock) k_partial_final(int nblocks, int nv, const double *__restrict__ partial,
+                                                          double *__restrict__ out) {
+    __shared__ double sh[16][kBlock / 64];
+    int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     for (int q = 0; q < nv; q++) {
         double s = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
-            s = s + ((volatile const double *)partial)[(size_t)q * gridDim.x + b];
-        s = block_sum(s, sh);
-        if (threadIdx.x == 0) out[q] = s;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s = s + partial[(size_t)q * nblocks + b];
+        s = wave_sum(s);
+        if (lane == 0) sh[q][wave] = s;
     }
-    if (threadIdx.x == 0) *ticket = 0u;
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; w++) t = t + sh[threadIdx.x][w];
+        out[threadIdx.x] = t;
+    }
 }
 
 // y = y + sign * sum_q h[q] * V[q]  (h on the device)
@@ -301,13 +337,13 @@ bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, co
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s) {
     long long n = g.n();
-    DBuf<int32_t> bad;
-    BO_TRY(bad.alloc(1));
-    BO_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
-    k_bsr_to_slots<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, rp, ci, v, slots, bad.p);
+    int32_t *bad = nullptr;
+    BO_TRY(scratch_get(SC_FLAG, sizeof(int32_t), (void **)&bad));
+    BO_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+    k_bsr_to_slots<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, rp, ci, v, slots, bad);
     BO_HIP(hipGetLastError());
     int32_t h = 0;
-    BO_HIP(hipMemcpyAsync(&h, bad.p, sizeof h, hipMemcpyDeviceToHost, s));
+    BO_HIP(hipMemcpyAsync(&h, bad, sizeof h, hipMemcpyDeviceToHost, s));
     BO_HIP(hipStreamSynchronize(s));
     if (h) return fail(BO_ERR_UNSUPPORTED, "matrix pattern is not the 7-point stencil of the grid");
     return BO_OK;
@@ -344,9 +380,17 @@ bo_status scale_copy(long long n, const double *inv, const double *x, double *y,
 
 bo_status Reducer::init() {
     BO_TRY(partial.alloc((size_t)kRedBlocks * 16));
-    BO_TRY(ticket.alloc(1));
-    BO_HIP(hipMemset(ticket.p, 0, sizeof(unsigned)));
     return BO_OK;
+}
+
+static void launch_partial(int nv, long long n, const double *x, const VecList &L, double *partial, hipStream_t s) {
+    switch (nv) {
+#define BO_MD(K) case K: k_multidot_partial<K><<<kRedBlocks, kBlock, 0, s>>>(n, x, L, partial); break;
+        BO_MD(1) BO_MD(2) BO_MD(3) BO_MD(4) BO_MD(5) BO_MD(6) BO_MD(7) BO_MD(8)
+        BO_MD(9) BO_MD(10) BO_MD(11) BO_MD(12) BO_MD(13) BO_MD(14) BO_MD(15) BO_MD(16)
+#undef BO_MD
+    default: break;
+    }
 }
 
 bo_status Reducer::multidot(long long n, const double *x, const double *const *Vhost, int nv, double *out,
@@ -355,7 +399,8 @@ bo_status Reducer::multidot(long long n, const double *x, const double *const *V
         int c = std::min(16, nv - q0);
         VecList L{};
         for (int q = 0; q < c; q++) L.p[q] = Vhost[q0 + q];
-        k_multidot<16><<<kRedBlocks, kBlock, 0, s>>>(n, x, L, c, partial.p, ticket.p, out + q0);
+        launch_partial(c, n, x, L, partial.p, s);
+        k_partial_final<<<1, kBlock, 0, s>>>(kRedBlocks, c, partial.p, out + q0);
     }
     BO_HIP(hipGetLastError());
     return BO_OK;
@@ -364,7 +409,8 @@ bo_status Reducer::multidot(long long n, const double *x, const double *const *V
 bo_status Reducer::dot(long long n, const double *x, const double *y, double *out, hipStream_t s) {
     VecList L{};
     L.p[0] = y;
-    k_multidot<1><<<kRedBlocks, kBlock, 0, s>>>(n, x, L, 1, partial.p, ticket.p, out);
+    launch_partial(1, n, x, L, partial.p, s);
+    k_partial_final<<<1, kBlock, 0, s>>>(kRedBlocks, 1, partial.p, out);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }

@@ -28,7 +28,6 @@ constexpr int kRedBlocks = 1024;  // fixed reduction grid (determinism)
 // Deterministic dot products; results land in device memory.
 struct Reducer {
     DBuf<double> partial;
-    DBuf<unsigned> ticket;
     bo_status init();
     // out[q] = <x, V[q]>, q < nv; Vhost is a host array of device pointers
     bo_status multidot(long long n, const double *x, const double *const *Vhost, int nv, double *out,

@@ -24,6 +24,7 @@ bo_status qi_decouple(bo_cpr *pc, hipStream_t s);
 bo_status qi_restrict(bo_cpr *pc, const double *v, double *rp, hipStream_t s);
 bo_status amg_setup(bo_cpr *pc, hipStream_t s);
 bo_status amg_vcycle(bo_cpr *pc, const double *b, double *x, hipStream_t s);
+bo_status amg_vcycle_ptr(bo_cpr *pc, const double *b, const double **res, hipStream_t s);
 bo_status fstage_setup(bo_cpr *pc, hipStream_t s);
 bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, double *wbuf, hipStream_t s);
 
@@ -46,10 +47,11 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     const Grid &g = pc->g;
     if (!pc->o.fpf) {
         if (pc->o.use_amg) {
+            const double *dp;
             BO_TRY(qi_restrict(pc, v, pc->rp_.p, s));
-            BO_TRY(amg_vcycle(pc, pc->rp_.p, pc->dp_.p, s));
-            BO_TRY(slot_col0_residual(g, pc->A.p, v, pc->dp_.p, pc->t3a.p, s));
-            return fstage_apply(pc, pc->t3a.p, pc->dp_.p, z, pc->wf.p, s);
+            BO_TRY(amg_vcycle_ptr(pc, pc->rp_.p, &dp, s));
+            BO_TRY(slot_col0_residual(g, pc->A.p, v, dp, pc->t3a.p, s));
+            return fstage_apply(pc, pc->t3a.p, dp, z, pc->wf.p, s);
         }
         return fstage_apply(pc, v, nullptr, z, pc->wf.p, s);
     }
@@ -58,9 +60,10 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     if (pc->o.use_amg) {
         BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
         BO_TRY(slot_spmv(g, pc->A.p, -1.0, z, 1.0, pc->t3a.p, s));
+        const double *dp;
         BO_TRY(qi_restrict(pc, pc->t3a.p, pc->rp_.p, s));
-        BO_TRY(amg_vcycle(pc, pc->rp_.p, pc->dp_.p, s));
-        k_add_p<<<grid_for(n), kBlock, 0, s>>>(n, pc->dp_.p, z);
+        BO_TRY(amg_vcycle_ptr(pc, pc->rp_.p, &dp, s));
+        k_add_p<<<grid_for(n), kBlock, 0, s>>>(n, dp, z);
         BO_HIP(hipGetLastError());
     }
     BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
@@ -164,6 +167,23 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
     return BO_OK;
 }
 
+extern "C" bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream) {
+    if (!pc || !A || !A->rowptr || !A->colind || !A->val)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: NULL argument");
+    if (A->nbrows != pc->n) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: matrix size differs from the setup");
+    bo_grid g{pc->g.nx, pc->g.ny, pc->g.nz};
+    bo_cpr_opts o = pc->o;
+    bo_status st = setup_impl(A, &g, &o, pc, (hipStream_t)stream);
+    if (st != BO_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        pc->nlev = 0;
+        pc->broken = true;
+    } else {
+        pc->broken = false;
+    }
+    return st;
+}
+
 extern "C" void bo_cpr_destroy(bo_cpr *pc) {
     if (!pc) return;
     (void)hipDeviceSynchronize();
@@ -172,6 +192,7 @@ extern "C" void bo_cpr_destroy(bo_cpr *pc) {
 
 extern "C" bo_status bo_cpr_apply(bo_cpr *pc, const double *v, double *z, void *stream) {
     if (!pc || !v || !z) return fail(BO_ERR_INVALID_ARG, "bo_cpr_apply: NULL argument");
+    if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_cpr_apply: the last bo_cpr_update failed");
     return cpr_apply(pc, v, z, (hipStream_t)stream);
 }
 
@@ -270,6 +291,7 @@ bo_status krylov_alloc(bo_cpr *pc, int m) {
 extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, const bo_fgmres_opts *opts,
                                      bo_solve_stats *stats, void *stream) {
     if (!pc || !b || !x || !opts) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: NULL argument");
+    if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: the last bo_cpr_update failed");
     int m = opts->m;
     if (m < 1 || m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || (opts->orth != 0 && opts->orth != 1))
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");

@@ -291,3 +291,42 @@ def test_pattern_mismatch_is_rejected(B, O):
     with pytest.raises(B.BoError) as e:
         B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx + 1, case.ny, case.nz))
     assert e.value.status == B.BO_ERR_INVALID_ARG
+
+
+def test_update_equals_fresh_setup(B, O):
+    """bo_cpr_update on a new Jacobian gives bit-identical results to a fresh
+    bo_cpr_setup of that Jacobian (the setup is deterministic)."""
+    import torch
+    c1 = ragged_case(seed=51)
+    c2 = ragged_case(seed=52)
+    _, rp1, ci1, val1, b1 = oracle_system(O, c1)
+    _, rp2, ci2, val2, b2 = oracle_system(O, c2)
+    grid = (c1.nx, c1.ny, c1.nz)
+    pc = B.bo_cpr_setup(device_bsr(B, rp1, ci1, val1), grid)
+    B.bo_cpr_update(pc, device_bsr(B, rp2, ci2, val2))
+    fresh = B.bo_cpr_setup(device_bsr(B, rp2, ci2, val2), grid)
+    v = np.random.default_rng(9).standard_normal(3 * c2.n)
+    a = run_stage(B, pc, B.bo_cpr_apply, v, 3 * c2.n)
+    f = run_stage(B, fresh, B.bo_cpr_apply, v, 3 * c2.n)
+    assert np.array_equal(a, f)
+    x1 = torch.zeros(3 * c2.n, dtype=torch.float64, device="cuda")
+    x2 = torch.zeros_like(x1)
+    i1 = B.bo_fgmres_solve(pc, to_dev(b2), x1)
+    i2 = B.bo_fgmres_solve(fresh, to_dev(b2), x2)
+    assert i1["iterations"] == i2["iterations"] and np.array_equal(to_host(x1), to_host(x2))
+
+
+def test_failed_update_leaves_handle_unusable(B, O):
+    import torch
+    c1 = ragged_case(seed=53)
+    _, rp, ci, val, b = oracle_system(O, c1)
+    pc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (c1.nx, c1.ny, c1.nz))
+    bad = val.copy()
+    bad[7, 0, 0] = np.nan
+    with pytest.raises(B.BoError):
+        B.bo_cpr_update(pc, device_bsr(B, rp, ci, bad))
+    x = torch.zeros(3 * c1.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.BoError):
+        B.bo_fgmres_solve(pc, to_dev(b), x)
+    B.bo_cpr_update(pc, device_bsr(B, rp, ci, val))
+    assert B.bo_fgmres_solve(pc, to_dev(b), x)["converged"]
