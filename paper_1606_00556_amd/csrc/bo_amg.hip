@@ -130,13 +130,16 @@ __global__ void k_diag(int n, const int32_t *__restrict__ rp, const int32_t *__r
     dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
 }
 
+// G lanes per row, each entry on its own
+template <int G>
 __global__ void k_strength(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                            const double *__restrict__ v, const int32_t *__restrict__ dpos, double t2,
                            uint8_t *__restrict__ sf) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = gid / G, sub = gid % G;
     if (i >= n) return;
     double aii = dpos[i] >= 0 ? v[dpos[i]] : 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; e++) {
+    for (int e = rp[i] + sub; e < rp[i + 1]; e += G) {
         int j = ci[e];
         if (j == i) { sf[e] = 0; continue; }
         double ajj = dpos[j] >= 0 ? v[dpos[j]] : 0.0;
@@ -658,10 +661,22 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double *__restrict
         int ncol = w - (k + 1);
         int rows_per = (int)blockDim.x / ncol;
         if (rows_per >= 1) {
+            // f[k] = 0 leaves the pivot row unchanged; rows go in batches of
+            // four independent updates
             int rr0 = t / ncol, c = k + 1 + t % ncol;
-            if (rr0 < rows_per)
-                for (int rr = rr0; rr < n; rr += rows_per)
-                    if (rr != k) M[rr * w + c] = M[rr * w + c] - f[rr] * M[k * w + c];
+            if (rr0 < rows_per) {
+                double pk = M[k * w + c];
+                int rr = rr0;
+                for (; rr + 3 * rows_per < n; rr += 4 * rows_per) {
+                    int r1 = rr + rows_per, r2 = rr + 2 * rows_per, r3 = rr + 3 * rows_per;
+                    double m0 = M[rr * w + c], m1 = M[r1 * w + c], m2 = M[r2 * w + c], m3 = M[r3 * w + c];
+                    M[rr * w + c] = m0 - f[rr] * pk;
+                    M[r1 * w + c] = m1 - f[r1] * pk;
+                    M[r2 * w + c] = m2 - f[r2] * pk;
+                    M[r3 * w + c] = m3 - f[r3] * pk;
+                }
+                for (; rr < n; rr += rows_per) M[rr * w + c] = M[rr * w + c] - f[rr] * pk;
+            }
         } else {
             for (int c = k + 1 + t; c < w; c += blockDim.x) {
                 double pk = M[k * w + c];
@@ -941,8 +956,12 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         if (l == 0)
             k_strength_slots<<<grid_for(n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->app.p, L.rp.p, t2,
                                                              L.sf.p);
+        else if ((double)L.nnz / n <= 12.0)
+            k_strength<4><<<grid_for((long long)n * 4), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, t2,
+                                                                        L.sf.p);
         else
-            k_strength<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, t2, L.sf.p);
+            k_strength<32><<<grid_for((long long)n * 32), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p,
+                                                                          t2, L.sf.p);
         // MIS-2
         DBuf<uint8_t> &state = W.state, &nw = W.nw, &d1 = W.d1;
         DBuf<uint64_t> &m1 = W.m1;

@@ -74,8 +74,9 @@ struct bo_cpr {
     // (tile, step, lane) order with the cell index of each slot and the
     // forward-sweep result in the same order
     bo::DBuf<double> einv;
-    bo::DBuf<double> ilu, ilu_w;
-    bo::DBuf<int32_t> ilu_cell;
+    bo::DBuf<double2> ilu_f, ilu_b;
+    bo::DBuf<double> ilu_w, ilu_r;
+    bo::DBuf<int32_t> ilu_cell, ilu_slot;
     bo::DBuf<float> einv32;
     bo::DBuf<uint16_t> einv16, A16;  // bf16 copies (mixed-bf16 form)
     bo::DBuf<float> A32;          // fp32 copy of A's off-diagonal slots for the ILU apply

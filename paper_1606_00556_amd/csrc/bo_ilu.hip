@@ -13,9 +13,9 @@
 // -z neighbours were handled one step earlier by lanes t-1, t-tile_x and t
 // itself; their values arrive through cross-lane shuffles (no LDS, no
 // barriers).  The factors are stored in the same (tile, step, lane) order,
-// field by field, so each step reads every field with one contiguous 512-byte
-// wavefront load, and the next step's fields are loaded before the current
-// step is computed.  Block Jacobi (x_i = A_ii^{-1} r_i) is the alternative F
+// packed in pairs, so each step reads its 36 doubles with 18 contiguous 1 KB
+// wavefront loads, and the fields of the next two steps are loaded before the
+// current step is computed.  Block Jacobi (x_i = A_ii^{-1} r_i) is the alternative F
 // stage.
 #include "bo_cpr.hpp"
 
@@ -27,8 +27,15 @@ struct TileGeom {
     __host__ __device__ long long slots() const { return (long long)ntx * nty * ns * 64; }
 };
 
-// fields of the (tile, step, lane) factor layout
-enum { F_EINV = 0, F_LZ = 9, F_LY = 18, F_LX = 27, F_UX = 36, F_UY = 45, F_UZ = 54, F_NUM = 63 };
+// The factors of one slot for one sweep are 36 doubles: E^{-1} and the three
+// lower blocks (-z, -y, -x) for the forward sweep, E^{-1} and the three upper
+// blocks (+x, +y, +z) for the backward sweep.  They are packed as 18 double2
+// per slot in (tile, step, pair, lane) order, so one wavefront load of a
+// pair reads 1 KB contiguously and a step needs 18 load instructions.
+constexpr int kPairs = 18;
+__device__ __forceinline__ size_t pk_index(int tile, int ns, int s, int pair, int lane) {
+    return (((size_t)tile * ns + s) * kPairs + pair) * 64 + lane;
+}
 
 __device__ __forceinline__ void load_blk(const double *__restrict__ A, int slot, size_t N, int g, double *o) {
     const double *p = A + (size_t)slot * 9 * N + g;
@@ -53,7 +60,8 @@ __device__ __forceinline__ void shfl_arr(const double *src, double *dst, int lan
 // grid) into the (tile, step, lane) layout, and the cell index of each slot
 // (-1 for idle slots).  E^{-1} by Gauss-Jordan with partial pivoting.
 __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__restrict__ A,
-                                                   double *__restrict__ F, int32_t *__restrict__ cell,
+                                                   double2 *__restrict__ Ff, double2 *__restrict__ Fb,
+                                                   int32_t *__restrict__ cell, int32_t *__restrict__ slot_of,
                                                    int32_t *__restrict__ bad) {
     int t = threadIdx.x;
     int a = t % T.tx, b = t / T.tx;
@@ -64,8 +72,6 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
     bool has_mx = a > 0, has_my = b > 0;
     bool has_px = a + 1 < T.tx && i + 1 < T.nx, has_py = b + 1 < T.ty && j + 1 < T.ny;
     size_t N = (size_t)T.nx * T.ny * T.nz;
-    size_t S = (size_t)T.slots();
-    int nxy = T.nx * T.ny;
     double Ep[9], Uxp[9], Uyp[9], Uzp[9];  // this lane's values from the previous step
     for (int z = 0; z < 9; z++) Ep[z] = Uxp[z] = Uyp[z] = Uzp[z] = 0.0;
     for (int s = 0; s < T.ns; s++) {
@@ -80,69 +86,83 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
         if (active && k >= 0 && k < T.nz) {
             int g = i + T.nx * (j + T.ny * k);
             double E[9], L[9], Lk[9], tmp[9];
+            double fw[36], bw[36];  // packed slot data: [E^{-1} | Lz Ly Lx] and [E^{-1} | Ux Uy Uz]
+            for (int z = 0; z < 36; z++) fw[z] = bw[z] = 0.0;
             load_blk(A, S_D, N, g, E);
             // -z, -y, -x in ascending order
             if (k > 0) {
                 load_blk(A, S_MZ, N, g, L);
                 mul3(L, Ep, Lk); mul3(Lk, Uzp, tmp);
                 for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
-                for (int z = 0; z < 9; z++) F[(size_t)(F_LZ + z) * S + q] = L[z];
+                for (int z = 0; z < 9; z++) fw[9 + z] = L[z];
             }
             if (has_my) {
                 load_blk(A, S_MY, N, g, L);
                 mul3(L, Ey, Lk); mul3(Lk, Uy, tmp);
                 for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
-                for (int z = 0; z < 9; z++) F[(size_t)(F_LY + z) * S + q] = L[z];
+                for (int z = 0; z < 9; z++) fw[18 + z] = L[z];
             }
             if (has_mx) {
                 load_blk(A, S_MX, N, g, L);
                 mul3(L, Ex, Lk); mul3(Lk, Ux, tmp);
                 for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
-                for (int z = 0; z < 9; z++) F[(size_t)(F_LX + z) * S + q] = L[z];
+                for (int z = 0; z < 9; z++) fw[27 + z] = L[z];
             }
             double Ei[9];
             if (!inv3_gj(E, Ei)) {
                 *bad = 1;
                 for (int z = 0; z < 9; z++) Ei[z] = 0.0;
             }
-            for (int z = 0; z < 9; z++) { F[(size_t)(F_EINV + z) * S + q] = Ei[z]; Ep[z] = Ei[z]; }
+            for (int z = 0; z < 9; z++) { fw[z] = Ei[z]; bw[z] = Ei[z]; Ep[z] = Ei[z]; }
             // upper blocks: this row's +x, +y, +z (zero outside the tile)
             if (has_px) load_blk(A, S_PX, N, g, Uxp); else for (int z = 0; z < 9; z++) Uxp[z] = 0.0;
             if (has_py) load_blk(A, S_PY, N, g, Uyp); else for (int z = 0; z < 9; z++) Uyp[z] = 0.0;
             if (k + 1 < T.nz) load_blk(A, S_PZ, N, g, Uzp); else for (int z = 0; z < 9; z++) Uzp[z] = 0.0;
-            for (int z = 0; z < 9; z++) {
-                F[(size_t)(F_UX + z) * S + q] = Uxp[z];
-                F[(size_t)(F_UY + z) * S + q] = Uyp[z];
-                F[(size_t)(F_UZ + z) * S + q] = Uzp[z];
+            for (int z = 0; z < 9; z++) { bw[9 + z] = Uxp[z]; bw[18 + z] = Uyp[z]; bw[27 + z] = Uzp[z]; }
+            for (int p2 = 0; p2 < kPairs; p2++) {
+                Ff[pk_index(tile, T.ns, s, p2, t)] = make_double2(fw[2 * p2], fw[2 * p2 + 1]);
+                Fb[pk_index(tile, T.ns, s, p2, t)] = make_double2(bw[2 * p2], bw[2 * p2 + 1]);
             }
             cell[q] = g;
-            (void)nxy;
+            slot_of[g] = (int32_t)q;
         } else {
             cell[q] = -1;
         }
     }
 }
 
-struct Fwd {
-    double e[9], lz[9], ly[9], lx[9];
+struct Pack {
+    double v[36];
+    double w[3];   // the sweep's vector operand at this slot
     int g;
 };
 
-__device__ __forceinline__ void load_fwd(const double *__restrict__ F, const int32_t *__restrict__ cell, size_t S,
-                                         size_t q, Fwd &f) {
-    f.g = cell[q];
+__device__ __forceinline__ void load_pack(const double2 *__restrict__ F, const int32_t *__restrict__ cell,
+                                          const double *__restrict__ vec, size_t S, int tile, int ns, int s, int t,
+                                          Pack &p) {
+    size_t q = ((size_t)tile * ns + s) * 64 + t;
+    p.g = cell[q];
 #pragma unroll
-    for (int z = 0; z < 9; z++) {
-        f.e[z] = F[(size_t)(F_EINV + z) * S + q];
-        f.lz[z] = F[(size_t)(F_LZ + z) * S + q];
-        f.ly[z] = F[(size_t)(F_LY + z) * S + q];
-        f.lx[z] = F[(size_t)(F_LX + z) * S + q];
+    for (int p2 = 0; p2 < kPairs; p2++) {
+        double2 d = F[pk_index(tile, ns, s, p2, t)];
+        p.v[2 * p2] = d.x;
+        p.v[2 * p2 + 1] = d.y;
     }
+    p.w[0] = vec[q]; p.w[1] = vec[S + q]; p.w[2] = vec[2 * S + q];
 }
 
-// forward sweep; w is stored in (tile, step, lane) order: wq[c * S + q]
-__global__ void __launch_bounds__(64) k_ilu_forward(TileGeom T, const double *__restrict__ F,
-                                                    const int32_t *__restrict__ cell, const double *__restrict__ r,
+// scatter a natural-order 3N vector into (tile, step, lane) order
+__global__ void k_to_slots(long long n, const int32_t *__restrict__ slot_of, size_t S, const double *__restrict__ r,
+                           double *__restrict__ rq) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    size_t q = (size_t)slot_of[g];
+    rq[q] = r[3 * g]; rq[S + q] = r[3 * g + 1]; rq[2 * S + q] = r[3 * g + 2];
+}
+
+// forward sweep: w = E^{-1}(r - L w_lower); r and w in (tile, step, lane) order
+__global__ void __launch_bounds__(64) k_ilu_forward(TileGeom T, const double2 *__restrict__ F,
+                                                    const int32_t *__restrict__ cell, const double *__restrict__ rq,
                                                     double *__restrict__ wq) {
     int t = threadIdx.x;
     int a = t % T.tx, b = t / T.tx;
@@ -150,25 +170,24 @@ __global__ void __launch_bounds__(64) k_ilu_forward(TileGeom T, const double *__
     size_t S = (size_t)T.slots();
     int lx = a > 0 ? t - 1 : t, ly = b > 0 ? t - T.tx : t;
     double wp[3] = {0.0, 0.0, 0.0};
-    // two steps of factors in flight ahead of the one being computed
-    Fwd cur, n1, n2;
-    load_fwd(F, cell, S, ((size_t)tile * T.ns) * 64 + t, n1);
-    if (T.ns > 1) load_fwd(F, cell, S, ((size_t)tile * T.ns + 1) * 64 + t, n2);
+    // two steps of operands in flight ahead of the one being computed
+    Pack cur, n1, n2;
+    load_pack(F, cell, rq, S, tile, T.ns, 0, t, n1);
+    if (T.ns > 1) load_pack(F, cell, rq, S, tile, T.ns, 1, t, n2);
     for (int s = 0; s < T.ns; s++) {
         cur = n1;
         n1 = n2;
-        if (s + 2 < T.ns) load_fwd(F, cell, S, ((size_t)tile * T.ns + s + 2) * 64 + t, n2);
+        if (s + 2 < T.ns) load_pack(F, cell, rq, S, tile, T.ns, s + 2, t, n2);
         double wy[3], wx[3];
         for (int c = 0; c < 3; c++) { wx[c] = __shfl(wp[c], lx, 64); wy[c] = __shfl(wp[c], ly, 64); }
         if (cur.g >= 0) {
-            size_t g = (size_t)cur.g;
-            double v[3] = {r[3 * g], r[3 * g + 1], r[3 * g + 2]};
+            double v[3] = {cur.w[0], cur.w[1], cur.w[2]};
             double y[3];
             // zero blocks stand for missing neighbours
-            mv3(cur.lz, wp, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
-            mv3(cur.ly, wy, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
-            mv3(cur.lx, wx, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
-            mv3(cur.e, v, wp);
+            mv3(cur.v + 9, wp, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
+            mv3(cur.v + 18, wy, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
+            mv3(cur.v + 27, wx, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
+            mv3(cur.v, v, wp);
             size_t q = ((size_t)tile * T.ns + s) * 64 + t;
             wq[q] = wp[0]; wq[S + q] = wp[1]; wq[2 * S + q] = wp[2];
         } else {
@@ -177,27 +196,9 @@ __global__ void __launch_bounds__(64) k_ilu_forward(TileGeom T, const double *__
     }
 }
 
-struct Bwd {
-    double e[9], ux[9], uy[9], uz[9], w[3];
-    int g;
-};
-
-__device__ __forceinline__ void load_bwd(const double *__restrict__ F, const int32_t *__restrict__ cell,
-                                         const double *__restrict__ wq, size_t S, size_t q, Bwd &f) {
-    f.g = cell[q];
-#pragma unroll
-    for (int z = 0; z < 9; z++) {
-        f.e[z] = F[(size_t)(F_EINV + z) * S + q];
-        f.ux[z] = F[(size_t)(F_UX + z) * S + q];
-        f.uy[z] = F[(size_t)(F_UY + z) * S + q];
-        f.uz[z] = F[(size_t)(F_UZ + z) * S + q];
-    }
-    f.w[0] = wq[q]; f.w[1] = wq[S + q]; f.w[2] = wq[2 * S + q];
-}
-
 // backward sweep: x_i = w_i - E_i^{-1} sum_{upper} A_ij x_j, written in
 // natural order as out = x + (dp, 0, 0) (dp may be NULL)
-__global__ void __launch_bounds__(64) k_ilu_backward(TileGeom T, const double *__restrict__ F,
+__global__ void __launch_bounds__(64) k_ilu_backward(TileGeom T, const double2 *__restrict__ F,
                                                      const int32_t *__restrict__ cell, const double *__restrict__ wq,
                                                      const double *__restrict__ dp, double *__restrict__ out) {
     int t = threadIdx.x;
@@ -207,22 +208,21 @@ __global__ void __launch_bounds__(64) k_ilu_backward(TileGeom T, const double *_
     int px = a + 1 < T.tx && t + 1 < 64 ? t + 1 : t;
     int py = b + 1 < T.ty && t + T.tx < 64 ? t + T.tx : t;
     double xp[3] = {0.0, 0.0, 0.0};
-    // the forward sweep must have finished this tile: wq is read ahead
-    Bwd cur, n1, n2;
-    load_bwd(F, cell, wq, S, ((size_t)tile * T.ns + T.ns - 1) * 64 + t, n1);
-    if (T.ns > 1) load_bwd(F, cell, wq, S, ((size_t)tile * T.ns + T.ns - 2) * 64 + t, n2);
+    Pack cur, n1, n2;
+    load_pack(F, cell, wq, S, tile, T.ns, T.ns - 1, t, n1);
+    if (T.ns > 1) load_pack(F, cell, wq, S, tile, T.ns, T.ns - 2, t, n2);
     for (int s = T.ns - 1; s >= 0; s--) {
         cur = n1;
         n1 = n2;
-        if (s >= 2) load_bwd(F, cell, wq, S, ((size_t)tile * T.ns + s - 2) * 64 + t, n2);
+        if (s >= 2) load_pack(F, cell, wq, S, tile, T.ns, s - 2, t, n2);
         double xx[3], xy[3];
         for (int c = 0; c < 3; c++) { xx[c] = __shfl(xp[c], px, 64); xy[c] = __shfl(xp[c], py, 64); }
         if (cur.g >= 0) {
             double acc[3], y[3];
-            mv3(cur.ux, xx, acc);
-            mv3(cur.uy, xy, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
-            mv3(cur.uz, xp, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
-            mv3(cur.e, acc, y);
+            mv3(cur.v + 9, xx, acc);
+            mv3(cur.v + 18, xy, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
+            mv3(cur.v + 27, xp, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
+            mv3(cur.v, acc, y);
             xp[0] = cur.w[0] - y[0]; xp[1] = cur.w[1] - y[1]; xp[2] = cur.w[2] - y[2];
             size_t g = (size_t)cur.g;
             out[3 * g] = dp ? dp[g] + xp[0] : xp[0];
@@ -282,11 +282,17 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
     } else {
         TileGeom T = geom(pc);
         size_t S = (size_t)T.slots();
-        BO_TRY(pc->ilu.alloc(S * F_NUM));
+        BO_TRY(pc->ilu_f.alloc(S * kPairs));
+        BO_TRY(pc->ilu_b.alloc(S * kPairs));
         BO_TRY(pc->ilu_cell.alloc(S));
+        BO_TRY(pc->ilu_slot.alloc(n));
         BO_TRY(pc->ilu_w.alloc(3 * S));
-        BO_HIP(hipMemsetAsync(pc->ilu.p, 0, sizeof(double) * S * F_NUM, s));
-        k_ilu_factor<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->A.p, pc->ilu.p, pc->ilu_cell.p, pc->flag.p);
+        BO_TRY(pc->ilu_r.alloc(3 * S));
+        // idle slots keep zero factors
+        BO_HIP(hipMemsetAsync(pc->ilu_f.p, 0, sizeof(double2) * S * kPairs, s));
+        BO_HIP(hipMemsetAsync(pc->ilu_b.p, 0, sizeof(double2) * S * kPairs, s));
+        k_ilu_factor<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
+                                                   pc->ilu_slot.p, pc->flag.p);
     }
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
@@ -296,19 +302,23 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
     return BO_OK;
 }
 
-// out = F(r) (+ Pi_p dp when dp != NULL)
-bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, double *wbuf, hipStream_t s) {
-    (void)wbuf;
+// out = F(r) (+ Pi_p dp when dp != NULL).  With r_in_slots the residual is
+// already in the F stage's slot order (pc->ilu_r, written by the caller).
+bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, bool r_in_slots, hipStream_t s) {
     long long n = pc->n;
     if (pc->o.ftype == BO_F_BJ) {
         k_bj_apply<<<grid_for(n), kBlock, 0, s>>>(n, pc->einv.p, r, dp, out);
     } else {
         TileGeom T = geom(pc);
-        k_ilu_forward<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->ilu.p, pc->ilu_cell.p, r, pc->ilu_w.p);
-        k_ilu_backward<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->ilu.p, pc->ilu_cell.p, pc->ilu_w.p, dp, out);
+        size_t S = (size_t)T.slots();
+        if (!r_in_slots) k_to_slots<<<grid_for(n), kBlock, 0, s>>>(n, pc->ilu_slot.p, S, r, pc->ilu_r.p);
+        k_ilu_forward<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->ilu_f.p, pc->ilu_cell.p, pc->ilu_r.p, pc->ilu_w.p);
+        k_ilu_backward<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->ilu_b.p, pc->ilu_cell.p, pc->ilu_w.p, dp, out);
     }
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
+
+size_t fstage_slots(const bo_cpr *pc) { return (size_t)geom(pc).slots(); }
 
 }  // namespace bo

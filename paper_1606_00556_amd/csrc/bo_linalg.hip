@@ -228,6 +228,39 @@ __global__ void __launch_bounds__(kBlock) k_slot_col0_residual(int nx, int ny, i
     r[3 * (size_t)i + 2] = v[3 * (size_t)i + 2] - s2;
 }
 
+// The same residual written in the F stage's slot order: component c of cell
+// i goes to out[c * S + slot_of[i]].
+__global__ void __launch_bounds__(kBlock) k_slot_col0_residual_perm(int nx, int ny, int nz,
+                                                                    const double *__restrict__ A,
+                                                                    const double *__restrict__ v,
+                                                                    const double *__restrict__ dp,
+                                                                    const int32_t *__restrict__ slot_of, size_t S,
+                                                                    double *__restrict__ out) {
+    int n = nx * ny * nz;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    size_t N = (size_t)n;
+    int nxy = nx * ny;
+    int ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
+                       ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int s = 0; s < NSLOT; s++) {
+        int j = nb[s];
+        if (j < 0) continue;
+        const double *a = A + (size_t)s * 9 * N + i;
+        double p = dp[j];
+        s0 = s0 + a[0 * N] * p;
+        s1 = s1 + a[3 * N] * p;
+        s2 = s2 + a[6 * N] * p;
+    }
+    size_t q = (size_t)slot_of[i];
+    out[q] = v[3 * (size_t)i] - s0;
+    out[S + q] = v[3 * (size_t)i + 1] - s1;
+    out[2 * S + q] = v[3 * (size_t)i + 2] - s2;
+}
+
 // ---- BLAS-1 -------------------------------------------------------------------
 __global__ void k_axpby(long long n, double a, const double *__restrict__ x, double b, double *__restrict__ y) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -277,10 +310,65 @@ __global__ void __launch_bounds__(kBlock) k_multidot_partial(long long n, const 
     }
 }
 
+// Classical Gram-Schmidt pass over the basis V (nv <= NV vectors), one read of
+// every vector per element:
+//   h == NULL:            partial sums of <w, V[q]>
+//   h != NULL, dots != 0: w -= sum_q h[q] V[q], then partial sums of <w, V[q]>
+//   h != NULL, dots == 0: w -= sum_q h[q] V[q], then the partial sum of <w, w>
+// The basis values of an element stay in registers between the update and
+// the dot products.
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_cgs_pass(long long n, double *__restrict__ w, VecList V, int nv,
+                                                     const double *__restrict__ h, int dots,
+                                                     double *__restrict__ partial) {
+    __shared__ double hs[NV];
+    __shared__ double sh[NV][kBlock / 64];
+    if (h && threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) acc[q] = 0.0;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        double we = w[e];
+        double vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) vq[q] = q < nv ? V.p[q][e] : 0.0;
+        if (h) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NV; q++)
+                if (q < nv) s = s + hs[q] * vq[q];
+            we = we - s;
+            w[e] = we;
+        }
+        if (dots || !h) {
+#pragma unroll
+            for (int q = 0; q < NV; q++) acc[q] = acc[q] + we * vq[q];
+        } else {
+            acc[0] = acc[0] + we * we;
+        }
+    }
+    int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    int nout = (dots || !h) ? nv : 1;
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        double t = wave_sum(acc[q]);
+        if (lane == 0) sh[q][wave] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < nout) {
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < kBlock / 64; u++) t = t + sh[threadIdx.x][u];
+        partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
 // pass 2 (one workgroup): out[q] = sum over the partials in a fixed order
 __global__ void __launch_bounds__(kBlock) k_partial_final(int nblocks, int nv, const double *__restrict__ partial,
                                                           double *__restrict__ out) {
-    __shared__ double sh[16][kBlock / 64];
+    __shared__ double sh[kMaxVecList][kBlock / 64];
     int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     for (int q = 0; q < nv; q++) {
         double s = 0.0;
@@ -334,6 +422,14 @@ bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, co
     return BO_OK;
 }
 
+bo_status slot_col0_residual_perm(const Grid &g, const double *A, const double *v, const double *dp,
+                                  const int32_t *slot_of, size_t S, double *out, hipStream_t s) {
+    long long n = g.n();
+    k_slot_col0_residual_perm<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, v, dp, slot_of, S, out);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s) {
     long long n = g.n();
@@ -379,7 +475,26 @@ bo_status scale_copy(long long n, const double *inv, const double *x, double *y,
 }
 
 bo_status Reducer::init() {
-    BO_TRY(partial.alloc((size_t)kRedBlocks * 16));
+    BO_TRY(partial.alloc((size_t)kRedBlocks * kMaxVecList));
+    return BO_OK;
+}
+
+bo_status Reducer::cgs_pass(long long n, double *w, const double *const *Vhost, int nv, const double *h, bool dots,
+                            double *out, hipStream_t s) {
+    if (nv < 1 || nv > kMaxVecList) return fail(BO_ERR_INVALID_ARG, "cgs_pass: 1..64 vectors");
+    VecList L{};
+    for (int q = 0; q < nv; q++) L.p[q] = Vhost[q];
+    if (nv <= 8)
+        k_cgs_pass<8><<<kRedBlocks, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
+    else if (nv <= 16)
+        k_cgs_pass<16><<<kRedBlocks, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
+    else if (nv <= 32)
+        k_cgs_pass<32><<<kRedBlocks, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
+    else
+        k_cgs_pass<64><<<kRedBlocks, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
+    int nout = (dots || !h) ? nv : 1;
+    k_partial_final<<<1, kBlock, 0, s>>>(kRedBlocks, nout, partial.p, out);
+    BO_HIP(hipGetLastError());
     return BO_OK;
 }
 

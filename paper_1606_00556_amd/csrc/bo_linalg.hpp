@@ -8,6 +8,8 @@ bo_status slot_spmv(const Grid &g, const double *A, double alpha, const double *
                     hipStream_t s);
 bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, const double *dp, double *r,
                              hipStream_t s);
+bo_status slot_col0_residual_perm(const Grid &g, const double *A, const double *v, const double *dp,
+                                  const int32_t *slot_of, size_t S, double *out, hipStream_t s);
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s);
 bo_status axpby(long long n, double a, const double *x, double b, double *y, hipStream_t s);
@@ -33,6 +35,9 @@ struct Reducer {
     bo_status multidot(long long n, const double *x, const double *const *Vhost, int nv, double *out,
                        hipStream_t s);
     bo_status dot(long long n, const double *x, const double *y, double *out, hipStream_t s);
+    // one classical Gram-Schmidt pass (see k_cgs_pass); results land in out
+    bo_status cgs_pass(long long n, double *w, const double *const *Vhost, int nv, const double *h, bool dots,
+                       double *out, hipStream_t s);
 };
 
 }  // namespace bo

@@ -26,7 +26,8 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s);
 bo_status amg_vcycle(bo_cpr *pc, const double *b, double *x, hipStream_t s);
 bo_status amg_vcycle_ptr(bo_cpr *pc, const double *b, const double **res, hipStream_t s);
 bo_status fstage_setup(bo_cpr *pc, hipStream_t s);
-bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, double *wbuf, hipStream_t s);
+bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, bool r_in_slots, hipStream_t s);
+size_t fstage_slots(const bo_cpr *pc);
 
 namespace {
 
@@ -50,13 +51,18 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
             const double *dp;
             BO_TRY(qi_restrict(pc, v, pc->rp_.p, s));
             BO_TRY(amg_vcycle_ptr(pc, pc->rp_.p, &dp, s));
+            if (pc->o.ftype == BO_F_ILU_TILED) {
+                // the residual goes straight into the F stage's slot order
+                BO_TRY(slot_col0_residual_perm(g, pc->A.p, v, dp, pc->ilu_slot.p, fstage_slots(pc), pc->ilu_r.p, s));
+                return fstage_apply(pc, nullptr, dp, z, true, s);
+            }
             BO_TRY(slot_col0_residual(g, pc->A.p, v, dp, pc->t3a.p, s));
-            return fstage_apply(pc, pc->t3a.p, dp, z, pc->wf.p, s);
+            return fstage_apply(pc, pc->t3a.p, dp, z, false, s);
         }
-        return fstage_apply(pc, v, nullptr, z, pc->wf.p, s);
+        return fstage_apply(pc, v, nullptr, z, false, s);
     }
     // FPF
-    BO_TRY(fstage_apply(pc, v, nullptr, z, pc->wf.p, s));
+    BO_TRY(fstage_apply(pc, v, nullptr, z, false, s));
     if (pc->o.use_amg) {
         BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
         BO_TRY(slot_spmv(g, pc->A.p, -1.0, z, 1.0, pc->t3a.p, s));
@@ -68,7 +74,7 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     }
     BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
     BO_TRY(slot_spmv(g, pc->A.p, -1.0, z, 1.0, pc->t3a.p, s));
-    BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, pc->t3b.p, pc->wf.p, s));
+    BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, pc->t3b.p, false, s));
     return axpby(3 * n, 1.0, pc->t3b.p, 1.0, z, s);
 }
 
@@ -214,7 +220,7 @@ extern "C" bo_status bo_cpr_vcycle(bo_cpr *pc, const double *b, double *x, void 
 
 extern "C" bo_status bo_cpr_fstage(bo_cpr *pc, const double *r, double *x, void *stream) {
     if (!pc || !r || !x) return fail(BO_ERR_INVALID_ARG, "bo_cpr_fstage: NULL argument");
-    return fstage_apply(pc, r, nullptr, x, pc->wf.p, (hipStream_t)stream);
+    return fstage_apply(pc, r, nullptr, x, false, (hipStream_t)stream);
 }
 
 extern "C" bo_status bo_cpr_levels(bo_cpr *pc, int32_t *nlevels) {
@@ -352,17 +358,17 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
             BO_TRY(slot_spmv(g, pc->A.p, 1.0, zj, 0.0, w, s));
             int nv = j + 1;
             if (opts->orth == 1) {
-                BO_TRY(pc->red.multidot(len, w, K.vptr.data(), nv, hd, s));
-                BO_TRY(multiaxpy(len, K.vptr.data(), nv, hd, -1.0, w, s));
-                BO_TRY(pc->red.multidot(len, w, K.vptr.data(), nv, hd + (m + 1), s));
-                BO_TRY(multiaxpy(len, K.vptr.data(), nv, hd + (m + 1), -1.0, w, s));
+                // h1 = V^T w; w -= V h1 with h2 = V^T w; w -= V h2 with |w|^2
+                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, nullptr, true, hd, s));
+                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, hd, true, hd + (m + 1), s));
+                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, hd + (m + 1), false, hd + 2 * (m + 1), s));
             } else {
                 for (int i = 0; i < nv; i++) {
                     BO_TRY(pc->red.multidot(len, w, K.vptr.data() + i, 1, hd + i, s));
                     BO_TRY(multiaxpy(len, K.vptr.data() + i, 1, hd + i, -1.0, w, s));
                 }
+                BO_TRY(pc->red.dot(len, w, w, hd + 2 * (m + 1), s));
             }
-            BO_TRY(pc->red.dot(len, w, w, hd + 2 * (m + 1), s));
             BO_TRY(fetch(2 * (m + 1) + 1));
             double hn = std::sqrt(hh[2 * (m + 1)]);
             for (int i = 0; i <= j; i++)
