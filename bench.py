@@ -1,19 +1,23 @@
 """Benchmark: CPR-FGMRES time-to-solution on fully implicit black-oil Jacobians.
 
 One step = the whole hot path for one Newton system of the workload: Jacobian
-and right-hand side assembly (bo_jacobian_bsr), CPR setup (bo_cpr_setup) and
-the FGMRES(30) solve to a true relative residual of 1e-6 (bo_fgmres_solve).
+and right-hand side assembly (bo_jacobian_bsr), CPR setup for that Jacobian
+(bo_cpr_update: decoupling, AMG hierarchy and ILU factors rebuilt in the
+handle's memory) and the FGMRES(30) solve to a true relative residual of 1e-6
+(bo_fgmres_solve).
 Steps cycle through the 10 systems of the synthetic step sequence; all inputs
 are resident in HBM before timing starts.
 
 Prints one JSON line with the time per system (`value`, seconds), the SpMV
-roofline figure (its average launch duration measured with HIP events on the
-library's stream) and the CPU oracle timed on a bounded sample.
+roofline figure (the solver's SpMV launches in the timed steps, timed with HIP
+events on the library's stream) and the CPU oracle timed on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -30,6 +34,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2))
+    ap.add_argument("--spmv-isolated", action="store_true",
+                    help="also time isolated SpMV launches (after a cache-evicting pass, and back to back)")
     ap.add_argument("--spmv-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
@@ -70,6 +76,7 @@ def main():
     grid = (c0.nx, c0.ny, c0.nz)
     copts = B.bo_cpr_default_opts()
     fopts = B.bo_fgmres_default_opts()
+    fopts_timed = B.bo_fgmres_default_opts(timing=1)
     torch.cuda.synchronize()
 
     # the preconditioner handle lives across systems, as in a Newton loop:
@@ -88,7 +95,7 @@ def main():
         B.bo_cpr_update(pc, J)
         if e: e[2].record(stream)
         x.zero_()
-        info = B.bo_fgmres_solve(pc, b, x, fopts)
+        info = B.bo_fgmres_solve(pc, b, x, fopts if record is None else fopts_timed)
         if e: e[3].record(stream)
         if not info["converged"]:
             raise RuntimeError(f"system {i} did not converge: {info}")
@@ -115,46 +122,26 @@ def main():
               f"solve {solve_ms:.2f} ms, iterations {its}")
 
     # SpMV roofline: algorithmic bytes = 72 B per stored block (3x3 FP64) +
-    # 24 B x read + 24 B y written per block row.  Each timed launch follows a
-    # 1 GiB read-only pass (clean lines, nothing to write back), so that neither
-    # the L2 nor the 256 MB Infinity Cache holds the matrix: every launch pays
-    # the HBM traffic the algorithmic count assumes, as the solver's own SpMVs
-    # do between other kernels.  The back-to-back (warm) figure is reported
-    # beside it.
-    xin = torch.randn(3 * n, dtype=torch.float64, device=dev)
-    yout = torch.empty_like(xin)
-    flush = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-    for _ in range(3):
-        B.bo_cpr_spmv(pc, 1.0, xin, 0.0, yout)
-    cold = []
-    sink = torch.zeros(1, dtype=torch.float64, device=dev)
-    for _ in range(args.spmv_reps):
-        torch.sum(flush, dim=0, keepdim=True, out=sink)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        B.bo_cpr_spmv(pc, 1.0, xin, 0.0, yout)
-        e1.record(stream)
-        cold.append((e0, e1))
-    torch.cuda.synchronize()
-    spmv_us = 1000.0 * sum(a.elapsed_time(b_) for a, b_ in cold) / len(cold)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record(stream)
-    for _ in range(args.spmv_reps):
-        B.bo_cpr_spmv(pc, 1.0, xin, 0.0, yout)
-    ev[1].record(stream)
-    torch.cuda.synchronize()
-    warm_us = 1000.0 * ev[0].elapsed_time(ev[1]) / args.spmv_reps
+    # 24 B x read + 24 B y written per block row, divided by the average
+    # duration of the solver's own Arnoldi SpMVs over the timed steps (HIP
+    # events recorded by the library on this stream around each launch).
+    spmv_calls = sum(inf["spmv_calls"] for _, inf in rec)
+    spmv_us = 1000.0 * sum(inf["spmv_ms"] for _, inf in rec) / max(spmv_calls, 1)
     spmv_bytes = 72.0 * nnzb + 48.0 * n
     spmv_gbs = spmv_bytes / (spmv_us * 1e-6) / 1e9
+    spmv = {"us": spmv_us, "GBs": spmv_gbs, "bytes": spmv_bytes, "launches": spmv_calls}
+    if args.spmv_isolated:
+        spmv.update(isolated_spmv(args, B, pc, n, dev, stream))
     # plain copy of known size: calibrates the HBM byte counters of a profile
     # taken of this run (FETCH_SIZE / WRITE_SIZE of this copy vs 256 MiB)
-    cal = torch.empty(1 << 25, dtype=torch.float64, device=dev)
-    cal.copy_(flush[: 1 << 25])
+    src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+    cal = torch.empty_like(src)
+    cal.copy_(src)
     torch.cuda.synchronize()
-    del flush, cal
+    del src, cal
     pc.close()
-    log(args, f"[bench] SpMV cold {spmv_us:.1f} us = {spmv_gbs:.0f} GB/s algorithmic ({spmv_bytes / 1e6:.1f} MB); "
-              f"back-to-back {warm_us:.1f} us")
+    log(args, f"[bench] SpMV in the solver: {spmv_us:.1f} us avg over {spmv_calls} launches = "
+              f"{spmv_gbs:.0f} GB/s algorithmic ({spmv_bytes / 1e6:.1f} MB)")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -183,12 +170,73 @@ def main():
         },
         "breakdown_ms": {"assembly": asm_ms, "setup": setup_ms, "solve": solve_ms},
         "iterations": its,
-        "spmv": {"us": spmv_us, "GBs": spmv_gbs, "bytes": spmv_bytes, "back_to_back_us": warm_us},
+        "spmv": spmv,
         "roofline": {"bound": "hbm", "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_slot_spmv"},
+                     "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": spmv_traffic() if wl == 1 else None,
+                     "traffic_unit": "B per launch", "kernel": "k_slot_spmv"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "slot_spmv_cfg1_500k_hbm_traffic.md")
+
+
+def spmv_source_hash():
+    """sha256 over the text of k_slot_spmv and its launcher."""
+    src = open(os.path.join(ROOT, "paper_1606_00556_amd", "csrc", "bo_linalg.hip")).read()
+    k0 = src.rindex("__global__", 0, src.index("k_slot_spmv(int nx"))
+    k1 = src.index("\n}\n", k0) + 3
+    w0 = src.index("bo_status slot_spmv(")
+    w1 = src.index("\n}\n", w0) + 3
+    return hashlib.sha256((src[k0:k1] + src[w0:w1]).encode()).hexdigest()
+
+
+def spmv_traffic():
+    """HBM bytes per SpMV launch from the committed counter summary (rocprofv3
+    FETCH_SIZE / WRITE_SIZE scaled by a 256 MiB copy), or None once the kernel
+    source differs from the one the counters were taken of."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m_t = re.search(r"traffic per launch \(bytes\): (\d+)", text)
+    m_h = re.search(r"kernel source sha256: ([0-9a-f]{64})", text)
+    if not (m_t and m_h) or m_h.group(1) != spmv_source_hash():
+        return None
+    return float(m_t.group(1))
+
+
+def isolated_spmv(args, B, pc, n, dev, stream):
+    """SpMV launches outside the solver: each after a 1 GiB read-only pass
+    (clean lines, nothing to write back) that evicts L2 and the 256 MB
+    Infinity Cache, and back to back (matrix partly cache-resident)."""
+    import torch
+    xin = torch.randn(3 * n, dtype=torch.float64, device=dev)
+    yout = torch.empty_like(xin)
+    flush = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        B.bo_cpr_spmv(pc, 1.0, xin, 0.0, yout)
+    cold = []
+    for _ in range(args.spmv_reps):
+        torch.sum(flush, dim=0, keepdim=True, out=sink)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.bo_cpr_spmv(pc, 1.0, xin, 0.0, yout)
+        e1.record(stream)
+        cold.append((e0, e1))
+    torch.cuda.synchronize()
+    cold_us = 1000.0 * sum(a.elapsed_time(b_) for a, b_ in cold) / len(cold)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(args.spmv_reps):
+        B.bo_cpr_spmv(pc, 1.0, xin, 0.0, yout)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    warm_us = 1000.0 * ev[0].elapsed_time(ev[1]) / args.spmv_reps
+    log(args, f"[bench] isolated SpMV: after eviction {cold_us:.1f} us, back to back {warm_us:.1f} us")
+    return {"isolated_cold_us": cold_us, "isolated_back_to_back_us": warm_us}
 
 
 def cpu_baseline(args, case):

@@ -195,9 +195,11 @@ typedef struct {
     int32_t maxit;      /* preconditioner applications allowed */
     double rtol;        /* stop when ||b - A x|| <= rtol ||b|| (true residual) */
     int32_t orth;       /* 0: modified Gram-Schmidt, 1: classical GS twice */
+    int32_t timing;     /* 1: time every Arnoldi SpMV with HIP events on the
+                           solve's stream (stats.spmv_ms / spmv_calls) */
 } bo_fgmres_opts;
 
-void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, CGS2 */
+void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, CGS2, no timing */
 
 typedef struct {
     int32_t iterations;     /* preconditioner applications */
@@ -205,6 +207,8 @@ typedef struct {
     int32_t converged;
     double rel_residual;    /* true ||b - A x|| / ||b|| at exit */
     double est_residual;    /* last Arnoldi estimate |g_{j+1}| / ||b|| */
+    double spmv_ms;         /* with opts.timing: summed duration of the timed SpMVs */
+    int32_t spmv_calls;     /* with opts.timing: their number (one per iteration) */
 } bo_solve_stats;
 
 /* Right-preconditioned FGMRES(m) on A x = b with the operator and

@@ -76,12 +76,14 @@ class BoGrid(C.Structure):
 
 
 class BoFgmresOpts(C.Structure):
-    _fields_ = [("m", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("orth", C.c_int32)]
+    _fields_ = [("m", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("orth", C.c_int32),
+                ("timing", C.c_int32)]
 
 
 class BoSolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
-                ("rel_residual", C.c_double), ("est_residual", C.c_double)]
+                ("rel_residual", C.c_double), ("est_residual", C.c_double), ("spmv_ms", C.c_double),
+                ("spmv_calls", C.c_int32)]
 
 
 _lib = None
@@ -350,4 +352,5 @@ def bo_fgmres_solve(pc: Cpr, b, x, opts: Optional[BoFgmresOpts] = None, stream=N
     rc = lib().bo_fgmres_solve(pc.h, _ptr(b), _ptr(x), C.byref(o), C.byref(st), _stream(stream))
     _check(rc, allowed=(BO_OK, BO_NOT_CONVERGED))
     return dict(status=rc, iterations=st.iterations, restarts=st.restarts, converged=bool(st.converged),
-                rel_residual=st.rel_residual, est_residual=st.est_residual)
+                rel_residual=st.rel_residual, est_residual=st.est_residual, spmv_ms=st.spmv_ms,
+                spmv_calls=st.spmv_calls)

@@ -86,4 +86,5 @@ struct bo_cpr {
     bo::SetupWork sw;
     bo::Reducer red;
     bo::Krylov kr;
+    hipEvent_t ev[2] = {nullptr, nullptr};  // SpMV timing in bo_fgmres_solve
 };

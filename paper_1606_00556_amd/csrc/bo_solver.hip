@@ -104,6 +104,7 @@ extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
     o->maxit = 1500;
     o->rtol = 1e-6;
     o->orth = 1;
+    o->timing = 0;
 }
 
 static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc,
@@ -193,6 +194,8 @@ extern "C" bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream) {
 extern "C" void bo_cpr_destroy(bo_cpr *pc) {
     if (!pc) return;
     (void)hipDeviceSynchronize();
+    for (hipEvent_t &e : pc->ev)
+        if (e) (void)hipEventDestroy(e);
     delete pc;
 }
 
@@ -299,10 +302,15 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     if (!pc || !b || !x || !opts) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: NULL argument");
     if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: the last bo_cpr_update failed");
     int m = opts->m;
-    if (m < 1 || m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || (opts->orth != 0 && opts->orth != 1))
+    if (m < 1 || m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || (opts->orth != 0 && opts->orth != 1) ||
+        (opts->timing != 0 && opts->timing != 1))
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
     hipStream_t s = (hipStream_t)stream;
     bo_solve_stats st{};
+    const bool timed = opts->timing == 1;
+    if (timed)
+        for (hipEvent_t &e : pc->ev)
+            if (!e) BO_HIP(hipEventCreate(&e));
     BO_TRY(krylov_alloc(pc, m));
     Krylov &K = pc->kr;
     const long long len = K.len;
@@ -355,7 +363,9 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
             double *vj = V + (size_t)j * len, *zj = Z + (size_t)j * len, *w = V + (size_t)(j + 1) * len;
             BO_TRY(cpr_apply(pc, vj, zj, s));
             its++;
+            if (timed) BO_HIP(hipEventRecord(pc->ev[0], s));
             BO_TRY(slot_spmv(g, pc->A.p, 1.0, zj, 0.0, w, s));
+            if (timed) BO_HIP(hipEventRecord(pc->ev[1], s));
             int nv = j + 1;
             if (opts->orth == 1) {
                 // h1 = V^T w; w -= V h1 with h2 = V^T w; w -= V h2 with |w|^2
@@ -370,6 +380,12 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
                 BO_TRY(pc->red.dot(len, w, w, hd + 2 * (m + 1), s));
             }
             BO_TRY(fetch(2 * (m + 1) + 1));
+            if (timed) {  // the fetch synchronised the stream: both events are complete
+                float ms = 0.f;
+                BO_HIP(hipEventElapsedTime(&ms, pc->ev[0], pc->ev[1]));
+                st.spmv_ms += ms;
+                st.spmv_calls++;
+            }
             double hn = std::sqrt(hh[2 * (m + 1)]);
             for (int i = 0; i <= j; i++)
                 H[(size_t)i * m + j] = opts->orth == 1 ? hh[i] + hh[m + 1 + i] : hh[i];

@@ -234,6 +234,22 @@ def test_fgmres_deterministic(B, O):
     assert np.array_equal(xs[0], xs[1])
 
 
+def test_fgmres_timing_option_keeps_result(B, O):
+    """Timing records events around the SpMVs only: same iterates, one timed
+    SpMV per iteration, a positive total."""
+    import torch
+    case = ragged_case()
+    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
+    xs, infos = [], []
+    for t in (0, 1):
+        x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(timing=t)))
+        xs.append(to_host(x))
+    assert np.array_equal(xs[0], xs[1])
+    assert infos[0]["spmv_calls"] == 0 and infos[0]["spmv_ms"] == 0.0
+    assert infos[1]["spmv_calls"] == infos[1]["iterations"] and infos[1]["spmv_ms"] > 0.0
+
+
 def test_fgmres_small_restart_and_maxit(B, O):
     import torch
     case = ragged_case()
