@@ -113,7 +113,20 @@ typedef struct {
     int sweeps;           /* pre = post sweeps */
     int use_amg;          /* 0: pressure stage skipped (F only) */
     int qi_mode;          /* OR_QI_DIAG or OR_QI_BLOCK */
+    int precision;        /* OR_PREC_*: mixed-precision emulation of the inner stages */
 } or_cpr_opts;
+
+/* Mixed precision (emulated): OR_PREC_FP32 stores the AMG hierarchy and the F
+ * stage's factors rounded to FP32 and runs the V-cycle and the F-stage sweeps
+ * in float arithmetic; OR_PREC_FP32_BF16 stores the F stage's factors in BF16
+ * (round to nearest even from the FP32 value).  Decoupling, restriction,
+ * residuals and the final sums stay FP64; values enter the FP32 stages by
+ * rounding and leave them exactly.  The tiled / natural / red-black F stages
+ * use the diagonal form of block ILU(0) (valid on the 7-point pattern, whose
+ * graph has no triangles), storing E^{-1} and the blocks of A. */
+enum { OR_PREC_FP64 = 0, OR_PREC_FP32 = 1, OR_PREC_FP32_BF16 = 2 };
+/* FP32 -> BF16 (8 significant bits), round to nearest even */
+float or_bf16_round(float f);
 
 typedef struct or_cpr or_cpr;
 

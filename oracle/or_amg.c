@@ -280,6 +280,8 @@ void or_amg_free(or_amg *h)
         or_csr_free(&h->A[l]); or_csr_free(&h->P[l]); or_csr_free(&h->R[l]);
         free(h->agg[l]); free(h->sf[l]); free(h->color[l]); free(h->root[l]);
     }
+    for (int l = 0; l < OR_MAXLEV; l++) { free(h->A32[l]); free(h->P32[l]); free(h->R32[l]); }
+    free(h->cinv32);
     free(h->dense);
     memset(h, 0, sizeof *h);
 }
@@ -445,4 +447,128 @@ static void vcycle(const or_amg *h, int l, const double *b, double *x)
 void or_amg_vcycle(const or_amg *h, const double *b, double *x)
 {
     vcycle(h, 0, b, x);
+}
+
+/* ---- mixed-precision emulation ------------------------------------------
+ * The hierarchy built above (FP64) is stored rounded to FP32 (C's double to
+ * float conversion rounds to nearest even); the cycle then runs the same
+ * steps as vcycle() with float arithmetic and float vectors.  The coarsest
+ * level is solved with the FP32-rounded inverse of the FP64 coarsest matrix
+ * (columns of the inverse by dense LU), applied as a float product. */
+
+static float *round_f32(const double *a, size_t n)
+{
+    float *b = malloc(sizeof(float) * (n ? n : 1));
+    for (size_t i = 0; i < n; i++) b[i] = (float)a[i];
+    return b;
+}
+
+int or_amg_make_f32(or_amg *h)
+{
+    for (int l = 0; l < h->nlev; l++) {
+        h->A32[l] = round_f32(h->A[l].v, (size_t)h->A[l].nnz);
+        if (l < h->nlev - 1) {
+            h->P32[l] = round_f32(h->P[l].v, (size_t)h->P[l].nnz);
+            h->R32[l] = round_f32(h->R[l].v, (size_t)h->R[l].nnz);
+        }
+    }
+    const or_csr *C = &h->A[h->nlev - 1];
+    int n = C->n;
+    double *M = malloc(sizeof(double) * (size_t)n * n), *col = malloc(sizeof(double) * (size_t)n);
+    h->cinv32 = malloc(sizeof(float) * (size_t)n * n);
+    for (int j = 0; j < n; j++) {
+        memset(M, 0, sizeof(double) * (size_t)n * n);
+        for (int i = 0; i < n; i++)
+            for (int e = C->rp[i]; e < C->rp[i + 1]; e++) M[(size_t)i * n + C->ci[e]] = C->v[e];
+        memset(col, 0, sizeof(double) * (size_t)n);
+        col[j] = 1.0;
+        if (or_dense_solve(n, M, col)) { free(M); free(col); return OR_ERR_SINGULAR_COARSE; }
+        for (int i = 0; i < n; i++) h->cinv32[(size_t)i * n + j] = (float)col[i];
+    }
+    free(M); free(col);
+    return OR_OK;
+}
+
+static void gs_colour_f32(const or_csr *A, const float *v, const int32_t *color, int c, const float *b, float *x)
+{
+    for (int i = 0; i < A->n; i++) {
+        if (color[i] != c) continue;
+        float s = b[i], d = 0.0f;
+        for (int e = A->rp[i]; e < A->rp[i + 1]; e++) {
+            int j = A->ci[e];
+            if (j == i) d = v[e];
+            else s -= v[e] * x[j];
+        }
+        x[i] = s / d;
+    }
+}
+
+static void smooth_f32(const or_amg *h, int l, const float *b, float *x, int forward)
+{
+    const or_csr *A = &h->A[l];
+    const float *v = h->A32[l];
+    int n = A->n;
+    int kind = l == 0 ? h->smoother : OR_SMOOTH_JACOBI;
+    const float w = (float)(2.0 / 3.0);
+    for (int sw = 0; sw < h->sweeps; sw++) {
+        if (kind == OR_SMOOTH_JACOBI) {
+            float *t = malloc(sizeof(float) * (size_t)n);
+            for (int i = 0; i < n; i++) {
+                float s = 0.0f, d = 0.0f;
+                for (int e = A->rp[i]; e < A->rp[i + 1]; e++) {
+                    s += v[e] * x[A->ci[e]];
+                    if (A->ci[e] == i) d = v[e];
+                }
+                t[i] = x[i] + w * ((b[i] - s) / d);
+            }
+            memcpy(x, t, sizeof(float) * (size_t)n);
+            free(t);
+        } else if (forward) {
+            for (int c = 0; c < h->ncolor[l]; c++) gs_colour_f32(A, v, h->color[l], c, b, x);
+        } else {
+            for (int c = h->ncolor[l] - 1; c >= 0; c--) gs_colour_f32(A, v, h->color[l], c, b, x);
+        }
+    }
+}
+
+static void csr_mv_f32(const or_csr *A, const float *v, const float *x, float *y)
+{
+    for (int i = 0; i < A->n; i++) {
+        float s = 0.0f;
+        for (int e = A->rp[i]; e < A->rp[i + 1]; e++) s += v[e] * x[A->ci[e]];
+        y[i] = s;
+    }
+}
+
+static void vcycle_f32(const or_amg *h, int l, const float *b, float *x)
+{
+    const or_csr *A = &h->A[l];
+    int n = A->n;
+    if (l == h->nlev - 1) {
+        for (int i = 0; i < n; i++) {
+            float s = 0.0f;
+            for (int j = 0; j < n; j++) s += h->cinv32[(size_t)i * n + j] * b[j];
+            x[i] = s;
+        }
+        return;
+    }
+    memset(x, 0, sizeof(float) * (size_t)n);
+    smooth_f32(h, l, b, x, 1);
+    float *r = malloc(sizeof(float) * (size_t)n);
+    csr_mv_f32(A, h->A32[l], x, r);
+    for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
+    int nc = h->A[l + 1].n;
+    float *bc = malloc(sizeof(float) * (size_t)nc), *xc = malloc(sizeof(float) * (size_t)nc);
+    csr_mv_f32(&h->R[l], h->R32[l], r, bc);
+    vcycle_f32(h, l + 1, bc, xc);
+    float *px = malloc(sizeof(float) * (size_t)n);
+    csr_mv_f32(&h->P[l], h->P32[l], xc, px);
+    for (int i = 0; i < n; i++) x[i] = x[i] + px[i];
+    smooth_f32(h, l, b, x, 0);
+    free(r); free(bc); free(xc); free(px);
+}
+
+void or_amg_vcycle_f32(const or_amg *h, const float *b, float *x)
+{
+    vcycle_f32(h, 0, b, x);
 }

@@ -42,7 +42,99 @@ struct or_cpr {
     int32_t *rank, *order;       /* ILU ordering */
     uint8_t *drop;               /* per entry: coupling dropped by tiling */
     int32_t *diag;               /* entry index of the diagonal block per row */
+    /* mixed-precision emulation */
+    float *inv32;                /* N*9: rounded pivots (ILU) or diagonal inverses (BJ) */
+    float *A32;                  /* nnzb*9: rounded blocks of A (ILU, dropped ones zero) */
 };
+
+float or_bf16_round(float f)
+{
+    if (f == 0.0f || !isfinite(f)) return f;
+    int e;
+    float fr = frexpf(f, &e);                     /* f = fr 2^e, 0.5 <= |fr| < 1 */
+    return ldexpf(rintf(ldexpf(fr, 8)), e - 8);   /* 8 significant bits, ties to even */
+}
+
+static float store_round(const or_cpr *c, double v, int bf16_ok)
+{
+    float f = (float)v;
+    return (bf16_ok && c->o.precision == OR_PREC_FP32_BF16) ? or_bf16_round(f) : f;
+}
+
+/* rounded copies of the F stage's factors (and of the AMG hierarchy) */
+static int mixed_setup(or_cpr *c)
+{
+    int n = c->n, nnzb = c->rp[n];
+    c->inv32 = malloc(sizeof(float) * 9 * (size_t)n);
+    for (size_t e = 0; e < 9 * (size_t)n; e++) c->inv32[e] = store_round(c, c->inv[e], 1);
+    if (c->o.ftype != OR_F_BJ) {
+        c->A32 = malloc(sizeof(float) * 9 * (size_t)(nnzb > 0 ? nnzb : 1));
+        for (int e = 0; e < nnzb; e++)
+            for (int z = 0; z < 9; z++)
+                c->A32[9 * (size_t)e + z] = c->drop[e] ? 0.0f : store_round(c, c->Aval[9 * (size_t)e + z], 1);
+    }
+    if (c->has_amg) {
+        if (!c->amg.coarse_direct) return OR_ERR_ARG;
+        return or_amg_make_f32(&c->amg);
+    }
+    return OR_OK;
+}
+
+static void mv3f(const float *A, const float *x, float *y)
+{
+    y[0] = A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
+    y[1] = A[3] * x[0] + A[4] * x[1] + A[5] * x[2];
+    y[2] = A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
+}
+
+/* F stage in float: x = F(r).  Block Jacobi: x_i = E_i^{-1} r_i.  Block
+ * ILU(0) in its diagonal form: w_i = E_i^{-1}(r_i - sum_{k in L(i)} A_ik w_k)
+ * in order, then x_i = w_i - E_i^{-1} sum_{j in U(i)} A_ij x_j in reverse
+ * order, neighbours in ascending column order. */
+static void fstage_f32(const or_cpr *c, const float *r, float *x)
+{
+    int n = c->n;
+    if (c->o.ftype == OR_F_BJ) {
+        for (int i = 0; i < n; i++) mv3f(c->inv32 + 9 * (size_t)i, r + 3 * (size_t)i, x + 3 * (size_t)i);
+        return;
+    }
+    float *w = malloc(sizeof(float) * 3 * (size_t)n);
+    for (int ps = 0; ps < n; ps++) {
+        int i = c->order[ps];
+        float v[3] = { r[3 * i], r[3 * i + 1], r[3 * i + 2] }, t[3];
+        for (int e = c->rp[i]; e < c->rp[i + 1]; e++) {
+            int k = c->ci[e];
+            if (c->drop[e] || c->rank[k] >= c->rank[i]) continue;
+            mv3f(c->A32 + 9 * (size_t)e, w + 3 * (size_t)k, t);
+            for (int q = 0; q < 3; q++) v[q] = v[q] - t[q];
+        }
+        mv3f(c->inv32 + 9 * (size_t)i, v, w + 3 * (size_t)i);
+    }
+    for (int ps = n - 1; ps >= 0; ps--) {
+        int i = c->order[ps];
+        float acc[3] = { 0.0f, 0.0f, 0.0f }, t[3];
+        for (int e = c->rp[i]; e < c->rp[i + 1]; e++) {
+            int j = c->ci[e];
+            if (c->drop[e] || c->rank[j] <= c->rank[i]) continue;
+            mv3f(c->A32 + 9 * (size_t)e, x + 3 * (size_t)j, t);
+            for (int q = 0; q < 3; q++) acc[q] = acc[q] + t[q];
+        }
+        mv3f(c->inv32 + 9 * (size_t)i, acc, t);
+        for (int q = 0; q < 3; q++) x[3 * i + q] = w[3 * i + q] - t[q];
+    }
+    free(w);
+}
+
+/* F stage at the mixed form's boundary: FP64 r in, rounded, FP64 out */
+static void fstage_mixed(const or_cpr *c, const double *r, double *x)
+{
+    size_t len = 3 * (size_t)c->n;
+    float *rf = malloc(sizeof(float) * len), *xf = malloc(sizeof(float) * len);
+    for (size_t e = 0; e < len; e++) rf[e] = (float)r[e];
+    fstage_f32(c, rf, xf);
+    for (size_t e = 0; e < len; e++) x[e] = (double)xf[e];
+    free(rf); free(xf);
+}
 
 static int grid_cell(const or_problem *p, int g, int *i, int *j, int *k)
 {
@@ -128,6 +220,10 @@ static int ilu_setup(or_cpr *c, const or_problem *p)
 int or_cpr_fstage(or_cpr *c, const double *r, double *x)
 {
     int n = c->n;
+    if (c->o.precision != OR_PREC_FP64) {
+        fstage_mixed(c, r, x);
+        return OR_OK;
+    }
     if (c->o.ftype == OR_F_BJ) {
         for (int i = 0; i < n; i++) or_mv3(c->inv + 9 * (size_t)i, r + 3 * (size_t)i, x + 3 * (size_t)i);
         return OR_OK;
@@ -208,6 +304,11 @@ int or_cpr_setup(const or_problem *p, int n, const int32_t *rowptr, const int32_
         st = ilu_setup(c, p);
         if (st) { or_cpr_free(c); return st; }
     }
+    if (o->precision != OR_PREC_FP64) {
+        if (o->precision != OR_PREC_FP32 && o->precision != OR_PREC_FP32_BF16) { or_cpr_free(c); return OR_ERR_ARG; }
+        st = mixed_setup(c);
+        if (st) { or_cpr_free(c); return st; }
+    }
     *out = c;
     return OR_OK;
 }
@@ -218,6 +319,7 @@ void or_cpr_free(or_cpr *c)
     if (c->has_amg) or_amg_free(&c->amg);
     free(c->Aval); free(c->cw); free(c->LU); free(c->inv); free(c->rank); free(c->order);
     free(c->drop); free(c->diag); free(c->rp); free(c->ci);
+    free(c->inv32); free(c->A32);
     free(c);
 }
 
@@ -228,10 +330,26 @@ int or_cpr_restrict(or_cpr *c, const double *v, double *rp)
     return OR_OK;
 }
 
+/* one V-cycle; in the mixed form b is rounded to float on entry and the
+ * float result is returned exactly */
+static void vcycle_any(or_cpr *c, const double *b, double *x)
+{
+    int n = c->n;
+    if (c->o.precision == OR_PREC_FP64) {
+        or_amg_vcycle(&c->amg, b, x);
+        return;
+    }
+    float *bf = calloc((size_t)n, sizeof(float)), *xf = calloc((size_t)n, sizeof(float));
+    for (int i = 0; i < n; i++) bf[i] = (float)b[i];
+    or_amg_vcycle_f32(&c->amg, bf, xf);
+    for (int i = 0; i < n; i++) x[i] = (double)xf[i];
+    free(bf); free(xf);
+}
+
 int or_cpr_vcycle(or_cpr *c, const double *b, double *x)
 {
     if (!c->has_amg) return OR_ERR_ARG;
-    or_amg_vcycle(&c->amg, b, x);
+    vcycle_any(c, b, x);
     return OR_OK;
 }
 
@@ -241,7 +359,7 @@ static void pressure_stage(or_cpr *c, const double *r, double *x)
     int n = c->n;
     double *rp = malloc(sizeof(double) * (size_t)n), *dp = malloc(sizeof(double) * (size_t)n);
     or_cpr_restrict(c, r, rp);
-    or_amg_vcycle(&c->amg, rp, dp);
+    vcycle_any(c, rp, dp);
     for (int i = 0; i < n; i++) x[3 * i] += dp[i];
     free(rp); free(dp);
 }

@@ -19,6 +19,7 @@ OR_OK, OR_NOT_CONVERGED = 0, 1
 F_BJ, F_ILU_NATURAL, F_ILU_RB, F_ILU_TILED = 0, 1, 2, 3
 QI_DIAG, QI_BLOCK = 0, 1
 SMOOTH_GS, SMOOTH_JACOBI = 0, 1
+PREC_FP64, PREC_FP32, PREC_FP32_BF16 = 0, 1, 2
 
 _i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
@@ -49,7 +50,8 @@ class OrProblem(C.Structure):
 class CprOpts(C.Structure):
     _fields_ = [("fpf", C.c_int), ("ftype", C.c_int), ("tile_x", C.c_int), ("tile_y", C.c_int),
                 ("theta", C.c_double), ("coarse_max", C.c_int), ("max_levels", C.c_int),
-                ("smoother", C.c_int), ("sweeps", C.c_int), ("use_amg", C.c_int), ("qi_mode", C.c_int)]
+                ("smoother", C.c_int), ("sweeps", C.c_int), ("use_amg", C.c_int), ("qi_mode", C.c_int),
+                ("precision", C.c_int)]
 
 
 class FgmresOpts(C.Structure):
@@ -105,8 +107,15 @@ def lib():
                             C.POINTER(FgmresOpts), C.POINTER(FgmresStats), C.c_void_p]
     L.or_arnoldi.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _f64p, C.c_int, C.c_int,
                              _f64p, _f64p, _f64p]
+    L.or_bf16_round.argtypes = [C.c_float]
+    L.or_bf16_round.restype = C.c_float
     _lib = L
     return L
+
+
+def bf16_round(f: float) -> float:
+    """The oracle's FP32 -> BF16 rounding (nearest even) of a float value."""
+    return float(lib().or_bf16_round(float(np.float32(f))))
 
 
 def _ptr(a: np.ndarray, ct):
@@ -252,9 +261,10 @@ def qi_decouple(rp, ci, val, mode=1):
 
 
 def cpr_opts(fpf=0, ftype=F_ILU_TILED, tile=(8, 8), theta=0.08, coarse_max=256, max_levels=12,
-             smoother=SMOOTH_GS, sweeps=1, use_amg=1, qi_mode=QI_BLOCK) -> CprOpts:
+             smoother=SMOOTH_GS, sweeps=1, use_amg=1, qi_mode=QI_BLOCK, precision=0) -> CprOpts:
+    """precision: PREC_FP64, or the emulated mixed forms PREC_FP32 / PREC_FP32_BF16."""
     return CprOpts(fpf, ftype, tile[0], tile[1], theta, coarse_max, max_levels, smoother,
-                   sweeps, use_amg, qi_mode)
+                   sweeps, use_amg, qi_mode, precision)
 
 
 class Cpr:
