@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--spmv-isolated", action="store_true",
                     help="also time isolated SpMV launches (after a cache-evicting pass, and back to back)")
     ap.add_argument("--spmv-reps", type=int, default=20)
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32", "bf16"),
+                    help="inner stages of the preconditioner: FP64, FP32, or FP32 with BF16 ILU factors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -74,7 +76,8 @@ def main():
     b = torch.empty(3 * n, dtype=torch.float64, device=dev)
     x = torch.empty(3 * n, dtype=torch.float64, device=dev)
     grid = (c0.nx, c0.ny, c0.nz)
-    copts = B.bo_cpr_default_opts()
+    prec = {"fp64": B.BO_PREC_FP64, "fp32": B.BO_PREC_FP32, "bf16": B.BO_PREC_FP32_BF16}[args.precision]
+    copts = B.bo_cpr_default_opts(precision=prec)
     fopts = B.bo_fgmres_default_opts()
     fopts_timed = B.bo_fgmres_default_opts(timing=1)
     torch.cuda.synchronize()
@@ -157,13 +160,15 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f64 (Krylov, residuals) + f32 (AMG, ILU)",
+                  "bf16": "f64 (Krylov, residuals) + f32 (AMG) + bf16-stored ILU factors"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": (f"cfg{wl}: {c0.nx}x{c0.ny}x{c0.nz} black-oil 3x3-block Jacobians "
                          f"({n} cells, {3 * n} unknowns, {nnzb} blocks), "
                          + ("10 systems of the synthetic 30-day step sequence" if wl else "one system")),
             "solver": "FGMRES(30), CPR-PF: block quasi-IMPES, SA-AMG V(1,1) RB-GS/Jacobi, tiled BILU0 8x8",
+            "precision": args.precision,
             "rtol": 1e-6,
             "step": "bo_jacobian_bsr + bo_cpr_update (full rebuild, memory reused) + bo_fgmres_solve",
             "parallelism": "1 GPU",

@@ -129,6 +129,15 @@ bo_status bo_bsr_spmv(const bo_bsr *A, double alpha, const double *x, double bet
 enum { BO_F_BJ = 0, BO_F_ILU_TILED = 3 };          /* F stage: block Jacobi / tiled block ILU(0) */
 enum { BO_SMOOTH_GS = 0, BO_SMOOTH_JACOBI = 1 };   /* level-0 smoother */
 enum { BO_QI_DIAG = 0, BO_QI_BLOCK = 1 };          /* quasi-IMPES weights */
+/* Precision of the preconditioner's inner stages.  BO_PREC_FP64: everything
+ * FP64.  BO_PREC_FP32: the AMG hierarchy (level operators, P, R, coarsest
+ * inverse) and the F stage's factors are built in FP64 and stored rounded to
+ * FP32; the V-cycle and the ILU / block-Jacobi sweeps run in FP32 arithmetic
+ * on FP32 vectors.  BO_PREC_FP32_BF16: as FP32, with the F stage's factors
+ * stored in BF16 (rounded to nearest even from the FP32 value).  In every form
+ * the decoupling, the restriction Pi_r v, the residual v - A x1 and the sum
+ * x1 + F(r) are FP64; values cross into FP32 by round-to-nearest at the entry
+ * of the V-cycle and of the F stage and leave it exactly. */
 enum { BO_PREC_FP64 = 0, BO_PREC_FP32 = 1, BO_PREC_FP32_BF16 = 2 };
 
 typedef struct {

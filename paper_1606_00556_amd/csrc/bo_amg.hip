@@ -99,11 +99,13 @@ __global__ void k_stencil_counts(int nx, int ny, int nz, int32_t *cnt) {
 }
 
 // restriction of a 3N residual: rp_i = c_i . v_i
+// r_p = c_i . v_i in FP64, stored as T (FP32 at the mixed form's boundary)
+template <typename T>
 __global__ void k_qi_restrict(long long n, const double *__restrict__ cw, const double *__restrict__ v,
-                              double *__restrict__ rp) {
+                              T *__restrict__ rp) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    rp[i] = cw[3 * i] * v[3 * i] + cw[3 * i + 1] * v[3 * i + 1] + cw[3 * i + 2] * v[3 * i + 2];
+    rp[i] = (T)(cw[3 * i] * v[3 * i] + cw[3 * i + 1] * v[3 * i + 1] + cw[3 * i + 2] * v[3 * i + 2]);
 }
 
 // ---- CSR utilities ---------------------------------------------------------------
@@ -698,9 +700,14 @@ __global__ void k_extract_inverse(int n, const double *__restrict__ M, double *_
 }
 
 // ---- cycle kernels -------------------------------------------------------------------
+// Every cycle kernel is instantiated for double (FP64 form) and float (mixed
+// form: hierarchy stored in FP32, FP32 arithmetic and accumulation).
+template <typename T> __device__ __forceinline__ T two_thirds() { return (T)(2.0 / 3.0); }
+
 // level 0 on the grid (slot form), colour c of red-black Gauss-Seidel
-__global__ void __launch_bounds__(kBlock) k_gs_slots(int nx, int ny, int nz, const double *__restrict__ A,
-                                                     const double *__restrict__ b, double *__restrict__ x, int colour) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs_slots(int nx, int ny, int nz, const T *__restrict__ A,
+                                                     const T *__restrict__ b, T *__restrict__ x, int colour) {
     int n = nx * ny * nz;
     int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -710,12 +717,12 @@ __global__ void __launch_bounds__(kBlock) k_gs_slots(int nx, int ny, int nz, con
     const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
                        ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
     size_t N = (size_t)n;
-    double s = b[i], d = 0.0;
+    T s = b[i], d = 0;
 #pragma unroll
     for (int q = 0; q < NSLOT; q++) {
         int j = nb[q];
         if (j < 0) continue;
-        double a = A[(size_t)q * N + i];
+        T a = A[(size_t)q * N + i];
         if (q == S_D) d = a;
         else s = s - a * x[j];
     }
@@ -723,9 +730,10 @@ __global__ void __launch_bounds__(kBlock) k_gs_slots(int nx, int ny, int nz, con
 }
 
 // level 0 damped Jacobi sweep (slot form): xo = xi + (2/3) (b - A xi) / a_ii
-__global__ void __launch_bounds__(kBlock) k_jacobi_slots(int nx, int ny, int nz, const double *__restrict__ A,
-                                                         const double *__restrict__ b, const double *__restrict__ xi,
-                                                         double *__restrict__ xo) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_jacobi_slots(int nx, int ny, int nz, const T *__restrict__ A,
+                                                         const T *__restrict__ b, const T *__restrict__ xi,
+                                                         T *__restrict__ xo) {
     int n = nx * ny * nz;
     int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -734,22 +742,23 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_slots(int nx, int ny, int nz,
     const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
                        ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
     size_t N = (size_t)n;
-    double s = 0.0, d = 0.0;
+    T s = 0, d = 0;
 #pragma unroll
     for (int q = 0; q < NSLOT; q++) {
         int j = nb[q];
         if (j < 0) continue;
-        double a = A[(size_t)q * N + i];
+        T a = A[(size_t)q * N + i];
         s = s + a * xi[j];
         if (q == S_D) d = a;
     }
-    xo[i] = xi[i] + (2.0 / 3.0) * ((b[i] - s) / d);
+    xo[i] = xi[i] + two_thirds<T>() * ((b[i] - s) / d);
 }
 
 // r = b - A x (slot form)
-__global__ void __launch_bounds__(kBlock) k_resid_slots(int nx, int ny, int nz, const double *__restrict__ A,
-                                                        const double *__restrict__ b, const double *__restrict__ x,
-                                                        double *__restrict__ r) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_resid_slots(int nx, int ny, int nz, const T *__restrict__ A,
+                                                        const T *__restrict__ b, const T *__restrict__ x,
+                                                        T *__restrict__ r) {
     int n = nx * ny * nz;
     int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -758,7 +767,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_slots(int nx, int ny, int nz, 
     const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
                        ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
     size_t N = (size_t)n;
-    double s = 0.0;
+    T s = 0;
 #pragma unroll
     for (int q = 0; q < NSLOT; q++) {
         int j = nb[q];
@@ -773,21 +782,20 @@ __global__ void __launch_bounds__(kBlock) k_resid_slots(int nx, int ny, int nz, 
 // cross-lane shuffles.
 enum { OP_MV = 0, OP_RESID = 1, OP_ADD = 2, OP_JACOBI = 3, OP_JACOBI0 = 4 };
 
-template <int G>
+template <int G, typename T>
 __global__ void __launch_bounds__(kBlock) k_csr_rowop(int n, const int32_t *__restrict__ rp,
-                                                      const int32_t *__restrict__ ci, const double *__restrict__ v,
-                                                      const double *__restrict__ x, int op,
-                                                      const double *__restrict__ b,
-                                                      const int32_t *__restrict__ dpos, double *__restrict__ y) {
+                                                      const int32_t *__restrict__ ci, const T *__restrict__ v,
+                                                      const T *__restrict__ x, int op, const T *__restrict__ b,
+                                                      const int32_t *__restrict__ dpos, T *__restrict__ y) {
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
     int row = gid / G, sub = gid % G;
     if (row >= n) return;  // whole groups leave together
     if (op == OP_JACOBI0) {
         // one damped Jacobi sweep from a zero guess
-        if (sub == 0) y[row] = (2.0 / 3.0) * (b[row] / v[dpos[row]]);
+        if (sub == 0) y[row] = two_thirds<T>() * (b[row] / v[dpos[row]]);
         return;
     }
-    double s = 0.0;
+    T s = 0;
     for (int e = rp[row] + sub; e < rp[row + 1]; e += G) s = s + v[e] * x[ci[e]];
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) s = s + __shfl_xor(s, off, G);
@@ -797,23 +805,41 @@ __global__ void __launch_bounds__(kBlock) k_csr_rowop(int n, const int32_t *__re
     case OP_RESID: y[row] = b[row] - s; break;
     case OP_ADD: y[row] = y[row] + s; break;
     default: {
-        double d = v[dpos[row]];
-        y[row] = x[row] + (2.0 / 3.0) * ((b[row] - s) / d);
+        T d = v[dpos[row]];
+        y[row] = x[row] + two_thirds<T>() * ((b[row] - s) / d);
     }
     }
 }
 
 // dense y = M x, one wavefront per row
-__global__ void __launch_bounds__(kBlock) k_dense_mv(int n, const double *__restrict__ M,
-                                                     const double *__restrict__ x, double *__restrict__ y) {
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dense_mv(int n, const T *__restrict__ M, const T *__restrict__ x,
+                                                     T *__restrict__ y) {
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
     int row = gid / 64, lane = gid % 64;
     if (row >= n) return;
-    double s = 0.0;
+    T s = 0;
     for (int c = lane; c < n; c += 64) s = s + M[(size_t)row * n + c] * x[c];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s = s + __shfl_xor(s, off, 64);
     if (lane == 0) y[row] = s;
+}
+
+// round an FP64 array to FP32 (round to nearest even)
+__global__ void k_to_f32(long long n, const double *__restrict__ a, float *__restrict__ b) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+template <typename T>
+__global__ void k_zero(long long n, T *__restrict__ x) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = (T)0;
+}
+
+__global__ void k_f32_to_f64(long long n, const float *__restrict__ a, double *__restrict__ b) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (double)a[i];
 }
 
 bo_status read_flag(int32_t *dflag, hipStream_t s, int32_t *out) {
@@ -825,19 +851,27 @@ bo_status read_flag(int32_t *dflag, hipStream_t s, int32_t *out) {
 }  // namespace
 
 // y = op(A x) for a CSR matrix with nnz entries over n rows (see k_csr_rowop)
-static bo_status csr_rowop(int n, int nnz, const int32_t *rp, const int32_t *ci, const double *v, const double *x,
-                           int op, const double *b, const int32_t *dpos, double *y, hipStream_t s) {
+template <typename T>
+static bo_status csr_rowop(int n, int nnz, const int32_t *rp, const int32_t *ci, const T *v, const T *x, int op,
+                           const T *b, const int32_t *dpos, T *y, hipStream_t s) {
     double avg = n > 0 ? (double)nnz / n : 1.0;
     long long threads;
 #define BO_ROWOP(G)                                                                                  \
     threads = (long long)n * G;                                                                      \
-    k_csr_rowop<G><<<grid_for(threads), kBlock, 0, s>>>(n, rp, ci, v, x, op, b, dpos, y)
+    k_csr_rowop<G, T><<<grid_for(threads), kBlock, 0, s>>>(n, rp, ci, v, x, op, b, dpos, y)
     if (avg <= 6.0) { BO_ROWOP(4); }
     else if (avg <= 12.0) { BO_ROWOP(8); }
     else if (avg <= 24.0) { BO_ROWOP(16); }
     else if (avg <= 48.0) { BO_ROWOP(32); }
     else { BO_ROWOP(64); }
 #undef BO_ROWOP
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+static bo_status to_f32(long long n, const double *a, float *b, hipStream_t s) {
+    if (n <= 0) return BO_OK;
+    k_to_f32<<<grid_for(n), kBlock, 0, s>>>(n, a, b);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
@@ -859,7 +893,14 @@ bo_status qi_decouple(bo_cpr *pc, hipStream_t s) {
 
 bo_status qi_restrict(bo_cpr *pc, const double *v, double *rp, hipStream_t s) {
     long long n = pc->n;
-    k_qi_restrict<<<grid_for(n), kBlock, 0, s>>>(n, pc->cw.p, v, rp);
+    k_qi_restrict<double><<<grid_for(n), kBlock, 0, s>>>(n, pc->cw.p, v, rp);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status qi_restrict_f32(bo_cpr *pc, const double *v, float *rp, hipStream_t s) {
+    long long n = pc->n;
+    k_qi_restrict<float><<<grid_for(n), kBlock, 0, s>>>(n, pc->cw.p, v, rp);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
@@ -1077,18 +1118,46 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
 }
 
 // ---- host: V-cycle -------------------------------------------------------------------
-static bo_status smooth0(bo_cpr *pc, const double *b, double *x, bool forward, hipStream_t s) {
+// the arrays a cycle in precision T works on
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+    static const double *v(const Level &L) { return L.v.p; }
+    static const double *pv(const Level &L) { return L.pv.p; }
+    static const double *rv(const Level &L) { return L.rv.p; }
+    static double *x(Level &L) { return L.x.p; }
+    static double *b(Level &L) { return L.b.p; }
+    static double *r(Level &L) { return L.r.p; }
+    static double *t(Level &L) { return L.t.p; }
+    static const double *app(const bo_cpr *pc) { return pc->app.p; }
+    static const double *cinv(const bo_cpr *pc) { return pc->cinv.p; }
+};
+template <> struct Prec<float> {
+    static const float *v(const Level &L) { return L.v32.p; }
+    static const float *pv(const Level &L) { return L.pv32.p; }
+    static const float *rv(const Level &L) { return L.rv32.p; }
+    static float *x(Level &L) { return L.x32.p; }
+    static float *b(Level &L) { return L.b32.p; }
+    static float *r(Level &L) { return L.r32.p; }
+    static float *t(Level &L) { return L.t32.p; }
+    static const float *app(const bo_cpr *pc) { return pc->app32.p; }
+    static const float *cinv(const bo_cpr *pc) { return pc->cinv32.p; }
+};
+
+template <typename T>
+static bo_status smooth0(bo_cpr *pc, const T *b, T *x, bool forward, hipStream_t s) {
     const Grid &g = pc->g;
     long long n = pc->n;
     Level &L = pc->lv[0];
+    const T *A = Prec<T>::app(pc);
     for (int sw = 0; sw < pc->o.sweeps; sw++) {
         if (pc->o.smoother == BO_SMOOTH_GS) {
             int c0 = forward ? 0 : 1;
-            k_gs_slots<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, pc->app.p, b, x, c0);
-            k_gs_slots<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, pc->app.p, b, x, 1 - c0);
+            k_gs_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, c0);
+            k_gs_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, 1 - c0);
         } else {
-            k_jacobi_slots<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, pc->app.p, b, x, L.r.p);
-            BO_HIP(hipMemcpyAsync(x, L.r.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            T *t = Prec<T>::r(L);
+            k_jacobi_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, t);
+            BO_HIP(hipMemcpyAsync(x, t, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
         }
     }
     BO_HIP(hipGetLastError());
@@ -1096,18 +1165,19 @@ static bo_status smooth0(bo_cpr *pc, const double *b, double *x, bool forward, h
 }
 
 // coarse-level damped Jacobi; `x` holds the guess (NULL: zero) and the
-// result is returned in one of x / L.t
-static bo_status smooth_c(Level &L, int sweeps, const double *b, double *x, double **res, hipStream_t s) {
-    double *cur = x, *oth = L.t.p;
+// result is returned in one of x / t
+template <typename T>
+static bo_status smooth_c(Level &L, int sweeps, const T *b, T *x, T **res, hipStream_t s) {
+    T *cur = x, *oth = Prec<T>::t(L);
     int first = 0;
     if (!x) {
-        BO_TRY(csr_rowop(L.n, L.nnz, L.rp.p, L.ci.p, L.v.p, nullptr, OP_JACOBI0, b, L.diagpos.p, L.x.p, s));
-        cur = L.x.p;
-        oth = L.t.p;
+        BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), nullptr, OP_JACOBI0, b, L.diagpos.p,
+                            Prec<T>::x(L), s));
+        cur = Prec<T>::x(L);
         first = 1;
     }
     for (int sw = first; sw < sweeps; sw++) {
-        BO_TRY(csr_rowop(L.n, L.nnz, L.rp.p, L.ci.p, L.v.p, cur, OP_JACOBI, b, L.diagpos.p, oth, s));
+        BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), cur, OP_JACOBI, b, L.diagpos.p, oth, s));
         std::swap(cur, oth);
     }
     *res = cur;
@@ -1115,34 +1185,37 @@ static bo_status smooth_c(Level &L, int sweeps, const double *b, double *x, doub
 }
 
 // one V-cycle on level l for right-hand side b; returns the result pointer
-static bo_status vcycle_rec(bo_cpr *pc, int l, const double *b, double **res, hipStream_t s) {
+template <typename T>
+static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t s) {
     Level &L = pc->lv[l];
     if (l == pc->nlev - 1) {
-        k_dense_mv<<<grid_for((long long)L.n * 64), kBlock, 0, s>>>(L.n, pc->cinv.p, b, L.x.p);
+        k_dense_mv<T><<<grid_for((long long)L.n * 64), kBlock, 0, s>>>(L.n, Prec<T>::cinv(pc), b, Prec<T>::x(L));
         BO_HIP(hipGetLastError());
-        *res = L.x.p;
+        *res = Prec<T>::x(L);
         return BO_OK;
     }
-    double *x;
+    T *x;
     if (l == 0) {
-        x = L.x.p;
-        BO_TRY(fill(L.n, 0.0, x, s));
-        BO_TRY(smooth0(pc, b, x, true, s));
-        k_resid_slots<<<grid_for(L.n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->app.p, b, x, L.r.p);
+        x = Prec<T>::x(L);
+        k_zero<T><<<grid_for(L.n), kBlock, 0, s>>>(L.n, x);
+        BO_TRY(smooth0<T>(pc, b, x, true, s));
+        k_resid_slots<T><<<grid_for(L.n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, Prec<T>::app(pc), b, x,
+                                                           Prec<T>::r(L));
     } else {
-        BO_TRY(smooth_c(L, pc->o.sweeps, b, nullptr, &x, s));
-        BO_TRY(csr_rowop(L.n, L.nnz, L.rp.p, L.ci.p, L.v.p, x, OP_RESID, b, nullptr, L.r.p, s));
+        BO_TRY(smooth_c<T>(L, pc->o.sweeps, b, nullptr, &x, s));
+        BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), x, OP_RESID, b, nullptr, Prec<T>::r(L), s));
     }
     Level &C = pc->lv[l + 1];
-    BO_TRY(csr_rowop(C.n, L.pnnz, L.rrp.p, L.rci.p, L.rv.p, L.r.p, OP_MV, nullptr, nullptr, C.b.p, s));
-    double *xc;
-    BO_TRY(vcycle_rec(pc, l + 1, C.b.p, &xc, s));
-    BO_TRY(csr_rowop(L.n, L.pnnz, L.prp.p, L.pci.p, L.pv.p, xc, OP_ADD, nullptr, nullptr, x, s));
+    BO_TRY(csr_rowop<T>(C.n, L.pnnz, L.rrp.p, L.rci.p, Prec<T>::rv(L), Prec<T>::r(L), OP_MV, nullptr, nullptr,
+                        Prec<T>::b(C), s));
+    T *xc;
+    BO_TRY(vcycle_rec<T>(pc, l + 1, Prec<T>::b(C), &xc, s));
+    BO_TRY(csr_rowop<T>(L.n, L.pnnz, L.prp.p, L.pci.p, Prec<T>::pv(L), xc, OP_ADD, nullptr, nullptr, x, s));
     if (l == 0) {
-        BO_TRY(smooth0(pc, b, x, false, s));
+        BO_TRY(smooth0<T>(pc, b, x, false, s));
         *res = x;
     } else {
-        BO_TRY(smooth_c(L, pc->o.sweeps, b, x, res, s));
+        BO_TRY(smooth_c<T>(L, pc->o.sweeps, b, x, res, s));
     }
     return BO_OK;
 }
@@ -1151,15 +1224,55 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const double *b, double **res, hi
 // valid until the next cycle)
 bo_status amg_vcycle_ptr(bo_cpr *pc, const double *b, const double **res, hipStream_t s) {
     double *r;
-    BO_TRY(vcycle_rec(pc, 0, b, &r, s));
+    BO_TRY(vcycle_rec<double>(pc, 0, b, &r, s));
+    *res = r;
+    return BO_OK;
+}
+
+// mixed form: b is the FP32 right-hand side, the cycle runs in FP32
+bo_status amg_vcycle_ptr_f32(bo_cpr *pc, const float *b, const float **res, hipStream_t s) {
+    float *r;
+    BO_TRY(vcycle_rec<float>(pc, 0, b, &r, s));
     *res = r;
     return BO_OK;
 }
 
 bo_status amg_vcycle(bo_cpr *pc, const double *b, double *x, hipStream_t s) {
+    if (pc->o.precision != BO_PREC_FP64) {
+        // FP64 in and out, FP32 inside: the stage boundaries of the mixed form
+        Level &L0 = pc->lv[0];
+        BO_TRY(to_f32(pc->n, b, L0.b32.p, s));
+        const float *res;
+        BO_TRY(amg_vcycle_ptr_f32(pc, L0.b32.p, &res, s));
+        k_f32_to_f64<<<grid_for(pc->n), kBlock, 0, s>>>(pc->n, res, x);
+        BO_HIP(hipGetLastError());
+        return BO_OK;
+    }
     const double *res;
     BO_TRY(amg_vcycle_ptr(pc, b, &res, s));
     if (res != x) BO_HIP(hipMemcpyAsync(x, res, sizeof(double) * pc->n, hipMemcpyDeviceToDevice, s));
+    return BO_OK;
+}
+
+// FP32 copies of the hierarchy for the mixed form (the setup itself is FP64)
+bo_status amg_make_f32(bo_cpr *pc, hipStream_t s) {
+    BO_TRY(pc->app32.alloc(7 * (size_t)pc->n));
+    BO_TRY(to_f32(7 * (long long)pc->n, pc->app.p, pc->app32.p, s));
+    for (int l = 0; l < pc->nlev; l++) {
+        Level &L = pc->lv[l];
+        BO_TRY(L.x32.alloc(L.n)); BO_TRY(L.b32.alloc(L.n)); BO_TRY(L.r32.alloc(L.n)); BO_TRY(L.t32.alloc(L.n));
+        if (l > 0) {
+            BO_TRY(L.v32.alloc(L.nnz));
+            BO_TRY(to_f32(L.nnz, L.v.p, L.v32.p, s));
+        }
+        if (l + 1 < pc->nlev) {
+            BO_TRY(L.pv32.alloc(L.pnnz)); BO_TRY(L.rv32.alloc(L.pnnz));
+            BO_TRY(to_f32(L.pnnz, L.pv.p, L.pv32.p, s));
+            BO_TRY(to_f32(L.pnnz, L.rv.p, L.rv32.p, s));
+        }
+    }
+    BO_TRY(pc->cinv32.alloc((size_t)pc->coarse_n * pc->coarse_n));
+    BO_TRY(to_f32((long long)pc->coarse_n * pc->coarse_n, pc->cinv.p, pc->cinv32.p, s));
     return BO_OK;
 }
 

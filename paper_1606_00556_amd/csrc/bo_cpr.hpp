@@ -26,7 +26,7 @@ struct Level {
     // cycle work vectors
     DBuf<double> x, b, r, t;
     // single-precision copies (mixed form)
-    DBuf<float> v32, pv32, rv32, dinv32, x32, b32, r32;
+    DBuf<float> v32, pv32, rv32, x32, b32, r32, t32;
 };
 
 // setup temporaries kept with the handle, reused (grow-only) by later setups
@@ -72,14 +72,13 @@ struct bo_cpr {
     bo::DBuf<float> cinv32;
     // F stage: block-Jacobi inverses (SoA 9 * N), or the tiled ILU factors in
     // (tile, step, lane) order with the cell index of each slot and the
-    // forward-sweep result in the same order
+    // forward-sweep result in the same order; in the mixed form the same
+    // buffers hold FP32 or BF16 values
     bo::DBuf<double> einv;
     bo::DBuf<double2> ilu_f, ilu_b;
     bo::DBuf<double> ilu_w, ilu_r;
+    bo::DBuf<float> ilu_w32, ilu_r32;   // mixed form
     bo::DBuf<int32_t> ilu_cell, ilu_slot;
-    bo::DBuf<float> einv32;
-    bo::DBuf<uint16_t> einv16, A16;  // bf16 copies (mixed-bf16 form)
-    bo::DBuf<float> A32;          // fp32 copy of A's off-diagonal slots for the ILU apply
     // work vectors
     bo::DBuf<double> rp_, dp_, t3a, t3b, t3c, wf;
     bo::DBuf<int32_t> flag;

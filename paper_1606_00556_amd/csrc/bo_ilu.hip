@@ -17,6 +17,11 @@
 // wavefront loads, and the fields of the next two steps are loaded before the
 // current step is computed.  Block Jacobi (x_i = A_ii^{-1} r_i) is the alternative F
 // stage.
+//
+// Mixed form: the factors (E^{-1} and the blocks of A) are computed in FP64
+// and stored rounded to FP32 (9 float4 per slot and sweep) or to BF16 (9 uint2
+// per slot and sweep, round to nearest even from the FP32 value); the sweeps
+// run in FP32 on FP32 vectors.
 #include "bo_cpr.hpp"
 
 namespace bo {
@@ -37,13 +42,49 @@ __device__ __forceinline__ size_t pk_index(int tile, int ns, int s, int pair, in
     return (((size_t)tile * ns + s) * kPairs + pair) * 64 + lane;
 }
 
+enum { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
+constexpr int kQuads = 9;  // 36 values as 9 groups of four (FP32 / BF16 forms)
+__device__ __forceinline__ size_t pq_index(int tile, int ns, int s, int quad, int lane) {
+    return (((size_t)tile * ns + s) * kQuads + quad) * 64 + lane;
+}
+
+// FP32 -> BF16, round to nearest even (inputs are finite)
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
+
+// store one slot's 36 FP64 values in the chosen format
+template <int St>
+__device__ __forceinline__ void store_pack(void *F, int tile, int ns, int s, int t, const double *v) {
+    if constexpr (St == ST_F64) {
+        double2 *D = (double2 *)F;
+        for (int p2 = 0; p2 < kPairs; p2++) D[pk_index(tile, ns, s, p2, t)] = make_double2(v[2 * p2], v[2 * p2 + 1]);
+    } else if constexpr (St == ST_F32) {
+        float4 *D = (float4 *)F;
+        for (int qd = 0; qd < kQuads; qd++)
+            D[pq_index(tile, ns, s, qd, t)] = make_float4((float)v[4 * qd], (float)v[4 * qd + 1],
+                                                          (float)v[4 * qd + 2], (float)v[4 * qd + 3]);
+    } else {
+        uint2 *D = (uint2 *)F;
+        for (int qd = 0; qd < kQuads; qd++) {
+            uint32_t h0 = bf16_bits((float)v[4 * qd]), h1 = bf16_bits((float)v[4 * qd + 1]);
+            uint32_t h2 = bf16_bits((float)v[4 * qd + 2]), h3 = bf16_bits((float)v[4 * qd + 3]);
+            D[pq_index(tile, ns, s, qd, t)] = make_uint2(h0 | (h1 << 16), h2 | (h3 << 16));
+        }
+    }
+}
+
 __device__ __forceinline__ void load_blk(const double *__restrict__ A, int slot, size_t N, int g, double *o) {
     const double *p = A + (size_t)slot * 9 * N + g;
 #pragma unroll
     for (int z = 0; z < 9; z++) o[z] = p[(size_t)z * N];
 }
 
-__device__ __forceinline__ void mv3(const double *A, const double *x, double *y) {
+template <typename T>
+__device__ __forceinline__ void mv3(const T *A, const T *x, T *y) {
     y[0] = A[0] * x[0] + A[1] * x[1] + A[2] * x[2];
     y[1] = A[3] * x[0] + A[4] * x[1] + A[5] * x[2];
     y[2] = A[6] * x[0] + A[7] * x[1] + A[8] * x[2];
@@ -59,8 +100,9 @@ __device__ __forceinline__ void shfl_arr(const double *src, double *dst, int lan
 // (+x,+y,+z) of each cell (zero where the neighbour lies outside the tile or
 // grid) into the (tile, step, lane) layout, and the cell index of each slot
 // (-1 for idle slots).  E^{-1} by Gauss-Jordan with partial pivoting.
+template <int St>
 __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__restrict__ A,
-                                                   double2 *__restrict__ Ff, double2 *__restrict__ Fb,
+                                                   void *__restrict__ Ff, void *__restrict__ Fb,
                                                    int32_t *__restrict__ cell, int32_t *__restrict__ slot_of,
                                                    int32_t *__restrict__ bad) {
     int t = threadIdx.x;
@@ -119,10 +161,8 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
             if (has_py) load_blk(A, S_PY, N, g, Uyp); else for (int z = 0; z < 9; z++) Uyp[z] = 0.0;
             if (k + 1 < T.nz) load_blk(A, S_PZ, N, g, Uzp); else for (int z = 0; z < 9; z++) Uzp[z] = 0.0;
             for (int z = 0; z < 9; z++) { bw[9 + z] = Uxp[z]; bw[18 + z] = Uyp[z]; bw[27 + z] = Uzp[z]; }
-            for (int p2 = 0; p2 < kPairs; p2++) {
-                Ff[pk_index(tile, T.ns, s, p2, t)] = make_double2(fw[2 * p2], fw[2 * p2 + 1]);
-                Fb[pk_index(tile, T.ns, s, p2, t)] = make_double2(bw[2 * p2], bw[2 * p2 + 1]);
-            }
+            store_pack<St>(Ff, tile, T.ns, s, t, fw);
+            store_pack<St>(Fb, tile, T.ns, s, t, bw);
             cell[q] = g;
             slot_of[g] = (int32_t)q;
         } else {
@@ -131,110 +171,135 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
     }
 }
 
+template <typename T>
 struct Pack {
-    double v[36];
-    double w[3];   // the sweep's vector operand at this slot
+    T v[36];
+    T w[3];   // the sweep's vector operand at this slot
     int g;
 };
 
-__device__ __forceinline__ void load_pack(const double2 *__restrict__ F, const int32_t *__restrict__ cell,
-                                          const double *__restrict__ vec, size_t S, int tile, int ns, int s, int t,
-                                          Pack &p) {
+template <int St, typename T>
+__device__ __forceinline__ void load_pack(const void *__restrict__ F, const int32_t *__restrict__ cell,
+                                          const T *__restrict__ vec, size_t S, int tile, int ns, int s, int t,
+                                          Pack<T> &p) {
     size_t q = ((size_t)tile * ns + s) * 64 + t;
     p.g = cell[q];
+    if constexpr (St == ST_F64) {
+        const double2 *D = (const double2 *)F;
 #pragma unroll
-    for (int p2 = 0; p2 < kPairs; p2++) {
-        double2 d = F[pk_index(tile, ns, s, p2, t)];
-        p.v[2 * p2] = d.x;
-        p.v[2 * p2 + 1] = d.y;
+        for (int p2 = 0; p2 < kPairs; p2++) {
+            double2 d = D[pk_index(tile, ns, s, p2, t)];
+            p.v[2 * p2] = d.x;
+            p.v[2 * p2 + 1] = d.y;
+        }
+    } else if constexpr (St == ST_F32) {
+        const float4 *D = (const float4 *)F;
+#pragma unroll
+        for (int qd = 0; qd < kQuads; qd++) {
+            float4 f = D[pq_index(tile, ns, s, qd, t)];
+            p.v[4 * qd] = f.x; p.v[4 * qd + 1] = f.y; p.v[4 * qd + 2] = f.z; p.v[4 * qd + 3] = f.w;
+        }
+    } else {
+        const uint2 *D = (const uint2 *)F;
+#pragma unroll
+        for (int qd = 0; qd < kQuads; qd++) {
+            uint2 u = D[pq_index(tile, ns, s, qd, t)];
+            p.v[4 * qd] = bf16_value(u.x & 0xFFFFu); p.v[4 * qd + 1] = bf16_value(u.x >> 16);
+            p.v[4 * qd + 2] = bf16_value(u.y & 0xFFFFu); p.v[4 * qd + 3] = bf16_value(u.y >> 16);
+        }
     }
     p.w[0] = vec[q]; p.w[1] = vec[S + q]; p.w[2] = vec[2 * S + q];
 }
 
 // scatter a natural-order 3N vector into (tile, step, lane) order
+template <typename T>
 __global__ void k_to_slots(long long n, const int32_t *__restrict__ slot_of, size_t S, const double *__restrict__ r,
-                           double *__restrict__ rq) {
+                           T *__restrict__ rq) {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     size_t q = (size_t)slot_of[g];
-    rq[q] = r[3 * g]; rq[S + q] = r[3 * g + 1]; rq[2 * S + q] = r[3 * g + 2];
+    rq[q] = (T)r[3 * g]; rq[S + q] = (T)r[3 * g + 1]; rq[2 * S + q] = (T)r[3 * g + 2];
 }
 
 // forward sweep: w = E^{-1}(r - L w_lower); r and w in (tile, step, lane) order
-__global__ void __launch_bounds__(64) k_ilu_forward(TileGeom T, const double2 *__restrict__ F,
-                                                    const int32_t *__restrict__ cell, const double *__restrict__ rq,
-                                                    double *__restrict__ wq) {
+template <int St, typename T>
+__global__ void __launch_bounds__(64) k_ilu_forward(TileGeom G, const void *__restrict__ F,
+                                                    const int32_t *__restrict__ cell, const T *__restrict__ rq,
+                                                    T *__restrict__ wq) {
     int t = threadIdx.x;
-    int a = t % T.tx, b = t / T.tx;
+    int a = t % G.tx, b = t / G.tx;
     int tile = blockIdx.x;
-    size_t S = (size_t)T.slots();
-    int lx = a > 0 ? t - 1 : t, ly = b > 0 ? t - T.tx : t;
-    double wp[3] = {0.0, 0.0, 0.0};
+    size_t S = (size_t)G.slots();
+    int lx = a > 0 ? t - 1 : t, ly = b > 0 ? t - G.tx : t;
+    T wp[3] = {0, 0, 0};
     // two steps of operands in flight ahead of the one being computed
-    Pack cur, n1, n2;
-    load_pack(F, cell, rq, S, tile, T.ns, 0, t, n1);
-    if (T.ns > 1) load_pack(F, cell, rq, S, tile, T.ns, 1, t, n2);
-    for (int s = 0; s < T.ns; s++) {
+    Pack<T> cur, n1, n2;
+    load_pack<St, T>(F, cell, rq, S, tile, G.ns, 0, t, n1);
+    if (G.ns > 1) load_pack<St, T>(F, cell, rq, S, tile, G.ns, 1, t, n2);
+    for (int s = 0; s < G.ns; s++) {
         cur = n1;
         n1 = n2;
-        if (s + 2 < T.ns) load_pack(F, cell, rq, S, tile, T.ns, s + 2, t, n2);
-        double wy[3], wx[3];
+        if (s + 2 < G.ns) load_pack<St, T>(F, cell, rq, S, tile, G.ns, s + 2, t, n2);
+        T wy[3], wx[3];
         for (int c = 0; c < 3; c++) { wx[c] = __shfl(wp[c], lx, 64); wy[c] = __shfl(wp[c], ly, 64); }
         if (cur.g >= 0) {
-            double v[3] = {cur.w[0], cur.w[1], cur.w[2]};
-            double y[3];
+            T v[3] = {cur.w[0], cur.w[1], cur.w[2]};
+            T y[3];
             // zero blocks stand for missing neighbours
             mv3(cur.v + 9, wp, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
             mv3(cur.v + 18, wy, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
             mv3(cur.v + 27, wx, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
             mv3(cur.v, v, wp);
-            size_t q = ((size_t)tile * T.ns + s) * 64 + t;
+            size_t q = ((size_t)tile * G.ns + s) * 64 + t;
             wq[q] = wp[0]; wq[S + q] = wp[1]; wq[2 * S + q] = wp[2];
         } else {
-            wp[0] = wp[1] = wp[2] = 0.0;
+            wp[0] = wp[1] = wp[2] = 0;
         }
     }
 }
 
 // backward sweep: x_i = w_i - E_i^{-1} sum_{upper} A_ij x_j, written in
-// natural order as out = x + (dp, 0, 0) (dp may be NULL)
-__global__ void __launch_bounds__(64) k_ilu_backward(TileGeom T, const double2 *__restrict__ F,
-                                                     const int32_t *__restrict__ cell, const double *__restrict__ wq,
-                                                     const double *__restrict__ dp, double *__restrict__ out) {
+// natural order as out = x + (dp, 0, 0) in FP64 (dp may be NULL)
+template <int St, typename T, typename TD>
+__global__ void __launch_bounds__(64) k_ilu_backward(TileGeom G, const void *__restrict__ F,
+                                                     const int32_t *__restrict__ cell, const T *__restrict__ wq,
+                                                     const TD *__restrict__ dp, double *__restrict__ out) {
     int t = threadIdx.x;
-    int a = t % T.tx, b = t / T.tx;
+    int a = t % G.tx, b = t / G.tx;
     int tile = blockIdx.x;
-    size_t S = (size_t)T.slots();
-    int px = a + 1 < T.tx && t + 1 < 64 ? t + 1 : t;
-    int py = b + 1 < T.ty && t + T.tx < 64 ? t + T.tx : t;
-    double xp[3] = {0.0, 0.0, 0.0};
-    Pack cur, n1, n2;
-    load_pack(F, cell, wq, S, tile, T.ns, T.ns - 1, t, n1);
-    if (T.ns > 1) load_pack(F, cell, wq, S, tile, T.ns, T.ns - 2, t, n2);
-    for (int s = T.ns - 1; s >= 0; s--) {
+    size_t S = (size_t)G.slots();
+    int px = a + 1 < G.tx && t + 1 < 64 ? t + 1 : t;
+    int py = b + 1 < G.ty && t + G.tx < 64 ? t + G.tx : t;
+    T xp[3] = {0, 0, 0};
+    Pack<T> cur, n1, n2;
+    load_pack<St, T>(F, cell, wq, S, tile, G.ns, G.ns - 1, t, n1);
+    if (G.ns > 1) load_pack<St, T>(F, cell, wq, S, tile, G.ns, G.ns - 2, t, n2);
+    for (int s = G.ns - 1; s >= 0; s--) {
         cur = n1;
         n1 = n2;
-        if (s >= 2) load_pack(F, cell, wq, S, tile, T.ns, s - 2, t, n2);
-        double xx[3], xy[3];
+        if (s >= 2) load_pack<St, T>(F, cell, wq, S, tile, G.ns, s - 2, t, n2);
+        T xx[3], xy[3];
         for (int c = 0; c < 3; c++) { xx[c] = __shfl(xp[c], px, 64); xy[c] = __shfl(xp[c], py, 64); }
         if (cur.g >= 0) {
-            double acc[3], y[3];
+            T acc[3], y[3];
             mv3(cur.v + 9, xx, acc);
             mv3(cur.v + 18, xy, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
             mv3(cur.v + 27, xp, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
             mv3(cur.v, acc, y);
             xp[0] = cur.w[0] - y[0]; xp[1] = cur.w[1] - y[1]; xp[2] = cur.w[2] - y[2];
             size_t g = (size_t)cur.g;
-            out[3 * g] = dp ? dp[g] + xp[0] : xp[0];
-            out[3 * g + 1] = xp[1];
-            out[3 * g + 2] = xp[2];
+            out[3 * g] = dp ? (double)dp[g] + (double)xp[0] : (double)xp[0];
+            out[3 * g + 1] = (double)xp[1];
+            out[3 * g + 2] = (double)xp[2];
         } else {
-            xp[0] = xp[1] = xp[2] = 0.0;
+            xp[0] = xp[1] = xp[2] = 0;
         }
     }
 }
 
-__global__ void k_bj_setup(long long n, const double *__restrict__ A, double *__restrict__ einv,
+// block Jacobi: E_i^{-1} = A_ii^{-1} (FP64), stored as FP64, FP32 or BF16 (9 x N, SoA)
+template <int St>
+__global__ void k_bj_setup(long long n, const double *__restrict__ A, void *__restrict__ einv,
                            int32_t *__restrict__ bad) {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
@@ -245,20 +310,33 @@ __global__ void k_bj_setup(long long n, const double *__restrict__ A, double *__
         *bad = 1;
         for (int z = 0; z < 9; z++) Ei[z] = 0.0;
     }
-    for (int z = 0; z < 9; z++) einv[(size_t)z * N + g] = Ei[z];
+    for (int z = 0; z < 9; z++) {
+        if constexpr (St == ST_F64) ((double *)einv)[(size_t)z * N + g] = Ei[z];
+        else if constexpr (St == ST_F32) ((float *)einv)[(size_t)z * N + g] = (float)Ei[z];
+        else ((uint16_t *)einv)[(size_t)z * N + g] = (uint16_t)bf16_bits((float)Ei[z]);
+    }
 }
 
-__global__ void k_bj_apply(long long n, const double *__restrict__ einv, const double *__restrict__ r,
-                           const double *__restrict__ dp, double *__restrict__ out) {
+template <int St, typename T, typename TD>
+__global__ void k_bj_apply(long long n, const void *__restrict__ einv, const double *__restrict__ r,
+                           const TD *__restrict__ dp, double *__restrict__ out) {
     long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     size_t N = (size_t)n;
-    double Ei[9], v[3] = {r[3 * g], r[3 * g + 1], r[3 * g + 2]}, o[3];
-    for (int z = 0; z < 9; z++) Ei[z] = einv[(size_t)z * N + g];
+    T Ei[9], v[3] = {(T)r[3 * g], (T)r[3 * g + 1], (T)r[3 * g + 2]}, o[3];
+    for (int z = 0; z < 9; z++) {
+        if constexpr (St == ST_F64) Ei[z] = ((const double *)einv)[(size_t)z * N + g];
+        else if constexpr (St == ST_F32) Ei[z] = ((const float *)einv)[(size_t)z * N + g];
+        else Ei[z] = bf16_value(((const uint16_t *)einv)[(size_t)z * N + g]);
+    }
     mv3(Ei, v, o);
-    out[3 * g] = dp ? dp[g] + o[0] : o[0];
-    out[3 * g + 1] = o[1];
-    out[3 * g + 2] = o[2];
+    out[3 * g] = dp ? (double)dp[g] + (double)o[0] : (double)o[0];
+    out[3 * g + 1] = (double)o[1];
+    out[3 * g + 2] = (double)o[2];
+}
+
+int store_of(const bo_cpr *pc) {
+    return pc->o.precision == BO_PREC_FP64 ? ST_F64 : pc->o.precision == BO_PREC_FP32 ? ST_F32 : ST_BF16;
 }
 
 TileGeom geom(const bo_cpr *pc) {
@@ -275,24 +353,42 @@ TileGeom geom(const bo_cpr *pc) {
 
 bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
     long long n = pc->n;
+    int st = store_of(pc);
     BO_HIP(hipMemsetAsync(pc->flag.p, 0, sizeof(int32_t), s));
     if (pc->o.ftype == BO_F_BJ) {
-        BO_TRY(pc->einv.alloc(9 * n));
-        k_bj_setup<<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, pc->einv.p, pc->flag.p);
+        BO_TRY(pc->einv.alloc(9 * n));  // FP64 size: large enough for every format
+        void *E = pc->einv.p;
+        if (st == ST_F64) k_bj_setup<ST_F64><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
+        else if (st == ST_F32) k_bj_setup<ST_F32><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
+        else k_bj_setup<ST_BF16><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
     } else {
         TileGeom T = geom(pc);
         size_t S = (size_t)T.slots();
+        // factor buffers sized for FP64; the FP32 and BF16 forms use a prefix
         BO_TRY(pc->ilu_f.alloc(S * kPairs));
         BO_TRY(pc->ilu_b.alloc(S * kPairs));
         BO_TRY(pc->ilu_cell.alloc(S));
         BO_TRY(pc->ilu_slot.alloc(n));
-        BO_TRY(pc->ilu_w.alloc(3 * S));
-        BO_TRY(pc->ilu_r.alloc(3 * S));
+        if (st == ST_F64) {
+            BO_TRY(pc->ilu_w.alloc(3 * S));
+            BO_TRY(pc->ilu_r.alloc(3 * S));
+        } else {
+            BO_TRY(pc->ilu_w32.alloc(3 * S));
+            BO_TRY(pc->ilu_r32.alloc(3 * S));
+        }
         // idle slots keep zero factors
         BO_HIP(hipMemsetAsync(pc->ilu_f.p, 0, sizeof(double2) * S * kPairs, s));
         BO_HIP(hipMemsetAsync(pc->ilu_b.p, 0, sizeof(double2) * S * kPairs, s));
-        k_ilu_factor<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
+        int nb = T.ntx * T.nty;
+        if (st == ST_F64)
+            k_ilu_factor<ST_F64><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
                                                    pc->ilu_slot.p, pc->flag.p);
+        else if (st == ST_F32)
+            k_ilu_factor<ST_F32><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
+                                                   pc->ilu_slot.p, pc->flag.p);
+        else
+            k_ilu_factor<ST_BF16><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
+                                                    pc->ilu_slot.p, pc->flag.p);
     }
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
@@ -302,21 +398,43 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
     return BO_OK;
 }
 
-// out = F(r) (+ Pi_p dp when dp != NULL).  With r_in_slots the residual is
-// already in the F stage's slot order (pc->ilu_r, written by the caller).
-bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, bool r_in_slots, hipStream_t s) {
+namespace {
+template <int St, typename T, typename TD>
+bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, bool r_in_slots, T *rq, T *wq,
+                     hipStream_t s) {
     long long n = pc->n;
     if (pc->o.ftype == BO_F_BJ) {
-        k_bj_apply<<<grid_for(n), kBlock, 0, s>>>(n, pc->einv.p, r, dp, out);
+        k_bj_apply<St, T, TD><<<grid_for(n), kBlock, 0, s>>>(n, pc->einv.p, r, dp, out);
     } else {
-        TileGeom T = geom(pc);
-        size_t S = (size_t)T.slots();
-        if (!r_in_slots) k_to_slots<<<grid_for(n), kBlock, 0, s>>>(n, pc->ilu_slot.p, S, r, pc->ilu_r.p);
-        k_ilu_forward<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->ilu_f.p, pc->ilu_cell.p, pc->ilu_r.p, pc->ilu_w.p);
-        k_ilu_backward<<<T.ntx * T.nty, 64, 0, s>>>(T, pc->ilu_b.p, pc->ilu_cell.p, pc->ilu_w.p, dp, out);
+        TileGeom G = geom(pc);
+        size_t S = (size_t)G.slots();
+        if (!r_in_slots) k_to_slots<T><<<grid_for(n), kBlock, 0, s>>>(n, pc->ilu_slot.p, S, r, rq);
+        k_ilu_forward<St, T><<<G.ntx * G.nty, 64, 0, s>>>(G, pc->ilu_f.p, pc->ilu_cell.p, rq, wq);
+        k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 64, 0, s>>>(G, pc->ilu_b.p, pc->ilu_cell.p, wq, dp, out);
     }
     BO_HIP(hipGetLastError());
     return BO_OK;
+}
+}  // namespace
+
+// out = F(r) (+ Pi_p dp when dp != NULL).  With r_in_slots the residual is
+// already in the F stage's slot order (ilu_r, or ilu_r32 in the mixed form).
+bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, bool r_in_slots, hipStream_t s) {
+    switch (store_of(pc)) {
+    case ST_F64: return fstage_run<ST_F64, double, double>(pc, r, dp, out, r_in_slots, pc->ilu_r.p, pc->ilu_w.p, s);
+    case ST_F32: return fstage_run<ST_F32, float, double>(pc, r, dp, out, r_in_slots, pc->ilu_r32.p, pc->ilu_w32.p, s);
+    default: return fstage_run<ST_BF16, float, double>(pc, r, dp, out, r_in_slots, pc->ilu_r32.p, pc->ilu_w32.p, s);
+    }
+}
+
+// mixed form with the FP32 pressure correction of the V-cycle
+bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, bool r_in_slots,
+                             hipStream_t s) {
+    switch (store_of(pc)) {
+    case ST_F32: return fstage_run<ST_F32, float, float>(pc, r, dp, out, r_in_slots, pc->ilu_r32.p, pc->ilu_w32.p, s);
+    case ST_BF16: return fstage_run<ST_BF16, float, float>(pc, r, dp, out, r_in_slots, pc->ilu_r32.p, pc->ilu_w32.p, s);
+    default: return fail(BO_ERR_INVALID_ARG, "F stage: FP32 pressure correction in the FP64 form");
+    }
 }
 
 size_t fstage_slots(const bo_cpr *pc) { return (size_t)geom(pc).slots(); }

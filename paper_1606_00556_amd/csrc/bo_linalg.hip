@@ -198,12 +198,14 @@ __global__ void __launch_bounds__(kBlock) k_slot_spmv(int nx, int ny, int nz, co
     }
 }
 
-// r = v - A (Pi_p dp): only column 0 of each block is needed.
+// r = v - A (Pi_p dp): only column 0 of each block is needed.  The residual
+// is formed in FP64; dp may be FP32 (mixed form) and r is stored as TO.
+template <typename TD, typename TO>
 __global__ void __launch_bounds__(kBlock) k_slot_col0_residual(int nx, int ny, int nz,
                                                                const double *__restrict__ A,
                                                                const double *__restrict__ v,
-                                                               const double *__restrict__ dp,
-                                                               double *__restrict__ r) {
+                                                               const TD *__restrict__ dp,
+                                                               TO *__restrict__ r) {
     int n = nx * ny * nz;
     int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -218,24 +220,25 @@ __global__ void __launch_bounds__(kBlock) k_slot_col0_residual(int nx, int ny, i
         int j = nb[s];
         if (j < 0) continue;
         const double *a = A + (size_t)s * 9 * N + i;
-        double p = dp[j];
+        double p = (double)dp[j];
         s0 = s0 + a[0 * N] * p;
         s1 = s1 + a[3 * N] * p;
         s2 = s2 + a[6 * N] * p;
     }
-    r[3 * (size_t)i] = v[3 * (size_t)i] - s0;
-    r[3 * (size_t)i + 1] = v[3 * (size_t)i + 1] - s1;
-    r[3 * (size_t)i + 2] = v[3 * (size_t)i + 2] - s2;
+    r[3 * (size_t)i] = (TO)(v[3 * (size_t)i] - s0);
+    r[3 * (size_t)i + 1] = (TO)(v[3 * (size_t)i + 1] - s1);
+    r[3 * (size_t)i + 2] = (TO)(v[3 * (size_t)i + 2] - s2);
 }
 
 // The same residual written in the F stage's slot order: component c of cell
 // i goes to out[c * S + slot_of[i]].
+template <typename TD, typename TO>
 __global__ void __launch_bounds__(kBlock) k_slot_col0_residual_perm(int nx, int ny, int nz,
                                                                     const double *__restrict__ A,
                                                                     const double *__restrict__ v,
-                                                                    const double *__restrict__ dp,
+                                                                    const TD *__restrict__ dp,
                                                                     const int32_t *__restrict__ slot_of, size_t S,
-                                                                    double *__restrict__ out) {
+                                                                    TO *__restrict__ out) {
     int n = nx * ny * nz;
     int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -250,15 +253,15 @@ __global__ void __launch_bounds__(kBlock) k_slot_col0_residual_perm(int nx, int 
         int j = nb[s];
         if (j < 0) continue;
         const double *a = A + (size_t)s * 9 * N + i;
-        double p = dp[j];
+        double p = (double)dp[j];
         s0 = s0 + a[0 * N] * p;
         s1 = s1 + a[3 * N] * p;
         s2 = s2 + a[6 * N] * p;
     }
     size_t q = (size_t)slot_of[i];
-    out[q] = v[3 * (size_t)i] - s0;
-    out[S + q] = v[3 * (size_t)i + 1] - s1;
-    out[2 * S + q] = v[3 * (size_t)i + 2] - s2;
+    out[q] = (TO)(v[3 * (size_t)i] - s0);
+    out[S + q] = (TO)(v[3 * (size_t)i + 1] - s1);
+    out[2 * S + q] = (TO)(v[3 * (size_t)i + 2] - s2);
 }
 
 // ---- BLAS-1 -------------------------------------------------------------------
@@ -414,21 +417,32 @@ bo_status slot_spmv(const Grid &g, const double *A, double alpha, const double *
     return BO_OK;
 }
 
-bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, const double *dp, double *r,
-                             hipStream_t s) {
+template <typename TD, typename TO>
+bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, const TD *dp, TO *r, hipStream_t s) {
     long long n = g.n();
-    k_slot_col0_residual<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, v, dp, r);
+    k_slot_col0_residual<TD, TO><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, v, dp, r);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
+template bo_status slot_col0_residual<double, double>(const Grid &, const double *, const double *, const double *,
+                                                      double *, hipStream_t);
+template bo_status slot_col0_residual<float, double>(const Grid &, const double *, const double *, const float *,
+                                                     double *, hipStream_t);
 
-bo_status slot_col0_residual_perm(const Grid &g, const double *A, const double *v, const double *dp,
-                                  const int32_t *slot_of, size_t S, double *out, hipStream_t s) {
+template <typename TD, typename TO>
+bo_status slot_col0_residual_perm(const Grid &g, const double *A, const double *v, const TD *dp,
+                                  const int32_t *slot_of, size_t S, TO *out, hipStream_t s) {
     long long n = g.n();
-    k_slot_col0_residual_perm<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, v, dp, slot_of, S, out);
+    k_slot_col0_residual_perm<TD, TO><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, v, dp, slot_of, S, out);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
+template bo_status slot_col0_residual_perm<double, double>(const Grid &, const double *, const double *,
+                                                           const double *, const int32_t *, size_t, double *,
+                                                           hipStream_t);
+template bo_status slot_col0_residual_perm<float, float>(const Grid &, const double *, const double *,
+                                                         const float *, const int32_t *, size_t, float *,
+                                                         hipStream_t);
 
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s) {

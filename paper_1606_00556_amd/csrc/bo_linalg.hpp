@@ -6,10 +6,13 @@ namespace bo {
 
 bo_status slot_spmv(const Grid &g, const double *A, double alpha, const double *x, double beta, double *y,
                     hipStream_t s);
-bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, const double *dp, double *r,
-                             hipStream_t s);
-bo_status slot_col0_residual_perm(const Grid &g, const double *A, const double *v, const double *dp,
-                                  const int32_t *slot_of, size_t S, double *out, hipStream_t s);
+// r = v - A (Pi_p dp) (FP64 arithmetic; dp FP64 or FP32, r stored as TO)
+template <typename TD, typename TO>
+bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, const TD *dp, TO *r, hipStream_t s);
+// the same, written in the F stage's slot order
+template <typename TD, typename TO>
+bo_status slot_col0_residual_perm(const Grid &g, const double *A, const double *v, const TD *dp,
+                                  const int32_t *slot_of, size_t S, TO *out, hipStream_t s);
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s);
 bo_status axpby(long long n, double a, const double *x, double b, double *y, hipStream_t s);

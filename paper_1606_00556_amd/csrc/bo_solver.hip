@@ -25,8 +25,13 @@ bo_status qi_restrict(bo_cpr *pc, const double *v, double *rp, hipStream_t s);
 bo_status amg_setup(bo_cpr *pc, hipStream_t s);
 bo_status amg_vcycle(bo_cpr *pc, const double *b, double *x, hipStream_t s);
 bo_status amg_vcycle_ptr(bo_cpr *pc, const double *b, const double **res, hipStream_t s);
+bo_status amg_vcycle_ptr_f32(bo_cpr *pc, const float *b, const float **res, hipStream_t s);
+bo_status amg_make_f32(bo_cpr *pc, hipStream_t s);
+bo_status qi_restrict_f32(bo_cpr *pc, const double *v, float *rp, hipStream_t s);
 bo_status fstage_setup(bo_cpr *pc, hipStream_t s);
 bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, bool r_in_slots, hipStream_t s);
+bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, bool r_in_slots,
+                             hipStream_t s);
 size_t fstage_slots(const bo_cpr *pc);
 
 namespace {
@@ -36,40 +41,61 @@ __global__ void k_check_finite(long long n, const double *__restrict__ v, int32_
     if (i < n && !isfinite(v[i])) *bad = 1;
 }
 
-__global__ void k_add_p(long long n, const double *__restrict__ dp, double *__restrict__ z) {
+template <typename TD>
+__global__ void k_add_p(long long n, const TD *__restrict__ dp, double *__restrict__ z) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) z[3 * i] = z[3 * i] + dp[i];
+    if (i < n) z[3 * i] = z[3 * i] + (double)dp[i];
 }
 
 }  // namespace
 
+// the pressure stage: Pi_r v -> one V-cycle; *dp points at the result in the
+// hierarchy's precision (FP64, or FP32 in the mixed form)
+static bo_status pressure_stage(bo_cpr *pc, const double *v, const void **dp, hipStream_t s) {
+    if (pc->o.precision == BO_PREC_FP64) {
+        BO_TRY(qi_restrict(pc, v, pc->rp_.p, s));
+        return amg_vcycle_ptr(pc, pc->rp_.p, (const double **)dp, s);
+    }
+    float *b32 = pc->lv[0].b32.p;
+    BO_TRY(qi_restrict_f32(pc, v, b32, s));
+    return amg_vcycle_ptr_f32(pc, b32, (const float **)dp, s);
+}
+
 bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     long long n = pc->n;
     const Grid &g = pc->g;
+    const bool mixed = pc->o.precision != BO_PREC_FP64;
     if (!pc->o.fpf) {
-        if (pc->o.use_amg) {
-            const double *dp;
-            BO_TRY(qi_restrict(pc, v, pc->rp_.p, s));
-            BO_TRY(amg_vcycle_ptr(pc, pc->rp_.p, &dp, s));
-            if (pc->o.ftype == BO_F_ILU_TILED) {
-                // the residual goes straight into the F stage's slot order
-                BO_TRY(slot_col0_residual_perm(g, pc->A.p, v, dp, pc->ilu_slot.p, fstage_slots(pc), pc->ilu_r.p, s));
-                return fstage_apply(pc, nullptr, dp, z, true, s);
+        if (!pc->o.use_amg) return fstage_apply(pc, v, nullptr, z, false, s);
+        const void *dp;
+        BO_TRY(pressure_stage(pc, v, &dp, s));
+        if (pc->o.ftype == BO_F_ILU_TILED) {
+            // the residual goes straight into the F stage's slot order
+            if (mixed) {
+                BO_TRY(slot_col0_residual_perm(g, pc->A.p, v, (const float *)dp, pc->ilu_slot.p, fstage_slots(pc),
+                                               pc->ilu_r32.p, s));
+                return fstage_apply_f32dp(pc, nullptr, (const float *)dp, z, true, s);
             }
-            BO_TRY(slot_col0_residual(g, pc->A.p, v, dp, pc->t3a.p, s));
-            return fstage_apply(pc, pc->t3a.p, dp, z, false, s);
+            BO_TRY(slot_col0_residual_perm(g, pc->A.p, v, (const double *)dp, pc->ilu_slot.p, fstage_slots(pc),
+                                           pc->ilu_r.p, s));
+            return fstage_apply(pc, nullptr, (const double *)dp, z, true, s);
         }
-        return fstage_apply(pc, v, nullptr, z, false, s);
+        if (mixed) {
+            BO_TRY(slot_col0_residual(g, pc->A.p, v, (const float *)dp, pc->t3a.p, s));
+            return fstage_apply_f32dp(pc, pc->t3a.p, (const float *)dp, z, false, s);
+        }
+        BO_TRY(slot_col0_residual(g, pc->A.p, v, (const double *)dp, pc->t3a.p, s));
+        return fstage_apply(pc, pc->t3a.p, (const double *)dp, z, false, s);
     }
     // FPF
     BO_TRY(fstage_apply(pc, v, nullptr, z, false, s));
     if (pc->o.use_amg) {
         BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
         BO_TRY(slot_spmv(g, pc->A.p, -1.0, z, 1.0, pc->t3a.p, s));
-        const double *dp;
-        BO_TRY(qi_restrict(pc, pc->t3a.p, pc->rp_.p, s));
-        BO_TRY(amg_vcycle_ptr(pc, pc->rp_.p, &dp, s));
-        k_add_p<<<grid_for(n), kBlock, 0, s>>>(n, dp, z);
+        const void *dp;
+        BO_TRY(pressure_stage(pc, pc->t3a.p, &dp, s));
+        if (mixed) k_add_p<float><<<grid_for(n), kBlock, 0, s>>>(n, (const float *)dp, z);
+        else k_add_p<double><<<grid_for(n), kBlock, 0, s>>>(n, (const double *)dp, z);
         BO_HIP(hipGetLastError());
     }
     BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
@@ -125,7 +151,10 @@ static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_o
     if (bad) return fail(BO_ERR_NONFINITE, "bo_cpr_setup: the matrix holds NaN or Inf");
     BO_TRY(bsr_to_slots(pc->g, A->rowptr, A->colind, A->val, pc->A.p, s));
     BO_TRY(qi_decouple(pc, s));
-    if (pc->o.use_amg) BO_TRY(amg_setup(pc, s));
+    if (pc->o.use_amg) {
+        BO_TRY(amg_setup(pc, s));
+        if (pc->o.precision != BO_PREC_FP64) BO_TRY(amg_make_f32(pc, s));
+    }
     BO_TRY(fstage_setup(pc, s));
     BO_TRY(pc->rp_.alloc(n));
     BO_TRY(pc->dp_.alloc(n));
@@ -160,8 +189,8 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown smoother");
     if (o.qi_mode != BO_QI_DIAG && o.qi_mode != BO_QI_BLOCK)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown quasi-IMPES mode");
-    if (o.precision != BO_PREC_FP64)
-        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: this precision is not available");
+    if (o.precision != BO_PREC_FP64 && o.precision != BO_PREC_FP32 && o.precision != BO_PREC_FP32_BF16)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown precision");
     bo_cpr *pc = new (std::nothrow) bo_cpr();
     if (!pc) return fail(BO_ERR_ALLOC, "bo_cpr_setup: out of host memory");
     bo_status st = setup_impl(A, grid, opts, pc, (hipStream_t)stream);

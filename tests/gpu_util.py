@@ -46,7 +46,7 @@ def rel_err(a, b):
 
 
 def matching_opts(O, B, ftype="tiled", fpf=0, tile=(8, 8), coarse_max=256, smoother="gs", sweeps=1,
-                  use_amg=1, qi="block", theta=0.08):
+                  use_amg=1, qi="block", theta=0.08, precision="fp64"):
     """The same CPR configuration for the oracle and the library."""
     oft = dict(tiled=O.F_ILU_TILED, bj=O.F_BJ)[ftype]
     bft = dict(tiled=B.BO_F_ILU_TILED, bj=B.BO_F_BJ)[ftype]
@@ -54,11 +54,44 @@ def matching_opts(O, B, ftype="tiled", fpf=0, tile=(8, 8), coarse_max=256, smoot
     bsm = dict(gs=B.BO_SMOOTH_GS, jacobi=B.BO_SMOOTH_JACOBI)[smoother]
     oqi = dict(block=O.QI_BLOCK, diag=O.QI_DIAG)[qi]
     bqi = dict(block=B.BO_QI_BLOCK, diag=B.BO_QI_DIAG)[qi]
+    opr = dict(fp64=O.PREC_FP64, fp32=O.PREC_FP32, bf16=O.PREC_FP32_BF16)[precision]
+    bpr = dict(fp64=B.BO_PREC_FP64, fp32=B.BO_PREC_FP32, bf16=B.BO_PREC_FP32_BF16)[precision]
     oo = O.cpr_opts(fpf=fpf, ftype=oft, tile=tile, theta=theta, coarse_max=coarse_max, smoother=osm,
-                    sweeps=sweeps, use_amg=use_amg, qi_mode=oqi)
+                    sweeps=sweeps, use_amg=use_amg, qi_mode=oqi, precision=opr)
     bo = B.bo_cpr_default_opts(fpf=fpf, ftype=bft, tile=tile, theta=theta, coarse_max=coarse_max,
-                               smoother=bsm, sweeps=sweeps, use_amg=use_amg, qi_mode=bqi)
+                               smoother=bsm, sweeps=sweeps, use_amg=use_amg, qi_mode=bqi, precision=bpr)
     return oo, bo
+
+
+def setup_both(B, O, case, **kw):
+    """The oracle's and the library's CPR for the same case and options."""
+    P, rp, ci, val, b = oracle_system(O, case)
+    oo, bo_ = matching_opts(O, B, **kw)
+    opc = O.Cpr(P, rp, ci, val, oo)
+    A = device_bsr(B, rp, ci, val)
+    gpc = B.bo_cpr_setup(A, (case.nx, case.ny, case.nz), bo_)
+    return P, rp, ci, val, b, opc, gpc
+
+
+def run_stage(B, gpc, fn, v, m):
+    """Calls one stage entry point (fn(handle, in, out)) on a host vector."""
+    import torch
+    out = torch.zeros(m, dtype=torch.float64, device="cuda")
+    fn(gpc, to_dev(v), out)
+    return to_host(out)
+
+
+def solve_both(B, O, case, **kw):
+    """FGMRES with the oracle and with the library; the GPU solution's true
+    residual is measured with the oracle's SpMV."""
+    import torch
+    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case, **kw)
+    xo, oinfo = O.fgmres(rp, ci, val, b, opc)
+    x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+    ginfo = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    xg = to_host(x)
+    r = b - O.bsr_spmv(rp, ci, val, xg)
+    return oinfo, ginfo, np.linalg.norm(r) / np.linalg.norm(b), xg, xo
 
 
 def ragged_case(seed=21):

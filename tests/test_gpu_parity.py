@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 import bo_casegen as cg
-from tests.gpu_util import (device_bsr, matching_opts, oracle_system, ragged_case, rel_err, to_dev, to_host)
+from tests.gpu_util import (device_bsr, matching_opts, oracle_system, ragged_case, rel_err, run_stage, setup_both,
+                            solve_both, to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -109,15 +110,6 @@ def test_spmv_axpby_random(B, O):
     assert rel_err(to_host(y), ref) <= 1e-12
 
 
-def setup_both(B, O, case, **kw):
-    P, rp, ci, val, b = oracle_system(O, case)
-    oo, bo_ = matching_opts(O, B, **kw)
-    opc = O.Cpr(P, rp, ci, val, oo)
-    A = device_bsr(B, rp, ci, val)
-    gpc = B.bo_cpr_setup(A, (case.nx, case.ny, case.nz), bo_)
-    return P, rp, ci, val, b, opc, gpc
-
-
 def test_decoupling_weights_bitwise(B, O):
     case = cg.make_case(0)
     _, _, _, _, _, opc, gpc = setup_both(B, O, case)
@@ -142,13 +134,6 @@ def test_amg_hierarchy_matches_oracle(B, O, name):
             assert np.array_equal(gl["p_colind"], ol["p_colind"])
             assert rel_err(gl["p_val"], ol["p_val"]) <= 1e-12
             assert gl["omega"] == pytest.approx(ol["omega"], rel=1e-14)
-
-
-def run_stage(B, gpc, fn, v, m):
-    import torch
-    out = torch.zeros(m, dtype=torch.float64, device="cuda")
-    fn(gpc, to_dev(v), out)
-    return to_host(out)
 
 
 @pytest.mark.parametrize("name", ["ragged", "cfg0", "line"])
@@ -186,18 +171,6 @@ def test_ilu_pivots_bitwise(B, O):
     v[0] = 1.0
     x = run_stage(B, gpc, B.bo_cpr_fstage, v, 3 * case.n)
     assert rel_err(x, opc.fstage(v)) <= 1e-13
-
-
-def solve_both(B, O, case, **kw):
-    import torch
-    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case, **kw)
-    xo, oinfo = O.fgmres(rp, ci, val, b, opc)
-    x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-    ginfo = B.bo_fgmres_solve(gpc, to_dev(b), x)
-    xg = to_host(x)
-    # true residual measured independently with the oracle's SpMV
-    r = b - O.bsr_spmv(rp, ci, val, xg)
-    return oinfo, ginfo, np.linalg.norm(r) / np.linalg.norm(b), xg, xo
 
 
 @pytest.mark.parametrize("name", ["ragged", "cfg0"])
