@@ -109,12 +109,14 @@ typedef struct {
     int tile_x, tile_y;   /* tiled ILU0 */
     double theta;         /* strength threshold */
     int coarse_max, max_levels;
-    int smoother;         /* OR_SMOOTH_* on level 0 (levels >= 1: damped Jacobi) */
+    int smoother;         /* OR_SMOOTH_* on level 0 */
     int sweeps;           /* pre = post sweeps */
     int use_amg;          /* 0: pressure stage skipped (F only) */
     int qi_mode;          /* OR_QI_DIAG or OR_QI_BLOCK */
     int precision;        /* OR_PREC_*: mixed-precision emulation of the inner stages */
+    int csmoother;        /* OR_CSMOOTH_* on levels >= 1 */
 } or_cpr_opts;
+enum { OR_CSMOOTH_JACOBI = 0, OR_CSMOOTH_L1 = 1 };
 
 /* Mixed precision (emulated): OR_PREC_FP32 stores the AMG hierarchy and the F
  * stage's factors rounded to FP32 and runs the V-cycle and the F-stage sweeps

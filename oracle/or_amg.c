@@ -22,7 +22,9 @@
  *   cycle        V(s,s) from a zero guess.  Level 0 of a grid: red-black
  *                Gauss-Seidel by (i+j+k) mod 2, red then black before the
  *                coarse correction and black then red after it (or damped
- *                Jacobi); coarser levels: damped Jacobi, omega = 2/3; coarsest
+ *                Jacobi); coarser levels: l1-Jacobi, x += (b - A x) / sum_j
+ *                |a_ij| (the l1 smoother of hypre's BoomerAMG, the AMG the
+ *                paper uses), or damped Jacobi with omega = 2/3; coarsest
  *                level by dense LU with partial pivoting.
  * fmix32 is the public MurmurHash3 finaliser.
  */
@@ -279,6 +281,7 @@ void or_amg_free(or_amg *h)
     for (int l = 0; l < OR_MAXLEV; l++) {
         or_csr_free(&h->A[l]); or_csr_free(&h->P[l]); or_csr_free(&h->R[l]);
         free(h->agg[l]); free(h->sf[l]); free(h->color[l]); free(h->root[l]);
+        free(h->dl1[l]); free(h->dl132[l]);
     }
     for (int l = 0; l < OR_MAXLEV; l++) { free(h->A32[l]); free(h->P32[l]); free(h->R32[l]); }
     free(h->cinv32);
@@ -287,10 +290,10 @@ void or_amg_free(or_amg *h)
 }
 
 int or_amg_setup(or_amg *h, const or_csr *A0, int nx, int ny, int nz, double theta,
-                 int coarse_max, int max_levels, int smoother, int sweeps)
+                 int coarse_max, int max_levels, int smoother, int sweeps, int csmoother)
 {
     memset(h, 0, sizeof *h);
-    h->smoother = smoother; h->sweeps = sweeps;
+    h->smoother = smoother; h->sweeps = sweeps; h->csmoother = csmoother;
     if (max_levels > OR_MAXLEV) max_levels = OR_MAXLEV;
     if (max_levels < 1) max_levels = 1;
     or_csr *A = &h->A[0];
@@ -329,6 +332,16 @@ int or_amg_setup(or_amg *h, const or_csr *A0, int nx, int ny, int nz, double the
         if (st) return st;
     }
     h->nlev = l + 1;
+    /* l1 row norms, ascending column order */
+    for (int q = 0; q < h->nlev; q++) {
+        const or_csr *Aq = &h->A[q];
+        h->dl1[q] = malloc(sizeof(double) * (size_t)(Aq->n > 0 ? Aq->n : 1));
+        for (int i = 0; i < Aq->n; i++) {
+            double s = 0.0;
+            for (int e = Aq->rp[i]; e < Aq->rp[i + 1]; e++) s += fabs(Aq->v[e]);
+            h->dl1[q][i] = s;
+        }
+    }
     /* Gauss-Seidel colours exist only for level 0 of a grid: red-black */
     if (nx > 0 && nx * ny * nz == h->A[0].n) {
         int n = h->A[0].n;
@@ -380,8 +393,18 @@ static void smooth(const or_amg *h, int l, const double *b, double *x, int forwa
     const or_csr *A = &h->A[l];
     int n = A->n;
     int kind = l == 0 ? h->smoother : OR_SMOOTH_JACOBI;
+    int l1 = l > 0 && h->csmoother == OR_CSMOOTH_L1;
     for (int sw = 0; sw < h->sweeps; sw++) {
-        if (kind == OR_SMOOTH_JACOBI) {
+        if (l1) {
+            double *t = malloc(sizeof(double) * (size_t)n);
+            for (int i = 0; i < n; i++) {
+                double s = 0.0;
+                for (int e = A->rp[i]; e < A->rp[i + 1]; e++) s += A->v[e] * x[A->ci[e]];
+                t[i] = x[i] + (b[i] - s) / h->dl1[l][i];
+            }
+            memcpy(x, t, sizeof(double) * (size_t)n);
+            free(t);
+        } else if (kind == OR_SMOOTH_JACOBI) {
             double *t = malloc(sizeof(double) * (size_t)n);
             for (int i = 0; i < n; i++) {
                 double s = 0.0, d = 0.0;
@@ -467,6 +490,7 @@ int or_amg_make_f32(or_amg *h)
 {
     for (int l = 0; l < h->nlev; l++) {
         h->A32[l] = round_f32(h->A[l].v, (size_t)h->A[l].nnz);
+        h->dl132[l] = round_f32(h->dl1[l], (size_t)h->A[l].n);
         if (l < h->nlev - 1) {
             h->P32[l] = round_f32(h->P[l].v, (size_t)h->P[l].nnz);
             h->R32[l] = round_f32(h->R[l].v, (size_t)h->R[l].nnz);
@@ -509,9 +533,19 @@ static void smooth_f32(const or_amg *h, int l, const float *b, float *x, int for
     const float *v = h->A32[l];
     int n = A->n;
     int kind = l == 0 ? h->smoother : OR_SMOOTH_JACOBI;
+    int l1 = l > 0 && h->csmoother == OR_CSMOOTH_L1;
     const float w = (float)(2.0 / 3.0);
     for (int sw = 0; sw < h->sweeps; sw++) {
-        if (kind == OR_SMOOTH_JACOBI) {
+        if (l1) {
+            float *t = malloc(sizeof(float) * (size_t)n);
+            for (int i = 0; i < n; i++) {
+                float s = 0.0f;
+                for (int e = A->rp[i]; e < A->rp[i + 1]; e++) s += v[e] * x[A->ci[e]];
+                t[i] = x[i] + (b[i] - s) / h->dl132[l][i];
+            }
+            memcpy(x, t, sizeof(float) * (size_t)n);
+            free(t);
+        } else if (kind == OR_SMOOTH_JACOBI) {
             float *t = malloc(sizeof(float) * (size_t)n);
             for (int i = 0; i < n; i++) {
                 float s = 0.0f, d = 0.0f;

@@ -21,6 +21,9 @@ typedef struct {
     double *dense;              /* coarsest matrix, row-major, when solved directly */
     int coarse_direct;
     int smoother, sweeps;
+    int csmoother;              /* levels >= 1: OR_CSMOOTH_* */
+    double *dl1[OR_MAXLEV];     /* l1 row norms sum_j |a_ij| of each level */
+    float *dl132[OR_MAXLEV];    /* their FP32 roundings (mixed form) */
     /* mixed-precision emulation: FP32 copies of the level operators, P, R and
      * the coarsest inverse (NULL until or_amg_make_f32) */
     float *A32[OR_MAXLEV], *P32[OR_MAXLEV], *R32[OR_MAXLEV];
@@ -28,7 +31,7 @@ typedef struct {
 } or_amg;
 
 int or_amg_setup(or_amg *h, const or_csr *A0, int nx, int ny, int nz, double theta,
-                 int coarse_max, int max_levels, int smoother, int sweeps);
+                 int coarse_max, int max_levels, int smoother, int sweeps, int csmoother);
 void or_amg_vcycle(const or_amg *h, const double *b, double *x);
 void or_amg_free(or_amg *h);
 int or_amg_make_f32(or_amg *h);

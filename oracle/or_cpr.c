@@ -288,7 +288,7 @@ int or_cpr_setup(const or_problem *p, int n, const int32_t *rowptr, const int32_
         or_csr A0 = { n, n, nnzb, (int32_t *)rowptr, (int32_t *)colind, app };
         int nx = p ? p->nx : 0, ny = p ? p->ny : 0, nz = p ? p->nz : 0;
         st = or_amg_setup(&c->amg, &A0, nx, ny, nz, o->theta, o->coarse_max, o->max_levels,
-                          o->smoother, o->sweeps);
+                          o->smoother, o->sweeps, o->csmoother);
         c->has_amg = 1;
         if (st) { free(app); or_cpr_free(c); return st; }
     }

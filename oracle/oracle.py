@@ -20,6 +20,7 @@ F_BJ, F_ILU_NATURAL, F_ILU_RB, F_ILU_TILED = 0, 1, 2, 3
 QI_DIAG, QI_BLOCK = 0, 1
 SMOOTH_GS, SMOOTH_JACOBI = 0, 1
 PREC_FP64, PREC_FP32, PREC_FP32_BF16 = 0, 1, 2
+CSMOOTH_JACOBI, CSMOOTH_L1 = 0, 1
 
 _i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
@@ -51,7 +52,7 @@ class CprOpts(C.Structure):
     _fields_ = [("fpf", C.c_int), ("ftype", C.c_int), ("tile_x", C.c_int), ("tile_y", C.c_int),
                 ("theta", C.c_double), ("coarse_max", C.c_int), ("max_levels", C.c_int),
                 ("smoother", C.c_int), ("sweeps", C.c_int), ("use_amg", C.c_int), ("qi_mode", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("csmoother", C.c_int)]
 
 
 class FgmresOpts(C.Structure):
@@ -261,10 +262,12 @@ def qi_decouple(rp, ci, val, mode=1):
 
 
 def cpr_opts(fpf=0, ftype=F_ILU_TILED, tile=(8, 8), theta=0.08, coarse_max=256, max_levels=12,
-             smoother=SMOOTH_GS, sweeps=1, use_amg=1, qi_mode=QI_BLOCK, precision=0) -> CprOpts:
-    """precision: PREC_FP64, or the emulated mixed forms PREC_FP32 / PREC_FP32_BF16."""
+             smoother=SMOOTH_GS, sweeps=1, use_amg=1, qi_mode=QI_BLOCK, precision=0,
+             csmoother=1) -> CprOpts:
+    """precision: PREC_FP64, or the emulated mixed forms PREC_FP32 / PREC_FP32_BF16;
+    csmoother: CSMOOTH_L1 (default) or CSMOOTH_JACOBI on the coarse levels."""
     return CprOpts(fpf, ftype, tile[0], tile[1], theta, coarse_max, max_levels, smoother,
-                   sweeps, use_amg, qi_mode, precision)
+                   sweeps, use_amg, qi_mode, precision, csmoother)
 
 
 class Cpr:
