@@ -128,6 +128,11 @@ bo_status bo_bsr_spmv(const bo_bsr *A, double alpha, const double *x, double bet
 
 enum { BO_F_BJ = 0, BO_F_ILU_TILED = 3 };          /* F stage: block Jacobi / tiled block ILU(0) */
 enum { BO_SMOOTH_GS = 0, BO_SMOOTH_JACOBI = 1 };   /* level-0 smoother */
+/* smoother of the levels between the finest and the coarsest: l1-Jacobi,
+ * x += (b - A x) / sum_j |a_ij| (hypre's l1 smoother, robust where Galerkin
+ * products of a high-contrast pressure matrix lose diagonal dominance), or
+ * damped Jacobi, x += (2/3)(b - A x) / a_ii */
+enum { BO_CSMOOTH_JACOBI = 0, BO_CSMOOTH_L1 = 1 };
 enum { BO_QI_DIAG = 0, BO_QI_BLOCK = 1 };          /* quasi-IMPES weights */
 /* Precision of the preconditioner's inner stages.  BO_PREC_FP64: everything
  * FP64.  BO_PREC_FP32: the AMG hierarchy (level operators, P, R, coarsest
@@ -147,15 +152,17 @@ typedef struct {
     double theta;           /* AMG strength threshold */
     int32_t coarse_max;     /* coarsest level size bound (<= 1024) */
     int32_t max_levels;     /* <= 16 */
-    int32_t smoother;       /* level 0: BO_SMOOTH_GS (red-black) or BO_SMOOTH_JACOBI; coarser: Jacobi */
+    int32_t smoother;       /* level 0: BO_SMOOTH_GS (red-black) or BO_SMOOTH_JACOBI */
     int32_t sweeps;         /* pre- and post-smoothing sweeps */
     int32_t use_amg;        /* 0: no pressure stage */
     int32_t qi_mode;        /* BO_QI_* */
     int32_t precision;      /* BO_PREC_*: storage/arithmetic of the AMG hierarchy and ILU factors */
+    int32_t csmoother;      /* BO_CSMOOTH_*: levels between the finest and the coarsest */
 } bo_cpr_opts;
 
 /* Fills `o` [host] with the defaults: PF, tiled ILU0 8x8, theta 0.08,
- * coarse_max 256, 12 levels, red-black GS, 1 sweep, AMG on, block QI, FP64. */
+ * coarse_max 256, 12 levels, red-black GS, 1 sweep, AMG on, block QI, FP64,
+ * l1-Jacobi on the coarse levels. */
 void bo_cpr_default_opts(bo_cpr_opts *o);
 
 typedef struct bo_cpr bo_cpr;

@@ -22,6 +22,7 @@ BO_F_BJ, BO_F_ILU_TILED = 0, 3
 BO_SMOOTH_GS, BO_SMOOTH_JACOBI = 0, 1
 BO_QI_DIAG, BO_QI_BLOCK = 0, 1
 BO_PREC_FP64, BO_PREC_FP32, BO_PREC_FP32_BF16 = 0, 1, 2
+BO_CSMOOTH_JACOBI, BO_CSMOOTH_L1 = 0, 1
 
 EXPORTS = [
     "bo_last_error", "bo_version", "bo_jacobian_bsr_size", "bo_jacobian_bsr", "bo_bsr_spmv",
@@ -68,7 +69,7 @@ class BoCprOpts(C.Structure):
     _fields_ = [("fpf", C.c_int32), ("ftype", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
                 ("theta", C.c_double), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("smoother", C.c_int32), ("sweeps", C.c_int32), ("use_amg", C.c_int32),
-                ("qi_mode", C.c_int32), ("precision", C.c_int32)]
+                ("qi_mode", C.c_int32), ("precision", C.c_int32), ("csmoother", C.c_int32)]
 
 
 class BoGrid(C.Structure):

@@ -120,8 +120,9 @@ __device__ __forceinline__ int find_col(const int32_t *ci, int lo, int hi, int c
     return -1;
 }
 
+// diagonal position and l1 row norm sum_j |a_ij| (ascending columns) of each row
 __global__ void k_diag(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                       const double *__restrict__ v, int32_t *__restrict__ dpos, double *__restrict__ dinv,
+                       const double *__restrict__ v, int32_t *__restrict__ dpos, double *__restrict__ dl1,
                        int32_t *__restrict__ bad) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -129,7 +130,9 @@ __global__ void k_diag(int n, const int32_t *__restrict__ rp, const int32_t *__r
     dpos[i] = p;
     double d = p >= 0 ? v[p] : 0.0;
     if (d == 0.0 || !isfinite(d)) *bad = 1;
-    dinv[i] = d != 0.0 ? 1.0 / d : 0.0;
+    double s = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; e++) s = s + fabs(v[e]);
+    dl1[i] = s;
 }
 
 // G lanes per row, each entry on its own
@@ -780,19 +783,26 @@ __global__ void __launch_bounds__(kBlock) k_resid_slots(int nx, int ny, int nz, 
 // CSR row operations on coarse levels: G lanes per row (G a power of two
 // dividing 64) sum the row's products in strides of G and combine them with
 // cross-lane shuffles.
-enum { OP_MV = 0, OP_RESID = 1, OP_ADD = 2, OP_JACOBI = 3, OP_JACOBI0 = 4 };
+// OP_JACOBI: damped Jacobi sweep, y = x + (2/3)(b - A x) / a_ii; OP_L1: l1-Jacobi
+// sweep, y = x + (b - A x) / sum_j |a_ij|; the *0 forms start from x = 0.
+enum { OP_MV = 0, OP_RESID = 1, OP_ADD = 2, OP_JACOBI = 3, OP_JACOBI0 = 4, OP_L1 = 5, OP_L10 = 6 };
 
 template <int G, typename T>
 __global__ void __launch_bounds__(kBlock) k_csr_rowop(int n, const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ ci, const T *__restrict__ v,
                                                       const T *__restrict__ x, int op, const T *__restrict__ b,
-                                                      const int32_t *__restrict__ dpos, T *__restrict__ y) {
+                                                      const int32_t *__restrict__ dpos, const T *__restrict__ dl1,
+                                                      T *__restrict__ y) {
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
     int row = gid / G, sub = gid % G;
     if (row >= n) return;  // whole groups leave together
     if (op == OP_JACOBI0) {
         // one damped Jacobi sweep from a zero guess
         if (sub == 0) y[row] = two_thirds<T>() * (b[row] / v[dpos[row]]);
+        return;
+    }
+    if (op == OP_L10) {
+        if (sub == 0) y[row] = b[row] / dl1[row];
         return;
     }
     T s = 0;
@@ -804,6 +814,7 @@ __global__ void __launch_bounds__(kBlock) k_csr_rowop(int n, const int32_t *__re
     case OP_MV: y[row] = s; break;
     case OP_RESID: y[row] = b[row] - s; break;
     case OP_ADD: y[row] = y[row] + s; break;
+    case OP_L1: y[row] = x[row] + (b[row] - s) / dl1[row]; break;
     default: {
         T d = v[dpos[row]];
         y[row] = x[row] + two_thirds<T>() * ((b[row] - s) / d);
@@ -853,12 +864,12 @@ bo_status read_flag(int32_t *dflag, hipStream_t s, int32_t *out) {
 // y = op(A x) for a CSR matrix with nnz entries over n rows (see k_csr_rowop)
 template <typename T>
 static bo_status csr_rowop(int n, int nnz, const int32_t *rp, const int32_t *ci, const T *v, const T *x, int op,
-                           const T *b, const int32_t *dpos, T *y, hipStream_t s) {
+                           const T *b, const int32_t *dpos, T *y, hipStream_t s, const T *dl1 = nullptr) {
     double avg = n > 0 ? (double)nnz / n : 1.0;
     long long threads;
 #define BO_ROWOP(G)                                                                                  \
     threads = (long long)n * G;                                                                      \
-    k_csr_rowop<G, T><<<grid_for(threads), kBlock, 0, s>>>(n, rp, ci, v, x, op, b, dpos, y)
+    k_csr_rowop<G, T><<<grid_for(threads), kBlock, 0, s>>>(n, rp, ci, v, x, op, b, dpos, dl1, y)
     if (avg <= 6.0) { BO_ROWOP(4); }
     else if (avg <= 12.0) { BO_ROWOP(8); }
     else if (avg <= 24.0) { BO_ROWOP(16); }
@@ -908,9 +919,9 @@ bo_status qi_restrict_f32(bo_cpr *pc, const double *v, float *rp, hipStream_t s)
 // ---- host: hierarchy ---------------------------------------------------------------
 static bo_status level_diag(Level &L, int32_t *flag, hipStream_t s) {
     BO_TRY(L.diagpos.alloc(L.n));
-    BO_TRY(L.dinv.alloc(L.n));
+    BO_TRY(L.dl1.alloc(L.n));
     BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    k_diag<<<grid_for(L.n), kBlock, 0, s>>>(L.n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.dinv.p, flag);
+    k_diag<<<grid_for(L.n), kBlock, 0, s>>>(L.n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.dl1.p, flag);
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
     BO_TRY(read_flag(flag, s, &bad));
@@ -1128,6 +1139,7 @@ template <> struct Prec<double> {
     static double *b(Level &L) { return L.b.p; }
     static double *r(Level &L) { return L.r.p; }
     static double *t(Level &L) { return L.t.p; }
+    static const double *dl1(const Level &L) { return L.dl1.p; }
     static const double *app(const bo_cpr *pc) { return pc->app.p; }
     static const double *cinv(const bo_cpr *pc) { return pc->cinv.p; }
 };
@@ -1139,6 +1151,7 @@ template <> struct Prec<float> {
     static float *b(Level &L) { return L.b32.p; }
     static float *r(Level &L) { return L.r32.p; }
     static float *t(Level &L) { return L.t32.p; }
+    static const float *dl1(const Level &L) { return L.dl132.p; }
     static const float *app(const bo_cpr *pc) { return pc->app32.p; }
     static const float *cinv(const bo_cpr *pc) { return pc->cinv32.p; }
 };
@@ -1164,20 +1177,22 @@ static bo_status smooth0(bo_cpr *pc, const T *b, T *x, bool forward, hipStream_t
     return BO_OK;
 }
 
-// coarse-level damped Jacobi; `x` holds the guess (NULL: zero) and the
-// result is returned in one of x / t
+// coarse-level l1-Jacobi or damped Jacobi; `x` holds the guess (NULL: zero)
+// and the result is returned in one of x / t
 template <typename T>
-static bo_status smooth_c(Level &L, int sweeps, const T *b, T *x, T **res, hipStream_t s) {
+static bo_status smooth_c(Level &L, int sweeps, bool l1, const T *b, T *x, T **res, hipStream_t s) {
     T *cur = x, *oth = Prec<T>::t(L);
+    const T *d = Prec<T>::dl1(L);
     int first = 0;
     if (!x) {
-        BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), nullptr, OP_JACOBI0, b, L.diagpos.p,
-                            Prec<T>::x(L), s));
+        BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), nullptr, l1 ? OP_L10 : OP_JACOBI0, b,
+                            L.diagpos.p, Prec<T>::x(L), s, d));
         cur = Prec<T>::x(L);
         first = 1;
     }
     for (int sw = first; sw < sweeps; sw++) {
-        BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), cur, OP_JACOBI, b, L.diagpos.p, oth, s));
+        BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), cur, l1 ? OP_L1 : OP_JACOBI, b, L.diagpos.p,
+                            oth, s, d));
         std::swap(cur, oth);
     }
     *res = cur;
@@ -1202,7 +1217,7 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t 
         k_resid_slots<T><<<grid_for(L.n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, Prec<T>::app(pc), b, x,
                                                            Prec<T>::r(L));
     } else {
-        BO_TRY(smooth_c<T>(L, pc->o.sweeps, b, nullptr, &x, s));
+        BO_TRY(smooth_c<T>(L, pc->o.sweeps, pc->o.csmoother == BO_CSMOOTH_L1, b, nullptr, &x, s));
         BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), x, OP_RESID, b, nullptr, Prec<T>::r(L), s));
     }
     Level &C = pc->lv[l + 1];
@@ -1215,7 +1230,7 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t 
         BO_TRY(smooth0<T>(pc, b, x, false, s));
         *res = x;
     } else {
-        BO_TRY(smooth_c<T>(L, pc->o.sweeps, b, x, res, s));
+        BO_TRY(smooth_c<T>(L, pc->o.sweeps, pc->o.csmoother == BO_CSMOOTH_L1, b, x, res, s));
     }
     return BO_OK;
 }
@@ -1264,6 +1279,10 @@ bo_status amg_make_f32(bo_cpr *pc, hipStream_t s) {
         if (l > 0) {
             BO_TRY(L.v32.alloc(L.nnz));
             BO_TRY(to_f32(L.nnz, L.v.p, L.v32.p, s));
+        }
+        if (l > 0 && l + 1 < pc->nlev) {
+            BO_TRY(L.dl132.alloc(L.n));
+            BO_TRY(to_f32(L.n, L.dl1.p, L.dl132.p, s));
         }
         if (l + 1 < pc->nlev) {
             BO_TRY(L.pv32.alloc(L.pnnz)); BO_TRY(L.rv32.alloc(L.pnnz));

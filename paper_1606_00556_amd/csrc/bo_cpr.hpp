@@ -15,7 +15,7 @@ struct Level {
     DBuf<int32_t> rp, ci;
     DBuf<double> v;
     DBuf<int32_t> diagpos;
-    DBuf<double> dinv;
+    DBuf<double> dl1;             // l1 row norms sum_j |a_ij|
     // transfer to level + 1
     int nc = 0, pnnz = 0;
     DBuf<int32_t> prp, pci, rrp, rci;
@@ -26,7 +26,7 @@ struct Level {
     // cycle work vectors
     DBuf<double> x, b, r, t;
     // single-precision copies (mixed form)
-    DBuf<float> v32, pv32, rv32, x32, b32, r32, t32;
+    DBuf<float> v32, pv32, rv32, x32, b32, r32, t32, dl132;
 };
 
 // setup temporaries kept with the handle, reused (grow-only) by later setups

@@ -122,6 +122,7 @@ extern "C" void bo_cpr_default_opts(bo_cpr_opts *o) {
     o->use_amg = 1;
     o->qi_mode = BO_QI_BLOCK;
     o->precision = BO_PREC_FP64;
+    o->csmoother = BO_CSMOOTH_L1;
 }
 
 extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
@@ -187,6 +188,8 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: AMG options out of range");
     if (o.smoother != BO_SMOOTH_GS && o.smoother != BO_SMOOTH_JACOBI)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown smoother");
+    if (o.csmoother != BO_CSMOOTH_JACOBI && o.csmoother != BO_CSMOOTH_L1)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown coarse-level smoother");
     if (o.qi_mode != BO_QI_DIAG && o.qi_mode != BO_QI_BLOCK)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown quasi-IMPES mode");
     if (o.precision != BO_PREC_FP64 && o.precision != BO_PREC_FP32 && o.precision != BO_PREC_FP32_BF16)

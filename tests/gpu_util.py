@@ -46,7 +46,7 @@ def rel_err(a, b):
 
 
 def matching_opts(O, B, ftype="tiled", fpf=0, tile=(8, 8), coarse_max=256, smoother="gs", sweeps=1,
-                  use_amg=1, qi="block", theta=0.08, precision="fp64"):
+                  use_amg=1, qi="block", theta=0.08, precision="fp64", csmoother="l1"):
     """The same CPR configuration for the oracle and the library."""
     oft = dict(tiled=O.F_ILU_TILED, bj=O.F_BJ)[ftype]
     bft = dict(tiled=B.BO_F_ILU_TILED, bj=B.BO_F_BJ)[ftype]
@@ -56,10 +56,13 @@ def matching_opts(O, B, ftype="tiled", fpf=0, tile=(8, 8), coarse_max=256, smoot
     bqi = dict(block=B.BO_QI_BLOCK, diag=B.BO_QI_DIAG)[qi]
     opr = dict(fp64=O.PREC_FP64, fp32=O.PREC_FP32, bf16=O.PREC_FP32_BF16)[precision]
     bpr = dict(fp64=B.BO_PREC_FP64, fp32=B.BO_PREC_FP32, bf16=B.BO_PREC_FP32_BF16)[precision]
+    ocs = dict(jacobi=O.CSMOOTH_JACOBI, l1=O.CSMOOTH_L1)[csmoother]
+    bcs = dict(jacobi=B.BO_CSMOOTH_JACOBI, l1=B.BO_CSMOOTH_L1)[csmoother]
     oo = O.cpr_opts(fpf=fpf, ftype=oft, tile=tile, theta=theta, coarse_max=coarse_max, smoother=osm,
-                    sweeps=sweeps, use_amg=use_amg, qi_mode=oqi, precision=opr)
+                    sweeps=sweeps, use_amg=use_amg, qi_mode=oqi, precision=opr, csmoother=ocs)
     bo = B.bo_cpr_default_opts(fpf=fpf, ftype=bft, tile=tile, theta=theta, coarse_max=coarse_max,
-                               smoother=bsm, sweeps=sweeps, use_amg=use_amg, qi_mode=bqi, precision=bpr)
+                               smoother=bsm, sweeps=sweeps, use_amg=use_amg, qi_mode=bqi, precision=bpr,
+                               csmoother=bcs)
     return oo, bo
 
 

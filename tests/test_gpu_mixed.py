@@ -51,7 +51,7 @@ def test_mixed_stages_match_emulation(B, O, prec, name):
 
 
 @pytest.mark.parametrize("kw", [dict(fpf=1), dict(ftype="bj"), dict(smoother="jacobi", sweeps=2),
-                                dict(tile=(5, 3)), dict(use_amg=0)])
+                                dict(tile=(5, 3)), dict(use_amg=0), dict(csmoother="jacobi")])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_mixed_variants_match_emulation(B, O, prec, kw):
     case = ragged_case(seed=31)

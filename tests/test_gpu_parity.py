@@ -152,7 +152,8 @@ def test_stages_match_oracle(B, O, name):
 
 
 @pytest.mark.parametrize("kw", [dict(fpf=1), dict(ftype="bj"), dict(smoother="jacobi", sweeps=2),
-                                dict(tile=(4, 4)), dict(tile=(5, 3)), dict(qi="diag"), dict(use_amg=0)])
+                                dict(tile=(4, 4)), dict(tile=(5, 3)), dict(qi="diag"), dict(use_amg=0),
+                                dict(csmoother="jacobi"), dict(csmoother="jacobi", sweeps=2)])
 def test_cpr_variants_match_oracle(B, O, kw):
     case = ragged_case(seed=31)
     _, _, _, _, b, opc, gpc = setup_both(B, O, case, coarse_max=40, **kw)
