@@ -298,3 +298,22 @@ def tiny_case(nx: int, ny: int, nz: int, seed: int = 7, *, sigma: float = 1.0,
     return Case(f"tiny{nx}x{ny}x{nz}", nx, ny, nz, 50.0, 50.0, 10.0, 8000.0, kx, kx.copy(),
                 kz_ratio * kx, _porosity(seed, n), x_old, x_new, dt, wells, dict(FLUID),
                 gravity=gravity)
+
+
+# ---- learned pressure-stage correction: seeded initial weights ---------------
+_F_CNN = 40
+
+
+def cnn_init(seed: int = 1606300, channels=(2, 16, 16, 16, 1), last_scale: float = 0.1):
+    """He-normal initial weights W[t, c_in, c_out] (27 taps) and zero biases
+    per layer, float32, from the counter-based generator; the last layer is
+    scaled by ``last_scale`` so that an untrained correction starts small."""
+    params = []
+    for l in range(len(channels) - 1):
+        ci, co = channels[l], channels[l + 1]
+        idx = np.arange(27 * ci * co, dtype=np.uint64)
+        w = normal(seed, _F_CNN + l, idx).reshape(27, ci, co) * math.sqrt(2.0 / (27 * ci))
+        if l == len(channels) - 2:
+            w = w * last_scale
+        params.append((w.astype(np.float32), np.zeros(co, dtype=np.float32)))
+    return params
