@@ -225,6 +225,7 @@ typedef struct {
     double est_residual;    /* last Arnoldi estimate |g_{j+1}| / ||b|| */
     double spmv_ms;         /* with opts.timing: summed duration of the timed SpMVs */
     int32_t spmv_calls;     /* with opts.timing: their number (one per iteration) */
+    int32_t nn_used;        /* with a network attached: applications whose correction was kept */
 } bo_solve_stats;
 
 /* Right-preconditioned FGMRES(m) on A x = b with the operator and
@@ -233,6 +234,58 @@ typedef struct {
  * column per iteration.  Returns BO_OK, BO_NOT_CONVERGED or an error. */
 bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, const bo_fgmres_opts *opts,
                           bo_solve_stats *stats, void *stream);
+
+/* ---- a9: learned pressure-stage correction ----------------------------
+ * Not part of the paper, which stops at AMG for the pressure block (Section
+ * 3.2); this stage adds to the V-cycle result a correction predicted by a
+ * small 3-D convolutional network and keeps it only where it lowers the
+ * pressure residual, so the plain V-cycle is always the fallback.
+ *
+ * Network: four zero-padded 3x3x3 convolutions, channels 2 -> 16 -> 16 -> 16
+ * -> 1, biases, ReLU after the first three.  Input channels: r_p / s and the
+ * standardised log-permeability, s = RMS(r_p); output: the correction / s.
+ * Weights are FP32 masters; the passes use BF16 operands with FP32
+ * accumulation on the matrix cores.  Parameters, flat FP32: per layer
+ * W[t][c_in][c_out] (tap t = 9(dz+1) + 3(dy+1) + (dx+1)) then b[c_out];
+ * bo_nn_num_params() values in total.  Tensors are channel-last,
+ * [nb][nz][ny][nx][channels].  A handle is not thread-safe. */
+typedef struct bo_nn bo_nn;
+
+bo_status bo_nn_create(bo_nn **out);            /* [host] out; parameters zero */
+void bo_nn_destroy(bo_nn *nn);
+int32_t bo_nn_num_params(void);
+/* [host] params: bo_nn_num_params() floats; resets the Adam state */
+bo_status bo_nn_set_params(bo_nn *nn, const float *params, void *stream);
+/* [host] params / grads (either may be NULL): the current parameters and the
+ * gradients of the last bo_nn_backward */
+bo_status bo_nn_get_params(bo_nn *nn, float *params, float *grads, void *stream);
+/* out = N(in): in [nb][nz][ny][nx][2] FP32, out [nb][nz][ny][nx] FP32.  Keeps
+ * the activations for bo_nn_backward. */
+bo_status bo_nn_forward(bo_nn *nn, const float *in, float *out, int32_t nb, int32_t nz, int32_t ny, int32_t nx,
+                        void *stream);
+/* Gradients of the mean squared error between the last bo_nn_forward output
+ * and target ([nb][nz][ny][nx] FP32); loss [host, may be NULL] receives the
+ * loss.  Synchronous.  Fails after a forward pass made inside CPR. */
+bo_status bo_nn_backward(bo_nn *nn, const float *target, double *loss, void *stream);
+/* Adam (beta 0.9 / 0.999, eps 1e-8, bias-corrected) with learning rate lr on
+ * the gradients of the last bo_nn_backward. */
+bo_status bo_nn_adam_step(bo_nn *nn, float lr, void *stream);
+
+/* Attaches nn (not owned; NULL detaches) to the pressure stage of pc; logk:
+ * N FP64 values of ln k, standardised here.  With a network attached, each
+ * pressure stage computes dp = V(r_p) and c = s N([r_p / s, z]) and uses
+ * dp + c if ||r_p - A_pp (dp + c)|| < ||r_p - A_pp dp||, else dp
+ * (bo_solve_stats.nn_used counts the kept corrections). */
+bo_status bo_cpr_attach_nn(bo_cpr *pc, bo_nn *nn, const double *logk, void *stream);
+/* Training pairs from a solve of A x = b (A of the last setup/update): runs
+ * FGMRES with pc for at most ncalls preconditioner applications, recording the
+ * pressure-stage inputs r_p of the first ncalls of them in rp_out
+ * ([ncalls][N] FP32, caller-allocated), and writes e = A_pp^{-1} r_p - V(r_p)
+ * to e_out ([ncalls][N] FP32), with A_pp^{-1} r_p from GMRES on A_pp
+ * preconditioned by the V-cycle to relative residual rtol_inner.  *got [host]
+ * receives the number of pairs.  The attached network is not used. */
+bo_status bo_cpr_collect_pairs(bo_cpr *pc, const double *b, int32_t ncalls, double rtol_inner, float *rp_out,
+                               float *e_out, int32_t *got, void *stream);
 
 #ifdef __cplusplus
 }

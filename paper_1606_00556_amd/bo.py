@@ -12,6 +12,8 @@ import os
 from dataclasses import dataclass
 from typing import Optional
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbo.so")
 
@@ -29,6 +31,8 @@ EXPORTS = [
     "bo_cpr_default_opts", "bo_cpr_setup", "bo_cpr_update", "bo_cpr_destroy", "bo_cpr_apply", "bo_cpr_spmv",
     "bo_cpr_restrict", "bo_cpr_vcycle", "bo_cpr_fstage", "bo_cpr_levels", "bo_cpr_level_info",
     "bo_cpr_level_copy", "bo_cpr_copy_weights", "bo_fgmres_default_opts", "bo_fgmres_solve",
+    "bo_nn_create", "bo_nn_destroy", "bo_nn_num_params", "bo_nn_set_params", "bo_nn_get_params",
+    "bo_nn_forward", "bo_nn_backward", "bo_nn_adam_step", "bo_cpr_attach_nn", "bo_cpr_collect_pairs",
 ]
 
 
@@ -84,7 +88,7 @@ class BoFgmresOpts(C.Structure):
 class BoSolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
                 ("rel_residual", C.c_double), ("est_residual", C.c_double), ("spmv_ms", C.c_double),
-                ("spmv_calls", C.c_int32)]
+                ("spmv_calls", C.c_int32), ("nn_used", C.c_int32)]
 
 
 _lib = None
@@ -124,9 +128,21 @@ def lib():
     L.bo_fgmres_default_opts.argtypes = [C.POINTER(BoFgmresOpts)]
     L.bo_fgmres_default_opts.restype = None
     L.bo_fgmres_solve.argtypes = [vp, vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats), vp]
+    L.bo_nn_create.argtypes = [C.POINTER(vp)]
+    L.bo_nn_destroy.argtypes = [vp]
+    L.bo_nn_destroy.restype = None
+    L.bo_nn_num_params.argtypes = []
+    L.bo_nn_num_params.restype = C.c_int32
+    L.bo_nn_set_params.argtypes = [vp, vp, vp]
+    L.bo_nn_get_params.argtypes = [vp, vp, vp, vp]
+    L.bo_nn_forward.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
+    L.bo_nn_backward.argtypes = [vp, vp, C.POINTER(C.c_double), vp]
+    L.bo_nn_adam_step.argtypes = [vp, C.c_float, vp]
+    L.bo_cpr_attach_nn.argtypes = [vp, vp, vp, vp]
+    L.bo_cpr_collect_pairs.argtypes = [vp, vp, C.c_int32, C.c_double, vp, vp, C.POINTER(C.c_int32), vp]
     for f in EXPORTS:
         if f not in ("bo_last_error", "bo_version", "bo_cpr_default_opts", "bo_cpr_destroy",
-                     "bo_fgmres_default_opts"):
+                     "bo_fgmres_default_opts", "bo_nn_destroy", "bo_nn_num_params"):
             getattr(L, f).restype = st
     _lib = L
     return L
@@ -354,4 +370,96 @@ def bo_fgmres_solve(pc: Cpr, b, x, opts: Optional[BoFgmresOpts] = None, stream=N
     _check(rc, allowed=(BO_OK, BO_NOT_CONVERGED))
     return dict(status=rc, iterations=st.iterations, restarts=st.restarts, converged=bool(st.converged),
                 rel_residual=st.rel_residual, est_residual=st.est_residual, spmv_ms=st.spmv_ms,
-                spmv_calls=st.spmv_calls)
+                spmv_calls=st.spmv_calls, nn_used=st.nn_used)
+
+
+# ---- learned pressure-stage correction ---------------------------------------
+
+NN_CHANNELS = (2, 16, 16, 16, 1)
+
+
+def nn_flatten(params) -> np.ndarray:
+    """[(W[27, c_in, c_out], b[c_out]) per layer] -> the flat FP32 parameter
+    vector of the library (per layer W then b)."""
+    return np.concatenate([np.concatenate([np.asarray(W, np.float32).reshape(-1), np.asarray(b, np.float32)])
+                           for W, b in params]).astype(np.float32)
+
+
+def nn_unflatten(flat: np.ndarray):
+    out, off = [], 0
+    for l in range(4):
+        ci, co = NN_CHANNELS[l], NN_CHANNELS[l + 1]
+        W = flat[off:off + 27 * ci * co].reshape(27, ci, co)
+        off += 27 * ci * co
+        out.append((W, flat[off:off + co]))
+        off += co
+    return out
+
+
+class Nn:
+    """Owns a bo_nn handle."""
+
+    def __init__(self, params=None):
+        h = C.c_void_p()
+        _check(lib().bo_nn_create(C.byref(h)))
+        self.h = h
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if self.h:
+            lib().bo_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, stream=None):
+        flat = params if isinstance(params, np.ndarray) else nn_flatten(params)
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == lib().bo_nn_num_params()
+        _check(lib().bo_nn_set_params(self.h, flat.ctypes.data, _stream(stream)))
+
+    def get(self, stream=None):
+        n = lib().bo_nn_num_params()
+        p = np.empty(n, np.float32)
+        g = np.empty(n, np.float32)
+        _check(lib().bo_nn_get_params(self.h, p.ctypes.data, g.ctypes.data, _stream(stream)))
+        return p, g
+
+    def forward(self, x, out, stream=None):
+        """x: [nb, nz, ny, nx, 2] float32 device tensor; out: [nb, nz, ny, nx]."""
+        nb, nz, ny, nx, c = x.shape
+        assert c == 2 and x.is_contiguous() and out.is_contiguous() and out.numel() == nb * nz * ny * nx
+        _check(lib().bo_nn_forward(self.h, _ptr(x), _ptr(out), nb, nz, ny, nx, _stream(stream)))
+        return out
+
+    def backward(self, target, stream=None) -> float:
+        assert target.is_contiguous()
+        loss = C.c_double()
+        _check(lib().bo_nn_backward(self.h, _ptr(target), C.byref(loss), _stream(stream)))
+        return loss.value
+
+    def adam_step(self, lr: float = 1e-3, stream=None):
+        _check(lib().bo_nn_adam_step(self.h, C.c_float(lr), _stream(stream)))
+
+
+def bo_cpr_attach_nn(pc: "Cpr", nn: Optional[Nn], logk=None, stream=None):
+    _check(lib().bo_cpr_attach_nn(pc.h, nn.h if nn is not None else None,
+                                  _ptr(logk) if logk is not None else None, _stream(stream)))
+
+
+def bo_cpr_collect_pairs(pc: "Cpr", b, ncalls: int = 4, rtol_inner: float = 1e-10, stream=None):
+    """Returns (rp, e, got): [ncalls, N] float32 device tensors and the number
+    of recorded pairs."""
+    import torch
+    n = pc.n
+    rp = torch.zeros((ncalls, n), dtype=torch.float32, device=b.device)
+    e = torch.zeros((ncalls, n), dtype=torch.float32, device=b.device)
+    got = C.c_int32()
+    _check(lib().bo_cpr_collect_pairs(pc.h, _ptr(b), ncalls, rtol_inner, _ptr(rp), _ptr(e), C.byref(got),
+                                      _stream(stream)))
+    return rp, e, got.value

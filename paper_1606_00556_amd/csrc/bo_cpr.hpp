@@ -86,4 +86,14 @@ struct bo_cpr {
     bo::Reducer red;
     bo::Krylov kr;
     hipEvent_t ev[2] = {nullptr, nullptr};  // SpMV timing in bo_fgmres_solve
+    // learned pressure-stage correction (not owned) and its work arrays
+    bo_nn *nn = nullptr;
+    bo::DBuf<float> nn_z;                 // standardised log-permeability
+    bo::DBuf<double> nn_part, nn_mom, nn_dp;
+    bo::DBuf<float> nn_dp32;
+    bo::DBuf<int32_t> nn_flag, nn_used;
+    // pair collection: recorded pressure-stage inputs (caller's buffer)
+    float *rec_out = nullptr;
+    int rec_max = 0, rec_n = 0;
+    bo::DBuf<double> pg_V, pg_Z, pg_h, pg_x, pg_r, pg_v, pg_xs;
 };

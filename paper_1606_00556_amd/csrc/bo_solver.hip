@@ -32,6 +32,10 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s);
 bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, bool r_in_slots, hipStream_t s);
 bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, bool r_in_slots,
                              hipStream_t s);
+template <typename T>
+bo_status nn_correct(bo_cpr *pc, const T *rp, const T *dp, const T **out, hipStream_t s);
+template <typename T>
+bo_status nn_record(bo_cpr *pc, const T *rp, hipStream_t s);
 size_t fstage_slots(const bo_cpr *pc);
 
 namespace {
@@ -51,14 +55,26 @@ __global__ void k_add_p(long long n, const TD *__restrict__ dp, double *__restri
 
 // the pressure stage: Pi_r v -> one V-cycle; *dp points at the result in the
 // hierarchy's precision (FP64, or FP32 in the mixed form)
+// With a network attached the V-cycle result is replaced by the judged
+// corrected one (see bo_nn_cpr.hip).
 static bo_status pressure_stage(bo_cpr *pc, const double *v, const void **dp, hipStream_t s) {
     if (pc->o.precision == BO_PREC_FP64) {
         BO_TRY(qi_restrict(pc, v, pc->rp_.p, s));
-        return amg_vcycle_ptr(pc, pc->rp_.p, (const double **)dp, s);
+        BO_TRY(nn_record<double>(pc, pc->rp_.p, s));
+        const double *d;
+        BO_TRY(amg_vcycle_ptr(pc, pc->rp_.p, &d, s));
+        if (pc->nn) BO_TRY(nn_correct<double>(pc, pc->rp_.p, d, &d, s));
+        *dp = d;
+        return BO_OK;
     }
     float *b32 = pc->lv[0].b32.p;
     BO_TRY(qi_restrict_f32(pc, v, b32, s));
-    return amg_vcycle_ptr_f32(pc, b32, (const float **)dp, s);
+    BO_TRY(nn_record<float>(pc, b32, s));
+    const float *d;
+    BO_TRY(amg_vcycle_ptr_f32(pc, b32, &d, s));
+    if (pc->nn) BO_TRY(nn_correct<float>(pc, b32, d, &d, s));
+    *dp = d;
+    return BO_OK;
 }
 
 bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
@@ -340,6 +356,7 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     hipStream_t s = (hipStream_t)stream;
     bo_solve_stats st{};
     const bool timed = opts->timing == 1;
+    if (pc->nn) BO_HIP(hipMemsetAsync(pc->nn_used.p, 0, sizeof(int32_t), s));
     if (timed)
         for (hipEvent_t &e : pc->ev)
             if (!e) BO_HIP(hipEventCreate(&e));
@@ -452,6 +469,7 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     }
 done:
     st.iterations = its;
+    if (pc->nn) BO_HIP(hipMemcpyAsync(&st.nn_used, pc->nn_used.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BO_HIP(hipStreamSynchronize(s));
     if (stats) *stats = st;
     return status;

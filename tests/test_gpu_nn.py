@@ -1,0 +1,201 @@
+"""GPU tests of the learned pressure-stage correction: the BF16 matrix-core
+forward and backward passes against the oracle's BF16 emulation and FP64
+network, Adam against the oracle's Adam, the judge's fallback (a zero network
+changes nothing, bit for bit), the training pairs against a direct solve, and
+the measured gain of a network trained on the GPU from pairs the solver
+produced.
+
+Tolerances: forward element-wise 2^-7 relative to the emulation (plus a floor
+of 1e-2 of the output's RMS for values near zero) for at least 99 % of the
+outputs and 2^-5 for all (BF16 rounding of an intermediate activation may
+land on the neighbouring value when the FP32 sums differ in their last bits),
+and 1e-3 norm-wise;
+gradients 1e-2 norm-wise per layer against the emulation; Adam 1e-5."""
+import numpy as np
+import pytest
+
+import bo_casegen as cg
+from oracle import cnn as N
+from tests.gpu_util import oracle_system, ragged_case, setup_both, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1606_00556_amd import bo
+    bo.lib()
+    return bo
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+SHAPE = (2, 5, 7, 19)   # nb, nz, ny, nx: ragged against 16 x 4 x 4 tiles
+
+
+def f64(params):
+    return [(np.asarray(W, np.float64), np.asarray(b, np.float64)) for W, b in params]
+
+
+def gpu_forward(B, nn, X):
+    import torch
+    x = to_dev(X.astype(np.float32))
+    out = torch.empty(X.shape[:4], dtype=torch.float32, device="cuda")
+    nn.forward(x, out)
+    return to_host(out)
+
+
+def test_forward_matches_bf16_emulation(B):
+    rng = np.random.default_rng(1)
+    params = cg.cnn_init(21, last_scale=1.0)
+    params = [(W, rng.standard_normal(b.shape).astype(np.float32) * 0.1) for W, b in params]
+    X = rng.standard_normal(SHAPE + (2,))
+    nn = B.Nn(params)
+    Y = gpu_forward(B, nn, X)
+    for v in range(SHAPE[0]):
+        emu, _ = N.forward(f64(params), X[v], emulate_bf16=True)
+        ref64, _ = N.forward(f64(params), X[v])
+        e, y = emu[..., 0], Y[v]
+        floor = 1e-2 * np.sqrt(np.mean(e * e))
+        ratio = np.abs(y - e) / (2.0**-7 * (np.abs(e) + floor))
+        nerr = np.linalg.norm(y - e) / np.linalg.norm(e)
+        print(f"volume {v}: worst element {ratio.max():.3f} of the bound ({(ratio > 1).sum()} of {ratio.size} "
+              f"above), norm-wise {nerr:.2e}")
+        # an intermediate activation whose FP32 sum lies next to a BF16 rounding
+        # boundary may round to the neighbouring BF16 value on one side (the
+        # matrix cores sum in another order than the emulation): a few outputs
+        # may exceed the 2^-7 bound, none by more than a factor 4
+        assert (ratio > 1.0).mean() <= 0.01 and ratio.max() <= 4.0
+        assert nerr <= 1e-3
+        # and the BF16 network is close to the FP64 one
+        assert np.linalg.norm(y - ref64[..., 0]) <= 2.0**-5 * np.linalg.norm(ref64)
+
+
+def test_backward_matches_oracle_and_adam(B):
+    rng = np.random.default_rng(2)
+    params = cg.cnn_init(22, last_scale=1.0)
+    X = rng.standard_normal(SHAPE + (2,))
+    T = rng.standard_normal(SHAPE)
+    nn = B.Nn(params)
+    import torch
+    Y = gpu_forward(B, nn, X)
+    loss = nn.backward(to_dev(T.astype(np.float32)))
+    p0, g = nn.get()
+    gl = B.nn_unflatten(g)
+    # oracle gradients of the same loss (mean over every voxel of the batch)
+    M = T.size
+    ge = None
+    g64 = None
+    lref = 0.0
+    for v in range(SHAPE[0]):
+        ye, cache = N.forward(f64(params), X[v], emulate_bf16=True)
+        # backward scales by the voxels of this volume; rescale to the batch
+        gv = N.backward(f64(params), cache, ye, T[v][..., None], emulate_bf16=True)
+        w = T[v].size / M
+        ge = [(w * a, w * b) for a, b in gv] if ge is None else [(A + w * a, Bb + w * b) for (A, Bb), (a, b) in zip(ge, gv)]
+        y6, c6 = N.forward(f64(params), X[v])
+        gv6 = N.backward(f64(params), c6, y6, T[v][..., None])
+        g64 = [(w * a, w * b) for a, b in gv6] if g64 is None else [(A + w * a, Bb + w * b) for (A, Bb), (a, b) in zip(g64, gv6)]
+        lref += w * N.mse(ye, T[v][..., None])
+    assert abs(loss - lref) <= 1e-3 * lref
+    for l in range(4):
+        for q in range(2):
+            a, e, e6 = np.asarray(gl[l][q], np.float64), ge[l][q], g64[l][q]
+            assert np.linalg.norm(a - e) <= 1e-2 * np.linalg.norm(e), (l, q)
+            # BF16 operands against the FP64 network: a few per cent
+            assert np.linalg.norm(a - e6) <= 0.1 * np.linalg.norm(e6), (l, q)
+    # one Adam step against the oracle's Adam on the GPU's gradients
+    nn.adam_step(1e-3)
+    p1, _ = nn.get()
+    opt = N.Adam(f64(params), lr=1e-3)
+    ref = opt.step(f64(params), [(np.asarray(W, np.float64), np.asarray(b, np.float64)) for W, b in gl])
+    assert np.allclose(p1, B.nn_flatten(ref), rtol=1e-5, atol=1e-7)
+
+
+def test_zero_network_changes_nothing(B, O):
+    """A network whose last layer is zero predicts c = 0, the judge never keeps
+    it, and the solve is bit for bit the plain CPR solve."""
+    import torch
+    case = ragged_case()
+    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
+    params = cg.cnn_init(23)
+    params[-1] = (np.zeros_like(params[-1][0]), np.zeros_like(params[-1][1]))
+    nn = B.Nn(params)
+    xs, infos = [], []
+    for attach in (False, True):
+        if attach:
+            B.bo_cpr_attach_nn(gpc, nn, to_dev(np.log(case.kx)))
+        x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x))
+        xs.append(to_host(x))
+    assert infos[0]["iterations"] == infos[1]["iterations"]
+    assert infos[1]["nn_used"] == 0
+    assert np.array_equal(xs[0], xs[1])
+
+
+def test_collect_pairs_matches_direct_solve(B, O):
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    case = ragged_case()
+    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case, coarse_max=40)
+    r, e, got = B.bo_cpr_collect_pairs(gpc, to_dev(b), ncalls=3, rtol_inner=1e-11)
+    assert got == 3
+    r, e = to_host(r).astype(np.float64), to_host(e).astype(np.float64)
+    # first pressure-stage input: Pi_r of v_1 = b / ||b||
+    r0 = opc.restrict(b / np.linalg.norm(b))
+    assert np.linalg.norm(r[0] - r0) <= 1e-6 * np.linalg.norm(r0)
+    w, app = O.qi_decouple(rp, ci, val)
+    A = sp.csr_matrix((app, ci, rp), shape=(case.n, case.n)).tocsc()
+    for q in range(got):
+        xs = spla.spsolve(A, r[q])
+        eref = xs - opc.vcycle(r[q])
+        assert np.linalg.norm(e[q] - eref) <= 1e-5 * np.linalg.norm(eref), q
+
+
+def test_trained_network_gain(B, O):
+    """Train the network on the GPU from pairs the solver collects on a few
+    seeded systems, then solve held-out systems with and without it.  The
+    gain is measured and printed; the corrected solves must reach the FP64
+    residual of 1e-6."""
+    import torch
+    train = [cg.tiny_case(32, 24, 8, seed=s, sigma=1.5, step=0.01, dt=3.0) for s in (101, 102, 103, 104)]
+    test = [cg.tiny_case(32, 24, 8, seed=s, sigma=1.5, step=0.01, dt=3.0) for s in (201, 202)]
+    X, Tg = [], []
+    for c in train:
+        P, rp, ci, val, b, opc, gpc = setup_both(B, O, c)
+        r, e, got = B.bo_cpr_collect_pairs(gpc, to_dev(b), ncalls=4)
+        lk = np.log(c.kx)
+        z = (lk - lk.mean()) / lk.std()
+        for q in range(got):
+            rq = to_host(r[q]).astype(np.float64)
+            s = np.sqrt(np.mean(rq * rq))
+            X.append(np.stack([rq / s, z], -1).reshape(c.nz, c.ny, c.nx, 2))
+            Tg.append(to_host(e[q]).astype(np.float64).reshape(c.nz, c.ny, c.nx) / s)
+    X = to_dev(np.stack(X).astype(np.float32))
+    Tg = to_dev(np.stack(Tg).astype(np.float32))
+    nn = B.Nn(cg.cnn_init(24))
+    out = torch.empty(Tg.shape, dtype=torch.float32, device="cuda")
+    losses = []
+    for it in range(300):
+        nn.forward(X, out)
+        losses.append(nn.backward(Tg))
+        nn.adam_step(3e-3 if it < 200 else 1e-3)
+    assert losses[-1] < losses[0]
+    for c in test:
+        P, rp, ci, val, b, opc, gpc = setup_both(B, O, c)
+        res = {}
+        for attach in (False, True):
+            if attach:
+                B.bo_cpr_attach_nn(gpc, nn, to_dev(np.log(c.kx)))
+            x = torch.zeros(3 * c.n, dtype=torch.float64, device="cuda")
+            info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+            rr = b - O.bsr_spmv(rp, ci, val, to_host(x))
+            assert info["converged"] and np.linalg.norm(rr) <= 1e-6 * np.linalg.norm(b)
+            res[attach] = info
+        print(f"{c.name}: loss {losses[0]:.3e} -> {losses[-1]:.3e}; iterations AMG {res[False]['iterations']}, "
+              f"AMG+network {res[True]['iterations']} (corrections kept {res[True]['nn_used']})")
