@@ -122,10 +122,26 @@ class Case:
     fluid: dict
     gravity: bool = True
     inj_total_mobility: bool = True
+    # dual porosity: matrix permeability (isotropic, for the transfer term) and
+    # porosity per location; x_old / x_new then hold N fracture cells, N matrix
+    # cells and one (p_h, 0, 0) triple per fixed-rate well
+    dual: bool = False
+    km: Optional[np.ndarray] = None
+    phim: Optional[np.ndarray] = None
+    sigma: float = 0.0
 
     @property
     def n(self) -> int:
         return self.nx * self.ny * self.nz
+
+    @property
+    def nrate(self) -> int:
+        return sum(1 for w in self.wells if w.control != "bhp")
+
+    @property
+    def rows(self) -> int:
+        """Block rows of the system: cells (N or 2N) then fixed-rate wells."""
+        return self.n * (2 if self.dual else 1) + self.nrate
 
 
 def base_seed(cfg: int) -> int:
@@ -317,3 +333,86 @@ def cnn_init(seed: int = 1606300, channels=(2, 16, 16, 16, 1), last_scale: float
             w = w * last_scale
         params.append((w.astype(np.float32), np.zeros(co, dtype=np.float32)))
     return params
+
+
+# ---- dual porosity with fixed-rate wells -----------------------------------------
+_F_KM, _F_PHIM, _F_WJIT, _F_WCTRL, _F_MSTATE = 50, 51, 52, 53, 54
+SHAPE_L = 10.0        # fracture spacing (ft) in each direction
+PHI_F = 0.01          # fracture porosity
+
+
+def kazemi_sigma(lx=SHAPE_L, ly=SHAPE_L, lz=SHAPE_L) -> float:
+    """Shape factor sigma = 4 (1/Lx^2 + 1/Ly^2 + 1/Lz^2) (ft^-2)."""
+    return 4.0 * (1.0 / lx ** 2 + 1.0 / ly ** 2 + 1.0 / lz ** 2)
+
+
+def _dual_state(seed, nx, ny, nz, xf_old, xf_new, wells):
+    """Matrix cells lag the fractures by one step, with their own correlated
+    noise; fixed-rate wells start from the target BHP of their kind."""
+    n = nx * ny * nz
+    lag = 1.0 + 0.02 * (smooth_noise(seed, _F_MSTATE, nx, ny, nz) - 0.5)
+    xm_new = xf_old.copy()
+    xm_new[0::3] *= lag
+    xm_old = xm_new.copy()
+    xm_old[0::3] = xm_new[0::3] - 0.5 * (xf_new[0::3] - xf_old[0::3])
+    wl = []
+    for w in wells:
+        if w.control != "bhp":
+            wl += [3200.0 if w.kind == "inj" else 2800.0, 0.0, 0.0]
+    wv = np.array(wl, dtype=np.float64)
+    return (np.concatenate([xf_old, xm_old, wv]), np.concatenate([xf_new, xm_new, wv]))
+
+
+def line_drive_wells(seed, nx, ny, nz, lines, cols, jitter, rate=2000.0):
+    """Wells on lines j = lines[q] (injector and producer lines alternating),
+    columns i = cols[r], jittered by up to +-jitter cells; each well's control
+    (fixed BHP or fixed rate) by a seeded coin flip."""
+    wells = []
+    idx = 0
+    for q, j0 in enumerate(lines):
+        kind = "inj" if q % 2 == 0 else "prod"
+        for i0 in cols:
+            u = uniform(seed, _F_WJIT, np.array([2 * idx, 2 * idx + 1], dtype=np.uint64))
+            i = int(min(max(i0 + round((2 * u[0] - 1) * jitter), 0), nx - 1))
+            j = int(min(max(j0 + round((2 * u[1] - 1) * jitter), 0), ny - 1))
+            flip = uniform(seed, _F_WCTRL, np.array([idx], dtype=np.uint64))[0] < 0.5
+            if flip:
+                wells.append(Well(i, j, 0, nz - 1, kind, "wrat" if kind == "inj" else "lrat", rate))
+            else:
+                wells.append(Well(i, j, 0, nz - 1, kind, "bhp", 3500.0 if kind == "inj" else 2500.0))
+            idx += 1
+    return wells
+
+
+def make_dual_case(nx: int, ny: int, nz: int, seed: int, system: int = 1, wells=None,
+                   kf_mean: float = 500.0, km_mean: float = 1.0, sigma_ln: float = 1.0, name=None) -> Case:
+    """Dual-porosity case: fractures log-normal around kf_mean (kz = 0.1 kx),
+    matrix log-normal around km_mean, phi_f = 0.01, phi_m = U[0.15, 0.25],
+    the step sequence of the other workloads applied to the fractures."""
+    dx, dy, dz, top = 50.0, 50.0, 10.0, 8000.0
+    n = nx * ny * nz
+    kx = _lognormal(seed, n, math.log(kf_mean), sigma_ln)
+    km = np.exp(math.log(km_mean) + sigma_ln * normal(seed, _F_KM, np.arange(n, dtype=np.uint64)))
+    phim = 0.15 + 0.10 * uniform(seed, _F_PHIM, np.arange(n, dtype=np.uint64))
+    if wells is None:
+        wells = _five_spot(nx, ny, nz)
+    base = _noisy_state(seed, nx, ny, nz)
+    xf_old = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * (system - 1))
+    xf_new = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * system)
+    x_old, x_new = _dual_state(seed, nx, ny, nz, xf_old, xf_new, wells)
+    return Case(name or f"dual{nx}x{ny}x{nz}.{system}", nx, ny, nz, dx, dy, dz, top, kx, kx.copy(), 0.1 * kx,
+                np.full(n, PHI_F), x_old, x_new, 3.0, wells, dict(FLUID), dual=True, km=km, phim=phim,
+                sigma=kazemi_sigma())
+
+
+def make_cfg4(system: int = 1, scale: int = 1) -> Case:
+    """The dual-porosity workload: 400x400x100 locations (32M cells), 20 wells
+    on 4 lines x 5 columns with seeded jitter and controls.  ``scale`` > 1
+    divides nx, ny by it and nz by half of it (a smaller twin for parity)."""
+    nx, ny, nz = 400 // scale, 400 // scale, max(100 // max(scale // 2, 1), 4)
+    def f(v):
+        return int(round(v / scale)) if scale > 1 else v
+    lines = [f(v) for v in (50, 150, 250, 350)]
+    cols = [f(v) for v in (40, 120, 200, 280, 360)]
+    wells = line_drive_wells(base_seed(4), nx, ny, nz, lines, cols, max(10 // scale, 1))
+    return make_dual_case(nx, ny, nz, base_seed(4), system, wells, name=f"cfg4/{scale}.{system}")

@@ -51,11 +51,29 @@ typedef struct {
     double tcoef, rb_ft3, grav;
     int gravity;               /* 0: potentials without the density term */
     int inj_total_mobility;    /* 1: water injectors use the cell's total mobility */
-    /* wells: nwells entries each */
+    /* wells: nwells entries each; ctrl OR_CTRL_*; target: BHP (psi) or rate
+     * (STB/day, positive for injection and for production alike) */
     int nwells;
-    const int32_t *w_i, *w_j, *w_ktop, *w_kbot, *w_inj, *w_ctrl; /* ctrl 0 = fixed BHP */
+    const int32_t *w_i, *w_j, *w_ktop, *w_kbot, *w_inj, *w_ctrl;
     const double *w_target, *w_rw, *w_skin;
+    /* dual porosity (fractured reservoirs, Section 2.1): with dual != 0 every
+     * grid cell g also holds a matrix cell, block row N + g, that exchanges
+     * fluid only with its fracture cell g through T_mf = tcoef sigma km V_b;
+     * kx, ky, kz and phi0 then describe the fractures */
+    int dual;
+    const double *km, *phim;
+    double sigma;
 } or_problem;
+
+/* Well controls (Section 2.3).  A fixed-rate well adds one block row after the
+ * cell rows (in well order) whose unknowns are (p_h, 0, 0): row 0 is the rate
+ * constraint sum_m q_m - target (water rate of an injector, oil + water rate
+ * of a producer, in STB/day), rows 1 and 2 are the identity. */
+enum { OR_CTRL_BHP = 0, OR_CTRL_WRATE = 1, OR_CTRL_LRATE = 2 };
+
+/* Block rows of the system: cells (N, or 2N with dual porosity) then one per
+ * fixed-rate well; *ncell receives the number of cell rows. */
+int or_rows(const or_problem *p, int *ncell);
 
 /* Relative permeabilities (Section 2.1; Stone II for oil).  out[0..5] =
  * krw, krow, krg, krog, kro, and out[5] = dkro/dSw, out[6] = dkro/dSg. */
@@ -66,18 +84,24 @@ void or_relperm(const or_problem *p, double sw, double sg, double *out);
 double or_transmissibility(const or_problem *p, int a, int b);
 double or_pore_volume(const or_problem *p, int g, double pr);
 double or_well_index(const or_problem *p, int g, double rw, double skin);
+/* fracture-matrix transfer coefficient of location g (dual porosity) */
+double or_transfer(const or_problem *p, int g);
 
-/* BSR pattern of the 7-point stencil: returns nnzb; fills rowptr (N+1) and
- * colind (nnzb) when they are not NULL. */
+/* BSR pattern: the 7-point stencil between (fracture) cells, the fracture-
+ * matrix pair of each location, and the couplings of each fixed-rate well row
+ * with its perforated cells; ascending columns.  Returns nnzb; fills rowptr
+ * (rows + 1) and colind (nnzb) when they are not NULL. */
 int or_pattern(const or_problem *p, int32_t *rowptr, int32_t *colind);
 
-/* Residual R (3N) of the discrete black-oil equations at x_new with old state
- * x_old; when val != NULL also the analytic Jacobian dR/dx_new into the BSR
- * values on the pattern of or_pattern.  Returns OR_OK or an error code. */
+/* Residual R (3 rows) of the discrete black-oil equations at x_new with old
+ * state x_old (both 3 rows long; a fixed-rate well's entries are (p_h, 0, 0));
+ * when val != NULL also the analytic Jacobian dR/dx_new into the BSR values on
+ * the pattern of or_pattern.  Returns OR_OK or an error code. */
 int or_assemble(const or_problem *p, const double *x_old, const double *x_new, double dt,
                 double *R, const int32_t *rowptr, const int32_t *colind, double *val);
 
-/* Flux-only residual (no accumulation, no wells): used for conservation pins. */
+/* Flux-only residual (faces and fracture-matrix transfer; no accumulation, no
+ * wells) over the cell rows: used for conservation pins. */
 int or_flux_residual(const or_problem *p, const double *x, double *R);
 
 /* y = alpha*A*x + beta*y for a BSR matrix with bs x bs blocks (beta == 0 ignores y). */
@@ -101,7 +125,9 @@ int or_qi_decouple(int n, const int32_t *rowptr, const int32_t *colind, const do
 
 /* ---- CPR preconditioner and FGMRES ---------------------------------- */
 enum { OR_F_BJ = 0, OR_F_ILU_NATURAL = 1, OR_F_ILU_RB = 2, OR_F_ILU_TILED = 3 };
-enum { OR_SMOOTH_GS = 0, OR_SMOOTH_JACOBI = 1 };
+/* level-0 smoother: red-black Gauss-Seidel (needs the grid), damped Jacobi,
+ * or l1-Jacobi (any graph) */
+enum { OR_SMOOTH_GS = 0, OR_SMOOTH_JACOBI = 1, OR_SMOOTH_L1 = 2 };
 
 typedef struct {
     int fpf;              /* 0: two-stage PF, 1: Algorithm CPR-FPF */
@@ -115,6 +141,8 @@ typedef struct {
     int qi_mode;          /* OR_QI_DIAG or OR_QI_BLOCK */
     int precision;        /* OR_PREC_*: mixed-precision emulation of the inner stages */
     int csmoother;        /* OR_CSMOOTH_* on levels >= 1 */
+    int npr;              /* pressure rows: the first npr block rows (cells); later rows
+                             (fixed-rate wells) stay out of A_pp.  0: all rows */
 } or_cpr_opts;
 enum { OR_CSMOOTH_JACOBI = 0, OR_CSMOOTH_L1 = 1 };
 

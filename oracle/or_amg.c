@@ -343,7 +343,7 @@ int or_amg_setup(or_amg *h, const or_csr *A0, int nx, int ny, int nz, double the
         }
     }
     /* Gauss-Seidel colours exist only for level 0 of a grid: red-black */
-    if (nx > 0 && nx * ny * nz == h->A[0].n) {
+    if (smoother == OR_SMOOTH_GS && nx > 0 && nx * ny * nz == h->A[0].n) {
         int n = h->A[0].n;
         h->color[0] = malloc(sizeof(int32_t) * (size_t)n);
         for (int g = 0; g < n; g++) {
@@ -393,7 +393,7 @@ static void smooth(const or_amg *h, int l, const double *b, double *x, int forwa
     const or_csr *A = &h->A[l];
     int n = A->n;
     int kind = l == 0 ? h->smoother : OR_SMOOTH_JACOBI;
-    int l1 = l > 0 && h->csmoother == OR_CSMOOTH_L1;
+    int l1 = (l > 0 && h->csmoother == OR_CSMOOTH_L1) || (l == 0 && h->smoother == OR_SMOOTH_L1);
     for (int sw = 0; sw < h->sweeps; sw++) {
         if (l1) {
             double *t = malloc(sizeof(double) * (size_t)n);
@@ -533,7 +533,7 @@ static void smooth_f32(const or_amg *h, int l, const float *b, float *x, int for
     const float *v = h->A32[l];
     int n = A->n;
     int kind = l == 0 ? h->smoother : OR_SMOOTH_JACOBI;
-    int l1 = l > 0 && h->csmoother == OR_CSMOOTH_L1;
+    int l1 = (l > 0 && h->csmoother == OR_CSMOOTH_L1) || (l == 0 && h->smoother == OR_SMOOTH_L1);
     const float w = (float)(2.0 / 3.0);
     for (int sw = 0; sw < h->sweeps; sw++) {
         if (l1) {

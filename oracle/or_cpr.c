@@ -42,6 +42,7 @@ struct or_cpr {
     int32_t *rank, *order;       /* ILU ordering */
     uint8_t *drop;               /* per entry: coupling dropped by tiling */
     int32_t *diag;               /* entry index of the diagonal block per row */
+    int npr;                     /* rows of the pressure system */
     /* mixed-precision emulation */
     float *inv32;                /* N*9: rounded pivots (ILU) or diagonal inverses (BJ) */
     float *A32;                  /* nnzb*9: rounded blocks of A (ILU, dropped ones zero) */
@@ -284,11 +285,25 @@ int or_cpr_setup(const or_problem *p, int n, const int32_t *rowptr, const int32_
     double *app = malloc(sizeof(double) * (size_t)nnzb);
     int st = or_qi_decouple(n, rowptr, colind, val, o->qi_mode, c->cw, app);
     if (st) { free(app); or_cpr_free(c); return st; }
+    int npr = o->npr > 0 && o->npr < n ? o->npr : n;
+    c->npr = npr;
     if (o->use_amg) {
-        or_csr A0 = { n, n, nnzb, (int32_t *)rowptr, (int32_t *)colind, app };
-        int nx = p ? p->nx : 0, ny = p ? p->ny : 0, nz = p ? p->nz : 0;
+        /* A_pp: the first npr rows and columns of the decoupled pressure block */
+        int32_t *prp = malloc(sizeof(int32_t) * (size_t)(npr + 1)), *pci = malloc(sizeof(int32_t) * (size_t)nnzb);
+        double *pv = malloc(sizeof(double) * (size_t)nnzb);
+        int cnt = 0;
+        prp[0] = 0;
+        for (int i = 0; i < npr; i++) {
+            for (int e = rowptr[i]; e < rowptr[i + 1]; e++)
+                if (colind[e] < npr) { pci[cnt] = colind[e]; pv[cnt] = app[e]; cnt++; }
+            prp[i + 1] = cnt;
+        }
+        or_csr A0 = { npr, npr, cnt, prp, pci, pv };
+        int grid = p && p->nx * p->ny * p->nz == npr;
+        int nx = grid ? p->nx : 0, ny = grid ? p->ny : 0, nz = grid ? p->nz : 0;
         st = or_amg_setup(&c->amg, &A0, nx, ny, nz, o->theta, o->coarse_max, o->max_levels,
                           o->smoother, o->sweeps, o->csmoother);
+        free(prp); free(pci); free(pv);
         c->has_amg = 1;
         if (st) { free(app); or_cpr_free(c); return st; }
     }
@@ -325,7 +340,7 @@ void or_cpr_free(or_cpr *c)
 
 int or_cpr_restrict(or_cpr *c, const double *v, double *rp)
 {
-    for (int i = 0; i < c->n; i++)
+    for (int i = 0; i < c->npr; i++)
         rp[i] = c->cw[3 * i] * v[3 * i] + c->cw[3 * i + 1] * v[3 * i + 1] + c->cw[3 * i + 2] * v[3 * i + 2];
     return OR_OK;
 }
@@ -334,7 +349,7 @@ int or_cpr_restrict(or_cpr *c, const double *v, double *rp)
  * float result is returned exactly */
 static void vcycle_any(or_cpr *c, const double *b, double *x)
 {
-    int n = c->n;
+    int n = c->npr;
     if (c->o.precision == OR_PREC_FP64) {
         or_amg_vcycle(&c->amg, b, x);
         return;
@@ -356,7 +371,7 @@ int or_cpr_vcycle(or_cpr *c, const double *b, double *x)
 /* x += Pi_p V(Pi_r r) */
 static void pressure_stage(or_cpr *c, const double *r, double *x)
 {
-    int n = c->n;
+    int n = c->npr;
     double *rp = malloc(sizeof(double) * (size_t)n), *dp = malloc(sizeof(double) * (size_t)n);
     or_cpr_restrict(c, r, rp);
     vcycle_any(c, rp, dp);

@@ -4,8 +4,17 @@
  *
  * Model: Section 2.1 (three-component black oil, Darcy's law, constraints on
  * potentials and saturations, no-flow outer boundary, Stone II oil relative
- * permeability), Section 2.3 (Peaceman well model, fixed bottom-hole pressure
- * control), Section 3 (finite differences on a structured hexahedral grid).
+ * permeability; for fractured reservoirs a dual-porosity model in which each
+ * location holds a fracture cell and a matrix cell joined by a transfer
+ * term), Section 2.3 (Peaceman well model with fixed bottom-hole pressure or
+ * fixed water / liquid rate, the latter adding the bottom-hole pressure as an
+ * unknown and the rate constraint as an equation), Section 3 (finite
+ * differences on a structured hexahedral grid).
+ *
+ * Dual porosity (the paper names the model without its transfer function):
+ * Kazemi's shape factor, T_mf = tcoef sigma k_m V_b with sigma = 4 (1/Lx^2 +
+ * 1/Ly^2 + 1/Lz^2), upstream-weighted like a face between two cells at the
+ * same depth; matrix cells have no matrix-matrix faces and no wells.
  *
  * Readings where the paper is silent: the equations are written per unit of
  * surface volume (oil and water in STB/day, gas in Mscf/day); capillary
@@ -82,6 +91,16 @@ typedef struct {
     double lg, lg_g;                          /* gas mobility and d/dSg */
 } props;
 
+static int ncells(const or_problem *p) { return p->nx * p->ny * p->nz; }
+
+/* porosity at p_ref of cell row g: fracture (or single-porosity) cells use
+ * phi0, matrix cells (rows N..2N-1) phim */
+static double phi_ref(const or_problem *p, int g)
+{
+    int n = ncells(p);
+    return g < n ? p->phi0[g] : p->phim[g - n];
+}
+
 static void cell_props(const or_problem *p, int g, const double *x, props *c)
 {
     double pr = x[3 * g], sw = x[3 * g + 1], sg = x[3 * g + 2];
@@ -91,8 +110,8 @@ static void cell_props(const or_problem *p, int g, const double *x, props *c)
     recip_fvf(p->Bg0, p->cg, p->p_ref, pr, &c->bg, &c->dbg);
     c->rs = p->Rs0 * (1.0 + p->crs * (pr - p->p_ref));
     c->drs = p->Rs0 * p->crs;
-    c->phi = p->phi0[g] * (1.0 + p->c_r * (pr - p->p_ref));
-    c->dphi = p->phi0[g] * p->c_r;
+    c->phi = phi_ref(p, g) * (1.0 + p->c_r * (pr - p->p_ref));
+    c->dphi = phi_ref(p, g) * p->c_r;
     /* densities (lbm/ft3): surface densities carried by b; 1000 scf per Mscf */
     double gas_per_stb = 1000.0 * p->rho_gsc / p->rb_ft3;
     c->rw = p->rho_wsc * c->bw;
@@ -144,9 +163,37 @@ double or_well_index(const or_problem *p, int g, double rw, double skin)
 
 /* -------- BSR pattern ------------------------------------------------ */
 
+int or_rows(const or_problem *p, int *ncell)
+{
+    int nc = ncells(p) * (p->dual ? 2 : 1), rows = nc;
+    for (int w = 0; w < p->nwells; w++)
+        if (p->w_ctrl[w] != OR_CTRL_BHP) rows++;
+    if (ncell) *ncell = nc;
+    return rows;
+}
+
+/* block row of fixed-rate well w (-1 for a fixed-BHP well) */
+static int well_row(const or_problem *p, int w)
+{
+    int nc, r = 0;
+    or_rows(p, &nc);
+    if (p->w_ctrl[w] == OR_CTRL_BHP) return -1;
+    for (int q = 0; q < w; q++)
+        if (p->w_ctrl[q] != OR_CTRL_BHP) r++;
+    return nc + r;
+}
+
+static int perforates(const or_problem *p, int w, int g)
+{
+    int nx = p->nx, nxy = p->nx * p->ny;
+    int i = g % nx, j = (g / nx) % p->ny, k = g / nxy;
+    return i == p->w_i[w] && j == p->w_j[w] && k >= p->w_ktop[w] && k <= p->w_kbot[w];
+}
+
 int or_pattern(const or_problem *p, int32_t *rowptr, int32_t *colind)
 {
     int nx = p->nx, ny = p->ny, nz = p->nz, nxy = nx * ny, n = nx * ny * nz;
+    int nc, rows = or_rows(p, &nc);
     int cnt = 0;
     if (rowptr) rowptr[0] = 0;
     for (int g = 0; g < n; g++) {
@@ -158,8 +205,36 @@ int or_pattern(const or_problem *p, int32_t *rowptr, int32_t *colind)
             if (colind) colind[cnt] = cand[s];
             cnt++;
         }
+        if (p->dual) {
+            if (colind) colind[cnt] = n + g;
+            cnt++;
+        }
+        for (int w = 0; w < p->nwells; w++) {
+            int wr = well_row(p, w);
+            if (wr < 0 || !perforates(p, w, g)) continue;
+            if (colind) colind[cnt] = wr;
+            cnt++;
+        }
         if (rowptr) rowptr[g + 1] = cnt;
     }
+    if (p->dual)
+        for (int g = 0; g < n; g++) {
+            if (colind) { colind[cnt] = g; colind[cnt + 1] = n + g; }
+            cnt += 2;
+            if (rowptr) rowptr[n + g + 1] = cnt;
+        }
+    for (int w = 0; w < p->nwells; w++) {
+        int wr = well_row(p, w);
+        if (wr < 0) continue;
+        for (int k = p->w_ktop[w]; k <= p->w_kbot[w]; k++) {
+            if (colind) colind[cnt] = p->w_i[w] + nx * (p->w_j[w] + ny * k);
+            cnt++;
+        }
+        if (colind) colind[cnt] = wr;
+        cnt++;
+        if (rowptr) rowptr[wr + 1] = cnt;
+    }
+    (void)rows;
     return cnt;
 }
 
@@ -226,13 +301,13 @@ static void phase_density(const props *c, int phase, double *rho, double *drho)
     else { *rho = c->rg; *drho = c->drg; }
 }
 
-/* Adds the flux terms of the face (l, h), l < h, to R and (optionally) the Jacobian. */
-static void face_terms(const or_problem *p, int l, int h, const props *cl, const props *ch,
-                       double *R, const int32_t *rowptr, const int32_t *colind, double *val)
+/* Adds the flux terms of the connection (l, h), l < h, with transmissibility T
+ * and depth difference ddep = depth(l) - depth(h), to R and (optionally) the
+ * Jacobian: a face between two cells, or the fracture-matrix transfer. */
+static void flux_terms(const or_problem *p, int l, int h, double T, double ddep, const props *cl,
+                       const props *ch, double *R, const int32_t *rowptr, const int32_t *colind, double *val)
 {
-    double T = or_transmissibility(p, l, h);
     double g = p->gravity ? p->grav : 0.0;
-    double ddep = depth_of(p, l) - depth_of(p, h);
     /* component row, stream kind, phase whose potential drives it */
     static const int row_of[4] = { 0, 1, 2, 2 };
     static const int phase_of[4] = { 0, 1, 2, 0 };
@@ -274,6 +349,19 @@ static void face_terms(const or_problem *p, int l, int h, const props *cl, const
     }
 }
 
+static void face_terms(const or_problem *p, int l, int h, const props *cl, const props *ch,
+                       double *R, const int32_t *rowptr, const int32_t *colind, double *val)
+{
+    flux_terms(p, l, h, or_transmissibility(p, l, h), depth_of(p, l) - depth_of(p, h), cl, ch, R, rowptr,
+               colind, val);
+}
+
+double or_transfer(const or_problem *p, int g)
+{
+    return p->tcoef * p->sigma * p->km[g] * p->dx * p->dy * p->dz;
+}
+
+/* faces between (fracture) cells, then the fracture-matrix transfers */
 static void for_each_face(const or_problem *p, const props *c, double *R, const int32_t *rowptr,
                           const int32_t *colind, double *val)
 {
@@ -286,39 +374,54 @@ static void for_each_face(const or_problem *p, const props *c, double *R, const 
                 if (j < ny - 1) face_terms(p, g, g + nx, &c[g], &c[g + nx], R, rowptr, colind, val);
                 if (k < nz - 1) face_terms(p, g, g + nxy, &c[g], &c[g + nxy], R, rowptr, colind, val);
             }
+    if (p->dual) {
+        int n = nx * ny * nz;
+        for (int g = 0; g < n; g++)
+            flux_terms(p, g, n + g, or_transfer(p, g), 0.0, &c[g], &c[n + g], R, rowptr, colind, val);
+    }
 }
 
 /* Peaceman well terms (Section 2.3): q = WI * lambda * b * (p_h - p - rho g (z_h - z)).
- * The residual subtracts the source, so R -= q and J -= dq. */
-static int well_terms(const or_problem *p, const props *c, double *R, const int32_t *rowptr,
+ * The residual subtracts the source, so R -= q and J -= dq.  For a fixed-rate
+ * well p_h is the unknown of its well row: the cell rows also get dq/dp_h in
+ * column 0 of their block in the well's column, and the well row collects the
+ * rate constraint. */
+static int well_terms(const or_problem *p, const props *c, const double *x, double *R, const int32_t *rowptr,
                       const int32_t *colind, double *val)
 {
     double g = p->gravity ? p->grav : 0.0;
     for (int w = 0; w < p->nwells; w++) {
-        if (p->w_ctrl[w] != 0) return OR_ERR_ARG;   /* only fixed-BHP controls */
+        int ctrl = p->w_ctrl[w];
+        if (ctrl != OR_CTRL_BHP && ctrl != OR_CTRL_WRATE && ctrl != OR_CTRL_LRATE) return OR_ERR_ARG;
+        if (ctrl == OR_CTRL_WRATE && !p->w_inj[w]) return OR_ERR_ARG;
+        if (ctrl == OR_CTRL_LRATE && p->w_inj[w]) return OR_ERR_ARG;
+        int wr = well_row(p, w);
+        double ph = wr < 0 ? p->w_target[w] : x[3 * wr];
         int top = p->w_i[w] + p->nx * (p->w_j[w] + p->ny * p->w_ktop[w]);
         double zh = depth_of(p, top);
+        double *Jww = (val && wr >= 0) ? block_at(rowptr, colind, val, wr, wr) : NULL;
         for (int k = p->w_ktop[w]; k <= p->w_kbot[w]; k++) {
             int cell = p->w_i[w] + p->nx * (p->w_j[w] + p->ny * k);
             const props *cc = &c[cell];
             double WI = or_well_index(p, cell, p->w_rw[w], p->w_skin[w]);
             double dz = zh - depth_of(p, cell);
-            double q[3] = { 0, 0, 0 }, dq[3][3];
+            double q[3] = { 0, 0, 0 }, dq[3][3], dqh[3] = { 0, 0, 0 };
             memset(dq, 0, sizeof dq);
             if (p->w_inj[w]) {
                 double lt = cc->lo + cc->lw + cc->lg;
                 double lt_w = cc->lo_w + cc->lw_w, lt_g = cc->lo_g + cc->lg_g;
                 if (!p->inj_total_mobility) { lt = cc->lw; lt_w = cc->lw_w; lt_g = 0.0; }
-                double dw = p->w_target[w] - cc->p - cc->rw * g * dz;
+                double dw = ph - cc->p - cc->rw * g * dz;
                 double dw_p = -1.0 - cc->drw * g * dz;
                 q[1] = WI * lt * cc->bw * dw;
                 dq[1][0] = WI * lt * (cc->dbw * dw + cc->bw * dw_p);
                 dq[1][1] = WI * lt_w * cc->bw * dw;
                 dq[1][2] = WI * lt_g * cc->bw * dw;
+                dqh[1] = WI * lt * cc->bw;
             } else {
-                double d_o = p->w_target[w] - cc->p - cc->ro * g * dz;
-                double d_w = p->w_target[w] - cc->p - cc->rw * g * dz;
-                double d_g = p->w_target[w] - cc->p - cc->rg * g * dz;
+                double d_o = ph - cc->p - cc->ro * g * dz;
+                double d_w = ph - cc->p - cc->rw * g * dz;
+                double d_g = ph - cc->p - cc->rg * g * dz;
                 double do_p = -1.0 - cc->dro * g * dz;
                 double dw_p = -1.0 - cc->drw * g * dz;
                 double dg_p = -1.0 - cc->drg * g * dz;
@@ -334,6 +437,9 @@ static int well_terms(const or_problem *p, const props *c, double *R, const int3
                 dq[2][0] = WI * cc->lg * (cc->dbg * d_g + cc->bg * dg_p) + cc->drs * q[0] + cc->rs * dq[0][0];
                 dq[2][1] = cc->rs * dq[0][1];
                 dq[2][2] = WI * cc->lg_g * cc->bg * d_g + cc->rs * dq[0][2];
+                dqh[0] = WI * cc->lo * cc->bo;
+                dqh[1] = WI * cc->lw * cc->bw;
+                dqh[2] = WI * cc->lg * cc->bg + cc->rs * dqh[0];
             }
             for (int r = 0; r < 3; r++) R[3 * cell + r] -= q[r];
             if (val) {
@@ -341,6 +447,26 @@ static int well_terms(const or_problem *p, const props *c, double *R, const int3
                 for (int r = 0; r < 3; r++)
                     for (int s = 0; s < 3; s++) J[3 * r + s] -= dq[r][s];
             }
+            if (wr < 0) continue;
+            /* rate constraint: injected water, or produced oil + water */
+            double sgn = p->w_inj[w] ? 1.0 : -1.0;
+            double qc = p->w_inj[w] ? q[1] : q[0] + q[1];
+            double dqc[3], dqch = p->w_inj[w] ? dqh[1] : dqh[0] + dqh[1];
+            for (int s = 0; s < 3; s++) dqc[s] = p->w_inj[w] ? dq[1][s] : dq[0][s] + dq[1][s];
+            R[3 * wr] += sgn * qc;
+            if (val) {
+                double *Jcw = block_at(rowptr, colind, val, cell, wr);
+                double *Jwc = block_at(rowptr, colind, val, wr, cell);
+                for (int r = 0; r < 3; r++) Jcw[3 * r] -= dqh[r];
+                for (int s = 0; s < 3; s++) Jwc[s] += sgn * dqc[s];
+                Jww[0] += sgn * dqch;
+            }
+        }
+        if (wr >= 0) {
+            R[3 * wr] -= p->w_target[w];
+            R[3 * wr + 1] = x[3 * wr + 1];
+            R[3 * wr + 2] = x[3 * wr + 2];
+            if (Jww) { Jww[4] = 1.0; Jww[8] = 1.0; }
         }
     }
     return OR_OK;
@@ -349,16 +475,17 @@ static int well_terms(const or_problem *p, const props *c, double *R, const int3
 int or_assemble(const or_problem *p, const double *x_old, const double *x_new, double dt,
                 double *R, const int32_t *rowptr, const int32_t *colind, double *val)
 {
-    int n = p->nx * p->ny * p->nz;
-    if (n <= 0 || dt <= 0.0) return OR_ERR_ARG;
-    props *cn = malloc(sizeof(props) * (size_t)n);
+    int nc, rows = or_rows(p, &nc);
+    if (ncells(p) <= 0 || dt <= 0.0) return OR_ERR_ARG;
+    if (p->dual && (!p->km || !p->phim || !(p->sigma > 0.0))) return OR_ERR_ARG;
+    props *cn = malloc(sizeof(props) * (size_t)nc);
     if (!cn) return OR_ERR_ALLOC;
-    for (int g = 0; g < n; g++) cell_props(p, g, x_new, &cn[g]);
-    memset(R, 0, sizeof(double) * 3 * (size_t)n);
-    if (val) memset(val, 0, sizeof(double) * 9 * (size_t)rowptr[n]);
+    for (int g = 0; g < nc; g++) cell_props(p, g, x_new, &cn[g]);
+    memset(R, 0, sizeof(double) * 3 * (size_t)rows);
+    if (val) memset(val, 0, sizeof(double) * 9 * (size_t)rowptr[rows]);
     /* accumulation: V_b / (5.615 dt) * (m(x_new) - m(x_old)) */
     double acc = p->dx * p->dy * p->dz / (p->rb_ft3 * dt);
-    for (int g = 0; g < n; g++) {
+    for (int g = 0; g < nc; g++) {
         props co;
         cell_props(p, g, x_old, &co);
         double m1[3], dm1[3][3], m0[3];
@@ -372,21 +499,22 @@ int or_assemble(const or_problem *p, const double *x_old, const double *x_new, d
         }
     }
     for_each_face(p, cn, R, rowptr, colind, val);
-    int st = well_terms(p, cn, R, rowptr, colind, val);
+    int st = well_terms(p, cn, x_new, R, rowptr, colind, val);
     free(cn);
     if (st != OR_OK) return st;
-    for (int e = 0; e < 3 * n; e++)
+    for (int e = 0; e < 3 * rows; e++)
         if (!isfinite(R[e])) return OR_ERR_NONFINITE;
     return OR_OK;
 }
 
 int or_flux_residual(const or_problem *p, const double *x, double *R)
 {
-    int n = p->nx * p->ny * p->nz;
-    props *c = malloc(sizeof(props) * (size_t)n);
+    int nc;
+    or_rows(p, &nc);
+    props *c = malloc(sizeof(props) * (size_t)nc);
     if (!c) return OR_ERR_ALLOC;
-    for (int g = 0; g < n; g++) cell_props(p, g, x, &c[g]);
-    memset(R, 0, sizeof(double) * 3 * (size_t)n);
+    for (int g = 0; g < nc; g++) cell_props(p, g, x, &c[g]);
+    memset(R, 0, sizeof(double) * 3 * (size_t)nc);
     for_each_face(p, c, R, NULL, NULL, NULL);
     free(c);
     return OR_OK;

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 OR_OK, OR_NOT_CONVERGED = 0, 1
 F_BJ, F_ILU_NATURAL, F_ILU_RB, F_ILU_TILED = 0, 1, 2, 3
 QI_DIAG, QI_BLOCK = 0, 1
-SMOOTH_GS, SMOOTH_JACOBI = 0, 1
+SMOOTH_GS, SMOOTH_JACOBI, SMOOTH_L1 = 0, 1, 2
+CTRL = {"bhp": 0, "wrat": 1, "lrat": 2}
 PREC_FP64, PREC_FP32, PREC_FP32_BF16 = 0, 1, 2
 CSMOOTH_JACOBI, CSMOOTH_L1 = 0, 1
 
@@ -45,6 +46,7 @@ class OrProblem(C.Structure):
         ("nwells", C.c_int),
         ("w_i", _ip), ("w_j", _ip), ("w_ktop", _ip), ("w_kbot", _ip), ("w_inj", _ip), ("w_ctrl", _ip),
         ("w_target", _dp), ("w_rw", _dp), ("w_skin", _dp),
+        ("dual", C.c_int), ("km", _dp), ("phim", _dp), ("sigma", C.c_double),
     ]
 
 
@@ -52,7 +54,7 @@ class CprOpts(C.Structure):
     _fields_ = [("fpf", C.c_int), ("ftype", C.c_int), ("tile_x", C.c_int), ("tile_y", C.c_int),
                 ("theta", C.c_double), ("coarse_max", C.c_int), ("max_levels", C.c_int),
                 ("smoother", C.c_int), ("sweeps", C.c_int), ("use_amg", C.c_int), ("qi_mode", C.c_int),
-                ("precision", C.c_int), ("csmoother", C.c_int)]
+                ("precision", C.c_int), ("csmoother", C.c_int), ("npr", C.c_int)]
 
 
 class FgmresOpts(C.Structure):
@@ -77,6 +79,9 @@ def lib():
     L = C.CDLL(LIB_PATH)
     P = C.POINTER(OrProblem)
     L.or_relperm.argtypes = [P, C.c_double, C.c_double, _f64p]
+    L.or_rows.argtypes = [P, C.POINTER(C.c_int)]
+    L.or_transfer.argtypes = [P, C.c_int]
+    L.or_transfer.restype = C.c_double
     L.or_transmissibility.argtypes = [P, C.c_int, C.c_int]
     L.or_transmissibility.restype = C.c_double
     L.or_pore_volume.argtypes = [P, C.c_int, C.c_double]
@@ -159,11 +164,18 @@ class Problem:
         s.w_ktop = i([w.k_top for w in W] or [0])
         s.w_kbot = i([w.k_bot for w in W] or [0])
         s.w_inj = i([1 if w.kind == "inj" else 0 for w in W] or [0])
-        s.w_ctrl = i([0 if w.control == "bhp" else 1 for w in W] or [0])
+        s.w_ctrl = i([CTRL[w.control] for w in W] or [0])
         s.w_target = d([w.target for w in W] or [0.0])
         s.w_rw = d([w.rw for w in W] or [0.25])
         s.w_skin = d([w.skin for w in W] or [0.0])
+        s.dual = int(getattr(case, "dual", False))
+        s.km = d(case.km if s.dual else [0.0])
+        s.phim = d(case.phim if s.dual else [0.0])
+        s.sigma = float(getattr(case, "sigma", 0.0))
         self.s = s
+        nc = C.c_int()
+        self.rows = lib().or_rows(self.ref, C.byref(nc))
+        self.ncell = nc.value
 
     @property
     def ref(self):
@@ -193,7 +205,7 @@ def pattern(prob: Problem):
     L = lib()
     nnzb = L.or_pattern(prob.ref, None, None)
     n = prob.case.n
-    rp = np.zeros(n + 1, np.int32)
+    rp = np.zeros(prob.rows + 1, np.int32)
     ci = np.zeros(nnzb, np.int32)
     L.or_pattern(prob.ref, rp.ctypes.data, ci.ctypes.data)
     return rp, ci
@@ -203,7 +215,7 @@ def residual(prob: Problem, x_old=None, x_new=None, dt=None) -> np.ndarray:
     c = prob.case
     x_old = np.ascontiguousarray(c.x_old if x_old is None else x_old, dtype=np.float64)
     x_new = np.ascontiguousarray(c.x_new if x_new is None else x_new, dtype=np.float64)
-    R = np.zeros(3 * c.n)
+    R = np.zeros(3 * prob.rows)
     st = lib().or_assemble(prob.ref, x_old, x_new, c.dt if dt is None else dt, R, None, None, None)
     if st != OR_OK:
         raise RuntimeError(f"or_assemble failed: {st}")
@@ -217,7 +229,7 @@ def jacobian(prob: Problem, x_old=None, x_new=None, dt=None):
     x_new = np.ascontiguousarray(c.x_new if x_new is None else x_new, dtype=np.float64)
     rp, ci = pattern(prob)
     val = np.zeros(9 * len(ci))
-    R = np.zeros(3 * c.n)
+    R = np.zeros(3 * prob.rows)
     st = lib().or_assemble(prob.ref, x_old, x_new, c.dt if dt is None else dt, R,
                            rp.ctypes.data, ci.ctypes.data, val.ctypes.data)
     if st != OR_OK:
@@ -228,9 +240,13 @@ def jacobian(prob: Problem, x_old=None, x_new=None, dt=None):
 def flux_residual(prob: Problem, x=None) -> np.ndarray:
     c = prob.case
     x = np.ascontiguousarray(c.x_new if x is None else x, dtype=np.float64)
-    R = np.zeros(3 * c.n)
+    R = np.zeros(3 * prob.ncell)
     lib().or_flux_residual(prob.ref, x, R)
     return R
+
+
+def transfer(prob: Problem, g: int) -> float:
+    return lib().or_transfer(prob.ref, g)
 
 
 def bsr_spmv(rp, ci, val, x, alpha=1.0, beta=0.0, y=None, bs=3) -> np.ndarray:
@@ -263,11 +279,13 @@ def qi_decouple(rp, ci, val, mode=1):
 
 def cpr_opts(fpf=0, ftype=F_ILU_TILED, tile=(8, 8), theta=0.08, coarse_max=256, max_levels=12,
              smoother=SMOOTH_GS, sweeps=1, use_amg=1, qi_mode=QI_BLOCK, precision=0,
-             csmoother=1) -> CprOpts:
+             csmoother=1, npr=0) -> CprOpts:
     """precision: PREC_FP64, or the emulated mixed forms PREC_FP32 / PREC_FP32_BF16;
-    csmoother: CSMOOTH_L1 (default) or CSMOOTH_JACOBI on the coarse levels."""
+    csmoother: CSMOOTH_L1 (default) or CSMOOTH_JACOBI on the coarse levels;
+    npr: rows of the pressure system (0: all; the cell rows of a system with
+    fixed-rate well rows)."""
     return CprOpts(fpf, ftype, tile[0], tile[1], theta, coarse_max, max_levels, smoother,
-                   sweeps, use_amg, qi_mode, precision, csmoother)
+                   sweeps, use_amg, qi_mode, precision, csmoother, npr)
 
 
 class Cpr:
@@ -279,6 +297,7 @@ class Cpr:
         self.val = np.ascontiguousarray(val, dtype=np.float64).reshape(-1)
         self.n = len(self.rp) - 1
         self.opts = opts if opts is not None else cpr_opts(**kw)
+        self.npr = self.opts.npr if 0 < self.opts.npr < self.n else self.n
         h = C.c_void_p()
         st = lib().or_cpr_setup(C.addressof(prob.s) if prob is not None else None, self.n,
                                 self.rp, self.ci, self.val, C.byref(self.opts), C.byref(h))
@@ -304,10 +323,10 @@ class Cpr:
         return self._call("or_cpr_apply", v, 3 * self.n)
 
     def restrict(self, v):
-        return self._call("or_cpr_restrict", v, self.n)
+        return self._call("or_cpr_restrict", v, self.npr)
 
     def vcycle(self, b):
-        return self._call("or_cpr_vcycle", b, self.n)
+        return self._call("or_cpr_vcycle", b, self.npr)
 
     def fstage(self, r):
         return self._call("or_cpr_fstage", r, 3 * self.n)

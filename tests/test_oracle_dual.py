@@ -1,0 +1,159 @@
+"""Pins of the oracle's dual-porosity model and fixed-rate wells (CPU only):
+the pattern, the transfer coefficient's closed form, the Jacobian against
+central finite differences in every column, conservation of the fluxes and
+transfers, the rate constraint's p_h derivative in closed form, and the
+single-porosity limit of a vanishing transfer."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import bo_casegen as cg
+
+WELLS = [cg.Well(0, 0, 0, 3, "inj", "wrat", 500.0), cg.Well(5, 4, 0, 3, "prod", "lrat", 400.0),
+         cg.Well(2, 2, 1, 2, "prod", "bhp", 2500.0)]
+
+
+def case(**kw):
+    return cg.make_dual_case(6, 5, 4, seed=3, wells=WELLS, **kw)
+
+
+def test_pattern(oracle_lib):
+    O = oracle_lib
+    c = case()
+    P = O.Problem(c)
+    rp, ci = O.pattern(P)
+    n = c.n
+    assert P.rows == 2 * n + 2 and len(rp) == P.rows + 1
+    for r in range(P.rows):
+        cols = ci[rp[r]:rp[r + 1]]
+        assert np.all(np.diff(cols) > 0)
+        if n <= r < 2 * n:
+            assert list(cols) == [r - n, r]
+        elif r < n:
+            assert n + r in cols
+    # well rows: perforated fracture cells then the row itself
+    w0 = 2 * n
+    assert list(ci[rp[w0]:rp[w0 + 1]]) == [0 + 6 * (0 + 5 * k) for k in range(4)] + [w0]
+
+
+def test_transfer_closed_form(oracle_lib):
+    O = oracle_lib
+    c = case()
+    P = O.Problem(c)
+    sigma = 4.0 * 3 / 100.0
+    assert c.sigma == pytest.approx(sigma, rel=1e-15)
+    for g in (0, 17, 119):
+        assert O.transfer(P, g) == pytest.approx(0.001127 * sigma * c.km[g] * 50 * 50 * 10, rel=1e-14)
+
+
+def test_jacobian_matches_finite_differences(oracle_lib):
+    O = oracle_lib
+    c = case()
+    P = O.Problem(c)
+    rp, ci, val, R = O.jacobian(P)
+    A = O.bsr_to_dense(rp, ci, val)
+    x = c.x_new
+    worst = 0.0
+    for j in range(len(x)):
+        if j >= 3 * 2 * c.n and j % 3 != 0:
+            continue  # dummy unknowns of the well rows: identity, checked below
+        h = 1e-6 * max(abs(x[j]), 1.0) if j % 3 == 0 else 1e-7
+        xp, xm = x.copy(), x.copy()
+        xp[j] += h
+        xm[j] -= h
+        fd = (O.residual(P, x_new=xp) - O.residual(P, x_new=xm)) / (2 * h)
+        scale = max(np.abs(A[:, j]).max(), 1e-300)
+        worst = max(worst, np.abs(fd - A[:, j]).max() / scale)
+    assert worst <= 1e-6, worst
+    for w in range(2):
+        r = 2 * c.n + w
+        blk = val[[e for e in range(rp[r], rp[r + 1]) if ci[e] == r][0]]
+        assert blk[1, 1] == 1.0 and blk[2, 2] == 1.0 and not blk[1:, 0].any()
+
+
+def test_fluxes_and_transfers_conserve_mass(oracle_lib):
+    O = oracle_lib
+    c = case()
+    P = O.Problem(c)
+    F = O.flux_residual(P)
+    assert len(F) == 3 * 2 * c.n
+    for comp in range(3):
+        tot = F[comp::3].sum()
+        assert abs(tot) <= 1e-12 * np.abs(F[comp::3]).sum()
+    # the transfer alone: matrix rows are minus their fracture's transfer part
+    c0 = dataclasses.replace(c, km=np.zeros(c.n))
+    F0 = O.flux_residual(O.Problem(c0))
+    assert not F0[3 * c.n:].any()
+    assert np.allclose((F - F0)[:3 * c.n], -F[3 * c.n:], rtol=1e-12, atol=1e-12 * np.abs(F).max())
+
+
+def test_rate_constraint_bhp_derivative(oracle_lib):
+    """d(rate residual)/d p_h = sum over perforations of WI lambda b, with the
+    injector's total mobility and b_w, the producer's oil + water."""
+    O = oracle_lib
+    c = case()
+    P = O.Problem(c)
+    rp, ci, val, R = O.jacobian(P)
+    f = c.fluid
+    for w, r in ((0, 2 * c.n), (1, 2 * c.n + 1)):
+        W = WELLS[w]
+        blk = val[[e for e in range(rp[r], rp[r + 1]) if ci[e] == r][0]]
+        ref = 0.0
+        for k in range(W.k_top, W.k_bot + 1):
+            g = W.i + c.nx * (W.j + c.ny * k)
+            p, sw, sg = c.x_new[3 * g:3 * g + 3]
+            kr = O.relperm(P, sw, sg)
+            bw = 1.0 / (f["Bw0"] * (1 - f["cw"] * (p - f["p_ref"])))
+            bo = 1.0 / (f["Bo0"] * (1 - f["co"] * (p - f["p_ref"])))
+            wi = O.well_index(P, g)
+            if W.kind == "inj":
+                lt = kr["krw"] / f["mu_w"] + kr["kro"] / f["mu_o"] + kr["krg"] / f["mu_g"]
+                ref += wi * lt * bw
+            else:
+                ref -= wi * (kr["kro"] / f["mu_o"] * bo + kr["krw"] / f["mu_w"] * bw)
+        assert blk[0, 0] == pytest.approx(ref, rel=1e-12)
+
+
+def test_vanishing_transfer_reduces_to_single_porosity(oracle_lib):
+    O = oracle_lib
+    wells = [cg.Well(0, 0, 0, 3, "inj", "bhp", 3500.0), cg.Well(5, 4, 0, 3, "prod", "bhp", 2500.0)]
+    c = cg.make_dual_case(6, 5, 4, seed=3, wells=wells)
+    c = dataclasses.replace(c, km=np.zeros(c.n))
+    rp, ci, val, R = O.jacobian(O.Problem(c))
+    n = c.n
+    s = dataclasses.replace(c, dual=False, km=None, phim=None, sigma=0.0,
+                            x_old=c.x_old[:3 * n], x_new=c.x_new[:3 * n])
+    rp1, ci1, val1, R1 = O.jacobian(O.Problem(s))
+    assert np.array_equal(R[:3 * n], R1)
+    for r in range(n):
+        cols = [e for e in range(rp[r], rp[r + 1]) if ci[e] < n]
+        assert np.array_equal(ci[cols], ci1[rp1[r]:rp1[r + 1]])
+        assert np.array_equal(val[cols], val1[rp1[r]:rp1[r + 1]])
+
+
+@pytest.mark.parametrize("ftype", ["bj", "natural"])
+def test_cpr_on_dual_system_matches_dense_solve(oracle_lib, ftype):
+    """CPR with the pressure system over the cell rows only (the well rows stay
+    out of A_pp) and an l1-Jacobi level-0 smoother (the dual graph has no grid
+    colouring): FGMRES reaches the exact solution of a tiny system."""
+    O = oracle_lib
+    c = cg.make_dual_case(4, 3, 3, seed=5, wells=[cg.Well(0, 0, 0, 2, "inj", "wrat", 300.0),
+                                                   cg.Well(3, 2, 0, 2, "prod", "lrat", 250.0)])
+    P = O.Problem(c)
+    rp, ci, val, R = O.jacobian(P)
+    b = -R
+    ft = dict(bj=O.F_BJ, natural=O.F_ILU_NATURAL)[ftype]
+    pc = O.Cpr(P, rp, ci, val, ftype=ft, smoother=O.SMOOTH_L1, npr=P.ncell, coarse_max=10)
+    assert pc.nlevels() >= 2 and pc.npr == 2 * c.n
+    x, info = O.fgmres(rp, ci, val, b, pc, rtol=1e-12)
+    A = O.bsr_to_dense(rp, ci, val)
+    xs = O.dense_solve(A, b)
+    cond = np.linalg.cond(A)
+    assert info["converged"]
+    assert np.linalg.norm(x - xs) <= cond * 1e-12 * np.linalg.norm(xs)
+    # the well rows are outside A_pp: restricting a vector that is zero on the
+    # cell rows gives zero
+    v = np.zeros(3 * P.rows)
+    v[3 * 2 * c.n:] = 1.0
+    assert not pc.restrict(v).any()
