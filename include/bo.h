@@ -85,10 +85,19 @@ typedef struct {
 typedef struct {
     int32_t i, j, k_top, k_bot;
     int32_t injector;   /* 1: water injector, 0: producer */
-    int32_t control;    /* 0: fixed bottom-hole pressure (Section 2.3); others unsupported */
-    double target;      /* bottom-hole pressure at the top perforation's depth, psi */
+    int32_t control;    /* BO_CTRL_* (Section 2.3) */
+    double target;      /* BO_CTRL_BHP: bottom-hole pressure at the top perforation's
+                           depth, psi; rate controls: rate in STB/day (> 0 for
+                           injection and production alike) */
     double rw, skin;    /* wellbore radius (ft) and skin */
 } bo_well;
+
+/* Well controls (Section 2.3).  A fixed-rate well adds one block row after the
+ * cell rows, in well order, with unknowns (p_h, 0, 0): row 0 is the rate
+ * constraint sum_m q_m - target (injected water for BO_CTRL_WRATE, which
+ * needs an injector; produced oil + water for BO_CTRL_LRATE, which needs a
+ * producer), rows 1 and 2 the identity. */
+enum { BO_CTRL_BHP = 0, BO_CTRL_WRATE = 1, BO_CTRL_LRATE = 2 };
 
 typedef struct {
     int32_t nx, ny, nz;
@@ -99,22 +108,35 @@ typedef struct {
     bo_fluid fluid;
     int32_t nwells;
     const bo_well *wells;       /* [host] nwells entries; no two perforations may share a cell */
+    /* dual porosity (fractured reservoirs, Section 2.1): with dual != 0 each
+     * location g also holds a matrix cell, block row N + g, exchanging fluid
+     * only with its fracture cell g through T_mf = tcoef sigma km V_b (upstream
+     * weighted, same depth); kx, ky, kz and phi0 then describe the fractures,
+     * wells perforate fracture cells */
+    int32_t dual;
+    const double *km;           /* N matrix permeabilities, mD (dual only) */
+    const double *phim;         /* N matrix porosities at p_ref (dual only) */
+    double sigma;               /* shape factor, ft^-2 (dual only) */
 } bo_problem;
 
 /* ---- a1: Jacobian and right-hand side -------------------------------- */
 
-/* [host only] Sizes of the Jacobian of `p`: nbrows = N, nnzb = blocks of the
- * 7-point pattern.  Fails with BO_ERR_INVALID_ARG when 9*nnzb overflows int32
- * addressing assumptions are violated (N >= 2^31/7). */
+/* [host only] Sizes of the Jacobian of `p`: nbrows = N cell rows (2N with
+ * dual porosity) plus one per fixed-rate well; nnzb = blocks of the 7-point
+ * pattern, plus the fracture-matrix pairs (3 per location), plus 2 per
+ * perforation of a fixed-rate well and 1 per such well.  Fails with
+ * BO_ERR_INVALID_ARG when indices would overflow int32. */
 bo_status bo_jacobian_bsr_size(const bo_problem *p, int32_t *nbrows, int32_t *nnzb);
 
 /* Residual R of the discrete black-oil equations (Sections 2.1, 2.3, 3) at the
- * Newton iterate x_new (3N) with old state x_old (3N) and time step dt (days),
- * and its analytic Jacobian dR/dx_new.  Writes J's pattern and values into the
- * caller-allocated J (rowptr N+1, colind nnzb, val 9*nnzb from
- * bo_jacobian_bsr_size) and b = -R (3N), so that J dx = b is the Newton
- * system.  Residual rows are per unit surface volume (STB/day for oil and water,
- * Mscf/day for gas). */
+ * Newton iterate x_new with old state x_old (3 nbrows each; a fixed-rate
+ * well's entries are (p_h, 0, 0)) and time step dt (days), and its analytic
+ * Jacobian dR/dx_new.  Writes J's pattern and values into the caller-allocated
+ * J (rowptr nbrows+1, colind nnzb, val 9*nnzb from bo_jacobian_bsr_size) and
+ * b = -R, so that J dx = b is the Newton system.  Row order: fracture (or
+ * single-porosity) cells, matrix cells, fixed-rate wells; columns ascending
+ * (stencil, then the matrix cell, then the well).  Residual rows are per unit
+ * surface volume (STB/day for oil and water, Mscf/day for gas). */
 bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, const double *x_new, double dt,
                           bo_bsr *J, double *b, void *stream);
 
@@ -127,7 +149,9 @@ bo_status bo_bsr_spmv(const bo_bsr *A, double alpha, const double *x, double bet
 /* ---- a2-a6: CPR preconditioner --------------------------------------- */
 
 enum { BO_F_BJ = 0, BO_F_ILU_TILED = 3 };          /* F stage: block Jacobi / tiled block ILU(0) */
-enum { BO_SMOOTH_GS = 0, BO_SMOOTH_JACOBI = 1 };   /* level-0 smoother */
+/* level-0 smoother: red-black Gauss-Seidel (needs the grid), damped Jacobi,
+ * or l1-Jacobi (for the general form without a grid) */
+enum { BO_SMOOTH_GS = 0, BO_SMOOTH_JACOBI = 1, BO_SMOOTH_L1 = 2 };
 /* smoother of the levels between the finest and the coarsest: l1-Jacobi,
  * x += (b - A x) / sum_j |a_ij| (hypre's l1 smoother, robust where Galerkin
  * products of a high-contrast pressure matrix lose diagonal dominance), or
@@ -158,6 +182,9 @@ typedef struct {
     int32_t qi_mode;        /* BO_QI_* */
     int32_t precision;      /* BO_PREC_*: storage/arithmetic of the AMG hierarchy and ILU factors */
     int32_t csmoother;      /* BO_CSMOOTH_*: levels between the finest and the coarsest */
+    int32_t npr;            /* general form: the pressure system is the first npr block
+                               rows (cells; later rows, e.g. fixed-rate wells, stay out
+                               of A_pp and are only smoothed by the F stage); 0: all */
 } bo_cpr_opts;
 
 /* Fills `o` [host] with the defaults: PF, tiled ILU0 8x8, theta 0.08,
@@ -174,7 +201,11 @@ typedef struct { int32_t nx, ny, nz; } bo_grid;
 /* Builds the CPR preconditioner of A (Section 3.2): quasi-IMPES weights and the
  * decoupled pressure block, the AMG hierarchy on it, and the F-stage factors.
  * Keeps a private copy of A's values in its own layout; A may be freed after
- * return.  Synchronises `stream` (the hierarchy sizes are decided on the host). */
+ * return.  Synchronises `stream` (the hierarchy sizes are decided on the host).
+ * grid == NULL selects the general form for any block pattern (e.g. dual
+ * porosity with fixed-rate wells): A is kept in BSR form, the pressure system
+ * is the first opts->npr rows, the level-0 smoother must be Jacobi or l1-Jacobi
+ * and the F stage block Jacobi. */
 bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
                        bo_cpr **out, void *stream);
 /* Rebuilds pc for new values of a matrix with the same grid, pattern and

@@ -21,10 +21,11 @@ BO_OK, BO_NOT_CONVERGED = 0, 1
 BO_ERR_INVALID_ARG, BO_ERR_HIP, BO_ERR_ALLOC, BO_ERR_NONFINITE = -1, -2, -3, -4
 BO_ERR_SINGULAR_BLOCK, BO_ERR_SINGULAR_COARSE, BO_ERR_UNSUPPORTED = -5, -6, -8
 BO_F_BJ, BO_F_ILU_TILED = 0, 3
-BO_SMOOTH_GS, BO_SMOOTH_JACOBI = 0, 1
+BO_SMOOTH_GS, BO_SMOOTH_JACOBI, BO_SMOOTH_L1 = 0, 1, 2
 BO_QI_DIAG, BO_QI_BLOCK = 0, 1
 BO_PREC_FP64, BO_PREC_FP32, BO_PREC_FP32_BF16 = 0, 1, 2
 BO_CSMOOTH_JACOBI, BO_CSMOOTH_L1 = 0, 1
+BO_CTRL_BHP, BO_CTRL_WRATE, BO_CTRL_LRATE = 0, 1, 2
 
 EXPORTS = [
     "bo_last_error", "bo_version", "bo_jacobian_bsr_size", "bo_jacobian_bsr", "bo_bsr_spmv",
@@ -66,14 +67,16 @@ class BoProblem(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("top_depth", C.c_double),
                 ("kx", C.c_void_p), ("ky", C.c_void_p), ("kz", C.c_void_p), ("phi0", C.c_void_p),
-                ("fluid", BoFluid), ("nwells", C.c_int32), ("wells", C.POINTER(BoWell))]
+                ("fluid", BoFluid), ("nwells", C.c_int32), ("wells", C.POINTER(BoWell)),
+                ("dual", C.c_int32), ("km", C.c_void_p), ("phim", C.c_void_p), ("sigma", C.c_double)]
 
 
 class BoCprOpts(C.Structure):
     _fields_ = [("fpf", C.c_int32), ("ftype", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
                 ("theta", C.c_double), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("smoother", C.c_int32), ("sweeps", C.c_int32), ("use_amg", C.c_int32),
-                ("qi_mode", C.c_int32), ("precision", C.c_int32), ("csmoother", C.c_int32)]
+                ("qi_mode", C.c_int32), ("precision", C.c_int32), ("csmoother", C.c_int32),
+                ("npr", C.c_int32)]
 
 
 class BoGrid(C.Structure):
@@ -186,15 +189,17 @@ def problem_from_case(case, device="cuda") -> DeviceProblem:
                                          "swc", "sor", "sorg", "sgc")],
                  int(f["nw"]), int(f["no"]), int(f["ng"]), float(f["tcoef"]), float(f["rb_ft3"]),
                  float(f["grav"]), int(case.gravity), int(case.inj_total_mobility))
-    t = tuple(torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
-              for a in (case.kx, case.ky, case.kz, case.phi0))
+    dual = bool(getattr(case, "dual", False))
+    fields = [case.kx, case.ky, case.kz, case.phi0] + ([case.km, case.phim] if dual else [])
+    t = tuple(torch.as_tensor(a, dtype=torch.float64).to(device).contiguous() for a in fields)
     W = (BoWell * max(len(case.wells), 1))()
     for q, w in enumerate(case.wells):
-        ctrl = {"bhp": 0, "wrat": 1, "orat": 2, "lrat": 3}[w.control]
+        ctrl = {"bhp": BO_CTRL_BHP, "wrat": BO_CTRL_WRATE, "lrat": BO_CTRL_LRATE}[w.control]
         W[q] = BoWell(w.i, w.j, w.k_top, w.k_bot, 1 if w.kind == "inj" else 0, ctrl, w.target, w.rw, w.skin)
     s = BoProblem(case.nx, case.ny, case.nz, case.dx, case.dy, case.dz, case.top_depth,
                   _ptr(t[0]), _ptr(t[1]), _ptr(t[2]), _ptr(t[3]), fl, len(case.wells),
-                  C.cast(W, C.POINTER(BoWell)))
+                  C.cast(W, C.POINTER(BoWell)), int(dual), _ptr(t[4]) if dual else None,
+                  _ptr(t[5]) if dual else None, float(getattr(case, "sigma", 0.0)))
     return DeviceProblem(s, t, W)
 
 
@@ -285,11 +290,13 @@ class Cpr:
 
 
 def bo_cpr_setup(A: DeviceBsr, grid, opts: Optional[BoCprOpts] = None, stream=None) -> Cpr:
+    """grid: (nx, ny, nz), or None for the general form (see include/bo.h)."""
     o = opts if opts is not None else bo_cpr_default_opts()
-    g = BoGrid(*grid)
+    g = BoGrid(*grid) if grid is not None else None
     h = C.c_void_p()
     s = A.s
-    _check(lib().bo_cpr_setup(C.byref(s), C.byref(g), C.byref(o), C.byref(h), _stream(stream)))
+    _check(lib().bo_cpr_setup(C.byref(s), C.byref(g) if g is not None else None, C.byref(o), C.byref(h),
+                              _stream(stream)))
     return Cpr(h.value, s.nbrows)
 
 

@@ -73,6 +73,65 @@ __global__ void k_qi_decouple(int nx, int ny, int nz, const double *__restrict__
     }
 }
 
+// General BSR form (no grid): the weights c_i of every block row from its
+// diagonal block (a fixed-rate well row has zero saturation couplings, so its
+// weights are (+-1, 0, 0), i.e. no decoupling)
+__global__ void k_qi_weights_bsr(int nrows, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                 const double *__restrict__ val, int mode, double *__restrict__ cw,
+                                 int32_t *__restrict__ bad) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    int e = rp[i];
+    while (e < rp[i + 1] && ci[e] != i) e++;
+    if (e == rp[i + 1]) { *bad = 1; cw[3 * (size_t)i] = 1.0; cw[3 * (size_t)i + 1] = cw[3 * (size_t)i + 2] = 0.0; return; }
+    const double *B = val + 9 * (size_t)e;
+    double a = B[4], b = B[5], c = B[7], d = B[8];
+    double p0 = B[1], p1 = B[2];
+    double w0, w1;
+    if (mode == BO_QI_DIAG) {
+        if (a == 0.0 || d == 0.0) { *bad = 1; w0 = w1 = 0.0; }
+        else { w0 = p0 / a; w1 = p1 / d; }
+    } else {
+        double det = a * d - b * c;
+        if (det == 0.0 || !isfinite(det)) { *bad = 1; w0 = w1 = 0.0; }
+        else {
+            w0 = (p0 * d - p1 * c) / det;
+            w1 = (p1 * a - p0 * b) / det;
+        }
+    }
+    double dpp = B[0] - w0 * B[3] - w1 * B[6];
+    double sg = dpp < 0.0 ? -1.0 : 1.0;
+    cw[3 * (size_t)i] = sg;
+    cw[3 * (size_t)i + 1] = -sg * w0;
+    cw[3 * (size_t)i + 2] = -sg * w1;
+}
+
+// A_pp of the general form: the first npr rows and columns of c_i . A_ij[:, 0]
+__global__ void k_app_counts(int npr, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                             int32_t *__restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npr) return;
+    int c = 0;
+    for (int e = rp[i]; e < rp[i + 1]; e++) c += ci[e] < npr;
+    cnt[i] = c;
+}
+
+__global__ void k_app_fill(int npr, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ val, const double *__restrict__ cw,
+                           const int32_t *__restrict__ prp, int32_t *__restrict__ pci, double *__restrict__ pv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npr) return;
+    double c0 = cw[3 * (size_t)i], c1 = cw[3 * (size_t)i + 1], c2 = cw[3 * (size_t)i + 2];
+    int o = prp[i];
+    for (int e = rp[i]; e < rp[i + 1]; e++) {
+        if (ci[e] >= npr) continue;
+        const double *A = val + 9 * (size_t)e;
+        pci[o] = ci[e];
+        pv[o] = c0 * A[0] + c1 * A[3] + c2 * A[6];
+        o++;
+    }
+}
+
 // level-0 CSR from the slot form (pattern = the 7-point stencil)
 __global__ void k_slots_to_csr(int nx, int ny, int nz, const double *__restrict__ app,
                                const int32_t *__restrict__ rp, int32_t *__restrict__ ci, double *__restrict__ v) {
@@ -890,6 +949,32 @@ static bo_status to_f32(long long n, const double *a, float *b, hipStream_t s) {
 // ---- host: decoupling -------------------------------------------------------------
 bo_status qi_decouple(bo_cpr *pc, hipStream_t s) {
     long long n = pc->n;
+    if (pc->general) {
+        // weights of every row, then A_pp in CSR as level 0 of the hierarchy
+        BO_TRY(pc->cw.alloc(3 * n));
+        BO_HIP(hipMemsetAsync(pc->flag.p, 0, sizeof(int32_t), s));
+        k_qi_weights_bsr<<<grid_for(n), kBlock, 0, s>>>((int)n, pc->Arp.p, pc->Aci.p, pc->Aval.p, pc->o.qi_mode,
+                                                        pc->cw.p, pc->flag.p);
+        BO_HIP(hipGetLastError());
+        int32_t bad = 0;
+        BO_TRY(read_flag(pc->flag.p, s, &bad));
+        if (bad) return fail(BO_ERR_SINGULAR_BLOCK, "quasi-IMPES: singular saturation block or missing diagonal");
+        Level &L0 = pc->lv[0];
+        int npr = pc->npr;
+        L0.n = npr;
+        BO_TRY(pc->sw.cnt.alloc(npr));
+        BO_TRY(L0.rp.alloc(npr + 1));
+        k_app_counts<<<grid_for(npr), kBlock, 0, s>>>(npr, pc->Arp.p, pc->Aci.p, pc->sw.cnt.p);
+        int32_t total = 0;
+        BO_TRY(scan_counts(pc->sw.cnt.p, L0.rp.p, npr, &total, s));
+        L0.nnz = total;
+        BO_TRY(L0.ci.alloc(total));
+        BO_TRY(L0.v.alloc(total));
+        k_app_fill<<<grid_for(npr), kBlock, 0, s>>>(npr, pc->Arp.p, pc->Aci.p, pc->Aval.p, pc->cw.p, L0.rp.p,
+                                                    L0.ci.p, L0.v.p);
+        BO_HIP(hipGetLastError());
+        return BO_OK;
+    }
     BO_TRY(pc->cw.alloc(3 * n));
     BO_TRY(pc->app.alloc(7 * n));
     BO_HIP(hipMemsetAsync(pc->flag.p, 0, sizeof(int32_t), s));
@@ -903,14 +988,14 @@ bo_status qi_decouple(bo_cpr *pc, hipStream_t s) {
 }
 
 bo_status qi_restrict(bo_cpr *pc, const double *v, double *rp, hipStream_t s) {
-    long long n = pc->n;
+    long long n = pc->npr;
     k_qi_restrict<double><<<grid_for(n), kBlock, 0, s>>>(n, pc->cw.p, v, rp);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
 
 bo_status qi_restrict_f32(bo_cpr *pc, const double *v, float *rp, hipStream_t s) {
-    long long n = pc->n;
+    long long n = pc->npr;
     k_qi_restrict<float><<<grid_for(n), kBlock, 0, s>>>(n, pc->cw.p, v, rp);
     BO_HIP(hipGetLastError());
     return BO_OK;
@@ -974,11 +1059,12 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
 bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
     const bo_cpr_opts &o = pc->o;
     int32_t *flag = pc->flag.p;
-    // level 0: CSR with the stencil pattern
+    // level 0: CSR with the stencil pattern (the general form built it with
+    // the decoupling)
     Level &L0 = pc->lv[0];
-    L0.n = pc->n;
     SetupWork &W = pc->sw;
-    {
+    if (!pc->general) {
+        L0.n = pc->n;
         DBuf<int32_t> &cnt = W.cnt;
         BO_TRY(cnt.alloc(L0.n));
         BO_TRY(L0.rp.alloc(L0.n + 1));
@@ -1005,7 +1091,7 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         if (L.n <= o.coarse_max || l + 1 >= max_levels) break;
         int n = L.n;
         BO_TRY(L.sf.alloc(L.nnz));
-        if (l == 0)
+        if (l == 0 && !pc->general)
             k_strength_slots<<<grid_for(n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->app.p, L.rp.p, t2,
                                                              L.sf.p);
         else if ((double)L.nnz / n <= 12.0)
@@ -1210,14 +1296,16 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t 
         return BO_OK;
     }
     T *x;
-    if (l == 0) {
+    const bool slots0 = l == 0 && !pc->general;
+    const bool l1 = l == 0 ? pc->o.smoother == BO_SMOOTH_L1 : pc->o.csmoother == BO_CSMOOTH_L1;
+    if (slots0) {
         x = Prec<T>::x(L);
         k_zero<T><<<grid_for(L.n), kBlock, 0, s>>>(L.n, x);
         BO_TRY(smooth0<T>(pc, b, x, true, s));
         k_resid_slots<T><<<grid_for(L.n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, Prec<T>::app(pc), b, x,
                                                            Prec<T>::r(L));
     } else {
-        BO_TRY(smooth_c<T>(L, pc->o.sweeps, pc->o.csmoother == BO_CSMOOTH_L1, b, nullptr, &x, s));
+        BO_TRY(smooth_c<T>(L, pc->o.sweeps, l1, b, nullptr, &x, s));
         BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), x, OP_RESID, b, nullptr, Prec<T>::r(L), s));
     }
     Level &C = pc->lv[l + 1];
@@ -1226,11 +1314,11 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t 
     T *xc;
     BO_TRY(vcycle_rec<T>(pc, l + 1, Prec<T>::b(C), &xc, s));
     BO_TRY(csr_rowop<T>(L.n, L.pnnz, L.prp.p, L.pci.p, Prec<T>::pv(L), xc, OP_ADD, nullptr, nullptr, x, s));
-    if (l == 0) {
+    if (slots0) {
         BO_TRY(smooth0<T>(pc, b, x, false, s));
         *res = x;
     } else {
-        BO_TRY(smooth_c<T>(L, pc->o.sweeps, pc->o.csmoother == BO_CSMOOTH_L1, b, x, res, s));
+        BO_TRY(smooth_c<T>(L, pc->o.sweeps, l1, b, x, res, s));
     }
     return BO_OK;
 }
@@ -1256,31 +1344,34 @@ bo_status amg_vcycle(bo_cpr *pc, const double *b, double *x, hipStream_t s) {
     if (pc->o.precision != BO_PREC_FP64) {
         // FP64 in and out, FP32 inside: the stage boundaries of the mixed form
         Level &L0 = pc->lv[0];
-        BO_TRY(to_f32(pc->n, b, L0.b32.p, s));
+        BO_TRY(to_f32(pc->npr, b, L0.b32.p, s));
         const float *res;
         BO_TRY(amg_vcycle_ptr_f32(pc, L0.b32.p, &res, s));
-        k_f32_to_f64<<<grid_for(pc->n), kBlock, 0, s>>>(pc->n, res, x);
+        k_f32_to_f64<<<grid_for(pc->npr), kBlock, 0, s>>>(pc->npr, res, x);
         BO_HIP(hipGetLastError());
         return BO_OK;
     }
     const double *res;
     BO_TRY(amg_vcycle_ptr(pc, b, &res, s));
-    if (res != x) BO_HIP(hipMemcpyAsync(x, res, sizeof(double) * pc->n, hipMemcpyDeviceToDevice, s));
+    if (res != x) BO_HIP(hipMemcpyAsync(x, res, sizeof(double) * pc->npr, hipMemcpyDeviceToDevice, s));
     return BO_OK;
 }
 
 // FP32 copies of the hierarchy for the mixed form (the setup itself is FP64)
 bo_status amg_make_f32(bo_cpr *pc, hipStream_t s) {
-    BO_TRY(pc->app32.alloc(7 * (size_t)pc->n));
-    BO_TRY(to_f32(7 * (long long)pc->n, pc->app.p, pc->app32.p, s));
+    if (!pc->general) {
+        BO_TRY(pc->app32.alloc(7 * (size_t)pc->n));
+        BO_TRY(to_f32(7 * (long long)pc->n, pc->app.p, pc->app32.p, s));
+    }
     for (int l = 0; l < pc->nlev; l++) {
         Level &L = pc->lv[l];
+        const bool csr = l > 0 || pc->general;
         BO_TRY(L.x32.alloc(L.n)); BO_TRY(L.b32.alloc(L.n)); BO_TRY(L.r32.alloc(L.n)); BO_TRY(L.t32.alloc(L.n));
-        if (l > 0) {
+        if (csr) {
             BO_TRY(L.v32.alloc(L.nnz));
             BO_TRY(to_f32(L.nnz, L.v.p, L.v32.p, s));
         }
-        if (l > 0 && l + 1 < pc->nlev) {
+        if (csr && l + 1 < pc->nlev) {
             BO_TRY(L.dl132.alloc(L.n));
             BO_TRY(to_f32(L.n, L.dl1.p, L.dl132.p, s));
         }

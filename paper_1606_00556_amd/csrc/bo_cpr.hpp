@@ -56,7 +56,12 @@ struct Krylov {
 struct bo_cpr {
     bool broken = false;          // a failed bo_cpr_update leaves the handle unusable
     bo::Grid g{};
-    int n = 0;                    // cells
+    int n = 0;                    // block rows (the cells of a grid)
+    int npr = 0;                  // rows of the pressure system (the first npr block rows)
+    bool general = false;         // no grid: A kept in BSR form (Arp, Aci, Aval)
+    int nnzb = 0;
+    bo::DBuf<int32_t> Arp, Aci;
+    bo::DBuf<double> Aval;
     bo_cpr_opts o{};
     // operator (copy of A) in slot layout, 63 * N
     bo::DBuf<double> A;

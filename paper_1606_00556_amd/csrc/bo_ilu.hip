@@ -317,6 +317,33 @@ __global__ void k_bj_setup(long long n, const double *__restrict__ A, void *__re
     }
 }
 
+// the same from a general BSR matrix (diagonal block located in each row)
+template <int St>
+__global__ void k_bj_setup_bsr(long long n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                               const double *__restrict__ val, void *__restrict__ einv, int32_t *__restrict__ bad) {
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    size_t N = (size_t)n;
+    int e = rp[g];
+    while (e < rp[g + 1] && ci[e] != (int)g) e++;
+    double E[9], Ei[9];
+    if (e == rp[g + 1]) {
+        *bad = 1;
+        for (int z = 0; z < 9; z++) Ei[z] = 0.0;
+    } else {
+        for (int z = 0; z < 9; z++) E[z] = val[9 * (size_t)e + z];
+        if (!inv3_gj(E, Ei)) {
+            *bad = 1;
+            for (int z = 0; z < 9; z++) Ei[z] = 0.0;
+        }
+    }
+    for (int z = 0; z < 9; z++) {
+        if constexpr (St == ST_F64) ((double *)einv)[(size_t)z * N + g] = Ei[z];
+        else if constexpr (St == ST_F32) ((float *)einv)[(size_t)z * N + g] = (float)Ei[z];
+        else ((uint16_t *)einv)[(size_t)z * N + g] = (uint16_t)bf16_bits((float)Ei[z]);
+    }
+}
+
 template <int St, typename T, typename TD>
 __global__ void k_bj_apply(long long n, const void *__restrict__ einv, const double *__restrict__ r,
                            const TD *__restrict__ dp, double *__restrict__ out) {
@@ -358,7 +385,13 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
     if (pc->o.ftype == BO_F_BJ) {
         BO_TRY(pc->einv.alloc(9 * n));  // FP64 size: large enough for every format
         void *E = pc->einv.p;
-        if (st == ST_F64) k_bj_setup<ST_F64><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
+        if (pc->general) {
+            const int32_t *rp = pc->Arp.p, *ci = pc->Aci.p;
+            const double *v = pc->Aval.p;
+            if (st == ST_F64) k_bj_setup_bsr<ST_F64><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, E, pc->flag.p);
+            else if (st == ST_F32) k_bj_setup_bsr<ST_F32><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, E, pc->flag.p);
+            else k_bj_setup_bsr<ST_BF16><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, E, pc->flag.p);
+        } else if (st == ST_F64) k_bj_setup<ST_F64><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
         else if (st == ST_F32) k_bj_setup<ST_F32><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
         else k_bj_setup<ST_BF16><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
     } else {

@@ -8,11 +8,20 @@
 // the upstream cell of each phase potential carries the mobility, ties going
 // to the lower cell index; face densities are the mean of the two cells.
 //
+// Dual porosity (fractured reservoirs): each location also holds a matrix
+// cell (rows N..2N-1) coupled only to its fracture cell by a transfer term
+// T_mf = tcoef sigma k_m V_b, upstream-weighted like a face at zero depth
+// difference (Kazemi's shape factor; the paper names the model, not its
+// transfer function).  Fixed-rate wells (Section 2.3) add their bottom-hole
+// pressure as an unknown and the rate constraint as a block row.
+//
 // Layout: one thread per cell gathers its own accumulation and its six faces
-// (in the order -z, -y, -x, +x, +y, +z) and writes its whole block row, so no
-// atomics are needed and every face flux is evaluated identically from both
-// sides (lower cell first).  A second kernel adds the well terms (one thread
-// per well; perforated cells are distinct).
+// (in the order -z, -y, -x, +x, +y, +z), then the transfer, and writes its
+// whole block row, so no atomics are needed and every face flux is evaluated
+// identically from both sides (lower cell first).  A second kernel writes the
+// matrix rows, a third the well terms (one thread per well; perforated cells
+// are distinct), including the well rows and the well columns of the
+// perforated cells (the last block of their rows).
 #include "bo_common.hpp"
 
 namespace bo {
@@ -30,6 +39,9 @@ struct GridG {
     int nx, ny, nz;
     double dx, dy, dz, top;
     const double *kx, *ky, *kz, *phi0;
+    int dual;
+    const double *km, *phim;
+    double sigma;
 };
 
 struct Props {
@@ -170,13 +182,16 @@ __device__ inline double trans(const GridG &g, const Fl &f, int a, int b) {
     return f.tcoef * area / (len / (2.0 * ka) + len / (2.0 * kb));
 }
 
-__global__ void k_row_counts(int nx, int ny, int nz, int32_t *cnt) {
+// blocks per row: stencil (+1 for the matrix cell) on fracture rows, 2 on
+// matrix rows; the well columns and well rows are added by k_well_counts
+__global__ void k_row_counts(int nx, int ny, int nz, int dual, int32_t *cnt) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     int n = nx * ny * nz;
     if (g >= n) return;
     int c = 0;
     for (int s = 0; s < NSLOT; s++) c += nbr_of(g, s, nx, ny, nz) >= 0;
-    cnt[g] = c;
+    cnt[g] = c + (dual ? 1 : 0);
+    if (dual) cnt[n + g] = 2;
 }
 
 __global__ void __launch_bounds__(kBlock) k_jac_cells(GridG G, Fl f, const double *__restrict__ xo,
@@ -255,7 +270,35 @@ __global__ void __launch_bounds__(kBlock) k_jac_cells(GridG G, Fl f, const doubl
             }
         }
     }
+    // fracture-matrix transfer (this cell is the lower index)
+    double Jm[9];
+    if (G.dual) {
+        Props cm;
+        props_of(f, G.phim[g], xn + 3 * ((size_t)n + g), cm);
+        double T = f.tcoef * G.sigma * G.km[g] * G.dx * G.dy * G.dz;
+        for (int z = 0; z < 9; z++) Jm[z] = 0.0;
+        for (int st = 0; st < 4; st++) {
+            int row = row_of[st];
+            double dphi = c.p - cm.p;
+            bool up_l = dphi >= 0.0;
+            double M, dM[3];
+            stream_q(up_l ? c : cm, st, M, dM);
+            double F = T * M * dphi;
+            double dFl[3], dFh[3];
+            dFl[0] = T * M * 1.0;
+            dFh[0] = T * M * -1.0;
+            dFl[1] = dFl[2] = dFh[1] = dFh[2] = 0.0;
+            if (up_l) { for (int k = 0; k < 3; k++) dFl[k] = dFl[k] + T * dM[k] * dphi; }
+            else      { for (int k = 0; k < 3; k++) dFh[k] = dFh[k] + T * dM[k] * dphi; }
+            R[row] = R[row] + F;
+            for (int k = 0; k < 3; k++) {
+                Jd[3 * row + k] = Jd[3 * row + k] + dFl[k];
+                Jm[3 * row + k] = Jm[3 * row + k] + dFh[k];
+            }
+        }
+    }
     // write the block row in ascending column order: -z -y -x diag +x +y +z
+    // (matrix cell) (well)
     int e = rowptr[g];
     for (int q = 0; q < 3; q++) {
         if (nb_of[q] < 0) continue;
@@ -272,7 +315,68 @@ __global__ void __launch_bounds__(kBlock) k_jac_cells(GridG G, Fl f, const doubl
         for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Joff[q][z];
         e++;
     }
+    if (G.dual) {
+        colind[e] = n + g;
+        for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Jm[z];
+    }
     for (int r = 0; r < 3; r++) b[3 * (size_t)g + r] = -R[r];
+}
+
+// matrix rows N + g: accumulation with the matrix porosity and minus the
+// fracture-matrix transfer; blocks (fracture g, matrix N + g)
+__global__ void __launch_bounds__(kBlock) k_jac_matrix(GridG G, Fl f, const double *__restrict__ xo,
+                                                        const double *__restrict__ xn, double acc,
+                                                        const int32_t *__restrict__ rowptr,
+                                                        int32_t *__restrict__ colind, double *__restrict__ val,
+                                                        double *__restrict__ b) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = G.nx * G.ny * G.nz;
+    if (g >= n) return;
+    size_t m = (size_t)n + g;
+    Props cm, cf;
+    props_of(f, G.phim[g], xn + 3 * m, cm);
+    props_of(f, G.phi0[g], xn + 3 * (size_t)g, cf);
+    double R[3], Jd[9], Jf[9];
+    {
+        Props co;
+        props_of(f, G.phim[g], xo + 3 * m, co);
+        double m1[3], dm1[3][3], m0[3], dd[3][3];
+        masses(cm, m1, dm1, true);
+        masses(co, m0, dd, false);
+        for (int r = 0; r < 3; r++) R[r] = acc * (m1[r] - m0[r]);
+        for (int r = 0; r < 3; r++)
+            for (int s = 0; s < 3; s++) Jd[3 * r + s] = acc * dm1[r][s];
+    }
+    for (int z = 0; z < 9; z++) Jf[z] = 0.0;
+    const int row_of[4] = {0, 1, 2, 2};
+    double T = f.tcoef * G.sigma * G.km[g] * G.dx * G.dy * G.dz;
+    for (int st = 0; st < 4; st++) {
+        int row = row_of[st];
+        double dphi = cf.p - cm.p;
+        bool up_l = dphi >= 0.0;
+        double M, dM[3];
+        stream_q(up_l ? cf : cm, st, M, dM);
+        double F = T * M * dphi;
+        double dFl[3], dFh[3];
+        dFl[0] = T * M * 1.0;
+        dFh[0] = T * M * -1.0;
+        dFl[1] = dFl[2] = dFh[1] = dFh[2] = 0.0;
+        if (up_l) { for (int k = 0; k < 3; k++) dFl[k] = dFl[k] + T * dM[k] * dphi; }
+        else      { for (int k = 0; k < 3; k++) dFh[k] = dFh[k] + T * dM[k] * dphi; }
+        R[row] = R[row] - F;
+        for (int k = 0; k < 3; k++) {
+            Jf[3 * row + k] = Jf[3 * row + k] - dFl[k];
+            Jd[3 * row + k] = Jd[3 * row + k] - dFh[k];
+        }
+    }
+    int e = rowptr[m];
+    colind[e] = g;
+    colind[e + 1] = (int32_t)m;
+    for (int z = 0; z < 9; z++) {
+        val[9 * (size_t)e + z] = Jf[z];
+        val[9 * (size_t)(e + 1) + z] = Jd[z];
+    }
+    for (int r = 0; r < 3; r++) b[3 * m + r] = -R[r];
 }
 
 // Peaceman well index of a perforated cell (Section 2.3)
@@ -286,43 +390,62 @@ __device__ inline double well_index(const GridG &G, const Fl &f, int cell, doubl
 constexpr int kWellChunk = 64;
 struct WellChunk {
     bo_well w[kWellChunk];
+    int32_t row[kWellChunk];  // block row of a fixed-rate well, -1 for fixed BHP
 };
+
+// pattern counts of the fixed-rate wells: one more block in each perforated
+// cell row (the well column), and nperf + 1 blocks in the well row
+__global__ void k_well_counts(int nx, int ny, int nwells, WellChunk wells, int32_t *cnt) {
+    int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nwells || wells.row[w] < 0) return;
+    bo_well W = wells.w[w];
+    for (int k = W.k_top; k <= W.k_bot; k++) cnt[W.i + nx * (W.j + ny * k)] += 1;
+    cnt[wells.row[w]] = W.k_bot - W.k_top + 2;
+}
 
 // One thread per well (a chunk of up to 64 wells passed by value): subtract
 // the source from R (b += q) and dq from the diagonal block of each
-// perforated cell.
+// perforated cell; for a fixed-rate well also write dq/dp_h into column 0 of
+// the perforated rows' well block (their last block), and the well row: the
+// rate constraint and its derivatives, then the identity rows.
 __global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nwells, WellChunk wells,
-                            const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
+                            const int32_t *__restrict__ rowptr, int32_t *__restrict__ colind,
                             double *__restrict__ val, double *__restrict__ b) {
     int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nwells) return;
     bo_well W = wells.w[w];
+    const int wr = wells.row[w];
     double gg = f.gravity ? f.grav : 0.0;
     int top = W.i + G.nx * (W.j + G.ny * W.k_top);
     double zh = depth_of(G, top);
+    const double ph = wr < 0 ? W.target : xn[3 * (size_t)wr];
+    double Rw = 0.0, Jww = 0.0;
+    int ew = wr >= 0 ? rowptr[wr] : 0;     // next block of the well row
+    const double sgn = W.injector ? 1.0 : -1.0;
     for (int k = W.k_top; k <= W.k_bot; k++) {
         int cell = W.i + G.nx * (W.j + G.ny * k);
         Props c;
         props_of(f, G.phi0[cell], xn + 3 * (size_t)cell, c);
         double WI = well_index(G, f, cell, W.rw, W.skin);
         double dz = zh - depth_of(G, cell);
-        double q[3] = {0.0, 0.0, 0.0}, dq[3][3];
+        double q[3] = {0.0, 0.0, 0.0}, dq[3][3], dqh[3] = {0.0, 0.0, 0.0};
         for (int r = 0; r < 3; r++)
             for (int s = 0; s < 3; s++) dq[r][s] = 0.0;
         if (W.injector) {
             double lt = c.lo + c.lw + c.lg;
             double lt_w = c.lo_w + c.lw_w, lt_g = c.lo_g + c.lg_g;
             if (!f.inj_total_mobility) { lt = c.lw; lt_w = c.lw_w; lt_g = 0.0; }
-            double dw = W.target - c.p - c.rw * gg * dz;
+            double dw = ph - c.p - c.rw * gg * dz;
             double dw_p = -1.0 - c.drw * gg * dz;
             q[1] = WI * lt * c.bw * dw;
             dq[1][0] = WI * lt * (c.dbw * dw + c.bw * dw_p);
             dq[1][1] = WI * lt_w * c.bw * dw;
             dq[1][2] = WI * lt_g * c.bw * dw;
+            dqh[1] = WI * lt * c.bw;
         } else {
-            double d_o = W.target - c.p - c.ro * gg * dz;
-            double d_w = W.target - c.p - c.rw * gg * dz;
-            double d_g = W.target - c.p - c.rg * gg * dz;
+            double d_o = ph - c.p - c.ro * gg * dz;
+            double d_w = ph - c.p - c.rw * gg * dz;
+            double d_g = ph - c.p - c.rg * gg * dz;
             double do_p = -1.0 - c.dro * gg * dz;
             double dw_p = -1.0 - c.drw * gg * dz;
             double dg_p = -1.0 - c.drg * gg * dz;
@@ -338,6 +461,9 @@ __global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nw
             dq[2][0] = WI * c.lg * (c.dbg * d_g + c.bg * dg_p) + c.drs * q[0] + c.rs * dq[0][0];
             dq[2][1] = c.rs * dq[0][1];
             dq[2][2] = WI * c.lg_g * c.bg * d_g + c.rs * dq[0][2];
+            dqh[0] = WI * c.lo * c.bo;
+            dqh[1] = WI * c.lw * c.bw;
+            dqh[2] = WI * c.lg * c.bg + c.rs * dqh[0];
         }
         int dpos = rowptr[cell];
         while (colind[dpos] != cell) dpos++;  // the diagonal is in the row by construction
@@ -346,6 +472,38 @@ __global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nw
             b[3 * (size_t)cell + r] = b[3 * (size_t)cell + r] + q[r];
             for (int s = 0; s < 3; s++) J[3 * r + s] = J[3 * r + s] - dq[r][s];
         }
+        if (wr < 0) continue;
+        // the cell row's well block (its last block)
+        int ec = rowptr[cell + 1] - 1;
+        colind[ec] = wr;
+        double *Jc = val + 9 * (size_t)ec;
+        for (int r = 0; r < 3; r++) {
+            Jc[3 * r] = 0.0 - dqh[r];
+            Jc[3 * r + 1] = 0.0;
+            Jc[3 * r + 2] = 0.0;
+        }
+        // the well row: rate constraint (injected water / produced oil + water)
+        double qc = W.injector ? q[1] : q[0] + q[1];
+        double dqch = W.injector ? dqh[1] : dqh[0] + dqh[1];
+        Rw = Rw + sgn * qc;
+        colind[ew] = cell;
+        double *Jw = val + 9 * (size_t)ew;
+        for (int z = 0; z < 9; z++) Jw[z] = 0.0;
+        for (int s2 = 0; s2 < 3; s2++) Jw[s2] = 0.0 + sgn * (W.injector ? dq[1][s2] : dq[0][s2] + dq[1][s2]);
+        Jww = Jww + sgn * dqch;
+        ew++;
+    }
+    if (wr >= 0) {
+        Rw = Rw - W.target;
+        colind[ew] = wr;
+        double *Jw = val + 9 * (size_t)ew;
+        for (int z = 0; z < 9; z++) Jw[z] = 0.0;
+        Jw[0] = Jww;
+        Jw[4] = 1.0;
+        Jw[8] = 1.0;
+        b[3 * (size_t)wr] = -Rw;
+        b[3 * (size_t)wr + 1] = -xn[3 * (size_t)wr + 1];
+        b[3 * (size_t)wr + 2] = -xn[3 * (size_t)wr + 2];
     }
 }
 
@@ -354,34 +512,68 @@ __global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nw
 
 using namespace bo;
 
-extern "C" bo_status bo_jacobian_bsr_size(const bo_problem *p, int32_t *nbrows, int32_t *nnzb) {
-    if (!p || !nbrows || !nnzb) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr_size: NULL argument");
+namespace {
+// fixed-rate wells and the pattern sizes of a problem (host)
+struct Layout {
+    long long n = 0, cells = 0, rows = 0, nnz = 0;
+    std::vector<int32_t> well_row;
+};
+
+bo_status layout_of(const bo_problem *p, Layout &L) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(BO_ERR_INVALID_ARG, "grid dimensions must be >= 1");
+    if (p->nwells < 0 || (p->nwells > 0 && !p->wells)) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: wells");
     long long n = (long long)p->nx * p->ny * p->nz;
     long long faces = (long long)(p->nx - 1) * p->ny * p->nz + (long long)p->nx * (p->ny - 1) * p->nz +
                       (long long)p->nx * p->ny * (p->nz - 1);
-    long long nnz = n + 2 * faces;
-    if (n >= (1LL << 31) / 7 || nnz >= (1LL << 31))
+    L.n = n;
+    L.cells = n * (p->dual ? 2 : 1);
+    L.nnz = n + 2 * faces + (p->dual ? 3 * n : 0);
+    L.rows = L.cells;
+    L.well_row.assign(p->nwells, -1);
+    for (int w = 0; w < p->nwells; w++) {
+        const bo_well &W = p->wells[w];
+        if (W.control == BO_CTRL_BHP) continue;
+        if (W.control != BO_CTRL_WRATE && W.control != BO_CTRL_LRATE)
+            return fail(BO_ERR_INVALID_ARG, "well " + std::to_string(w) + ": unknown control");
+        if ((W.control == BO_CTRL_WRATE) != (W.injector != 0))
+            return fail(BO_ERR_INVALID_ARG, "well " + std::to_string(w) +
+                                                ": water rate needs an injector, liquid rate a producer");
+        long long nperf = (long long)W.k_bot - W.k_top + 1;
+        L.well_row[w] = (int32_t)L.rows;
+        L.rows++;
+        L.nnz += 2 * nperf + 1;
+    }
+    if (L.rows >= (1LL << 31) / 8 || L.nnz >= (1LL << 31))
         return fail(BO_ERR_INVALID_ARG, "grid too large for 32-bit block indices");
-    *nbrows = (int32_t)n;
-    *nnzb = (int32_t)nnz;
+    return BO_OK;
+}
+}  // namespace
+
+extern "C" bo_status bo_jacobian_bsr_size(const bo_problem *p, int32_t *nbrows, int32_t *nnzb) {
+    if (!p || !nbrows || !nnzb) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr_size: NULL argument");
+    Layout L;
+    BO_TRY(layout_of(p, L));
+    *nbrows = (int32_t)L.rows;
+    *nnzb = (int32_t)L.nnz;
     return BO_OK;
 }
 
 extern "C" bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, const double *x_new, double dt,
                                      bo_bsr *J, double *b, void *stream) {
-    int32_t n, nnz;
-    BO_TRY(bo_jacobian_bsr_size(p, &n, &nnz));
+    if (!p) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL problem");
+    Layout Ly;
+    BO_TRY(layout_of(p, Ly));
+    const int32_t rows = (int32_t)Ly.rows, nnz = (int32_t)Ly.nnz, n = (int32_t)Ly.n;
     if (!x_old || !x_new || !J || !b || !J->rowptr || !J->colind || !J->val)
         return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL pointer");
     if (!(dt > 0.0)) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: dt must be > 0");
     if (!p->kx || !p->ky || !p->kz || !p->phi0) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL field");
-    if (p->nwells < 0 || (p->nwells > 0 && !p->wells)) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: wells");
+    if (p->dual && (!p->km || !p->phim || !(p->sigma > 0.0)))
+        return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: dual porosity needs km, phim and sigma > 0");
     // wells: validate on the host, no shared perforated cells
     std::vector<long long> cells;
     for (int w = 0; w < p->nwells; w++) {
         const bo_well &W = p->wells[w];
-        if (W.control != 0) return fail(BO_ERR_UNSUPPORTED, "only fixed-BHP well control is supported");
         if (W.i < 0 || W.i >= p->nx || W.j < 0 || W.j >= p->ny || W.k_top < 0 || W.k_bot >= p->nz ||
             W.k_top > W.k_bot || !(W.rw > 0.0))
             return fail(BO_ERR_INVALID_ARG, "well " + std::to_string(w) + " is outside the grid or malformed");
@@ -392,15 +584,30 @@ extern "C" bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, c
     for (size_t t = 1; t < sorted.size(); t++)
         if (sorted[t] == sorted[t - 1]) return fail(BO_ERR_INVALID_ARG, "two perforations share a cell");
     hipStream_t s = (hipStream_t)stream;
-    J->nbrows = n;
+    J->nbrows = rows;
     J->nnzb = nnz;
     int32_t *cnt = nullptr;
-    BO_TRY(scratch_get(SC_JAC_CNT, sizeof(int32_t) * (size_t)n, (void **)&cnt));
-    k_row_counts<<<grid_for(n), kBlock, 0, s>>>(p->nx, p->ny, p->nz, cnt);
+    BO_TRY(scratch_get(SC_JAC_CNT, sizeof(int32_t) * (size_t)rows, (void **)&cnt));
+    k_row_counts<<<grid_for(n), kBlock, 0, s>>>(p->nx, p->ny, p->nz, p->dual, cnt);
+    auto chunk_of = [&](int w0, WellChunk &ch) {
+        int c = std::min(kWellChunk, p->nwells - w0);
+        for (int q = 0; q < c; q++) {
+            ch.w[q] = p->wells[w0 + q];
+            ch.row[q] = Ly.well_row[w0 + q];
+        }
+        return c;
+    };
+    for (int w0 = 0; w0 < p->nwells; w0 += kWellChunk) {
+        WellChunk ch{};
+        int c = chunk_of(w0, ch);
+        k_well_counts<<<1, kWellChunk, 0, s>>>(p->nx, p->ny, c, ch, cnt);
+    }
+    BO_HIP(hipGetLastError());
     int32_t total = 0;
-    BO_TRY(scan_counts(cnt, J->rowptr, n, &total, s));
+    BO_TRY(scan_counts(cnt, J->rowptr, rows, &total, s));
     if (total != nnz) return fail(BO_ERR_HIP, "row count scan disagrees with the pattern size");
-    GridG G{p->nx, p->ny, p->nz, p->dx, p->dy, p->dz, p->top_depth, p->kx, p->ky, p->kz, p->phi0};
+    GridG G{p->nx, p->ny, p->nz, p->dx, p->dy, p->dz, p->top_depth, p->kx, p->ky, p->kz, p->phi0,
+            p->dual, p->km, p->phim, p->sigma};
     const bo_fluid &q = p->fluid;
     Fl f{q.p_ref, q.Bw0, q.cw, q.Bo0, q.co, q.Bg0, q.cg, q.Rs0, q.crs, q.mu_w, q.mu_o, q.mu_g, q.c_r,
          q.rho_wsc, q.rho_osc, q.rho_gsc, q.swc, q.sor, q.sorg, q.sgc, q.nw, q.no, q.ng,
@@ -408,12 +615,12 @@ extern "C" bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, c
     if (f.nw < 1 || f.no < 1 || f.ng < 1) return fail(BO_ERR_INVALID_ARG, "Corey exponents must be >= 1");
     double acc = p->dx * p->dy * p->dz / (q.rb_ft3 * dt);
     k_jac_cells<<<grid_for(n), kBlock, 0, s>>>(G, f, x_old, x_new, acc, J->rowptr, J->colind, J->val, b);
+    if (p->dual) k_jac_matrix<<<grid_for(n), kBlock, 0, s>>>(G, f, x_old, x_new, acc, J->rowptr, J->colind, J->val, b);
     BO_HIP(hipGetLastError());
     for (int w0 = 0; w0 < p->nwells; w0 += kWellChunk) {
         WellChunk ch{};
-        int cnt = std::min(kWellChunk, p->nwells - w0);
-        for (int q = 0; q < cnt; q++) ch.w[q] = p->wells[w0 + q];
-        k_jac_wells<<<1, kWellChunk, 0, s>>>(G, f, x_new, cnt, ch, J->rowptr, J->colind, J->val, b);
+        int c = chunk_of(w0, ch);
+        k_jac_wells<<<1, kWellChunk, 0, s>>>(G, f, x_new, c, ch, J->rowptr, J->colind, J->val, b);
         BO_HIP(hipGetLastError());
     }
     return BO_OK;

@@ -321,6 +321,7 @@ extern "C" bo_status bo_cpr_attach_nn(bo_cpr *pc, bo_nn *nn, const double *logk,
     }
     if (!logk) return fail(BO_ERR_INVALID_ARG, "bo_cpr_attach_nn: logk is NULL");
     if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_attach_nn: the handle has no pressure stage");
+    if (pc->general) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_attach_nn: the network needs the grid form");
     hipStream_t s = (hipStream_t)stream;
     long long n = pc->n;
     BO_TRY(pc->nn_z.alloc(n));
@@ -345,6 +346,7 @@ extern "C" bo_status bo_cpr_collect_pairs(bo_cpr *pc, const double *b, int32_t n
     if (!pc || !b || !rp_out || !e_out || !got) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: NULL argument");
     if (ncalls < 1 || !(rtol_inner > 0.0)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: bad arguments");
     if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: the handle has no pressure stage");
+    if (pc->general) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_collect_pairs: pairs need the grid form");
     hipStream_t s = (hipStream_t)stream;
     long long n = pc->n;
     *got = 0;

@@ -38,6 +38,13 @@ template <typename T>
 bo_status nn_record(bo_cpr *pc, const T *rp, hipStream_t s);
 size_t fstage_slots(const bo_cpr *pc);
 
+// y = alpha A x + beta y with the handle's copy of A (slot or BSR form)
+static bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s) {
+    if (!pc->general) return slot_spmv(pc->g, pc->A.p, alpha, x, beta, y, s);
+    bo_bsr B{pc->n, pc->nnzb, pc->Arp.p, pc->Aci.p, pc->Aval.p};
+    return bo_bsr_spmv(&B, alpha, x, beta, y, s);
+}
+
 namespace {
 
 __global__ void k_check_finite(long long n, const double *__restrict__ v, int32_t *__restrict__ bad) {
@@ -78,9 +85,26 @@ static bo_status pressure_stage(bo_cpr *pc, const double *v, const void **dp, hi
 }
 
 bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
-    long long n = pc->n;
+    long long n = pc->n, npr = pc->npr;
     const Grid &g = pc->g;
     const bool mixed = pc->o.precision != BO_PREC_FP64;
+    if (!pc->o.fpf && pc->general) {
+        // x1 = Pi_p V(Pi_r v); z = x1 + F(v - A x1) with the BSR operator
+        if (!pc->o.use_amg) return fstage_apply(pc, v, nullptr, z, false, s);
+        const void *dp;
+        BO_TRY(pressure_stage(pc, v, &dp, s));
+        BO_TRY(fill(3 * n, 0.0, pc->t3b.p, s));
+        if (mixed) k_add_p<float><<<grid_for(npr), kBlock, 0, s>>>(npr, (const float *)dp, pc->t3b.p);
+        else k_add_p<double><<<grid_for(npr), kBlock, 0, s>>>(npr, (const double *)dp, pc->t3b.p);
+        BO_HIP(hipGetLastError());
+        BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+        BO_TRY(op_spmv(pc, -1.0, pc->t3b.p, 1.0, pc->t3a.p, s));
+        BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, z, false, s));
+        if (mixed) k_add_p<float><<<grid_for(npr), kBlock, 0, s>>>(npr, (const float *)dp, z);
+        else k_add_p<double><<<grid_for(npr), kBlock, 0, s>>>(npr, (const double *)dp, z);
+        BO_HIP(hipGetLastError());
+        return BO_OK;
+    }
     if (!pc->o.fpf) {
         if (!pc->o.use_amg) return fstage_apply(pc, v, nullptr, z, false, s);
         const void *dp;
@@ -107,15 +131,15 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     BO_TRY(fstage_apply(pc, v, nullptr, z, false, s));
     if (pc->o.use_amg) {
         BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-        BO_TRY(slot_spmv(g, pc->A.p, -1.0, z, 1.0, pc->t3a.p, s));
+        BO_TRY(op_spmv(pc, -1.0, z, 1.0, pc->t3a.p, s));
         const void *dp;
         BO_TRY(pressure_stage(pc, pc->t3a.p, &dp, s));
-        if (mixed) k_add_p<float><<<grid_for(n), kBlock, 0, s>>>(n, (const float *)dp, z);
-        else k_add_p<double><<<grid_for(n), kBlock, 0, s>>>(n, (const double *)dp, z);
+        if (mixed) k_add_p<float><<<grid_for(npr), kBlock, 0, s>>>(npr, (const float *)dp, z);
+        else k_add_p<double><<<grid_for(npr), kBlock, 0, s>>>(npr, (const double *)dp, z);
         BO_HIP(hipGetLastError());
     }
     BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-    BO_TRY(slot_spmv(g, pc->A.p, -1.0, z, 1.0, pc->t3a.p, s));
+    BO_TRY(op_spmv(pc, -1.0, z, 1.0, pc->t3a.p, s));
     BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, pc->t3b.p, false, s));
     return axpby(3 * n, 1.0, pc->t3b.p, 1.0, z, s);
 }
@@ -139,6 +163,7 @@ extern "C" void bo_cpr_default_opts(bo_cpr_opts *o) {
     o->qi_mode = BO_QI_BLOCK;
     o->precision = BO_PREC_FP64;
     o->csmoother = BO_CSMOOTH_L1;
+    o->npr = 0;
 }
 
 extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
@@ -150,14 +175,19 @@ extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
     o->timing = 0;
 }
 
+// grid == NULL: the general form (A kept as BSR; block-Jacobi F stage; the
+// pressure system over the first opts->npr rows)
 static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc,
                             hipStream_t s) {
-    pc->g = Grid{grid->nx, grid->ny, grid->nz};
-    pc->n = (int)pc->g.n();
+    pc->general = grid == nullptr;
+    pc->g = grid ? Grid{grid->nx, grid->ny, grid->nz} : Grid{A->nbrows, 1, 1};
+    pc->n = A->nbrows;
+    pc->nnzb = A->nnzb;
     pc->o = *opts;
+    pc->npr = (opts->npr > 0 && opts->npr < pc->n) ? opts->npr : pc->n;
     long long n = pc->n;
     BO_TRY(pc->flag.alloc(1));
-    BO_TRY(pc->A.alloc(63 * n));
+    if (!pc->general) BO_TRY(pc->A.alloc(63 * n));
     // inputs must be finite
     BO_HIP(hipMemsetAsync(pc->flag.p, 0, sizeof(int32_t), s));
     k_check_finite<<<grid_for(9LL * A->nnzb), kBlock, 0, s>>>(9LL * A->nnzb, A->val, pc->flag.p);
@@ -166,7 +196,16 @@ static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_o
     BO_HIP(hipMemcpyAsync(&bad, pc->flag.p, sizeof bad, hipMemcpyDeviceToHost, s));
     BO_HIP(hipStreamSynchronize(s));
     if (bad) return fail(BO_ERR_NONFINITE, "bo_cpr_setup: the matrix holds NaN or Inf");
-    BO_TRY(bsr_to_slots(pc->g, A->rowptr, A->colind, A->val, pc->A.p, s));
+    if (pc->general) {
+        BO_TRY(pc->Arp.alloc(n + 1));
+        BO_TRY(pc->Aci.alloc(A->nnzb));
+        BO_TRY(pc->Aval.alloc(9 * (size_t)A->nnzb));
+        BO_HIP(hipMemcpyAsync(pc->Arp.p, A->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+        BO_HIP(hipMemcpyAsync(pc->Aci.p, A->colind, sizeof(int32_t) * A->nnzb, hipMemcpyDeviceToDevice, s));
+        BO_HIP(hipMemcpyAsync(pc->Aval.p, A->val, sizeof(double) * 9 * (size_t)A->nnzb, hipMemcpyDeviceToDevice, s));
+    } else {
+        BO_TRY(bsr_to_slots(pc->g, A->rowptr, A->colind, A->val, pc->A.p, s));
+    }
     BO_TRY(qi_decouple(pc, s));
     if (pc->o.use_amg) {
         BO_TRY(amg_setup(pc, s));
@@ -188,11 +227,21 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
                                   bo_cpr **out, void *stream) {
     if (!out) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: out is NULL");
     *out = nullptr;
-    if (!A || !grid || !opts || !A->rowptr || !A->colind || !A->val)
+    if (!A || !opts || !A->rowptr || !A->colind || !A->val)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: NULL argument");
-    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 ||
-        (long long)grid->nx * grid->ny * grid->nz != (long long)A->nbrows)
+    if (A->nbrows < 1 || A->nnzb < A->nbrows) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: empty matrix");
+    if (grid && (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 ||
+                 (long long)grid->nx * grid->ny * grid->nz != (long long)A->nbrows))
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: grid does not match the matrix size");
+    if (!grid && opts->ftype != BO_F_BJ)
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: without a grid the F stage must be BO_F_BJ");
+    if (!grid && opts->use_amg && opts->smoother == BO_SMOOTH_GS)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: red-black Gauss-Seidel needs the grid");
+    if (grid && opts->smoother == BO_SMOOTH_L1)
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: the l1 level-0 smoother is for the general form");
+    if (opts->npr < 0 || opts->npr > A->nbrows) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: npr out of range");
+    if (grid && opts->npr != 0 && opts->npr != A->nbrows)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: on a grid every row is a pressure row");
     if ((long long)A->nbrows * 7 >= (1LL << 31)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: matrix too large");
     const bo_cpr_opts &o = *opts;
     if (o.ftype != BO_F_BJ && o.ftype != BO_F_ILU_TILED)
@@ -202,7 +251,7 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
     if (o.use_amg && (o.coarse_max < 1 || o.coarse_max > kCoarseMaxLimit || !(o.theta >= 0.0) ||
                       o.sweeps < 1 || o.sweeps > 8 || o.max_levels < 1))
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: AMG options out of range");
-    if (o.smoother != BO_SMOOTH_GS && o.smoother != BO_SMOOTH_JACOBI)
+    if (o.smoother != BO_SMOOTH_GS && o.smoother != BO_SMOOTH_JACOBI && o.smoother != BO_SMOOTH_L1)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown smoother");
     if (o.csmoother != BO_CSMOOTH_JACOBI && o.csmoother != BO_CSMOOTH_L1)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown coarse-level smoother");
@@ -228,7 +277,7 @@ extern "C" bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream) {
     if (A->nbrows != pc->n) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: matrix size differs from the setup");
     bo_grid g{pc->g.nx, pc->g.ny, pc->g.nz};
     bo_cpr_opts o = pc->o;
-    bo_status st = setup_impl(A, &g, &o, pc, (hipStream_t)stream);
+    bo_status st = setup_impl(A, pc->general ? nullptr : &g, &o, pc, (hipStream_t)stream);
     if (st != BO_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         pc->nlev = 0;
@@ -255,7 +304,7 @@ extern "C" bo_status bo_cpr_apply(bo_cpr *pc, const double *v, double *z, void *
 
 extern "C" bo_status bo_cpr_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, void *stream) {
     if (!pc || !x || !y) return fail(BO_ERR_INVALID_ARG, "bo_cpr_spmv: NULL argument");
-    return slot_spmv(pc->g, pc->A.p, alpha, x, beta, y, (hipStream_t)stream);
+    return op_spmv(pc, alpha, x, beta, y, (hipStream_t)stream);
 }
 
 extern "C" bo_status bo_cpr_restrict(bo_cpr *pc, const double *v, double *rp, void *stream) {
@@ -395,7 +444,7 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     for (;;) {
         // r = b - A x into V[0]
         BO_HIP(hipMemcpyAsync(V, b, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
-        BO_TRY(slot_spmv(g, pc->A.p, -1.0, x, 1.0, V, s));
+        BO_TRY(op_spmv(pc, -1.0, x, 1.0, V, s));
         BO_TRY(pc->red.dot(len, V, V, hd, s));
         BO_TRY(fetch(1));
         double beta = std::sqrt(hh[0]);
@@ -413,7 +462,7 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
             BO_TRY(cpr_apply(pc, vj, zj, s));
             its++;
             if (timed) BO_HIP(hipEventRecord(pc->ev[0], s));
-            BO_TRY(slot_spmv(g, pc->A.p, 1.0, zj, 0.0, w, s));
+            BO_TRY(op_spmv(pc, 1.0, zj, 0.0, w, s));
             if (timed) BO_HIP(hipEventRecord(pc->ev[1], s));
             int nv = j + 1;
             if (opts->orth == 1) {

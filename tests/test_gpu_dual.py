@@ -1,0 +1,158 @@
+"""GPU parity for dual porosity and fixed-rate wells: the Jacobian (fracture,
+matrix and well rows) against the oracle, and the general form of CPR (BSR
+operator, pressure system over the cell rows, l1-Jacobi level-0 smoother,
+block-Jacobi F stage) stage by stage and through FGMRES, in FP64 and the
+mixed form.  Tolerances as for the grid form: Jacobian 1e-12 per block,
+stages 1e-10 (FP64) or 1e-5 (FP32 form against its emulation), solves to the
+true residual 1e-6 with iterations within max(1, ceil(0.1 * oracle))."""
+import math
+
+import numpy as np
+import pytest
+
+import bo_casegen as cg
+from tests.gpu_util import device_bsr, rel_err, run_stage, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1606_00556_amd import bo
+    bo.lib()
+    return bo
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def dual_case(nx=19, ny=13, nz=5, seed=7):
+    wells = [cg.Well(0, 0, 0, nz - 1, "inj", "wrat", 900.0), cg.Well(nx - 1, ny - 1, 0, nz - 1, "prod", "lrat", 700.0),
+             cg.Well(nx // 2, ny // 2, 1, nz - 2, "prod", "bhp", 2500.0),
+             cg.Well(nx - 1, 0, 0, nz - 1, "inj", "bhp", 3500.0)]
+    return cg.make_dual_case(nx, ny, nz, seed=seed, wells=wells)
+
+
+def single_rate_case():
+    wells = [cg.Well(0, 0, 0, 5, "inj", "wrat", 800.0), cg.Well(18, 12, 0, 5, "prod", "lrat", 600.0)]
+    return cg.tiny_case(19, 13, 6, seed=21, step=0.01, wells=wells)
+
+
+CASES = {"dual": dual_case, "single_rate": single_rate_case}
+CASES_BUILT = {}
+
+
+def gpu_jacobian(B, case):
+    p = B.problem_from_case(case)
+    J, b = B.bo_jacobian_bsr(p, to_dev(case.x_old), to_dev(case.x_new), case.dt)
+    return to_host(J.rowptr), to_host(J.colind), to_host(J.val).reshape(-1, 3, 3), to_host(b)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_jacobian_matches_oracle(B, O, name):
+    case = CASES[name]()
+    if not case.dual:
+        extra = np.array([3200.0, 0.0, 0.0, 2800.0, 0.0, 0.0])
+        import dataclasses
+        case = dataclasses.replace(case, x_old=np.concatenate([case.x_old, extra]),
+                                   x_new=np.concatenate([case.x_new, extra]))
+    P = O.Problem(case)
+    rp, ci, val, R = O.jacobian(P)
+    grp, gci, gval, gb = gpu_jacobian(B, case)
+    assert np.array_equal(grp, rp) and np.array_equal(gci, ci)
+    scale = np.abs(val).max()
+    for e in range(len(ci)):
+        d = np.abs(gval[e] - val[e]).max()
+        assert d <= 1e-12 * max(np.abs(val[e]).max(), 1e-300 * scale), (e, d)
+    assert rel_err(gb, -R) <= 1e-12
+    CASES_BUILT[name] = (case, P, rp, ci, val, -R)
+
+
+def system(O, name):
+    if name not in CASES_BUILT:
+        case = CASES[name]()
+        if not case.dual:
+            import dataclasses
+            extra = np.array([3200.0, 0.0, 0.0, 2800.0, 0.0, 0.0])
+            case = dataclasses.replace(case, x_old=np.concatenate([case.x_old, extra]),
+                                       x_new=np.concatenate([case.x_new, extra]))
+        P = O.Problem(case)
+        rp, ci, val, R = O.jacobian(P)
+        CASES_BUILT[name] = (case, P, rp, ci, val, -R)
+    return CASES_BUILT[name]
+
+
+def both(B, O, name, precision="fp64", **kw):
+    case, P, rp, ci, val, b = system(O, name)
+    op = dict(fp64=O.PREC_FP64, fp32=O.PREC_FP32, bf16=O.PREC_FP32_BF16)[precision]
+    bp = dict(fp64=B.BO_PREC_FP64, fp32=B.BO_PREC_FP32, bf16=B.BO_PREC_FP32_BF16)[precision]
+    opc = O.Cpr(P, rp, ci, val, ftype=O.F_BJ, smoother=O.SMOOTH_L1, npr=P.ncell, coarse_max=40,
+                precision=op, **kw)
+    opts = B.bo_cpr_default_opts(ftype=B.BO_F_BJ, smoother=B.BO_SMOOTH_L1, npr=P.ncell, coarse_max=40,
+                                 precision=bp, **kw)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), None, opts)
+    return case, P, rp, ci, val, b, opc, gpc
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_general_cpr_stages_match_oracle(B, O, name):
+    case, P, rp, ci, val, b, opc, gpc = both(B, O, name)
+    rows, npr = P.rows, P.ncell
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(3 * rows)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_restrict, v, npr), opc.restrict(v)) <= 1e-14
+    r = rng.standard_normal(npr)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_vcycle, r, npr), opc.vcycle(r)) <= 1e-10
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_fstage, v, 3 * rows), opc.fstage(v)) <= 1e-10
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * rows), opc.apply(v)) <= 1e-10
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, b, 3 * rows), opc.apply(b)) <= 1e-10
+
+
+@pytest.mark.parametrize("kw", [dict(fpf=1), dict(smoother=1, sweeps=2), dict(csmoother=0)])
+def test_general_cpr_variants(B, O, kw):
+    okw = dict(kw)
+    c, P, rp, ci, val, b = system(O, "dual")
+    smoother = kw.get("smoother", 2)
+    opc = O.Cpr(P, rp, ci, val, ftype=O.F_BJ, npr=P.ncell, coarse_max=40,
+                **{k: v for k, v in dict(okw, smoother=smoother).items()})
+    opts = B.bo_cpr_default_opts(ftype=B.BO_F_BJ, npr=P.ncell, coarse_max=40,
+                                 **{k: v for k, v in dict(okw, smoother=smoother).items()})
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), None, opts)
+    v = np.random.default_rng(4).standard_normal(3 * P.rows)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * P.rows), opc.apply(v)) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_general_mixed_matches_emulation(B, O, prec):
+    case, P, rp, ci, val, b, opc, gpc = both(B, O, "dual", precision=prec)
+    v = np.random.default_rng(5).standard_normal(3 * P.rows)
+    tol = 1e-5 if prec == "fp32" else 2.0**-7
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * P.rows), opc.apply(v)) <= tol
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_general_fgmres(B, O, name, prec):
+    import torch
+    case, P, rp, ci, val, b, opc, gpc = both(B, O, name, precision=prec)
+    xo, oinfo = O.fgmres(rp, ci, val, b, opc)
+    x = torch.zeros(3 * P.rows, dtype=torch.float64, device="cuda")
+    info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    r = b - O.bsr_spmv(rp, ci, val, to_host(x))
+    assert info["converged"] and np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+    io = oinfo["iterations"]
+    assert abs(info["iterations"] - io) <= max(1, math.ceil(0.1 * io))
+    print(f"{name} {prec}: its {info['iterations']} (oracle {io})")
+
+
+def test_general_form_rejects_grid_only_options(B, O):
+    case, P, rp, ci, val, b = system(O, "dual")
+    A = device_bsr(B, rp, ci, val)
+    with pytest.raises(B.BoError):
+        B.bo_cpr_setup(A, None, B.bo_cpr_default_opts(npr=P.ncell))        # tiled ILU needs the grid
+    with pytest.raises(B.BoError):
+        B.bo_cpr_setup(A, None, B.bo_cpr_default_opts(ftype=B.BO_F_BJ, npr=P.ncell))  # RB-GS needs the grid
