@@ -151,14 +151,26 @@ static int ilu_setup(or_cpr *c, const or_problem *p)
     c->drop = calloc((size_t)nnzb, 1);
     c->LU = malloc(sizeof(double) * 9 * (size_t)nnzb);
     c->inv = malloc(sizeof(double) * 9 * (size_t)n);
-    int grid = p && p->nx * p->ny * p->nz == n;
+    /* a grid's cells, or (dual porosity / fixed-rate wells) the fracture cells
+     * 0..N-1, matrix cells N..2N-1 paired with fracture cell g - N, and well
+     * rows after the cells */
+    int N = p ? p->nx * p->ny * p->nz : 0;
+    int ncell = 0, rows = p ? or_rows(p, &ncell) : 0;
+    int grid = p && (N == n || (rows == n && ncell >= N));
     if (c->o.ftype != OR_F_ILU_NATURAL && !grid) return OR_ERR_ARG;
-    /* ordering key: (class, g) with class = colour or tile */
+    /* ordering key: (class, g) with class = colour or tile; a matrix cell takes
+     * its fracture cell's class (so it follows the tile's fracture cells), the
+     * well rows form one class of their own after every tile */
     int32_t *cls = calloc((size_t)n, sizeof(int32_t));
+    int ntiles = 0;
+    if (grid && c->o.ftype == OR_F_ILU_TILED)
+        ntiles = ((p->nx + c->o.tile_x - 1) / c->o.tile_x) * ((p->ny + c->o.tile_y - 1) / c->o.tile_y);
     for (int g = 0; g < n; g++) {
         int i, j, k;
         if (!grid) { cls[g] = 0; continue; }
-        grid_cell(p, g, &i, &j, &k);
+        if (g >= (ncell > N ? ncell : N)) { cls[g] = c->o.ftype == OR_F_ILU_TILED ? ntiles : 2; continue; }
+        int gg = g < N ? g : g - N;
+        grid_cell(p, gg, &i, &j, &k);
         if (c->o.ftype == OR_F_ILU_RB) cls[g] = (i + j + k) & 1;
         else if (c->o.ftype == OR_F_ILU_TILED) {
             int ntx = (p->nx + c->o.tile_x - 1) / c->o.tile_x;

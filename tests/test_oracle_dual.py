@@ -132,7 +132,7 @@ def test_vanishing_transfer_reduces_to_single_porosity(oracle_lib):
         assert np.array_equal(val[cols], val1[rp1[r]:rp1[r + 1]])
 
 
-@pytest.mark.parametrize("ftype", ["bj", "natural"])
+@pytest.mark.parametrize("ftype", ["bj", "natural", "tiled"])
 def test_cpr_on_dual_system_matches_dense_solve(oracle_lib, ftype):
     """CPR with the pressure system over the cell rows only (the well rows stay
     out of A_pp) and an l1-Jacobi level-0 smoother (the dual graph has no grid
@@ -143,8 +143,8 @@ def test_cpr_on_dual_system_matches_dense_solve(oracle_lib, ftype):
     P = O.Problem(c)
     rp, ci, val, R = O.jacobian(P)
     b = -R
-    ft = dict(bj=O.F_BJ, natural=O.F_ILU_NATURAL)[ftype]
-    pc = O.Cpr(P, rp, ci, val, ftype=ft, smoother=O.SMOOTH_L1, npr=P.ncell, coarse_max=10)
+    ft = dict(bj=O.F_BJ, natural=O.F_ILU_NATURAL, tiled=O.F_ILU_TILED)[ftype]
+    pc = O.Cpr(P, rp, ci, val, ftype=ft, smoother=O.SMOOTH_L1, npr=P.ncell, coarse_max=10, tile=(2, 2))
     assert pc.nlevels() >= 2 and pc.npr == 2 * c.n
     x, info = O.fgmres(rp, ci, val, b, pc, rtol=1e-12)
     A = O.bsr_to_dense(rp, ci, val)
@@ -157,3 +157,26 @@ def test_cpr_on_dual_system_matches_dense_solve(oracle_lib, ftype):
     v = np.zeros(3 * P.rows)
     v[3 * 2 * c.n:] = 1.0
     assert not pc.restrict(v).any()
+
+
+def test_tiled_ilu_with_one_tile_equals_natural_order(oracle_lib):
+    """One tile covering the grid orders the dual system as the natural order
+    does (fracture cells, then matrix cells); without well rows nothing is
+    dropped, so both F stages agree to rounding."""
+    O = oracle_lib
+    c = cg.make_dual_case(5, 4, 3, seed=5, wells=[cg.Well(0, 0, 0, 2, "inj", "bhp", 3500.0)])
+    P = O.Problem(c)
+    rp, ci, val, R = O.jacobian(P)
+    t = O.Cpr(P, rp, ci, val, ftype=O.F_ILU_TILED, tile=(8, 8), use_amg=0)
+    nat = O.Cpr(P, rp, ci, val, ftype=O.F_ILU_NATURAL, use_amg=0)
+    v = np.random.default_rng(3).standard_normal(3 * P.rows)
+    a, b = t.fstage(v), nat.fstage(v)
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+    # with a fixed-rate well the tiled form drops the well's couplings
+    c2 = cg.make_dual_case(5, 4, 3, seed=5, wells=[cg.Well(0, 0, 0, 2, "inj", "wrat", 300.0)])
+    P2 = O.Problem(c2)
+    rp2, ci2, val2, _ = O.jacobian(P2)
+    v2 = np.random.default_rng(4).standard_normal(3 * P2.rows)
+    a2 = O.Cpr(P2, rp2, ci2, val2, ftype=O.F_ILU_TILED, tile=(8, 8), use_amg=0).fstage(v2)
+    b2 = O.Cpr(P2, rp2, ci2, val2, ftype=O.F_ILU_NATURAL, use_amg=0).fstage(v2)
+    assert np.linalg.norm(a2 - b2) > 1e-8 * np.linalg.norm(b2)
