@@ -33,7 +33,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2))
+    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2, 4),
+                    help="0: 20x20x5; 1: 100x100x50 (default); 2: 200x200x50; 4: dual porosity 400x400x100 "
+                         "locations with fixed-rate wells (general CPR form)")
+    ap.add_argument("--systems", type=int, default=0,
+                    help="systems of the step sequence to cycle through (default: all 10; workload 4: 2)")
+    ap.add_argument("--scale", type=int, default=1,
+                    help="workload 4 only: divide nx, ny by this (nz by half of it), a smaller twin")
     ap.add_argument("--spmv-isolated", action="store_true",
                     help="also time isolated SpMV launches (after a cache-evicting pass, and back to back)")
     ap.add_argument("--spmv-reps", type=int, default=20)
@@ -63,9 +69,16 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     wl = args.workload
-    systems = [0] if wl == 0 else list(range(1, cg.N_SYSTEMS + 1))
+    nsys = args.systems or (2 if wl == 4 else cg.N_SYSTEMS)
+    systems = [0] if wl == 0 else list(range(1, nsys + 1))
     log(args, f"[bench] generating workload {wl} ({len(systems)} systems)")
-    cases = [cg.make_case(wl, k) if wl else cg.make_case(0) for k in systems]
+    if wl == 4:
+        cases = []
+        for k in systems:
+            cases.append(cg.make_cfg4(k, scale=args.scale))
+            log(args, f"[bench] generated system {k}: {cases[-1].rows} block rows")
+    else:
+        cases = [cg.make_case(wl, k) if wl else cg.make_case(0) for k in systems]
     c0 = cases[0]
     prob = B.problem_from_case(c0, dev)
     states = [(torch.from_numpy(c.x_old).to(dev), torch.from_numpy(c.x_new).to(dev), c.dt) for c in cases]
@@ -75,9 +88,18 @@ def main():
                     torch.empty(9 * nnzb, dtype=torch.float64, device=dev))
     b = torch.empty(3 * n, dtype=torch.float64, device=dev)
     x = torch.empty(3 * n, dtype=torch.float64, device=dev)
-    grid = (c0.nx, c0.ny, c0.nz)
     prec = {"fp64": B.BO_PREC_FP64, "fp32": B.BO_PREC_FP32, "bf16": B.BO_PREC_FP32_BF16}[args.precision]
-    copts = B.bo_cpr_default_opts(precision=prec)
+    if wl == 4:
+        # the extended grid form: BSR operator; the pressure system over every
+        # row (cells and fixed-rate wells); Algorithm CPR-FPF with the tiled
+        # ILU ordered fracture tiles, matrix cells, wells (FP64; the mixed
+        # forms use block Jacobi)
+        grid = (c0.nx, c0.ny, c0.nz, 1)
+        ft = B.BO_F_ILU_TILED if prec == B.BO_PREC_FP64 else B.BO_F_BJ
+        copts = B.bo_cpr_default_opts(precision=prec, ftype=ft, smoother=B.BO_SMOOTH_L1, npr=c0.rows, fpf=1)
+    else:
+        grid = (c0.nx, c0.ny, c0.nz)
+        copts = B.bo_cpr_default_opts(precision=prec)
     fopts = B.bo_fgmres_default_opts()
     fopts_timed = B.bo_fgmres_default_opts(timing=1)
     torch.cuda.synchronize()
@@ -130,7 +152,8 @@ def main():
     # events recorded by the library on this stream around each launch).
     spmv_calls = sum(inf["spmv_calls"] for _, inf in rec)
     spmv_us = 1000.0 * sum(inf["spmv_ms"] for _, inf in rec) / max(spmv_calls, 1)
-    spmv_bytes = 72.0 * nnzb + 48.0 * n
+    # (the general BSR form of workload 4 also reads its int32 indices)
+    spmv_bytes = 72.0 * nnzb + 48.0 * n if wl != 4 else 76.0 * nnzb + 52.0 * n
     spmv_gbs = spmv_bytes / (spmv_us * 1e-6) / 1e9
     spmv = {"us": spmv_us, "GBs": spmv_gbs, "bytes": spmv_bytes, "launches": spmv_calls}
     if args.spmv_isolated:
@@ -148,7 +171,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, cases[0])
+        cpu = cpu_baseline(args, cases[0] if wl != 4 else cg.make_cfg4(1, scale=8), wl)
     out = {
         "metric": METRIC,
         "value": ms_per_step / 1000.0,
@@ -164,10 +187,14 @@ def main():
                   "bf16": "f64 (Krylov, residuals) + f32 (AMG) + bf16-stored ILU factors"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": (f"cfg{wl}: {c0.nx}x{c0.ny}x{c0.nz} black-oil 3x3-block Jacobians "
-                         f"({n} cells, {3 * n} unknowns, {nnzb} blocks), "
-                         + ("10 systems of the synthetic 30-day step sequence" if wl else "one system")),
-            "solver": "FGMRES(30), CPR-PF: block quasi-IMPES, SA-AMG V(1,1) RB-GS/Jacobi, tiled BILU0 8x8",
+            "workload": (f"cfg{wl}: {c0.nx}x{c0.ny}x{c0.nz} "
+                         + ("dual-porosity locations with fixed-rate wells, " if wl == 4 else "")
+                         + f"black-oil 3x3-block Jacobians ({n} block rows, {3 * n} unknowns, {nnzb} blocks), "
+                         + (f"{len(systems)} systems of the synthetic 30-day step sequence" if wl else "one system")),
+            "solver": ("FGMRES(30), CPR-PF: block quasi-IMPES, SA-AMG V(1,1) RB-GS/l1-Jacobi, tiled BILU0 8x8"
+                       if wl != 4 else
+                       "FGMRES(30), CPR-FPF extended grid form: block quasi-IMPES over cell and well rows, "
+                       "SA-AMG V(1,1) l1-Jacobi, tiled BILU0 8x8 (fracture tiles, matrix cells, wells)"),
             "precision": args.precision,
             "rtol": 1e-6,
             "step": "bo_jacobian_bsr + bo_cpr_update (full rebuild, memory reused) + bo_fgmres_solve",
@@ -244,14 +271,18 @@ def isolated_spmv(args, B, pc, n, dev, stream):
     return {"isolated_cold_us": cold_us, "isolated_back_to_back_us": warm_us}
 
 
-def cpu_baseline(args, case):
-    """The FP64 oracle on the host: one system (assembly + setup + solve)."""
+def cpu_baseline(args, case, wl):
+    """The FP64 oracle on the host: one system (assembly + setup + solve); for
+    the dual-porosity workload on its 50x50x12 twin."""
     from oracle import oracle as O
     log(args, "[bench] cpu baseline: oracle on one system")
     t0 = time.perf_counter()
     P = O.Problem(case)
     rp, ci, val, R = O.jacobian(P)
-    pc = O.Cpr(P, rp, ci, val)
+    if wl == 4:
+        pc = O.Cpr(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, npr=P.rows, fpf=1)
+    else:
+        pc = O.Cpr(P, rp, ci, val)
     x, info = O.fgmres(rp, ci, val, -R, pc)
     t1 = time.perf_counter()
     log(args, f"[bench] cpu baseline: {t1 - t0:.2f} s, its={info['iterations']}")

@@ -194,18 +194,24 @@ void bo_cpr_default_opts(bo_cpr_opts *o);
 
 typedef struct bo_cpr bo_cpr;
 
-/* [host] grid of the matrix: the F stage tiles and the level-0 colours use it,
- * and A's pattern must be the 7-point stencil of this grid. */
-typedef struct { int32_t nx, ny, nz; } bo_grid;
+/* [host] grid of the matrix: the F stage tiles and the level-0 colours use it.
+ * With nbrows == nx*ny*nz A's pattern must be the 7-point stencil of the grid.
+ * Otherwise (the extended grid form) the first nx*ny*nz rows are the grid's
+ * (fracture) cells, followed by nx*ny*nz matrix cells when dual != 0, then
+ * other rows (fixed-rate wells), as bo_jacobian_bsr writes them. */
+typedef struct { int32_t nx, ny, nz, dual; } bo_grid;
 
 /* Builds the CPR preconditioner of A (Section 3.2): quasi-IMPES weights and the
  * decoupled pressure block, the AMG hierarchy on it, and the F-stage factors.
  * Keeps a private copy of A's values in its own layout; A may be freed after
  * return.  Synchronises `stream` (the hierarchy sizes are decided on the host).
- * grid == NULL selects the general form for any block pattern (e.g. dual
- * porosity with fixed-rate wells): A is kept in BSR form, the pressure system
- * is the first opts->npr rows, the level-0 smoother must be Jacobi or l1-Jacobi
- * and the F stage block Jacobi. */
+ * The general form, for a block pattern other than a grid's 7-point stencil,
+ * keeps A in BSR form and takes the pressure system over the first opts->npr
+ * rows; its level-0 smoother must be Jacobi or l1-Jacobi.  With grid == NULL
+ * its F stage must be block Jacobi; with the extended grid form (see bo_grid)
+ * it may also be the tiled block ILU(0) (FP64 precision only), ordered tile by
+ * tile: the tile's fracture cells, their matrix cells, and the remaining rows
+ * as one block-Jacobi class of their own. */
 bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
                        bo_cpr **out, void *stream);
 /* Rebuilds pc for new values of a matrix with the same grid, pattern and

@@ -80,7 +80,7 @@ class BoCprOpts(C.Structure):
 
 
 class BoGrid(C.Structure):
-    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32)]
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dual", C.c_int32)]
 
 
 class BoFgmresOpts(C.Structure):
@@ -290,7 +290,8 @@ class Cpr:
 
 
 def bo_cpr_setup(A: DeviceBsr, grid, opts: Optional[BoCprOpts] = None, stream=None) -> Cpr:
-    """grid: (nx, ny, nz), or None for the general form (see include/bo.h)."""
+    """grid: (nx, ny, nz) or (nx, ny, nz, dual), or None for the general form
+    (see include/bo.h)."""
     o = opts if opts is not None else bo_cpr_default_opts()
     g = BoGrid(*grid) if grid is not None else None
     h = C.c_void_p()

@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_long(int n, const int32_t *_
     if (i >= n) return;
     int b = rp[i], len = rp[i + 1] - b;
     if (len <= KP) return;  // handled by the register path
-    if (len > KW) { if (lane == 0) *bad = 1; return; }
+    if (len > KW) return;   // handled by k_p_vlong
     for (int q = lane; q < len; q += 64) {
         int e = b + q;
         bool take = p_takes(e, i, ci, sf, agg);
@@ -515,6 +515,58 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_long(int n, const int32_t *_
             int Ju = J[wave][u];
             if (u >= q && Ju == Jq) sum = sum + A[wave][u];
             rank += first[wave][u] && Ju < Jq;
+        }
+        pci[prp[i] + rank] = Jq;
+        pv[prp[i] + rank] = (ai == Jq ? 1.0 : 0.0) - d * sum;
+    }
+}
+
+// The same for the rare rows longer than the LDS staging (a well row and its
+// aggregates on coarse levels): one wavefront per row, the row's aggregate
+// ids and values re-read from global memory, quadratic in the row length.
+__global__ void __launch_bounds__(64 * kPWaves) k_p_vlong(int n, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const double *__restrict__ v,
+                                                           const uint8_t *__restrict__ sf,
+                                                           const int32_t *__restrict__ agg,
+                                                           const double *__restrict__ aF, double omega,
+                                                           const int32_t *__restrict__ prp, int32_t *__restrict__ pci,
+                                                           double *__restrict__ pv, int32_t *__restrict__ cnt) {
+    int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    int i = blockIdx.x * kPWaves + wave;
+    if (i >= n) return;
+    int b = rp[i], len = rp[i + 1] - b;
+    if (len <= KW) return;
+    auto jof = [&](int q) -> int { int e = b + q; return p_takes(e, i, ci, sf, agg) ? agg[ci[e]] : -1; };
+    auto aof = [&](int q) -> double {
+        int e = b + q;
+        return p_takes(e, i, ci, sf, agg) ? (ci[e] == i ? aF[i] : v[e]) : 0.0;
+    };
+    auto is_first = [&](int q, int Jq) -> bool {
+        if (Jq < 0) return false;
+        for (int u = 0; u < q; u++)
+            if (jof(u) == Jq) return false;
+        return true;
+    };
+    if (cnt) {
+        int mycount = 0;
+        for (int q = lane; q < len; q += 64) mycount += is_first(q, jof(q));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mycount += __shfl_xor(mycount, off, 64);
+        if (lane == 0) cnt[i] = mycount;
+        return;
+    }
+    double d = omega / aF[i];
+    int ai = agg[i];
+    for (int q = lane; q < len; q += 64) {
+        int Jq = jof(q);
+        if (!is_first(q, Jq)) continue;
+        double sum = 0.0;
+        int rank = 0;
+        for (int u = 0; u < len; u++) {
+            int Ju = jof(u);
+            if (u >= q && Ju == Jq) sum = sum + aof(u);
+            rank += Ju >= 0 && Ju < Jq && is_first(u, Ju);
         }
         pci[prp[i] + rank] = Jq;
         pv[prp[i] + rank] = (ai == Jq ? 1.0 : 0.0) - d * sum;
@@ -1156,6 +1208,8 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         k_p_long<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
                                                                        aF.p, 0.0, nullptr, nullptr, nullptr,
                                                                        cnt.p, flag);
+        k_p_vlong<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
+                                                                        aF.p, 0.0, nullptr, nullptr, nullptr, cnt.p);
         BO_TRY(L.prp.alloc(n + 1));
         int32_t pnnz = 0;
         BO_TRY(scan_counts(cnt.p, L.prp.p, n, &pnnz, s));
@@ -1166,6 +1220,9 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         k_p_long<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
                                                                        aF.p, L.omega, L.prp.p, L.pci.p, L.pv.p,
                                                                        nullptr, flag);
+        k_p_vlong<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
+                                                                        aF.p, L.omega, L.prp.p, L.pci.p, L.pv.p,
+                                                                        nullptr);
         BO_HIP(hipGetLastError());
         BO_TRY(read_flag(flag, s, &bad));
         if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: prolongator row longer than the LDS staging limit");

@@ -58,8 +58,14 @@ struct bo_cpr {
     bo::Grid g{};
     int n = 0;                    // block rows (the cells of a grid)
     int npr = 0;                  // rows of the pressure system (the first npr block rows)
-    bool general = false;         // no grid: A kept in BSR form (Arp, Aci, Aval)
+    bool general = false;         // A kept in BSR form (Arp, Aci, Aval): no grid, or a grid
+                                  // with extra rows (dual porosity, wells)
     int nnzb = 0;
+    bool has_grid = false;        // set up with a grid (plain or extended form)
+    int ncell = 0;                // cell rows (N, or 2N with dual porosity); later rows are wells
+    // extended grid form's F stage: natural-order fracture pivots, matrix
+    // pivots and couplings, well-row inverses (SoA 9 x count)
+    bo::DBuf<double> x_einv_f, x_einv_m, x_amf, x_afm, x_einv_w;
     bo::DBuf<int32_t> Arp, Aci;
     bo::DBuf<double> Aval;
     bo_cpr_opts o{};

@@ -104,7 +104,7 @@ template <int St>
 __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__restrict__ A,
                                                    void *__restrict__ Ff, void *__restrict__ Fb,
                                                    int32_t *__restrict__ cell, int32_t *__restrict__ slot_of,
-                                                   int32_t *__restrict__ bad) {
+                                                   int32_t *__restrict__ bad, double *__restrict__ einv_nat) {
     int t = threadIdx.x;
     int a = t % T.tx, b = t / T.tx;
     int tile = blockIdx.x;
@@ -156,6 +156,8 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
                 for (int z = 0; z < 9; z++) Ei[z] = 0.0;
             }
             for (int z = 0; z < 9; z++) { fw[z] = Ei[z]; bw[z] = Ei[z]; Ep[z] = Ei[z]; }
+            if (einv_nat)
+                for (int z = 0; z < 9; z++) einv_nat[(size_t)z * N + g] = Ei[z];
             // upper blocks: this row's +x, +y, +z (zero outside the tile)
             if (has_px) load_blk(A, S_PX, N, g, Uxp); else for (int z = 0; z < 9; z++) Uxp[z] = 0.0;
             if (has_py) load_blk(A, S_PY, N, g, Uyp); else for (int z = 0; z < 9; z++) Uyp[z] = 0.0;
@@ -366,6 +368,134 @@ int store_of(const bo_cpr *pc) {
     return pc->o.precision == BO_PREC_FP64 ? ST_F64 : pc->o.precision == BO_PREC_FP32 ? ST_F32 : ST_BF16;
 }
 
+// ---- the extended grid form: dual porosity and well rows -----------------------
+// Block ILU(0) of the whole system ordered tile by tile: a tile's fracture
+// cells (wavefront order as above), then their matrix cells, and the well rows
+// as one class of their own after every tile (their couplings to the cells
+// dropped, like the couplings between tiles).  A matrix cell's only lower
+// neighbour is its fracture cell, so its pivot is E_m = A_mm - (A_mf E_f^{-1})
+// A_fm, and a fracture cell's only extra upper neighbour is its matrix cell:
+//   forward   w_f (tiles),  w_m = E_m^{-1} (r_m - A_mf w_f)
+//   backward  x_m = w_m,    x_f = w_f - E_f^{-1} (A_fm x_m + sum_stencil A x)
+// The term E_f^{-1} A_fm x_m is taken out of w_f before the tile sweep.
+
+// stencil blocks (columns < N) of the first N rows of a BSR matrix into the
+// slot layout
+__global__ void k_bsr_stencil_slots(int nx, int ny, int nz, const int32_t *__restrict__ rp,
+                                    const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                    double *__restrict__ slots, int32_t *__restrict__ bad) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = nx * ny * nz;
+    if (i >= n) return;
+    size_t N = (size_t)n;
+    int e = rp[i], end = rp[i + 1];
+    for (int s = 0; s < NSLOT; s++) {
+        int nb = nbr_of(i, s, nx, ny, nz);
+        bool have = nb >= 0 && e < end && ci[e] == nb;
+        for (int z = 0; z < 9; z++) slots[((size_t)s * 9 + z) * N + i] = have ? v[9 * (size_t)e + z] : 0.0;
+        if (have) e++;
+        else if (nb >= 0) *bad = 1;
+    }
+}
+
+// matrix pivots E_m^{-1} and the coupling blocks A_mf (row N+g, col g) and
+// A_fm (row g, col N+g), SoA 9 x N
+__global__ void k_dual_pivots(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                              const double *__restrict__ v, const double *__restrict__ einv_f,
+                              double *__restrict__ einv_m, double *__restrict__ amf, double *__restrict__ afm,
+                              int32_t *__restrict__ bad) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    size_t N = (size_t)n;
+    int ef = rp[g];
+    while (ef < rp[g + 1] && ci[ef] != n + g) ef++;
+    int em = rp[n + g];  // row N+g holds (g, N+g)
+    if (ef == rp[g + 1] || rp[n + g + 1] - em != 2 || ci[em] != g || ci[em + 1] != n + g) {
+        *bad = 1;
+        return;
+    }
+    double Af[9], Am[9], Amm[9], Ef[9], L[9], t[9], E[9], Ei[9];
+    for (int z = 0; z < 9; z++) {
+        Af[z] = v[9 * (size_t)ef + z];
+        Am[z] = v[9 * (size_t)em + z];
+        Amm[z] = v[9 * (size_t)(em + 1) + z];
+        Ef[z] = einv_f[(size_t)z * N + g];
+    }
+    mul3(Am, Ef, L);
+    mul3(L, Af, t);
+    for (int z = 0; z < 9; z++) E[z] = Amm[z] - t[z];
+    if (!inv3_gj(E, Ei)) {
+        *bad = 1;
+        for (int z = 0; z < 9; z++) Ei[z] = 0.0;
+    }
+    for (int z = 0; z < 9; z++) {
+        einv_m[(size_t)z * N + g] = Ei[z];
+        amf[(size_t)z * N + g] = Am[z];
+        afm[(size_t)z * N + g] = Af[z];
+    }
+}
+
+// inverses of the diagonal blocks of rows [r0, r0 + cnt) (the well rows), 9 x cnt
+__global__ void k_rows_inv(int r0, int cnt, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                           const double *__restrict__ v, double *__restrict__ out, int32_t *__restrict__ bad) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cnt) return;
+    int r = r0 + q;
+    int e = rp[r];
+    while (e < rp[r + 1] && ci[e] != r) e++;
+    double E[9], Ei[9];
+    if (e == rp[r + 1]) {
+        *bad = 1;
+        for (int z = 0; z < 9; z++) Ei[z] = 0.0;
+    } else {
+        for (int z = 0; z < 9; z++) E[z] = v[9 * (size_t)e + z];
+        if (!inv3_gj(E, Ei)) {
+            *bad = 1;
+            for (int z = 0; z < 9; z++) Ei[z] = 0.0;
+        }
+    }
+    for (int z = 0; z < 9; z++) out[(size_t)z * cnt + q] = Ei[z];
+}
+
+// forward step of the matrix cells and the fracture adjustment:
+// x_m = E_m^{-1}(r_m - A_mf w_f) into out, w_f -= E_f^{-1} A_fm x_m (slot order)
+__global__ void k_dual_forward(int n, const int32_t *__restrict__ slot_of, size_t S, const double *__restrict__ r,
+                               const double *__restrict__ einv_m, const double *__restrict__ amf,
+                               const double *__restrict__ afm, const double *__restrict__ einv_f,
+                               double *__restrict__ wq, double *__restrict__ out) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    size_t N = (size_t)n;
+    size_t q = (size_t)slot_of[g];
+    double wf[3] = {wq[q], wq[S + q], wq[2 * S + q]};
+    double B[9], y[3], v3[3], xm[3];
+    for (int z = 0; z < 9; z++) B[z] = amf[(size_t)z * N + g];
+    mv3(B, wf, y);
+    for (int c = 0; c < 3; c++) v3[c] = r[3 * (N + g) + c] - y[c];
+    for (int z = 0; z < 9; z++) B[z] = einv_m[(size_t)z * N + g];
+    mv3(B, v3, xm);
+    for (int c = 0; c < 3; c++) out[3 * (N + g) + c] = xm[c];
+    for (int z = 0; z < 9; z++) B[z] = afm[(size_t)z * N + g];
+    mv3(B, xm, y);
+    for (int z = 0; z < 9; z++) B[z] = einv_f[(size_t)z * N + g];
+    mv3(B, y, v3);
+    wq[q] = wf[0] - v3[0];
+    wq[S + q] = wf[1] - v3[1];
+    wq[2 * S + q] = wf[2] - v3[2];
+}
+
+// well rows: x_r = E_r^{-1} r_r
+__global__ void k_rows_apply(int r0, int cnt, const double *__restrict__ inv, const double *__restrict__ r,
+                             double *__restrict__ out) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= cnt) return;
+    size_t R = (size_t)(r0 + q);
+    double B[9], v3[3] = {r[3 * R], r[3 * R + 1], r[3 * R + 2]}, o[3];
+    for (int z = 0; z < 9; z++) B[z] = inv[(size_t)z * cnt + q];
+    mv3(B, v3, o);
+    for (int c = 0; c < 3; c++) out[3 * R + c] = o[c];
+}
+
 TileGeom geom(const bo_cpr *pc) {
     TileGeom T;
     T.nx = pc->g.nx; T.ny = pc->g.ny; T.nz = pc->g.nz;
@@ -397,6 +527,16 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
     } else {
         TileGeom T = geom(pc);
         size_t S = (size_t)T.slots();
+        const long long N = pc->g.n();
+        const bool ext = pc->general;  // the extended grid form (extra matrix / well rows)
+        if (ext) {
+            if (st != ST_F64) return fail(BO_ERR_UNSUPPORTED, "F stage: the extended grid form's ILU is FP64 only");
+            BO_TRY(pc->A.alloc(63 * N));
+            BO_HIP(hipMemsetAsync(pc->flag.p, 0, sizeof(int32_t), s));
+            k_bsr_stencil_slots<<<grid_for(N), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->Arp.p, pc->Aci.p,
+                                                               pc->Aval.p, pc->A.p, pc->flag.p);
+            BO_TRY(pc->x_einv_f.alloc(9 * N));
+        }
         // factor buffers sized for FP64; the FP32 and BF16 forms use a prefix
         BO_TRY(pc->ilu_f.alloc(S * kPairs));
         BO_TRY(pc->ilu_b.alloc(S * kPairs));
@@ -415,13 +555,26 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
         int nb = T.ntx * T.nty;
         if (st == ST_F64)
             k_ilu_factor<ST_F64><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
-                                                   pc->ilu_slot.p, pc->flag.p);
+                                                   pc->ilu_slot.p, pc->flag.p, ext ? pc->x_einv_f.p : nullptr);
+        if (ext && pc->ncell > N) {
+            BO_TRY(pc->x_einv_m.alloc(9 * N));
+            BO_TRY(pc->x_amf.alloc(9 * N));
+            BO_TRY(pc->x_afm.alloc(9 * N));
+            k_dual_pivots<<<grid_for(N), kBlock, 0, s>>>((int)N, pc->Arp.p, pc->Aci.p, pc->Aval.p, pc->x_einv_f.p,
+                                                         pc->x_einv_m.p, pc->x_amf.p, pc->x_afm.p, pc->flag.p);
+        }
+        if (ext && pc->n > pc->ncell) {
+            int cnt = pc->n - pc->ncell;
+            BO_TRY(pc->x_einv_w.alloc(9 * (size_t)cnt));
+            k_rows_inv<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->Arp.p, pc->Aci.p, pc->Aval.p,
+                                                        pc->x_einv_w.p, pc->flag.p);
+        }
         else if (st == ST_F32)
             k_ilu_factor<ST_F32><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
-                                                   pc->ilu_slot.p, pc->flag.p);
+                                                   pc->ilu_slot.p, pc->flag.p, nullptr);
         else
             k_ilu_factor<ST_BF16><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
-                                                    pc->ilu_slot.p, pc->flag.p);
+                                                    pc->ilu_slot.p, pc->flag.p, nullptr);
     }
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
@@ -453,6 +606,28 @@ bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, boo
 // out = F(r) (+ Pi_p dp when dp != NULL).  With r_in_slots the residual is
 // already in the F stage's slot order (ilu_r, or ilu_r32 in the mixed form).
 bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, bool r_in_slots, hipStream_t s) {
+    if (pc->general && pc->o.ftype == BO_F_ILU_TILED) {
+        // the extended grid form (FP64): tiles of fracture cells, then matrix
+        // cells, then well rows
+        if (dp || r_in_slots) return fail(BO_ERR_INVALID_ARG, "F stage: extended form takes r in natural order");
+        TileGeom G = geom(pc);
+        size_t S = (size_t)G.slots();
+        const long long N = pc->g.n();
+        k_to_slots<double><<<grid_for(N), kBlock, 0, s>>>(N, pc->ilu_slot.p, S, r, pc->ilu_r.p);
+        k_ilu_forward<ST_F64, double><<<G.ntx * G.nty, 64, 0, s>>>(G, pc->ilu_f.p, pc->ilu_cell.p, pc->ilu_r.p,
+                                                                    pc->ilu_w.p);
+        if (pc->ncell > N)
+            k_dual_forward<<<grid_for(N), kBlock, 0, s>>>((int)N, pc->ilu_slot.p, S, r, pc->x_einv_m.p, pc->x_amf.p,
+                                                          pc->x_afm.p, pc->x_einv_f.p, pc->ilu_w.p, out);
+        if (pc->n > pc->ncell) {
+            int cnt = pc->n - pc->ncell;
+            k_rows_apply<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out);
+        }
+        k_ilu_backward<ST_F64, double, double><<<G.ntx * G.nty, 64, 0, s>>>(G, pc->ilu_b.p, pc->ilu_cell.p,
+                                                                             pc->ilu_w.p, nullptr, out);
+        BO_HIP(hipGetLastError());
+        return BO_OK;
+    }
     switch (store_of(pc)) {
     case ST_F64: return fstage_run<ST_F64, double, double>(pc, r, dp, out, r_in_slots, pc->ilu_r.p, pc->ilu_w.p, s);
     case ST_F32: return fstage_run<ST_F32, float, double>(pc, r, dp, out, r_in_slots, pc->ilu_r32.p, pc->ilu_w32.p, s);

@@ -179,9 +179,11 @@ extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
 // pressure system over the first opts->npr rows)
 static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc,
                             hipStream_t s) {
-    pc->general = grid == nullptr;
+    pc->has_grid = grid != nullptr;
     pc->g = grid ? Grid{grid->nx, grid->ny, grid->nz} : Grid{A->nbrows, 1, 1};
+    pc->general = grid == nullptr || pc->g.n() != A->nbrows;
     pc->n = A->nbrows;
+    pc->ncell = grid ? (int)(pc->g.n() * (grid->dual ? 2 : 1)) : A->nbrows;
     pc->nnzb = A->nnzb;
     pc->o = *opts;
     pc->npr = (opts->npr > 0 && opts->npr < pc->n) ? opts->npr : pc->n;
@@ -230,17 +232,21 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
     if (!A || !opts || !A->rowptr || !A->colind || !A->val)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: NULL argument");
     if (A->nbrows < 1 || A->nnzb < A->nbrows) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: empty matrix");
-    if (grid && (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 ||
-                 (long long)grid->nx * grid->ny * grid->nz != (long long)A->nbrows))
+    const long long gn = grid ? (long long)grid->nx * grid->ny * grid->nz : 0;
+    if (grid && (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || gn * (grid->dual ? 2 : 1) > A->nbrows ||
+                 (grid->dual && gn * 2 > A->nbrows)))
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: grid does not match the matrix size");
+    const bool general = !grid || gn != A->nbrows;
     if (!grid && opts->ftype != BO_F_BJ)
         return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: without a grid the F stage must be BO_F_BJ");
-    if (!grid && opts->use_amg && opts->smoother == BO_SMOOTH_GS)
-        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: red-black Gauss-Seidel needs the grid");
-    if (grid && opts->smoother == BO_SMOOTH_L1)
+    if (general && opts->ftype == BO_F_ILU_TILED && opts->precision != BO_PREC_FP64)
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: the extended grid form's tiled ILU is FP64 only");
+    if (general && opts->use_amg && opts->smoother == BO_SMOOTH_GS)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: red-black Gauss-Seidel needs the plain grid form");
+    if (!general && opts->smoother == BO_SMOOTH_L1)
         return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: the l1 level-0 smoother is for the general form");
     if (opts->npr < 0 || opts->npr > A->nbrows) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: npr out of range");
-    if (grid && opts->npr != 0 && opts->npr != A->nbrows)
+    if (!general && opts->npr != 0 && opts->npr != A->nbrows)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: on a grid every row is a pressure row");
     if ((long long)A->nbrows * 7 >= (1LL << 31)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: matrix too large");
     const bo_cpr_opts &o = *opts;
@@ -275,9 +281,9 @@ extern "C" bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream) {
     if (!pc || !A || !A->rowptr || !A->colind || !A->val)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: NULL argument");
     if (A->nbrows != pc->n) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: matrix size differs from the setup");
-    bo_grid g{pc->g.nx, pc->g.ny, pc->g.nz};
+    bo_grid g{pc->g.nx, pc->g.ny, pc->g.nz, pc->ncell > pc->g.n() ? 1 : 0};
     bo_cpr_opts o = pc->o;
-    bo_status st = setup_impl(A, pc->general ? nullptr : &g, &o, pc, (hipStream_t)stream);
+    bo_status st = setup_impl(A, pc->has_grid ? &g : nullptr, &o, pc, (hipStream_t)stream);
     if (st != BO_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         pc->nlev = 0;

@@ -149,6 +149,33 @@ def test_general_fgmres(B, O, name, prec):
     print(f"{name} {prec}: its {info['iterations']} (oracle {io})")
 
 
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("kw", [dict(), dict(fpf=1), dict(wells_in_pressure=True, fpf=1)])
+def test_extended_grid_form_tiled_ilu(B, O, name, kw):
+    """The extended grid form: tiled block ILU(0) over fracture tiles, then the
+    tiles' matrix cells, then the well rows as a class of their own."""
+    import torch
+    kw = dict(kw)
+    wp = kw.pop("wells_in_pressure", False)
+    case, P, rp, ci, val, b = system(O, name)
+    npr = P.rows if wp else P.ncell
+    opc = O.Cpr(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, npr=npr, coarse_max=40, **kw)
+    opts = B.bo_cpr_default_opts(ftype=B.BO_F_ILU_TILED, smoother=B.BO_SMOOTH_L1, npr=npr, coarse_max=40, **kw)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz, int(case.dual)), opts)
+    rows = P.rows
+    v = np.random.default_rng(6).standard_normal(3 * rows)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_fstage, v, 3 * rows), opc.fstage(v)) <= 1e-10
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * rows), opc.apply(v)) <= 1e-10
+    xo, oinfo = O.fgmres(rp, ci, val, b, opc)
+    x = torch.zeros(3 * rows, dtype=torch.float64, device="cuda")
+    info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    r = b - O.bsr_spmv(rp, ci, val, to_host(x))
+    assert info["converged"] and np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+    io = oinfo["iterations"]
+    assert abs(info["iterations"] - io) <= max(1, math.ceil(0.1 * io))
+    print(f"{name} tiled {kw} wells-in-pressure={wp}: its {info['iterations']} (oracle {io})")
+
+
 def test_general_form_rejects_grid_only_options(B, O):
     case, P, rp, ci, val, b = system(O, "dual")
     A = device_bsr(B, rp, ci, val)
@@ -156,3 +183,34 @@ def test_general_form_rejects_grid_only_options(B, O):
         B.bo_cpr_setup(A, None, B.bo_cpr_default_opts(npr=P.ncell))        # tiled ILU needs the grid
     with pytest.raises(B.BoError):
         B.bo_cpr_setup(A, None, B.bo_cpr_default_opts(ftype=B.BO_F_BJ, npr=P.ncell))  # RB-GS needs the grid
+    grid = (case.nx, case.ny, case.nz, 1)
+    with pytest.raises(B.BoError):   # the extended form's tiled ILU is FP64 only
+        B.bo_cpr_setup(A, grid, B.bo_cpr_default_opts(smoother=B.BO_SMOOTH_L1, npr=P.ncell,
+                                                      precision=B.BO_PREC_FP32))
+
+
+def test_long_well_row_hierarchy_matches_oracle(B, O):
+    """A fixed-rate well through 600 layers makes a pressure row of 601
+    entries: its prolongator row takes the global-memory path; the hierarchy
+    must still equal the oracle's."""
+    import dataclasses
+    case = cg.tiny_case(3, 3, 600, seed=9, step=0.01,
+                        wells=[cg.Well(1, 1, 0, 599, "prod", "lrat", 500.0),
+                               cg.Well(0, 0, 0, 599, "inj", "bhp", 3500.0)])
+    case = dataclasses.replace(case, x_old=np.concatenate([case.x_old, [2800.0, 0.0, 0.0]]),
+                               x_new=np.concatenate([case.x_new, [2800.0, 0.0, 0.0]]))
+    P = O.Problem(case)
+    rp, ci, val, R = O.jacobian(P)
+    assert rp[-1] - rp[-2] == 601
+    opc = O.Cpr(P, rp, ci, val, ftype=O.F_BJ, smoother=O.SMOOTH_L1, npr=P.rows, coarse_max=40)
+    opts = B.bo_cpr_default_opts(ftype=B.BO_F_BJ, smoother=B.BO_SMOOTH_L1, npr=P.rows, coarse_max=40)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), None, opts)
+    nl = opc.nlevels()
+    assert B.bo_cpr_levels(gpc) == nl and nl >= 2
+    for l in range(nl - 1):
+        ol, gl = opc.level(l), B.bo_cpr_level_copy(gpc, l)
+        assert np.array_equal(gl["agg"], ol["agg"])
+        assert np.array_equal(gl["p_rowptr"], ol["p_rowptr"]) and np.array_equal(gl["p_colind"], ol["p_colind"])
+        assert rel_err(gl["p_val"], ol["p_val"]) <= 1e-12
+    v = np.random.default_rng(9).standard_normal(3 * P.rows)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * P.rows), opc.apply(v)) <= 1e-10
