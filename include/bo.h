@@ -250,9 +250,11 @@ typedef struct {
     int32_t orth;       /* 0: modified Gram-Schmidt, 1: classical GS twice */
     int32_t timing;     /* 1: time every Arnoldi SpMV with HIP events on the
                            solve's stream (stats.spmv_ms / spmv_calls) */
+    int32_t graph;      /* 1: replay the preconditioner as a HIP graph captured once per
+                           setup (same kernels, same results; fewer launches) */
 } bo_fgmres_opts;
 
-void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, CGS2, no timing */
+void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, CGS2, no timing, graph replay on */
 
 typedef struct {
     int32_t iterations;     /* preconditioner applications */

@@ -85,7 +85,7 @@ class BoGrid(C.Structure):
 
 class BoFgmresOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("orth", C.c_int32),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("graph", C.c_int32)]
 
 
 class BoSolveStats(C.Structure):

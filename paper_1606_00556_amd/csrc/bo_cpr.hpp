@@ -97,6 +97,10 @@ struct bo_cpr {
     bo::Reducer red;
     bo::Krylov kr;
     hipEvent_t ev[2] = {nullptr, nullptr};  // SpMV timing in bo_fgmres_solve
+    // the preconditioner as a HIP graph (captured once per setup)
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    bo::DBuf<double> g_in, g_out;
     // learned pressure-stage correction (not owned) and its work arrays
     bo_nn *nn = nullptr;
     bo::DBuf<float> nn_z;                 // standardised log-permeability

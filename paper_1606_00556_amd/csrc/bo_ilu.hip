@@ -553,9 +553,16 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
         BO_HIP(hipMemsetAsync(pc->ilu_f.p, 0, sizeof(double2) * S * kPairs, s));
         BO_HIP(hipMemsetAsync(pc->ilu_b.p, 0, sizeof(double2) * S * kPairs, s));
         int nb = T.ntx * T.nty;
-        if (st == ST_F64)
+        if (st == ST_F64) {
             k_ilu_factor<ST_F64><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
                                                    pc->ilu_slot.p, pc->flag.p, ext ? pc->x_einv_f.p : nullptr);
+        } else if (st == ST_F32) {
+            k_ilu_factor<ST_F32><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
+                                                   pc->ilu_slot.p, pc->flag.p, nullptr);
+        } else {
+            k_ilu_factor<ST_BF16><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
+                                                    pc->ilu_slot.p, pc->flag.p, nullptr);
+        }
         if (ext && pc->ncell > N) {
             BO_TRY(pc->x_einv_m.alloc(9 * N));
             BO_TRY(pc->x_amf.alloc(9 * N));
@@ -569,12 +576,6 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
             k_rows_inv<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->Arp.p, pc->Aci.p, pc->Aval.p,
                                                         pc->x_einv_w.p, pc->flag.p);
         }
-        else if (st == ST_F32)
-            k_ilu_factor<ST_F32><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
-                                                   pc->ilu_slot.p, pc->flag.p, nullptr);
-        else
-            k_ilu_factor<ST_BF16><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
-                                                    pc->ilu_slot.p, pc->flag.p, nullptr);
     }
     BO_HIP(hipGetLastError());
     int32_t bad = 0;

@@ -368,22 +368,23 @@ __global__ void __launch_bounds__(kBlock) k_cgs_pass(long long n, double *__rest
     }
 }
 
-// pass 2 (one workgroup): out[q] = sum over the partials in a fixed order
-__global__ void __launch_bounds__(kBlock) k_partial_final(int nblocks, int nv, const double *__restrict__ partial,
+// pass 2 (one workgroup per result): out[q] = sum over the partials in a
+// fixed order (strided per thread, then across the wavefront, then across the
+// four wavefronts in order)
+__global__ void __launch_bounds__(kBlock) k_partial_final(int nblocks, const double *__restrict__ partial,
                                                           double *__restrict__ out) {
-    __shared__ double sh[kMaxVecList][kBlock / 64];
+    __shared__ double sh[kBlock / 64];
     int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    for (int q = 0; q < nv; q++) {
-        double s = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s = s + partial[(size_t)q * nblocks + b];
-        s = wave_sum(s);
-        if (lane == 0) sh[q][wave] = s;
-    }
+    int q = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s = s + partial[(size_t)q * nblocks + b];
+    s = wave_sum(s);
+    if (lane == 0) sh[wave] = s;
     __syncthreads();
-    if (threadIdx.x < nv) {
+    if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < kBlock / 64; w++) t = t + sh[threadIdx.x][w];
-        out[threadIdx.x] = t;
+        for (int w = 0; w < kBlock / 64; w++) t = t + sh[w];
+        out[q] = t;
     }
 }
 
@@ -507,7 +508,7 @@ bo_status Reducer::cgs_pass(long long n, double *w, const double *const *Vhost, 
     else
         k_cgs_pass<64><<<kRedBlocks, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
     int nout = (dots || !h) ? nv : 1;
-    k_partial_final<<<1, kBlock, 0, s>>>(kRedBlocks, nout, partial.p, out);
+    k_partial_final<<<nout, kBlock, 0, s>>>(kRedBlocks, partial.p, out);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
@@ -529,7 +530,7 @@ bo_status Reducer::multidot(long long n, const double *x, const double *const *V
         VecList L{};
         for (int q = 0; q < c; q++) L.p[q] = Vhost[q0 + q];
         launch_partial(c, n, x, L, partial.p, s);
-        k_partial_final<<<1, kBlock, 0, s>>>(kRedBlocks, c, partial.p, out + q0);
+        k_partial_final<<<c, kBlock, 0, s>>>(kRedBlocks, partial.p, out + q0);
     }
     BO_HIP(hipGetLastError());
     return BO_OK;
@@ -539,7 +540,7 @@ bo_status Reducer::dot(long long n, const double *x, const double *y, double *ou
     VecList L{};
     L.p[0] = y;
     launch_partial(1, n, x, L, partial.p, s);
-    k_partial_final<<<1, kBlock, 0, s>>>(kRedBlocks, 1, partial.p, out);
+    k_partial_final<<<1, kBlock, 0, s>>>(kRedBlocks, partial.p, out);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }

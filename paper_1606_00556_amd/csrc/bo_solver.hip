@@ -144,6 +144,35 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     return axpby(3 * n, 1.0, pc->t3b.p, 1.0, z, s);
 }
 
+// z = M^{-1} v through a HIP graph of cpr_apply captured once per setup on a
+// private stream (input and output go through fixed buffers of the handle)
+bo_status cpr_apply_graph(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
+    size_t len = 3 * (size_t)pc->n;
+    if (!pc->gexec) {
+        BO_TRY(pc->g_in.alloc(len));
+        BO_TRY(pc->g_out.alloc(len));
+        if (!pc->cap_stream) BO_HIP(hipStreamCreateWithFlags(&pc->cap_stream, hipStreamNonBlocking));
+        BO_HIP(hipStreamBeginCapture(pc->cap_stream, hipStreamCaptureModeThreadLocal));
+        bo_status st = cpr_apply(pc, pc->g_in.p, pc->g_out.p, pc->cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(pc->cap_stream, &graph);
+        if (st != BO_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st != BO_OK ? st : fail(BO_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        e = hipGraphInstantiate(&pc->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            pc->gexec = nullptr;
+            return fail(BO_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+    }
+    BO_HIP(hipMemcpyAsync(pc->g_in.p, v, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
+    BO_HIP(hipGraphLaunch(pc->gexec, s));
+    BO_HIP(hipMemcpyAsync(z, pc->g_out.p, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
+    return BO_OK;
+}
+
 }  // namespace bo
 
 using namespace bo;
@@ -173,12 +202,17 @@ extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
     o->rtol = 1e-6;
     o->orth = 1;
     o->timing = 0;
+    o->graph = 1;
 }
 
 // grid == NULL: the general form (A kept as BSR; block-Jacobi F stage; the
 // pressure system over the first opts->npr rows)
 static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc,
                             hipStream_t s) {
+    if (pc->gexec) {  // buffers and levels may change: capture again on the next solve
+        (void)hipGraphExecDestroy(pc->gexec);
+        pc->gexec = nullptr;
+    }
     pc->has_grid = grid != nullptr;
     pc->g = grid ? Grid{grid->nx, grid->ny, grid->nz} : Grid{A->nbrows, 1, 1};
     pc->general = grid == nullptr || pc->g.n() != A->nbrows;
@@ -299,6 +333,8 @@ extern "C" void bo_cpr_destroy(bo_cpr *pc) {
     (void)hipDeviceSynchronize();
     for (hipEvent_t &e : pc->ev)
         if (e) (void)hipEventDestroy(e);
+    if (pc->gexec) (void)hipGraphExecDestroy(pc->gexec);
+    if (pc->cap_stream) (void)hipStreamDestroy(pc->cap_stream);
     delete pc;
 }
 
@@ -406,11 +442,15 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: the last bo_cpr_update failed");
     int m = opts->m;
     if (m < 1 || m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || (opts->orth != 0 && opts->orth != 1) ||
-        (opts->timing != 0 && opts->timing != 1))
+        (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1))
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
     hipStream_t s = (hipStream_t)stream;
     bo_solve_stats st{};
     const bool timed = opts->timing == 1;
+    // graph replay of the preconditioner (not with a network attached, whose
+    // buffers may grow during an application, nor while pairs are recorded,
+    // which counts applications on the host)
+    const bool use_graph = opts->graph == 1 && !pc->nn && !pc->rec_out;
     if (pc->nn) BO_HIP(hipMemsetAsync(pc->nn_used.p, 0, sizeof(int32_t), s));
     if (timed)
         for (hipEvent_t &e : pc->ev)
@@ -465,7 +505,8 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
         int k = 0;
         for (int j = 0; j < m; j++) {
             double *vj = V + (size_t)j * len, *zj = Z + (size_t)j * len, *w = V + (size_t)(j + 1) * len;
-            BO_TRY(cpr_apply(pc, vj, zj, s));
+            if (use_graph) BO_TRY(cpr_apply_graph(pc, vj, zj, s));
+            else BO_TRY(cpr_apply(pc, vj, zj, s));
             its++;
             if (timed) BO_HIP(hipEventRecord(pc->ev[0], s));
             BO_TRY(op_spmv(pc, 1.0, zj, 0.0, w, s));
