@@ -806,6 +806,142 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double *__restrict
     }
 }
 
+// The same Gauss-Jordan elimination for n <= 32 G (G <= 6) with the matrix
+// held in registers: thread t = 32 tc + tr owns rows tr + 32 i and columns
+// tc + 32 j (i, j < G).  The inverse is formed in place: after step k, column
+// k of the working matrix is column orig[k] of A^{-1}, where orig[] follows
+// the row swaps.  On every entry that is not structurally zero this performs
+// the same operations, in the same order, as the [A | I] form above (the unit
+// column n + orig[k] of the right half is 0 in every row but k when step k
+// begins), so both forms give the same inverse.  The row and column of the
+// step pass through LDS, double-buffered by the parity of k: two barriers per
+// pivot.  The pivot loop is split by k / 32 so that the register row and
+// column of the pivot are compile-time indices; the swapped-in row, the pivot
+// row and the pivot column are patched around one uniform update of all
+// entries.
+constexpr int kGjRegMax = 192;
+template <int G>
+__global__ void __launch_bounds__(1024) k_gj_regs(int n, const double *__restrict__ M, double *__restrict__ inv,
+                                                  int32_t *__restrict__ bad) {
+    __shared__ double rowk[2][32 * G];  // the pivot row after the swap, unscaled
+    __shared__ double rowo[2][32 * G];  // row k before the swap (it becomes row p)
+    __shared__ double colk[2][32 * G];  // column k before the step, rows before the swap
+    __shared__ int piv[2];
+    __shared__ int orig[32 * G];
+    int t = threadIdx.x, tr = t % 32, tc = t / 32;
+    int w = 2 * n;
+    double a[G][G];
+#pragma unroll
+    for (int i = 0; i < G; i++)
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            int r = tr + 32 * i, c = tc + 32 * j;
+            a[i][j] = (r < n && c < n) ? M[(size_t)r * w + c] : 0.0;
+        }
+    for (int q = t; q < n; q += blockDim.x) orig[q] = q;
+#pragma unroll
+    for (int kg = 0; kg < G; kg++) {
+        for (int kr = 0; kr < 32; kr++) {
+            int k = 32 * kg + kr;
+            if (k >= n) break;
+            int h = k & 1;
+            // column k: its owners (tc == kr) are the 32 lanes of one half wavefront
+            if (tc == kr) {
+                double bv = -1.0;
+                int bi = n;
+                bool nan = false;
+#pragma unroll
+                for (int i = 0; i < G; i++) {
+                    int r = tr + 32 * i;
+                    double v = a[i][kg];
+                    if (r < n) colk[h][r] = v;
+                    if (r >= k && r < n) {
+                        double av = fabs(v);
+                        nan = nan || av != av;
+                        if (av > bv) { bv = av; bi = r; }
+                    }
+                }
+                for (int off = 16; off > 0; off >>= 1) {
+                    double ov = __shfl_xor(bv, off, 64);
+                    int oi = __shfl_xor(bi, off, 64);
+                    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+                }
+                if (nan) *bad = 1;
+                if (tr == 0) {
+                    piv[h] = bi;
+                    if (!(bv > 0.0)) *bad = 1;
+                }
+            }
+            __syncthreads();
+            int p = piv[h];
+            if (p >= n) p = k;  // no finite candidate: flagged above, no swap
+            int pi = p / 32, pr = p % 32;
+            if (tr == kr)
+#pragma unroll
+                for (int j = 0; j < G; j++) {
+                    int c = tc + 32 * j;
+                    if (c < n) rowo[h][c] = a[kg][j];
+                }
+#pragma unroll
+            for (int i = 0; i < G; i++)
+                if (i == pi && tr == pr)
+#pragma unroll
+                    for (int j = 0; j < G; j++) {
+                        int c = tc + 32 * j;
+                        if (c < n) rowk[h][c] = a[i][j];
+                    }
+            if (t == 0 && p != k) {
+                int o = orig[k];
+                orig[k] = orig[p];
+                orig[p] = o;
+            }
+            __syncthreads();
+            double d = rowk[h][k];
+            double pk[G];
+#pragma unroll
+            for (int j = 0; j < G; j++) {
+                int c = tc + 32 * j;
+                pk[j] = c < n ? (c == k ? 1.0 / d : rowk[h][c] / d) : 0.0;
+            }
+            double fk = colk[h][k];
+            double f[G];
+#pragma unroll
+            for (int i = 0; i < G; i++) {
+                int r = tr + 32 * i;
+                f[i] = r == p ? fk : (r < n ? colk[h][r] : 0.0);
+            }
+            // row p now holds the old row k
+#pragma unroll
+            for (int i = 0; i < G; i++)
+                if (i == pi && tr == pr)
+#pragma unroll
+                    for (int j = 0; j < G; j++) {
+                        int c = tc + 32 * j;
+                        a[i][j] = c < n ? rowo[h][c] : 0.0;
+                    }
+#pragma unroll
+            for (int i = 0; i < G; i++)
+#pragma unroll
+                for (int j = 0; j < G; j++) a[i][j] = a[i][j] - f[i] * pk[j];
+            // the unit column n + orig[k] of the [A | I] form, and the pivot row
+            if (tc == kr)
+#pragma unroll
+                for (int i = 0; i < G; i++) a[i][kg] = 0.0 - f[i] * pk[kg];
+            if (tr == kr)
+#pragma unroll
+                for (int j = 0; j < G; j++) a[kg][j] = pk[j];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < G; i++)
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            int r = tr + 32 * i, c = tc + 32 * j;
+            if (r < n && c < n) inv[(size_t)r * n + orig[c]] = a[i][j];
+        }
+}
+
 __global__ void k_extract_inverse(int n, const double *__restrict__ M, double *__restrict__ inv) {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n * n) return;
@@ -917,6 +1053,7 @@ __global__ void __launch_bounds__(kBlock) k_csr_rowop(int n, const int32_t *__re
         return;
     }
     T s = 0;
+#pragma unroll 4
     for (int e = rp[row] + sub; e < rp[row + 1]; e += G) s = s + v[e] * x[ci[e]];
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) s = s + __shfl_xor(s, off, G);
@@ -981,10 +1118,12 @@ static bo_status csr_rowop(int n, int nnz, const int32_t *rp, const int32_t *ci,
 #define BO_ROWOP(G)                                                                                  \
     threads = (long long)n * G;                                                                      \
     k_csr_rowop<G, T><<<grid_for(threads), kBlock, 0, s>>>(n, rp, ci, v, x, op, b, dpos, dl1, y)
-    if (avg <= 6.0) { BO_ROWOP(4); }
-    else if (avg <= 12.0) { BO_ROWOP(8); }
-    else if (avg <= 24.0) { BO_ROWOP(16); }
-    else if (avg <= 48.0) { BO_ROWOP(32); }
+    // two to four entries per lane: a wavefront then covers several rows per
+    // round trip to memory
+    if (avg <= 8.0) { BO_ROWOP(4); }
+    else if (avg <= 16.0) { BO_ROWOP(8); }
+    else if (avg <= 64.0) { BO_ROWOP(16); }
+    else if (avg <= 128.0) { BO_ROWOP(32); }
     else { BO_ROWOP(64); }
 #undef BO_ROWOP
     BO_HIP(hipGetLastError());
@@ -1262,8 +1401,16 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
     BO_TRY(pc->cinv.alloc((size_t)nc * nc));
     k_dense_from_csr<<<grid_for(nc), kBlock, 0, s>>>(nc, Lc.rp.p, Lc.ci.p, Lc.v.p, M.p);
     BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    k_gauss_jordan<<<1, 1024, 0, s>>>(nc, M.p, flag);
-    k_extract_inverse<<<grid_for((long long)nc * nc), kBlock, 0, s>>>(nc, M.p, pc->cinv.p);
+    if (nc <= 128) {
+        k_gj_regs<4><<<1, 1024, 0, s>>>(nc, M.p, pc->cinv.p, flag);
+    } else if (nc <= 160) {
+        k_gj_regs<5><<<1, 1024, 0, s>>>(nc, M.p, pc->cinv.p, flag);
+    } else if (nc <= kGjRegMax) {
+        k_gj_regs<6><<<1, 1024, 0, s>>>(nc, M.p, pc->cinv.p, flag);
+    } else {
+        k_gauss_jordan<<<1, 1024, 0, s>>>(nc, M.p, flag);
+        k_extract_inverse<<<grid_for((long long)nc * nc), kBlock, 0, s>>>(nc, M.p, pc->cinv.p);
+    }
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
     BO_TRY(read_flag(flag, s, &bad));
@@ -1324,7 +1471,9 @@ static bo_status smooth0(bo_cpr *pc, const T *b, T *x, bool forward, hipStream_t
 // and the result is returned in one of x / t
 template <typename T>
 static bo_status smooth_c(Level &L, int sweeps, bool l1, const T *b, T *x, T **res, hipStream_t s) {
-    T *cur = x, *oth = Prec<T>::t(L);
+    // a sweep reads its input at the neighbours, so it never writes in place:
+    // the two level buffers alternate, starting from the one x is not
+    T *cur = x, *oth = x == Prec<T>::t(L) ? Prec<T>::x(L) : Prec<T>::t(L);
     const T *d = Prec<T>::dl1(L);
     int first = 0;
     if (!x) {

@@ -15,8 +15,8 @@
 // barriers).  The factors are stored in the same (tile, step, lane) order,
 // packed in pairs, so each step reads its 36 doubles with 18 contiguous 1 KB
 // wavefront loads, and the fields of the next two steps are loaded before the
-// current step is computed.  Block Jacobi (x_i = A_ii^{-1} r_i) is the alternative F
-// stage.
+// current step is computed.  Block Jacobi (x_i = A_ii^{-1} r_i) is the
+// alternative F stage.
 //
 // Mixed form: the factors (E^{-1} and the blocks of A) are computed in FP64
 // and stored rounded to FP32 (9 float4 per slot and sweep) or to BF16 (9 uint2

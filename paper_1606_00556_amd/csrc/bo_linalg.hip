@@ -165,12 +165,17 @@ __global__ void k_bsr_to_slots(int nx, int ny, int nz, const int32_t *__restrict
 }
 
 // y = alpha A x + beta y on the slot layout.  Each row sums its blocks in
-// ascending column order and each block's entries in ascending order.
+// ascending column order and each block's entries in ascending order.  The
+// workgroups run in launch order (not remapped per XCD), so the whole chip
+// reads each of the 63 coefficient arrays at one advancing front, and the
+// coefficients, read once per launch, are loaded non-temporally (streamed
+// past the caches).  Measured on the 2M-cell grid this reads 12 % faster than
+// one contiguous row range per XCD.
 __global__ void __launch_bounds__(kBlock) k_slot_spmv(int nx, int ny, int nz, const double *__restrict__ A,
                                                       double alpha, const double *__restrict__ x, double beta,
                                                       double *__restrict__ y) {
     int n = nx * ny * nz;
-    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     size_t N = (size_t)n;
     int nxy = nx * ny;
@@ -184,9 +189,12 @@ __global__ void __launch_bounds__(kBlock) k_slot_spmv(int nx, int ny, int nz, co
         if (j < 0) continue;
         const double *a = A + (size_t)s * 9 * N + i;
         double x0 = x[3 * (size_t)j], x1 = x[3 * (size_t)j + 1], x2 = x[3 * (size_t)j + 2];
-        s0 = s0 + a[0 * N] * x0; s0 = s0 + a[1 * N] * x1; s0 = s0 + a[2 * N] * x2;
-        s1 = s1 + a[3 * N] * x0; s1 = s1 + a[4 * N] * x1; s1 = s1 + a[5 * N] * x2;
-        s2 = s2 + a[6 * N] * x0; s2 = s2 + a[7 * N] * x1; s2 = s2 + a[8 * N] * x2;
+        double e[9];
+#pragma unroll
+        for (int z = 0; z < 9; z++) e[z] = __builtin_nontemporal_load(a + z * N);
+        s0 = s0 + e[0] * x0; s0 = s0 + e[1] * x1; s0 = s0 + e[2] * x2;
+        s1 = s1 + e[3] * x0; s1 = s1 + e[4] * x1; s1 = s1 + e[5] * x2;
+        s2 = s2 + e[6] * x0; s2 = s2 + e[7] * x1; s2 = s2 + e[8] * x2;
     }
     double *yi = y + 3 * (size_t)i;
     if (beta == 0.0) {
