@@ -246,51 +246,90 @@ __global__ void k_mis_init(int n, const int32_t *__restrict__ rp, const uint8_t 
     state[i] = deg ? UND : ISO;
 }
 
+// The MIS-2 round kernels take G lanes per row (G a power of two dividing
+// 64): the lanes stride the row's entries and combine their maxima or flags
+// with cross-lane shuffles.  Maxima and ORs do not depend on the order, so
+// every G gives the same round.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off, int width) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = (uint32_t)__shfl_xor((int)lo, off, width);
+    hi = (uint32_t)__shfl_xor((int)hi, off, width);
+    return ((uint64_t)hi << 32) | lo;
+}
+template <int G>
+__device__ __forceinline__ uint64_t group_max(uint64_t m) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        uint64_t o = shfl_xor_u64(m, off, G);
+        if (o > m) m = o;
+    }
+    return m;
+}
+template <int G>
+__device__ __forceinline__ int group_or(int d) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) d |= __shfl_xor(d, off, G);
+    return d;
+}
+
+template <int G>
 __global__ void k_mis_m1(int n, int level, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                          const uint8_t *__restrict__ sf, const uint8_t *__restrict__ state,
                          uint64_t *__restrict__ m1) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint64_t m = state[i] == UND ? prio(i, level) : 0ull;
-    for (int e = rp[i]; e < rp[i + 1]; e++)
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int i = (int)(gid / G), sub = (int)(gid % G);
+    if (i >= n) return;  // whole groups leave together
+    uint64_t m = sub == 0 && state[i] == UND ? prio(i, level) : 0ull;
+    for (int e = rp[i] + sub; e < rp[i + 1]; e += G)
         if (sf[e] && state[ci[e]] == UND) {
             uint64_t q = prio(ci[e], level);
             if (q > m) m = q;
         }
-    m1[i] = m;
+    m = group_max<G>(m);
+    if (sub == 0) m1[i] = m;
 }
 
+template <int G>
 __global__ void k_mis_m2(int n, int level, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                          const uint8_t *__restrict__ sf, const uint8_t *__restrict__ state,
                          const uint64_t *__restrict__ m1, uint8_t *__restrict__ nw) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int i = (int)(gid / G), sub = (int)(gid % G);
     if (i >= n) return;
-    uint64_t m = m1[i];
-    for (int e = rp[i]; e < rp[i + 1]; e++)
+    uint64_t m = sub == 0 ? m1[i] : 0ull;
+    for (int e = rp[i] + sub; e < rp[i + 1]; e += G)
         if (sf[e] && m1[ci[e]] > m) m = m1[ci[e]];
-    nw[i] = state[i] == UND && m == prio(i, level);
+    m = group_max<G>(m);
+    if (sub == 0) nw[i] = state[i] == UND && m == prio(i, level);
 }
 
+template <int G>
 __global__ void k_mis_spread(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                              const uint8_t *__restrict__ sf, const uint8_t *__restrict__ in,
                              uint8_t *__restrict__ out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int i = (int)(gid / G), sub = (int)(gid % G);
     if (i >= n) return;
-    uint8_t d = in[i];
-    for (int e = rp[i]; e < rp[i + 1]; e++)
+    int d = sub == 0 ? in[i] : 0;
+    for (int e = rp[i] + sub; e < rp[i + 1]; e += G)
         if (sf[e]) d |= in[ci[e]];
-    out[i] = d;
+    d = group_or<G>(d);
+    if (sub == 0) out[i] = (uint8_t)d;
 }
 
+template <int G>
 __global__ void k_mis_update(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                              const uint8_t *__restrict__ sf, const uint8_t *__restrict__ nw,
                              const uint8_t *__restrict__ d1, uint8_t *__restrict__ state,
                              int32_t *__restrict__ any) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int i = (int)(gid / G), sub = (int)(gid % G);
     if (i >= n) return;
-    uint8_t d = d1[i];
-    for (int e = rp[i]; e < rp[i + 1]; e++)
+    int d = sub == 0 ? d1[i] : 0;
+    for (int e = rp[i] + sub; e < rp[i + 1]; e += G)
         if (sf[e]) d |= d1[ci[e]];
+    d = group_or<G>(d);
+    if (sub != 0) return;
     uint8_t st = state[i];
     if (nw[i]) st = IN;
     else if (st == UND && d) st = OUT;
@@ -635,13 +674,15 @@ __global__ void __launch_bounds__(kBlock) k_sort_rows(int n, const int32_t *__re
 __global__ void k_spgemm_bound(int n, const int32_t *__restrict__ arp, const int32_t *__restrict__ aci,
                                const int32_t *__restrict__ brp, int32_t *__restrict__ mx) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     int c = 0;
-    for (int e = arp[i]; e < arp[i + 1]; e++) c += brp[aci[e] + 1] - brp[aci[e]];
-    atomicMax(mx, c);
+    if (i < n)
+        for (int e = arp[i]; e < arp[i + 1]; e++) c += brp[aci[e] + 1] - brp[aci[e]];
+    // one atomic per wavefront
+    for (int off = 32; off > 0; off >>= 1) c = max(c, __shfl_xor(c, off, 64));
+    if (threadIdx.x % 64 == 0 && c > 0) atomicMax(mx, c);
 }
 
-template <int G, int H>
+template <int G, int H, bool NUM>
 __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict__ arp,
                                                const int32_t *__restrict__ aci, const double *__restrict__ av,
                                                const int32_t *__restrict__ brp, const int32_t *__restrict__ bci,
@@ -649,33 +690,75 @@ __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict
                                                const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
                                                double *__restrict__ cv, int32_t *__restrict__ bad) {
     constexpr int R = 256 / G;
+    constexpr int HV = NUM ? H : 1;  // the counting pass keeps no values
     __shared__ int key[R][H];
-    __shared__ double val[R][H];
+    __shared__ double val[R][HV];
     __shared__ int nl[R];
     int grp = threadIdx.x / G, sub = threadIdx.x % G;
     int i = blockIdx.x * R + grp;
-    for (int t = sub; t < H; t += G) { key[grp][t] = -1; val[grp][t] = 0.0; }
+    for (int t = sub; t < H; t += G) key[grp][t] = -1;
+    if (NUM)
+        for (int t = sub; t < HV; t += G) val[grp][t] = 0.0;
     if (sub == 0) nl[grp] = 0;
     __syncthreads();
     if (i >= n) return;
-    const bool numeric = cci != nullptr;
-    for (int e = arp[i]; e < arp[i + 1]; e++) {
-        int k = aci[e];
-        double a = numeric ? av[e] : 0.0;
-        for (int f = brp[k] + sub; f < brp[k + 1]; f += G) {
-            int c = bci[f];
-            unsigned h = ((unsigned)c * 2654435761u) & (H - 1);
-            int slot = -1;
-            for (int probe = 0; probe < H; probe++) {
-                int old = atomicCAS(&key[grp][h], -1, c);
-                if (old == -1 || old == c) { slot = (int)h; break; }
-                h = (h + 1) & (H - 1);
-            }
-            if (slot < 0) { *bad = 1; continue; }
-            if (numeric) val[grp][slot] = val[grp][slot] + a * bv[f];
+    constexpr bool numeric = NUM;
+    // one product: the column's slot (linear probing), then its sum
+    auto insert = [&](int c, double prod) {
+        unsigned h = ((unsigned)c * 2654435761u) & (H - 1);
+        int slot = -1;
+        for (int probe = 0; probe < H; probe++) {
+            int old = atomicCAS(&key[grp][h], -1, c);
+            if (old == -1 || old == c) { slot = (int)h; break; }
+            h = (h + 1) & (H - 1);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
+        if (slot < 0) { *bad = 1; return; }
+        if (numeric) val[grp][slot % HV] = val[grp][slot % HV] + prod;
+    };
+    // The row of A goes in chunks of G entries: lane u of the group holds
+    // entry u of the chunk with the bounds of its row of B.  The first G
+    // entries of the next kP rows of B are loaded together before they are
+    // hashed, so the loads' latency is paid once per kP entries of A.
+    constexpr int kP = 8;
+    const int a0 = arp[i], a1 = arp[i + 1];
+    for (int c0 = a0; c0 < a1; c0 += G) {
+        const int m = min(G, a1 - c0);
+        int lk_s = 0, lk_e = 0;
+        double lk_a = 0.0;
+        if (sub < m) {
+            int k = aci[c0 + sub];
+            lk_s = brp[k];
+            lk_e = brp[k + 1];
+            lk_a = numeric ? av[c0 + sub] : 0.0;
+        }
+        for (int u0 = 0; u0 < m; u0 += kP) {
+            int cc[kP], fs[kP], fe[kP];
+            double bb[kP], aq[kP];
+#pragma unroll
+            for (int q = 0; q < kP; q++) {
+                cc[q] = -1; bb[q] = 0.0; aq[q] = 0.0; fs[q] = 0; fe[q] = 0;
+                if (u0 + q < m) {
+                    fs[q] = __shfl(lk_s, u0 + q, G);
+                    fe[q] = __shfl(lk_e, u0 + q, G);
+                    aq[q] = __shfl(lk_a, u0 + q, G);
+                    int f = fs[q] + sub;
+                    if (f < fe[q]) {
+                        cc[q] = bci[f];
+                        if (numeric) bb[q] = bv[f];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kP; q++) {
+                if (u0 + q < m) {
+                    if (cc[q] >= 0) insert(cc[q], aq[q] * bb[q]);
+                    for (int f = fs[q] + sub + G; f < fe[q]; f += G) insert(bci[f], numeric ? aq[q] * bv[f] : 0.0);
+                }
+                // the next entry of A may add to the same columns
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -687,7 +770,7 @@ __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict
 #pragma unroll
     for (int u = 0; u < PER; u++) {
         kk[u] = key[grp][sub + u * G];
-        vv[u] = numeric ? val[grp][sub + u * G] : 0.0;
+        vv[u] = numeric ? val[grp][(sub + u * G) % HV] : 0.0;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -696,26 +779,26 @@ __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict
         if (kk[u] >= 0) {
             int p = atomicAdd(&nl[grp], 1);
             key[grp][p] = kk[u];
-            val[grp][p] = vv[u];
+            if (numeric) val[grp][p % HV] = vv[u];
         }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     int L = nl[grp];
-    if (!numeric) {
+    if constexpr (!numeric) {
         if (sub == 0) {
             cnt[i] = L;
             if (L > H / 2) *bad = 1;
         }
-        return;
-    }
-    // each distinct column goes to its rank among the row's columns
-    int base = crp[i];
-    for (int t = sub; t < L; t += G) {
-        int c = key[grp][t];
-        int rank = 0;
-        for (int u = 0; u < L; u++) rank += key[grp][u] < c;
-        cci[base + rank] = c;
-        cv[base + rank] = val[grp][t];
+    } else {
+        // each distinct column goes to its rank among the row's columns
+        int base = crp[i];
+        for (int t = sub; t < L; t += G) {
+            int c = key[grp][t];
+            int rank = 0;
+            for (int u = 0; u < L; u++) rank += key[grp][u] < c;
+            cci[base + rank] = c;
+            cv[base + rank] = val[grp][t];
+        }
     }
 }
 
@@ -1219,16 +1302,24 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     // row grow with the work per row
     int sel;
     if (bound <= 32) sel = 0;
+    else if (bound <= 64) sel = 4;
     else if (bound <= 128) sel = 1;
     else if (bound <= 512) sel = 2;
     else sel = 3;
     auto launch = [&](int32_t *c, const int32_t *rp_, int32_t *ci_, double *v_) {
+#define BO_SPGEMM(G, H)                                                                                   \
+    if (ci_) k_spgemm<G, H, true><<<grid_for((long long)n * G), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, \
+                                                                           c, rp_, ci_, v_, flag);        \
+    else k_spgemm<G, H, false><<<grid_for((long long)n * G), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, \
+                                                                         rp_, ci_, v_, flag)
         switch (sel) {
-        case 0: k_spgemm<8, 64><<<grid_for((long long)n * 8), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, rp_, ci_, v_, flag); break;
-        case 1: k_spgemm<16, 256><<<grid_for((long long)n * 16), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, rp_, ci_, v_, flag); break;
-        case 2: k_spgemm<64, 1024><<<grid_for((long long)n * 64), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, rp_, ci_, v_, flag); break;
-        default: k_spgemm<64, 2048><<<grid_for((long long)n * 64), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, rp_, ci_, v_, flag); break;
+        case 0: BO_SPGEMM(8, 64); break;
+        case 4: BO_SPGEMM(8, 128); break;
+        case 1: BO_SPGEMM(16, 256); break;
+        case 2: BO_SPGEMM(64, 1024); break;
+        default: BO_SPGEMM(64, 2048); break;
         }
+#undef BO_SPGEMM
     };
     launch(cnt.p, nullptr, nullptr, nullptr);
     BO_HIP(hipGetLastError());
@@ -1302,10 +1393,21 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
             if (round > 10000) return fail(BO_ERR_HIP, "AMG: MIS-2 did not terminate");
             for (int rep = 0; rep < 2; rep++) {
                 BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-                k_mis_m1<<<grid_for(n), kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p);
-                k_mis_m2<<<grid_for(n), kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p, nw.p);
-                k_mis_spread<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p);
-                k_mis_update<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p, state.p, flag);
+                // lanes per row: about two to four entries per lane
+#define BO_MIS_ROUND(G)                                                                                       \
+    do {                                                                                                      \
+        unsigned gb = grid_for((long long)n * G);                                                            \
+        k_mis_m1<G><<<gb, kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p);                      \
+        k_mis_m2<G><<<gb, kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p, nw.p);                \
+        k_mis_spread<G><<<gb, kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p);                        \
+        k_mis_update<G><<<gb, kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p, state.p, flag);         \
+    } while (0)
+                double avg = (double)L.nnz / n;
+                if (avg <= 10.0) BO_MIS_ROUND(1);
+                else if (avg <= 20.0) BO_MIS_ROUND(4);
+                else if (avg <= 40.0) BO_MIS_ROUND(8);
+                else BO_MIS_ROUND(16);
+#undef BO_MIS_ROUND
             }
             BO_HIP(hipGetLastError());
             int32_t any = 0;
