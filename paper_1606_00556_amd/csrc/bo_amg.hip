@@ -389,20 +389,26 @@ __global__ void k_filter(int n, const int32_t *__restrict__ rp, const int32_t *_
                          const uint8_t *__restrict__ sf, double *__restrict__ aF,
                          unsigned long long *__restrict__ rho_bits) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double aii = v[dpos[i]];
-    double d = aii;
-    for (int e = rp[i]; e < rp[i + 1]; e++)
-        if (ci[e] != i && !sf[e]) d = d + v[e];
-    if (d == 0.0) d = aii;
-    aF[i] = d;
-    double rs = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; e++) {
-        if (ci[e] == i) rs = rs + fabs(d);
-        else if (sf[e]) rs = rs + fabs(v[e]);
+    uint64_t bits = 0;
+    if (i < n) {
+        double aii = v[dpos[i]];
+        double d = aii;
+        for (int e = rp[i]; e < rp[i + 1]; e++)
+            if (ci[e] != i && !sf[e]) d = d + v[e];
+        if (d == 0.0) d = aii;
+        aF[i] = d;
+        double rs = 0.0;
+        for (int e = rp[i]; e < rp[i + 1]; e++) {
+            if (ci[e] == i) rs = rs + fabs(d);
+            else if (sf[e]) rs = rs + fabs(v[e]);
+        }
+        double ratio = rs / fabs(d);
+        bits = (uint64_t)__double_as_longlong(ratio);
     }
-    double ratio = rs / fabs(d);
-    atomicMax(rho_bits, (unsigned long long)__double_as_longlong(ratio));
+    // the ratios are >= 0, so their bit patterns order as the values; one
+    // atomic per wavefront
+    bits = group_max<64>(bits);
+    if (threadIdx.x % 64 == 0) atomicMax(rho_bits, (unsigned long long)bits);
 }
 
 __device__ __forceinline__ bool p_takes(int e, int i, const int32_t *ci, const uint8_t *sf, const int32_t *agg) {
@@ -1185,9 +1191,8 @@ __global__ void k_f32_to_f64(long long n, const float *__restrict__ a, double *_
 }
 
 bo_status read_flag(int32_t *dflag, hipStream_t s, int32_t *out) {
-    BO_HIP(hipMemcpyAsync(out, dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    BO_HIP(hipStreamSynchronize(s));
-    return BO_OK;
+    HostRead r{dflag, sizeof(int32_t), out};
+    return host_reads(&r, 1, s);
 }
 
 }  // namespace
@@ -1323,17 +1328,15 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     };
     launch(cnt.p, nullptr, nullptr, nullptr);
     BO_HIP(hipGetLastError());
-    int32_t bad = 0;
-    BO_TRY(read_flag(flag, s, &bad));
+    int32_t bad = 0, total = 0;
+    BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s, flag, &bad));
     if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: Galerkin product row exceeds the LDS hash capacity");
-    int32_t total = 0;
-    BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s));
     BO_TRY(cci.alloc(total));
     BO_TRY(cv.alloc(total));
+    // with every row within half the hash (checked above) no insertion of the
+    // second pass can fail
     launch(nullptr, crp.p, cci.p, cv.p);
     BO_HIP(hipGetLastError());
-    BO_TRY(read_flag(flag, s, &bad));
-    if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: Galerkin product row exceeds the LDS hash capacity");
     *cnnz = total;
     return BO_OK;
 }
@@ -1387,11 +1390,12 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         DBuf<uint64_t> &m1 = W.m1;
         BO_TRY(state.alloc(n)); BO_TRY(nw.alloc(n)); BO_TRY(d1.alloc(n)); BO_TRY(m1.alloc(n));
         k_mis_init<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.sf.p, state.p);
-        // rounds are checked for completion every second round: a round on a
-        // graph with no undecided node changes nothing
+        // rounds are checked for completion after the fourth and then every
+        // second round: a round on a graph with no undecided node changes
+        // nothing
         for (int round = 0;; round += 2) {
             if (round > 10000) return fail(BO_ERR_HIP, "AMG: MIS-2 did not terminate");
-            for (int rep = 0; rep < 2; rep++) {
+            for (int rep = 0; rep < (round == 0 ? 4 : 2); rep++) {
                 BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
                 // lanes per row: about two to four entries per lane
 #define BO_MIS_ROUND(G)                                                                                       \
@@ -1438,8 +1442,8 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         BO_HIP(hipMemsetAsync(rho.p, 0, sizeof(unsigned long long), s));
         k_filter<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.sf.p, aF.p, rho.p);
         unsigned long long rb = 0;
-        BO_HIP(hipMemcpyAsync(&rb, rho.p, sizeof rb, hipMemcpyDeviceToHost, s));
-        BO_HIP(hipStreamSynchronize(s));
+        HostRead rr{rho.p, sizeof rb, &rb};
+        BO_TRY(host_reads(&rr, 1, s));
         double rhov;
         std::memcpy(&rhov, &rb, sizeof rhov);
         if (!(rhov > 0.0) || !(rhov < INFINITY)) return fail(BO_ERR_SINGULAR_COARSE, "AMG: bad smoother bound");

@@ -46,9 +46,15 @@ struct DBuf {
         p = nullptr;
         n = 0;
     }
+    // Grows only: a buffer that has to grow again (a rebuild for a system
+    // with larger coarse levels) takes a quarter more than asked, so that a
+    // sequence of similar systems stops reallocating (hipFree / hipMalloc
+    // synchronise the device).
     bo_status alloc(size_t count) {
         if (count <= n && p) return BO_OK;
+        bool regrow = p != nullptr;
         release();
+        if (regrow) count = std::max(count, count + count / 4);
         size_t bytes = (count ? count : 1) * sizeof(T);
         hipError_t e = hipMalloc((void **)&p, bytes);
         if (e != hipSuccess) {
@@ -172,9 +178,22 @@ __device__ inline double block_sum(double v, double *sh) {
 enum ScratchSlot { SC_SCAN = 0, SC_FLAG, SC_JAC_CNT, SC_COUNT };
 bo_status scratch_get(int slot, size_t bytes, void **ptr);
 
+// ---- small device-to-host reads ----------------------------------------------------
+// Each read goes through a pinned host buffer (one per host thread, 4 KB,
+// never freed), so the copy is a direct DMA; one stream synchronisation
+// serves all the reads of a call.
+struct HostRead {
+    const void *src;  // device
+    size_t bytes;
+    void *dst;        // host
+};
+bo_status host_reads(const HostRead *r, int count, hipStream_t s);
+
 // ---- host-side scan / reductions (declared in bo_linalg.hip) -------------------
 // Exclusive prefix sum of n int32 counts into out (n+1 entries, out[n] = total);
-// returns the total on the host (synchronises the stream).
-bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s);
+// returns the total on the host (synchronises the stream).  With dflag set,
+// *hflag receives that device word in the same synchronisation.
+bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s,
+                      const int32_t *dflag = nullptr, int32_t *hflag = nullptr);
 
 }  // namespace bo

@@ -579,8 +579,8 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
     }
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
-    BO_HIP(hipMemcpyAsync(&bad, pc->flag.p, sizeof bad, hipMemcpyDeviceToHost, s));
-    BO_HIP(hipStreamSynchronize(s));
+    HostRead rd{pc->flag.p, sizeof bad, &bad};
+    BO_TRY(host_reads(&rd, 1, s));
     if (bad) return fail(BO_ERR_SINGULAR_BLOCK, "F stage: singular 3x3 pivot block");
     return BO_OK;
 }

@@ -13,6 +13,7 @@
 // the partials in a fixed order (no device-scope fences in the hot loop).
 #include <algorithm>
 #include "bo_common.hpp"
+#include <cstring>
 #include "bo_linalg.hpp"
 
 namespace bo {
@@ -40,6 +41,31 @@ bo_status scratch_get(int slot, size_t bytes, void **ptr) {
         cap[slot] = want;
     }
     *ptr = buf[slot];
+    return BO_OK;
+}
+
+bo_status host_reads(const HostRead *r, int count, hipStream_t s) {
+    constexpr size_t kMail = 4096;
+    static thread_local char *mail = nullptr;
+    if (!mail) {
+        hipError_t e = hipHostMalloc((void **)&mail, kMail, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            mail = nullptr;
+            return fail(BO_ERR_ALLOC, std::string("hipHostMalloc of the read buffer failed: ") + hipGetErrorString(e));
+        }
+    }
+    size_t off = 0;
+    for (int q = 0; q < count; q++) {
+        if (off + r[q].bytes > kMail) return fail(BO_ERR_INVALID_ARG, "host_reads: more than 4 KB");
+        BO_HIP(hipMemcpyAsync(mail + off, r[q].src, r[q].bytes, hipMemcpyDeviceToHost, s));
+        off += (r[q].bytes + 15) / 16 * 16;
+    }
+    BO_HIP(hipStreamSynchronize(s));
+    off = 0;
+    for (int q = 0; q < count; q++) {
+        std::memcpy(r[q].dst, mail + off, r[q].bytes);
+        off += (r[q].bytes + 15) / 16 * 16;
+    }
     return BO_OK;
 }
 
@@ -100,11 +126,17 @@ __global__ void k_scan_apply(const int32_t *in, int n, const int32_t *sums, int3
     if (base + t == n - 1) out[n] = sums[blockIdx.x] + sh[t];
 }
 
-bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s) {
+bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s,
+                      const int32_t *dflag, int32_t *hflag) {
     if (n <= 0) {
         int32_t z = 0;
         BO_HIP(hipMemcpyAsync(out, &z, sizeof z, hipMemcpyHostToDevice, s));
-        BO_HIP(hipStreamSynchronize(s));
+        if (dflag) {
+            HostRead r{dflag, sizeof(int32_t), hflag};
+            BO_TRY(host_reads(&r, 1, s));
+        } else {
+            BO_HIP(hipStreamSynchronize(s));
+        }
         if (total) *total = 0;
         return BO_OK;
     }
@@ -116,8 +148,8 @@ bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total
     k_scan_apply<<<nb, kScanBlock, 0, s>>>(counts, n, sums, out);
     BO_HIP(hipGetLastError());
     int32_t tot = 0;
-    BO_HIP(hipMemcpyAsync(&tot, out + n, sizeof tot, hipMemcpyDeviceToHost, s));
-    BO_HIP(hipStreamSynchronize(s));
+    HostRead r[2] = {{out + n, sizeof tot, &tot}, {dflag, sizeof(int32_t), hflag}};
+    BO_TRY(host_reads(r, dflag ? 2 : 1, s));
     if (total) *total = tot;
     return BO_OK;
 }
@@ -462,8 +494,8 @@ bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, cons
     k_bsr_to_slots<<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, rp, ci, v, slots, bad);
     BO_HIP(hipGetLastError());
     int32_t h = 0;
-    BO_HIP(hipMemcpyAsync(&h, bad, sizeof h, hipMemcpyDeviceToHost, s));
-    BO_HIP(hipStreamSynchronize(s));
+    HostRead r{bad, sizeof h, &h};
+    BO_TRY(host_reads(&r, 1, s));
     if (h) return fail(BO_ERR_UNSUPPORTED, "matrix pattern is not the 7-point stencil of the grid");
     return BO_OK;
 }

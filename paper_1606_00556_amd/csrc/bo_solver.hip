@@ -229,8 +229,8 @@ static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_o
     k_check_finite<<<grid_for(9LL * A->nnzb), kBlock, 0, s>>>(9LL * A->nnzb, A->val, pc->flag.p);
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
-    BO_HIP(hipMemcpyAsync(&bad, pc->flag.p, sizeof bad, hipMemcpyDeviceToHost, s));
-    BO_HIP(hipStreamSynchronize(s));
+    HostRead rd{pc->flag.p, sizeof bad, &bad};
+    BO_TRY(host_reads(&rd, 1, s));
     if (bad) return fail(BO_ERR_NONFINITE, "bo_cpr_setup: the matrix holds NaN or Inf");
     if (pc->general) {
         BO_TRY(pc->Arp.alloc(n + 1));
