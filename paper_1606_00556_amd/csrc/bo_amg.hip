@@ -1043,10 +1043,13 @@ __global__ void k_extract_inverse(int n, const double *__restrict__ M, double *_
 // form: hierarchy stored in FP32, FP32 arithmetic and accumulation).
 template <typename T> __device__ __forceinline__ T two_thirds() { return (T)(2.0 / 3.0); }
 
-// level 0 on the grid (slot form), colour c of red-black Gauss-Seidel
+// level 0 on the grid (slot form), colour c of red-black Gauss-Seidel; with
+// zero set the other colour is taken as 0 and x is not read (b - 0 is b
+// exactly, so this equals the sweep over a zeroed x)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gs_slots(int nx, int ny, int nz, const T *__restrict__ A,
-                                                     const T *__restrict__ b, T *__restrict__ x, int colour) {
+                                                     const T *__restrict__ b, T *__restrict__ x, int colour,
+                                                     int zero) {
     int n = nx * ny * nz;
     int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -1056,14 +1059,14 @@ __global__ void __launch_bounds__(kBlock) k_gs_slots(int nx, int ny, int nz, con
     const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
                        ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
     size_t N = (size_t)n;
-    T s = b[i], d = 0;
+    T s = b[i], d = A[(size_t)S_D * N + i];
+    if (!zero) {
 #pragma unroll
-    for (int q = 0; q < NSLOT; q++) {
-        int j = nb[q];
-        if (j < 0) continue;
-        T a = A[(size_t)q * N + i];
-        if (q == S_D) d = a;
-        else s = s - a * x[j];
+        for (int q = 0; q < NSLOT; q++) {
+            int j = nb[q];
+            if (j < 0 || q == S_D) continue;
+            s = s - A[(size_t)q * N + i] * x[j];
+        }
     }
     x[i] = s / d;
 }
@@ -1552,17 +1555,21 @@ template <> struct Prec<float> {
     static const float *cinv(const bo_cpr *pc) { return pc->cinv32.p; }
 };
 
+// zero: x holds no guess (the cycle's pre-smoother); the Gauss-Seidel form
+// then skips the neighbour reads of its first colour, the Jacobi form starts
+// from a zeroed x
 template <typename T>
-static bo_status smooth0(bo_cpr *pc, const T *b, T *x, bool forward, hipStream_t s) {
+static bo_status smooth0(bo_cpr *pc, const T *b, T *x, bool forward, bool zero, hipStream_t s) {
     const Grid &g = pc->g;
     long long n = pc->n;
     Level &L = pc->lv[0];
     const T *A = Prec<T>::app(pc);
+    if (zero && pc->o.smoother != BO_SMOOTH_GS) k_zero<T><<<grid_for(n), kBlock, 0, s>>>(n, x);
     for (int sw = 0; sw < pc->o.sweeps; sw++) {
         if (pc->o.smoother == BO_SMOOTH_GS) {
             int c0 = forward ? 0 : 1;
-            k_gs_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, c0);
-            k_gs_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, 1 - c0);
+            k_gs_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, c0, zero && sw == 0 ? 1 : 0);
+            k_gs_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, 1 - c0, 0);
         } else {
             T *t = Prec<T>::r(L);
             k_jacobi_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, t);
@@ -1612,8 +1619,7 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t 
     const bool l1 = l == 0 ? pc->o.smoother == BO_SMOOTH_L1 : pc->o.csmoother == BO_CSMOOTH_L1;
     if (slots0) {
         x = Prec<T>::x(L);
-        k_zero<T><<<grid_for(L.n), kBlock, 0, s>>>(L.n, x);
-        BO_TRY(smooth0<T>(pc, b, x, true, s));
+        BO_TRY(smooth0<T>(pc, b, x, true, true, s));
         k_resid_slots<T><<<grid_for(L.n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, Prec<T>::app(pc), b, x,
                                                            Prec<T>::r(L));
     } else {
@@ -1627,7 +1633,7 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t 
     BO_TRY(vcycle_rec<T>(pc, l + 1, Prec<T>::b(C), &xc, s));
     BO_TRY(csr_rowop<T>(L.n, L.pnnz, L.prp.p, L.pci.p, Prec<T>::pv(L), xc, OP_ADD, nullptr, nullptr, x, s));
     if (slots0) {
-        BO_TRY(smooth0<T>(pc, b, x, false, s));
+        BO_TRY(smooth0<T>(pc, b, x, false, false, s));
         *res = x;
     } else {
         BO_TRY(smooth_c<T>(L, pc->o.sweeps, l1, b, x, res, s));

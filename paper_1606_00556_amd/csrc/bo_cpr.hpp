@@ -45,9 +45,9 @@ struct Krylov {
     long long len = 0;
     DBuf<double> V, Z;            // (m+1) x len, m x len
     std::vector<const double *> vptr, zptr;   // host lists of the basis vectors
-    DBuf<double> h;               // device scalars of one Arnoldi step
+    DBuf<double> h;               // device scalars of two Arnoldi steps, 2m+3 each
     DBuf<double> y;               // m coefficients for the update
-    double *host = nullptr;       // pinned: [0, 2m+3) fetched scalars, [2m+3, 3m+4) coefficients
+    double *host = nullptr;       // pinned: two sets of 2m+3 fetched scalars, then m+1 coefficients
     ~Krylov() { if (host) (void)hipHostFree(host); }
 };
 
@@ -96,7 +96,8 @@ struct bo_cpr {
     bo::SetupWork sw;
     bo::Reducer red;
     bo::Krylov kr;
-    hipEvent_t ev[2] = {nullptr, nullptr};  // SpMV timing in bo_fgmres_solve
+    hipEvent_t ev[4] = {};        // SpMV timing in bo_fgmres_solve (two Arnoldi steps in flight)
+    hipEvent_t evf[2] = {};       // completion of an Arnoldi step's scalars
     // the preconditioner as a HIP graph (captured once per setup)
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;

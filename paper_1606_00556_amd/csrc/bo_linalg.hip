@@ -311,6 +311,15 @@ __global__ void k_axpby(long long n, double a, const double *__restrict__ x, dou
     y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
 }
 
+// w <- w / sqrt(nrm2[0]) unless that norm is <= 1e-300 (Arnoldi breakdown):
+// the same product (1/h) w as axpby with the factor formed on the host
+__global__ void k_normalize(long long n, const double *__restrict__ nrm2, double *__restrict__ w) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double h = sqrt(nrm2[0]);
+    if (h > 1e-300) w[i] = (1.0 / h) * w[i];
+}
+
 __global__ void k_fill(long long n, double v, double *__restrict__ y) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = v;
@@ -502,6 +511,12 @@ bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, cons
 
 bo_status axpby(long long n, double a, const double *x, double b, double *y, hipStream_t s) {
     k_axpby<<<grid_for(n), kBlock, 0, s>>>(n, a, x, b, y);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status normalize(long long n, const double *nrm2, double *w, hipStream_t s) {
+    k_normalize<<<grid_for(n), kBlock, 0, s>>>(n, nrm2, w);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }

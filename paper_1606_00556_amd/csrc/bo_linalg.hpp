@@ -17,6 +17,8 @@ bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, cons
                        hipStream_t s);
 bo_status axpby(long long n, double a, const double *x, double b, double *y, hipStream_t s);
 bo_status fill(long long n, double v, double *y, hipStream_t s);
+// w /= sqrt(*nrm2) on the device (left unchanged when that is <= 1e-300)
+bo_status normalize(long long n, const double *nrm2, double *w, hipStream_t s);
 constexpr int kMaxVecList = 64;
 // A list of device vectors passed to a kernel by value.
 struct VecList {

@@ -333,6 +333,8 @@ extern "C" void bo_cpr_destroy(bo_cpr *pc) {
     (void)hipDeviceSynchronize();
     for (hipEvent_t &e : pc->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t &e : pc->evf)
+        if (e) (void)hipEventDestroy(e);
     if (pc->gexec) (void)hipGraphExecDestroy(pc->gexec);
     if (pc->cap_stream) (void)hipStreamDestroy(pc->cap_stream);
     delete pc;
@@ -420,11 +422,11 @@ bo_status krylov_alloc(bo_cpr *pc, int m) {
     K.m = 0;
     BO_TRY(K.V.alloc((size_t)(m + 1) * len));
     BO_TRY(K.Z.alloc((size_t)m * len));
-    BO_TRY(K.h.alloc(2 * (m + 1) + 1));
+    BO_TRY(K.h.alloc(2 * (2 * (m + 1) + 1)));
     BO_TRY(K.y.alloc(m + 1));
     if (K.host) (void)hipHostFree(K.host);
     K.host = nullptr;
-    BO_HIP(hipHostMalloc((void **)&K.host, sizeof(double) * (3 * m + 4), hipHostMallocDefault));
+    BO_HIP(hipHostMalloc((void **)&K.host, sizeof(double) * (2 * (2 * m + 3) + m + 1), hipHostMallocDefault));
     K.vptr.resize(m + 1);
     K.zptr.resize(m);
     for (int i = 0; i <= m; i++) K.vptr[i] = K.V.p + (size_t)i * len;
@@ -451,18 +453,26 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     // buffers may grow during an application, nor while pairs are recorded,
     // which counts applications on the host)
     const bool use_graph = opts->graph == 1 && !pc->nn && !pc->rec_out;
+    // steps enqueued ahead (not with a network, whose stage synchronises, nor
+    // while pairs are recorded, which would record a discarded step)
+    const bool allow_ahead = !pc->nn && !pc->rec_out;
     if (pc->nn) BO_HIP(hipMemsetAsync(pc->nn_used.p, 0, sizeof(int32_t), s));
     if (timed)
         for (hipEvent_t &e : pc->ev)
             if (!e) BO_HIP(hipEventCreate(&e));
+    for (hipEvent_t &e : pc->evf)
+        if (!e) BO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     BO_TRY(krylov_alloc(pc, m));
     Krylov &K = pc->kr;
     const long long len = K.len;
     const Grid &g = pc->g;
     double *V = K.V.p, *Z = K.Z.p;
-    double *hd = K.h.p;                 // [0, m+1): h1, [m+1, 2m+2): h2, [2m+2]: |w|^2
-    double *hh = K.host;                // pinned copies of hd
-    double *yh = K.host + 2 * m + 3;    // pinned update coefficients
+    // scalars of an Arnoldi step, two sets (steps j and j+1 may be in flight):
+    // [0, m+1): h1, [m+1, 2m+2): h2, [2m+2]: |w|^2
+    const int hs = 2 * m + 3;
+    double *hd = K.h.p;                 // device
+    double *hh = K.host;                // pinned copies
+    double *yh = K.host + 2 * hs;       // pinned update coefficients
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1);
     auto fetch = [&](int count) -> bo_status {
         BO_HIP(hipMemcpyAsync(hh, hd, sizeof(double) * count, hipMemcpyDeviceToHost, s));
@@ -503,41 +513,62 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
         std::fill(gv.begin(), gv.end(), 0.0);
         gv[0] = beta;
         int k = 0;
-        for (int j = 0; j < m; j++) {
+        // One Arnoldi step is enqueued as: preconditioner, SpMV, orthogonalisation
+        // (scalars into set p = j % 2), normalisation of w on the device, an
+        // asynchronous copy of the scalars and an event.  While the estimate is
+        // far from the tolerance the next step is enqueued before the host waits
+        // for this one's scalars, so the GPU does not idle during the Givens
+        // update; a step enqueued past convergence is discarded.
+        auto enqueue_step = [&](int j) -> bo_status {
             double *vj = V + (size_t)j * len, *zj = Z + (size_t)j * len, *w = V + (size_t)(j + 1) * len;
+            const int p = j & 1;
+            double *hdp = hd + p * hs;
             if (use_graph) BO_TRY(cpr_apply_graph(pc, vj, zj, s));
             else BO_TRY(cpr_apply(pc, vj, zj, s));
-            its++;
-            if (timed) BO_HIP(hipEventRecord(pc->ev[0], s));
+            if (timed) BO_HIP(hipEventRecord(pc->ev[2 * p], s));
             BO_TRY(op_spmv(pc, 1.0, zj, 0.0, w, s));
-            if (timed) BO_HIP(hipEventRecord(pc->ev[1], s));
+            if (timed) BO_HIP(hipEventRecord(pc->ev[2 * p + 1], s));
             int nv = j + 1;
             if (opts->orth == 1) {
                 // h1 = V^T w; w -= V h1 with h2 = V^T w; w -= V h2 with |w|^2
-                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, nullptr, true, hd, s));
-                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, hd, true, hd + (m + 1), s));
-                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, hd + (m + 1), false, hd + 2 * (m + 1), s));
+                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, nullptr, true, hdp, s));
+                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, hdp, true, hdp + (m + 1), s));
+                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, hdp + (m + 1), false, hdp + 2 * (m + 1), s));
             } else {
                 for (int i = 0; i < nv; i++) {
-                    BO_TRY(pc->red.multidot(len, w, K.vptr.data() + i, 1, hd + i, s));
-                    BO_TRY(multiaxpy(len, K.vptr.data() + i, 1, hd + i, -1.0, w, s));
+                    BO_TRY(pc->red.multidot(len, w, K.vptr.data() + i, 1, hdp + i, s));
+                    BO_TRY(multiaxpy(len, K.vptr.data() + i, 1, hdp + i, -1.0, w, s));
                 }
-                BO_TRY(pc->red.dot(len, w, w, hd + 2 * (m + 1), s));
+                BO_TRY(pc->red.dot(len, w, w, hdp + 2 * (m + 1), s));
             }
-            BO_TRY(fetch(2 * (m + 1) + 1));
-            if (timed) {  // the fetch synchronised the stream: both events are complete
+            BO_TRY(normalize(len, hdp + 2 * (m + 1), w, s));
+            BO_HIP(hipMemcpyAsync(hh + p * hs, hdp, sizeof(double) * hs, hipMemcpyDeviceToHost, s));
+            BO_HIP(hipEventRecord(pc->evf[p], s));
+            return BO_OK;
+        };
+        BO_TRY(enqueue_step(0));
+        bool next_enqueued = true;  // step j is in the stream
+        for (int j = 0; j < m; j++) {
+            if (!next_enqueued) BO_TRY(enqueue_step(j));
+            const bool ahead = allow_ahead && j + 1 < m && its + 1 < opts->maxit && std::fabs(gv[j]) > 8.0 * tol;
+            if (ahead) BO_TRY(enqueue_step(j + 1));
+            next_enqueued = ahead;
+            const int p = j & 1;
+            const double *hq = hh + p * hs;
+            BO_HIP(hipEventSynchronize(pc->evf[p]));
+            its++;
+            if (timed) {  // both events precede the scalars' copy, so they are complete
                 float ms = 0.f;
-                BO_HIP(hipEventElapsedTime(&ms, pc->ev[0], pc->ev[1]));
+                BO_HIP(hipEventElapsedTime(&ms, pc->ev[2 * p], pc->ev[2 * p + 1]));
                 st.spmv_ms += ms;
                 st.spmv_calls++;
             }
-            double hn = std::sqrt(hh[2 * (m + 1)]);
+            double hn = std::sqrt(hq[2 * (m + 1)]);
             for (int i = 0; i <= j; i++)
-                H[(size_t)i * m + j] = opts->orth == 1 ? hh[i] + hh[m + 1 + i] : hh[i];
+                H[(size_t)i * m + j] = opts->orth == 1 ? hq[i] + hq[m + 1 + i] : hq[i];
             H[(size_t)(j + 1) * m + j] = hn;
             bool breakdown = !(hn > 1e-300);
             if (!std::isfinite(hn)) { status = fail(BO_ERR_NONFINITE, "bo_fgmres_solve: NaN in the iteration"); goto done; }
-            if (!breakdown) BO_TRY(axpby(len, 1.0 / hn, w, 0.0, w, s));
             for (int i = 0; i < j; i++) {
                 double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
                 H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
