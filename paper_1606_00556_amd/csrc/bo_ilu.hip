@@ -8,15 +8,14 @@
 // The solve is w_i = E_i^{-1}(r_i - sum_{k<i} A_ik w_k) followed by
 // x_i = w_i - E_i^{-1} sum_{j>i} A_ij x_j.
 //
-// Schedule: lane t = a + tile_x*b of the tile's wavefront owns grid column
-// (i0+a, j0+b) and at step s handles layer k = s - a - b, so its -x, -y and
-// -z neighbours were handled one step earlier by lanes t-1, t-tile_x and t
-// itself; their values arrive through cross-lane shuffles (no LDS, no
-// barriers).  The factors are stored in the same (tile, step, lane) order,
-// packed in pairs, so each step reads its 36 doubles with 18 contiguous 1 KB
-// wavefront loads, and the fields of the next two steps are loaded before the
-// current step is computed.  Block Jacobi (x_i = A_ii^{-1} r_i) is the
-// alternative F stage.
+// Schedule: lane t = a + tile_x*b of the tile owns grid column (i0+a, j0+b)
+// and at step s handles layer k = s - a - b, so its -x, -y and -z neighbours
+// were handled one step earlier by lanes t-1, t-tile_x and t itself.  The
+// factors are stored in the same (tile, step, lane) order, packed in pairs, so
+// each step reads its 36 doubles with 18 contiguous 1 KB loads.  Two
+// wavefronts share a tile, each loading half of the factors several steps
+// ahead and exchanging partial products through LDS (see the sweeps below).
+// Block Jacobi (x_i = A_ii^{-1} r_i) is the alternative F stage.
 //
 // Mixed form: the factors (E^{-1} and the blocks of A) are computed in FP64
 // and stored rounded to FP32 (9 float4 per slot and sweep) or to BF16 (9 uint2
@@ -34,7 +33,7 @@ struct TileGeom {
 
 // The factors of one slot for one sweep are 36 doubles: E^{-1} and the three
 // lower blocks (-z, -y, -x) for the forward sweep, E^{-1} and the three upper
-// blocks (+x, +y, +z) for the backward sweep.  They are packed as 18 double2
+// blocks (+z, +x, +y) for the backward sweep.  They are packed as 18 double2
 // per slot in (tile, step, pair, lane) order, so one wavefront load of a
 // pair reads 1 KB contiguously and a step needs 18 load instructions.
 constexpr int kPairs = 18;
@@ -128,7 +127,7 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
         if (active && k >= 0 && k < T.nz) {
             int g = i + T.nx * (j + T.ny * k);
             double E[9], L[9], Lk[9], tmp[9];
-            double fw[36], bw[36];  // packed slot data: [E^{-1} | Lz Ly Lx] and [E^{-1} | Ux Uy Uz]
+            double fw[36], bw[36];  // packed slot data: [E^{-1} | Lz Ly Lx] and [E^{-1} | Uz Ux Uy]
             for (int z = 0; z < 36; z++) fw[z] = bw[z] = 0.0;
             load_blk(A, S_D, N, g, E);
             // -z, -y, -x in ascending order
@@ -162,7 +161,7 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
             if (has_px) load_blk(A, S_PX, N, g, Uxp); else for (int z = 0; z < 9; z++) Uxp[z] = 0.0;
             if (has_py) load_blk(A, S_PY, N, g, Uyp); else for (int z = 0; z < 9; z++) Uyp[z] = 0.0;
             if (k + 1 < T.nz) load_blk(A, S_PZ, N, g, Uzp); else for (int z = 0; z < 9; z++) Uzp[z] = 0.0;
-            for (int z = 0; z < 9; z++) { bw[9 + z] = Uxp[z]; bw[18 + z] = Uyp[z]; bw[27 + z] = Uzp[z]; }
+            for (int z = 0; z < 9; z++) { bw[9 + z] = Uzp[z]; bw[18 + z] = Uxp[z]; bw[27 + z] = Uyp[z]; }
             store_pack<St>(Ff, tile, T.ns, s, t, fw);
             store_pack<St>(Fb, tile, T.ns, s, t, bw);
             cell[q] = g;
@@ -173,44 +172,49 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
     }
 }
 
+// One half of a slot's 36 factor values: half 0 = values 0..17 (E^{-1} and
+// the first block), half 1 = values 18..35 (the other two blocks).  In the
+// FP32 / BF16 forms the quad holding values 16..19 is read by both halves.
 template <typename T>
-struct Pack {
-    T v[36];
-    T w[3];   // the sweep's vector operand at this slot
-    int g;
+struct Half {
+    T v[18];
 };
-
-template <int St, typename T>
-__device__ __forceinline__ void load_pack(const void *__restrict__ F, const int32_t *__restrict__ cell,
-                                          const T *__restrict__ vec, size_t S, int tile, int ns, int s, int t,
-                                          Pack<T> &p) {
-    size_t q = ((size_t)tile * ns + s) * 64 + t;
-    p.g = cell[q];
+template <int St, typename T, int H>
+__device__ __forceinline__ void load_half(const void *__restrict__ F, int tile, int ns, int s, int t, Half<T> &p) {
+    // (callers pass lane 0 for idle slots: all idle lanes of a load then hit
+    // one cache line)
     if constexpr (St == ST_F64) {
         const double2 *D = (const double2 *)F;
 #pragma unroll
-        for (int p2 = 0; p2 < kPairs; p2++) {
-            double2 d = D[pk_index(tile, ns, s, p2, t)];
-            p.v[2 * p2] = d.x;
-            p.v[2 * p2 + 1] = d.y;
-        }
-    } else if constexpr (St == ST_F32) {
-        const float4 *D = (const float4 *)F;
-#pragma unroll
-        for (int qd = 0; qd < kQuads; qd++) {
-            float4 f = D[pq_index(tile, ns, s, qd, t)];
-            p.v[4 * qd] = f.x; p.v[4 * qd + 1] = f.y; p.v[4 * qd + 2] = f.z; p.v[4 * qd + 3] = f.w;
+        for (int i = 0; i < 9; i++) {
+            double2 d = D[pk_index(tile, ns, s, 9 * H + i, t)];
+            p.v[2 * i] = d.x;
+            p.v[2 * i + 1] = d.y;
         }
     } else {
-        const uint2 *D = (const uint2 *)F;
+        T u[20];
 #pragma unroll
-        for (int qd = 0; qd < kQuads; qd++) {
-            uint2 u = D[pq_index(tile, ns, s, qd, t)];
-            p.v[4 * qd] = bf16_value(u.x & 0xFFFFu); p.v[4 * qd + 1] = bf16_value(u.x >> 16);
-            p.v[4 * qd + 2] = bf16_value(u.y & 0xFFFFu); p.v[4 * qd + 3] = bf16_value(u.y >> 16);
+        for (int i = 0; i < 5; i++) {
+            int qd = 4 * H + i;
+            if constexpr (St == ST_F32) {
+                float4 f = ((const float4 *)F)[pq_index(tile, ns, s, qd, t)];
+                u[4 * i] = f.x; u[4 * i + 1] = f.y; u[4 * i + 2] = f.z; u[4 * i + 3] = f.w;
+            } else {
+                uint2 b = ((const uint2 *)F)[pq_index(tile, ns, s, qd, t)];
+                u[4 * i] = bf16_value(b.x & 0xFFFFu); u[4 * i + 1] = bf16_value(b.x >> 16);
+                u[4 * i + 2] = bf16_value(b.y & 0xFFFFu); u[4 * i + 3] = bf16_value(b.y >> 16);
+            }
         }
+        // half 0: values 0..17 = u[0..17]; half 1: values 18..35 = u[2..19]
+#pragma unroll
+        for (int i = 0; i < 18; i++) p.v[i] = u[i + 2 * H];
     }
-    p.w[0] = vec[q]; p.w[1] = vec[S + q]; p.w[2] = vec[2 * S + q];
+}
+
+// the sweep's vector operand at one slot (three arrays S apart)
+template <typename T>
+__device__ __forceinline__ void load_vec(const T *__restrict__ vec, size_t S, size_t q, T *w) {
+    w[0] = vec[q]; w[1] = vec[S + q]; w[2] = vec[2 * S + q];
 }
 
 // scatter a natural-order 3N vector into (tile, step, lane) order
@@ -223,83 +227,236 @@ __global__ void k_to_slots(long long n, const int32_t *__restrict__ slot_of, siz
     rq[q] = (T)r[3 * g]; rq[S + q] = (T)r[3 * g + 1]; rq[2 * S + q] = (T)r[3 * g + 2];
 }
 
+// Sweeps: two wavefronts per tile.  Wavefront 0 loads the first half of each
+// slot's factors (E^{-1} and the -z block forward; E^{-1} and the +z block
+// backward) with the vector operand, wavefront 1 the second half (the -y and
+// -x blocks; the +x and +y blocks), so each keeps more steps of loads in
+// flight (three and four steps ahead).  Per step, wavefront 1 multiplies its
+// blocks with the neighbours' values of the previous step (read from LDS) and
+// hands the products to wavefront 0 through LDS; wavefront 0 completes the
+// step and hands the new values back.  The products are combined in the
+// order of the one-wavefront formula, so the results do not change.  Idle
+// slots (column outside the tile or grid, layer outside 0..nz-1) load
+// nothing.
+struct SweepLane {
+    int t, a, b;
+    bool col_ok;
+    __device__ SweepLane(const TileGeom &G, int tile, int lane) : t(lane) {
+        a = lane % G.tx;
+        b = lane / G.tx;
+        int ti = tile % G.ntx, tj = tile / G.ntx;
+        col_ok = lane < G.tx * G.ty && ti * G.tx + a < G.nx && tj * G.ty + b < G.ny;
+    }
+    __device__ bool active(const TileGeom &G, int s) const {
+        int k = s - a - b;
+        return col_ok && k >= 0 && k < G.nz;
+    }
+    // the grid cell of an active slot (the factorisation's cell index)
+    __device__ size_t cell(const TileGeom &G, int tile, int s) const {
+        int i = (tile % G.ntx) * G.tx + a, j = (tile / G.ntx) * G.ty + b, k = s - a - b;
+        return (size_t)i + (size_t)G.nx * ((size_t)j + (size_t)G.ny * k);
+    }
+};
+
+// Each wavefront keeps a ring of register buffers, one per step in flight;
+// the step loop is unrolled by the ring length, so a buffer is refilled in
+// place once its step is done and no register holding a load in flight is
+// ever copied (a copy would have to wait for the load).  Every lane loads at
+// every step (idle slots and steps past the end read lane 0's data of a
+// valid step of the tile and ignore it, so the idle lanes of a load share one
+// cache line): loads that some paths skip would make the compiler wait for
+// all outstanding loads before using any of them.
+constexpr int kAhead0 = 4;  // wavefront 0: 9 factor + 3 vector loads and 3 stores per step
+constexpr int kAhead1 = 6;  // wavefront 1: 9 factor loads per step
+
 // forward sweep: w = E^{-1}(r - L w_lower); r and w in (tile, step, lane) order
 template <int St, typename T>
-__global__ void __launch_bounds__(64) k_ilu_forward(TileGeom G, const void *__restrict__ F,
-                                                    const int32_t *__restrict__ cell, const T *__restrict__ rq,
-                                                    T *__restrict__ wq) {
-    int t = threadIdx.x;
-    int a = t % G.tx, b = t / G.tx;
-    int tile = blockIdx.x;
-    size_t S = (size_t)G.slots();
-    int lx = a > 0 ? t - 1 : t, ly = b > 0 ? t - G.tx : t;
-    T wp[3] = {0, 0, 0};
-    // two steps of operands in flight ahead of the one being computed
-    Pack<T> cur, n1, n2;
-    load_pack<St, T>(F, cell, rq, S, tile, G.ns, 0, t, n1);
-    if (G.ns > 1) load_pack<St, T>(F, cell, rq, S, tile, G.ns, 1, t, n2);
-    for (int s = 0; s < G.ns; s++) {
-        cur = n1;
-        n1 = n2;
-        if (s + 2 < G.ns) load_pack<St, T>(F, cell, rq, S, tile, G.ns, s + 2, t, n2);
-        T wy[3], wx[3];
-        for (int c = 0; c < 3; c++) { wx[c] = __shfl(wp[c], lx, 64); wy[c] = __shfl(wp[c], ly, 64); }
-        if (cur.g >= 0) {
-            T v[3] = {cur.w[0], cur.w[1], cur.w[2]};
-            T y[3];
-            // zero blocks stand for missing neighbours
-            mv3(cur.v + 9, wp, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
-            mv3(cur.v + 18, wy, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
-            mv3(cur.v + 27, wx, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
-            mv3(cur.v, v, wp);
-            size_t q = ((size_t)tile * G.ns + s) * 64 + t;
-            wq[q] = wp[0]; wq[S + q] = wp[1]; wq[2 * S + q] = wp[2];
-        } else {
-            wp[0] = wp[1] = wp[2] = 0;
+__global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__restrict__ F,
+                                                     const int32_t *__restrict__ cell, const T *__restrict__ rq,
+                                                     T *__restrict__ wq) {
+    __shared__ T wsh[2][3][64];  // w of a step, by step parity
+    __shared__ T ysh[2][6][64];  // wavefront 1's products L_y w_y and L_x w_x
+    const int wv = threadIdx.x / 64;
+    const int tile = blockIdx.x;
+    const SweepLane L(G, tile, threadIdx.x % 64);
+    const int t = L.t;
+    const size_t S = (size_t)G.slots();
+    const int ns = G.ns;
+    if (wv == 1) {
+        const int lx = L.a > 0 ? t - 1 : t, ly = L.b > 0 ? t - G.tx : t;
+        Half<T> buf[kAhead1];
+        auto fetch = [&](int s, Half<T> &h) {
+            const int sc = min(s, ns - 1);
+            load_half<St, T, 1>(F, tile, ns, sc, L.active(G, sc) ? t : 0, h);
+        };
+        auto step = [&](int s, Half<T> &h) {
+            T wy[3] = {0, 0, 0}, wx[3] = {0, 0, 0};
+            if (s > 0) {
+                const int p = (s - 1) & 1;
+                for (int c = 0; c < 3; c++) { wy[c] = wsh[p][c][ly]; wx[c] = wsh[p][c][lx]; }
+            }
+            T ya[3] = {0, 0, 0}, yb[3] = {0, 0, 0};
+            if (L.active(G, s)) {
+                mv3(h.v, wy, ya);
+                mv3(h.v + 9, wx, yb);
+            }
+            fetch(s + kAhead1, h);
+            for (int c = 0; c < 3; c++) { ysh[s & 1][c][t] = ya[c]; ysh[s & 1][3 + c][t] = yb[c]; }
+            __syncthreads();  // products of step s published
+            __syncthreads();  // w of step s published
+        };
+#pragma unroll
+        for (int u = 0; u < kAhead1; u++) fetch(u, buf[u]);
+        int s0 = 0;
+        for (; s0 + kAhead1 <= ns; s0 += kAhead1) {
+#pragma unroll
+            for (int u = 0; u < kAhead1; u++) step(s0 + u, buf[u]);
         }
+#pragma unroll
+        for (int u = 0; u < kAhead1; u++)
+            if (s0 + u < ns) step(s0 + u, buf[u]);
+    } else {
+        T wp[3] = {0, 0, 0};
+        Half<T> buf[kAhead0];
+        T vec[kAhead0][3];
+        auto fetch = [&](int s, Half<T> &h, T *w) {
+            const int sc = min(s, ns - 1);
+            const int tl = L.active(G, sc) ? t : 0;
+            load_half<St, T, 0>(F, tile, ns, sc, tl, h);
+            load_vec(rq, S, ((size_t)tile * ns + sc) * 64 + tl, w);
+        };
+        auto step = [&](int s, Half<T> &h, T *w) {
+            __syncthreads();  // products of step s published
+            if (L.active(G, s)) {
+                T v[3] = {w[0], w[1], w[2]};
+                T y[3];
+                // zero blocks stand for missing neighbours
+                mv3(h.v + 9, wp, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
+                v[0] = v[0] - ysh[s & 1][0][t]; v[1] = v[1] - ysh[s & 1][1][t]; v[2] = v[2] - ysh[s & 1][2][t];
+                v[0] = v[0] - ysh[s & 1][3][t]; v[1] = v[1] - ysh[s & 1][4][t]; v[2] = v[2] - ysh[s & 1][5][t];
+                mv3(h.v, v, wp);
+            } else {
+                wp[0] = wp[1] = wp[2] = 0;
+            }
+            for (int c = 0; c < 3; c++) wsh[s & 1][c][t] = wp[c];
+            {  // idle slots store 0
+                size_t q = ((size_t)tile * ns + s) * 64 + t;
+                wq[q] = wp[0]; wq[S + q] = wp[1]; wq[2 * S + q] = wp[2];
+            }
+            fetch(s + kAhead0, h, w);
+            __syncthreads();  // w of step s published
+        };
+#pragma unroll
+        for (int u = 0; u < kAhead0; u++) fetch(u, buf[u], vec[u]);
+        int s0 = 0;
+        for (; s0 + kAhead0 <= ns; s0 += kAhead0) {
+#pragma unroll
+            for (int u = 0; u < kAhead0; u++) step(s0 + u, buf[u], vec[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead0; u++)
+            if (s0 + u < ns) step(s0 + u, buf[u], vec[u]);
     }
 }
 
 // backward sweep: x_i = w_i - E_i^{-1} sum_{upper} A_ij x_j, written in
 // natural order as out = x + (dp, 0, 0) in FP64 (dp may be NULL)
 template <int St, typename T, typename TD>
-__global__ void __launch_bounds__(64) k_ilu_backward(TileGeom G, const void *__restrict__ F,
-                                                     const int32_t *__restrict__ cell, const T *__restrict__ wq,
-                                                     const TD *__restrict__ dp, double *__restrict__ out) {
-    int t = threadIdx.x;
-    int a = t % G.tx, b = t / G.tx;
-    int tile = blockIdx.x;
-    size_t S = (size_t)G.slots();
-    int px = a + 1 < G.tx && t + 1 < 64 ? t + 1 : t;
-    int py = b + 1 < G.ty && t + G.tx < 64 ? t + G.tx : t;
-    T xp[3] = {0, 0, 0};
-    Pack<T> cur, n1, n2;
-    load_pack<St, T>(F, cell, wq, S, tile, G.ns, G.ns - 1, t, n1);
-    if (G.ns > 1) load_pack<St, T>(F, cell, wq, S, tile, G.ns, G.ns - 2, t, n2);
-    for (int s = G.ns - 1; s >= 0; s--) {
-        cur = n1;
-        n1 = n2;
-        if (s >= 2) load_pack<St, T>(F, cell, wq, S, tile, G.ns, s - 2, t, n2);
-        T xx[3], xy[3];
-        for (int c = 0; c < 3; c++) { xx[c] = __shfl(xp[c], px, 64); xy[c] = __shfl(xp[c], py, 64); }
-        if (cur.g >= 0) {
-            T acc[3], y[3];
-            mv3(cur.v + 9, xx, acc);
-            mv3(cur.v + 18, xy, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
-            mv3(cur.v + 27, xp, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
-            mv3(cur.v, acc, y);
-            xp[0] = cur.w[0] - y[0]; xp[1] = cur.w[1] - y[1]; xp[2] = cur.w[2] - y[2];
-            size_t g = (size_t)cur.g;
-            out[3 * g] = dp ? (double)dp[g] + (double)xp[0] : (double)xp[0];
-            out[3 * g + 1] = (double)xp[1];
-            out[3 * g + 2] = (double)xp[2];
-        } else {
-            xp[0] = xp[1] = xp[2] = 0;
+__global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__restrict__ F,
+                                                      const int32_t *__restrict__ cell, const T *__restrict__ wq,
+                                                      const TD *__restrict__ dp, double *__restrict__ out) {
+    __shared__ T xsh[2][3][64];  // x of a step, by step parity
+    __shared__ T ash[2][3][64];  // wavefront 1's U_x x_x + U_y x_y
+    const int wv = threadIdx.x / 64;
+    const int tile = blockIdx.x;
+    const SweepLane L(G, tile, threadIdx.x % 64);
+    const int t = L.t;
+    const size_t S = (size_t)G.slots();
+    const int ns = G.ns, e = G.ns - 1;
+    if (wv == 1) {
+        const int px = L.a + 1 < G.tx && t + 1 < 64 ? t + 1 : t;
+        const int py = L.b + 1 < G.ty && t + G.tx < 64 ? t + G.tx : t;
+        Half<T> buf[kAhead1];
+        auto fetch = [&](int s, Half<T> &h) {
+            const int sc = max(s, 0);
+            load_half<St, T, 1>(F, tile, ns, sc, L.active(G, sc) ? t : 0, h);
+        };
+        auto step = [&](int s, Half<T> &h) {
+            T xx[3] = {0, 0, 0}, xy[3] = {0, 0, 0};
+            if (s < e) {
+                const int p = (s + 1) & 1;
+                for (int c = 0; c < 3; c++) { xx[c] = xsh[p][c][px]; xy[c] = xsh[p][c][py]; }
+            }
+            T acc[3] = {0, 0, 0};
+            if (L.active(G, s)) {
+                T y[3];
+                mv3(h.v, xx, acc);
+                mv3(h.v + 9, xy, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
+            }
+            fetch(s - kAhead1, h);
+            for (int c = 0; c < 3; c++) ash[s & 1][c][t] = acc[c];
+            __syncthreads();  // products of step s published
+            __syncthreads();  // x of step s published
+        };
+#pragma unroll
+        for (int u = 0; u < kAhead1; u++) fetch(e - u, buf[u]);
+        int s0 = e;
+        for (; s0 - kAhead1 + 1 >= 0; s0 -= kAhead1) {
+#pragma unroll
+            for (int u = 0; u < kAhead1; u++) step(s0 - u, buf[u]);
         }
+#pragma unroll
+        for (int u = 0; u < kAhead1; u++)
+            if (s0 - u >= 0) step(s0 - u, buf[u]);
+    } else {
+        T xp[3] = {0, 0, 0};
+        Half<T> buf[kAhead0];
+        T vec[kAhead0][3];
+        TD dpv[kAhead0];
+        // dp of the slot's cell is loaded with the slot (a load waited for
+        // inside the step would wait for every load in flight)
+        auto fetch = [&](int s, Half<T> &h, T *w, TD &d) {
+            const int sc = max(s, 0);
+            const bool act = L.active(G, sc);
+            const int tl = act ? t : 0;
+            load_half<St, T, 0>(F, tile, ns, sc, tl, h);
+            load_vec(wq, S, ((size_t)tile * ns + sc) * 64 + tl, w);
+            if (dp) d = dp[act ? L.cell(G, tile, sc) : 0];
+        };
+        auto step = [&](int s, Half<T> &h, T *w, TD &d) {
+            __syncthreads();  // products of step s published
+            if (L.active(G, s)) {
+                T acc[3], y[3];
+                acc[0] = ash[s & 1][0][t]; acc[1] = ash[s & 1][1][t]; acc[2] = ash[s & 1][2][t];
+                mv3(h.v + 9, xp, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
+                mv3(h.v, acc, y);
+                xp[0] = w[0] - y[0]; xp[1] = w[1] - y[1]; xp[2] = w[2] - y[2];
+            } else {
+                xp[0] = xp[1] = xp[2] = 0;
+            }
+            for (int c = 0; c < 3; c++) xsh[s & 1][c][t] = xp[c];
+            if (L.active(G, s)) {
+                size_t g = L.cell(G, tile, s);
+                out[3 * g] = dp ? (double)d + (double)xp[0] : (double)xp[0];
+                out[3 * g + 1] = (double)xp[1];
+                out[3 * g + 2] = (double)xp[2];
+            }
+            fetch(s - kAhead0, h, w, d);
+            __syncthreads();  // x of step s published
+        };
+#pragma unroll
+        for (int u = 0; u < kAhead0; u++) fetch(e - u, buf[u], vec[u], dpv[u]);
+        int s0 = e;
+        for (; s0 - kAhead0 + 1 >= 0; s0 -= kAhead0) {
+#pragma unroll
+            for (int u = 0; u < kAhead0; u++) step(s0 - u, buf[u], vec[u], dpv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead0; u++)
+            if (s0 - u >= 0) step(s0 - u, buf[u], vec[u], dpv[u]);
     }
 }
 
-// block Jacobi: E_i^{-1} = A_ii^{-1} (FP64), stored as FP64, FP32 or BF16 (9 x N, SoA)
 template <int St>
 __global__ void k_bj_setup(long long n, const double *__restrict__ A, void *__restrict__ einv,
                            int32_t *__restrict__ bad) {
@@ -549,9 +706,7 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
             BO_TRY(pc->ilu_w32.alloc(3 * S));
             BO_TRY(pc->ilu_r32.alloc(3 * S));
         }
-        // idle slots keep zero factors
-        BO_HIP(hipMemsetAsync(pc->ilu_f.p, 0, sizeof(double2) * S * kPairs, s));
-        BO_HIP(hipMemsetAsync(pc->ilu_b.p, 0, sizeof(double2) * S * kPairs, s));
+        // idle slots are never read by the sweeps: their factors stay unset
         int nb = T.ntx * T.nty;
         if (st == ST_F64) {
             k_ilu_factor<ST_F64><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
@@ -596,8 +751,8 @@ bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, boo
         TileGeom G = geom(pc);
         size_t S = (size_t)G.slots();
         if (!r_in_slots) k_to_slots<T><<<grid_for(n), kBlock, 0, s>>>(n, pc->ilu_slot.p, S, r, rq);
-        k_ilu_forward<St, T><<<G.ntx * G.nty, 64, 0, s>>>(G, pc->ilu_f.p, pc->ilu_cell.p, rq, wq);
-        k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 64, 0, s>>>(G, pc->ilu_b.p, pc->ilu_cell.p, wq, dp, out);
+        k_ilu_forward<St, T><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, pc->ilu_cell.p, rq, wq);
+        k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, pc->ilu_cell.p, wq, dp, out);
     }
     BO_HIP(hipGetLastError());
     return BO_OK;
@@ -615,7 +770,7 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
         size_t S = (size_t)G.slots();
         const long long N = pc->g.n();
         k_to_slots<double><<<grid_for(N), kBlock, 0, s>>>(N, pc->ilu_slot.p, S, r, pc->ilu_r.p);
-        k_ilu_forward<ST_F64, double><<<G.ntx * G.nty, 64, 0, s>>>(G, pc->ilu_f.p, pc->ilu_cell.p, pc->ilu_r.p,
+        k_ilu_forward<ST_F64, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, pc->ilu_cell.p, pc->ilu_r.p,
                                                                     pc->ilu_w.p);
         if (pc->ncell > N)
             k_dual_forward<<<grid_for(N), kBlock, 0, s>>>((int)N, pc->ilu_slot.p, S, r, pc->x_einv_m.p, pc->x_amf.p,
@@ -624,7 +779,7 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
             int cnt = pc->n - pc->ncell;
             k_rows_apply<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out);
         }
-        k_ilu_backward<ST_F64, double, double><<<G.ntx * G.nty, 64, 0, s>>>(G, pc->ilu_b.p, pc->ilu_cell.p,
+        k_ilu_backward<ST_F64, double, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, pc->ilu_cell.p,
                                                                              pc->ilu_w.p, nullptr, out);
         BO_HIP(hipGetLastError());
         return BO_OK;
