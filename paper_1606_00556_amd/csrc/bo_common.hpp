@@ -175,7 +175,7 @@ __device__ inline double block_sum(double v, double *sh) {
 // the stream before returning (so a buffer is idle whenever a call starts);
 // steady-state calls then do not allocate, and hipFree does not synchronise
 // the device.  One set per host thread; never freed.
-enum ScratchSlot { SC_SCAN = 0, SC_FLAG, SC_JAC_CNT, SC_COUNT };
+enum ScratchSlot { SC_SCAN = 0, SC_FLAG, SC_JAC_CNT, SC_SELL, SC_COUNT };
 bo_status scratch_get(int slot, size_t bytes, void **ptr);
 
 // ---- small device-to-host reads ----------------------------------------------------

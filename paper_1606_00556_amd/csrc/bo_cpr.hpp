@@ -68,6 +68,8 @@ struct bo_cpr {
     bo::DBuf<double> x_einv_f, x_einv_m, x_amf, x_afm, x_einv_w;
     bo::DBuf<int32_t> Arp, Aci;
     bo::DBuf<double> Aval;
+    bo::DBuf<int32_t> Asoff, Asci;  // sliced copy of A for the solver's SpMV (general form)
+    bo::DBuf<double> Asv;
     bo_cpr_opts o{};
     // operator (copy of A) in slot layout, 63 * N
     bo::DBuf<double> A;

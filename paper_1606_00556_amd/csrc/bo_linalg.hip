@@ -177,6 +177,70 @@ __global__ void k_bsr_spmv(int n, const int32_t *__restrict__ rp, const int32_t 
     }
 }
 
+// ---- sliced BSR (general operator of the solver) -------------------------------
+__global__ void k_sell_width(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ width) {
+    int S = blockIdx.x * blockDim.x + threadIdx.x;
+    int nsl = (n + 63) / 64;
+    if (S >= nsl) return;
+    int r0 = 64 * S, r1 = min(n, r0 + 64), w = 0;
+    for (int r = r0; r < r1; r++) w = max(w, rp[r + 1] - rp[r]);
+    width[S] = w;
+}
+
+__global__ void k_sell_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                            const double *__restrict__ v, const int32_t *__restrict__ soff,
+                            int32_t *__restrict__ sci, double *__restrict__ sv) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int S = r >> 6, lane = r & 63;
+    int k0 = soff[S], K = soff[S + 1] - k0;
+    int e0 = rp[r], len = rp[r + 1] - e0;
+    for (int k = 0; k < K; k++) {
+        size_t b = (size_t)(k0 + k) * 64 + lane;
+        if (k < len) {
+            sci[b] = ci[e0 + k];
+            for (int z = 0; z < 9; z++) sv[((size_t)(k0 + k) * 9 + z) * 64 + lane] = v[9 * (size_t)(e0 + k) + z];
+        } else {
+            sci[b] = -1;
+        }
+    }
+}
+
+// y = alpha A x + beta y on the sliced layout: the blocks of a row in their
+// BSR order and each block's entries in order, as k_bsr_spmv; the 64 lanes of
+// a wavefront read each of a block column's 9 value arrays as one 512 B line
+// pair (non-temporal: read once per launch).
+__global__ void __launch_bounds__(kBlock) k_sell_spmv(int n, const int32_t *__restrict__ soff,
+                                                      const int32_t *__restrict__ sci,
+                                                      const double *__restrict__ sv, double alpha,
+                                                      const double *__restrict__ x, double beta,
+                                                      double *__restrict__ y) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int S = r >> 6, lane = r & 63;
+    int k0 = soff[S], K = soff[S + 1] - k0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < K; k++) {
+        int c = sci[(size_t)(k0 + k) * 64 + lane];
+        if (c < 0) break;  // the rest of the row is padding
+        const double *blk = sv + (size_t)(k0 + k) * 9 * 64 + lane;
+        double e[9];
+#pragma unroll
+        for (int z = 0; z < 9; z++) e[z] = __builtin_nontemporal_load(blk + z * 64);
+        double x0 = x[3 * (size_t)c], x1 = x[3 * (size_t)c + 1], x2 = x[3 * (size_t)c + 2];
+        s0 = s0 + e[0] * x0; s0 = s0 + e[1] * x1; s0 = s0 + e[2] * x2;
+        s1 = s1 + e[3] * x0; s1 = s1 + e[4] * x1; s1 = s1 + e[5] * x2;
+        s2 = s2 + e[6] * x0; s2 = s2 + e[7] * x1; s2 = s2 + e[8] * x2;
+    }
+    double *yi = y + 3 * (size_t)r;
+    double t0 = beta == 0.0 ? 0.0 : beta * yi[0];
+    double t1 = beta == 0.0 ? 0.0 : beta * yi[1];
+    double t2 = beta == 0.0 ? 0.0 : beta * yi[2];
+    yi[0] = alpha * s0 + t0;
+    yi[1] = alpha * s1 + t1;
+    yi[2] = alpha * s2 + t2;
+}
+
 // ---- BSR -> slot layout -------------------------------------------------------
 __global__ void k_bsr_to_slots(int nx, int ny, int nz, const int32_t *__restrict__ rp,
                                const int32_t *__restrict__ ci, const double *__restrict__ v,
@@ -493,6 +557,31 @@ template bo_status slot_col0_residual_perm<double, double>(const Grid &, const d
 template bo_status slot_col0_residual_perm<float, float>(const Grid &, const double *, const double *,
                                                          const float *, const int32_t *, size_t, float *,
                                                          hipStream_t);
+
+bo_status sell_build(int n, const int32_t *rp, const int32_t *ci, const double *v, DBuf<int32_t> &soff,
+                     DBuf<int32_t> &sci, DBuf<double> &sv, hipStream_t s) {
+    int nsl = (n + 63) / 64;
+    BO_TRY(soff.alloc((size_t)nsl + 1));
+    int32_t *width = nullptr;
+    BO_TRY(scratch_get(SC_SELL, sizeof(int32_t) * (size_t)std::max(nsl, 1), (void **)&width));
+    k_sell_width<<<grid_for(nsl), kBlock, 0, s>>>(n, rp, width);
+    BO_HIP(hipGetLastError());
+    int32_t cols = 0;
+    BO_TRY(scan_counts(width, soff.p, nsl, &cols, s));
+    BO_TRY(sci.alloc((size_t)cols * 64));
+    BO_TRY(sv.alloc((size_t)cols * 64 * 9));
+    if (n > 0) k_sell_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, soff.p, sci.p, sv.p);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double *sv, double alpha,
+                    const double *x, double beta, double *y, hipStream_t s) {
+    if (n <= 0) return BO_OK;
+    k_sell_spmv<<<grid_for(n), kBlock, 0, s>>>(n, soff, sci, sv, alpha, x, beta, y);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
 
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s) {

@@ -13,6 +13,14 @@ bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, co
 template <typename TD, typename TO>
 bo_status slot_col0_residual_perm(const Grid &g, const double *A, const double *v, const TD *dp,
                                   const int32_t *slot_of, size_t S, TO *out, hipStream_t s);
+// Sliced layout of a BSR matrix for the solver's SpMV: slices of 64 rows; a
+// slice of width K (its longest row) stores, for k < K, the k-th block of each
+// of its rows as 9 arrays of 64 doubles and one array of 64 column indices
+// (-1 past the end of a row).  soff[S] = sum of the widths of slices < S.
+bo_status sell_build(int n, const int32_t *rp, const int32_t *ci, const double *v, DBuf<int32_t> &soff,
+                     DBuf<int32_t> &sci, DBuf<double> &sv, hipStream_t s);
+bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double *sv, double alpha,
+                    const double *x, double beta, double *y, hipStream_t s);
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s);
 bo_status axpby(long long n, double a, const double *x, double b, double *y, hipStream_t s);

@@ -41,8 +41,7 @@ size_t fstage_slots(const bo_cpr *pc);
 // y = alpha A x + beta y with the handle's copy of A (slot or BSR form)
 static bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s) {
     if (!pc->general) return slot_spmv(pc->g, pc->A.p, alpha, x, beta, y, s);
-    bo_bsr B{pc->n, pc->nnzb, pc->Arp.p, pc->Aci.p, pc->Aval.p};
-    return bo_bsr_spmv(&B, alpha, x, beta, y, s);
+    return sell_spmv(pc->n, pc->Asoff.p, pc->Asci.p, pc->Asv.p, alpha, x, beta, y, s);
 }
 
 namespace {
@@ -239,6 +238,7 @@ static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_o
         BO_HIP(hipMemcpyAsync(pc->Arp.p, A->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
         BO_HIP(hipMemcpyAsync(pc->Aci.p, A->colind, sizeof(int32_t) * A->nnzb, hipMemcpyDeviceToDevice, s));
         BO_HIP(hipMemcpyAsync(pc->Aval.p, A->val, sizeof(double) * 9 * (size_t)A->nnzb, hipMemcpyDeviceToDevice, s));
+        BO_TRY(sell_build(n, pc->Arp.p, pc->Aci.p, pc->Aval.p, pc->Asoff, pc->Asci, pc->Asv, s));
     } else {
         BO_TRY(bsr_to_slots(pc->g, A->rowptr, A->colind, A->val, pc->A.p, s));
     }
