@@ -273,7 +273,7 @@ def isolated_spmv(args, B, pc, n, dev, stream):
 
 def cpu_baseline(args, case, wl):
     """The FP64 oracle on the host: one system (assembly + setup + solve); for
-    the dual-porosity workload on its 50x50x12 twin."""
+    the dual-porosity workload on its 50x50x25 twin."""
     from oracle import oracle as O
     log(args, "[bench] cpu baseline: oracle on one system")
     t0 = time.perf_counter()
