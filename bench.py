@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--spmv-isolated", action="store_true",
                     help="also time isolated SpMV launches (after a cache-evicting pass, and back to back)")
     ap.add_argument("--spmv-reps", type=int, default=20)
+    ap.add_argument("--ceiling", action="store_true",
+                    help="also time plain 1 GiB streams (read-only reduction, copy) as the HBM ceiling")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32", "bf16"),
                     help="inner stages of the preconditioner: FP64, FP32, or FP32 with BF16 ILU factors")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -158,6 +160,8 @@ def main():
     spmv = {"us": spmv_us, "GBs": spmv_gbs, "bytes": spmv_bytes, "launches": spmv_calls}
     if args.spmv_isolated:
         spmv.update(isolated_spmv(args, B, pc, n, dev, stream))
+    if args.ceiling:
+        spmv.update(stream_ceiling(args, dev, stream))
     # plain copy of known size: calibrates the HBM byte counters of a profile
     # taken of this run (FETCH_SIZE / WRITE_SIZE of this copy vs 256 MiB)
     src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
@@ -237,6 +241,38 @@ def spmv_traffic():
     if not (m_t and m_h) or m_h.group(1) != spmv_source_hash():
         return None
     return float(m_t.group(1))
+
+
+def stream_ceiling(args, dev, stream):
+    """The box's streaming ceiling beside the 8 TB/s nominal: a 1 GiB
+    read-only reduction and a 1 GiB copy (torch's kernels), each launch after
+    a 1 GiB read that evicts L2 and the Infinity Cache, HIP events around the
+    launch as for the SpMV."""
+    import torch
+    nd = 1 << 27
+    a = torch.ones(nd, dtype=torch.float64, device=dev)
+    c = torch.empty_like(a)
+    flush = torch.ones(nd, dtype=torch.float64, device=dev)
+    sink = torch.zeros(1, dtype=torch.float64, device=dev)
+    out = {}
+    for name, op, nbytes in (("read", lambda: torch.sum(a, dim=0, keepdim=True, out=sink), 8.0 * nd),
+                             ("copy", lambda: c.copy_(a), 16.0 * nd)):
+        for _ in range(2):
+            op()
+        ev = []
+        for _ in range(args.spmv_reps):
+            torch.sum(flush, dim=0, keepdim=True, out=sink)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            op()
+            e1.record(stream)
+            ev.append((e0, e1))
+        torch.cuda.synchronize()
+        us = 1000.0 * sorted(x.elapsed_time(y) for x, y in ev)[len(ev) // 2]
+        out[f"ceiling_{name}_GBs"] = nbytes / (us * 1e-6) / 1e9
+        log(args, f"[bench] ceiling {name}: {nbytes / 1e9:.2f} GB in {us:.1f} us (median) = "
+                  f"{out[f'ceiling_{name}_GBs']:.0f} GB/s")
+    return out
 
 
 def isolated_spmv(args, B, pc, n, dev, stream):

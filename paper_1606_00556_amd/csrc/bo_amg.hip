@@ -454,11 +454,12 @@ __global__ void k_p_count(int n, const int32_t *__restrict__ rp, const int32_t *
 // stored in ascending J.
 __global__ void k_p_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                          const double *__restrict__ v, const uint8_t *__restrict__ sf,
-                         const int32_t *__restrict__ agg, const double *__restrict__ aF, double omega,
-                         const int32_t *__restrict__ prp, int32_t *__restrict__ pci, double *__restrict__ pv) {
+                         const int32_t *__restrict__ agg, const double *__restrict__ aF,
+                         const double *__restrict__ omega, const int32_t *__restrict__ prp,
+                         int32_t *__restrict__ pci, double *__restrict__ pv) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double d = omega / aF[i];
+    double d = omega[0] / aF[i];
     int len = rp[i + 1] - rp[i];
     int ai = agg[i];
     if (len > KP) return;  // long rows: k_p_long
@@ -512,7 +513,7 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_long(int n, const int32_t *_
                                                           const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                           const uint8_t *__restrict__ sf,
                                                           const int32_t *__restrict__ agg,
-                                                          const double *__restrict__ aF, double omega,
+                                                          const double *__restrict__ aF, const double *__restrict__ omega,
                                                           const int32_t *__restrict__ prp, int32_t *__restrict__ pci,
                                                           double *__restrict__ pv, int32_t *__restrict__ cnt,
                                                           int32_t *__restrict__ bad) {
@@ -549,7 +550,7 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_long(int n, const int32_t *_
         if (lane == 0) cnt[i] = mycount;
         return;
     }
-    double d = omega / aF[i];
+    double d = omega[0] / aF[i];
     int ai = agg[i];
     for (int q = lane; q < len; q += 64) {
         if (!first[wave][q]) continue;
@@ -574,7 +575,7 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_vlong(int n, const int32_t *
                                                            const double *__restrict__ v,
                                                            const uint8_t *__restrict__ sf,
                                                            const int32_t *__restrict__ agg,
-                                                           const double *__restrict__ aF, double omega,
+                                                           const double *__restrict__ aF, const double *__restrict__ omega,
                                                            const int32_t *__restrict__ prp, int32_t *__restrict__ pci,
                                                            double *__restrict__ pv, int32_t *__restrict__ cnt) {
     int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -601,7 +602,7 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_vlong(int n, const int32_t *
         if (lane == 0) cnt[i] = mycount;
         return;
     }
-    double d = omega / aF[i];
+    double d = omega[0] / aF[i];
     int ai = agg[i];
     for (int q = lane; q < len; q += 64) {
         int Jq = jof(q);
@@ -1284,16 +1285,26 @@ bo_status qi_restrict_f32(bo_cpr *pc, const double *v, float *rp, hipStream_t s)
 }
 
 // ---- host: hierarchy ---------------------------------------------------------------
-static bo_status level_diag(Level &L, int32_t *flag, hipStream_t s) {
+// dflag: a deferred flag (checked at the end of the setup; a zero diagonal
+// only makes values non-finite, every index stays valid)
+static bo_status level_diag(Level &L, int32_t *dflag, hipStream_t s) {
     BO_TRY(L.diagpos.alloc(L.n));
     BO_TRY(L.dl1.alloc(L.n));
-    BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    k_diag<<<grid_for(L.n), kBlock, 0, s>>>(L.n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.dl1.p, flag);
+    k_diag<<<grid_for(L.n), kBlock, 0, s>>>(L.n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.dl1.p, dflag);
     BO_HIP(hipGetLastError());
-    int32_t bad = 0;
-    BO_TRY(read_flag(flag, s, &bad));
-    if (bad) return fail(BO_ERR_SINGULAR_COARSE, "AMG: zero or non-finite diagonal in the pressure hierarchy");
     return BO_OK;
+}
+
+// smoother weight of the prolongator, (4/3)/rho, on the device
+__global__ void k_omega(const unsigned long long *__restrict__ rho_bits, double *__restrict__ omega,
+                        int32_t *__restrict__ bad) {
+    double rho = __longlong_as_double((long long)rho_bits[0]);
+    if (!(rho > 0.0) || !(rho < INFINITY)) {
+        *bad = 1;
+        *omega = 0.0;
+    } else {
+        *omega = (4.0 / 3.0) / rho;
+    }
 }
 
 static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const double *av, const int32_t *brp,
@@ -1368,10 +1379,15 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
     }
     int max_levels = std::min(std::max(o.max_levels, 1), kMaxLevels);
     double t2 = o.theta * o.theta;
+    // flags whose failure leaves every index valid are checked once, at the
+    // end: [0] zero diagonal, [1] unaggregated node, [2] smoother bound
+    BO_TRY(W.dfl.alloc(4));
+    BO_TRY(W.omg.alloc(kMaxLevels));
+    BO_HIP(hipMemsetAsync(W.dfl.p, 0, sizeof(int32_t) * 4, s));
     int l = 0;
     for (;; l++) {
         Level &L = pc->lv[l];
-        BO_TRY(level_diag(L, flag, s));
+        BO_TRY(level_diag(L, W.dfl.p, s));
         BO_TRY(L.x.alloc(L.n));
         BO_TRY(L.b.alloc(L.n));
         BO_TRY(L.r.alloc(L.n));
@@ -1431,12 +1447,9 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         BO_TRY(scan_counts(cnt.p, id.p, n, &nc, s));
         if (nc == 0 || (double)nc > 0.8 * (double)n) break;
         k_agg1<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, state.p, id.p, a1.p);
-        BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-        k_agg2<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, state.p, a1.p, L.agg.p, flag);
+        k_agg2<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, state.p, a1.p, L.agg.p,
+                                              W.dfl.p + 1);
         BO_HIP(hipGetLastError());
-        int32_t bad = 0;
-        BO_TRY(read_flag(flag, s, &bad));
-        if (bad) return fail(BO_ERR_HIP, "AMG: a node could not be aggregated");
         L.nc = nc;
         // prolongator
         DBuf<double> &aF = W.aF;
@@ -1444,36 +1457,29 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         BO_TRY(aF.alloc(n)); BO_TRY(rho.alloc(1));
         BO_HIP(hipMemsetAsync(rho.p, 0, sizeof(unsigned long long), s));
         k_filter<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.sf.p, aF.p, rho.p);
-        unsigned long long rb = 0;
-        HostRead rr{rho.p, sizeof rb, &rb};
-        BO_TRY(host_reads(&rr, 1, s));
-        double rhov;
-        std::memcpy(&rhov, &rb, sizeof rhov);
-        if (!(rhov > 0.0) || !(rhov < INFINITY)) return fail(BO_ERR_SINGULAR_COARSE, "AMG: bad smoother bound");
-        L.omega = (4.0 / 3.0) / rhov;
+        const double *omega = W.omg.p + l;
+        k_omega<<<1, 1, 0, s>>>(rho.p, W.omg.p + l, W.dfl.p + 2);
         BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
         k_p_count<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, L.agg.p, cnt.p);
         k_p_long<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
-                                                                       aF.p, 0.0, nullptr, nullptr, nullptr,
+                                                                       aF.p, omega, nullptr, nullptr, nullptr,
                                                                        cnt.p, flag);
         k_p_vlong<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
-                                                                        aF.p, 0.0, nullptr, nullptr, nullptr, cnt.p);
+                                                                        aF.p, omega, nullptr, nullptr, nullptr, cnt.p);
         BO_TRY(L.prp.alloc(n + 1));
         int32_t pnnz = 0;
         BO_TRY(scan_counts(cnt.p, L.prp.p, n, &pnnz, s));
         L.pnnz = pnnz;
         BO_TRY(L.pci.alloc(pnnz)); BO_TRY(L.pv.alloc(pnnz));
-        k_p_fill<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, L.omega,
+        k_p_fill<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega,
                                                 L.prp.p, L.pci.p, L.pv.p);
         k_p_long<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
-                                                                       aF.p, L.omega, L.prp.p, L.pci.p, L.pv.p,
+                                                                       aF.p, omega, L.prp.p, L.pci.p, L.pv.p,
                                                                        nullptr, flag);
         k_p_vlong<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
-                                                                        aF.p, L.omega, L.prp.p, L.pci.p, L.pv.p,
+                                                                        aF.p, omega, L.prp.p, L.pci.p, L.pv.p,
                                                                         nullptr);
         BO_HIP(hipGetLastError());
-        BO_TRY(read_flag(flag, s, &bad));
-        if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: prolongator row longer than the LDS staging limit");
         // R = P^T
         DBuf<int32_t> &rc = W.rc, &fp = W.fp;
         BO_TRY(rc.alloc(nc)); BO_TRY(fp.alloc(nc));
@@ -1495,7 +1501,6 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         Level &C = pc->lv[l + 1];
         C.n = nc;
         BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, flag, W.gcnt, s));
-        BO_HIP(hipStreamSynchronize(s));
     }
     pc->nlev = l + 1;
     // coarsest: dense inverse
@@ -1521,9 +1526,15 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         k_extract_inverse<<<grid_for((long long)nc * nc), kBlock, 0, s>>>(nc, M.p, pc->cinv.p);
     }
     BO_HIP(hipGetLastError());
-    int32_t bad = 0;
-    BO_TRY(read_flag(flag, s, &bad));
+    int32_t bad = 0, dfl[3] = {0, 0, 0};
+    double omg[kMaxLevels] = {};
+    HostRead rd[3] = {{flag, sizeof bad, &bad}, {W.dfl.p, sizeof dfl, dfl}, {W.omg.p, sizeof(double) * kMaxLevels, omg}};
+    BO_TRY(host_reads(rd, pc->nlev > 1 ? 3 : 2, s));
+    if (dfl[0]) return fail(BO_ERR_SINGULAR_COARSE, "AMG: zero or non-finite diagonal in the pressure hierarchy");
+    if (dfl[1]) return fail(BO_ERR_HIP, "AMG: a node could not be aggregated");
+    if (dfl[2]) return fail(BO_ERR_SINGULAR_COARSE, "AMG: bad smoother bound");
     if (bad) return fail(BO_ERR_SINGULAR_COARSE, "AMG: the coarsest matrix is singular");
+    for (int q = 0; q + 1 < pc->nlev; q++) pc->lv[q].omega = omg[q];
     return BO_OK;
 }
 

@@ -36,6 +36,8 @@ struct SetupWork {
     DBuf<int32_t> cnt, id, a1, rc, fp, gcnt;
     DBuf<double> aF;
     DBuf<unsigned long long> rho;
+    DBuf<int32_t> dfl;            // deferred setup flags, read once at the end (see amg_setup)
+    DBuf<double> omg;             // smoother weight of each level
     DBuf<int32_t> aprp, apci;
     DBuf<double> apv, dense;
 };
@@ -91,7 +93,7 @@ struct bo_cpr {
     bo::DBuf<double2> ilu_f, ilu_b;
     bo::DBuf<double> ilu_w, ilu_r;
     bo::DBuf<float> ilu_w32, ilu_r32;   // mixed form
-    bo::DBuf<int32_t> ilu_cell, ilu_slot;
+    bo::DBuf<int32_t> ilu_slot;
     // work vectors
     bo::DBuf<double> rp_, dp_, t3a, t3b, t3c, wf;
     bo::DBuf<int32_t> flag;

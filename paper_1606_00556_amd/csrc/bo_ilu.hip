@@ -96,13 +96,13 @@ __device__ __forceinline__ void shfl_arr(const double *src, double *dst, int lan
 }
 
 // Factorisation: writes E^{-1}, the lower blocks (-z,-y,-x) and upper blocks
-// (+x,+y,+z) of each cell (zero where the neighbour lies outside the tile or
-// grid) into the (tile, step, lane) layout, and the cell index of each slot
-// (-1 for idle slots).  E^{-1} by Gauss-Jordan with partial pivoting.
+// (+z,+x,+y) of each cell (zero where the neighbour lies outside the tile or
+// grid) into the (tile, step, lane) layout, and the slot of each cell.
+// E^{-1} by Gauss-Jordan with partial pivoting.
 template <int St>
 __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__restrict__ A,
                                                    void *__restrict__ Ff, void *__restrict__ Fb,
-                                                   int32_t *__restrict__ cell, int32_t *__restrict__ slot_of,
+                                                   int32_t *__restrict__ slot_of,
                                                    int32_t *__restrict__ bad, double *__restrict__ einv_nat) {
     int t = threadIdx.x;
     int a = t % T.tx, b = t / T.tx;
@@ -164,10 +164,7 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
             for (int z = 0; z < 9; z++) { bw[9 + z] = Uzp[z]; bw[18 + z] = Uxp[z]; bw[27 + z] = Uyp[z]; }
             store_pack<St>(Ff, tile, T.ns, s, t, fw);
             store_pack<St>(Fb, tile, T.ns, s, t, bw);
-            cell[q] = g;
             slot_of[g] = (int32_t)q;
-        } else {
-            cell[q] = -1;
         }
     }
 }
@@ -272,7 +269,7 @@ constexpr int kAhead1 = 6;  // wavefront 1: 9 factor loads per step
 // forward sweep: w = E^{-1}(r - L w_lower); r and w in (tile, step, lane) order
 template <int St, typename T>
 __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__restrict__ F,
-                                                     const int32_t *__restrict__ cell, const T *__restrict__ rq,
+                                                     const T *__restrict__ rq,
                                                      T *__restrict__ wq) {
     __shared__ T wsh[2][3][64];  // w of a step, by step parity
     __shared__ T ysh[2][6][64];  // wavefront 1's products L_y w_y and L_x w_x
@@ -363,7 +360,7 @@ __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__r
 // natural order as out = x + (dp, 0, 0) in FP64 (dp may be NULL)
 template <int St, typename T, typename TD>
 __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__restrict__ F,
-                                                      const int32_t *__restrict__ cell, const T *__restrict__ wq,
+                                                      const T *__restrict__ wq,
                                                       const TD *__restrict__ dp, double *__restrict__ out) {
     __shared__ T xsh[2][3][64];  // x of a step, by step parity
     __shared__ T ash[2][3][64];  // wavefront 1's U_x x_x + U_y x_y
@@ -697,7 +694,6 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
         // factor buffers sized for FP64; the FP32 and BF16 forms use a prefix
         BO_TRY(pc->ilu_f.alloc(S * kPairs));
         BO_TRY(pc->ilu_b.alloc(S * kPairs));
-        BO_TRY(pc->ilu_cell.alloc(S));
         BO_TRY(pc->ilu_slot.alloc(n));
         if (st == ST_F64) {
             BO_TRY(pc->ilu_w.alloc(3 * S));
@@ -709,13 +705,13 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
         // idle slots are never read by the sweeps: their factors stay unset
         int nb = T.ntx * T.nty;
         if (st == ST_F64) {
-            k_ilu_factor<ST_F64><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
+            k_ilu_factor<ST_F64><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p,
                                                    pc->ilu_slot.p, pc->flag.p, ext ? pc->x_einv_f.p : nullptr);
         } else if (st == ST_F32) {
-            k_ilu_factor<ST_F32><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
+            k_ilu_factor<ST_F32><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p,
                                                    pc->ilu_slot.p, pc->flag.p, nullptr);
         } else {
-            k_ilu_factor<ST_BF16><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p, pc->ilu_cell.p,
+            k_ilu_factor<ST_BF16><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p,
                                                     pc->ilu_slot.p, pc->flag.p, nullptr);
         }
         if (ext && pc->ncell > N) {
@@ -751,8 +747,8 @@ bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, boo
         TileGeom G = geom(pc);
         size_t S = (size_t)G.slots();
         if (!r_in_slots) k_to_slots<T><<<grid_for(n), kBlock, 0, s>>>(n, pc->ilu_slot.p, S, r, rq);
-        k_ilu_forward<St, T><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, pc->ilu_cell.p, rq, wq);
-        k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, pc->ilu_cell.p, wq, dp, out);
+        k_ilu_forward<St, T><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, rq, wq);
+        k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, wq, dp, out);
     }
     BO_HIP(hipGetLastError());
     return BO_OK;
@@ -770,7 +766,7 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
         size_t S = (size_t)G.slots();
         const long long N = pc->g.n();
         k_to_slots<double><<<grid_for(N), kBlock, 0, s>>>(N, pc->ilu_slot.p, S, r, pc->ilu_r.p);
-        k_ilu_forward<ST_F64, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, pc->ilu_cell.p, pc->ilu_r.p,
+        k_ilu_forward<ST_F64, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, pc->ilu_r.p,
                                                                     pc->ilu_w.p);
         if (pc->ncell > N)
             k_dual_forward<<<grid_for(N), kBlock, 0, s>>>((int)N, pc->ilu_slot.p, S, r, pc->x_einv_m.p, pc->x_amf.p,
@@ -779,7 +775,7 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
             int cnt = pc->n - pc->ncell;
             k_rows_apply<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out);
         }
-        k_ilu_backward<ST_F64, double, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, pc->ilu_cell.p,
+        k_ilu_backward<ST_F64, double, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p,
                                                                              pc->ilu_w.p, nullptr, out);
         BO_HIP(hipGetLastError());
         return BO_OK;
