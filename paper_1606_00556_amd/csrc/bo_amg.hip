@@ -677,38 +677,62 @@ __global__ void __launch_bounds__(kBlock) k_sort_rows(int n, const int32_t *__re
 // accumulated in ascending k exactly as in a row-by-row Gustavson product.
 // The distinct columns are then compacted, ranked (sorted) and written.
 
-// products of each row (sum of the B row lengths it touches), max over rows
+// products of each row (sum of the B row lengths it touches), their maximum
+// (stat[0]) and the number of rows above kLongProducts (stat[1])
+constexpr int kLongProducts = 128;
 __global__ void k_spgemm_bound(int n, const int32_t *__restrict__ arp, const int32_t *__restrict__ aci,
-                               const int32_t *__restrict__ brp, int32_t *__restrict__ mx) {
+                               const int32_t *__restrict__ brp, int32_t *__restrict__ prod,
+                               int32_t *__restrict__ stat) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int c = 0;
-    if (i < n)
+    if (i < n) {
         for (int e = arp[i]; e < arp[i + 1]; e++) c += brp[aci[e] + 1] - brp[aci[e]];
-    // one atomic per wavefront
-    for (int off = 32; off > 0; off >>= 1) c = max(c, __shfl_xor(c, off, 64));
-    if (threadIdx.x % 64 == 0 && c > 0) atomicMax(mx, c);
+        prod[i] = c;
+    }
+    int lng = c > kLongProducts ? 1 : 0;
+    // one atomic of each kind per wavefront
+    for (int off = 32; off > 0; off >>= 1) {
+        c = max(c, __shfl_xor(c, off, 64));
+        lng += __shfl_xor(lng, off, 64);
+    }
+    if (threadIdx.x % 64 == 0) {
+        if (c > 0) atomicMax(&stat[0], c);
+        if (lng > 0) atomicAdd(&stat[1], lng);
+    }
 }
 
+// the rows above kLongProducts, in any order (each is computed on its own)
+__global__ void k_spgemm_long_rows(int n, const int32_t *__restrict__ prod, int32_t *__restrict__ rows,
+                                   int32_t *__restrict__ pos) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && prod[i] > kLongProducts) rows[atomicAdd(pos, 1)] = i;
+}
+
+// Rows: with rows != NULL the kernel takes rows[0..n) (the long rows); with
+// prod != NULL it takes rows 0..n-1 except those above kLongProducts products.
 template <int G, int H, bool NUM>
 __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict__ arp,
                                                const int32_t *__restrict__ aci, const double *__restrict__ av,
                                                const int32_t *__restrict__ brp, const int32_t *__restrict__ bci,
                                                const double *__restrict__ bv, int32_t *__restrict__ cnt,
                                                const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
-                                               double *__restrict__ cv, int32_t *__restrict__ bad) {
+                                               double *__restrict__ cv, int32_t *__restrict__ bad,
+                                               const int32_t *__restrict__ rows, const int32_t *__restrict__ prod) {
     constexpr int R = 256 / G;
     constexpr int HV = NUM ? H : 1;  // the counting pass keeps no values
     __shared__ int key[R][H];
     __shared__ double val[R][HV];
     __shared__ int nl[R];
     int grp = threadIdx.x / G, sub = threadIdx.x % G;
-    int i = blockIdx.x * R + grp;
+    int idx = blockIdx.x * R + grp;
     for (int t = sub; t < H; t += G) key[grp][t] = -1;
     if (NUM)
         for (int t = sub; t < HV; t += G) val[grp][t] = 0.0;
     if (sub == 0) nl[grp] = 0;
     __syncthreads();
-    if (i >= n) return;
+    if (idx >= n) return;
+    const int i = rows ? rows[idx] : idx;
+    if (prod && prod[i] > kLongProducts) return;  // left to the long-row launch
     constexpr bool numeric = NUM;
     // one product: the column's slot (linear probing), then its sum
     auto insert = [&](int c, double prod) {
@@ -1307,30 +1331,42 @@ __global__ void k_omega(const unsigned long long *__restrict__ rho_bits, double 
     }
 }
 
+// C = A B, counting pass, prefix sum, numeric pass.  The hash of a row must
+// hold twice its products: rows are sized by the longest row unless a few
+// rows (a well through many layers) are much longer than the rest; then the
+// others take the 256-slot hash and the long rows a launch of their own.
 static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const double *av, const int32_t *brp,
                         const int32_t *bci, const double *bv, DBuf<int32_t> &crp, DBuf<int32_t> &cci,
-                        DBuf<double> &cv, int *cnnz, int32_t *flag, DBuf<int32_t> &cnt, hipStream_t s) {
+                        DBuf<double> &cv, int *cnnz, int32_t *flag, SetupWork &W, hipStream_t s) {
+    DBuf<int32_t> &cnt = W.gcnt;
     BO_TRY(cnt.alloc(n));
     BO_TRY(crp.alloc(n + 1));
+    BO_TRY(W.sg_prod.alloc(n));
+    BO_TRY(W.sg_stat.alloc(4));
+    BO_HIP(hipMemsetAsync(W.sg_stat.p, 0, sizeof(int32_t) * 4, s));
     BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    k_spgemm_bound<<<grid_for(n), kBlock, 0, s>>>(n, arp, aci, brp, flag);
-    int32_t bound = 0;
-    BO_TRY(read_flag(flag, s, &bound));
-    BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-    // smallest hash holding twice the products of the longest row; lanes per
-    // row grow with the work per row
-    int sel;
-    if (bound <= 32) sel = 0;
-    else if (bound <= 64) sel = 4;
-    else if (bound <= 128) sel = 1;
-    else if (bound <= 512) sel = 2;
-    else sel = 3;
-    auto launch = [&](int32_t *c, const int32_t *rp_, int32_t *ci_, double *v_) {
-#define BO_SPGEMM(G, H)                                                                                   \
-    if (ci_) k_spgemm<G, H, true><<<grid_for((long long)n * G), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, \
-                                                                           c, rp_, ci_, v_, flag);        \
-    else k_spgemm<G, H, false><<<grid_for((long long)n * G), 256, 0, s>>>(n, arp, aci, av, brp, bci, bv, c, \
-                                                                         rp_, ci_, v_, flag)
+    k_spgemm_bound<<<grid_for(n), kBlock, 0, s>>>(n, arp, aci, brp, W.sg_prod.p, W.sg_stat.p);
+    int32_t stat[2] = {0, 0};
+    HostRead rd{W.sg_stat.p, sizeof stat, stat};
+    BO_TRY(host_reads(&rd, 1, s));
+    const int bound = stat[0], nlong = stat[1];
+    auto pick = [](int b) { return b <= 32 ? 0 : b <= 64 ? 4 : b <= 128 ? 1 : b <= 512 ? 2 : 3; };
+    // split when the long rows are few (below 1 %)
+    const bool split = bound > kLongProducts && (long long)nlong * 100 < n;
+    const int sel_all = split ? pick(kLongProducts) : pick(bound), sel_long = pick(bound);
+    const int32_t *prod = split ? W.sg_prod.p : nullptr;
+    if (split) {
+        BO_TRY(W.sg_rows.alloc(nlong));
+        k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, W.sg_prod.p, W.sg_rows.p, W.sg_stat.p + 2);
+    }
+    auto launch = [&](int sel, int rn, const int32_t *rows, const int32_t *pr, int32_t *c, const int32_t *rp_,
+                      int32_t *ci_, double *v_) {
+        if (rn <= 0) return;
+#define BO_SPGEMM(G, H)                                                                                        \
+    if (ci_) k_spgemm<G, H, true><<<grid_for((long long)rn * G), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv,  \
+                                                                            c, rp_, ci_, v_, flag, rows, pr);   \
+    else k_spgemm<G, H, false><<<grid_for((long long)rn * G), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, c,  \
+                                                                          rp_, ci_, v_, flag, rows, pr)
         switch (sel) {
         case 0: BO_SPGEMM(8, 64); break;
         case 4: BO_SPGEMM(8, 128); break;
@@ -1340,7 +1376,8 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         }
 #undef BO_SPGEMM
     };
-    launch(cnt.p, nullptr, nullptr, nullptr);
+    launch(sel_all, n, nullptr, prod, cnt.p, nullptr, nullptr, nullptr);
+    if (split) launch(sel_long, nlong, W.sg_rows.p, nullptr, cnt.p, nullptr, nullptr, nullptr);
     BO_HIP(hipGetLastError());
     int32_t bad = 0, total = 0;
     BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s, flag, &bad));
@@ -1349,7 +1386,8 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     BO_TRY(cv.alloc(total));
     // with every row within half the hash (checked above) no insertion of the
     // second pass can fail
-    launch(nullptr, crp.p, cci.p, cv.p);
+    launch(sel_all, n, nullptr, prod, nullptr, crp.p, cci.p, cv.p);
+    if (split) launch(sel_long, nlong, W.sg_rows.p, nullptr, nullptr, crp.p, cci.p, cv.p);
     BO_HIP(hipGetLastError());
     *cnnz = total;
     return BO_OK;
@@ -1497,10 +1535,10 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         DBuf<int32_t> &aprp = W.aprp, &apci = W.apci;
         DBuf<double> &apv = W.apv;
         int apnnz = 0;
-        BO_TRY(spgemm(n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p, aprp, apci, apv, &apnnz, flag, W.gcnt, s));
+        BO_TRY(spgemm(n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p, aprp, apci, apv, &apnnz, flag, W, s));
         Level &C = pc->lv[l + 1];
         C.n = nc;
-        BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, flag, W.gcnt, s));
+        BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, flag, W, s));
     }
     pc->nlev = l + 1;
     // coarsest: dense inverse

@@ -40,6 +40,7 @@ struct SetupWork {
     DBuf<double> omg;             // smoother weight of each level
     DBuf<int32_t> aprp, apci;
     DBuf<double> apv, dense;
+    DBuf<int32_t> sg_prod, sg_rows, sg_stat;  // sparse product: products per row, long rows, [max, #long]
 };
 
 struct Krylov {
@@ -91,8 +92,8 @@ struct bo_cpr {
     // buffers hold FP32 or BF16 values
     bo::DBuf<double> einv;
     bo::DBuf<double2> ilu_f, ilu_b;
-    bo::DBuf<double> ilu_w, ilu_r;
-    bo::DBuf<float> ilu_w32, ilu_r32;   // mixed form
+    bo::DBuf<double> ilu_w;
+    bo::DBuf<float> ilu_w32;           // mixed form
     bo::DBuf<int32_t> ilu_slot;
     // work vectors
     bo::DBuf<double> rp_, dp_, t3a, t3b, t3c, wf;

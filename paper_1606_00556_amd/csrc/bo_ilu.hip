@@ -214,16 +214,6 @@ __device__ __forceinline__ void load_vec(const T *__restrict__ vec, size_t S, si
     w[0] = vec[q]; w[1] = vec[S + q]; w[2] = vec[2 * S + q];
 }
 
-// scatter a natural-order 3N vector into (tile, step, lane) order
-template <typename T>
-__global__ void k_to_slots(long long n, const int32_t *__restrict__ slot_of, size_t S, const double *__restrict__ r,
-                           T *__restrict__ rq) {
-    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    size_t q = (size_t)slot_of[g];
-    rq[q] = (T)r[3 * g]; rq[S + q] = (T)r[3 * g + 1]; rq[2 * S + q] = (T)r[3 * g + 2];
-}
-
 // Sweeps: two wavefronts per tile.  Wavefront 0 loads the first half of each
 // slot's factors (E^{-1} and the -z block forward; E^{-1} and the +z block
 // backward) with the vector operand, wavefront 1 the second half (the -y and
@@ -266,10 +256,11 @@ struct SweepLane {
 constexpr int kAhead0 = 4;  // wavefront 0: 9 factor + 3 vector loads and 3 stores per step
 constexpr int kAhead1 = 6;  // wavefront 1: 9 factor loads per step
 
-// forward sweep: w = E^{-1}(r - L w_lower); r and w in (tile, step, lane) order
+// forward sweep: w = E^{-1}(r - L w_lower); r (FP64) in natural order, read at
+// the slot's cell and rounded to T; w in (tile, step, lane) order
 template <int St, typename T>
 __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__restrict__ F,
-                                                     const T *__restrict__ rq,
+                                                     const double *__restrict__ r,
                                                      T *__restrict__ wq) {
     __shared__ T wsh[2][3][64];  // w of a step, by step parity
     __shared__ T ysh[2][6][64];  // wavefront 1's products L_y w_y and L_x w_x
@@ -318,9 +309,10 @@ __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__r
         T vec[kAhead0][3];
         auto fetch = [&](int s, Half<T> &h, T *w) {
             const int sc = min(s, ns - 1);
-            const int tl = L.active(G, sc) ? t : 0;
-            load_half<St, T, 0>(F, tile, ns, sc, tl, h);
-            load_vec(rq, S, ((size_t)tile * ns + sc) * 64 + tl, w);
+            const bool act = L.active(G, sc);
+            load_half<St, T, 0>(F, tile, ns, sc, act ? t : 0, h);
+            const double *rg = r + 3 * (act ? L.cell(G, tile, sc) : 0);
+            w[0] = (T)rg[0]; w[1] = (T)rg[1]; w[2] = (T)rg[2];
         };
         auto step = [&](int s, Half<T> &h, T *w) {
             __syncthreads();  // products of step s published
@@ -695,13 +687,8 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
         BO_TRY(pc->ilu_f.alloc(S * kPairs));
         BO_TRY(pc->ilu_b.alloc(S * kPairs));
         BO_TRY(pc->ilu_slot.alloc(n));
-        if (st == ST_F64) {
-            BO_TRY(pc->ilu_w.alloc(3 * S));
-            BO_TRY(pc->ilu_r.alloc(3 * S));
-        } else {
-            BO_TRY(pc->ilu_w32.alloc(3 * S));
-            BO_TRY(pc->ilu_r32.alloc(3 * S));
-        }
+        if (st == ST_F64) BO_TRY(pc->ilu_w.alloc(3 * S));
+        else BO_TRY(pc->ilu_w32.alloc(3 * S));
         // idle slots are never read by the sweeps: their factors stay unset
         int nb = T.ntx * T.nty;
         if (st == ST_F64) {
@@ -738,16 +725,13 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
 
 namespace {
 template <int St, typename T, typename TD>
-bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, bool r_in_slots, T *rq, T *wq,
-                     hipStream_t s) {
+bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, T *wq, hipStream_t s) {
     long long n = pc->n;
     if (pc->o.ftype == BO_F_BJ) {
         k_bj_apply<St, T, TD><<<grid_for(n), kBlock, 0, s>>>(n, pc->einv.p, r, dp, out);
     } else {
         TileGeom G = geom(pc);
-        size_t S = (size_t)G.slots();
-        if (!r_in_slots) k_to_slots<T><<<grid_for(n), kBlock, 0, s>>>(n, pc->ilu_slot.p, S, r, rq);
-        k_ilu_forward<St, T><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, rq, wq);
+        k_ilu_forward<St, T><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, r, wq);
         k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, wq, dp, out);
     }
     BO_HIP(hipGetLastError());
@@ -755,19 +739,16 @@ bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, boo
 }
 }  // namespace
 
-// out = F(r) (+ Pi_p dp when dp != NULL).  With r_in_slots the residual is
-// already in the F stage's slot order (ilu_r, or ilu_r32 in the mixed form).
-bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, bool r_in_slots, hipStream_t s) {
+// out = F(r) (+ Pi_p dp when dp != NULL); r in natural order
+bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, hipStream_t s) {
     if (pc->general && pc->o.ftype == BO_F_ILU_TILED) {
         // the extended grid form (FP64): tiles of fracture cells, then matrix
         // cells, then well rows
-        if (dp || r_in_slots) return fail(BO_ERR_INVALID_ARG, "F stage: extended form takes r in natural order");
+        if (dp) return fail(BO_ERR_INVALID_ARG, "F stage: extended form takes no pressure correction");
         TileGeom G = geom(pc);
         size_t S = (size_t)G.slots();
         const long long N = pc->g.n();
-        k_to_slots<double><<<grid_for(N), kBlock, 0, s>>>(N, pc->ilu_slot.p, S, r, pc->ilu_r.p);
-        k_ilu_forward<ST_F64, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, pc->ilu_r.p,
-                                                                    pc->ilu_w.p);
+        k_ilu_forward<ST_F64, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, r, pc->ilu_w.p);
         if (pc->ncell > N)
             k_dual_forward<<<grid_for(N), kBlock, 0, s>>>((int)N, pc->ilu_slot.p, S, r, pc->x_einv_m.p, pc->x_amf.p,
                                                           pc->x_afm.p, pc->x_einv_f.p, pc->ilu_w.p, out);
@@ -781,22 +762,20 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
         return BO_OK;
     }
     switch (store_of(pc)) {
-    case ST_F64: return fstage_run<ST_F64, double, double>(pc, r, dp, out, r_in_slots, pc->ilu_r.p, pc->ilu_w.p, s);
-    case ST_F32: return fstage_run<ST_F32, float, double>(pc, r, dp, out, r_in_slots, pc->ilu_r32.p, pc->ilu_w32.p, s);
-    default: return fstage_run<ST_BF16, float, double>(pc, r, dp, out, r_in_slots, pc->ilu_r32.p, pc->ilu_w32.p, s);
+    case ST_F64: return fstage_run<ST_F64, double, double>(pc, r, dp, out, pc->ilu_w.p, s);
+    case ST_F32: return fstage_run<ST_F32, float, double>(pc, r, dp, out, pc->ilu_w32.p, s);
+    default: return fstage_run<ST_BF16, float, double>(pc, r, dp, out, pc->ilu_w32.p, s);
     }
 }
 
 // mixed form with the FP32 pressure correction of the V-cycle
-bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, bool r_in_slots,
-                             hipStream_t s) {
+bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, hipStream_t s) {
     switch (store_of(pc)) {
-    case ST_F32: return fstage_run<ST_F32, float, float>(pc, r, dp, out, r_in_slots, pc->ilu_r32.p, pc->ilu_w32.p, s);
-    case ST_BF16: return fstage_run<ST_BF16, float, float>(pc, r, dp, out, r_in_slots, pc->ilu_r32.p, pc->ilu_w32.p, s);
+    case ST_F32: return fstage_run<ST_F32, float, float>(pc, r, dp, out, pc->ilu_w32.p, s);
+    case ST_BF16: return fstage_run<ST_BF16, float, float>(pc, r, dp, out, pc->ilu_w32.p, s);
     default: return fail(BO_ERR_INVALID_ARG, "F stage: FP32 pressure correction in the FP64 form");
     }
 }
 
-size_t fstage_slots(const bo_cpr *pc) { return (size_t)geom(pc).slots(); }
 
 }  // namespace bo

@@ -336,38 +336,6 @@ __global__ void __launch_bounds__(kBlock) k_slot_col0_residual(int nx, int ny, i
 
 // The same residual written in the F stage's slot order: component c of cell
 // i goes to out[c * S + slot_of[i]].
-template <typename TD, typename TO>
-__global__ void __launch_bounds__(kBlock) k_slot_col0_residual_perm(int nx, int ny, int nz,
-                                                                    const double *__restrict__ A,
-                                                                    const double *__restrict__ v,
-                                                                    const TD *__restrict__ dp,
-                                                                    const int32_t *__restrict__ slot_of, size_t S,
-                                                                    TO *__restrict__ out) {
-    int n = nx * ny * nz;
-    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    size_t N = (size_t)n;
-    int nxy = nx * ny;
-    int ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
-    const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
-                       ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-    for (int s = 0; s < NSLOT; s++) {
-        int j = nb[s];
-        if (j < 0) continue;
-        const double *a = A + (size_t)s * 9 * N + i;
-        double p = (double)dp[j];
-        s0 = s0 + a[0 * N] * p;
-        s1 = s1 + a[3 * N] * p;
-        s2 = s2 + a[6 * N] * p;
-    }
-    size_t q = (size_t)slot_of[i];
-    out[q] = (TO)(v[3 * (size_t)i] - s0);
-    out[S + q] = (TO)(v[3 * (size_t)i + 1] - s1);
-    out[2 * S + q] = (TO)(v[3 * (size_t)i + 2] - s2);
-}
-
 // ---- BLAS-1 -------------------------------------------------------------------
 __global__ void k_axpby(long long n, double a, const double *__restrict__ x, double b, double *__restrict__ y) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -542,21 +510,6 @@ template bo_status slot_col0_residual<double, double>(const Grid &, const double
                                                       double *, hipStream_t);
 template bo_status slot_col0_residual<float, double>(const Grid &, const double *, const double *, const float *,
                                                      double *, hipStream_t);
-
-template <typename TD, typename TO>
-bo_status slot_col0_residual_perm(const Grid &g, const double *A, const double *v, const TD *dp,
-                                  const int32_t *slot_of, size_t S, TO *out, hipStream_t s) {
-    long long n = g.n();
-    k_slot_col0_residual_perm<TD, TO><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, v, dp, slot_of, S, out);
-    BO_HIP(hipGetLastError());
-    return BO_OK;
-}
-template bo_status slot_col0_residual_perm<double, double>(const Grid &, const double *, const double *,
-                                                           const double *, const int32_t *, size_t, double *,
-                                                           hipStream_t);
-template bo_status slot_col0_residual_perm<float, float>(const Grid &, const double *, const double *,
-                                                         const float *, const int32_t *, size_t, float *,
-                                                         hipStream_t);
 
 bo_status sell_build(int n, const int32_t *rp, const int32_t *ci, const double *v, DBuf<int32_t> &soff,
                      DBuf<int32_t> &sci, DBuf<double> &sv, hipStream_t s) {

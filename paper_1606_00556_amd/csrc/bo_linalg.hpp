@@ -9,10 +9,6 @@ bo_status slot_spmv(const Grid &g, const double *A, double alpha, const double *
 // r = v - A (Pi_p dp) (FP64 arithmetic; dp FP64 or FP32, r stored as TO)
 template <typename TD, typename TO>
 bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, const TD *dp, TO *r, hipStream_t s);
-// the same, written in the F stage's slot order
-template <typename TD, typename TO>
-bo_status slot_col0_residual_perm(const Grid &g, const double *A, const double *v, const TD *dp,
-                                  const int32_t *slot_of, size_t S, TO *out, hipStream_t s);
 // Sliced layout of a BSR matrix for the solver's SpMV: slices of 64 rows; a
 // slice of width K (its longest row) stores, for k < K, the k-th block of each
 // of its rows as 9 arrays of 64 doubles and one array of 64 column indices

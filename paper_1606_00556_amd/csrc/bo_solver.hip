@@ -29,14 +29,12 @@ bo_status amg_vcycle_ptr_f32(bo_cpr *pc, const float *b, const float **res, hipS
 bo_status amg_make_f32(bo_cpr *pc, hipStream_t s);
 bo_status qi_restrict_f32(bo_cpr *pc, const double *v, float *rp, hipStream_t s);
 bo_status fstage_setup(bo_cpr *pc, hipStream_t s);
-bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, bool r_in_slots, hipStream_t s);
-bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, bool r_in_slots,
-                             hipStream_t s);
+bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, hipStream_t s);
+bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, hipStream_t s);
 template <typename T>
 bo_status nn_correct(bo_cpr *pc, const T *rp, const T *dp, const T **out, hipStream_t s);
 template <typename T>
 bo_status nn_record(bo_cpr *pc, const T *rp, hipStream_t s);
-size_t fstage_slots(const bo_cpr *pc);
 
 // y = alpha A x + beta y with the handle's copy of A (slot or BSR form)
 static bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s) {
@@ -89,7 +87,7 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     const bool mixed = pc->o.precision != BO_PREC_FP64;
     if (!pc->o.fpf && pc->general) {
         // x1 = Pi_p V(Pi_r v); z = x1 + F(v - A x1) with the BSR operator
-        if (!pc->o.use_amg) return fstage_apply(pc, v, nullptr, z, false, s);
+        if (!pc->o.use_amg) return fstage_apply(pc, v, nullptr, z, s);
         const void *dp;
         BO_TRY(pressure_stage(pc, v, &dp, s));
         BO_TRY(fill(3 * n, 0.0, pc->t3b.p, s));
@@ -98,36 +96,25 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
         BO_HIP(hipGetLastError());
         BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
         BO_TRY(op_spmv(pc, -1.0, pc->t3b.p, 1.0, pc->t3a.p, s));
-        BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, z, false, s));
+        BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, z, s));
         if (mixed) k_add_p<float><<<grid_for(npr), kBlock, 0, s>>>(npr, (const float *)dp, z);
         else k_add_p<double><<<grid_for(npr), kBlock, 0, s>>>(npr, (const double *)dp, z);
         BO_HIP(hipGetLastError());
         return BO_OK;
     }
     if (!pc->o.fpf) {
-        if (!pc->o.use_amg) return fstage_apply(pc, v, nullptr, z, false, s);
+        if (!pc->o.use_amg) return fstage_apply(pc, v, nullptr, z, s);
         const void *dp;
         BO_TRY(pressure_stage(pc, v, &dp, s));
-        if (pc->o.ftype == BO_F_ILU_TILED) {
-            // the residual goes straight into the F stage's slot order
-            if (mixed) {
-                BO_TRY(slot_col0_residual_perm(g, pc->A.p, v, (const float *)dp, pc->ilu_slot.p, fstage_slots(pc),
-                                               pc->ilu_r32.p, s));
-                return fstage_apply_f32dp(pc, nullptr, (const float *)dp, z, true, s);
-            }
-            BO_TRY(slot_col0_residual_perm(g, pc->A.p, v, (const double *)dp, pc->ilu_slot.p, fstage_slots(pc),
-                                           pc->ilu_r.p, s));
-            return fstage_apply(pc, nullptr, (const double *)dp, z, true, s);
-        }
         if (mixed) {
             BO_TRY(slot_col0_residual(g, pc->A.p, v, (const float *)dp, pc->t3a.p, s));
-            return fstage_apply_f32dp(pc, pc->t3a.p, (const float *)dp, z, false, s);
+            return fstage_apply_f32dp(pc, pc->t3a.p, (const float *)dp, z, s);
         }
         BO_TRY(slot_col0_residual(g, pc->A.p, v, (const double *)dp, pc->t3a.p, s));
-        return fstage_apply(pc, pc->t3a.p, (const double *)dp, z, false, s);
+        return fstage_apply(pc, pc->t3a.p, (const double *)dp, z, s);
     }
     // FPF
-    BO_TRY(fstage_apply(pc, v, nullptr, z, false, s));
+    BO_TRY(fstage_apply(pc, v, nullptr, z, s));
     if (pc->o.use_amg) {
         BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
         BO_TRY(op_spmv(pc, -1.0, z, 1.0, pc->t3a.p, s));
@@ -139,7 +126,7 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     }
     BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
     BO_TRY(op_spmv(pc, -1.0, z, 1.0, pc->t3a.p, s));
-    BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, pc->t3b.p, false, s));
+    BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, pc->t3b.p, s));
     return axpby(3 * n, 1.0, pc->t3b.p, 1.0, z, s);
 }
 
@@ -364,7 +351,7 @@ extern "C" bo_status bo_cpr_vcycle(bo_cpr *pc, const double *b, double *x, void 
 
 extern "C" bo_status bo_cpr_fstage(bo_cpr *pc, const double *r, double *x, void *stream) {
     if (!pc || !r || !x) return fail(BO_ERR_INVALID_ARG, "bo_cpr_fstage: NULL argument");
-    return fstage_apply(pc, r, nullptr, x, false, (hipStream_t)stream);
+    return fstage_apply(pc, r, nullptr, x, (hipStream_t)stream);
 }
 
 extern "C" bo_status bo_cpr_levels(bo_cpr *pc, int32_t *nlevels) {
