@@ -710,6 +710,9 @@ __global__ void k_spgemm_long_rows(int n, const int32_t *__restrict__ prod, int3
 
 // Rows: with rows != NULL the kernel takes rows[0..n) (the long rows); with
 // prod != NULL it takes rows 0..n-1 except those above kLongProducts products.
+// The counting pass sizes its hash for the row's products and records the
+// largest distinct count in *maxl; the numeric pass then takes a hash of at
+// least twice that.
 template <int G, int H, bool NUM>
 __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict__ arp,
                                                const int32_t *__restrict__ aci, const double *__restrict__ av,
@@ -717,7 +720,9 @@ __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict
                                                const double *__restrict__ bv, int32_t *__restrict__ cnt,
                                                const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
                                                double *__restrict__ cv, int32_t *__restrict__ bad,
-                                               const int32_t *__restrict__ rows, const int32_t *__restrict__ prod) {
+                                               const int32_t *__restrict__ rows, const int32_t *__restrict__ prod,
+                                               int32_t *__restrict__ maxl) {
+    static_assert(H >= G && H % G == 0, "hash slots per lane");
     constexpr int R = 256 / G;
     constexpr int HV = NUM ? H : 1;  // the counting pass keeps no values
     __shared__ int key[R][H];
@@ -819,6 +824,8 @@ __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict
         if (sub == 0) {
             cnt[i] = L;
             if (L > H / 2) *bad = 1;
+            // rows rarely raise the maximum: read it before the atomic
+            if (L > __hip_atomic_load(maxl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxl, L);
         }
     } else {
         // each distinct column goes to its rank among the row's columns
@@ -1350,7 +1357,9 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     HostRead rd{W.sg_stat.p, sizeof stat, stat};
     BO_TRY(host_reads(&rd, 1, s));
     const int bound = stat[0], nlong = stat[1];
+    // counting pass: lanes per row and hash slots from the row's products
     auto pick = [](int b) { return b <= 32 ? 0 : b <= 64 ? 4 : b <= 128 ? 1 : b <= 512 ? 2 : 3; };
+    auto count_slots = [](int sel) { return sel == 0 ? 64 : sel == 4 ? 128 : sel == 1 ? 256 : sel == 2 ? 1024 : 2048; };
     // split when the long rows are few (below 1 %)
     const bool split = bound > kLongProducts && (long long)nlong * 100 < n;
     const int sel_all = split ? pick(kLongProducts) : pick(bound), sel_long = pick(bound);
@@ -1359,35 +1368,60 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         BO_TRY(W.sg_rows.alloc(nlong));
         k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, W.sg_prod.p, W.sg_rows.p, W.sg_stat.p + 2);
     }
-    auto launch = [&](int sel, int rn, const int32_t *rows, const int32_t *pr, int32_t *c, const int32_t *rp_,
-                      int32_t *ci_, double *v_) {
+    auto count = [&](int sel, int rn, const int32_t *rows, const int32_t *pr) {
         if (rn <= 0) return;
-#define BO_SPGEMM(G, H)                                                                                        \
-    if (ci_) k_spgemm<G, H, true><<<grid_for((long long)rn * G), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv,  \
-                                                                            c, rp_, ci_, v_, flag, rows, pr);   \
-    else k_spgemm<G, H, false><<<grid_for((long long)rn * G), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, c,  \
-                                                                          rp_, ci_, v_, flag, rows, pr)
+#define BO_SPGEMM_COUNT(G, H)                                                                                 \
+    k_spgemm<G, H, false><<<grid_for((long long)rn * G), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, cnt.p, \
+                                                                      nullptr, nullptr, nullptr, flag, rows,  \
+                                                                      pr, W.sg_stat.p + 3)
         switch (sel) {
-        case 0: BO_SPGEMM(8, 64); break;
-        case 4: BO_SPGEMM(8, 128); break;
-        case 1: BO_SPGEMM(16, 256); break;
-        case 2: BO_SPGEMM(64, 1024); break;
-        default: BO_SPGEMM(64, 2048); break;
+        case 0: BO_SPGEMM_COUNT(8, 64); break;
+        case 4: BO_SPGEMM_COUNT(8, 128); break;
+        case 1: BO_SPGEMM_COUNT(16, 256); break;
+        case 2: BO_SPGEMM_COUNT(64, 1024); break;
+        default: BO_SPGEMM_COUNT(64, 2048); break;
         }
-#undef BO_SPGEMM
+#undef BO_SPGEMM_COUNT
     };
-    launch(sel_all, n, nullptr, prod, cnt.p, nullptr, nullptr, nullptr);
-    if (split) launch(sel_long, nlong, W.sg_rows.p, nullptr, cnt.p, nullptr, nullptr, nullptr);
+    count(sel_all, n, nullptr, prod);
+    if (split) count(sel_long, nlong, W.sg_rows.p, nullptr);
     BO_HIP(hipGetLastError());
-    int32_t bad = 0, total = 0;
-    BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s, flag, &bad));
+    int32_t bad = 0, total = 0, lmax = 0;
+    HostRead ex[2] = {{flag, sizeof bad, &bad}, {W.sg_stat.p + 3, sizeof lmax, &lmax}};
+    BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s, ex, 2));
     if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: Galerkin product row exceeds the LDS hash capacity");
     BO_TRY(cci.alloc(total));
     BO_TRY(cv.alloc(total));
-    // with every row within half the hash (checked above) no insertion of the
-    // second pass can fail
-    launch(sel_all, n, nullptr, prod, nullptr, crp.p, cci.p, cv.p);
-    if (split) launch(sel_long, nlong, W.sg_rows.p, nullptr, nullptr, crp.p, cci.p, cv.p);
+    // numeric pass: the same lanes per row, a hash of at least twice the
+    // largest distinct count (never more than the counting pass had), so no
+    // insertion can fail and the LDS left over keeps more rows resident
+    auto numeric = [&](int sel, int rn, const int32_t *rows, const int32_t *pr) {
+        if (rn <= 0) return;
+        int h = 64;
+        while (h < 2 * lmax && h < count_slots(sel)) h *= 2;
+        const int G = sel == 0 || sel == 4 ? 8 : sel == 1 ? 16 : 64;
+#define BO_SPGEMM_NUM(GG, H)                                                                                    \
+    k_spgemm<GG, H, true><<<grid_for((long long)rn * GG), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, nullptr, \
+                                                                       crp.p, cci.p, cv.p, flag, rows, pr,     \
+                                                                       W.sg_stat.p + 3)
+        if (G == 8) {
+            if (h <= 64) BO_SPGEMM_NUM(8, 64); else BO_SPGEMM_NUM(8, 128);
+        } else if (G == 16) {
+            if (h <= 64) BO_SPGEMM_NUM(16, 64); else if (h <= 128) BO_SPGEMM_NUM(16, 128); else BO_SPGEMM_NUM(16, 256);
+        } else {
+            switch (h) {
+            case 64: BO_SPGEMM_NUM(64, 64); break;
+            case 128: BO_SPGEMM_NUM(64, 128); break;
+            case 256: BO_SPGEMM_NUM(64, 256); break;
+            case 512: BO_SPGEMM_NUM(64, 512); break;
+            case 1024: BO_SPGEMM_NUM(64, 1024); break;
+            default: BO_SPGEMM_NUM(64, 2048); break;
+            }
+        }
+#undef BO_SPGEMM_NUM
+    };
+    numeric(sel_all, n, nullptr, prod);
+    if (split) numeric(sel_long, nlong, W.sg_rows.p, nullptr);
     BO_HIP(hipGetLastError());
     *cnnz = total;
     return BO_OK;

@@ -191,9 +191,10 @@ bo_status host_reads(const HostRead *r, int count, hipStream_t s);
 
 // ---- host-side scan / reductions (declared in bo_linalg.hip) -------------------
 // Exclusive prefix sum of n int32 counts into out (n+1 entries, out[n] = total);
-// returns the total on the host (synchronises the stream).  With dflag set,
-// *hflag receives that device word in the same synchronisation.
+// returns the total on the host (synchronises the stream).  The nextra reads
+// in extra (device words the caller wants) are served in the same
+// synchronisation (at most three).
 bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s,
-                      const int32_t *dflag = nullptr, int32_t *hflag = nullptr);
+                      const HostRead *extra = nullptr, int nextra = 0);
 
 }  // namespace bo

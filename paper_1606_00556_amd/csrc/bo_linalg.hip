@@ -127,13 +127,15 @@ __global__ void k_scan_apply(const int32_t *in, int n, const int32_t *sums, int3
 }
 
 bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s,
-                      const int32_t *dflag, int32_t *hflag) {
+                      const HostRead *extra, int nextra) {
+    if (nextra < 0 || nextra > 3) return fail(BO_ERR_INVALID_ARG, "scan_counts: at most three extra reads");
+    HostRead r[4];
+    for (int q = 0; q < nextra; q++) r[1 + q] = extra[q];
     if (n <= 0) {
         int32_t z = 0;
         BO_HIP(hipMemcpyAsync(out, &z, sizeof z, hipMemcpyHostToDevice, s));
-        if (dflag) {
-            HostRead r{dflag, sizeof(int32_t), hflag};
-            BO_TRY(host_reads(&r, 1, s));
+        if (nextra > 0) {
+            BO_TRY(host_reads(r + 1, nextra, s));
         } else {
             BO_HIP(hipStreamSynchronize(s));
         }
@@ -148,8 +150,8 @@ bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total
     k_scan_apply<<<nb, kScanBlock, 0, s>>>(counts, n, sums, out);
     BO_HIP(hipGetLastError());
     int32_t tot = 0;
-    HostRead r[2] = {{out + n, sizeof tot, &tot}, {dflag, sizeof(int32_t), hflag}};
-    BO_TRY(host_reads(r, dflag ? 2 : 1, s));
+    r[0] = HostRead{out + n, sizeof tot, &tot};
+    BO_TRY(host_reads(r, 1 + nextra, s));
     if (total) *total = tot;
     return BO_OK;
 }
