@@ -47,6 +47,8 @@ def parse():
                     help="also time plain 1 GiB streams (read-only reduction, copy) as the HBM ceiling")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32", "bf16"),
                     help="inner stages of the preconditioner: FP64, FP32, or FP32 with BF16 ILU factors")
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
+                    help="1: replay the preconditioner as a HIP graph; 0: launch its kernels directly (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -102,8 +104,8 @@ def main():
     else:
         grid = (c0.nx, c0.ny, c0.nz)
         copts = B.bo_cpr_default_opts(precision=prec)
-    fopts = B.bo_fgmres_default_opts()
-    fopts_timed = B.bo_fgmres_default_opts(timing=1)
+    fopts = B.bo_fgmres_default_opts(graph=args.graph)
+    fopts_timed = B.bo_fgmres_default_opts(timing=1, graph=args.graph)
     torch.cuda.synchronize()
 
     # the preconditioner handle lives across systems, as in a Newton loop:

@@ -251,10 +251,12 @@ typedef struct {
     int32_t timing;     /* 1: time every Arnoldi SpMV with HIP events on the
                            solve's stream (stats.spmv_ms / spmv_calls) */
     int32_t graph;      /* 1: replay the preconditioner as a HIP graph captured once per
-                           setup (same kernels, same results; fewer launches) */
+                           setup (same kernels, same results; fewer host launches, but
+                           two copies through the graph's fixed buffers per
+                           application); 0: launch the kernels directly */
 } bo_fgmres_opts;
 
-void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, CGS2, no timing, graph replay on */
+void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, CGS2, no timing, direct launches (graph 0) */
 
 typedef struct {
     int32_t iterations;     /* preconditioner applications */

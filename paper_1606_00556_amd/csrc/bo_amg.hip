@@ -1194,6 +1194,31 @@ __global__ void __launch_bounds__(kBlock) k_csr_rowop(int n, const int32_t *__re
     }
 }
 
+// the zero-guess l1-Jacobi sweep and the residual in one pass: x = b / d_l1
+// and r = b - A x, the neighbours' x_j formed from b_j and d_j as the sweep
+// forms them (same values, same summation as the two passes)
+template <int G, typename T>
+__global__ void __launch_bounds__(kBlock) k_csr_l1_resid(int n, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci, const T *__restrict__ v,
+                                                         const T *__restrict__ b, const T *__restrict__ dl1,
+                                                         T *__restrict__ x, T *__restrict__ r) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    int row = gid / G, sub = gid % G;
+    if (row >= n) return;  // whole groups leave together
+    T s = 0;
+#pragma unroll 4
+    for (int e = rp[row] + sub; e < rp[row + 1]; e += G) {
+        int j = ci[e];
+        s = s + v[e] * (b[j] / dl1[j]);
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) s = s + __shfl_xor(s, off, G);
+    if (sub != 0) return;
+    T bi = b[row];
+    x[row] = bi / dl1[row];
+    r[row] = bi - s;
+}
+
 // dense y = M x, one wavefront per row
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dense_mv(int n, const T *__restrict__ M, const T *__restrict__ x,
@@ -1249,6 +1274,25 @@ static bo_status csr_rowop(int n, int nnz, const int32_t *rp, const int32_t *ci,
     else if (avg <= 128.0) { BO_ROWOP(32); }
     else { BO_ROWOP(64); }
 #undef BO_ROWOP
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+// x = b / d_l1 and r = b - A x (k_csr_l1_resid), lanes per row as csr_rowop
+template <typename T>
+static bo_status csr_l1_resid(int n, int nnz, const int32_t *rp, const int32_t *ci, const T *v, const T *b,
+                              const T *dl1, T *x, T *r, hipStream_t s) {
+    double avg = n > 0 ? (double)nnz / n : 1.0;
+    long long threads;
+#define BO_L1R(G)                                                                                    \
+    threads = (long long)n * G;                                                                      \
+    k_csr_l1_resid<G, T><<<grid_for(threads), kBlock, 0, s>>>(n, rp, ci, v, b, dl1, x, r)
+    if (avg <= 8.0) { BO_L1R(4); }
+    else if (avg <= 16.0) { BO_L1R(8); }
+    else if (avg <= 64.0) { BO_L1R(16); }
+    else if (avg <= 128.0) { BO_L1R(32); }
+    else { BO_L1R(64); }
+#undef BO_L1R
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
@@ -1705,6 +1749,10 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t 
         BO_TRY(smooth0<T>(pc, b, x, true, true, s));
         k_resid_slots<T><<<grid_for(L.n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, Prec<T>::app(pc), b, x,
                                                            Prec<T>::r(L));
+    } else if (l1 && pc->o.sweeps == 1) {
+        // the one zero-guess sweep fused with the residual
+        x = Prec<T>::x(L);
+        BO_TRY(csr_l1_resid<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), b, Prec<T>::dl1(L), x, Prec<T>::r(L), s));
     } else {
         BO_TRY(smooth_c<T>(L, pc->o.sweeps, l1, b, nullptr, &x, s));
         BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), x, OP_RESID, b, nullptr, Prec<T>::r(L), s));

@@ -402,7 +402,8 @@ __global__ void __launch_bounds__(kBlock) k_multidot_partial(long long n, const 
 //   h != NULL, dots != 0: w -= sum_q h[q] V[q], then partial sums of <w, V[q]>
 //   h != NULL, dots == 0: w -= sum_q h[q] V[q], then the partial sum of <w, w>
 // The basis values of an element stay in registers between the update and
-// the dot products.
+// the dot products.  This form takes up to NV vectors (loads predicated on
+// nv) and any length; k_cgs_exact below is the one the solver normally runs.
 template <int NV>
 __global__ void __launch_bounds__(kBlock) k_cgs_pass(long long n, double *__restrict__ w, VecList V, int nv,
                                                      const double *__restrict__ h, int dots,
@@ -444,6 +445,64 @@ __global__ void __launch_bounds__(kBlock) k_cgs_pass(long long n, double *__rest
     }
     __syncthreads();
     if (threadIdx.x < nout) {
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < kBlock / 64; u++) t = t + sh[threadIdx.x][u];
+        partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// The same pass for exactly NV vectors below 4 GiB each, one kernel per mode
+// (0: dots, 1: update then dots, 2: update then norm): no predicated loads (a
+// load that only some paths issue makes the compiler wait for every load in
+// flight) and no branches in the loop; each load is a vector base in scalar
+// registers plus one 32-bit byte offset shared by all vectors, so addresses
+// cost no vector registers.  Same arithmetic order as k_cgs_pass.
+template <int NV, int MODE>
+__global__ void __launch_bounds__(kBlock) k_cgs_exact(uint32_t n, double *__restrict__ w, VecList V,
+                                                      const double *__restrict__ h, int rev,
+                                                      double *__restrict__ partial) {
+    constexpr bool upd = MODE != 0;
+    constexpr int NA = MODE == 2 ? 1 : NV;  // accumulators
+    __shared__ double hs[NV];
+    __shared__ double sh[NA][kBlock / 64];
+    if (upd && threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    auto at = [](const double *p, uint32_t boff) -> const double * {
+        return (const double *)((const char *)p + boff);
+    };
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; q++) acc[q] = 0.0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const uint32_t boff = (rev ? n - 1 - e : e) * (uint32_t)sizeof(double);
+        double we = *at(w, boff);
+        double vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) vq[q] = *at(V.p[q], boff);
+        if constexpr (upd) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NV; q++) s = s + hs[q] * vq[q];
+            we = we - s;
+            *(double *)at(w, boff) = we;
+        }
+        if constexpr (MODE == 2) {
+            acc[0] = acc[0] + we * we;
+        } else {
+#pragma unroll
+            for (int q = 0; q < NV; q++) acc[q] = acc[q] + we * vq[q];
+        }
+    }
+    int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+    for (int q = 0; q < NA; q++) {
+        double t = wave_sum(acc[q]);
+        if (lane == 0) sh[q][wave] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < NA) {
         double t = 0.0;
 #pragma unroll
         for (int u = 0; u < kBlock / 64; u++) t = t + sh[threadIdx.x][u];
@@ -593,21 +652,65 @@ bo_status Reducer::init() {
     return BO_OK;
 }
 
+// Workgroups of k_cgs_exact: as many as are resident at once, at most four
+// per compute unit (kRedBlocks on a full device), found once per kernel and
+// device; a fixed count per kernel keeps the partial sums' order fixed.
+constexpr int kCgsExactMax = 32;
+static int resident_blocks(const void *kernel, int slot) {
+    constexpr int kSlots = (kCgsExactMax + 1) * 4, kDevs = 16;
+    static int cache[kDevs][kSlots] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs) return kRedBlocks;
+    int &c = cache[dev][slot];
+    if (c == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
+            cus < 1)
+            c = kRedBlocks;
+        else
+            c = std::min(kRedBlocks, std::min(per_cu, 4) * cus);
+    }
+    return c;
+}
+
 bo_status Reducer::cgs_pass(long long n, double *w, const double *const *Vhost, int nv, const double *h, bool dots,
-                            double *out, hipStream_t s) {
+                            double *out, hipStream_t s, bool reverse) {
     if (nv < 1 || nv > kMaxVecList) return fail(BO_ERR_INVALID_ARG, "cgs_pass: 1..64 vectors");
     VecList L{};
     for (int q = 0; q < nv; q++) L.p[q] = Vhost[q];
-    if (nv <= 8)
-        k_cgs_pass<8><<<kRedBlocks, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
-    else if (nv <= 16)
-        k_cgs_pass<16><<<kRedBlocks, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
-    else if (nv <= 32)
-        k_cgs_pass<32><<<kRedBlocks, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
-    else
-        k_cgs_pass<64><<<kRedBlocks, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
+    // a fixed grid per vector count (the partial sums' order does not depend
+    // on the device), small enough to be resident at once
+    int nb = kRedBlocks;
+    if (nv <= kCgsExactMax && n < (1ll << 29)) {
+        const uint32_t n32 = (uint32_t)n;
+        const int mode = !h ? 0 : dots ? 1 : 2, rev = reverse ? 1 : 0;
+        switch (nv * 4 + mode) {
+#define BO_CGS1(K, M)                                                                  \
+    case K * 4 + M:                                                                    \
+        nb = resident_blocks((const void *)k_cgs_exact<K, M>, K * 4 + M);              \
+        k_cgs_exact<K, M><<<nb, kBlock, 0, s>>>(n32, w, L, h, rev, partial.p);              \
+        break;
+#define BO_CGS(K) BO_CGS1(K, 0) BO_CGS1(K, 1) BO_CGS1(K, 2)
+            BO_CGS(1) BO_CGS(2) BO_CGS(3) BO_CGS(4) BO_CGS(5) BO_CGS(6) BO_CGS(7) BO_CGS(8)
+            BO_CGS(9) BO_CGS(10) BO_CGS(11) BO_CGS(12) BO_CGS(13) BO_CGS(14) BO_CGS(15) BO_CGS(16)
+            BO_CGS(17) BO_CGS(18) BO_CGS(19) BO_CGS(20) BO_CGS(21) BO_CGS(22) BO_CGS(23) BO_CGS(24)
+            BO_CGS(25) BO_CGS(26) BO_CGS(27) BO_CGS(28) BO_CGS(29) BO_CGS(30) BO_CGS(31) BO_CGS(32)
+#undef BO_CGS
+#undef BO_CGS1
+        default: break;
+        }
+    } else if (nv <= 8) {
+        k_cgs_pass<8><<<nb, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
+    } else if (nv <= 16) {
+        k_cgs_pass<16><<<nb, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
+    } else if (nv <= 32) {
+        k_cgs_pass<32><<<nb, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
+    } else {
+        k_cgs_pass<64><<<nb, kBlock, 0, s>>>(n, w, L, nv, h, dots ? 1 : 0, partial.p);
+    }
     int nout = (dots || !h) ? nv : 1;
-    k_partial_final<<<nout, kBlock, 0, s>>>(kRedBlocks, partial.p, out);
+    k_partial_final<<<nout, kBlock, 0, s>>>(nb, partial.p, out);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }

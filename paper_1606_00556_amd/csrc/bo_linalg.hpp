@@ -44,9 +44,11 @@ struct Reducer {
     bo_status multidot(long long n, const double *x, const double *const *Vhost, int nv, double *out,
                        hipStream_t s);
     bo_status dot(long long n, const double *x, const double *y, double *out, hipStream_t s);
-    // one classical Gram-Schmidt pass (see k_cgs_pass); results land in out
+    // one classical Gram-Schmidt pass (see k_cgs_pass); results land in out.
+    // reverse: walk the elements from the end (a pass that starts where the
+    // previous one ended finds that part of the vectors still in cache)
     bo_status cgs_pass(long long n, double *w, const double *const *Vhost, int nv, const double *h, bool dots,
-                       double *out, hipStream_t s);
+                       double *out, hipStream_t s, bool reverse = false);
 };
 
 }  // namespace bo

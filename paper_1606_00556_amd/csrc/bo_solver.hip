@@ -188,7 +188,9 @@ extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
     o->rtol = 1e-6;
     o->orth = 1;
     o->timing = 0;
-    o->graph = 1;
+    // direct launches: the host enqueues one Arnoldi step ahead, and the
+    // replayed graph's copies in and out cost more than the launches it saves
+    o->graph = 0;
 }
 
 // grid == NULL: the general form (A kept as BSR; block-Jacobi F stage; the
@@ -518,8 +520,10 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
             int nv = j + 1;
             if (opts->orth == 1) {
                 // h1 = V^T w; w -= V h1 with h2 = V^T w; w -= V h2 with |w|^2
+                // (the middle pass walks backwards: each pass starts on the
+                // part of the basis the previous one left in cache)
                 BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, nullptr, true, hdp, s));
-                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, hdp, true, hdp + (m + 1), s));
+                BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, hdp, true, hdp + (m + 1), s, true));
                 BO_TRY(pc->red.cgs_pass(len, w, K.vptr.data(), nv, hdp + (m + 1), false, hdp + 2 * (m + 1), s));
             } else {
                 for (int i = 0; i < nv; i++) {
