@@ -49,6 +49,9 @@ def parse():
                     help="inner stages of the preconditioner: FP64, FP32, or FP32 with BF16 ILU factors")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
                     help="1: replay the preconditioner as a HIP graph; 0: launch its kernels directly (default)")
+    ap.add_argument("--orth", type=int, default=None, choices=(0, 1, 2),
+                    help="Gram-Schmidt form (default: the library's): 0 MGS, 1 CGS2, 2 CGS2 with the "
+                         "re-orthogonalisation delayed one step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -104,8 +107,11 @@ def main():
     else:
         grid = (c0.nx, c0.ny, c0.nz)
         copts = B.bo_cpr_default_opts(precision=prec)
-    fopts = B.bo_fgmres_default_opts(graph=args.graph)
-    fopts_timed = B.bo_fgmres_default_opts(timing=1, graph=args.graph)
+    fo = {"graph": args.graph}
+    if args.orth is not None:
+        fo["orth"] = args.orth
+    fopts = B.bo_fgmres_default_opts(**fo)
+    fopts_timed = B.bo_fgmres_default_opts(timing=1, **fo)
     torch.cuda.synchronize()
 
     # the preconditioner handle lives across systems, as in a Newton loop:

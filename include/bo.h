@@ -247,7 +247,11 @@ typedef struct {
     int32_t m;          /* restart length (1..64) */
     int32_t maxit;      /* preconditioner applications allowed */
     double rtol;        /* stop when ||b - A x|| <= rtol ||b|| (true residual) */
-    int32_t orth;       /* 0: modified Gram-Schmidt, 1: classical GS twice */
+    int32_t orth;       /* 0: modified Gram-Schmidt, 1: classical GS twice (CGS2),
+                           2: CGS2 with the second projection of each vector
+                           delayed to the next step (two passes over the basis
+                           per step instead of three; m <= 31; falls back to 1
+                           with a network attached or 2^29+ unknowns) */
     int32_t timing;     /* 1: time every Arnoldi SpMV with HIP events on the
                            solve's stream (stats.spmv_ms / spmv_calls) */
     int32_t graph;      /* 1: replay the preconditioner as a HIP graph captured once per
@@ -256,7 +260,7 @@ typedef struct {
                            application); 0: launch the kernels directly */
 } bo_fgmres_opts;
 
-void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, CGS2, no timing, direct launches (graph 0) */
+void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, delayed CGS2 (orth 2), no timing, direct launches (graph 0) */
 
 typedef struct {
     int32_t iterations;     /* preconditioner applications */

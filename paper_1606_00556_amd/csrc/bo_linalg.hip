@@ -510,6 +510,123 @@ __global__ void __launch_bounds__(kBlock) k_cgs_exact(uint32_t n, double *__rest
     }
 }
 
+// ---- Gram-Schmidt with the re-orthogonalisation delayed by one step ---------
+// (classical Gram-Schmidt twice, each vector's second projection taken in the
+// step after it was formed, so one step reads the basis twice, not three
+// times; Arnoldi step j has the final basis V[0..j), the pending vector
+// V[j] = u (w of the previous step after its first projection) and w = A z_j)
+//
+// Dots: against u and w, for every vector of [V[0..j), u] (NV = j + 1):
+// partial sums of <V[q], u> into rows q, of <V[q], w> into rows NV + q.
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_dcgs_dots(uint32_t n, VecList V, const double *__restrict__ w,
+                                                      double *__restrict__ partial) {
+    __shared__ double sh[2 * NV][kBlock / 64];
+    auto at = [](const double *p, uint32_t boff) -> const double * {
+        return (const double *)((const char *)p + boff);
+    };
+    double a1[NV], a2[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) a1[q] = a2[q] = 0.0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const uint32_t boff = e * (uint32_t)sizeof(double);
+        double we = *at(w, boff);
+        double vq[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) vq[q] = *at(V.p[q], boff);
+        const double u = vq[NV - 1];
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            a1[q] = a1[q] + vq[q] * u;
+            a2[q] = a2[q] + vq[q] * we;
+        }
+    }
+    int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        double t1 = wave_sum(a1[q]), t2 = wave_sum(a2[q]);
+        if (lane == 0) { sh[q][wave] = t1; sh[NV + q][wave] = t2; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int u = 0; u < kBlock / 64; u++) t = t + sh[threadIdx.x][u];
+        partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// Update for step J, from the dots red = [<V[i],u> (s_i), <u,u>, <V[i],w> (p_i),
+// <u,w>]: beta = sqrt(<u,u> - |s|^2) (the norm of u - V s), the final vector
+// v = (u - V s) / beta into V[J], r = <v,w> = (<u,w> - s.p) / beta, and
+// w - V p - r v into V[J+1] (the next pending vector) with partial sums of
+// its squared norm.  beta and r go to sc[0], sc[1] (workgroup 0); every
+// workgroup forms the same coefficients.  A pending vector inside the span of
+// the basis (beta^2 <= 0) leaves beta = 0 in sc[0] and zero vectors.
+template <int J>
+__global__ void __launch_bounds__(kBlock) k_dcgs_update(uint32_t n, VecList V, const double *__restrict__ red,
+                                                        double *__restrict__ sc, int rev,
+                                                        double *__restrict__ partial) {
+    __shared__ double cs[J > 0 ? J : 1], cp[J > 0 ? J : 1], cb[2];
+    __shared__ double sh[kBlock / 64];
+    if (threadIdx.x == 0) {
+        double ss = 0.0, sp = 0.0;
+        for (int i = 0; i < J; i++) {
+            ss = ss + red[i] * red[i];
+            sp = sp + red[i] * red[J + 1 + i];
+        }
+        double b2 = red[J] - ss, beta = 0.0, r = 0.0, ib = 0.0;
+        if (b2 > 0.0) {
+            beta = sqrt(b2);
+            ib = 1.0 / beta;
+            r = (red[2 * J + 1] - sp) / beta;
+        }
+        cb[0] = ib;
+        cb[1] = r;
+        if (blockIdx.x == 0) { sc[0] = beta; sc[1] = r; }
+    }
+    if (threadIdx.x < J) {
+        cs[threadIdx.x] = red[threadIdx.x];
+        cp[threadIdx.x] = red[J + 1 + threadIdx.x];
+    }
+    __syncthreads();
+    const double ib = cb[0], r = ib > 0.0 ? cb[1] : 0.0;
+    auto at = [](const double *p, uint32_t boff) -> double * {
+        return (double *)((const char *)p + boff);
+    };
+    double acc = 0.0;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const uint32_t boff = (rev ? n - 1 - e : e) * (uint32_t)sizeof(double);
+        double vq[J > 0 ? J : 1];
+#pragma unroll
+        for (int q = 0; q < J; q++) vq[q] = *at(V.p[q], boff);
+        double u = *at(V.p[J], boff), we = *at(V.p[J + 1], boff);
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < J; q++) {
+            s1 = s1 + cs[q] * vq[q];
+            s2 = s2 + cp[q] * vq[q];
+        }
+        double v = (u - s1) * ib;
+        double wn = we - s2 - r * v;
+        *at(V.p[J], boff) = v;
+        *at(V.p[J + 1], boff) = wn;
+        acc = acc + wn * wn;
+    }
+    int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    double t = wave_sum(acc);
+    if (lane == 0) sh[wave] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double u = 0.0;
+#pragma unroll
+        for (int k = 0; k < kBlock / 64; k++) u = u + sh[k];
+        partial[blockIdx.x] = u;
+    }
+}
+
 // pass 2 (one workgroup per result): out[q] = sum over the partials in a
 // fixed order (strided per thread, then across the wavefront, then across the
 // four wavefronts in order)
@@ -652,12 +769,14 @@ bo_status Reducer::init() {
     return BO_OK;
 }
 
-// Workgroups of k_cgs_exact: as many as are resident at once, at most four
-// per compute unit (kRedBlocks on a full device), found once per kernel and
-// device; a fixed count per kernel keeps the partial sums' order fixed.
+// Workgroups of the Gram-Schmidt kernels: as many as are resident at once, at
+// most four per compute unit (kRedBlocks on a full device), found once per
+// kernel and device; a fixed count per kernel keeps the partial sums' order
+// fixed.  Slots: k_cgs_exact<K, M> 4K + M, k_dcgs_dots<K> 4K + 3,
+// k_dcgs_update<K> 4(kCgsExactMax + 1) + K.
 constexpr int kCgsExactMax = 32;
 static int resident_blocks(const void *kernel, int slot) {
-    constexpr int kSlots = (kCgsExactMax + 1) * 4, kDevs = 16;
+    constexpr int kSlots = (kCgsExactMax + 1) * 5, kDevs = 16;
     static int cache[kDevs][kSlots] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs) return kRedBlocks;
@@ -734,6 +853,59 @@ bo_status Reducer::multidot(long long n, const double *x, const double *const *V
         launch_partial(c, n, x, L, partial.p, s);
         k_partial_final<<<c, kBlock, 0, s>>>(kRedBlocks, partial.p, out + q0);
     }
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status Reducer::dcgs_dots(long long n, const double *const *Vhost, int nv, const double *w, double *out,
+                             hipStream_t s) {
+    if (nv < 1 || nv > kCgsExactMax || n >= (1ll << 29))
+        return fail(BO_ERR_INVALID_ARG, "dcgs_dots: 1..32 vectors below 2^29 elements");
+    VecList L{};
+    for (int q = 0; q < nv; q++) L.p[q] = Vhost[q];
+    const uint32_t n32 = (uint32_t)n;
+    int nb = kRedBlocks;
+    switch (nv) {
+#define BO_D(K)                                                                   \
+    case K:                                                                       \
+        nb = resident_blocks((const void *)k_dcgs_dots<K>, 4 * K + 3);            \
+        k_dcgs_dots<K><<<nb, kBlock, 0, s>>>(n32, L, w, partial.p);               \
+        break;
+        BO_D(1) BO_D(2) BO_D(3) BO_D(4) BO_D(5) BO_D(6) BO_D(7) BO_D(8)
+        BO_D(9) BO_D(10) BO_D(11) BO_D(12) BO_D(13) BO_D(14) BO_D(15) BO_D(16)
+        BO_D(17) BO_D(18) BO_D(19) BO_D(20) BO_D(21) BO_D(22) BO_D(23) BO_D(24)
+        BO_D(25) BO_D(26) BO_D(27) BO_D(28) BO_D(29) BO_D(30) BO_D(31) BO_D(32)
+#undef BO_D
+    default: break;
+    }
+    k_partial_final<<<2 * nv, kBlock, 0, s>>>(nb, partial.p, out);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+bo_status Reducer::dcgs_update(long long n, const double *const *Vhost, int j, const double *red, double *sc,
+                               double *norm2, hipStream_t s, bool reverse) {
+    if (j < 0 || j + 1 > kCgsExactMax || n >= (1ll << 29))
+        return fail(BO_ERR_INVALID_ARG, "dcgs_update: step 0..31 below 2^29 elements");
+    VecList L{};
+    for (int q = 0; q < j + 2; q++) L.p[q] = Vhost[q];
+    const uint32_t n32 = (uint32_t)n;
+    const int rev = reverse ? 1 : 0;
+    int nb = kRedBlocks;
+    switch (j) {
+#define BO_U(K)                                                                     \
+    case K:                                                                         \
+        nb = resident_blocks((const void *)k_dcgs_update<K>, 4 * (kCgsExactMax + 1) + K);          \
+        k_dcgs_update<K><<<nb, kBlock, 0, s>>>(n32, L, red, sc, rev, partial.p);    \
+        break;
+        BO_U(0) BO_U(1) BO_U(2) BO_U(3) BO_U(4) BO_U(5) BO_U(6) BO_U(7)
+        BO_U(8) BO_U(9) BO_U(10) BO_U(11) BO_U(12) BO_U(13) BO_U(14) BO_U(15)
+        BO_U(16) BO_U(17) BO_U(18) BO_U(19) BO_U(20) BO_U(21) BO_U(22) BO_U(23)
+        BO_U(24) BO_U(25) BO_U(26) BO_U(27) BO_U(28) BO_U(29) BO_U(30) BO_U(31)
+#undef BO_U
+    default: break;
+    }
+    k_partial_final<<<1, kBlock, 0, s>>>(nb, partial.p, norm2);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }

@@ -49,6 +49,14 @@ struct Reducer {
     // previous one ended finds that part of the vectors still in cache)
     bo_status cgs_pass(long long n, double *w, const double *const *Vhost, int nv, const double *h, bool dots,
                        double *out, hipStream_t s, bool reverse = false);
+    // delayed re-orthogonalisation (k_dcgs_dots / k_dcgs_update): dots of
+    // [V[0..nv-1)] and the pending V[nv-1] with itself and w into out[0..2nv);
+    // the update of step j over Vhost[0..j+2) (final basis, pending vector,
+    // w) from those dots, beta and r into sc[0..1], |new pending|^2 into norm2
+    bo_status dcgs_dots(long long n, const double *const *Vhost, int nv, const double *w, double *out,
+                        hipStream_t s);
+    bo_status dcgs_update(long long n, const double *const *Vhost, int j, const double *red, double *sc,
+                          double *norm2, hipStream_t s, bool reverse);
 };
 
 }  // namespace bo

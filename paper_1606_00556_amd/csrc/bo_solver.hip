@@ -186,7 +186,9 @@ extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
     o->m = 30;
     o->maxit = 1500;
     o->rtol = 1e-6;
-    o->orth = 1;
+    // CGS2 with the second projection delayed one step: the same iterations
+    // as CGS2 with two passes over the basis per step instead of three
+    o->orth = 2;
     o->timing = 0;
     // direct launches: the host enqueues one Arnoldi step ahead, and the
     // replayed graph's copies in and out cost more than the launches it saves
@@ -432,7 +434,7 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     if (!pc || !b || !x || !opts) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: NULL argument");
     if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: the last bo_cpr_update failed");
     int m = opts->m;
-    if (m < 1 || m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || (opts->orth != 0 && opts->orth != 1) ||
+    if (m < 1 || m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || opts->orth < 0 || opts->orth > 2 ||
         (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1))
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
     hipStream_t s = (hipStream_t)stream;
@@ -454,6 +456,10 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     BO_TRY(krylov_alloc(pc, m));
     Krylov &K = pc->kr;
     const long long len = K.len;
+    // the delayed form needs at most 32 vectors per pass and 32-bit offsets,
+    // and a preconditioner that is linear (the network's correction is not
+    // applied to an unnormalised vector); otherwise CGS2
+    const int orth = opts->orth == 2 && (m > 31 || len >= (1ll << 29) || pc->nn) ? 1 : opts->orth;
     const Grid &g = pc->g;
     double *V = K.V.p, *Z = K.Z.p;
     // scalars of an Arnoldi step, two sets (steps j and j+1 may be in flight):
@@ -463,6 +469,7 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     double *hh = K.host;                // pinned copies
     double *yh = K.host + 2 * hs;       // pinned update coefficients
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1);
+    std::vector<double> Hr(orth == 2 ? (size_t)(m + 1) * m : 0, 0.0);  // delayed form: unrotated H
     auto fetch = [&](int count) -> bo_status {
         BO_HIP(hipMemcpyAsync(hh, hd, sizeof(double) * count, hipMemcpyDeviceToHost, s));
         BO_HIP(hipStreamSynchronize(s));
@@ -501,6 +508,8 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
         BO_TRY(axpby(len, 1.0 / beta, V, 0.0, V, s));
         std::fill(gv.begin(), gv.end(), 0.0);
         gv[0] = beta;
+        if (orth == 2) std::fill(Hr.begin(), Hr.end(), 0.0);
+        double g0 = beta;  // delayed form: |r| in the rescaled first basis vector
         int k = 0;
         // One Arnoldi step is enqueued as: preconditioner, SpMV, orthogonalisation
         // (scalars into set p = j % 2), normalisation of w on the device, an
@@ -518,7 +527,17 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
             BO_TRY(op_spmv(pc, 1.0, zj, 0.0, w, s));
             if (timed) BO_HIP(hipEventRecord(pc->ev[2 * p + 1], s));
             int nv = j + 1;
-            if (opts->orth == 1) {
+            if (orth == 2) {
+                // V[j] is pending: dots of [V[0..j), V[j]] with V[j] and w, then
+                // V[j] final, w after its first projection pending in V[j+1]
+                // (walked backwards: the dots pass left its end in cache)
+                BO_TRY(pc->red.dcgs_dots(len, K.vptr.data(), nv, w, hdp, s));
+                BO_TRY(pc->red.dcgs_update(len, K.vptr.data(), j, hdp, hdp + 2 * m, hdp + 2 * m + 2, s, true));
+                BO_HIP(hipMemcpyAsync(hh + p * hs, hdp, sizeof(double) * hs, hipMemcpyDeviceToHost, s));
+                BO_HIP(hipEventRecord(pc->evf[p], s));
+                return BO_OK;
+            }
+            if (orth == 1) {
                 // h1 = V^T w; w -= V h1 with h2 = V^T w; w -= V h2 with |w|^2
                 // (the middle pass walks backwards: each pass starts on the
                 // part of the basis the previous one left in cache)
@@ -553,6 +572,55 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
                 BO_HIP(hipEventElapsedTime(&ms, pc->ev[2 * p], pc->ev[2 * p + 1]));
                 st.spmv_ms += ms;
                 st.spmv_calls++;
+            }
+            if (orth == 2) {
+                // dots [s (j), <u,u>, p (j), <u,w>], beta and r at 2m, the new
+                // pending vector's |.|^2 at 2m+2
+                const int nv = j + 1;
+                const double beta_u = hq[2 * m], r = hq[2 * m + 1], hn = std::sqrt(hq[2 * m + 2]);
+                if (!std::isfinite(beta_u) || !std::isfinite(r) || !std::isfinite(hn)) {
+                    status = fail(BO_ERR_NONFINITE, "bo_fgmres_solve: NaN in the iteration");
+                    goto done;
+                }
+                if (!(beta_u > 0.0)) {
+                    // the pending vector lies in the span of the basis: the space
+                    // was invariant one step earlier
+                    k = j;
+                    break;
+                }
+                if (j == 0) {
+                    g0 = beta * beta_u;  // V[0] was rescaled by 1 / beta_u
+                } else {
+                    // the pending vector u = beta_u v_j + V s: column j-1 completed
+                    for (int i = 0; i < j; i++) Hr[(size_t)i * m + j - 1] += hq[i];
+                    Hr[(size_t)j * m + j - 1] = beta_u;
+                }
+                for (int i = 0; i < j; i++) Hr[(size_t)i * m + j] = hq[nv + i];
+                Hr[(size_t)j * m + j] = r;
+                Hr[(size_t)(j + 1) * m + j] = hn;
+                // Givens QR of columns 0..j from the start (column j-1 changed)
+                std::fill(gv.begin(), gv.end(), 0.0);
+                gv[0] = g0;
+                for (int c = 0; c <= j; c++) {
+                    for (int i = 0; i <= c + 1; i++) H[(size_t)i * m + c] = Hr[(size_t)i * m + c];
+                    for (int i = 0; i < c; i++) {
+                        double a = H[(size_t)i * m + c], bb = H[(size_t)(i + 1) * m + c];
+                        H[(size_t)i * m + c] = cs[i] * a + sn[i] * bb;
+                        H[(size_t)(i + 1) * m + c] = -sn[i] * a + cs[i] * bb;
+                    }
+                    double a = H[(size_t)c * m + c], bb = H[(size_t)(c + 1) * m + c];
+                    double den = std::hypot(a, bb);
+                    cs[c] = a / den;
+                    sn[c] = bb / den;
+                    H[(size_t)c * m + c] = cs[c] * a + sn[c] * bb;
+                    H[(size_t)(c + 1) * m + c] = 0.0;
+                    gv[c + 1] = -sn[c] * gv[c];
+                    gv[c] = cs[c] * gv[c];
+                }
+                k = j + 1;
+                st.est_residual = std::fabs(gv[j + 1]) / bnorm;
+                if (std::fabs(gv[j + 1]) <= tol || its >= opts->maxit || !(hn > 1e-300)) break;
+                continue;
             }
             double hn = std::sqrt(hq[2 * (m + 1)]);
             for (int i = 0; i <= j; i++)

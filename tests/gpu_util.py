@@ -84,14 +84,16 @@ def run_stage(B, gpc, fn, v, m):
     return to_host(out)
 
 
-def solve_both(B, O, case, **kw):
-    """FGMRES with the oracle and with the library; the GPU solution's true
-    residual is measured with the oracle's SpMV."""
+def solve_both(B, O, case, fopts=None, **kw):
+    """FGMRES with the oracle and with the library (fopts: its solver options,
+    default: the library's); the GPU solution's true residual is measured with
+    the oracle's SpMV."""
     import torch
     P, rp, ci, val, b, opc, gpc = setup_both(B, O, case, **kw)
     xo, oinfo = O.fgmres(rp, ci, val, b, opc)
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-    ginfo = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    ginfo = B.bo_fgmres_solve(gpc, to_dev(b), x, fopts) if fopts is not None else B.bo_fgmres_solve(
+        gpc, to_dev(b), x)
     xg = to_host(x)
     r = b - O.bsr_spmv(rp, ci, val, xg)
     return oinfo, ginfo, np.linalg.norm(r) / np.linalg.norm(b), xg, xo

@@ -185,6 +185,39 @@ def test_fgmres_converges_like_oracle(B, O, name):
     assert abs(ginfo["iterations"] - io) <= max(1, math.ceil(0.1 * io))
 
 
+@pytest.mark.parametrize("orth", [1, 2])
+@pytest.mark.parametrize("name", ["ragged", "cfg0"])
+def test_fgmres_gram_schmidt_forms(B, O, name, orth):
+    """CGS2 (orth 1) and CGS2 with each vector's second projection delayed one
+    step (orth 2, the default) build the same Krylov basis up to rounding: the
+    oracle's (CGS2) iteration count within 10 % and the true residual at the
+    tolerance."""
+    case = CASES[name]()
+    oinfo, ginfo, true_rel, xg, xo = solve_both(B, O, case, fopts=B.bo_fgmres_default_opts(orth=orth))
+    assert ginfo["converged"] and ginfo["status"] == B.BO_OK
+    assert true_rel <= 1e-6
+    assert ginfo["rel_residual"] == pytest.approx(true_rel, rel=1e-6, abs=1e-12)
+    io = oinfo["iterations"]
+    assert abs(ginfo["iterations"] - io) <= max(1, math.ceil(0.1 * io))
+
+
+def test_fgmres_delayed_small_restart(B, O):
+    """The delayed form across restarts (m = 3, m = 1) and when the iteration
+    limit ends a cycle early."""
+    import torch
+    case = ragged_case()
+    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
+    for m in (3, 1):
+        x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+        info = B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(m=m, orth=2))
+        assert info["converged"] and info["restarts"] >= 1
+        r = b - O.bsr_spmv(rp, ci, val, to_host(x))
+        assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+    x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+    info = B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(orth=2, maxit=2, rtol=1e-12))
+    assert info["status"] == B.BO_NOT_CONVERGED and info["iterations"] == 2
+
+
 def test_fgmres_mgs_option(B, O):
     import torch
     case = cg.make_case(0)
