@@ -189,8 +189,18 @@ __global__ void k_diag(int n, const int32_t *__restrict__ rp, const int32_t *__r
     dpos[i] = p;
     double d = p >= 0 ? v[p] : 0.0;
     if (d == 0.0 || !isfinite(d)) *bad = 1;
+    // l1 row sum in entry order, the loads of kB entries issued together
+    constexpr int kB = 8;
+    const int b = rp[i], e1 = rp[i + 1];
     double s = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; e++) s = s + fabs(v[e]);
+    for (int e0 = b; e0 < e1; e0 += kB) {
+        double vv[kB];
+#pragma unroll
+        for (int k = 0; k < kB; k++) vv[k] = v[min(e0 + k, e1 - 1)];
+#pragma unroll
+        for (int k = 0; k < kB; k++)
+            if (e0 + k < e1) s = s + fabs(vv[k]);
+    }
     dl1[i] = s;
 }
 
@@ -352,10 +362,28 @@ __global__ void k_agg1(int n, const int32_t *__restrict__ rp, const int32_t *__r
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int a = -1;
-    if (state[i] == IN) a = id[i];
-    else
-        for (int e = rp[i]; e < rp[i + 1]; e++)
-            if (sf[e] && state[ci[e]] == IN) a = id[ci[e]];
+    if (state[i] == IN) {
+        a = id[i];
+    } else {
+        // entry order (the last strong root neighbour wins), kB entries'
+        // loads at a time
+        constexpr int kB = 8;
+        const int b = rp[i], e1 = rp[i + 1];
+        for (int e0 = b; e0 < e1; e0 += kB) {
+            int cc[kB], ss[kB], st[kB], idv[kB];
+#pragma unroll
+            for (int k = 0; k < kB; k++) {
+                const int e = min(e0 + k, e1 - 1);
+                cc[k] = ci[e];
+                ss[k] = sf[e];
+            }
+#pragma unroll
+            for (int k = 0; k < kB; k++) { st[k] = state[cc[k]]; idv[k] = id[cc[k]]; }
+#pragma unroll
+            for (int k = 0; k < kB; k++)
+                if (e0 + k < e1 && ss[k] && st[k] == IN) a = idv[k];
+        }
+    }
     a1[i] = a;
 }
 
@@ -370,11 +398,24 @@ __global__ void k_agg2(int n, const int32_t *__restrict__ rp, const int32_t *__r
     if (a < 0 && state[i] != ISO) {
         int best = -1;
         double bv = -1.0;
-        for (int e = rp[i]; e < rp[i + 1]; e++) {
-            int j = ci[e];
-            if (!sf[e] || a1[j] < 0) continue;
-            double x = fabs(v[e]);
-            if (x > bv || (x == bv && a1[j] < best)) { bv = x; best = a1[j]; }
+        constexpr int kB = 8;
+        const int b = rp[i], e1 = rp[i + 1];
+        for (int e0 = b; e0 < e1; e0 += kB) {
+            int ss[kB], aj[kB];
+            double vv[kB];
+#pragma unroll
+            for (int k = 0; k < kB; k++) {
+                const int e = min(e0 + k, e1 - 1);
+                ss[k] = sf[e];
+                aj[k] = a1[ci[e]];
+                vv[k] = v[e];
+            }
+#pragma unroll
+            for (int k = 0; k < kB; k++) {
+                if (e0 + k >= e1 || !ss[k] || aj[k] < 0) continue;
+                double x = fabs(vv[k]);
+                if (x > bv || (x == bv && aj[k] < best)) { bv = x; best = aj[k]; }
+            }
         }
         a = best;
         if (a < 0) *bad = 1;
@@ -384,31 +425,74 @@ __global__ void k_agg2(int n, const int32_t *__restrict__ rp, const int32_t *__r
 
 // filtered diagonal and the Gershgorin ratio of D_F^{-1} A_F (max via the
 // order-preserving bit pattern of non-negative doubles)
-__global__ void k_filter(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                         const double *__restrict__ v, const int32_t *__restrict__ dpos,
-                         const uint8_t *__restrict__ sf, double *__restrict__ aF,
-                         unsigned long long *__restrict__ rho_bits) {
+// Reductions of one value over a launch (a maximum or a count) go through
+// kRedSlots words: one atomic per workgroup, on word blockIdx % kRedSlots.
+// Atomics on one word from every wavefront of a large launch serialise (about
+// 12 ns each on the device), which made such a reduction cost more than the
+// kernel's own work; the reader combines the words.
+constexpr int kRedSlots = 64;
+__device__ __forceinline__ void block_max_to_slots(uint64_t v, unsigned long long *slots) {
+    __shared__ uint64_t wm[kBlock / 64];
+    v = group_max<64>(v);
+    if (threadIdx.x % 64 == 0) wm[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t m = wm[0];
+        for (int w = 1; w < (int)(blockDim.x / 64); w++) m = wm[w] > m ? wm[w] : m;
+        if (m > 0) atomicMax(&slots[blockIdx.x % kRedSlots], (unsigned long long)m);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_filter(int n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                   const int32_t *__restrict__ dpos, const uint8_t *__restrict__ sf,
+                                                   double *__restrict__ aF, unsigned long long *__restrict__ rho_bits) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t bits = 0;
     if (i < n) {
+        // the row in batches of kB entries: every load of a batch is issued
+        // before the sums, which still run in entry order; the row's values
+        // stay in registers for the second sum only as one batch, so it
+        // reloads them (cache hits)
+        constexpr int kB = 8;
+        const int b = rp[i], e1 = rp[i + 1];
         double aii = v[dpos[i]];
         double d = aii;
-        for (int e = rp[i]; e < rp[i + 1]; e++)
-            if (ci[e] != i && !sf[e]) d = d + v[e];
+        for (int e0 = b; e0 < e1; e0 += kB) {
+            int cc[kB], ss[kB];
+            double vv[kB];
+#pragma unroll
+            for (int k = 0; k < kB; k++) {
+                const int e = min(e0 + k, e1 - 1);  // rows are never empty (diagonal)
+                cc[k] = ci[e]; ss[k] = sf[e]; vv[k] = v[e];
+            }
+#pragma unroll
+            for (int k = 0; k < kB; k++)
+                if (e0 + k < e1 && cc[k] != i && !ss[k]) d = d + vv[k];
+        }
         if (d == 0.0) d = aii;
         aF[i] = d;
         double rs = 0.0;
-        for (int e = rp[i]; e < rp[i + 1]; e++) {
-            if (ci[e] == i) rs = rs + fabs(d);
-            else if (sf[e]) rs = rs + fabs(v[e]);
+        for (int e0 = b; e0 < e1; e0 += kB) {
+            int cc[kB], ss[kB];
+            double vv[kB];
+#pragma unroll
+            for (int k = 0; k < kB; k++) {
+                const int e = min(e0 + k, e1 - 1);
+                cc[k] = ci[e]; ss[k] = sf[e]; vv[k] = v[e];
+            }
+#pragma unroll
+            for (int k = 0; k < kB; k++) {
+                if (e0 + k >= e1) continue;
+                if (cc[k] == i) rs = rs + fabs(d);
+                else if (ss[k]) rs = rs + fabs(vv[k]);
+            }
         }
         double ratio = rs / fabs(d);
         bits = (uint64_t)__double_as_longlong(ratio);
     }
-    // the ratios are >= 0, so their bit patterns order as the values; one
-    // atomic per wavefront
-    bits = group_max<64>(bits);
-    if (threadIdx.x % 64 == 0) atomicMax(rho_bits, (unsigned long long)bits);
+    // the ratios are >= 0, so their bit patterns order as the values
+    block_max_to_slots(bits, rho_bits);
 }
 
 __device__ __forceinline__ bool p_takes(int e, int i, const int32_t *ci, const uint8_t *sf, const int32_t *agg) {
@@ -422,12 +506,22 @@ constexpr int KP = 16;  // register fast path for rows of up to KP entries
 
 __global__ void k_p_count(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                           const uint8_t *__restrict__ sf, const int32_t *__restrict__ agg,
-                          int32_t *__restrict__ cnt) {
+                          int32_t *__restrict__ cnt, int32_t *__restrict__ plong) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int len = rp[i + 1] - rp[i];
+    int len = i < n ? rp[i + 1] - rp[i] : 0;
+    // rows longer than KP go to plong[1..] (count in plong[0]) for k_p_long /
+    // k_p_vlong: one atomic per wavefront, each lane at its rank among them
+    const bool lng = len > KP;
+    const uint64_t m = __ballot(lng);
+    if (m) {
+        const int lane = threadIdx.x % 64;
+        int base = 0;
+        if (lane == __ffsll((unsigned long long)m) - 1) base = atomicAdd(plong, __popcll(m));
+        base = __shfl(base, __ffsll((unsigned long long)m) - 1, 64);
+        if (lng) plong[1 + base + __popcll(m & ((1ull << lane) - 1))] = i;
+    }
+    if (i >= n || lng) return;
     int c = 0;
-    if (len > KP) return;  // long rows: k_p_long
     {
         int J[KP];
 #pragma unroll
@@ -516,16 +610,21 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_long(int n, const int32_t *_
                                                           const double *__restrict__ aF, const double *__restrict__ omega,
                                                           const int32_t *__restrict__ prp, int32_t *__restrict__ pci,
                                                           double *__restrict__ pv, int32_t *__restrict__ cnt,
-                                                          int32_t *__restrict__ bad) {
+                                                          int32_t *__restrict__ bad,
+                                                          const int32_t *__restrict__ plong) {
     __shared__ int J[kPWaves][KW];
     __shared__ double A[kPWaves][KW];
     __shared__ uint8_t first[kPWaves][KW];
     int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    int i = blockIdx.x * kPWaves + wave;
-    if (i >= n) return;
+    // the rows k_p_count listed, a wavefront each, over a fixed grid
+    const int nl = plong[0];
+    for (int idx = blockIdx.x * kPWaves + wave; idx < nl; idx += gridDim.x * kPWaves) {
+    const int i = plong[1 + idx];
     int b = rp[i], len = rp[i + 1] - b;
-    if (len <= KP) return;  // handled by the register path
-    if (len > KW) return;   // handled by k_p_vlong
+    if (len > KW) continue;  // handled by k_p_vlong
+    // the previous row's LDS reads are done before this row's writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
     for (int q = lane; q < len; q += 64) {
         int e = b + q;
         bool take = p_takes(e, i, ci, sf, agg);
@@ -548,7 +647,7 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_long(int n, const int32_t *_
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) mycount += __shfl_xor(mycount, off, 64);
         if (lane == 0) cnt[i] = mycount;
-        return;
+        continue;
     }
     double d = omega[0] / aF[i];
     int ai = agg[i];
@@ -565,6 +664,7 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_long(int n, const int32_t *_
         pci[prp[i] + rank] = Jq;
         pv[prp[i] + rank] = (ai == Jq ? 1.0 : 0.0) - d * sum;
     }
+    }
 }
 
 // The same for the rare rows longer than the LDS staging (a well row and its
@@ -577,12 +677,14 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_vlong(int n, const int32_t *
                                                            const int32_t *__restrict__ agg,
                                                            const double *__restrict__ aF, const double *__restrict__ omega,
                                                            const int32_t *__restrict__ prp, int32_t *__restrict__ pci,
-                                                           double *__restrict__ pv, int32_t *__restrict__ cnt) {
+                                                           double *__restrict__ pv, int32_t *__restrict__ cnt,
+                                                           const int32_t *__restrict__ plong) {
     int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    int i = blockIdx.x * kPWaves + wave;
-    if (i >= n) return;
+    const int nl = plong[0];
+    for (int idx = blockIdx.x * kPWaves + wave; idx < nl; idx += gridDim.x * kPWaves) {
+    const int i = plong[1 + idx];
     int b = rp[i], len = rp[i + 1] - b;
-    if (len <= KW) return;
+    if (len <= KW) continue;
     auto jof = [&](int q) -> int { int e = b + q; return p_takes(e, i, ci, sf, agg) ? agg[ci[e]] : -1; };
     auto aof = [&](int q) -> double {
         int e = b + q;
@@ -600,7 +702,7 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_vlong(int n, const int32_t *
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) mycount += __shfl_xor(mycount, off, 64);
         if (lane == 0) cnt[i] = mycount;
-        return;
+        continue;
     }
     double d = omega[0] / aF[i];
     int ai = agg[i];
@@ -616,6 +718,7 @@ __global__ void __launch_bounds__(64 * kPWaves) k_p_vlong(int n, const int32_t *
         }
         pci[prp[i] + rank] = Jq;
         pv[prp[i] + rank] = (ai == Jq ? 1.0 : 0.0) - d * sum;
+    }
     }
 }
 
@@ -677,27 +780,46 @@ __global__ void __launch_bounds__(kBlock) k_sort_rows(int n, const int32_t *__re
 // accumulated in ascending k exactly as in a row-by-row Gustavson product.
 // The distinct columns are then compacted, ranked (sorted) and written.
 
-// products of each row (sum of the B row lengths it touches), their maximum
-// (stat[0]) and the number of rows above kLongProducts (stat[1])
+// products of each row (sum of the B row lengths it touches); their maximum
+// and the number of rows above kLongProducts go to the reduction words
+// stat[0..kRedSlots) and stat[kRedSlots..2 kRedSlots)
 constexpr int kLongProducts = 128;
-__global__ void k_spgemm_bound(int n, const int32_t *__restrict__ arp, const int32_t *__restrict__ aci,
-                               const int32_t *__restrict__ brp, int32_t *__restrict__ prod,
-                               int32_t *__restrict__ stat) {
+__global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *__restrict__ arp,
+                                                         const int32_t *__restrict__ aci,
+                                                         const int32_t *__restrict__ brp, int32_t *__restrict__ prod,
+                                                         int32_t *__restrict__ stat) {
+    __shared__ int wmax[kBlock / 64], wlng[kBlock / 64];
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int c = 0;
     if (i < n) {
-        for (int e = arp[i]; e < arp[i + 1]; e++) c += brp[aci[e] + 1] - brp[aci[e]];
+        // batches of kB entries, all loads of a batch issued together
+        constexpr int kB = 8;
+        const int a0 = arp[i], a1 = arp[i + 1];
+        for (int e0 = a0; e0 < a1; e0 += kB) {
+            int kk[kB];
+#pragma unroll
+            for (int k = 0; k < kB; k++) kk[k] = aci[min(e0 + k, a1 - 1)];
+            int lo[kB], hi[kB];
+#pragma unroll
+            for (int k = 0; k < kB; k++) { lo[k] = brp[kk[k]]; hi[k] = brp[kk[k] + 1]; }
+#pragma unroll
+            for (int k = 0; k < kB; k++)
+                if (e0 + k < a1) c += hi[k] - lo[k];
+        }
         prod[i] = c;
     }
     int lng = c > kLongProducts ? 1 : 0;
-    // one atomic of each kind per wavefront
     for (int off = 32; off > 0; off >>= 1) {
         c = max(c, __shfl_xor(c, off, 64));
         lng += __shfl_xor(lng, off, 64);
     }
-    if (threadIdx.x % 64 == 0) {
-        if (c > 0) atomicMax(&stat[0], c);
-        if (lng > 0) atomicAdd(&stat[1], lng);
+    if (threadIdx.x % 64 == 0) { wmax[threadIdx.x / 64] = c; wlng[threadIdx.x / 64] = lng; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0, l = 0;
+        for (int w = 0; w < (int)(blockDim.x / 64); w++) { m = max(m, wmax[w]); l += wlng[w]; }
+        if (m > 0) atomicMax(&stat[blockIdx.x % kRedSlots], m);
+        if (l > 0) atomicAdd(&stat[kRedSlots + blockIdx.x % kRedSlots], l);
     }
 }
 
@@ -1372,8 +1494,11 @@ static bo_status level_diag(Level &L, int32_t *dflag, hipStream_t s) {
 
 // smoother weight of the prolongator, (4/3)/rho, on the device
 __global__ void k_omega(const unsigned long long *__restrict__ rho_bits, double *__restrict__ omega,
-                        int32_t *__restrict__ bad) {
-    double rho = __longlong_as_double((long long)rho_bits[0]);
+                        int32_t *__restrict__ bad, int32_t *__restrict__ plong) {
+    plong[0] = 0;  // the long-row list of the prolongator, filled next
+    unsigned long long rb = 0;
+    for (int q = 0; q < kRedSlots; q++) rb = rho_bits[q] > rb ? rho_bits[q] : rb;
+    double rho = __longlong_as_double((long long)rb);
     if (!(rho > 0.0) || !(rho < INFINITY)) {
         *bad = 1;
         *omega = 0.0;
@@ -1393,14 +1518,21 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     BO_TRY(cnt.alloc(n));
     BO_TRY(crp.alloc(n + 1));
     BO_TRY(W.sg_prod.alloc(n));
-    BO_TRY(W.sg_stat.alloc(4));
-    BO_HIP(hipMemsetAsync(W.sg_stat.p, 0, sizeof(int32_t) * 4, s));
+    // [0, 2 kRedSlots): reduction words of the product bound and the long-row
+    // count, then the long-row list position and the largest distinct count
+    constexpr int kPos = 2 * kRedSlots, kMaxl = 2 * kRedSlots + 1;
+    BO_TRY(W.sg_stat.alloc(kMaxl + 1));
+    BO_HIP(hipMemsetAsync(W.sg_stat.p, 0, sizeof(int32_t) * (kMaxl + 1), s));
     BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
     k_spgemm_bound<<<grid_for(n), kBlock, 0, s>>>(n, arp, aci, brp, W.sg_prod.p, W.sg_stat.p);
-    int32_t stat[2] = {0, 0};
+    int32_t stat[2 * kRedSlots] = {};
     HostRead rd{W.sg_stat.p, sizeof stat, stat};
     BO_TRY(host_reads(&rd, 1, s));
-    const int bound = stat[0], nlong = stat[1];
+    int bound = 0, nlong = 0;
+    for (int q = 0; q < kRedSlots; q++) {
+        bound = std::max(bound, stat[q]);
+        nlong += stat[kRedSlots + q];
+    }
     // counting pass: lanes per row and hash slots from the row's products
     auto pick = [](int b) { return b <= 32 ? 0 : b <= 64 ? 4 : b <= 128 ? 1 : b <= 512 ? 2 : 3; };
     auto count_slots = [](int sel) { return sel == 0 ? 64 : sel == 4 ? 128 : sel == 1 ? 256 : sel == 2 ? 1024 : 2048; };
@@ -1410,14 +1542,14 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     const int32_t *prod = split ? W.sg_prod.p : nullptr;
     if (split) {
         BO_TRY(W.sg_rows.alloc(nlong));
-        k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, W.sg_prod.p, W.sg_rows.p, W.sg_stat.p + 2);
+        k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, W.sg_prod.p, W.sg_rows.p, W.sg_stat.p + kPos);
     }
     auto count = [&](int sel, int rn, const int32_t *rows, const int32_t *pr) {
         if (rn <= 0) return;
 #define BO_SPGEMM_COUNT(G, H)                                                                                 \
     k_spgemm<G, H, false><<<grid_for((long long)rn * G), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, cnt.p, \
                                                                       nullptr, nullptr, nullptr, flag, rows,  \
-                                                                      pr, W.sg_stat.p + 3)
+                                                                      pr, W.sg_stat.p + kMaxl)
         switch (sel) {
         case 0: BO_SPGEMM_COUNT(8, 64); break;
         case 4: BO_SPGEMM_COUNT(8, 128); break;
@@ -1431,7 +1563,7 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     if (split) count(sel_long, nlong, W.sg_rows.p, nullptr);
     BO_HIP(hipGetLastError());
     int32_t bad = 0, total = 0, lmax = 0;
-    HostRead ex[2] = {{flag, sizeof bad, &bad}, {W.sg_stat.p + 3, sizeof lmax, &lmax}};
+    HostRead ex[2] = {{flag, sizeof bad, &bad}, {W.sg_stat.p + kMaxl, sizeof lmax, &lmax}};
     BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s, ex, 2));
     if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: Galerkin product row exceeds the LDS hash capacity");
     BO_TRY(cci.alloc(total));
@@ -1447,7 +1579,7 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
 #define BO_SPGEMM_NUM(GG, H)                                                                                    \
     k_spgemm<GG, H, true><<<grid_for((long long)rn * GG), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, nullptr, \
                                                                        crp.p, cci.p, cv.p, flag, rows, pr,     \
-                                                                       W.sg_stat.p + 3)
+                                                                       W.sg_stat.p + kMaxl)
         if (G == 8) {
             if (h <= 64) BO_SPGEMM_NUM(8, 64); else BO_SPGEMM_NUM(8, 128);
         } else if (G == 16) {
@@ -1570,18 +1702,20 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         // prolongator
         DBuf<double> &aF = W.aF;
         DBuf<unsigned long long> &rho = W.rho;
-        BO_TRY(aF.alloc(n)); BO_TRY(rho.alloc(1));
-        BO_HIP(hipMemsetAsync(rho.p, 0, sizeof(unsigned long long), s));
+        BO_TRY(aF.alloc(n)); BO_TRY(rho.alloc(kRedSlots));
+        BO_HIP(hipMemsetAsync(rho.p, 0, sizeof(unsigned long long) * kRedSlots, s));
         k_filter<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.diagpos.p, L.sf.p, aF.p, rho.p);
         const double *omega = W.omg.p + l;
-        k_omega<<<1, 1, 0, s>>>(rho.p, W.omg.p + l, W.dfl.p + 2);
+        BO_TRY(W.plong.alloc(n + 1));
+        k_omega<<<1, 1, 0, s>>>(rho.p, W.omg.p + l, W.dfl.p + 2, W.plong.p);
         BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
-        k_p_count<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, L.agg.p, cnt.p);
-        k_p_long<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
-                                                                       aF.p, omega, nullptr, nullptr, nullptr,
-                                                                       cnt.p, flag);
-        k_p_vlong<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
-                                                                        aF.p, omega, nullptr, nullptr, nullptr, cnt.p);
+        k_p_count<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, L.agg.p, cnt.p, W.plong.p);
+        // the listed long rows, a wavefront each up to 65536 of them
+        const unsigned pgrid = (unsigned)std::min<long long>((n + kPWaves - 1) / kPWaves, 16384);
+        k_p_long<<<pgrid, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega, nullptr,
+                                                nullptr, nullptr, cnt.p, flag, W.plong.p);
+        k_p_vlong<<<pgrid, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega, nullptr,
+                                                 nullptr, nullptr, cnt.p, W.plong.p);
         BO_TRY(L.prp.alloc(n + 1));
         int32_t pnnz = 0;
         BO_TRY(scan_counts(cnt.p, L.prp.p, n, &pnnz, s));
@@ -1589,12 +1723,10 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         BO_TRY(L.pci.alloc(pnnz)); BO_TRY(L.pv.alloc(pnnz));
         k_p_fill<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega,
                                                 L.prp.p, L.pci.p, L.pv.p);
-        k_p_long<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
-                                                                       aF.p, omega, L.prp.p, L.pci.p, L.pv.p,
-                                                                       nullptr, flag);
-        k_p_vlong<<<(n + kPWaves - 1) / kPWaves, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p,
-                                                                        aF.p, omega, L.prp.p, L.pci.p, L.pv.p,
-                                                                        nullptr);
+        k_p_long<<<pgrid, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega, L.prp.p,
+                                                L.pci.p, L.pv.p, nullptr, flag, W.plong.p);
+        k_p_vlong<<<pgrid, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega, L.prp.p,
+                                                 L.pci.p, L.pv.p, nullptr, W.plong.p);
         BO_HIP(hipGetLastError());
         // R = P^T
         DBuf<int32_t> &rc = W.rc, &fp = W.fp;

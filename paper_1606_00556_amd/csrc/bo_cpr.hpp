@@ -40,7 +40,8 @@ struct SetupWork {
     DBuf<double> omg;             // smoother weight of each level
     DBuf<int32_t> aprp, apci;
     DBuf<double> apv, dense;
-    DBuf<int32_t> sg_prod, sg_rows, sg_stat;  // sparse product: products per row, long rows, [max, #long]
+    DBuf<int32_t> sg_prod, sg_rows, sg_stat;  // sparse product: products per row, long rows, reduction words
+    DBuf<int32_t> plong;          // prolongator rows longer than the register path: [count, rows...]
 };
 
 struct Krylov {

@@ -119,7 +119,8 @@ def test_backward_matches_oracle_and_adam(B):
 
 def test_zero_network_changes_nothing(B, O):
     """A network whose last layer is zero predicts c = 0, the judge never keeps
-    it, and the solve is bit for bit the plain CPR solve."""
+    it, and the solve is bit for bit the plain CPR solve (both with CGS2, the
+    form the solver takes with a network attached)."""
     import torch
     case = ragged_case()
     P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
@@ -131,7 +132,7 @@ def test_zero_network_changes_nothing(B, O):
         if attach:
             B.bo_cpr_attach_nn(gpc, nn, to_dev(np.log(case.kx)))
         x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x))
+        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(orth=1)))
         xs.append(to_host(x))
     assert infos[0]["iterations"] == infos[1]["iterations"]
     assert infos[1]["nn_used"] == 0
