@@ -125,13 +125,29 @@ __host__ __device__ inline bool inv3_gj(const double *A, double *Ainv) {
             if (a > amax) amax = a;
         }
     if (!(amax > 0.0) || !(amax < INFINITY)) return false;
+    // every index below is a compile-time constant once the loops unroll (the
+    // pivot row is chosen by selects, not by indexing), so M stays in
+    // registers on the GPU
+#pragma unroll
     for (int k = 0; k < 3; k++) {
         int piv = k;
-        for (int r = k + 1; r < 3; r++)
-            if (fabs(M[r][k]) > fabs(M[piv][k])) piv = r;
-        if (fabs(M[piv][k]) <= 1e-300 * amax) return false;
-        if (piv != k)
-            for (int c = 0; c < 6; c++) { double t = M[k][c]; M[k][c] = M[piv][c]; M[piv][c] = t; }
+        double best = fabs(M[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < 3; r++) {
+            double a = fabs(M[r][k]);
+            if (a > best) { best = a; piv = r; }
+        }
+        if (best <= 1e-300 * amax) return false;
+#pragma unroll
+        for (int r = k + 1; r < 3; r++) {
+            const bool sw = piv == r;
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                double t = M[k][c];
+                M[k][c] = sw ? M[r][c] : t;
+                M[r][c] = sw ? t : M[r][c];
+            }
+        }
         double d = M[k][k];
         for (int c = 0; c < 6; c++) M[k][c] = M[k][c] / d;
         for (int r = 0; r < 3; r++) {

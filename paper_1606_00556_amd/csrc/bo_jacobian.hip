@@ -218,16 +218,25 @@ __global__ void __launch_bounds__(kBlock) k_jac_cells(GridG G, Fl f, const doubl
     const double gg = f.gravity ? f.grav : 0.0;
     const int row_of[4] = {0, 1, 2, 2};
     const int phase_of[4] = {0, 1, 2, 0};
-    // faces in the order the lower-cell face loop visits them
+    // Faces in ascending column order (-z -y -x, then +x +y +z); each face's
+    // off-diagonal block is written as soon as it is complete, the diagonal
+    // (which every face adds to) at the end.  The loops unroll fully, so no
+    // block is indexed at run time and nothing spills to scratch memory.
     const int order[6] = {S_MZ, S_MY, S_MX, S_PX, S_PY, S_PZ};
-    double Joff[6][9];
-    int nb_of[6];
+    const int e0 = rowptr[g];
+    int nlow = 0;
+#pragma unroll
+    for (int q = 0; q < 3; q++) nlow += nbr_of(g, order[q], G.nx, G.ny, G.nz) >= 0;
+    const int ediag = e0 + nlow;
+    int elo = e0, ehi = ediag + 1;
+#pragma unroll
     for (int q = 0; q < 6; q++) {
-        int s = order[q];
-        int nb = nbr_of(g, s, G.nx, G.ny, G.nz);
-        nb_of[q] = nb;
-        for (int z = 0; z < 9; z++) Joff[q][z] = 0.0;
+        const int s = order[q];
+        const int nb = nbr_of(g, s, G.nx, G.ny, G.nz);
         if (nb < 0) continue;
+        double Joff[9];
+#pragma unroll
+        for (int z = 0; z < 9; z++) Joff[z] = 0.0;
         Props cn;
         props_of(f, G.phi0[nb], xn + 3 * (size_t)nb, cn);
         bool g_low = g < nb;
@@ -236,8 +245,9 @@ __global__ void __launch_bounds__(kBlock) k_jac_cells(GridG G, Fl f, const doubl
         const Props &ch = g_low ? cn : c;
         double T = trans(G, f, l, h);
         double ddep = depth_of(G, l) - depth_of(G, h);
+#pragma unroll
         for (int st = 0; st < 4; st++) {
-            int ph = phase_of[st], row = row_of[st];
+            const int ph = phase_of[st], row = row_of[st];
             double rl, drl, rh, drh;
             density(cl, ph, rl, drl);
             density(ch, ph, rh, drh);
@@ -259,16 +269,20 @@ __global__ void __launch_bounds__(kBlock) k_jac_cells(GridG G, Fl f, const doubl
                 R[row] = R[row] + F;
                 for (int k = 0; k < 3; k++) {
                     Jd[3 * row + k] = Jd[3 * row + k] + dFl[k];
-                    Joff[q][3 * row + k] = Joff[q][3 * row + k] + dFh[k];
+                    Joff[3 * row + k] = Joff[3 * row + k] + dFh[k];
                 }
             } else {
                 R[row] = R[row] - F;
                 for (int k = 0; k < 3; k++) {
-                    Joff[q][3 * row + k] = Joff[q][3 * row + k] - dFl[k];
+                    Joff[3 * row + k] = Joff[3 * row + k] - dFl[k];
                     Jd[3 * row + k] = Jd[3 * row + k] - dFh[k];
                 }
             }
         }
+        const int e = q < 3 ? elo++ : ehi++;
+        colind[e] = nb;
+#pragma unroll
+        for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Joff[z];
     }
     // fracture-matrix transfer (this cell is the lower index)
     double Jm[9];
@@ -297,24 +311,11 @@ __global__ void __launch_bounds__(kBlock) k_jac_cells(GridG G, Fl f, const doubl
             }
         }
     }
-    // write the block row in ascending column order: -z -y -x diag +x +y +z
-    // (matrix cell) (well)
-    int e = rowptr[g];
-    for (int q = 0; q < 3; q++) {
-        if (nb_of[q] < 0) continue;
-        colind[e] = nb_of[q];
-        for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Joff[q][z];
-        e++;
-    }
-    colind[e] = g;
-    for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Jd[z];
-    e++;
-    for (int q = 3; q < 6; q++) {
-        if (nb_of[q] < 0) continue;
-        colind[e] = nb_of[q];
-        for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Joff[q][z];
-        e++;
-    }
+    // the diagonal block between the lower and upper faces, then (matrix
+    // cell) (well) after the upper faces
+    colind[ediag] = g;
+    for (int z = 0; z < 9; z++) val[9 * (size_t)ediag + z] = Jd[z];
+    const int e = ehi;
     if (G.dual) {
         colind[e] = n + g;
         for (int z = 0; z < 9; z++) val[9 * (size_t)e + z] = Jm[z];
@@ -411,7 +412,9 @@ __global__ void k_well_counts(int nx, int ny, int nwells, WellChunk wells, int32
 __global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nwells, WellChunk wells,
                             const int32_t *__restrict__ rowptr, int32_t *__restrict__ colind,
                             double *__restrict__ val, double *__restrict__ b) {
-    int w = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wavefront per well, a lane per perforated layer (64 at a time); the
+    // well row's sums run in layer order over the lanes' terms
+    const int w = blockIdx.x, lane = threadIdx.x;
     if (w >= nwells) return;
     bo_well W = wells.w[w];
     const int wr = wells.row[w];
@@ -420,80 +423,90 @@ __global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nw
     double zh = depth_of(G, top);
     const double ph = wr < 0 ? W.target : xn[3 * (size_t)wr];
     double Rw = 0.0, Jww = 0.0;
-    int ew = wr >= 0 ? rowptr[wr] : 0;     // next block of the well row
+    const int ew0 = wr >= 0 ? rowptr[wr] : 0;  // the well row's first block
     const double sgn = W.injector ? 1.0 : -1.0;
-    for (int k = W.k_top; k <= W.k_bot; k++) {
-        int cell = W.i + G.nx * (W.j + G.ny * k);
-        Props c;
-        props_of(f, G.phi0[cell], xn + 3 * (size_t)cell, c);
-        double WI = well_index(G, f, cell, W.rw, W.skin);
-        double dz = zh - depth_of(G, cell);
-        double q[3] = {0.0, 0.0, 0.0}, dq[3][3], dqh[3] = {0.0, 0.0, 0.0};
-        for (int r = 0; r < 3; r++)
-            for (int s = 0; s < 3; s++) dq[r][s] = 0.0;
-        if (W.injector) {
-            double lt = c.lo + c.lw + c.lg;
-            double lt_w = c.lo_w + c.lw_w, lt_g = c.lo_g + c.lg_g;
-            if (!f.inj_total_mobility) { lt = c.lw; lt_w = c.lw_w; lt_g = 0.0; }
-            double dw = ph - c.p - c.rw * gg * dz;
-            double dw_p = -1.0 - c.drw * gg * dz;
-            q[1] = WI * lt * c.bw * dw;
-            dq[1][0] = WI * lt * (c.dbw * dw + c.bw * dw_p);
-            dq[1][1] = WI * lt_w * c.bw * dw;
-            dq[1][2] = WI * lt_g * c.bw * dw;
-            dqh[1] = WI * lt * c.bw;
-        } else {
-            double d_o = ph - c.p - c.ro * gg * dz;
-            double d_w = ph - c.p - c.rw * gg * dz;
-            double d_g = ph - c.p - c.rg * gg * dz;
-            double do_p = -1.0 - c.dro * gg * dz;
-            double dw_p = -1.0 - c.drw * gg * dz;
-            double dg_p = -1.0 - c.drg * gg * dz;
-            q[0] = WI * c.lo * c.bo * d_o;
-            dq[0][0] = WI * c.lo * (c.dbo * d_o + c.bo * do_p);
-            dq[0][1] = WI * c.lo_w * c.bo * d_o;
-            dq[0][2] = WI * c.lo_g * c.bo * d_o;
-            q[1] = WI * c.lw * c.bw * d_w;
-            dq[1][0] = WI * c.lw * (c.dbw * d_w + c.bw * dw_p);
-            dq[1][1] = WI * c.lw_w * c.bw * d_w;
-            double qgf = WI * c.lg * c.bg * d_g;
-            q[2] = qgf + c.rs * q[0];
-            dq[2][0] = WI * c.lg * (c.dbg * d_g + c.bg * dg_p) + c.drs * q[0] + c.rs * dq[0][0];
-            dq[2][1] = c.rs * dq[0][1];
-            dq[2][2] = WI * c.lg_g * c.bg * d_g + c.rs * dq[0][2];
-            dqh[0] = WI * c.lo * c.bo;
-            dqh[1] = WI * c.lw * c.bw;
-            dqh[2] = WI * c.lg * c.bg + c.rs * dqh[0];
+    for (int k0 = W.k_top; k0 <= W.k_bot; k0 += 64) {
+        const int k = k0 + lane, cnt = min(64, W.k_bot - k0 + 1);
+        double tq = 0.0, th = 0.0;  // this layer's terms of Rw and Jww
+        if (k <= W.k_bot) {
+            int cell = W.i + G.nx * (W.j + G.ny * k);
+            const int ew = ew0 + (k - W.k_top);
+            Props c;
+            props_of(f, G.phi0[cell], xn + 3 * (size_t)cell, c);
+            double WI = well_index(G, f, cell, W.rw, W.skin);
+            double dz = zh - depth_of(G, cell);
+            double q[3] = {0.0, 0.0, 0.0}, dq[3][3], dqh[3] = {0.0, 0.0, 0.0};
+            for (int r = 0; r < 3; r++)
+                for (int s = 0; s < 3; s++) dq[r][s] = 0.0;
+            if (W.injector) {
+                double lt = c.lo + c.lw + c.lg;
+                double lt_w = c.lo_w + c.lw_w, lt_g = c.lo_g + c.lg_g;
+                if (!f.inj_total_mobility) { lt = c.lw; lt_w = c.lw_w; lt_g = 0.0; }
+                double dw = ph - c.p - c.rw * gg * dz;
+                double dw_p = -1.0 - c.drw * gg * dz;
+                q[1] = WI * lt * c.bw * dw;
+                dq[1][0] = WI * lt * (c.dbw * dw + c.bw * dw_p);
+                dq[1][1] = WI * lt_w * c.bw * dw;
+                dq[1][2] = WI * lt_g * c.bw * dw;
+                dqh[1] = WI * lt * c.bw;
+            } else {
+                double d_o = ph - c.p - c.ro * gg * dz;
+                double d_w = ph - c.p - c.rw * gg * dz;
+                double d_g = ph - c.p - c.rg * gg * dz;
+                double do_p = -1.0 - c.dro * gg * dz;
+                double dw_p = -1.0 - c.drw * gg * dz;
+                double dg_p = -1.0 - c.drg * gg * dz;
+                q[0] = WI * c.lo * c.bo * d_o;
+                dq[0][0] = WI * c.lo * (c.dbo * d_o + c.bo * do_p);
+                dq[0][1] = WI * c.lo_w * c.bo * d_o;
+                dq[0][2] = WI * c.lo_g * c.bo * d_o;
+                q[1] = WI * c.lw * c.bw * d_w;
+                dq[1][0] = WI * c.lw * (c.dbw * d_w + c.bw * dw_p);
+                dq[1][1] = WI * c.lw_w * c.bw * d_w;
+                double qgf = WI * c.lg * c.bg * d_g;
+                q[2] = qgf + c.rs * q[0];
+                dq[2][0] = WI * c.lg * (c.dbg * d_g + c.bg * dg_p) + c.drs * q[0] + c.rs * dq[0][0];
+                dq[2][1] = c.rs * dq[0][1];
+                dq[2][2] = WI * c.lg_g * c.bg * d_g + c.rs * dq[0][2];
+                dqh[0] = WI * c.lo * c.bo;
+                dqh[1] = WI * c.lw * c.bw;
+                dqh[2] = WI * c.lg * c.bg + c.rs * dqh[0];
+            }
+            int dpos = rowptr[cell];
+            while (colind[dpos] != cell) dpos++;  // the diagonal is in the row by construction
+            double *J = val + 9 * (size_t)dpos;
+            for (int r = 0; r < 3; r++) {
+                b[3 * (size_t)cell + r] = b[3 * (size_t)cell + r] + q[r];
+                for (int s = 0; s < 3; s++) J[3 * r + s] = J[3 * r + s] - dq[r][s];
+            }
+            if (wr >= 0) {
+                // the cell row's well block (its last block)
+                int ec = rowptr[cell + 1] - 1;
+                colind[ec] = wr;
+                double *Jc = val + 9 * (size_t)ec;
+                for (int r = 0; r < 3; r++) {
+                    Jc[3 * r] = 0.0 - dqh[r];
+                    Jc[3 * r + 1] = 0.0;
+                    Jc[3 * r + 2] = 0.0;
+                }
+                // the well row: rate constraint (injected water / produced oil + water)
+                double qc = W.injector ? q[1] : q[0] + q[1];
+                double dqch = W.injector ? dqh[1] : dqh[0] + dqh[1];
+                tq = sgn * qc;
+                colind[ew] = cell;
+                double *Jw = val + 9 * (size_t)ew;
+                for (int z = 0; z < 9; z++) Jw[z] = 0.0;
+                for (int s2 = 0; s2 < 3; s2++) Jw[s2] = 0.0 + sgn * (W.injector ? dq[1][s2] : dq[0][s2] + dq[1][s2]);
+                th = sgn * dqch;
+            }
         }
-        int dpos = rowptr[cell];
-        while (colind[dpos] != cell) dpos++;  // the diagonal is in the row by construction
-        double *J = val + 9 * (size_t)dpos;
-        for (int r = 0; r < 3; r++) {
-            b[3 * (size_t)cell + r] = b[3 * (size_t)cell + r] + q[r];
-            for (int s = 0; s < 3; s++) J[3 * r + s] = J[3 * r + s] - dq[r][s];
+        for (int u = 0; u < cnt; u++) {
+            Rw = Rw + __shfl(tq, u, 64);
+            Jww = Jww + __shfl(th, u, 64);
         }
-        if (wr < 0) continue;
-        // the cell row's well block (its last block)
-        int ec = rowptr[cell + 1] - 1;
-        colind[ec] = wr;
-        double *Jc = val + 9 * (size_t)ec;
-        for (int r = 0; r < 3; r++) {
-            Jc[3 * r] = 0.0 - dqh[r];
-            Jc[3 * r + 1] = 0.0;
-            Jc[3 * r + 2] = 0.0;
-        }
-        // the well row: rate constraint (injected water / produced oil + water)
-        double qc = W.injector ? q[1] : q[0] + q[1];
-        double dqch = W.injector ? dqh[1] : dqh[0] + dqh[1];
-        Rw = Rw + sgn * qc;
-        colind[ew] = cell;
-        double *Jw = val + 9 * (size_t)ew;
-        for (int z = 0; z < 9; z++) Jw[z] = 0.0;
-        for (int s2 = 0; s2 < 3; s2++) Jw[s2] = 0.0 + sgn * (W.injector ? dq[1][s2] : dq[0][s2] + dq[1][s2]);
-        Jww = Jww + sgn * dqch;
-        ew++;
     }
-    if (wr >= 0) {
+    if (wr >= 0 && lane == 0) {
+        const int ew = ew0 + (W.k_bot - W.k_top + 1);
         Rw = Rw - W.target;
         colind[ew] = wr;
         double *Jw = val + 9 * (size_t)ew;
@@ -620,7 +633,7 @@ extern "C" bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, c
     for (int w0 = 0; w0 < p->nwells; w0 += kWellChunk) {
         WellChunk ch{};
         int c = chunk_of(w0, ch);
-        k_jac_wells<<<1, kWellChunk, 0, s>>>(G, f, x_new, c, ch, J->rowptr, J->colind, J->val, b);
+        k_jac_wells<<<c, 64, 0, s>>>(G, f, x_new, c, ch, J->rowptr, J->colind, J->val, b);
         BO_HIP(hipGetLastError());
     }
     return BO_OK;
