@@ -247,9 +247,12 @@ __global__ void k_strength_slots(int nx, int ny, int nz, const double *__restric
 
 enum { UND = 0, IN = 1, OUT = 2, ISO = 3 };
 
+// (also clears the change words of the level's MIS rounds, kMisWords of them)
+constexpr int kMisWords = 64;
 __global__ void k_mis_init(int n, const int32_t *__restrict__ rp, const uint8_t *__restrict__ sf,
-                           uint8_t *__restrict__ state) {
+                           uint8_t *__restrict__ state, int32_t *__restrict__ words) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kMisWords) words[i] = 0;
     if (i >= n) return;
     int deg = 0;
     for (int e = rp[i]; e < rp[i + 1]; e++) deg += sf[e];
@@ -1513,17 +1516,18 @@ __global__ void k_omega(const unsigned long long *__restrict__ rho_bits, double 
 // others take the 256-slot hash and the long rows a launch of their own.
 static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const double *av, const int32_t *brp,
                         const int32_t *bci, const double *bv, DBuf<int32_t> &crp, DBuf<int32_t> &cci,
-                        DBuf<double> &cv, int *cnnz, int32_t *flag, SetupWork &W, hipStream_t s) {
+                        DBuf<double> &cv, int *cnnz, SetupWork &W, hipStream_t s) {
     DBuf<int32_t> &cnt = W.gcnt;
     BO_TRY(cnt.alloc(n));
     BO_TRY(crp.alloc(n + 1));
     BO_TRY(W.sg_prod.alloc(n));
     // [0, 2 kRedSlots): reduction words of the product bound and the long-row
-    // count, then the long-row list position and the largest distinct count
-    constexpr int kPos = 2 * kRedSlots, kMaxl = 2 * kRedSlots + 1;
-    BO_TRY(W.sg_stat.alloc(kMaxl + 1));
-    BO_HIP(hipMemsetAsync(W.sg_stat.p, 0, sizeof(int32_t) * (kMaxl + 1), s));
-    BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    // count, then the long-row list position, the largest distinct count and
+    // the hash-capacity flag (one clear for all of them)
+    constexpr int kPos = 2 * kRedSlots, kMaxl = 2 * kRedSlots + 1, kBad = 2 * kRedSlots + 2;
+    BO_TRY(W.sg_stat.alloc(kBad + 1));
+    BO_HIP(hipMemsetAsync(W.sg_stat.p, 0, sizeof(int32_t) * (kBad + 1), s));
+    int32_t *const bflag = W.sg_stat.p + kBad;
     k_spgemm_bound<<<grid_for(n), kBlock, 0, s>>>(n, arp, aci, brp, W.sg_prod.p, W.sg_stat.p);
     int32_t stat[2 * kRedSlots] = {};
     HostRead rd{W.sg_stat.p, sizeof stat, stat};
@@ -1548,7 +1552,7 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         if (rn <= 0) return;
 #define BO_SPGEMM_COUNT(G, H)                                                                                 \
     k_spgemm<G, H, false><<<grid_for((long long)rn * G), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, cnt.p, \
-                                                                      nullptr, nullptr, nullptr, flag, rows,  \
+                                                                      nullptr, nullptr, nullptr, bflag, rows, \
                                                                       pr, W.sg_stat.p + kMaxl)
         switch (sel) {
         case 0: BO_SPGEMM_COUNT(8, 64); break;
@@ -1563,7 +1567,7 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     if (split) count(sel_long, nlong, W.sg_rows.p, nullptr);
     BO_HIP(hipGetLastError());
     int32_t bad = 0, total = 0, lmax = 0;
-    HostRead ex[2] = {{flag, sizeof bad, &bad}, {W.sg_stat.p + kMaxl, sizeof lmax, &lmax}};
+    HostRead ex[2] = {{bflag, sizeof bad, &bad}, {W.sg_stat.p + kMaxl, sizeof lmax, &lmax}};
     BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s, ex, 2));
     if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: Galerkin product row exceeds the LDS hash capacity");
     BO_TRY(cci.alloc(total));
@@ -1578,7 +1582,7 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         const int G = sel == 0 || sel == 4 ? 8 : sel == 1 ? 16 : 64;
 #define BO_SPGEMM_NUM(GG, H)                                                                                    \
     k_spgemm<GG, H, true><<<grid_for((long long)rn * GG), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, nullptr, \
-                                                                       crp.p, cci.p, cv.p, flag, rows, pr,     \
+                                                                       crp.p, cci.p, cv.p, bflag, rows, pr,    \
                                                                        W.sg_stat.p + kMaxl)
         if (G == 8) {
             if (h <= 64) BO_SPGEMM_NUM(8, 64); else BO_SPGEMM_NUM(8, 128);
@@ -1656,14 +1660,24 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         DBuf<uint8_t> &state = W.state, &nw = W.nw, &d1 = W.d1;
         DBuf<uint64_t> &m1 = W.m1;
         BO_TRY(state.alloc(n)); BO_TRY(nw.alloc(n)); BO_TRY(d1.alloc(n)); BO_TRY(m1.alloc(n));
-        k_mis_init<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.sf.p, state.p);
+        // each round reports a change in a word of its own (cleared by
+        // k_mis_init, kMisWords of them, cleared again when they run out), so
+        // no round needs a memset before it
+        BO_TRY(W.misw.alloc(kMisWords));
+        k_mis_init<<<grid_for(std::max(n, kMisWords)), kBlock, 0, s>>>(n, L.rp.p, L.sf.p, state.p, W.misw.p);
+        int word = 0;
         // rounds are checked for completion after the fourth and then every
         // second round: a round on a graph with no undecided node changes
         // nothing
         for (int round = 0;; round += 2) {
             if (round > 10000) return fail(BO_ERR_HIP, "AMG: MIS-2 did not terminate");
+            int32_t *rflag = nullptr;
             for (int rep = 0; rep < (round == 0 ? 4 : 2); rep++) {
-                BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+                if (word == kMisWords) {
+                    BO_HIP(hipMemsetAsync(W.misw.p, 0, sizeof(int32_t) * kMisWords, s));
+                    word = 0;
+                }
+                rflag = W.misw.p + word++;
                 // lanes per row: about two to four entries per lane
 #define BO_MIS_ROUND(G)                                                                                       \
     do {                                                                                                      \
@@ -1671,7 +1685,7 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         k_mis_m1<G><<<gb, kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p);                      \
         k_mis_m2<G><<<gb, kBlock, 0, s>>>(n, l, L.rp.p, L.ci.p, L.sf.p, state.p, m1.p, nw.p);                \
         k_mis_spread<G><<<gb, kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p);                        \
-        k_mis_update<G><<<gb, kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p, state.p, flag);         \
+        k_mis_update<G><<<gb, kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, nw.p, d1.p, state.p, rflag);        \
     } while (0)
                 double avg = (double)L.nnz / n;
                 if (avg <= 10.0) BO_MIS_ROUND(1);
@@ -1682,7 +1696,7 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
             }
             BO_HIP(hipGetLastError());
             int32_t any = 0;
-            BO_TRY(read_flag(flag, s, &any));
+            BO_TRY(read_flag(rflag, s, &any));  // the last round's word
             if (!any) break;
         }
         // aggregates
@@ -1708,7 +1722,6 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         const double *omega = W.omg.p + l;
         BO_TRY(W.plong.alloc(n + 1));
         k_omega<<<1, 1, 0, s>>>(rho.p, W.omg.p + l, W.dfl.p + 2, W.plong.p);
-        BO_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
         k_p_count<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, L.agg.p, cnt.p, W.plong.p);
         // the listed long rows, a wavefront each up to 65536 of them
         const unsigned pgrid = (unsigned)std::min<long long>((n + kPWaves - 1) / kPWaves, 16384);
@@ -1729,26 +1742,28 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
                                                  L.pci.p, L.pv.p, nullptr, W.plong.p);
         BO_HIP(hipGetLastError());
         // R = P^T
-        DBuf<int32_t> &rc = W.rc, &fp = W.fp;
-        BO_TRY(rc.alloc(nc)); BO_TRY(fp.alloc(nc));
-        BO_HIP(hipMemsetAsync(rc.p, 0, sizeof(int32_t) * nc, s));
-        BO_HIP(hipMemsetAsync(fp.p, 0, sizeof(int32_t) * nc, s));
-        k_col_counts<<<grid_for(pnnz), kBlock, 0, s>>>(pnnz, L.pci.p, rc.p);
+        // column counts and fill positions in one buffer (one clear); R has
+        // P's nnz, so its row pointers need no read back
+        DBuf<int32_t> &rc = W.rc;
+        BO_TRY(rc.alloc(2 * (size_t)nc));
+        int32_t *const rcnt = rc.p, *const fp = rc.p + nc;
+        BO_HIP(hipMemsetAsync(rc.p, 0, sizeof(int32_t) * 2 * nc, s));
+        k_col_counts<<<grid_for(pnnz), kBlock, 0, s>>>(pnnz, L.pci.p, rcnt);
         BO_TRY(L.rrp.alloc(nc + 1));
-        int32_t rn = 0;
-        BO_TRY(scan_counts(rc.p, L.rrp.p, nc, &rn, s));
+        BO_TRY(W.scan_sums.alloc(scan_sum_words(nc)));
+        BO_TRY(scan_counts_async(rcnt, L.rrp.p, nc, W.scan_sums.p, s));
         BO_TRY(L.rci.alloc(pnnz)); BO_TRY(L.rv.alloc(pnnz));
-        k_transpose_fill<<<grid_for(n), kBlock, 0, s>>>(n, L.prp.p, L.pci.p, L.pv.p, L.rrp.p, fp.p, L.rci.p, L.rv.p);
+        k_transpose_fill<<<grid_for(n), kBlock, 0, s>>>(n, L.prp.p, L.pci.p, L.pv.p, L.rrp.p, fp, L.rci.p, L.rv.p);
         k_sort_rows<<<grid_for((long long)nc * 64), kBlock, 0, s>>>(nc, L.rrp.p, L.rci.p, L.rv.p);
         BO_HIP(hipGetLastError());
         // A_c = R (A P)
         DBuf<int32_t> &aprp = W.aprp, &apci = W.apci;
         DBuf<double> &apv = W.apv;
         int apnnz = 0;
-        BO_TRY(spgemm(n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p, aprp, apci, apv, &apnnz, flag, W, s));
+        BO_TRY(spgemm(n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p, aprp, apci, apv, &apnnz, W, s));
         Level &C = pc->lv[l + 1];
         C.n = nc;
-        BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, flag, W, s));
+        BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, W, s));
     }
     pc->nlev = l + 1;
     // coarsest: dense inverse

@@ -212,5 +212,10 @@ bo_status host_reads(const HostRead *r, int count, hipStream_t s);
 // synchronisation (at most three).
 bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s,
                       const HostRead *extra = nullptr, int nextra = 0);
+// The same prefix sum enqueued without reading anything back (no
+// synchronisation), for callers that know the total; sums is the caller's
+// work buffer of scan_sum_words(n) words, in use until the stream reaches it.
+int scan_sum_words(int n);
+bo_status scan_counts_async(const int32_t *counts, int32_t *out, int n, int32_t *sums, hipStream_t s);
 
 }  // namespace bo

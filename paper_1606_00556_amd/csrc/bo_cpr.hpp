@@ -33,7 +33,7 @@ struct Level {
 struct SetupWork {
     DBuf<uint8_t> state, nw, d1;
     DBuf<uint64_t> m1;
-    DBuf<int32_t> cnt, id, a1, rc, fp, gcnt;
+    DBuf<int32_t> cnt, id, a1, rc, gcnt;
     DBuf<double> aF;
     DBuf<unsigned long long> rho;
     DBuf<int32_t> dfl;            // deferred setup flags, read once at the end (see amg_setup)
@@ -42,6 +42,8 @@ struct SetupWork {
     DBuf<double> apv, dense;
     DBuf<int32_t> sg_prod, sg_rows, sg_stat;  // sparse product: products per row, long rows, reduction words
     DBuf<int32_t> plong;          // prolongator rows longer than the register path: [count, rows...]
+    DBuf<int32_t> misw;           // change words of the MIS-2 rounds, one per round
+    DBuf<int32_t> scan_sums;      // block sums of the prefix sums that read nothing back
 };
 
 struct Krylov {

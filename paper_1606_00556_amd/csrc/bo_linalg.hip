@@ -126,6 +126,21 @@ __global__ void k_scan_apply(const int32_t *in, int n, const int32_t *sums, int3
     if (base + t == n - 1) out[n] = sums[blockIdx.x] + sh[t];
 }
 
+int scan_sum_words(int n) { return n > 0 ? (n + kScanBlock - 1) / kScanBlock : 1; }
+
+bo_status scan_counts_async(const int32_t *counts, int32_t *out, int n, int32_t *sums, hipStream_t s) {
+    if (n <= 0) {
+        BO_HIP(hipMemsetAsync(out, 0, sizeof(int32_t), s));
+        return BO_OK;
+    }
+    int nb = (n + kScanBlock - 1) / kScanBlock;
+    k_block_sums<<<nb, kScanBlock, 0, s>>>(counts, n, sums);
+    k_scan_sums<<<1, kScanBlock, 0, s>>>(sums, nb);
+    k_scan_apply<<<nb, kScanBlock, 0, s>>>(counts, n, sums, out);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
 bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total, hipStream_t s,
                       const HostRead *extra, int nextra) {
     if (nextra < 0 || nextra > 3) return fail(BO_ERR_INVALID_ARG, "scan_counts: at most three extra reads");
