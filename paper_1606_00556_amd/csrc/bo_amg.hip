@@ -1200,29 +1200,56 @@ __global__ void k_extract_inverse(int n, const double *__restrict__ M, double *_
 // form: hierarchy stored in FP32, FP32 arithmetic and accumulation).
 template <typename T> __device__ __forceinline__ T two_thirds() { return (T)(2.0 / 3.0); }
 
-// level 0 on the grid (slot form), colour c of red-black Gauss-Seidel; with
-// zero set the other colour is taken as 0 and x is not read (b - 0 is b
-// exactly, so this equals the sweep over a zeroed x)
+// Level 0 on the grid, red-black Gauss-Seidel, on a copy of the slot arrays
+// split by colour.  Cells 2h and 2h+1 always differ in the parity of i+j+k
+// (a step along x flips it, and a row or layer boundary that falls inside a
+// pair does too, since nx, or nx and ny, are then odd), so pair h holds one
+// cell of each colour, and out[(c*7 + q)*H + h] (H = ceil(n/2)) is slot q of
+// pair h's colour-c cell (0 where an odd n leaves the pair one cell).  A
+// colour's sweep then reads half of the coefficients, contiguously.
+__device__ __forceinline__ int cell_colour(int g, int nx, int nxy) { return ((g % nx) + (g % nxy) / nx + g / nxy) & 1; }
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_gs_slots(int nx, int ny, int nz, const T *__restrict__ A,
+__global__ void __launch_bounds__(kBlock) k_split_colours(int nx, int ny, int nz, const T *__restrict__ A,
+                                                          T *__restrict__ out, int32_t *__restrict__ bad) {
+    const int n = nx * ny * nz, nxy = nx * ny, H = (n + 1) / 2;
+    int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= H) return;
+    const size_t N = (size_t)n, HH = (size_t)H;
+    const int g0 = 2 * h, c0 = cell_colour(g0, nx, nxy);
+    const bool two = g0 + 1 < n;
+    if (two && cell_colour(g0 + 1, nx, nxy) == c0) *bad = 1;  // cannot happen (see above)
+#pragma unroll
+    for (int q = 0; q < NSLOT; q++) {
+        out[((size_t)c0 * NSLOT + q) * HH + h] = A[(size_t)q * N + g0];
+        out[((size_t)(1 - c0) * NSLOT + q) * HH + h] = two ? A[(size_t)q * N + g0 + 1] : (T)0;
+    }
+}
+
+// colour c of the sweep; with zero set the other colour is taken as 0 and x
+// is not read (b - 0 is b exactly, so this equals the sweep over a zeroed x).
+// Same operations in the same order as the sweep over the slot arrays.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs_split(int nx, int ny, int nz, const T *__restrict__ Ac,
                                                      const T *__restrict__ b, T *__restrict__ x, int colour,
                                                      int zero) {
-    int n = nx * ny * nz;
-    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int n = nx * ny * nz, nxy = nx * ny, H = (n + 1) / 2;
+    int h = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (h >= H) return;
+    const int g0 = 2 * h;
+    const int i = cell_colour(g0, nx, nxy) == colour ? g0 : g0 + 1;
     if (i >= n) return;
-    int nxy = nx * ny;
     int ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
-    if (((ix + iy + iz) & 1) != colour) return;
     const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
                        ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
-    size_t N = (size_t)n;
-    T s = b[i], d = A[(size_t)S_D * N + i];
+    const size_t HH = (size_t)H;
+    const T *Aq = Ac + (size_t)colour * NSLOT * HH;
+    T s = b[i], d = Aq[(size_t)S_D * HH + h];
     if (!zero) {
 #pragma unroll
         for (int q = 0; q < NSLOT; q++) {
             int j = nb[q];
             if (j < 0 || q == S_D) continue;
-            s = s - A[(size_t)q * N + i] * x[j];
+            s = s - Aq[(size_t)q * HH + h] * x[j];
         }
     }
     x[i] = s / d;
@@ -1632,10 +1659,19 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
     int max_levels = std::min(std::max(o.max_levels, 1), kMaxLevels);
     double t2 = o.theta * o.theta;
     // flags whose failure leaves every index valid are checked once, at the
-    // end: [0] zero diagonal, [1] unaggregated node, [2] smoother bound
+    // end: [0] zero diagonal, [1] unaggregated node, [2] smoother bound,
+    // [3] a colour pair of the split level-0 copy
     BO_TRY(W.dfl.alloc(4));
     BO_TRY(W.omg.alloc(kMaxLevels));
     BO_HIP(hipMemsetAsync(W.dfl.p, 0, sizeof(int32_t) * 4, s));
+    if (!pc->general && o.smoother == BO_SMOOTH_GS) {
+        // the colour-split copy the red-black sweeps read (k_gs_split)
+        const long long H = ((long long)L0.n + 1) / 2;
+        BO_TRY(pc->appc.alloc(2 * NSLOT * (size_t)H));
+        k_split_colours<double><<<grid_for(H), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->app.p, pc->appc.p,
+                                                               W.dfl.p + 3);
+        BO_HIP(hipGetLastError());
+    }
     int l = 0;
     for (;; l++) {
         Level &L = pc->lv[l];
@@ -1789,13 +1825,14 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         k_extract_inverse<<<grid_for((long long)nc * nc), kBlock, 0, s>>>(nc, M.p, pc->cinv.p);
     }
     BO_HIP(hipGetLastError());
-    int32_t bad = 0, dfl[3] = {0, 0, 0};
+    int32_t bad = 0, dfl[4] = {0, 0, 0, 0};
     double omg[kMaxLevels] = {};
     HostRead rd[3] = {{flag, sizeof bad, &bad}, {W.dfl.p, sizeof dfl, dfl}, {W.omg.p, sizeof(double) * kMaxLevels, omg}};
     BO_TRY(host_reads(rd, pc->nlev > 1 ? 3 : 2, s));
     if (dfl[0]) return fail(BO_ERR_SINGULAR_COARSE, "AMG: zero or non-finite diagonal in the pressure hierarchy");
     if (dfl[1]) return fail(BO_ERR_HIP, "AMG: a node could not be aggregated");
     if (dfl[2]) return fail(BO_ERR_SINGULAR_COARSE, "AMG: bad smoother bound");
+    if (dfl[3]) return fail(BO_ERR_HIP, "AMG: colour pairs of the level-0 sweep");
     if (bad) return fail(BO_ERR_SINGULAR_COARSE, "AMG: the coarsest matrix is singular");
     for (int q = 0; q + 1 < pc->nlev; q++) pc->lv[q].omega = omg[q];
     return BO_OK;
@@ -1814,6 +1851,7 @@ template <> struct Prec<double> {
     static double *t(Level &L) { return L.t.p; }
     static const double *dl1(const Level &L) { return L.dl1.p; }
     static const double *app(const bo_cpr *pc) { return pc->app.p; }
+    static const double *appc(const bo_cpr *pc) { return pc->appc.p; }
     static const double *cinv(const bo_cpr *pc) { return pc->cinv.p; }
 };
 template <> struct Prec<float> {
@@ -1826,6 +1864,7 @@ template <> struct Prec<float> {
     static float *t(Level &L) { return L.t32.p; }
     static const float *dl1(const Level &L) { return L.dl132.p; }
     static const float *app(const bo_cpr *pc) { return pc->app32.p; }
+    static const float *appc(const bo_cpr *pc) { return pc->appc32.p; }
     static const float *cinv(const bo_cpr *pc) { return pc->cinv32.p; }
 };
 
@@ -1842,8 +1881,10 @@ static bo_status smooth0(bo_cpr *pc, const T *b, T *x, bool forward, bool zero, 
     for (int sw = 0; sw < pc->o.sweeps; sw++) {
         if (pc->o.smoother == BO_SMOOTH_GS) {
             int c0 = forward ? 0 : 1;
-            k_gs_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, c0, zero && sw == 0 ? 1 : 0);
-            k_gs_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, 1 - c0, 0);
+            const T *Ac = Prec<T>::appc(pc);
+            const long long H = (n + 1) / 2;
+            k_gs_split<T><<<grid_for(H), kBlock, 0, s>>>(g.nx, g.ny, g.nz, Ac, b, x, c0, zero && sw == 0 ? 1 : 0);
+            k_gs_split<T><<<grid_for(H), kBlock, 0, s>>>(g.nx, g.ny, g.nz, Ac, b, x, 1 - c0, 0);
         } else {
             T *t = Prec<T>::r(L);
             k_jacobi_slots<T><<<grid_for(n), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, b, x, t);
@@ -1958,6 +1999,11 @@ bo_status amg_make_f32(bo_cpr *pc, hipStream_t s) {
     if (!pc->general) {
         BO_TRY(pc->app32.alloc(7 * (size_t)pc->n));
         BO_TRY(to_f32(7 * (long long)pc->n, pc->app.p, pc->app32.p, s));
+        if (pc->o.smoother == BO_SMOOTH_GS) {
+            const long long words = 2 * NSLOT * (((long long)pc->n + 1) / 2);
+            BO_TRY(pc->appc32.alloc(words));
+            BO_TRY(to_f32(words, pc->appc.p, pc->appc32.p, s));
+        }
     }
     for (int l = 0; l < pc->nlev; l++) {
         Level &L = pc->lv[l];

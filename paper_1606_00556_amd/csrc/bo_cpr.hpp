@@ -84,6 +84,9 @@ struct bo_cpr {
     // level-0 pressure matrix in slot layout (7 * N) and the hierarchy
     bo::DBuf<double> app;
     bo::DBuf<float> app32;
+    // the same split by colour for the red-black sweeps (2 x 7 x ceil(N/2))
+    bo::DBuf<double> appc;
+    bo::DBuf<float> appc32;
     int nlev = 0;
     bo::Level lv[bo::kMaxLevels];
     int coarse_n = 0;
