@@ -189,6 +189,27 @@ def test_general_form_rejects_grid_only_options(B, O):
                                                       precision=B.BO_PREC_FP32))
 
 
+def test_jacobian_deep_well_rows(B, O):
+    """Wells through 600 layers: the well kernel takes 64 layers per sweep of
+    its lanes (ten sweeps), and the fixed-rate well's row sums stay in layer
+    order, so the Jacobian matches the oracle as it does for short wells."""
+    import dataclasses
+    case = cg.tiny_case(3, 3, 600, seed=19, step=0.01,
+                        wells=[cg.Well(1, 1, 0, 599, "prod", "lrat", 500.0),
+                               cg.Well(0, 0, 0, 599, "inj", "bhp", 3500.0)])
+    case = dataclasses.replace(case, x_old=np.concatenate([case.x_old, [2800.0, 0.0, 0.0]]),
+                               x_new=np.concatenate([case.x_new, [2800.0, 0.0, 0.0]]))
+    P = O.Problem(case)
+    rp, ci, val, R = O.jacobian(P)
+    grp, gci, gval, gb = gpu_jacobian(B, case)
+    assert np.array_equal(grp, rp) and np.array_equal(gci, ci)
+    scale = np.abs(val).max()
+    for e in range(len(ci)):
+        d = np.abs(gval[e] - val[e]).max()
+        assert d <= 1e-12 * max(np.abs(val[e]).max(), 1e-300 * scale), (e, d)
+    assert rel_err(gb, -R) <= 1e-12
+
+
 def test_long_well_row_hierarchy_matches_oracle(B, O):
     """A fixed-rate well through 600 layers makes a pressure row of 601
     entries: its prolongator row takes the global-memory path; the hierarchy

@@ -161,6 +161,21 @@ def test_cpr_variants_match_oracle(B, O, kw):
     assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * case.n), opc.apply(v)) <= 1e-10
 
 
+@pytest.mark.parametrize("dims", [(9, 7, 5), (8, 7, 5), (7, 6, 5), (5, 5, 5)])
+def test_gauss_seidel_colour_pairs(B, O, dims):
+    """The level-0 red-black sweeps read a colour-split copy of the pressure
+    arrays, pairing cells 2h and 2h+1: grids with odd and even nx, ny and an
+    odd cell count (an unpaired last cell) give the oracle's cycle."""
+    nx, ny, nz = dims
+    case = cg.tiny_case(nx, ny, nz, seed=51, step=0.01)
+    _, _, _, _, b, opc, gpc = setup_both(B, O, case, coarse_max=40)
+    n = case.n
+    r = np.random.default_rng(12).standard_normal(n)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_vcycle, r, n), opc.vcycle(r)) <= 1e-10
+    v = np.random.default_rng(13).standard_normal(3 * n)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= 1e-10
+
+
 def test_ilu_pivots_bitwise(B, O):
     """The tiled block-ILU(0) pivots are produced by the same operations in the
     same order on both sides: identical bits."""
