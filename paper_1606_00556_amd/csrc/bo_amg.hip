@@ -1919,6 +1919,9 @@ static bo_status smooth_c(Level &L, int sweeps, bool l1, const T *b, T *x, T **r
     return BO_OK;
 }
 
+// levels up to this many rows take the fused zero-guess sweep and residual
+constexpr int kFuseRows = 1 << 20;
+
 // one V-cycle on level l for right-hand side b; returns the result pointer
 template <typename T>
 static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t s) {
@@ -1937,8 +1940,10 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t 
         BO_TRY(smooth0<T>(pc, b, x, true, true, s));
         k_resid_slots<T><<<grid_for(L.n), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, Prec<T>::app(pc), b, x,
                                                            Prec<T>::r(L));
-    } else if (l1 && pc->o.sweeps == 1) {
-        // the one zero-guess sweep fused with the residual
+    } else if (l1 && pc->o.sweeps == 1 && L.n <= kFuseRows) {
+        // the one zero-guess sweep fused with the residual (on small levels,
+        // where the launch it saves costs more than gathering b and d_l1
+        // instead of x)
         x = Prec<T>::x(L);
         BO_TRY(csr_l1_resid<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), b, Prec<T>::dl1(L), x, Prec<T>::r(L), s));
     } else {
