@@ -185,6 +185,10 @@ typedef struct {
     int32_t npr;            /* general form: the pressure system is the first npr block
                                rows (cells; later rows, e.g. fixed-rate wells, stay out
                                of A_pp and are only smoothed by the F stage); 0: all */
+    int32_t sell_rows;      /* AMG matrices (level operators in CSR form, P, R) of at
+                               least this many rows are also kept sliced (SELL-64, one
+                               thread per row in the cycle); 0: 2^20.  Same results up
+                               to the order of each row's sum. */
 } bo_cpr_opts;
 
 /* Fills `o` [host] with the defaults: PF, tiled ILU0 8x8, theta 0.08,

@@ -76,7 +76,7 @@ class BoCprOpts(C.Structure):
                 ("theta", C.c_double), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("smoother", C.c_int32), ("sweeps", C.c_int32), ("use_amg", C.c_int32),
                 ("qi_mode", C.c_int32), ("precision", C.c_int32), ("csmoother", C.c_int32),
-                ("npr", C.c_int32)]
+                ("npr", C.c_int32), ("sell_rows", C.c_int32)]
 
 
 class BoGrid(C.Structure):

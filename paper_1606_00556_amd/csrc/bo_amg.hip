@@ -1371,6 +1371,59 @@ __global__ void __launch_bounds__(kBlock) k_csr_l1_resid(int n, const int32_t *_
     r[row] = bi - s;
 }
 
+// ---- sliced copies of large CSR matrices --------------------------------------------
+// Matrices of at least kSellRows rows (bo_cpr_opts.sell_rows) are also kept
+// in SELL-64 form: one
+// thread per row then reads its entries with every load of a wavefront on
+// 64 consecutive words, where the lanes-per-row form reads short runs of a
+// row each (a level of 11M rows with 40 entries a row streamed at about 2
+// TB/s).  The row sums run in entry order.
+constexpr int kSellRows = 1 << 20;
+__global__ void k_csr_slice_width(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ w64) {
+    int S = blockIdx.x * blockDim.x + threadIdx.x;
+    int nsl = (n + 63) / 64;
+    if (S >= nsl) return;
+    int r0 = 64 * S, r1 = min(n, r0 + 64), w = 0;
+    for (int r = r0; r < r1; r++) w = max(w, rp[r + 1] - rp[r]);
+    w64[S] = 64 * w;
+}
+__global__ void k_csr_sell_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                const double *__restrict__ v, const int32_t *__restrict__ off,
+                                int32_t *__restrict__ col, double *__restrict__ val) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int S = r / 64, lane = r % 64;
+    const int base = off[S] + lane, w = (off[S + 1] - off[S]) / 64;
+    const int b = rp[r], len = rp[r + 1] - b;
+    // padding: the row's first column (a valid index of x for rectangular
+    // P and R too; column 0 for an empty row) with value 0
+    const int pad = len > 0 ? ci[b] : 0;
+    for (int p = 0; p < w; p++) {
+        col[base + 64 * p] = p < len ? ci[b + p] : pad;
+        val[base + 64 * p] = p < len ? v[b + p] : 0.0;
+    }
+}
+// y = op(A x) as k_csr_rowop, for OP_MV, OP_RESID, OP_ADD and OP_L1
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sell_rowop(int n, const int32_t *__restrict__ off,
+                                                       const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                       const T *__restrict__ x, int op, const T *__restrict__ b,
+                                                       const T *__restrict__ dl1, T *__restrict__ y) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int S = r / 64, lane = r % 64;
+    const int base = off[S] + lane, w = (off[S + 1] - off[S]) / 64;
+    T s = 0;
+#pragma unroll 4
+    for (int p = 0; p < w; p++) s = s + val[base + 64 * p] * x[col[base + 64 * p]];
+    switch (op) {
+    case OP_MV: y[r] = s; break;
+    case OP_RESID: y[r] = b[r] - s; break;
+    case OP_ADD: y[r] = y[r] + s; break;
+    default: y[r] = x[r] + (b[r] - s) / dl1[r]; break;  // OP_L1
+    }
+}
+
 // dense y = M x, one wavefront per row
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dense_mv(int n, const T *__restrict__ M, const T *__restrict__ x,
@@ -1409,10 +1462,48 @@ bo_status read_flag(int32_t *dflag, hipStream_t s, int32_t *out) {
 
 }  // namespace
 
+// the sliced copy of a CSR matrix of n rows (M.on stays false below min_rows)
+static bo_status sell_from_csr(SellMat &M, int n, const int32_t *rp, const int32_t *ci, const double *v,
+                               int min_rows, DBuf<int32_t> &work, hipStream_t s) {
+    M.on = false;
+    if (n < 1 || n < min_rows) return BO_OK;
+    const int nsl = (n + 63) / 64;
+    BO_TRY(work.alloc(nsl));
+    BO_TRY(M.off.alloc(nsl + 1));
+    k_csr_slice_width<<<grid_for(nsl), kBlock, 0, s>>>(n, rp, work.p);
+    // the padded size in 64 bits first: the prefix sum is 32-bit
+    std::vector<int32_t> w(nsl);
+    BO_HIP(hipMemcpyAsync(w.data(), work.p, sizeof(int32_t) * nsl, hipMemcpyDeviceToHost, s));
+    BO_HIP(hipStreamSynchronize(s));
+    long long padded = 0;
+    for (int32_t x : w) padded += x;
+    if (padded > (1ll << 30)) return BO_OK;  // keep the CSR form
+    int32_t total = 0;
+    BO_TRY(scan_counts(work.p, M.off.p, nsl, &total, s));
+    BO_TRY(M.col.alloc(total));
+    BO_TRY(M.val.alloc(total));
+    k_csr_sell_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, M.off.p, M.col.p, M.val.p);
+    BO_HIP(hipGetLastError());
+    M.len = total;
+    M.on = true;
+    return BO_OK;
+}
+
+template <typename T> static const T *sell_val(const SellMat &M);
+template <> const double *sell_val<double>(const SellMat &M) { return M.val.p; }
+template <> const float *sell_val<float>(const SellMat &M) { return M.val32.p; }
+
 // y = op(A x) for a CSR matrix with nnz entries over n rows (see k_csr_rowop)
 template <typename T>
 static bo_status csr_rowop(int n, int nnz, const int32_t *rp, const int32_t *ci, const T *v, const T *x, int op,
-                           const T *b, const int32_t *dpos, T *y, hipStream_t s, const T *dl1 = nullptr) {
+                           const T *b, const int32_t *dpos, T *y, hipStream_t s, const T *dl1 = nullptr,
+                           const SellMat *sm = nullptr) {
+    if (sm && sm->on && (op == OP_MV || op == OP_RESID || op == OP_ADD || op == OP_L1)) {
+        k_sell_rowop<T><<<grid_for(n), kBlock, 0, s>>>(n, sm->off.p, sm->col.p, sell_val<T>(*sm), x, op, b, dl1,
+                                                      y);
+        BO_HIP(hipGetLastError());
+        return BO_OK;
+    }
     double avg = n > 0 ? (double)nnz / n : 1.0;
     long long threads;
 #define BO_ROWOP(G)                                                                                  \
@@ -1802,6 +1893,15 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, W, s));
     }
     pc->nlev = l + 1;
+    // sliced copies of the large matrices the cycle applies row by row
+    const int sell_min = o.sell_rows > 0 ? o.sell_rows : kSellRows;
+    for (int q = 0; q + 1 < pc->nlev; q++) {
+        Level &L = pc->lv[q], &C = pc->lv[q + 1];
+        if (q > 0 || pc->general) BO_TRY(sell_from_csr(L.sA, L.n, L.rp.p, L.ci.p, L.v.p, sell_min, W.cnt, s));
+        else L.sA.on = false;
+        BO_TRY(sell_from_csr(L.sP, L.n, L.prp.p, L.pci.p, L.pv.p, sell_min, W.cnt, s));
+        BO_TRY(sell_from_csr(L.sR, C.n, L.rrp.p, L.rci.p, L.rv.p, sell_min, W.cnt, s));
+    }
     // coarsest: dense inverse
     Level &Lc = pc->lv[l];
     int nc = Lc.n;
@@ -1912,7 +2012,7 @@ static bo_status smooth_c(Level &L, int sweeps, bool l1, const T *b, T *x, T **r
     }
     for (int sw = first; sw < sweeps; sw++) {
         BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), cur, l1 ? OP_L1 : OP_JACOBI, b, L.diagpos.p,
-                            oth, s, d));
+                            oth, s, d, &L.sA));
         std::swap(cur, oth);
     }
     *res = cur;
@@ -1948,14 +2048,16 @@ static bo_status vcycle_rec(bo_cpr *pc, int l, const T *b, T **res, hipStream_t 
         BO_TRY(csr_l1_resid<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), b, Prec<T>::dl1(L), x, Prec<T>::r(L), s));
     } else {
         BO_TRY(smooth_c<T>(L, pc->o.sweeps, l1, b, nullptr, &x, s));
-        BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), x, OP_RESID, b, nullptr, Prec<T>::r(L), s));
+        BO_TRY(csr_rowop<T>(L.n, L.nnz, L.rp.p, L.ci.p, Prec<T>::v(L), x, OP_RESID, b, nullptr, Prec<T>::r(L), s,
+                            nullptr, &L.sA));
     }
     Level &C = pc->lv[l + 1];
     BO_TRY(csr_rowop<T>(C.n, L.pnnz, L.rrp.p, L.rci.p, Prec<T>::rv(L), Prec<T>::r(L), OP_MV, nullptr, nullptr,
-                        Prec<T>::b(C), s));
+                        Prec<T>::b(C), s, nullptr, &L.sR));
     T *xc;
     BO_TRY(vcycle_rec<T>(pc, l + 1, Prec<T>::b(C), &xc, s));
-    BO_TRY(csr_rowop<T>(L.n, L.pnnz, L.prp.p, L.pci.p, Prec<T>::pv(L), xc, OP_ADD, nullptr, nullptr, x, s));
+    BO_TRY(csr_rowop<T>(L.n, L.pnnz, L.prp.p, L.pci.p, Prec<T>::pv(L), xc, OP_ADD, nullptr, nullptr, x, s, nullptr,
+                        &L.sP));
     if (slots0) {
         BO_TRY(smooth0<T>(pc, b, x, false, false, s));
         *res = x;
@@ -2022,6 +2124,11 @@ bo_status amg_make_f32(bo_cpr *pc, hipStream_t s) {
             BO_TRY(L.dl132.alloc(L.n));
             BO_TRY(to_f32(L.n, L.dl1.p, L.dl132.p, s));
         }
+        for (SellMat *M : {&L.sA, &L.sP, &L.sR})
+            if (M->on) {
+                BO_TRY(M->val32.alloc(M->len));
+                BO_TRY(to_f32(M->len, M->val.p, M->val32.p, s));
+            }
         if (l + 1 < pc->nlev) {
             BO_TRY(L.pv32.alloc(L.pnnz)); BO_TRY(L.rv32.alloc(L.pnnz));
             BO_TRY(to_f32(L.pnnz, L.pv.p, L.pv32.p, s));

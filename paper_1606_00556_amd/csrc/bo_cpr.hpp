@@ -10,6 +10,19 @@ constexpr int kCoarseMaxLimit = 1024;
 
 // One level of the aggregation hierarchy: CSR operator (ascending columns),
 // and for every level but the coarsest the transfer operators to the next.
+// A CSR matrix of many rows also kept sliced (SELL-64): slices of 64 rows,
+// each entry position of a slice stored for its 64 rows together (column
+// indices and values), rows shorter than the slice's longest padded with
+// (their first column, 0).  off[S] is slice S's first element (64 x the widths of
+// the slices before it).
+struct SellMat {
+    bool on = false;
+    long long len = 0;            // stored elements (padding included)
+    DBuf<int32_t> off, col;
+    DBuf<double> val;
+    DBuf<float> val32;
+};
+
 struct Level {
     int n = 0, nnz = 0;
     DBuf<int32_t> rp, ci;
@@ -27,6 +40,8 @@ struct Level {
     DBuf<double> x, b, r, t;
     // single-precision copies (mixed form)
     DBuf<float> v32, pv32, rv32, x32, b32, r32, t32, dl132;
+    // sliced copies of A, P and R for levels of many rows (see SellMat)
+    SellMat sA, sP, sR;
 };
 
 // setup temporaries kept with the handle, reused (grow-only) by later setups

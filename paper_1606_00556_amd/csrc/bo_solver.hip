@@ -179,6 +179,7 @@ extern "C" void bo_cpr_default_opts(bo_cpr_opts *o) {
     o->precision = BO_PREC_FP64;
     o->csmoother = BO_CSMOOTH_L1;
     o->npr = 0;
+    o->sell_rows = 0;
 }
 
 extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
@@ -271,6 +272,7 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
     if (!general && opts->smoother == BO_SMOOTH_L1)
         return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: the l1 level-0 smoother is for the general form");
     if (opts->npr < 0 || opts->npr > A->nbrows) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: npr out of range");
+    if (opts->sell_rows < 0) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: sell_rows out of range");
     if (!general && opts->npr != 0 && opts->npr != A->nbrows)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: on a grid every row is a pressure row");
     if ((long long)A->nbrows * 7 >= (1LL << 31)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: matrix too large");

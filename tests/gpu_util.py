@@ -46,8 +46,10 @@ def rel_err(a, b):
 
 
 def matching_opts(O, B, ftype="tiled", fpf=0, tile=(8, 8), coarse_max=256, smoother="gs", sweeps=1,
-                  use_amg=1, qi="block", theta=0.08, precision="fp64", csmoother="l1"):
-    """The same CPR configuration for the oracle and the library."""
+                  use_amg=1, qi="block", theta=0.08, precision="fp64", csmoother="l1", sell_rows=0):
+    """The same CPR configuration for the oracle and the library (sell_rows:
+    the library's storage choice for large coarse matrices, not a change of
+    the method)."""
     oft = dict(tiled=O.F_ILU_TILED, bj=O.F_BJ)[ftype]
     bft = dict(tiled=B.BO_F_ILU_TILED, bj=B.BO_F_BJ)[ftype]
     osm = dict(gs=O.SMOOTH_GS, jacobi=O.SMOOTH_JACOBI)[smoother]
@@ -62,7 +64,7 @@ def matching_opts(O, B, ftype="tiled", fpf=0, tile=(8, 8), coarse_max=256, smoot
                     sweeps=sweeps, use_amg=use_amg, qi_mode=oqi, precision=opr, csmoother=ocs)
     bo = B.bo_cpr_default_opts(fpf=fpf, ftype=bft, tile=tile, theta=theta, coarse_max=coarse_max,
                                smoother=bsm, sweeps=sweeps, use_amg=use_amg, qi_mode=bqi, precision=bpr,
-                               csmoother=bcs)
+                               csmoother=bcs, sell_rows=sell_rows)
     return oo, bo
 
 

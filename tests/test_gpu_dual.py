@@ -112,6 +112,22 @@ def test_general_cpr_stages_match_oracle(B, O, name):
     assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, b, 3 * rows), opc.apply(b)) <= 1e-10
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_general_form_sliced_coarse_matrices(B, O, name):
+    """The general form with every CSR level (level 0 included), P and R also
+    kept sliced (sell_rows = 1): the cycle and CPR still match the oracle."""
+    case, P, rp, ci, val, b = system(O, name)
+    opc = O.Cpr(P, rp, ci, val, ftype=O.F_BJ, smoother=O.SMOOTH_L1, npr=P.ncell, coarse_max=40)
+    opts = B.bo_cpr_default_opts(ftype=B.BO_F_BJ, smoother=B.BO_SMOOTH_L1, npr=P.ncell, coarse_max=40,
+                                 sell_rows=1)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), None, opts)
+    rng = np.random.default_rng(6)
+    r = rng.standard_normal(P.ncell)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_vcycle, r, P.ncell), opc.vcycle(r)) <= 1e-10
+    v = rng.standard_normal(3 * P.rows)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * P.rows), opc.apply(v)) <= 1e-10
+
+
 @pytest.mark.parametrize("kw", [dict(fpf=1), dict(smoother=1, sweeps=2), dict(csmoother=0)])
 def test_general_cpr_variants(B, O, kw):
     okw = dict(kw)

@@ -176,6 +176,22 @@ def test_gauss_seidel_colour_pairs(B, O, dims):
     assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= 1e-10
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(precision="fp32"), dict(csmoother="jacobi", sweeps=2)])
+def test_sliced_coarse_matrices_match_oracle(B, O, kw):
+    """With sell_rows = 1 every coarse level operator, P and R is also kept
+    sliced (SELL-64, one thread per row, entry-order sums), the form the cycle
+    takes on levels of 2^20 rows and more: the V-cycle and the CPR
+    application still match the oracle (FP32: its emulation)."""
+    case = ragged_case(seed=71)
+    _, _, _, _, b, opc, gpc = setup_both(B, O, case, coarse_max=40, sell_rows=1, **kw)
+    tol = 1e-5 if kw.get("precision") == "fp32" else 1e-10
+    n = case.n
+    r = np.random.default_rng(14).standard_normal(n)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_vcycle, r, n), opc.vcycle(r)) <= tol
+    v = np.random.default_rng(15).standard_normal(3 * n)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= tol
+
+
 def test_ilu_pivots_bitwise(B, O):
     """The tiled block-ILU(0) pivots are produced by the same operations in the
     same order on both sides: identical bits."""
