@@ -826,15 +826,17 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *_
     }
 }
 
-// the rows above kLongProducts, in any order (each is computed on its own)
-__global__ void k_spgemm_long_rows(int n, const int32_t *__restrict__ prod, int32_t *__restrict__ rows,
+// the rows with val[i] > limit, in any order (each is computed on its own)
+__global__ void k_spgemm_long_rows(int n, const int32_t *__restrict__ val, int limit, int32_t *__restrict__ rows,
                                    int32_t *__restrict__ pos) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && prod[i] > kLongProducts) rows[atomicAdd(pos, 1)] = i;
+    if (i < n && val[i] > limit) rows[atomicAdd(pos, 1)] = i;
 }
 
-// Rows: with rows != NULL the kernel takes rows[0..n) (the long rows); with
-// prod != NULL it takes rows 0..n-1 except those above kLongProducts products.
+// Rows: with rows != NULL the kernel takes rows[0..n) (listed rows); with
+// prod != NULL it takes rows 0..n-1 except those with prod[i] > plimit (the
+// long rows by products, or in the numeric pass the rows of many distinct
+// columns).
 // The counting pass sizes its hash for the row's products and records the
 // largest distinct count in *maxl; the numeric pass then takes a hash of at
 // least twice that.
@@ -846,7 +848,7 @@ __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict
                                                const int32_t *__restrict__ crp, int32_t *__restrict__ cci,
                                                double *__restrict__ cv, int32_t *__restrict__ bad,
                                                const int32_t *__restrict__ rows, const int32_t *__restrict__ prod,
-                                               int32_t *__restrict__ maxl) {
+                                               int32_t *__restrict__ maxl, int plimit) {
     static_assert(H >= G && H % G == 0, "hash slots per lane");
     constexpr int R = 256 / G;
     constexpr int HV = NUM ? H : 1;  // the counting pass keeps no values
@@ -862,7 +864,7 @@ __global__ void __launch_bounds__(256) k_spgemm(int n, const int32_t *__restrict
     __syncthreads();
     if (idx >= n) return;
     const int i = rows ? rows[idx] : idx;
-    if (prod && prod[i] > kLongProducts) return;  // left to the long-row launch
+    if (prod && prod[i] > plimit) return;  // left to the launch over the listed rows
     constexpr bool numeric = NUM;
     // one product: the column's slot (linear probing), then its sum
     auto insert = [&](int c, double prod) {
@@ -1664,14 +1666,15 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     const int32_t *prod = split ? W.sg_prod.p : nullptr;
     if (split) {
         BO_TRY(W.sg_rows.alloc(nlong));
-        k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, W.sg_prod.p, W.sg_rows.p, W.sg_stat.p + kPos);
+        k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, W.sg_prod.p, kLongProducts, W.sg_rows.p,
+                                                           W.sg_stat.p + kPos);
     }
     auto count = [&](int sel, int rn, const int32_t *rows, const int32_t *pr) {
         if (rn <= 0) return;
 #define BO_SPGEMM_COUNT(G, H)                                                                                 \
     k_spgemm<G, H, false><<<grid_for((long long)rn * G), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, cnt.p, \
                                                                       nullptr, nullptr, nullptr, bflag, rows, \
-                                                                      pr, W.sg_stat.p + kMaxl)
+                                                                      pr, W.sg_stat.p + kMaxl, kLongProducts)
         switch (sel) {
         case 0: BO_SPGEMM_COUNT(8, 64); break;
         case 4: BO_SPGEMM_COUNT(8, 128); break;
@@ -1691,17 +1694,18 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     BO_TRY(cci.alloc(total));
     BO_TRY(cv.alloc(total));
     // numeric pass: the same lanes per row, a hash of at least twice the
-    // largest distinct count (never more than the counting pass had), so no
-    // insertion can fail and the LDS left over keeps more rows resident
-    auto numeric = [&](int sel, int rn, const int32_t *rows, const int32_t *pr) {
+    // largest distinct count of the rows it takes (never more than the
+    // counting pass had), so no insertion can fail and the LDS left over
+    // keeps more rows resident
+    auto numeric = [&](int sel, int rn, const int32_t *rows, const int32_t *pr, int plimit, int dmax) {
         if (rn <= 0) return;
         int h = 64;
-        while (h < 2 * lmax && h < count_slots(sel)) h *= 2;
+        while (h < 2 * dmax && h < count_slots(sel)) h *= 2;
         const int G = sel == 0 || sel == 4 ? 8 : sel == 1 ? 16 : 64;
 #define BO_SPGEMM_NUM(GG, H)                                                                                    \
     k_spgemm<GG, H, true><<<grid_for((long long)rn * GG), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, nullptr, \
                                                                        crp.p, cci.p, cv.p, bflag, rows, pr,    \
-                                                                       W.sg_stat.p + kMaxl)
+                                                                       W.sg_stat.p + kMaxl, plimit)
         if (G == 8) {
             if (h <= 64) BO_SPGEMM_NUM(8, 64); else BO_SPGEMM_NUM(8, 128);
         } else if (G == 16) {
@@ -1718,8 +1722,25 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         }
 #undef BO_SPGEMM_NUM
     };
-    numeric(sel_all, n, nullptr, prod);
-    if (split) numeric(sel_long, nlong, W.sg_rows.p, nullptr);
+    // A few rows of many distinct columns (a well's) would size every row's
+    // hash: below 10 % of the rows they are listed and take a launch of their
+    // own, the others a hash for kFewDistinct columns.
+    constexpr int kFewDistinct = 64;
+    int nbig = 0;
+    if (!split && lmax > kFewDistinct) {
+        int32_t *pos = W.sg_stat.p + kPos;  // unused without the products split
+        BO_TRY(W.sg_rows.alloc(n));
+        k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, cnt.p, kFewDistinct, W.sg_rows.p, pos);
+        HostRead rb{pos, sizeof nbig, &nbig};
+        BO_TRY(host_reads(&rb, 1, s));
+    }
+    if (nbig > 0 && (long long)nbig * 10 < n) {
+        numeric(sel_all, n, nullptr, cnt.p, kFewDistinct, kFewDistinct);
+        numeric(sel_all, nbig, W.sg_rows.p, nullptr, 0, lmax);
+    } else {
+        numeric(sel_all, n, nullptr, prod, kLongProducts, lmax);
+        if (split) numeric(sel_long, nlong, W.sg_rows.p, nullptr, 0, lmax);
+    }
     BO_HIP(hipGetLastError());
     *cnnz = total;
     return BO_OK;
