@@ -169,6 +169,130 @@ __global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__r
     }
 }
 
+// FP64 factorisation in two passes.  Pack: one thread per slot (tile, step,
+// lane), all slots at once, gathers its cell's blocks into the packed layout
+// (forward slot: [A_ii | Lz Ly Lx], backward slot: [- | Uz Ux Uy], zero where
+// the neighbour lies outside the tile or grid) and records the slot of each
+// cell.  Chain: one wavefront per tile walks the steps as k_ilu_factor does,
+// but reads each step's blocks from the packed layout (1 KB per load
+// instruction instead of one cache line per lane) and writes E^{-1} over
+// A_ii in the forward slot and into the backward slot.  Same operations in
+// the same order as k_ilu_factor, so the same bits.
+__global__ void __launch_bounds__(kBlock) k_ilu_pack(TileGeom T, const double *__restrict__ A,
+                                                     double2 *__restrict__ Ff, double2 *__restrict__ Fb,
+                                                     int32_t *__restrict__ slot_of) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T.slots()) return;
+    const int t = (int)(q % 64);
+    const long long ts = q / 64;
+    const int s = (int)(ts % T.ns), tile = (int)(ts / T.ns);
+    const int a = t % T.tx, b = t / T.tx;
+    const int ti = tile % T.ntx, tj = tile / T.ntx;
+    const int i = ti * T.tx + a, j = tj * T.ty + b, k = s - a - b;
+    if (!(t < T.tx * T.ty && i < T.nx && j < T.ny && k >= 0 && k < T.nz)) return;  // idle slot
+    const bool has_mx = a > 0, has_my = b > 0;
+    const bool has_px = a + 1 < T.tx && i + 1 < T.nx, has_py = b + 1 < T.ty && j + 1 < T.ny;
+    const size_t N = (size_t)T.nx * T.ny * T.nz;
+    const int g = i + T.nx * (j + T.ny * k);
+    double fw[36], bw[36];
+#pragma unroll
+    for (int z = 0; z < 36; z++) fw[z] = bw[z] = 0.0;
+    load_blk(A, S_D, N, g, fw);
+    if (k > 0) load_blk(A, S_MZ, N, g, fw + 9);
+    if (has_my) load_blk(A, S_MY, N, g, fw + 18);
+    if (has_mx) load_blk(A, S_MX, N, g, fw + 27);
+    if (k + 1 < T.nz) load_blk(A, S_PZ, N, g, bw + 9);
+    if (has_px) load_blk(A, S_PX, N, g, bw + 18);
+    if (has_py) load_blk(A, S_PY, N, g, bw + 27);
+#pragma unroll
+    for (int p2 = 0; p2 < kPairs; p2++) {
+        Ff[pk_index(tile, T.ns, s, p2, t)] = make_double2(fw[2 * p2], fw[2 * p2 + 1]);
+        if (p2 >= 4) Fb[pk_index(tile, T.ns, s, p2, t)] = make_double2(bw[2 * p2], bw[2 * p2 + 1]);
+    }
+    slot_of[g] = (int32_t)q;
+}
+
+__global__ void __launch_bounds__(64) k_ilu_chain(TileGeom T, double2 *__restrict__ Ff, double2 *__restrict__ Fb,
+                                                  int32_t *__restrict__ bad, double *__restrict__ einv_nat) {
+    int t = threadIdx.x;
+    int a = t % T.tx, b = t / T.tx;
+    int tile = blockIdx.x;
+    int ti = tile % T.ntx, tj = tile / T.ntx;
+    int i = ti * T.tx + a, j = tj * T.ty + b;
+    bool active = t < T.tx * T.ty && i < T.nx && j < T.ny;
+    bool has_mx = a > 0, has_my = b > 0;
+    size_t N = (size_t)T.nx * T.ny * T.nz;
+    double Ep[9], Uxp[9], Uyp[9], Uzp[9];  // this lane's values from the previous step
+    for (int z = 0; z < 9; z++) Ep[z] = Uxp[z] = Uyp[z] = Uzp[z] = 0.0;
+    for (int s = 0; s < T.ns; s++) {
+        double Ex[9], Ey[9], Ux[9], Uy[9];
+        shfl_arr<9>(Ep, Ex, has_mx ? t - 1 : t);
+        shfl_arr<9>(Uxp, Ux, has_mx ? t - 1 : t);
+        shfl_arr<9>(Ep, Ey, has_my ? t - T.tx : t);
+        shfl_arr<9>(Uyp, Uy, has_my ? t - T.tx : t);
+        int k = s - a - b;
+        const bool act = active && k >= 0 && k < T.nz;
+        // every lane loads (idle lanes read lane 0's slot) so that no load
+        // is skipped on some paths
+        const int tl = act ? t : 0;
+        double fw[36], uw[27];
+#pragma unroll
+        for (int p2 = 0; p2 < kPairs; p2++) {
+            double2 d = Ff[pk_index(tile, T.ns, s, p2, tl)];
+            fw[2 * p2] = d.x;
+            fw[2 * p2 + 1] = d.y;
+        }
+        {
+            double2 d = Fb[pk_index(tile, T.ns, s, 4, tl)];
+            uw[0] = d.y;
+#pragma unroll
+            for (int p2 = 5; p2 < kPairs; p2++) {
+                double2 e = Fb[pk_index(tile, T.ns, s, p2, tl)];
+                uw[2 * p2 - 9] = e.x;
+                uw[2 * p2 - 8] = e.y;
+            }
+        }
+        if (act) {
+            double E[9], Lk[9], tmp[9];
+            for (int z = 0; z < 9; z++) E[z] = fw[z];
+            // -z, -y, -x in ascending order (zero blocks where missing)
+            if (k > 0) {
+                mul3(fw + 9, Ep, Lk); mul3(Lk, Uzp, tmp);
+                for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
+            }
+            if (has_my) {
+                mul3(fw + 18, Ey, Lk); mul3(Lk, Uy, tmp);
+                for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
+            }
+            if (has_mx) {
+                mul3(fw + 27, Ex, Lk); mul3(Lk, Ux, tmp);
+                for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
+            }
+            double Ei[9];
+            if (!inv3_gj(E, Ei)) {
+                *bad = 1;
+                for (int z = 0; z < 9; z++) Ei[z] = 0.0;
+            }
+            for (int z = 0; z < 9; z++) Ep[z] = Ei[z];
+            if (einv_nat) {
+                const int g = i + T.nx * (j + T.ny * k);
+                for (int z = 0; z < 9; z++) einv_nat[(size_t)z * N + g] = Ei[z];
+            }
+            // E^{-1} into values 0..8 of both slots
+#pragma unroll
+            for (int p2 = 0; p2 < 4; p2++) {
+                const double2 e = make_double2(Ei[2 * p2], Ei[2 * p2 + 1]);
+                Ff[pk_index(tile, T.ns, s, p2, t)] = e;
+                Fb[pk_index(tile, T.ns, s, p2, t)] = e;
+            }
+            ((double *)&Ff[pk_index(tile, T.ns, s, 4, t)])[0] = Ei[8];
+            ((double *)&Fb[pk_index(tile, T.ns, s, 4, t)])[0] = Ei[8];
+            // this cell's upper blocks for the next step's neighbours
+            for (int z = 0; z < 9; z++) { Uzp[z] = uw[z]; Uxp[z] = uw[9 + z]; Uyp[z] = uw[18 + z]; }
+        }
+    }
+}
+
 // One half of a slot's 36 factor values: half 0 = values 0..17 (E^{-1} and
 // the first block), half 1 = values 18..35 (the other two blocks).  In the
 // FP32 / BF16 forms the quad holding values 16..19 is read by both halves.
@@ -692,8 +816,10 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
         // idle slots are never read by the sweeps: their factors stay unset
         int nb = T.ntx * T.nty;
         if (st == ST_F64) {
-            k_ilu_factor<ST_F64><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p,
-                                                   pc->ilu_slot.p, pc->flag.p, ext ? pc->x_einv_f.p : nullptr);
+            k_ilu_pack<<<grid_for(T.slots()), kBlock, 0, s>>>(T, pc->A.p, (double2 *)pc->ilu_f.p,
+                                                              (double2 *)pc->ilu_b.p, pc->ilu_slot.p);
+            k_ilu_chain<<<nb, 64, 0, s>>>(T, (double2 *)pc->ilu_f.p, (double2 *)pc->ilu_b.p, pc->flag.p,
+                                          ext ? pc->x_einv_f.p : nullptr);
         } else if (st == ST_F32) {
             k_ilu_factor<ST_F32><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p,
                                                    pc->ilu_slot.p, pc->flag.p, nullptr);
