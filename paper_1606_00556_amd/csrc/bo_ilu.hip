@@ -224,7 +224,34 @@ __global__ void __launch_bounds__(64) k_ilu_chain(TileGeom T, double2 *__restric
     size_t N = (size_t)T.nx * T.ny * T.nz;
     double Ep[9], Uxp[9], Uyp[9], Uzp[9];  // this lane's values from the previous step
     for (int z = 0; z < 9; z++) Ep[z] = Uxp[z] = Uyp[z] = Uzp[z] = 0.0;
-    for (int s = 0; s < T.ns; s++) {
+    // a step's 63 values, loaded one step ahead into a ring of two buffers
+    // (the loop is unrolled by two so that no buffer is copied: a copy of
+    // registers with loads in flight makes the compiler wait for all of them)
+    struct Slot {
+        double fw[36], uw[27];
+    };
+    auto fetch = [&](int s, Slot &S) {
+        const int sc = min(s, T.ns - 1);
+        const int k = sc - a - b;
+        // every lane loads (idle lanes read lane 0's slot) so that no load
+        // is skipped on some paths
+        const int tl = active && k >= 0 && k < T.nz ? t : 0;
+#pragma unroll
+        for (int p2 = 0; p2 < kPairs; p2++) {
+            double2 d = Ff[pk_index(tile, T.ns, sc, p2, tl)];
+            S.fw[2 * p2] = d.x;
+            S.fw[2 * p2 + 1] = d.y;
+        }
+        double2 d = Fb[pk_index(tile, T.ns, sc, 4, tl)];
+        S.uw[0] = d.y;
+#pragma unroll
+        for (int p2 = 5; p2 < kPairs; p2++) {
+            double2 e = Fb[pk_index(tile, T.ns, sc, p2, tl)];
+            S.uw[2 * p2 - 9] = e.x;
+            S.uw[2 * p2 - 8] = e.y;
+        }
+    };
+    auto step = [&](int s, const Slot &S) {
         double Ex[9], Ey[9], Ux[9], Uy[9];
         shfl_arr<9>(Ep, Ex, has_mx ? t - 1 : t);
         shfl_arr<9>(Uxp, Ux, has_mx ? t - 1 : t);
@@ -232,26 +259,7 @@ __global__ void __launch_bounds__(64) k_ilu_chain(TileGeom T, double2 *__restric
         shfl_arr<9>(Uyp, Uy, has_my ? t - T.tx : t);
         int k = s - a - b;
         const bool act = active && k >= 0 && k < T.nz;
-        // every lane loads (idle lanes read lane 0's slot) so that no load
-        // is skipped on some paths
-        const int tl = act ? t : 0;
-        double fw[36], uw[27];
-#pragma unroll
-        for (int p2 = 0; p2 < kPairs; p2++) {
-            double2 d = Ff[pk_index(tile, T.ns, s, p2, tl)];
-            fw[2 * p2] = d.x;
-            fw[2 * p2 + 1] = d.y;
-        }
-        {
-            double2 d = Fb[pk_index(tile, T.ns, s, 4, tl)];
-            uw[0] = d.y;
-#pragma unroll
-            for (int p2 = 5; p2 < kPairs; p2++) {
-                double2 e = Fb[pk_index(tile, T.ns, s, p2, tl)];
-                uw[2 * p2 - 9] = e.x;
-                uw[2 * p2 - 8] = e.y;
-            }
-        }
+        const double *fw = S.fw, *uw = S.uw;
         if (act) {
             double E[9], Lk[9], tmp[9];
             for (int z = 0; z < 9; z++) E[z] = fw[z];
@@ -290,7 +298,17 @@ __global__ void __launch_bounds__(64) k_ilu_chain(TileGeom T, double2 *__restric
             // this cell's upper blocks for the next step's neighbours
             for (int z = 0; z < 9; z++) { Uzp[z] = uw[z]; Uxp[z] = uw[9 + z]; Uyp[z] = uw[18 + z]; }
         }
+    };
+    Slot R0, R1;
+    fetch(0, R0);
+    int s0 = 0;
+    for (; s0 + 2 <= T.ns; s0 += 2) {
+        fetch(s0 + 1, R1);
+        step(s0, R0);
+        fetch(s0 + 2, R0);
+        step(s0 + 1, R1);
     }
+    if (s0 < T.ns) step(s0, R0);
 }
 
 // One half of a slot's 36 factor values: half 0 = values 0..17 (E^{-1} and
