@@ -69,6 +69,7 @@ struct Krylov {
     DBuf<double> h;               // device scalars of two Arnoldi steps, 2m+3 each
     DBuf<double> y;               // m coefficients for the update
     double *host = nullptr;       // pinned: two sets of 2m+3 fetched scalars, then m+1 coefficients
+    double *host_dev = nullptr;   // the same memory as the device addresses it
     ~Krylov() { if (host) (void)hipHostFree(host); }
 };
 

@@ -582,7 +582,7 @@ __global__ void __launch_bounds__(kBlock) k_dcgs_dots(uint32_t n, VecList V, con
 template <int J>
 __global__ void __launch_bounds__(kBlock) k_dcgs_update(uint32_t n, VecList V, const double *__restrict__ red,
                                                         double *__restrict__ sc, int rev,
-                                                        double *__restrict__ partial) {
+                                                        double *__restrict__ partial, double *sc_mirror) {
     __shared__ double cs[J > 0 ? J : 1], cp[J > 0 ? J : 1], cb[2];
     __shared__ double sh[kBlock / 64];
     if (threadIdx.x == 0) {
@@ -599,7 +599,10 @@ __global__ void __launch_bounds__(kBlock) k_dcgs_update(uint32_t n, VecList V, c
         }
         cb[0] = ib;
         cb[1] = r;
-        if (blockIdx.x == 0) { sc[0] = beta; sc[1] = r; }
+        if (blockIdx.x == 0) {
+            sc[0] = beta; sc[1] = r;
+            if (sc_mirror) { sc_mirror[0] = beta; sc_mirror[1] = r; }
+        }
     }
     if (threadIdx.x < J) {
         cs[threadIdx.x] = red[threadIdx.x];
@@ -645,8 +648,10 @@ __global__ void __launch_bounds__(kBlock) k_dcgs_update(uint32_t n, VecList V, c
 // pass 2 (one workgroup per result): out[q] = sum over the partials in a
 // fixed order (strided per thread, then across the wavefront, then across the
 // four wavefronts in order)
+// (with mirror set, each result is also written there: pinned host memory
+// the host reads after the stream's next event, instead of a copy)
 __global__ void __launch_bounds__(kBlock) k_partial_final(int nblocks, const double *__restrict__ partial,
-                                                          double *__restrict__ out) {
+                                                          double *__restrict__ out, double *mirror = nullptr) {
     __shared__ double sh[kBlock / 64];
     int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     int q = blockIdx.x;
@@ -659,6 +664,7 @@ __global__ void __launch_bounds__(kBlock) k_partial_final(int nblocks, const dou
         double t = 0.0;
         for (int w = 0; w < kBlock / 64; w++) t = t + sh[w];
         out[q] = t;
+        if (mirror) mirror[q] = t;
     }
 }
 
@@ -873,7 +879,7 @@ bo_status Reducer::multidot(long long n, const double *x, const double *const *V
 }
 
 bo_status Reducer::dcgs_dots(long long n, const double *const *Vhost, int nv, const double *w, double *out,
-                             hipStream_t s) {
+                             hipStream_t s, double *mirror) {
     if (nv < 1 || nv > kCgsExactMax || n >= (1ll << 29))
         return fail(BO_ERR_INVALID_ARG, "dcgs_dots: 1..32 vectors below 2^29 elements");
     VecList L{};
@@ -893,13 +899,13 @@ bo_status Reducer::dcgs_dots(long long n, const double *const *Vhost, int nv, co
 #undef BO_D
     default: break;
     }
-    k_partial_final<<<2 * nv, kBlock, 0, s>>>(nb, partial.p, out);
+    k_partial_final<<<2 * nv, kBlock, 0, s>>>(nb, partial.p, out, mirror);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
 
 bo_status Reducer::dcgs_update(long long n, const double *const *Vhost, int j, const double *red, double *sc,
-                               double *norm2, hipStream_t s, bool reverse) {
+                               double *norm2, hipStream_t s, bool reverse, double *sc_mirror, double *norm2_mirror) {
     if (j < 0 || j + 1 > kCgsExactMax || n >= (1ll << 29))
         return fail(BO_ERR_INVALID_ARG, "dcgs_update: step 0..31 below 2^29 elements");
     VecList L{};
@@ -911,7 +917,7 @@ bo_status Reducer::dcgs_update(long long n, const double *const *Vhost, int j, c
 #define BO_U(K)                                                                     \
     case K:                                                                         \
         nb = resident_blocks((const void *)k_dcgs_update<K>, 4 * (kCgsExactMax + 1) + K);          \
-        k_dcgs_update<K><<<nb, kBlock, 0, s>>>(n32, L, red, sc, rev, partial.p);    \
+        k_dcgs_update<K><<<nb, kBlock, 0, s>>>(n32, L, red, sc, rev, partial.p, sc_mirror); \
         break;
         BO_U(0) BO_U(1) BO_U(2) BO_U(3) BO_U(4) BO_U(5) BO_U(6) BO_U(7)
         BO_U(8) BO_U(9) BO_U(10) BO_U(11) BO_U(12) BO_U(13) BO_U(14) BO_U(15)
@@ -920,7 +926,7 @@ bo_status Reducer::dcgs_update(long long n, const double *const *Vhost, int j, c
 #undef BO_U
     default: break;
     }
-    k_partial_final<<<1, kBlock, 0, s>>>(nb, partial.p, norm2);
+    k_partial_final<<<1, kBlock, 0, s>>>(nb, partial.p, norm2, norm2_mirror);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }

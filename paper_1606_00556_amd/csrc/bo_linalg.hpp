@@ -53,10 +53,13 @@ struct Reducer {
     // [V[0..nv-1)] and the pending V[nv-1] with itself and w into out[0..2nv);
     // the update of step j over Vhost[0..j+2) (final basis, pending vector,
     // w) from those dots, beta and r into sc[0..1], |new pending|^2 into norm2
+    // (mirror arguments: pinned host memory that also receives the results,
+    // written by the kernels themselves)
     bo_status dcgs_dots(long long n, const double *const *Vhost, int nv, const double *w, double *out,
-                        hipStream_t s);
+                        hipStream_t s, double *mirror = nullptr);
     bo_status dcgs_update(long long n, const double *const *Vhost, int j, const double *red, double *sc,
-                          double *norm2, hipStream_t s, bool reverse);
+                          double *norm2, hipStream_t s, bool reverse, double *sc_mirror = nullptr,
+                          double *norm2_mirror = nullptr);
 };
 
 }  // namespace bo

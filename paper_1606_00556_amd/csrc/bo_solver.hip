@@ -419,7 +419,12 @@ bo_status krylov_alloc(bo_cpr *pc, int m) {
     BO_TRY(K.y.alloc(m + 1));
     if (K.host) (void)hipHostFree(K.host);
     K.host = nullptr;
-    BO_HIP(hipHostMalloc((void **)&K.host, sizeof(double) * (2 * (2 * m + 3) + m + 1), hipHostMallocDefault));
+    K.host_dev = nullptr;
+    // coherent and mapped: the delayed Gram-Schmidt kernels write their
+    // scalars here directly (through host_dev)
+    BO_HIP(hipHostMalloc((void **)&K.host, sizeof(double) * (2 * (2 * m + 3) + m + 1),
+                         hipHostMallocCoherent | hipHostMallocMapped));
+    BO_HIP(hipHostGetDevicePointer((void **)&K.host_dev, K.host, 0));
     K.vptr.resize(m + 1);
     K.zptr.resize(m);
     for (int i = 0; i <= m; i++) K.vptr[i] = K.V.p + (size_t)i * len;
@@ -533,9 +538,12 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
                 // V[j] is pending: dots of [V[0..j), V[j]] with V[j] and w, then
                 // V[j] final, w after its first projection pending in V[j+1]
                 // (walked backwards: the dots pass left its end in cache)
-                BO_TRY(pc->red.dcgs_dots(len, K.vptr.data(), nv, w, hdp, s));
-                BO_TRY(pc->red.dcgs_update(len, K.vptr.data(), j, hdp, hdp + 2 * m, hdp + 2 * m + 2, s, true));
-                BO_HIP(hipMemcpyAsync(hh + p * hs, hdp, sizeof(double) * hs, hipMemcpyDeviceToHost, s));
+                // the kernels also write their results into the pinned set p
+                // (no copy kernel between this step and the next)
+                double *hq = K.host_dev + p * hs;
+                BO_TRY(pc->red.dcgs_dots(len, K.vptr.data(), nv, w, hdp, s, hq));
+                BO_TRY(pc->red.dcgs_update(len, K.vptr.data(), j, hdp, hdp + 2 * m, hdp + 2 * m + 2, s, true,
+                                           hq + 2 * m, hq + 2 * m + 2));
                 BO_HIP(hipEventRecord(pc->evf[p], s));
                 return BO_OK;
             }
