@@ -1636,7 +1636,10 @@ __global__ void k_omega(const unsigned long long *__restrict__ rho_bits, double 
 // others take the 256-slot hash and the long rows a launch of their own.
 static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const double *av, const int32_t *brp,
                         const int32_t *bci, const double *bv, DBuf<int32_t> &crp, DBuf<int32_t> &cci,
-                        DBuf<double> &cv, int *cnnz, SetupWork &W, hipStream_t s) {
+                        DBuf<double> &cv, int *cnnz, SetupWork &W, hipStream_t s, double bavg) {
+    // rows of many products whose B rows are short (at most 32 entries on
+    // average) take 32 lanes, not 64, so that fewer lanes idle per B row
+    const bool g32 = bavg <= 32.0;
     DBuf<int32_t> &cnt = W.gcnt;
     BO_TRY(cnt.alloc(n));
     BO_TRY(crp.alloc(n + 1));
@@ -1679,8 +1682,8 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         case 0: BO_SPGEMM_COUNT(8, 64); break;
         case 4: BO_SPGEMM_COUNT(8, 128); break;
         case 1: BO_SPGEMM_COUNT(16, 256); break;
-        case 2: BO_SPGEMM_COUNT(64, 1024); break;
-        default: BO_SPGEMM_COUNT(64, 2048); break;
+        case 2: if (g32) BO_SPGEMM_COUNT(32, 1024); else BO_SPGEMM_COUNT(64, 1024); break;
+        default: if (g32) BO_SPGEMM_COUNT(32, 2048); else BO_SPGEMM_COUNT(64, 2048); break;
         }
 #undef BO_SPGEMM_COUNT
     };
@@ -1701,7 +1704,8 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         if (rn <= 0) return;
         int h = 64;
         while (h < 2 * dmax && h < count_slots(sel)) h *= 2;
-        const int G = sel == 0 || sel == 4 ? 8 : sel == 1 ? 16 : 64;
+        // (32 lanes hold at most a 1024-slot numeric hash within the LDS)
+        const int G = sel == 0 || sel == 4 ? 8 : sel == 1 ? 16 : (g32 && h <= 1024 ? 32 : 64);
 #define BO_SPGEMM_NUM(GG, H)                                                                                    \
     k_spgemm<GG, H, true><<<grid_for((long long)rn * GG), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, nullptr, \
                                                                        crp.p, cci.p, cv.p, bflag, rows, pr,    \
@@ -1710,6 +1714,14 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
             if (h <= 64) BO_SPGEMM_NUM(8, 64); else BO_SPGEMM_NUM(8, 128);
         } else if (G == 16) {
             if (h <= 64) BO_SPGEMM_NUM(16, 64); else if (h <= 128) BO_SPGEMM_NUM(16, 128); else BO_SPGEMM_NUM(16, 256);
+        } else if (G == 32) {
+            switch (h) {
+            case 64: BO_SPGEMM_NUM(32, 64); break;
+            case 128: BO_SPGEMM_NUM(32, 128); break;
+            case 256: BO_SPGEMM_NUM(32, 256); break;
+            case 512: BO_SPGEMM_NUM(32, 512); break;
+            default: BO_SPGEMM_NUM(32, 1024); break;
+            }
         } else {
             switch (h) {
             case 64: BO_SPGEMM_NUM(64, 64); break;
@@ -1908,10 +1920,12 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
         DBuf<int32_t> &aprp = W.aprp, &apci = W.apci;
         DBuf<double> &apv = W.apv;
         int apnnz = 0;
-        BO_TRY(spgemm(n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p, aprp, apci, apv, &apnnz, W, s));
+        BO_TRY(spgemm(n, L.rp.p, L.ci.p, L.v.p, L.prp.p, L.pci.p, L.pv.p, aprp, apci, apv, &apnnz, W, s,
+                      (double)L.pnnz / n));
         Level &C = pc->lv[l + 1];
         C.n = nc;
-        BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, W, s));
+        BO_TRY(spgemm(nc, L.rrp.p, L.rci.p, L.rv.p, aprp.p, apci.p, apv.p, C.rp, C.ci, C.v, &C.nnz, W, s,
+                      (double)apnnz / n));
     }
     pc->nlev = l + 1;
     // sliced copies of the large matrices the cycle applies row by row
