@@ -826,11 +826,19 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *_
     }
 }
 
-// the rows with val[i] > limit, in any order (each is computed on its own)
+// the rows with val[i] > limit, in any order (each is computed on its own);
+// one atomic per wavefront, each lane at its rank among the wavefront's rows
 __global__ void k_spgemm_long_rows(int n, const int32_t *__restrict__ val, int limit, int32_t *__restrict__ rows,
                                    int32_t *__restrict__ pos) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && val[i] > limit) rows[atomicAdd(pos, 1)] = i;
+    const bool take = i < n && val[i] > limit;
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    const int lane = threadIdx.x % 64, lead = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == lead) base = atomicAdd(pos, __popcll(m));
+    base = __shfl(base, lead, 64);
+    if (take) rows[base + __popcll(m & ((1ull << lane) - 1))] = i;
 }
 
 // Rows: with rows != NULL the kernel takes rows[0..n) (listed rows); with
