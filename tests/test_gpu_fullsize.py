@@ -1,0 +1,131 @@
+"""GPU parity at the benchmark's full sizes: the 100x100x50 workload (500k
+cells, the one bench.py times) and the 200x200x50 one (2M cells), first
+system of each step sequence, through the same entry points and launch
+configurations as the benchmark.
+
+Jacobian and SpMV are compared with the oracle in full (1e-12, and bit for
+bit on integer data); the CPR application on the 500k-cell system in full
+(1e-10); the solves by their true FP64 residual (recomputed with the
+oracle's SpMV) and by the oracle's iteration count (within 10 %)."""
+import math
+
+import numpy as np
+import pytest
+
+import bo_casegen as cg
+from tests.gpu_util import device_bsr, rel_err, run_stage, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1606_00556_amd import bo
+    bo.lib()
+    return bo
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+_SYSTEMS = {}
+
+
+def system(O, cfg):
+    """The oracle's Jacobian of the first system of workload cfg (cached)."""
+    if cfg not in _SYSTEMS:
+        case = cg.make_case(cfg, 1)
+        P = O.Problem(case)
+        rp, ci, val, R = O.jacobian(P)
+        _SYSTEMS[cfg] = (case, P, rp, ci, val, -R)
+    return _SYSTEMS[cfg]
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fullsize_jacobian(B, O, cfg):
+    import torch
+    case, P, rp, ci, val, b = system(O, cfg)
+    p = B.problem_from_case(case)
+    J, gb = B.bo_jacobian_bsr(p, to_dev(case.x_old), to_dev(case.x_new), case.dt)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(J.rowptr), rp) and np.array_equal(to_host(J.colind), ci)
+    gval = to_host(J.val).reshape(-1, 3, 3)
+    # per block, relative to the block's own size (as in the small-case test)
+    d = np.abs(gval - val).reshape(len(ci), 9).max(axis=1)
+    size = np.maximum(np.abs(val).reshape(len(ci), 9).max(axis=1), 1e-300 * np.abs(val).max())
+    assert np.all(d <= 1e-12 * size), int(np.argmax(d / size))
+    assert rel_err(to_host(gb), b) <= 1e-12
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fullsize_spmv(B, O, cfg):
+    """The solver's SpMV (slot layout, the launch the benchmark times) and the
+    ABI's BSR SpMV against the oracle's: integer data bit for bit, the
+    Jacobian with alpha, beta to 1e-12."""
+    import torch
+    case, P, rp, ci, val, b = system(O, cfg)
+    n = case.n
+    rng = np.random.default_rng(40 + cfg)
+    ival = rng.integers(-512, 513, size=(len(ci), 3, 3)).astype(np.float64)
+    # diagonally dominant diagonal blocks: the solver handle's setup inverts
+    # them (and their saturation parts); integers keep every sum exact
+    diag = ci == np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    for c in range(3):
+        ival[diag, c, c] = 8192.0 + rng.integers(0, 512, size=int(diag.sum()))
+    ix = rng.integers(-512, 513, size=3 * n).astype(np.float64)
+    ref = O.bsr_spmv(rp, ci, ival, ix)
+    A = device_bsr(B, rp, ci, ival)
+    pc = B.bo_cpr_setup(A, (case.nx, case.ny, case.nz), B.bo_cpr_default_opts(use_amg=0, ftype=B.BO_F_BJ))
+    y = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    B.bo_cpr_spmv(pc, 1.0, to_dev(ix), 0.0, y)
+    assert np.array_equal(to_host(y), ref)
+    y.zero_()
+    B.bo_bsr_spmv(A, 1.0, to_dev(ix), 0.0, y)
+    assert np.array_equal(to_host(y), ref)
+    # the Jacobian itself, y = 0.5 A x - 2 y0
+    x = rng.standard_normal(3 * n)
+    y0 = rng.standard_normal(3 * n)
+    ref = 0.5 * O.bsr_spmv(rp, ci, val, x) - 2.0 * y0
+    A = device_bsr(B, rp, ci, val)
+    pc = B.bo_cpr_setup(A, (case.nx, case.ny, case.nz), B.bo_cpr_default_opts(use_amg=0, ftype=B.BO_F_BJ))
+    y = to_dev(y0)
+    B.bo_cpr_spmv(pc, 0.5, to_dev(x), -2.0, y)
+    assert rel_err(to_host(y), ref) <= 1e-12
+
+
+def test_fullsize_cpr_apply(B, O):
+    """The default CPR (quasi-IMPES, SA-AMG V-cycle with red-black Gauss-Seidel
+    on level 0, 8x8-tile block ILU(0)) on the 500k-cell system, whole
+    vectors against the oracle."""
+    case, P, rp, ci, val, b = system(O, 1)
+    opc = O.Cpr(P, rp, ci, val)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), B.bo_cpr_default_opts())
+    assert B.bo_cpr_levels(gpc) == opc.nlevels()
+    n = case.n
+    v = np.random.default_rng(7).standard_normal(3 * n)
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= 1e-10
+    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, b, 3 * n), opc.apply(b)) <= 1e-10
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fullsize_solve(B, O, cfg):
+    """bench.py's solve (default options) at full size: converged, a true FP64
+    residual <= 1e-6 recomputed with the oracle's SpMV, and the oracle's
+    iteration count within 10 %."""
+    import torch
+    case, P, rp, ci, val, b = system(O, cfg)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), B.bo_cpr_default_opts())
+    x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+    info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    assert info["converged"] and info["status"] == B.BO_OK
+    r = b - O.bsr_spmv(rp, ci, val, to_host(x))
+    true_rel = np.linalg.norm(r) / np.linalg.norm(b)
+    assert true_rel <= 1e-6
+    assert info["rel_residual"] == pytest.approx(true_rel, rel=1e-6, abs=1e-12)
+    _, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val))
+    io = oinfo["iterations"]
+    assert abs(info["iterations"] - io) <= max(1, math.ceil(0.1 * io))
