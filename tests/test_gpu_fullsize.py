@@ -33,6 +33,7 @@ def O():
 
 
 _SYSTEMS = {}
+_ORACLE_ITS = {}  # the FP64 oracle's iteration count per workload
 
 
 def system(O, cfg):
@@ -128,4 +129,28 @@ def test_fullsize_solve(B, O, cfg):
     assert info["rel_residual"] == pytest.approx(true_rel, rel=1e-6, abs=1e-12)
     _, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val))
     io = oinfo["iterations"]
+    _ORACLE_ITS[cfg] = io
     assert abs(info["iterations"] - io) <= max(1, math.ceil(0.1 * io))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fullsize_mixed_solve(B, O, prec):
+    """The mixed-precision forms on the 2M-cell system (the workload they are
+    benchmarked on): a true FP64 residual <= 1e-6 and no more iterations than
+    the FP64 oracle's plus 10 %."""
+    import torch
+    case, P, rp, ci, val, b = system(O, 2)
+    bp = dict(fp32=B.BO_PREC_FP32, bf16=B.BO_PREC_FP32_BF16)[prec]
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz),
+                         B.bo_cpr_default_opts(precision=bp))
+    x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+    info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    assert info["converged"] and info["status"] == B.BO_OK
+    r = b - O.bsr_spmv(rp, ci, val, to_host(x))
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
+    if 2 not in _ORACLE_ITS:
+        _, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val))
+        _ORACLE_ITS[2] = oinfo["iterations"]
+    io = _ORACLE_ITS[2]
+    assert info["iterations"] <= io + max(1, math.ceil(0.1 * io))
+
