@@ -209,6 +209,8 @@ typedef struct { int32_t nx, ny, nz, dual; } bo_grid;
  * decoupled pressure block, the AMG hierarchy on it, and the F-stage factors.
  * Keeps a private copy of A's values in its own layout; A may be freed after
  * return.  Synchronises `stream` (the hierarchy sizes are decided on the host).
+ * The F-stage factors are built on a second stream of the handle, forked from
+ * `stream` and joined back before return, beside the AMG setup.
  * The general form, for a block pattern other than a grid's 7-point stencil,
  * keeps A in BSR form and takes the pressure system over the first opts->npr
  * rows; its level-0 smoother must be Jacobi or l1-Jacobi.  With grid == NULL

@@ -120,6 +120,9 @@ struct bo_cpr {
     // work vectors
     bo::DBuf<double> rp_, dp_, t3a, t3b, t3c, wf;
     bo::DBuf<int32_t> flag;
+    bo::DBuf<int32_t> fflag;      // the F stage's singular-pivot flag (its own: it runs beside the AMG setup)
+    hipStream_t side = nullptr;   // second stream of the setup: the F stage's factorisation
+    hipEvent_t evs[2] = {};       // fork to and join from that stream
     bo::SetupWork sw;
     bo::Reducer red;
     bo::Krylov kr;

@@ -796,22 +796,27 @@ TileGeom geom(const bo_cpr *pc) {
 
 }  // namespace
 
-bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
+// Launches the F stage's factorisation on stream s and reads nothing back:
+// its singular-pivot flag (pc->fflag) is read by fstage_check, so the
+// factorisation can run on a stream of its own beside the AMG setup.
+bo_status fstage_launch(bo_cpr *pc, hipStream_t s) {
     long long n = pc->n;
     int st = store_of(pc);
-    BO_HIP(hipMemsetAsync(pc->flag.p, 0, sizeof(int32_t), s));
+    BO_TRY(pc->fflag.alloc(1));
+    int32_t *ff = pc->fflag.p;
+    BO_HIP(hipMemsetAsync(ff, 0, sizeof(int32_t), s));
     if (pc->o.ftype == BO_F_BJ) {
         BO_TRY(pc->einv.alloc(9 * n));  // FP64 size: large enough for every format
         void *E = pc->einv.p;
         if (pc->general) {
             const int32_t *rp = pc->Arp.p, *ci = pc->Aci.p;
             const double *v = pc->Aval.p;
-            if (st == ST_F64) k_bj_setup_bsr<ST_F64><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, E, pc->flag.p);
-            else if (st == ST_F32) k_bj_setup_bsr<ST_F32><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, E, pc->flag.p);
-            else k_bj_setup_bsr<ST_BF16><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, E, pc->flag.p);
-        } else if (st == ST_F64) k_bj_setup<ST_F64><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
-        else if (st == ST_F32) k_bj_setup<ST_F32><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
-        else k_bj_setup<ST_BF16><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, pc->flag.p);
+            if (st == ST_F64) k_bj_setup_bsr<ST_F64><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, E, ff);
+            else if (st == ST_F32) k_bj_setup_bsr<ST_F32><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, E, ff);
+            else k_bj_setup_bsr<ST_BF16><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, E, ff);
+        } else if (st == ST_F64) k_bj_setup<ST_F64><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, ff);
+        else if (st == ST_F32) k_bj_setup<ST_F32><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, ff);
+        else k_bj_setup<ST_BF16><<<grid_for(n), kBlock, 0, s>>>(n, pc->A.p, E, ff);
     } else {
         TileGeom T = geom(pc);
         size_t S = (size_t)T.slots();
@@ -820,9 +825,9 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
         if (ext) {
             if (st != ST_F64) return fail(BO_ERR_UNSUPPORTED, "F stage: the extended grid form's ILU is FP64 only");
             BO_TRY(pc->A.alloc(63 * N));
-            BO_HIP(hipMemsetAsync(pc->flag.p, 0, sizeof(int32_t), s));
+            BO_HIP(hipMemsetAsync(ff, 0, sizeof(int32_t), s));
             k_bsr_stencil_slots<<<grid_for(N), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->Arp.p, pc->Aci.p,
-                                                               pc->Aval.p, pc->A.p, pc->flag.p);
+                                                               pc->Aval.p, pc->A.p, ff);
             BO_TRY(pc->x_einv_f.alloc(9 * N));
         }
         // factor buffers sized for FP64; the FP32 and BF16 forms use a prefix
@@ -836,32 +841,37 @@ bo_status fstage_setup(bo_cpr *pc, hipStream_t s) {
         if (st == ST_F64) {
             k_ilu_pack<<<grid_for(T.slots()), kBlock, 0, s>>>(T, pc->A.p, (double2 *)pc->ilu_f.p,
                                                               (double2 *)pc->ilu_b.p, pc->ilu_slot.p);
-            k_ilu_chain<<<nb, 64, 0, s>>>(T, (double2 *)pc->ilu_f.p, (double2 *)pc->ilu_b.p, pc->flag.p,
+            k_ilu_chain<<<nb, 64, 0, s>>>(T, (double2 *)pc->ilu_f.p, (double2 *)pc->ilu_b.p, ff,
                                           ext ? pc->x_einv_f.p : nullptr);
         } else if (st == ST_F32) {
             k_ilu_factor<ST_F32><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p,
-                                                   pc->ilu_slot.p, pc->flag.p, nullptr);
+                                                   pc->ilu_slot.p, ff, nullptr);
         } else {
             k_ilu_factor<ST_BF16><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p,
-                                                    pc->ilu_slot.p, pc->flag.p, nullptr);
+                                                    pc->ilu_slot.p, ff, nullptr);
         }
         if (ext && pc->ncell > N) {
             BO_TRY(pc->x_einv_m.alloc(9 * N));
             BO_TRY(pc->x_amf.alloc(9 * N));
             BO_TRY(pc->x_afm.alloc(9 * N));
             k_dual_pivots<<<grid_for(N), kBlock, 0, s>>>((int)N, pc->Arp.p, pc->Aci.p, pc->Aval.p, pc->x_einv_f.p,
-                                                         pc->x_einv_m.p, pc->x_amf.p, pc->x_afm.p, pc->flag.p);
+                                                         pc->x_einv_m.p, pc->x_amf.p, pc->x_afm.p, ff);
         }
         if (ext && pc->n > pc->ncell) {
             int cnt = pc->n - pc->ncell;
             BO_TRY(pc->x_einv_w.alloc(9 * (size_t)cnt));
             k_rows_inv<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->Arp.p, pc->Aci.p, pc->Aval.p,
-                                                        pc->x_einv_w.p, pc->flag.p);
+                                                        pc->x_einv_w.p, ff);
         }
     }
     BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+// The F stage's flag, once the work fstage_launch queued is ordered before s.
+bo_status fstage_check(bo_cpr *pc, hipStream_t s) {
     int32_t bad = 0;
-    HostRead rd{pc->flag.p, sizeof bad, &bad};
+    HostRead rd{pc->fflag.p, sizeof bad, &bad};
     BO_TRY(host_reads(&rd, 1, s));
     if (bad) return fail(BO_ERR_SINGULAR_BLOCK, "F stage: singular 3x3 pivot block");
     return BO_OK;

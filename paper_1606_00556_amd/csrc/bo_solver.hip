@@ -28,7 +28,8 @@ bo_status amg_vcycle_ptr(bo_cpr *pc, const double *b, const double **res, hipStr
 bo_status amg_vcycle_ptr_f32(bo_cpr *pc, const float *b, const float **res, hipStream_t s);
 bo_status amg_make_f32(bo_cpr *pc, hipStream_t s);
 bo_status qi_restrict_f32(bo_cpr *pc, const double *v, float *rp, hipStream_t s);
-bo_status fstage_setup(bo_cpr *pc, hipStream_t s);
+bo_status fstage_launch(bo_cpr *pc, hipStream_t s);
+bo_status fstage_check(bo_cpr *pc, hipStream_t s);
 bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, hipStream_t s);
 bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, hipStream_t s);
 template <typename T>
@@ -235,11 +236,28 @@ static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_o
         BO_TRY(bsr_to_slots(pc->g, A->rowptr, A->colind, A->val, pc->A.p, s));
     }
     BO_TRY(qi_decouple(pc, s));
-    if (pc->o.use_amg) {
-        BO_TRY(amg_setup(pc, s));
-        if (pc->o.precision != BO_PREC_FP64) BO_TRY(amg_make_f32(pc, s));
+    // The F stage's factors depend on A alone: they are built on a second
+    // stream, forked from s here and joined back below, while the AMG setup
+    // (many small launches and a few host reads) runs on s.
+    if (!pc->side) BO_HIP(hipStreamCreateWithFlags(&pc->side, hipStreamNonBlocking));
+    for (hipEvent_t &e : pc->evs)
+        if (!e) BO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    BO_HIP(hipEventRecord(pc->evs[0], s));
+    BO_HIP(hipStreamWaitEvent(pc->side, pc->evs[0], 0));
+    bo_status fst = fstage_launch(pc, pc->side);
+    bo_status ast = BO_OK;
+    if (fst == BO_OK && pc->o.use_amg) {
+        ast = amg_setup(pc, s);
+        if (ast == BO_OK && pc->o.precision != BO_PREC_FP64) ast = amg_make_f32(pc, s);
     }
-    BO_TRY(fstage_setup(pc, s));
+    // join on every path: nothing may still run on the side stream when this returns
+    BO_HIP(hipEventRecord(pc->evs[1], pc->side));
+    BO_HIP(hipStreamWaitEvent(s, pc->evs[1], 0));
+    if (fst != BO_OK || ast != BO_OK) {
+        (void)hipStreamSynchronize(s);
+        return fst != BO_OK ? fst : ast;
+    }
+    BO_TRY(fstage_check(pc, s));
     BO_TRY(pc->rp_.alloc(n));
     BO_TRY(pc->dp_.alloc(n));
     BO_TRY(pc->t3a.alloc(3 * n));
@@ -330,6 +348,9 @@ extern "C" void bo_cpr_destroy(bo_cpr *pc) {
         if (e) (void)hipEventDestroy(e);
     if (pc->gexec) (void)hipGraphExecDestroy(pc->gexec);
     if (pc->cap_stream) (void)hipStreamDestroy(pc->cap_stream);
+    for (hipEvent_t &e : pc->evs)
+        if (e) (void)hipEventDestroy(e);
+    if (pc->side) (void)hipStreamDestroy(pc->side);
     delete pc;
 }
 
