@@ -192,7 +192,7 @@ typedef struct {
 } bo_cpr_opts;
 
 /* Fills `o` [host] with the defaults: PF, tiled ILU0 8x8, theta 0.08,
- * coarse_max 256, 12 levels, red-black GS, 1 sweep, AMG on, block QI, FP64,
+ * coarse_max 192, 12 levels, red-black GS, 1 sweep, AMG on, block QI, FP64,
  * l1-Jacobi on the coarse levels. */
 void bo_cpr_default_opts(bo_cpr_opts *o);
 

@@ -277,7 +277,7 @@ def qi_decouple(rp, ci, val, mode=1):
     return w, app
 
 
-def cpr_opts(fpf=0, ftype=F_ILU_TILED, tile=(8, 8), theta=0.08, coarse_max=256, max_levels=12,
+def cpr_opts(fpf=0, ftype=F_ILU_TILED, tile=(8, 8), theta=0.08, coarse_max=192, max_levels=12,
              smoother=SMOOTH_GS, sweeps=1, use_amg=1, qi_mode=QI_BLOCK, precision=0,
              csmoother=1, npr=0) -> CprOpts:
     """precision: PREC_FP64, or the emulated mixed forms PREC_FP32 / PREC_FP32_BF16;

@@ -171,7 +171,7 @@ extern "C" void bo_cpr_default_opts(bo_cpr_opts *o) {
     o->tile_x = 8;
     o->tile_y = 8;
     o->theta = 0.08;
-    o->coarse_max = 256;
+    o->coarse_max = 192;
     o->max_levels = 12;
     o->smoother = BO_SMOOTH_GS;
     o->sweeps = 1;

@@ -49,7 +49,9 @@ def matching_opts(O, B, ftype="tiled", fpf=0, tile=(8, 8), coarse_max=256, smoot
                   use_amg=1, qi="block", theta=0.08, precision="fp64", csmoother="l1", sell_rows=0):
     """The same CPR configuration for the oracle and the library (sell_rows:
     the library's storage choice for large coarse matrices, not a change of
-    the method)."""
+    the method; coarse_max 256, above the default 192, keeps the coarsest
+    levels of the small workloads above the register Gauss-Jordan's 192 rows,
+    so the global-memory elimination stays under test)."""
     oft = dict(tiled=O.F_ILU_TILED, bj=O.F_BJ)[ftype]
     bft = dict(tiled=B.BO_F_ILU_TILED, bj=B.BO_F_BJ)[ftype]
     osm = dict(gs=O.SMOOTH_GS, jacobi=O.SMOOTH_JACOBI)[smoother]

@@ -46,7 +46,7 @@ def test_binding_reports_errors_without_gpu_work():
     assert b"NULL" in L.bo_last_error()
     o = bo.BoCprOpts()
     L.bo_cpr_default_opts(C.byref(o))
-    assert o.tile_x == 8 and o.ftype == bo.BO_F_ILU_TILED and o.coarse_max == 256 and o.sell_rows == 0
+    assert o.tile_x == 8 and o.ftype == bo.BO_F_ILU_TILED and o.coarse_max == 192 and o.sell_rows == 0
     f = bo.BoFgmresOpts()
     L.bo_fgmres_default_opts(C.byref(f))
     assert f.m == 30 and f.orth == 2 and f.graph == 0
