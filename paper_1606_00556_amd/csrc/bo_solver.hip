@@ -655,7 +655,7 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
             }
             double hn = std::sqrt(hq[2 * (m + 1)]);
             for (int i = 0; i <= j; i++)
-                H[(size_t)i * m + j] = opts->orth == 1 ? hq[i] + hq[m + 1 + i] : hq[i];
+                H[(size_t)i * m + j] = orth == 1 ? hq[i] + hq[m + 1 + i] : hq[i];
             H[(size_t)(j + 1) * m + j] = hn;
             bool breakdown = !(hn > 1e-300);
             if (!std::isfinite(hn)) { status = fail(BO_ERR_NONFINITE, "bo_fgmres_solve: NaN in the iteration"); goto done; }

@@ -139,6 +139,27 @@ def test_zero_network_changes_nothing(B, O):
     assert np.array_equal(xs[0], xs[1])
 
 
+def test_network_solve_with_default_options_equals_cgs2(B, O):
+    """With a network attached the solver takes CGS2 whatever form was
+    requested: a solve with the default options (orth 2 requested) equals an
+    explicit orth = 1 solve bit for bit, with a network that does change the
+    iterates."""
+    import torch
+    case = ragged_case()
+    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
+    nn = B.Nn(cg.cnn_init(25, last_scale=1.0))
+    B.bo_cpr_attach_nn(gpc, nn, to_dev(np.log(case.kx)))
+    xs, infos = [], []
+    for fo in (B.bo_fgmres_default_opts(), B.bo_fgmres_default_opts(orth=1)):
+        x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x, fo))
+        xs.append(to_host(x))
+    assert infos[0]["iterations"] == infos[1]["iterations"] and infos[0]["nn_used"] == infos[1]["nn_used"]
+    assert np.array_equal(xs[0], xs[1])
+    r = b - O.bsr_spmv(rp, ci, val, xs[0])
+    assert infos[0]["converged"] and np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+
+
 def test_collect_pairs_matches_direct_solve(B, O):
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla

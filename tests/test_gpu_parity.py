@@ -232,6 +232,26 @@ def test_fgmres_gram_schmidt_forms(B, O, name, orth):
     assert abs(ginfo["iterations"] - io) <= max(1, math.ceil(0.1 * io))
 
 
+def test_delayed_request_falls_back_to_cgs2_exactly(B, O):
+    """With m > 31 the delayed form (orth 2, the default request) is not
+    available and the solver runs CGS2: the Hessenberg columns must then sum
+    both projections, so the run equals an explicit orth = 1 run bit for
+    bit."""
+    import torch
+    case = ragged_case()
+    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
+    xs, infos = [], []
+    for orth in (2, 1):
+        x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(m=40, orth=orth)))
+        xs.append(to_host(x))
+    assert infos[0]["converged"] and infos[0]["iterations"] == infos[1]["iterations"]
+    assert infos[0]["est_residual"] == infos[1]["est_residual"]
+    assert np.array_equal(xs[0], xs[1])
+    r = b - O.bsr_spmv(rp, ci, val, xs[0])
+    assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+
+
 def test_fgmres_delayed_small_restart(B, O):
     """The delayed form across restarts (m = 3, m = 1) and when the iteration
     limit ends a cycle early."""
