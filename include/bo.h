@@ -140,6 +140,25 @@ bo_status bo_jacobian_bsr_size(const bo_problem *p, int32_t *nbrows, int32_t *nn
 bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, const double *x_new, double dt,
                           bo_bsr *J, double *b, void *stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same Jacobian and
+ * right-hand side as bo_jacobian_bsr, bit for bit, from the same kernels,
+ * without any allocation (no hipMalloc / hipFree, no pinned host memory, no
+ * host synchronisation, no memset).  Its only scratch memory, the block sums
+ * of the row-pointer scan, is a fixed device array of the library (one
+ * 32-bit word per 1024 block rows, at most 65536 words = 256 KiB per GPU,
+ * held until the process ends); the row counts are staged in J->colind
+ * before the value kernels overwrite it.  Fails with BO_ERR_INVALID_ARG for
+ * more than bo_jacobian_bsr_noalloc_max_rows() block rows.  Calls on one GPU
+ * share that array: calls that overlap in time on one GPU (on different
+ * streams, or from different host threads) race and must be serialised by
+ * the caller.  Unlike bo_jacobian_bsr it does not read the pattern size back
+ * to check it. */
+bo_status bo_jacobian_bsr_noalloc(const bo_problem *p, const double *x_old, const double *x_new, double dt,
+                                  bo_bsr *J, double *b, void *stream);
+/* Largest nbrows bo_jacobian_bsr_noalloc accepts (2^26). */
+int32_t bo_jacobian_bsr_noalloc_max_rows(void);
+
 /* ---- Basic operations (Section 3.4) ---------------------------------- */
 
 /* y = alpha*A*x + beta*y on the BSR layout (beta == 0: y is not read). */

@@ -34,6 +34,7 @@ EXPORTS = [
     "bo_cpr_level_copy", "bo_cpr_copy_weights", "bo_fgmres_default_opts", "bo_fgmres_solve",
     "bo_nn_create", "bo_nn_destroy", "bo_nn_num_params", "bo_nn_set_params", "bo_nn_get_params",
     "bo_nn_forward", "bo_nn_backward", "bo_nn_adam_step", "bo_cpr_attach_nn", "bo_cpr_collect_pairs",
+    "bo_jacobian_bsr_noalloc", "bo_jacobian_bsr_noalloc_max_rows",
 ]
 
 
@@ -113,6 +114,9 @@ def lib():
     L.bo_version.restype = C.c_char_p
     L.bo_jacobian_bsr_size.argtypes = [C.POINTER(BoProblem), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.bo_jacobian_bsr.argtypes = [C.POINTER(BoProblem), vp, vp, C.c_double, C.POINTER(BoBsr), vp, vp]
+    L.bo_jacobian_bsr_noalloc.argtypes = [C.POINTER(BoProblem), vp, vp, C.c_double, C.POINTER(BoBsr), vp, vp]
+    L.bo_jacobian_bsr_noalloc_max_rows.argtypes = []
+    L.bo_jacobian_bsr_noalloc_max_rows.restype = C.c_int32
     L.bo_bsr_spmv.argtypes = [C.POINTER(BoBsr), C.c_double, vp, C.c_double, vp, vp]
     L.bo_cpr_default_opts.argtypes = [C.POINTER(BoCprOpts)]
     L.bo_cpr_default_opts.restype = None
@@ -145,7 +149,8 @@ def lib():
     L.bo_cpr_collect_pairs.argtypes = [vp, vp, C.c_int32, C.c_double, vp, vp, C.POINTER(C.c_int32), vp]
     for f in EXPORTS:
         if f not in ("bo_last_error", "bo_version", "bo_cpr_default_opts", "bo_cpr_destroy",
-                     "bo_fgmres_default_opts", "bo_nn_destroy", "bo_nn_num_params"):
+                     "bo_fgmres_default_opts", "bo_nn_destroy", "bo_nn_num_params",
+                     "bo_jacobian_bsr_noalloc_max_rows"):
             getattr(L, f).restype = st
     _lib = L
     return L
@@ -243,6 +248,19 @@ def bo_jacobian_bsr(p: DeviceProblem, x_old, x_new, dt: float, J: Optional[Devic
     _check(lib().bo_jacobian_bsr(p.ref, _ptr(x_old), _ptr(x_new), float(dt), C.byref(s), _ptr(b),
                                  _stream(stream)))
     return J, b
+
+
+def bo_jacobian_bsr_noalloc(p: DeviceProblem, x_old, x_new, dt: float, J: DeviceBsr, b, stream=None):
+    """bo_jacobian_bsr without any allocation in the library; J and b are
+    the caller's (sizes from bo_jacobian_bsr_size)."""
+    s = J.s
+    _check(lib().bo_jacobian_bsr_noalloc(p.ref, _ptr(x_old), _ptr(x_new), float(dt), C.byref(s), _ptr(b),
+                                         _stream(stream)))
+    return J, b
+
+
+def bo_jacobian_bsr_noalloc_max_rows() -> int:
+    return int(lib().bo_jacobian_bsr_noalloc_max_rows())
 
 
 def bo_bsr_spmv(A: DeviceBsr, alpha: float, x, beta: float, y, stream=None):

@@ -22,6 +22,7 @@
 // matrix rows, a third the well terms (one thread per well; perforated cells
 // are distinct), including the well rows and the well columns of the
 // perforated cells (the last block of their rows).
+#include <mutex>
 #include "bo_common.hpp"
 
 namespace bo {
@@ -526,10 +527,10 @@ __global__ void k_jac_wells(GridG G, Fl f, const double *__restrict__ xn, int nw
 using namespace bo;
 
 namespace {
-// fixed-rate wells and the pattern sizes of a problem (host)
+// pattern sizes of a problem (host); fixed-rate well w's block row is
+// cells + (the number of fixed-rate wells before w)
 struct Layout {
     long long n = 0, cells = 0, rows = 0, nnz = 0;
-    std::vector<int32_t> well_row;
 };
 
 bo_status layout_of(const bo_problem *p, Layout &L) {
@@ -542,7 +543,6 @@ bo_status layout_of(const bo_problem *p, Layout &L) {
     L.cells = n * (p->dual ? 2 : 1);
     L.nnz = n + 2 * faces + (p->dual ? 3 * n : 0);
     L.rows = L.cells;
-    L.well_row.assign(p->nwells, -1);
     for (int w = 0; w < p->nwells; w++) {
         const bo_well &W = p->wells[w];
         if (W.control == BO_CTRL_BHP) continue;
@@ -552,12 +552,86 @@ bo_status layout_of(const bo_problem *p, Layout &L) {
             return fail(BO_ERR_INVALID_ARG, "well " + std::to_string(w) +
                                                 ": water rate needs an injector, liquid rate a producer");
         long long nperf = (long long)W.k_bot - W.k_top + 1;
-        L.well_row[w] = (int32_t)L.rows;
         L.rows++;
         L.nnz += 2 * nperf + 1;
     }
     if (L.rows >= (1LL << 31) / 8 || L.nnz >= (1LL << 31))
         return fail(BO_ERR_INVALID_ARG, "grid too large for 32-bit block indices");
+    return BO_OK;
+}
+
+// Argument and well checks shared by both entry points (no heap use: wells
+// are vertical, so two of them share a cell exactly when they sit in the
+// same column and their layer ranges overlap).
+bo_status check_args(const bo_problem *p, const double *x_old, const double *x_new, double dt, const bo_bsr *J,
+                     const double *b) {
+    if (!x_old || !x_new || !J || !b || !J->rowptr || !J->colind || !J->val)
+        return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL pointer");
+    if (!(dt > 0.0)) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: dt must be > 0");
+    if (!p->kx || !p->ky || !p->kz || !p->phi0) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL field");
+    if (p->dual && (!p->km || !p->phim || !(p->sigma > 0.0)))
+        return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: dual porosity needs km, phim and sigma > 0");
+    if (p->fluid.nw < 1 || p->fluid.no < 1 || p->fluid.ng < 1)
+        return fail(BO_ERR_INVALID_ARG, "Corey exponents must be >= 1");
+    for (int w = 0; w < p->nwells; w++) {
+        const bo_well &W = p->wells[w];
+        if (W.i < 0 || W.i >= p->nx || W.j < 0 || W.j >= p->ny || W.k_top < 0 || W.k_bot >= p->nz ||
+            W.k_top > W.k_bot || !(W.rw > 0.0))
+            return fail(BO_ERR_INVALID_ARG, "well " + std::to_string(w) + " is outside the grid or malformed");
+        for (int v = 0; v < w; v++) {
+            const bo_well &U = p->wells[v];
+            if (U.i == W.i && U.j == W.j && U.k_top <= W.k_bot && W.k_top <= U.k_bot)
+                return fail(BO_ERR_INVALID_ARG, "two perforations share a cell");
+        }
+    }
+    return BO_OK;
+}
+
+// Fills chunk ch with wells w0.. (at most kWellChunk) and their block rows
+// (next_row: the row of the next fixed-rate well, advanced here).
+int chunk_of(const bo_problem *p, int w0, long long &next_row, WellChunk &ch) {
+    int c = std::min(kWellChunk, p->nwells - w0);
+    for (int q = 0; q < c; q++) {
+        ch.w[q] = p->wells[w0 + q];
+        ch.row[q] = ch.w[q].control == BO_CTRL_BHP ? -1 : (int32_t)next_row++;
+    }
+    return c;
+}
+
+// Row counts of the pattern into cnt (rows entries).
+bo_status launch_counts(const bo_problem *p, const Layout &Ly, int32_t *cnt, hipStream_t s) {
+    k_row_counts<<<grid_for(Ly.n), kBlock, 0, s>>>(p->nx, p->ny, p->nz, p->dual, cnt);
+    long long next_row = Ly.cells;
+    for (int w0 = 0; w0 < p->nwells; w0 += kWellChunk) {
+        WellChunk ch{};
+        int c = chunk_of(p, w0, next_row, ch);
+        k_well_counts<<<1, kWellChunk, 0, s>>>(p->nx, p->ny, c, ch, cnt);
+    }
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+
+// Blocks and right-hand side, once J->rowptr holds the pattern's row pointers.
+bo_status launch_values(const bo_problem *p, const Layout &Ly, const double *x_old, const double *x_new, double dt,
+                        bo_bsr *J, double *b, hipStream_t s) {
+    GridG G{p->nx, p->ny, p->nz, p->dx, p->dy, p->dz, p->top_depth, p->kx, p->ky, p->kz, p->phi0,
+            p->dual, p->km, p->phim, p->sigma};
+    const bo_fluid &q = p->fluid;
+    Fl f{q.p_ref, q.Bw0, q.cw, q.Bo0, q.co, q.Bg0, q.cg, q.Rs0, q.crs, q.mu_w, q.mu_o, q.mu_g, q.c_r,
+         q.rho_wsc, q.rho_osc, q.rho_gsc, q.swc, q.sor, q.sorg, q.sgc, q.nw, q.no, q.ng,
+         q.tcoef, q.rb_ft3, q.grav, q.gravity, q.inj_total_mobility};
+    double acc = p->dx * p->dy * p->dz / (q.rb_ft3 * dt);
+    k_jac_cells<<<grid_for(Ly.n), kBlock, 0, s>>>(G, f, x_old, x_new, acc, J->rowptr, J->colind, J->val, b);
+    if (p->dual)
+        k_jac_matrix<<<grid_for(Ly.n), kBlock, 0, s>>>(G, f, x_old, x_new, acc, J->rowptr, J->colind, J->val, b);
+    BO_HIP(hipGetLastError());
+    long long next_row = Ly.cells;
+    for (int w0 = 0; w0 < p->nwells; w0 += kWellChunk) {
+        WellChunk ch{};
+        int c = chunk_of(p, w0, next_row, ch);
+        k_jac_wells<<<c, 64, 0, s>>>(G, f, x_new, c, ch, J->rowptr, J->colind, J->val, b);
+        BO_HIP(hipGetLastError());
+    }
     return BO_OK;
 }
 }  // namespace
@@ -576,65 +650,74 @@ extern "C" bo_status bo_jacobian_bsr(const bo_problem *p, const double *x_old, c
     if (!p) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL problem");
     Layout Ly;
     BO_TRY(layout_of(p, Ly));
-    const int32_t rows = (int32_t)Ly.rows, nnz = (int32_t)Ly.nnz, n = (int32_t)Ly.n;
-    if (!x_old || !x_new || !J || !b || !J->rowptr || !J->colind || !J->val)
-        return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL pointer");
-    if (!(dt > 0.0)) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: dt must be > 0");
-    if (!p->kx || !p->ky || !p->kz || !p->phi0) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: NULL field");
-    if (p->dual && (!p->km || !p->phim || !(p->sigma > 0.0)))
-        return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr: dual porosity needs km, phim and sigma > 0");
-    // wells: validate on the host, no shared perforated cells
-    std::vector<long long> cells;
-    for (int w = 0; w < p->nwells; w++) {
-        const bo_well &W = p->wells[w];
-        if (W.i < 0 || W.i >= p->nx || W.j < 0 || W.j >= p->ny || W.k_top < 0 || W.k_bot >= p->nz ||
-            W.k_top > W.k_bot || !(W.rw > 0.0))
-            return fail(BO_ERR_INVALID_ARG, "well " + std::to_string(w) + " is outside the grid or malformed");
-        for (int k = W.k_top; k <= W.k_bot; k++) cells.push_back(W.i + (long long)p->nx * (W.j + (long long)p->ny * k));
-    }
-    std::vector<long long> sorted = cells;
-    std::sort(sorted.begin(), sorted.end());
-    for (size_t t = 1; t < sorted.size(); t++)
-        if (sorted[t] == sorted[t - 1]) return fail(BO_ERR_INVALID_ARG, "two perforations share a cell");
+    BO_TRY(check_args(p, x_old, x_new, dt, J, b));
+    const int32_t rows = (int32_t)Ly.rows, nnz = (int32_t)Ly.nnz;
     hipStream_t s = (hipStream_t)stream;
     J->nbrows = rows;
     J->nnzb = nnz;
     int32_t *cnt = nullptr;
     BO_TRY(scratch_get(SC_JAC_CNT, sizeof(int32_t) * (size_t)rows, (void **)&cnt));
-    k_row_counts<<<grid_for(n), kBlock, 0, s>>>(p->nx, p->ny, p->nz, p->dual, cnt);
-    auto chunk_of = [&](int w0, WellChunk &ch) {
-        int c = std::min(kWellChunk, p->nwells - w0);
-        for (int q = 0; q < c; q++) {
-            ch.w[q] = p->wells[w0 + q];
-            ch.row[q] = Ly.well_row[w0 + q];
-        }
-        return c;
-    };
-    for (int w0 = 0; w0 < p->nwells; w0 += kWellChunk) {
-        WellChunk ch{};
-        int c = chunk_of(w0, ch);
-        k_well_counts<<<1, kWellChunk, 0, s>>>(p->nx, p->ny, c, ch, cnt);
-    }
-    BO_HIP(hipGetLastError());
+    BO_TRY(launch_counts(p, Ly, cnt, s));
     int32_t total = 0;
     BO_TRY(scan_counts(cnt, J->rowptr, rows, &total, s));
     if (total != nnz) return fail(BO_ERR_HIP, "row count scan disagrees with the pattern size");
-    GridG G{p->nx, p->ny, p->nz, p->dx, p->dy, p->dz, p->top_depth, p->kx, p->ky, p->kz, p->phi0,
-            p->dual, p->km, p->phim, p->sigma};
-    const bo_fluid &q = p->fluid;
-    Fl f{q.p_ref, q.Bw0, q.cw, q.Bo0, q.co, q.Bg0, q.cg, q.Rs0, q.crs, q.mu_w, q.mu_o, q.mu_g, q.c_r,
-         q.rho_wsc, q.rho_osc, q.rho_gsc, q.swc, q.sor, q.sorg, q.sgc, q.nw, q.no, q.ng,
-         q.tcoef, q.rb_ft3, q.grav, q.gravity, q.inj_total_mobility};
-    if (f.nw < 1 || f.no < 1 || f.ng < 1) return fail(BO_ERR_INVALID_ARG, "Corey exponents must be >= 1");
-    double acc = p->dx * p->dy * p->dz / (q.rb_ft3 * dt);
-    k_jac_cells<<<grid_for(n), kBlock, 0, s>>>(G, f, x_old, x_new, acc, J->rowptr, J->colind, J->val, b);
-    if (p->dual) k_jac_matrix<<<grid_for(n), kBlock, 0, s>>>(G, f, x_old, x_new, acc, J->rowptr, J->colind, J->val, b);
-    BO_HIP(hipGetLastError());
-    for (int w0 = 0; w0 < p->nwells; w0 += kWellChunk) {
-        WellChunk ch{};
-        int c = chunk_of(w0, ch);
-        k_jac_wells<<<c, 64, 0, s>>>(G, f, x_new, c, ch, J->rowptr, J->colind, J->val, b);
-        BO_HIP(hipGetLastError());
+    return launch_values(p, Ly, x_old, x_new, dt, J, b, s);
+}
+
+// ---- the variant that allocates nothing ------------------------------------------
+// Its only scratch is the row-pointer scan's block sums, one word per 1024
+// block rows, in this array.  Each GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as an
+// address: the device address comes from hipGetSymbolAddress, once per device.
+static constexpr int kNoAllocScanWords = 1 << 16;
+static __device__ __align__(256) int32_t scratch[kNoAllocScanWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t *g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's address of `scratch` (looked up on the first call on
+// that device, with that device current)
+bo_status scratch_address(int32_t **out) {
+    int dev = -1;
+    BO_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(BO_ERR_UNSUPPORTED, "bo_jacobian_bsr_noalloc: device index");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(BO_ERR_HIP, std::string("bo_jacobian_bsr_noalloc: hipGetSymbolAddress: ") +
+                                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = (int32_t *)ptr;
     }
+    *out = g_scratch_ptr[dev];
     return BO_OK;
+}
+}  // namespace
+
+extern "C" int32_t bo_jacobian_bsr_noalloc_max_rows(void) { return kNoAllocScanWords * 1024; }
+
+extern "C" bo_status bo_jacobian_bsr_noalloc(const bo_problem *p, const double *x_old, const double *x_new,
+                                             double dt, bo_bsr *J, double *b, void *stream) {
+    if (!p) return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr_noalloc: NULL problem");
+    Layout Ly;
+    BO_TRY(layout_of(p, Ly));
+    BO_TRY(check_args(p, x_old, x_new, dt, J, b));
+    if (Ly.rows > (long long)bo_jacobian_bsr_noalloc_max_rows())
+        return fail(BO_ERR_INVALID_ARG, "bo_jacobian_bsr_noalloc: " + std::to_string(Ly.rows) +
+                                            " block rows exceed the maximum of " +
+                                            std::to_string(bo_jacobian_bsr_noalloc_max_rows()));
+    int32_t *sums = nullptr;
+    BO_TRY(scratch_address(&sums));
+    const int32_t rows = (int32_t)Ly.rows;
+    hipStream_t s = (hipStream_t)stream;
+    J->nbrows = rows;
+    J->nnzb = (int32_t)Ly.nnz;
+    // the row counts go into J->colind (nnzb >= rows: every row holds its
+    // diagonal block), which the value kernels overwrite after the scan
+    BO_TRY(launch_counts(p, Ly, J->colind, s));
+    BO_TRY(scan_counts_async(J->colind, J->rowptr, rows, sums, s));
+    return launch_values(p, Ly, x_old, x_new, dt, J, b, s);
 }
