@@ -211,6 +211,24 @@ int or_fgmres(int n, const int32_t *rowptr, const int32_t *colind, const double 
 int or_arnoldi(int n, const int32_t *rowptr, const int32_t *colind, const double *val,
                or_cpr *pc, const double *b, int k, int orth, double *Z, double *V, double *H);
 
+/* ---- Exact elimination of the matrix cells (dual porosity) ------------- */
+/* For a dual-porosity system (rows: N fracture cells, N matrix cells, nw
+ * fixed-rate well rows) the reduced system over the fracture cells and the
+ * wells: S_gg = A_ff,gg - A_fm A_mm^-1 A_mf on each fracture row's diagonal,
+ * every other block copied; well row 2N+w and well column 2N+w become N+w.
+ * or_condense_pattern returns the reduced block count (srp / sci may be NULL)
+ * or -1 for a pattern that is not a dual-porosity one; or_condense_values
+ * fills sval on that pattern and, per location, A_mm^-1 (minv), A_mf (amf)
+ * and W = A_fm A_mm^-1 (wfm), 9 doubles each. */
+int or_condense_pattern(int N, int nw, const int32_t *rp, const int32_t *ci, int32_t *srp, int32_t *sci);
+int or_condense_values(int N, int nw, const int32_t *rp, const int32_t *ci, const double *val,
+                       double *sval, double *minv, double *amf, double *wfm);
+/* b' = (b_f - W b_m, b_w) (3(N+nw)) */
+void or_condense_rhs(int N, int nw, const double *b, const double *wfm, double *br);
+/* x = (x'_f, A_mm^-1 (b_m - A_mf x'_f), x'_w) (3(2N+nw)) */
+void or_condense_back(int N, int nw, const double *b, const double *xr, const double *minv, const double *amf,
+                      double *x);
+
 #ifdef __cplusplus
 }
 #endif

@@ -180,3 +180,62 @@ def test_tiled_ilu_with_one_tile_equals_natural_order(oracle_lib):
     a2 = O.Cpr(P2, rp2, ci2, val2, ftype=O.F_ILU_TILED, tile=(8, 8), use_amg=0).fstage(v2)
     b2 = O.Cpr(P2, rp2, ci2, val2, ftype=O.F_ILU_NATURAL, use_amg=0).fstage(v2)
     assert np.linalg.norm(a2 - b2) > 1e-8 * np.linalg.norm(b2)
+
+
+# ---- exact elimination of the matrix cells ----------------------------------------
+def _dense_schur(O, c, rp, ci, val):
+    """The plain definition: S = D_KK - D_KM D_MM^-1 D_MK on the dense matrix,
+    K = fracture and well unknowns, M = matrix unknowns (numpy's LU solve)."""
+    D = O.bsr_to_dense(rp, ci, val)
+    n = c.n
+    mu = np.arange(3 * n, 6 * n)
+    ku = np.concatenate([np.arange(3 * n), np.arange(6 * n, D.shape[0])])
+    return D, ku, mu, D[np.ix_(ku, ku)] - D[np.ix_(ku, mu)] @ np.linalg.solve(D[np.ix_(mu, mu)], D[np.ix_(mu, ku)])
+
+
+def test_condensed_operator_is_the_schur_complement(oracle_lib):
+    O = oracle_lib
+    c = case()
+    P = O.Problem(c)
+    rp, ci, val, R = O.jacobian(P)
+    cond = O.Condensed(P, rp, ci, val, ftype=O.F_BJ, smoother=O.SMOOTH_L1)
+    D, ku, mu, S = _dense_schur(O, c, rp, ci, val)
+    Sc = O.bsr_to_dense(cond.srp, cond.sci, cond.sval)
+    assert np.linalg.norm(Sc - S) <= 1e-12 * np.linalg.norm(S)
+    # the reduced pattern is the single-porosity one of the same grid and wells
+    rrp, rci = O.pattern(cond.red_prob)
+    assert np.array_equal(rrp, cond.srp) and np.array_equal(rci, cond.sci)
+    # right-hand side and back-substitution against the dense elimination
+    b = -R
+    br = cond.reduce(b)
+    ref = b[ku] - D[np.ix_(ku, mu)] @ np.linalg.solve(D[np.ix_(mu, mu)], b[mu])
+    assert np.linalg.norm(br - ref) <= 1e-12 * np.linalg.norm(ref)
+    xk = np.linalg.solve(S, br)
+    x = cond.back(b, xk)
+    xd = np.linalg.solve(D, b)
+    assert np.linalg.norm(x - xd) <= 1e-9 * np.linalg.norm(xd)
+    assert np.linalg.norm(b - D @ x) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_condensed_cpr_fgmres_solves_the_full_system(oracle_lib):
+    O = oracle_lib
+    c = cg.make_dual_case(12, 10, 6, seed=5, wells=[cg.Well(1, 1, 0, 5, "inj", "wrat", 900.0),
+                                                     cg.Well(10, 8, 0, 5, "prod", "lrat", 800.0),
+                                                     cg.Well(6, 2, 1, 4, "prod", "bhp", 2500.0)])
+    P = O.Problem(c)
+    rp, ci, val, R = O.jacobian(P)
+    b = -R
+    cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, fpf=1, coarse_max=40)
+    x, info = O.condensed_fgmres(rp, ci, val, b, cond)
+    assert info["converged"] and info["passes"] == 1
+    r = b - O.bsr_spmv(rp, ci, val, x)
+    assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+    xd = O.dense_solve(O.bsr_to_dense(rp, ci, val), b)
+    assert np.linalg.norm(x - xd) <= 1e-3 * np.linalg.norm(xd)
+    # the preconditioner of the full system: an exact solve of the matrix rows
+    # for any input (its output satisfies every matrix-cell equation)
+    v = np.random.default_rng(4).standard_normal(len(b))
+    z = cond.apply(v)
+    Az = O.bsr_spmv(rp, ci, val, z)
+    n = c.n
+    assert np.linalg.norm((Az - v)[3 * n:6 * n]) <= 1e-12 * np.linalg.norm(v[3 * n:6 * n])
