@@ -130,7 +130,7 @@ def main():
         B.bo_cpr_update(pc, J)
         if e: e[2].record(stream)
         x.zero_()
-        info = B.bo_fgmres_solve(pc, b, x, fopts if record is None else fopts_timed)
+        info = B.bo_fgmres_solve(pc, J, b, x, fopts if record is None else fopts_timed)
         if e: e[3].record(stream)
         if not info["converged"]:
             raise RuntimeError(f"system {i} did not converge: {info}")

@@ -12,7 +12,8 @@
  *   - Section 3.2: block structure of the Jacobian, quasi-IMPES decoupling, and
  *     the CPR-FPF preconditioner (RAS with ILU(0) subdomain solves, AMG on the
  *     pressure block);
- *   - Section 3.4: y = alpha A x + beta y, dot products and norms, and GMRES.
+ *   - Section 3.3 (data structures and algorithms): y = alpha A x + beta y,
+ *     dot products and norms, and the Krylov solvers (GMRES).
  *
  * Conventions shared by every entry point
  *   - Cells are numbered g = i + nx*(j + ny*k), i fastest.
@@ -41,12 +42,18 @@ extern "C" {
 typedef enum {
     BO_OK = 0,
     BO_NOT_CONVERGED = 1,         /* solver reached maxit; x holds the last iterate */
+    BO_NN_FALLBACK = 2,           /* information, not an error: the solve converged with a
+                                     network attached, and the judge kept none of its
+                                     corrections (every pressure stage was the plain V-cycle) */
     BO_ERR_INVALID_ARG = -1,
     BO_ERR_HIP = -2,              /* a HIP runtime call failed */
     BO_ERR_ALLOC = -3,
     BO_ERR_NONFINITE = -4,        /* NaN/Inf in an input or during the iteration */
     BO_ERR_SINGULAR_BLOCK = -5,   /* a 3x3 pivot block is singular */
     BO_ERR_SINGULAR_COARSE = -6,  /* the coarsest AMG matrix is singular */
+    BO_ERR_BREAKDOWN = -7,        /* Arnoldi breakdown with a singular Hessenberg matrix: the
+                                     Krylov space holds no better iterate (a singular or
+                                     inconsistent system); x keeps the last restart's iterate */
     BO_ERR_UNSUPPORTED = -8       /* e.g. a matrix pattern that is not the grid's 7-point stencil */
 } bo_status;
 
@@ -159,7 +166,7 @@ bo_status bo_jacobian_bsr_noalloc(const bo_problem *p, const double *x_old, cons
 /* Largest nbrows bo_jacobian_bsr_noalloc accepts (2^26). */
 int32_t bo_jacobian_bsr_noalloc_max_rows(void);
 
-/* ---- Basic operations (Section 3.4) ---------------------------------- */
+/* ---- Basic operations (Section 3.3) ---------------------------------- */
 
 /* y = alpha*A*x + beta*y on the BSR layout (beta == 0: y is not read). */
 bo_status bo_bsr_spmv(const bo_bsr *A, double alpha, const double *x, double beta, double *y,
@@ -208,11 +215,25 @@ typedef struct {
                                least this many rows are also kept sliced (SELL-64, one
                                thread per row in the cycle); 0: 2^20.  Same results up
                                to the order of each row's sum. */
+    int32_t condense;       /* 1 (dual-porosity extended grid form only): eliminate every
+                               matrix cell exactly (block Gaussian elimination of the
+                               fracture-matrix pairs of Section 2.1's model) and build the
+                               CPR of the reduced system over the fracture cells and the
+                               fixed-rate wells, with the other options of this struct
+                               (npr counts reduced rows, 0: all of them; the level-0
+                               smoother becomes l1-Jacobi when the reduced system has
+                               well rows and red-black Gauss-Seidel when it has none).
+                               bo_cpr_apply then applies elimination, reduced CPR and
+                               back-substitution to full-length vectors; bo_fgmres_solve
+                               runs FGMRES on the reduced system and checks the true
+                               residual of the full one; bo_cpr_spmv, the stage calls
+                               and the hierarchy introspection act on the reduced
+                               system (vectors of 3 (N + wells)). */
 } bo_cpr_opts;
 
 /* Fills `o` [host] with the defaults: PF, tiled ILU0 8x8, theta 0.08,
  * coarse_max 192, 12 levels, red-black GS, 1 sweep, AMG on, block QI, FP64,
- * l1-Jacobi on the coarse levels. */
+ * l1-Jacobi on the coarse levels, no condensation. */
 void bo_cpr_default_opts(bo_cpr_opts *o);
 
 typedef struct bo_cpr bo_cpr;
@@ -298,11 +319,16 @@ typedef struct {
     int32_t nn_used;        /* with a network attached: applications whose correction was kept */
 } bo_solve_stats;
 
-/* Right-preconditioned FGMRES(m) on A x = b with the operator and
- * preconditioner of pc (A captured at setup).  x holds the initial guess on
- * entry and the solution on exit.  Synchronous: it reads one Arnoldi scalar
- * column per iteration.  Returns BO_OK, BO_NOT_CONVERGED or an error. */
-bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, const bo_fgmres_opts *opts,
+/* Right-preconditioned FGMRES(m) (Section 3.3's Krylov solver, flexible
+ * form) on A x = b with the preconditioner of pc.  A must be the matrix of
+ * pc's last setup or update (same pattern and values, not modified since):
+ * the Arnoldi steps use pc's own layout of it, and the residual at every
+ * restart and at exit (the true residual ||b - A x||) is computed from A
+ * itself.  x holds the initial guess on entry and the solution on exit.
+ * Synchronous: it reads one Arnoldi scalar column per iteration.  Returns
+ * BO_OK, BO_NOT_CONVERGED, BO_NN_FALLBACK (converged; see bo_status),
+ * BO_ERR_BREAKDOWN or another error. */
+bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
                           bo_solve_stats *stats, void *stream);
 
 /* ---- a9: learned pressure-stage correction ----------------------------

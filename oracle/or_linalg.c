@@ -1,7 +1,7 @@
 /*
  * Oracle (test infrastructure only): sparse and dense linear-algebra basics.
  *
- * - y = alpha A x + beta y, the first basic operation listed in Section 3.4;
+ * - y = alpha A x + beta y, the first basic operation listed in Section 3.3;
  * - dense LU with partial pivoting (textbook Gaussian elimination);
  * - quasi-IMPES decoupling of Section 3.2.  The printed operator combines
  *   the pressure row with the secondary rows through D_ps D_ss^{-1}, where D_ps

@@ -17,9 +17,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbo.so")
 
-BO_OK, BO_NOT_CONVERGED = 0, 1
+BO_OK, BO_NOT_CONVERGED, BO_NN_FALLBACK = 0, 1, 2
 BO_ERR_INVALID_ARG, BO_ERR_HIP, BO_ERR_ALLOC, BO_ERR_NONFINITE = -1, -2, -3, -4
-BO_ERR_SINGULAR_BLOCK, BO_ERR_SINGULAR_COARSE, BO_ERR_UNSUPPORTED = -5, -6, -8
+BO_ERR_SINGULAR_BLOCK, BO_ERR_SINGULAR_COARSE, BO_ERR_BREAKDOWN, BO_ERR_UNSUPPORTED = -5, -6, -7, -8
 BO_F_BJ, BO_F_ILU_TILED = 0, 3
 BO_SMOOTH_GS, BO_SMOOTH_JACOBI, BO_SMOOTH_L1 = 0, 1, 2
 BO_QI_DIAG, BO_QI_BLOCK = 0, 1
@@ -77,7 +77,7 @@ class BoCprOpts(C.Structure):
                 ("theta", C.c_double), ("coarse_max", C.c_int32), ("max_levels", C.c_int32),
                 ("smoother", C.c_int32), ("sweeps", C.c_int32), ("use_amg", C.c_int32),
                 ("qi_mode", C.c_int32), ("precision", C.c_int32), ("csmoother", C.c_int32),
-                ("npr", C.c_int32), ("sell_rows", C.c_int32)]
+                ("npr", C.c_int32), ("sell_rows", C.c_int32), ("condense", C.c_int32)]
 
 
 class BoGrid(C.Structure):
@@ -134,7 +134,7 @@ def lib():
     L.bo_cpr_copy_weights.argtypes = [vp, vp]
     L.bo_fgmres_default_opts.argtypes = [C.POINTER(BoFgmresOpts)]
     L.bo_fgmres_default_opts.restype = None
-    L.bo_fgmres_solve.argtypes = [vp, vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats), vp]
+    L.bo_fgmres_solve.argtypes = [vp, C.POINTER(BoBsr), vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats), vp]
     L.bo_nn_create.argtypes = [C.POINTER(vp)]
     L.bo_nn_destroy.argtypes = [vp]
     L.bo_nn_destroy.restype = None
@@ -294,6 +294,7 @@ class Cpr:
     def __init__(self, h: int, n: int):
         self.h = C.c_void_p(h)
         self.n = n
+        self.A = None
 
     def close(self):
         if self.h:
@@ -316,12 +317,15 @@ def bo_cpr_setup(A: DeviceBsr, grid, opts: Optional[BoCprOpts] = None, stream=No
     s = A.s
     _check(lib().bo_cpr_setup(C.byref(s), C.byref(g) if g is not None else None, C.byref(o), C.byref(h),
                               _stream(stream)))
-    return Cpr(h.value, s.nbrows)
+    pc = Cpr(h.value, s.nbrows)
+    pc.A = A   # the matrix of the last setup or update (bo_fgmres_solve takes it)
+    return pc
 
 
 def bo_cpr_update(pc: Cpr, A: DeviceBsr, stream=None) -> Cpr:
     s = A.s
     _check(lib().bo_cpr_update(pc.h, C.byref(s), _stream(stream)))
+    pc.A = A
     return pc
 
 
@@ -389,11 +393,14 @@ def bo_cpr_copy_weights(pc: Cpr):
     return c
 
 
-def bo_fgmres_solve(pc: Cpr, b, x, opts: Optional[BoFgmresOpts] = None, stream=None) -> dict:
+def bo_fgmres_solve(pc: Cpr, A: DeviceBsr, b, x, opts: Optional[BoFgmresOpts] = None, stream=None) -> dict:
+    """A: the matrix of pc's last setup or update (the true residual is
+    computed from it)."""
     o = opts if opts is not None else bo_fgmres_default_opts()
     st = BoSolveStats()
-    rc = lib().bo_fgmres_solve(pc.h, _ptr(b), _ptr(x), C.byref(o), C.byref(st), _stream(stream))
-    _check(rc, allowed=(BO_OK, BO_NOT_CONVERGED))
+    s = A.s
+    rc = lib().bo_fgmres_solve(pc.h, C.byref(s), _ptr(b), _ptr(x), C.byref(o), C.byref(st), _stream(stream))
+    _check(rc, allowed=(BO_OK, BO_NOT_CONVERGED, BO_NN_FALLBACK))
     return dict(status=rc, iterations=st.iterations, restarts=st.restarts, converged=bool(st.converged),
                 rel_residual=st.rel_residual, est_residual=st.est_residual, spmv_ms=st.spmv_ms,
                 spmv_calls=st.spmv_calls, nn_used=st.nn_used)

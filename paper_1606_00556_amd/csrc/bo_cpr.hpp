@@ -73,10 +73,15 @@ struct Krylov {
     ~Krylov() { if (host) (void)hipHostFree(host); }
 };
 
+struct Condensed;                 // exact elimination of dual-porosity matrix cells (bo_condense.hip)
+
 }  // namespace bo
 
 struct bo_cpr {
     bool broken = false;          // a failed bo_cpr_update leaves the handle unusable
+    // condensed dual-porosity form: the matrix cells eliminated exactly, the
+    // CPR of the reduced system in cond->inner (every other member unused)
+    bo::Condensed *cond = nullptr;
     bo::Grid g{};
     int n = 0;                    // block rows (the cells of a grid)
     int npr = 0;                  // rows of the pressure system (the first npr block rows)
@@ -143,3 +148,21 @@ struct bo_cpr {
     int rec_max = 0, rec_n = 0;
     bo::DBuf<double> pg_V, pg_Z, pg_h, pg_x, pg_r, pg_v, pg_xs;
 };
+
+namespace bo {
+// setup of a handle (plain grid, extended grid or general form), see bo_cpr_setup
+bo_status cpr_setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc, hipStream_t s);
+bo_status cpr_check(int32_t nbrows, const bo_grid *grid, const bo_cpr_opts *opts);
+bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s);
+bo_status fgmres_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+                      bo_solve_stats *stats, hipStream_t s);
+// condensed form (bo_condense.hip)
+bo_status cond_setup(bo_cpr *pc, const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, hipStream_t s);
+bo_status cond_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s);
+bo_status cond_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+                     bo_solve_stats *stats, hipStream_t s);
+void cond_destroy(bo_cpr *pc);
+// the handle whose stages and hierarchy the entry points act on: the reduced
+// system's CPR for a condensed handle, pc itself otherwise (NULL stays NULL)
+bo_cpr *cond_inner(bo_cpr *pc);
+}  // namespace bo

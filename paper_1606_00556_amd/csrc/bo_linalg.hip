@@ -1,4 +1,4 @@
-// Basic operations of Section 3.4 on the GPU: y = alpha A x + beta y (BSR and
+// Basic operations of Section 3.3 (data structures and algorithms) on the GPU: y = alpha A x + beta y (BSR and
 // the library's slot layout), y = alpha x + beta y, dot products and norms,
 // plus the prefix sums the setup phases need.
 //

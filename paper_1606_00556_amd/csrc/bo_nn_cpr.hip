@@ -321,7 +321,7 @@ extern "C" bo_status bo_cpr_attach_nn(bo_cpr *pc, bo_nn *nn, const double *logk,
     }
     if (!logk) return fail(BO_ERR_INVALID_ARG, "bo_cpr_attach_nn: logk is NULL");
     if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_attach_nn: the handle has no pressure stage");
-    if (pc->general) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_attach_nn: the network needs the grid form");
+    if (pc->general || pc->cond) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_attach_nn: the network needs the grid form");
     hipStream_t s = (hipStream_t)stream;
     long long n = pc->n;
     BO_TRY(pc->nn_z.alloc(n));
@@ -338,15 +338,12 @@ extern "C" bo_status bo_cpr_attach_nn(bo_cpr *pc, bo_nn *nn, const double *logk,
     return BO_OK;
 }
 
-extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, const bo_fgmres_opts *opts,
-                                     bo_solve_stats *stats, void *stream);
-
 extern "C" bo_status bo_cpr_collect_pairs(bo_cpr *pc, const double *b, int32_t ncalls, double rtol_inner,
                                           float *rp_out, float *e_out, int32_t *got, void *stream) {
     if (!pc || !b || !rp_out || !e_out || !got) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: NULL argument");
     if (ncalls < 1 || !(rtol_inner > 0.0)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: bad arguments");
     if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: the handle has no pressure stage");
-    if (pc->general) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_collect_pairs: pairs need the grid form");
+    if (pc->general || pc->cond) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_collect_pairs: pairs need the grid form");
     hipStream_t s = (hipStream_t)stream;
     long long n = pc->n;
     *got = 0;
@@ -361,7 +358,7 @@ extern "C" bo_status bo_cpr_collect_pairs(bo_cpr *pc, const double *b, int32_t n
     bo_fgmres_default_opts(&o);
     o.maxit = ncalls;  // only the first ncalls applications are needed
     bo_solve_stats st;
-    bo_status rc = bo_fgmres_solve(pc, b, pc->pg_x.p, &o, &st, stream);
+    bo_status rc = fgmres_core(pc, nullptr, b, pc->pg_x.p, &o, &st, s);
     int rec = pc->rec_n;
     pc->rec_out = nullptr;
     pc->rec_max = pc->rec_n = 0;

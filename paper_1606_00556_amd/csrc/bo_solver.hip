@@ -181,6 +181,7 @@ extern "C" void bo_cpr_default_opts(bo_cpr_opts *o) {
     o->csmoother = BO_CSMOOTH_L1;
     o->npr = 0;
     o->sell_rows = 0;
+    o->condense = 0;
 }
 
 extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
@@ -199,8 +200,8 @@ extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
 
 // grid == NULL: the general form (A kept as BSR; block-Jacobi F stage; the
 // pressure system over the first opts->npr rows)
-static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc,
-                            hipStream_t s) {
+bo_status bo::cpr_setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc,
+                             hipStream_t s) {
     if (pc->gexec) {  // buffers and levels may change: capture again on the next solve
         (void)hipGraphExecDestroy(pc->gexec);
         pc->gexec = nullptr;
@@ -269,18 +270,14 @@ static bo_status setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_o
     return BO_OK;
 }
 
-extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
-                                  bo_cpr **out, void *stream) {
-    if (!out) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: out is NULL");
-    *out = nullptr;
-    if (!A || !opts || !A->rowptr || !A->colind || !A->val)
-        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: NULL argument");
-    if (A->nbrows < 1 || A->nnzb < A->nbrows) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: empty matrix");
+// Option and size checks of bo_cpr_setup for a matrix of nbrows block rows
+// (also applied to the reduced system of the condensed form).
+bo_status bo::cpr_check(int32_t nbrows, const bo_grid *grid, const bo_cpr_opts *opts) {
     const long long gn = grid ? (long long)grid->nx * grid->ny * grid->nz : 0;
-    if (grid && (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || gn * (grid->dual ? 2 : 1) > A->nbrows ||
-                 (grid->dual && gn * 2 > A->nbrows)))
+    if (grid && (grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || gn * (grid->dual ? 2 : 1) > nbrows ||
+                 (grid->dual && gn * 2 > nbrows)))
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: grid does not match the matrix size");
-    const bool general = !grid || gn != A->nbrows;
+    const bool general = !grid || gn != nbrows;
     if (!grid && opts->ftype != BO_F_BJ)
         return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: without a grid the F stage must be BO_F_BJ");
     if (general && opts->ftype == BO_F_ILU_TILED && opts->precision != BO_PREC_FP64)
@@ -289,11 +286,11 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: red-black Gauss-Seidel needs the plain grid form");
     if (!general && opts->smoother == BO_SMOOTH_L1)
         return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: the l1 level-0 smoother is for the general form");
-    if (opts->npr < 0 || opts->npr > A->nbrows) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: npr out of range");
+    if (opts->npr < 0 || opts->npr > nbrows) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: npr out of range");
     if (opts->sell_rows < 0) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: sell_rows out of range");
-    if (!general && opts->npr != 0 && opts->npr != A->nbrows)
+    if (!general && opts->npr != 0 && opts->npr != nbrows)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: on a grid every row is a pressure row");
-    if ((long long)A->nbrows * 7 >= (1LL << 31)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: matrix too large");
+    if ((long long)nbrows * 7 >= (1LL << 31)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: matrix too large");
     const bo_cpr_opts &o = *opts;
     if (o.ftype != BO_F_BJ && o.ftype != BO_F_ILU_TILED)
         return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: F stage must be BO_F_BJ or BO_F_ILU_TILED");
@@ -310,9 +307,28 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown quasi-IMPES mode");
     if (o.precision != BO_PREC_FP64 && o.precision != BO_PREC_FP32 && o.precision != BO_PREC_FP32_BF16)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: unknown precision");
+    return BO_OK;
+}
+
+extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
+                                  bo_cpr **out, void *stream) {
+    if (!out) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: out is NULL");
+    *out = nullptr;
+    if (!A || !opts || !A->rowptr || !A->colind || !A->val)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: NULL argument");
+    if (A->nbrows < 1 || A->nnzb < A->nbrows) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: empty matrix");
+    if (opts->condense != 0 && opts->condense != 1)
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: condense must be 0 or 1");
+    if (opts->condense) {
+        if (!grid || !grid->dual)
+            return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: condense needs the dual-porosity extended grid form");
+    } else {
+        BO_TRY(cpr_check(A->nbrows, grid, opts));
+    }
     bo_cpr *pc = new (std::nothrow) bo_cpr();
     if (!pc) return fail(BO_ERR_ALLOC, "bo_cpr_setup: out of host memory");
-    bo_status st = setup_impl(A, grid, opts, pc, (hipStream_t)stream);
+    bo_status st = opts->condense ? cond_setup(pc, A, grid, opts, (hipStream_t)stream)
+                                   : cpr_setup_impl(A, grid, opts, pc, (hipStream_t)stream);
     if (st != BO_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         delete pc;
@@ -326,9 +342,11 @@ extern "C" bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream) {
     if (!pc || !A || !A->rowptr || !A->colind || !A->val)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: NULL argument");
     if (A->nbrows != pc->n) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: matrix size differs from the setup");
+    if (A->nnzb != pc->nnzb) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: block count differs from the setup");
     bo_grid g{pc->g.nx, pc->g.ny, pc->g.nz, pc->ncell > pc->g.n() ? 1 : 0};
     bo_cpr_opts o = pc->o;
-    bo_status st = setup_impl(A, pc->has_grid ? &g : nullptr, &o, pc, (hipStream_t)stream);
+    bo_status st = pc->cond ? cond_setup(pc, A, &g, &o, (hipStream_t)stream)
+                            : cpr_setup_impl(A, pc->has_grid ? &g : nullptr, &o, pc, (hipStream_t)stream);
     if (st != BO_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
         pc->nlev = 0;
@@ -342,6 +360,7 @@ extern "C" bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream) {
 extern "C" void bo_cpr_destroy(bo_cpr *pc) {
     if (!pc) return;
     (void)hipDeviceSynchronize();
+    cond_destroy(pc);
     for (hipEvent_t &e : pc->ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t &e : pc->evf)
@@ -357,31 +376,37 @@ extern "C" void bo_cpr_destroy(bo_cpr *pc) {
 extern "C" bo_status bo_cpr_apply(bo_cpr *pc, const double *v, double *z, void *stream) {
     if (!pc || !v || !z) return fail(BO_ERR_INVALID_ARG, "bo_cpr_apply: NULL argument");
     if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_cpr_apply: the last bo_cpr_update failed");
+    if (pc->cond) return cond_apply(pc, v, z, (hipStream_t)stream);
     return cpr_apply(pc, v, z, (hipStream_t)stream);
 }
 
 extern "C" bo_status bo_cpr_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, void *stream) {
+    pc = cond_inner(pc);
     if (!pc || !x || !y) return fail(BO_ERR_INVALID_ARG, "bo_cpr_spmv: NULL argument");
     return op_spmv(pc, alpha, x, beta, y, (hipStream_t)stream);
 }
 
 extern "C" bo_status bo_cpr_restrict(bo_cpr *pc, const double *v, double *rp, void *stream) {
+    pc = cond_inner(pc);
     if (!pc || !v || !rp) return fail(BO_ERR_INVALID_ARG, "bo_cpr_restrict: NULL argument");
     return qi_restrict(pc, v, rp, (hipStream_t)stream);
 }
 
 extern "C" bo_status bo_cpr_vcycle(bo_cpr *pc, const double *b, double *x, void *stream) {
+    pc = cond_inner(pc);
     if (!pc || !b || !x) return fail(BO_ERR_INVALID_ARG, "bo_cpr_vcycle: NULL argument");
     if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_vcycle: built without AMG");
     return amg_vcycle(pc, b, x, (hipStream_t)stream);
 }
 
 extern "C" bo_status bo_cpr_fstage(bo_cpr *pc, const double *r, double *x, void *stream) {
+    pc = cond_inner(pc);
     if (!pc || !r || !x) return fail(BO_ERR_INVALID_ARG, "bo_cpr_fstage: NULL argument");
     return fstage_apply(pc, r, nullptr, x, (hipStream_t)stream);
 }
 
 extern "C" bo_status bo_cpr_levels(bo_cpr *pc, int32_t *nlevels) {
+    pc = cond_inner(pc);
     if (!pc || !nlevels) return fail(BO_ERR_INVALID_ARG, "bo_cpr_levels: NULL argument");
     *nlevels = pc->o.use_amg ? pc->nlev : 0;
     return BO_OK;
@@ -389,6 +414,7 @@ extern "C" bo_status bo_cpr_levels(bo_cpr *pc, int32_t *nlevels) {
 
 extern "C" bo_status bo_cpr_level_info(bo_cpr *pc, int32_t l, int32_t *n, int32_t *nnz, int32_t *pnnz,
                                        double *omega) {
+    pc = cond_inner(pc);
     if (!pc || l < 0 || l >= pc->nlev) return fail(BO_ERR_INVALID_ARG, "bo_cpr_level_info: bad level");
     const Level &L = pc->lv[l];
     bool last = l == pc->nlev - 1;
@@ -402,6 +428,7 @@ extern "C" bo_status bo_cpr_level_info(bo_cpr *pc, int32_t l, int32_t *n, int32_
 extern "C" bo_status bo_cpr_level_copy(bo_cpr *pc, int32_t l, int32_t *rowptr, int32_t *colind, double *val,
                                        int32_t *agg, uint8_t *root, int32_t *prowptr, int32_t *pcolind,
                                        double *pval) {
+    pc = cond_inner(pc);
     if (!pc || l < 0 || l >= pc->nlev) return fail(BO_ERR_INVALID_ARG, "bo_cpr_level_copy: bad level");
     const Level &L = pc->lv[l];
     bool last = l == pc->nlev - 1;
@@ -420,6 +447,7 @@ extern "C" bo_status bo_cpr_level_copy(bo_cpr *pc, int32_t l, int32_t *rowptr, i
 }
 
 extern "C" bo_status bo_cpr_copy_weights(bo_cpr *pc, double *c) {
+    pc = cond_inner(pc);
     if (!pc || !c) return fail(BO_ERR_INVALID_ARG, "bo_cpr_copy_weights: NULL argument");
     BO_HIP(hipDeviceSynchronize());
     BO_HIP(hipMemcpy(c, pc->cw.p, sizeof(double) * 3 * pc->n, hipMemcpyDeviceToHost));
@@ -457,15 +485,14 @@ bo_status krylov_alloc(bo_cpr *pc, int m) {
 
 }  // namespace
 
-extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, const bo_fgmres_opts *opts,
-                                     bo_solve_stats *stats, void *stream) {
-    if (!pc || !b || !x || !opts) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: NULL argument");
-    if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: the last bo_cpr_update failed");
+namespace bo {
+
+// FGMRES(m) on pc's operator.  The residual at each restart and at exit (the
+// true residual) is b - A x with the caller's BSR matrix A, or with the
+// handle's own copy when A is NULL (internal callers).
+bo_status fgmres_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+                      bo_solve_stats *stats, hipStream_t s) {
     int m = opts->m;
-    if (m < 1 || m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || opts->orth < 0 || opts->orth > 2 ||
-        (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1))
-        return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
-    hipStream_t s = (hipStream_t)stream;
     bo_solve_stats st{};
     const bool timed = opts->timing == 1;
     // graph replay of the preconditioner (not with a network attached, whose
@@ -524,7 +551,8 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
     for (;;) {
         // r = b - A x into V[0]
         BO_HIP(hipMemcpyAsync(V, b, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
-        BO_TRY(op_spmv(pc, -1.0, x, 1.0, V, s));
+        if (A) BO_TRY(bo_bsr_spmv(A, -1.0, x, 1.0, V, s));
+        else BO_TRY(op_spmv(pc, -1.0, x, 1.0, V, s));
         BO_TRY(pc->red.dot(len, V, V, hd, s));
         BO_TRY(fetch(1));
         double beta = std::sqrt(hh[0]);
@@ -641,6 +669,13 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
                     }
                     double a = H[(size_t)c * m + c], bb = H[(size_t)(c + 1) * m + c];
                     double den = std::hypot(a, bb);
+                    if (!(den > 0.0)) {
+                        status = fail(BO_ERR_BREAKDOWN, "bo_fgmres_solve: Arnoldi breakdown with a singular "
+                                                        "Hessenberg matrix (A maps a preconditioned basis "
+                                                        "vector into the span of the basis: singular or "
+                                                        "inconsistent system)");
+                        goto done;
+                    }
                     cs[c] = a / den;
                     sn[c] = bb / den;
                     H[(size_t)c * m + c] = cs[c] * a + sn[c] * bb;
@@ -666,6 +701,12 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const double *b, double *x, con
             }
             double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
             double den = std::hypot(a, bb);
+            if (!(den > 0.0)) {
+                status = fail(BO_ERR_BREAKDOWN, "bo_fgmres_solve: Arnoldi breakdown with a singular Hessenberg "
+                                                "matrix (A maps a preconditioned basis vector into the span "
+                                                "of the basis: singular or inconsistent system)");
+                goto done;
+            }
             cs[j] = a / den;
             sn[j] = bb / den;
             H[(size_t)j * m + j] = cs[j] * a + sn[j] * bb;
@@ -688,6 +729,24 @@ done:
     st.iterations = its;
     if (pc->nn) BO_HIP(hipMemcpyAsync(&st.nn_used, pc->nn_used.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BO_HIP(hipStreamSynchronize(s));
+    // converged with a network attached whose every correction was rejected
+    if (status == BO_OK && pc->nn && st.nn_used == 0 && its > 0) status = BO_NN_FALLBACK;
     if (stats) *stats = st;
     return status;
+}
+
+}  // namespace bo
+
+extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x,
+                                     const bo_fgmres_opts *opts, bo_solve_stats *stats, void *stream) {
+    if (!pc || !A || !b || !x || !opts || !A->rowptr || !A->colind || !A->val)
+        return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: NULL argument");
+    if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: the last bo_cpr_update failed");
+    if (A->nbrows != pc->n || A->nnzb != pc->nnzb)
+        return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: A is not the matrix of the last setup or update");
+    if (opts->m < 1 || opts->m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || opts->orth < 0 ||
+        opts->orth > 2 || (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1))
+        return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
+    if (pc->cond) return cond_solve(pc, A, b, x, opts, stats, (hipStream_t)stream);
+    return fgmres_core(pc, A, b, x, opts, stats, (hipStream_t)stream);
 }

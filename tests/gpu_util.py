@@ -45,6 +45,26 @@ def rel_err(a, b):
     return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
 
 
+def rel_err_parts(a, b, parts=3):
+    """The largest of the per-unknown relative errors: the Po, Sw and Sg
+    entries of interleaved 3-vectors compared separately (their scales differ
+    by orders of magnitude, so one norm over the whole vector would let the
+    small ones drift)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    worst = 0.0
+    for q in range(parts):
+        bq = b[q::parts]
+        den = np.linalg.norm(bq)
+        num = np.linalg.norm(a[q::parts] - bq)
+        if den == 0.0:
+            if num != 0.0:
+                return np.inf
+            continue
+        worst = max(worst, num / den)
+    return worst
+
+
 def matching_opts(O, B, ftype="tiled", fpf=0, tile=(8, 8), coarse_max=256, smoother="gs", sweeps=1,
                   use_amg=1, qi="block", theta=0.08, precision="fp64", csmoother="l1", sell_rows=0):
     """The same CPR configuration for the oracle and the library (sell_rows:
@@ -96,8 +116,8 @@ def solve_both(B, O, case, fopts=None, **kw):
     P, rp, ci, val, b, opc, gpc = setup_both(B, O, case, **kw)
     xo, oinfo = O.fgmres(rp, ci, val, b, opc)
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-    ginfo = B.bo_fgmres_solve(gpc, to_dev(b), x, fopts) if fopts is not None else B.bo_fgmres_solve(
-        gpc, to_dev(b), x)
+    ginfo = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, fopts) if fopts is not None else B.bo_fgmres_solve(
+        gpc, gpc.A, to_dev(b), x)
     xg = to_host(x)
     r = b - O.bsr_spmv(rp, ci, val, xg)
     return oinfo, ginfo, np.linalg.norm(r) / np.linalg.norm(b), xg, xo

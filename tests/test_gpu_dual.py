@@ -157,7 +157,7 @@ def test_general_fgmres(B, O, name, prec):
     case, P, rp, ci, val, b, opc, gpc = both(B, O, name, precision=prec)
     xo, oinfo = O.fgmres(rp, ci, val, b, opc)
     x = torch.zeros(3 * P.rows, dtype=torch.float64, device="cuda")
-    info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
     r = b - O.bsr_spmv(rp, ci, val, to_host(x))
     assert info["converged"] and np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
     io = oinfo["iterations"]
@@ -184,7 +184,7 @@ def test_extended_grid_form_tiled_ilu(B, O, name, kw):
     assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * rows), opc.apply(v)) <= 1e-10
     xo, oinfo = O.fgmres(rp, ci, val, b, opc)
     x = torch.zeros(3 * rows, dtype=torch.float64, device="cuda")
-    info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
     r = b - O.bsr_spmv(rp, ci, val, to_host(x))
     assert info["converged"] and np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
     io = oinfo["iterations"]

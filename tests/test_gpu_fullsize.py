@@ -121,7 +121,7 @@ def test_fullsize_solve(B, O, cfg):
     case, P, rp, ci, val, b = system(O, cfg)
     gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), B.bo_cpr_default_opts())
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-    info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
     assert info["converged"] and info["status"] == B.BO_OK
     r = b - O.bsr_spmv(rp, ci, val, to_host(x))
     true_rel = np.linalg.norm(r) / np.linalg.norm(b)
@@ -144,7 +144,7 @@ def test_fullsize_mixed_solve(B, O, prec):
     gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz),
                          B.bo_cpr_default_opts(precision=bp))
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-    info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
     assert info["converged"] and info["status"] == B.BO_OK
     r = b - O.bsr_spmv(rp, ci, val, to_host(x))
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6

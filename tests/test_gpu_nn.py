@@ -132,10 +132,12 @@ def test_zero_network_changes_nothing(B, O):
         if attach:
             B.bo_cpr_attach_nn(gpc, nn, to_dev(np.log(case.kx)))
         x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(orth=1)))
+        infos.append(B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, B.bo_fgmres_default_opts(orth=1)))
         xs.append(to_host(x))
     assert infos[0]["iterations"] == infos[1]["iterations"]
     assert infos[1]["nn_used"] == 0
+    # converged, every correction rejected: the informational status
+    assert infos[0]["status"] == B.BO_OK and infos[1]["status"] == B.BO_NN_FALLBACK and infos[1]["converged"]
     assert np.array_equal(xs[0], xs[1])
 
 
@@ -152,7 +154,7 @@ def test_network_solve_with_default_options_equals_cgs2(B, O):
     xs, infos = [], []
     for fo in (B.bo_fgmres_default_opts(), B.bo_fgmres_default_opts(orth=1)):
         x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x, fo))
+        infos.append(B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, fo))
         xs.append(to_host(x))
     assert infos[0]["iterations"] == infos[1]["iterations"] and infos[0]["nn_used"] == infos[1]["nn_used"]
     assert np.array_equal(xs[0], xs[1])
@@ -215,7 +217,7 @@ def test_trained_network_gain(B, O):
             if attach:
                 B.bo_cpr_attach_nn(gpc, nn, to_dev(np.log(c.kx)))
             x = torch.zeros(3 * c.n, dtype=torch.float64, device="cuda")
-            info = B.bo_fgmres_solve(gpc, to_dev(b), x)
+            info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
             rr = b - O.bsr_spmv(rp, ci, val, to_host(x))
             assert info["converged"] and np.linalg.norm(rr) <= 1e-6 * np.linalg.norm(b)
             res[attach] = info

@@ -243,7 +243,7 @@ def test_delayed_request_falls_back_to_cgs2_exactly(B, O):
     xs, infos = [], []
     for orth in (2, 1):
         x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(m=40, orth=orth)))
+        infos.append(B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, B.bo_fgmres_default_opts(m=40, orth=orth)))
         xs.append(to_host(x))
     assert infos[0]["converged"] and infos[0]["iterations"] == infos[1]["iterations"]
     assert infos[0]["est_residual"] == infos[1]["est_residual"]
@@ -260,12 +260,12 @@ def test_fgmres_delayed_small_restart(B, O):
     P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
     for m in (3, 1):
         x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-        info = B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(m=m, orth=2))
+        info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, B.bo_fgmres_default_opts(m=m, orth=2))
         assert info["converged"] and info["restarts"] >= 1
         r = b - O.bsr_spmv(rp, ci, val, to_host(x))
         assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-    info = B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(orth=2, maxit=2, rtol=1e-12))
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, B.bo_fgmres_default_opts(orth=2, maxit=2, rtol=1e-12))
     assert info["status"] == B.BO_NOT_CONVERGED and info["iterations"] == 2
 
 
@@ -274,7 +274,7 @@ def test_fgmres_mgs_option(B, O):
     case = cg.make_case(0)
     P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-    info = B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(orth=0))
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, B.bo_fgmres_default_opts(orth=0))
     assert info["converged"]
     r = b - O.bsr_spmv(rp, ci, val, to_host(x))
     assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
@@ -287,7 +287,7 @@ def test_fgmres_deterministic(B, O):
     xs = []
     for _ in range(2):
         x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-        B.bo_fgmres_solve(gpc, to_dev(b), x)
+        B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
         xs.append(to_host(x))
     assert np.array_equal(xs[0], xs[1])
 
@@ -301,7 +301,7 @@ def test_fgmres_timing_option_keeps_result(B, O):
     xs, infos = [], []
     for t in (0, 1):
         x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-        infos.append(B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(timing=t)))
+        infos.append(B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, B.bo_fgmres_default_opts(timing=t)))
         xs.append(to_host(x))
     assert np.array_equal(xs[0], xs[1])
     assert infos[0]["spmv_calls"] == 0 and infos[0]["spmv_ms"] == 0.0
@@ -323,7 +323,7 @@ def test_graph_replay_matches_eager(B, O, kw):
         xs = []
         for g in (0, 1):
             x = torch.zeros(3 * c1.n, dtype=torch.float64, device="cuda")
-            info = B.bo_fgmres_solve(gpc, to_dev(rhs), x, B.bo_fgmres_default_opts(graph=g))
+            info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(rhs), x, B.bo_fgmres_default_opts(graph=g))
             assert info["converged"]
             xs.append((to_host(x), info["iterations"]))
         assert xs[0][1] == xs[1][1] and np.array_equal(xs[0][0], xs[1][0])
@@ -334,10 +334,10 @@ def test_fgmres_small_restart_and_maxit(B, O):
     case = ragged_case()
     P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
-    info = B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(m=3))
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, B.bo_fgmres_default_opts(m=3))
     assert info["converged"] and info["restarts"] >= 1
     x.zero_()
-    info = B.bo_fgmres_solve(gpc, to_dev(b), x, B.bo_fgmres_default_opts(maxit=2, rtol=1e-12))
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, B.bo_fgmres_default_opts(maxit=2, rtol=1e-12))
     assert info["status"] == B.BO_NOT_CONVERGED and info["iterations"] == 2
 
 
@@ -346,7 +346,7 @@ def test_zero_rhs_gives_zero(B, O):
     case = ragged_case()
     P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
     x = torch.ones(3 * case.n, dtype=torch.float64, device="cuda")
-    info = B.bo_fgmres_solve(gpc, torch.zeros_like(x), x)
+    info = B.bo_fgmres_solve(gpc, gpc.A, torch.zeros_like(x), x)
     assert info["converged"] and float(x.abs().max()) == 0.0
 
 
@@ -358,7 +358,7 @@ def test_nonfinite_inputs_are_rejected(B, O):
     bad[5] = np.nan
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
     with pytest.raises(B.BoError) as e:
-        B.bo_fgmres_solve(gpc, to_dev(bad), x)
+        B.bo_fgmres_solve(gpc, gpc.A, to_dev(bad), x)
     assert e.value.status == B.BO_ERR_NONFINITE
     v2 = val.copy()
     v2[3, 1, 1] = np.inf
@@ -406,8 +406,8 @@ def test_update_equals_fresh_setup(B, O):
     assert np.array_equal(a, f)
     x1 = torch.zeros(3 * c2.n, dtype=torch.float64, device="cuda")
     x2 = torch.zeros_like(x1)
-    i1 = B.bo_fgmres_solve(pc, to_dev(b2), x1)
-    i2 = B.bo_fgmres_solve(fresh, to_dev(b2), x2)
+    i1 = B.bo_fgmres_solve(pc, pc.A, to_dev(b2), x1)
+    i2 = B.bo_fgmres_solve(fresh, fresh.A, to_dev(b2), x2)
     assert i1["iterations"] == i2["iterations"] and np.array_equal(to_host(x1), to_host(x2))
 
 
@@ -422,6 +422,6 @@ def test_failed_update_leaves_handle_unusable(B, O):
         B.bo_cpr_update(pc, device_bsr(B, rp, ci, bad))
     x = torch.zeros(3 * c1.n, dtype=torch.float64, device="cuda")
     with pytest.raises(B.BoError):
-        B.bo_fgmres_solve(pc, to_dev(b), x)
+        B.bo_fgmres_solve(pc, pc.A, to_dev(b), x)
     B.bo_cpr_update(pc, device_bsr(B, rp, ci, val))
-    assert B.bo_fgmres_solve(pc, to_dev(b), x)["converged"]
+    assert B.bo_fgmres_solve(pc, pc.A, to_dev(b), x)["converged"]
