@@ -33,11 +33,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2, 4),
-                    help="0: 20x20x5; 1: 100x100x50 (default); 2: 200x200x50; 4: dual porosity 400x400x100 "
-                         "locations with fixed-rate wells (general CPR form)")
+    ap.add_argument("--workload", type=int, default=4, choices=(0, 1, 2, 4),
+                    help="0: 20x20x5; 1: 100x100x50; 2: 200x200x50; 4 (default): dual porosity 400x400x100 "
+                         "locations (32M cells) with fixed- BHP and fixed-rate wells")
     ap.add_argument("--systems", type=int, default=0,
-                    help="systems of the step sequence to cycle through (default: all 10; workload 4: 2)")
+                    help="systems of the step sequence to cycle through (default: all 10)")
+    ap.add_argument("--form", default="condensed", choices=("condensed", "full"),
+                    help="workload 4: 'condensed' (matrix cells eliminated exactly, CPR-FPF on the reduced "
+                         "system; default) or 'full' (extended grid form on the whole system)")
     ap.add_argument("--scale", type=int, default=1,
                     help="workload 4 only: divide nx, ny by this (nz by half of it), a smaller twin")
     ap.add_argument("--spmv-isolated", action="store_true",
@@ -52,6 +55,9 @@ def parse():
     ap.add_argument("--orth", type=int, default=None, choices=(0, 1, 2),
                     help="Gram-Schmidt form (default: the library's): 0 MGS, 1 CGS2, 2 CGS2 with the "
                          "re-orthogonalisation delayed one step")
+    ap.add_argument("--fpf", type=int, default=None, choices=(0, 1),
+                    help="CPR form: 1 Algorithm CPR-FPF, 0 two-stage P then F (default: FPF on workload 4, "
+                         "two-stage otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -76,19 +82,20 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     wl = args.workload
-    nsys = args.systems or (2 if wl == 4 else cg.N_SYSTEMS)
+    nsys = args.systems or cg.N_SYSTEMS
     systems = [0] if wl == 0 else list(range(1, nsys + 1))
     log(args, f"[bench] generating workload {wl} ({len(systems)} systems)")
-    if wl == 4:
-        cases = []
-        for k in systems:
-            cases.append(cg.make_cfg4(k, scale=args.scale))
-            log(args, f"[bench] generated system {k}: {cases[-1].rows} block rows")
-    else:
-        cases = [cg.make_case(wl, k) if wl else cg.make_case(0) for k in systems]
-    c0 = cases[0]
+    # each system's states go to the device as soon as they are generated
+    # (the host keeps the first case's fields for the problem description)
+    states = []
+    c0 = None
+    for k in systems:
+        c = cg.make_cfg4(k, scale=args.scale) if wl == 4 else (cg.make_case(wl, k) if wl else cg.make_case(0))
+        states.append((torch.from_numpy(c.x_old).to(dev), torch.from_numpy(c.x_new).to(dev), c.dt))
+        if c0 is None:
+            c0 = c
+        log(args, f"[bench] generated system {k}: {c.rows} block rows")
     prob = B.problem_from_case(c0, dev)
-    states = [(torch.from_numpy(c.x_old).to(dev), torch.from_numpy(c.x_new).to(dev), c.dt) for c in cases]
     n, nnzb = B.bo_jacobian_bsr_size(prob)
     J = B.DeviceBsr(torch.empty(n + 1, dtype=torch.int32, device=dev),
                     torch.empty(nnzb, dtype=torch.int32, device=dev),
@@ -96,17 +103,22 @@ def main():
     b = torch.empty(3 * n, dtype=torch.float64, device=dev)
     x = torch.empty(3 * n, dtype=torch.float64, device=dev)
     prec = {"fp64": B.BO_PREC_FP64, "fp32": B.BO_PREC_FP32, "bf16": B.BO_PREC_FP32_BF16}[args.precision]
+    condensed = wl == 4 and args.form == "condensed"
     if wl == 4:
-        # the extended grid form: BSR operator; the pressure system over every
-        # row (cells and fixed-rate wells); Algorithm CPR-FPF with the tiled
-        # ILU ordered fracture tiles, matrix cells, wells (FP64; the mixed
-        # forms use block Jacobi)
+        # condensed: every matrix cell eliminated exactly, CPR on the reduced
+        # system (fracture cells and fixed-rate wells: pressure system over all
+        # of its rows, l1-Jacobi level 0, tiled ILU over the fracture tiles with
+        # the wells as a class of their own), Algorithm CPR-FPF.  full: the
+        # extended grid form over all 2N cells and the wells.  The tiled ILU of
+        # these forms is FP64; the mixed forms use block Jacobi.
         grid = (c0.nx, c0.ny, c0.nz, 1)
         ft = B.BO_F_ILU_TILED if prec == B.BO_PREC_FP64 else B.BO_F_BJ
-        copts = B.bo_cpr_default_opts(precision=prec, ftype=ft, smoother=B.BO_SMOOTH_L1, npr=c0.rows, fpf=1)
+        copts = B.bo_cpr_default_opts(precision=prec, ftype=ft, smoother=B.BO_SMOOTH_L1,
+                                      npr=0 if condensed else c0.rows, fpf=1 if args.fpf is None else args.fpf,
+                                      condense=int(condensed))
     else:
         grid = (c0.nx, c0.ny, c0.nz)
-        copts = B.bo_cpr_default_opts(precision=prec)
+        copts = B.bo_cpr_default_opts(precision=prec, fpf=args.fpf or 0)
     fo = {"graph": args.graph}
     if args.orth is not None:
         fo["orth"] = args.orth
@@ -157,17 +169,22 @@ def main():
               f"solve {solve_ms:.2f} ms, iterations {its}")
 
     # SpMV roofline: algorithmic bytes = 72 B per stored block (3x3 FP64) +
-    # 24 B x read + 24 B y written per block row, divided by the average
-    # duration of the solver's own Arnoldi SpMVs over the timed steps (HIP
-    # events recorded by the library on this stream around each launch).
+    # 24 B x read + 24 B y written per block row (structured indices: the
+    # column indices the sliced kernel also reads are not counted), divided by
+    # the average duration of the solver's own Arnoldi SpMVs over the timed
+    # steps (HIP events recorded by the library on this stream around each
+    # launch).  The condensed form's solver multiplies by the reduced system:
+    # N fracture rows and the wells, without the 3 blocks per location of the
+    # fracture-matrix pairs.
     spmv_calls = sum(inf["spmv_calls"] for _, inf in rec)
     spmv_us = 1000.0 * sum(inf["spmv_ms"] for _, inf in rec) / max(spmv_calls, 1)
-    # (the general BSR form of workload 4 also reads its int32 indices)
-    spmv_bytes = 72.0 * nnzb + 48.0 * n if wl != 4 else 76.0 * nnzb + 52.0 * n
+    op_rows = c0.n + c0.nrate if condensed else n
+    op_nnzb = nnzb - 3 * c0.n if condensed else nnzb
+    spmv_bytes = 72.0 * op_nnzb + 48.0 * op_rows
     spmv_gbs = spmv_bytes / (spmv_us * 1e-6) / 1e9
     spmv = {"us": spmv_us, "GBs": spmv_gbs, "bytes": spmv_bytes, "launches": spmv_calls}
     if args.spmv_isolated:
-        spmv.update(isolated_spmv(args, B, pc, n, dev, stream))
+        spmv.update(isolated_spmv(args, B, pc, op_rows, dev, stream))
     if args.ceiling:
         spmv.update(stream_ceiling(args, dev, stream))
     # plain copy of known size: calibrates the HBM byte counters of a profile
@@ -183,7 +200,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, cases[0] if wl != 4 else cg.make_cfg4(1, scale=8), wl)
+        cpu = cpu_baseline(args, c0 if wl != 4 else cg.make_cfg4(1, scale=8), wl, condensed)
     out = {
         "metric": METRIC,
         "value": ms_per_step / 1000.0,
@@ -205,6 +222,10 @@ def main():
                          + (f"{len(systems)} systems of the synthetic 30-day step sequence" if wl else "one system")),
             "solver": ("FGMRES(30), CPR-PF: block quasi-IMPES, SA-AMG V(1,1) RB-GS/l1-Jacobi, tiled BILU0 8x8"
                        if wl != 4 else
+                       "matrix cells eliminated exactly; FGMRES(30) on the reduced system (fracture cells and "
+                       "fixed-rate wells), CPR-FPF: block quasi-IMPES over all of its rows, SA-AMG V(1,1) "
+                       "l1-Jacobi, tiled BILU0 8x8 (fracture tiles, wells); true residual of the full system"
+                       if condensed else
                        "FGMRES(30), CPR-FPF extended grid form: block quasi-IMPES over cell and well rows, "
                        "SA-AMG V(1,1) l1-Jacobi, tiled BILU0 8x8 (fracture tiles, matrix cells, wells)"),
             "precision": args.precision,
@@ -216,8 +237,8 @@ def main():
         "iterations": its,
         "spmv": spmv,
         "roofline": {"bound": "hbm", "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": spmv_traffic() if wl == 1 else None,
-                     "traffic_unit": "B per launch", "kernel": "k_slot_spmv"},
+                     "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": spmv_traffic(wl, condensed),
+                     "traffic_unit": "B per launch", "kernel": "k_slot_spmv" if wl != 4 else "k_sell_spmv"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -236,10 +257,12 @@ def spmv_source_hash():
     return hashlib.sha256((src[k0:k1] + src[w0:w1]).encode()).hexdigest()
 
 
-def spmv_traffic():
+def spmv_traffic(wl, condensed):
     """HBM bytes per SpMV launch from the committed counter summary (rocprofv3
     FETCH_SIZE / WRITE_SIZE scaled by a 256 MiB copy), or None once the kernel
     source differs from the one the counters were taken of."""
+    if wl != 1:
+        return None
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
@@ -315,19 +338,23 @@ def isolated_spmv(args, B, pc, n, dev, stream):
     return {"isolated_cold_us": cold_us, "isolated_back_to_back_us": warm_us}
 
 
-def cpu_baseline(args, case, wl):
+def cpu_baseline(args, case, wl, condensed):
     """The FP64 oracle on the host: one system (assembly + setup + solve); for
-    the dual-porosity workload on its 50x50x25 twin."""
+    the dual-porosity workload on its 50x50x25-location twin."""
     from oracle import oracle as O
     log(args, "[bench] cpu baseline: oracle on one system")
     t0 = time.perf_counter()
     P = O.Problem(case)
     rp, ci, val, R = O.jacobian(P)
-    if wl == 4:
+    if wl == 4 and condensed:
+        cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, fpf=1)
+        x, info = O.condensed_fgmres(rp, ci, val, -R, cond)
+    elif wl == 4:
         pc = O.Cpr(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, npr=P.rows, fpf=1)
+        x, info = O.fgmres(rp, ci, val, -R, pc)
     else:
         pc = O.Cpr(P, rp, ci, val)
-    x, info = O.fgmres(rp, ci, val, -R, pc)
+        x, info = O.fgmres(rp, ci, val, -R, pc)
     t1 = time.perf_counter()
     log(args, f"[bench] cpu baseline: {t1 - t0:.2f} s, its={info['iterations']}")
     return {"value": t1 - t0, "unit": "s", "cores": 1, "kind": "oracle",

@@ -30,6 +30,7 @@ noise amplitude, as in a Newton iterate of a real run.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import List, Optional
 
@@ -163,21 +164,25 @@ NOISE_LATTICE = (8, 8, 4)
 def smooth_noise(seed, field_id, nx, ny, nz, lattice=NOISE_LATTICE) -> np.ndarray:
     """Spatially correlated noise in [-1, 1]: i.i.d. U(-1,1) values on a coarse
     lattice with spacing ``lattice`` cells, trilinearly interpolated to cell
-    centres."""
+    centres (the weight of each of the 8 lattice corners is the product of
+    its x, y and z weights, taken in that order)."""
     Lx, Ly, Lz = lattice
     mx, my, mz = nx // Lx + 2, ny // Ly + 2, nz // Lz + 2
     lat = (2.0 * uniform(seed, field_id, np.arange(mx * my * mz, dtype=np.uint64)) - 1.0).reshape(mz, my, mx)
-    i, j, k = _cell_ijk(nx, ny, nz)
-    fx, fy, fz = (i + 0.5) / Lx, (j + 0.5) / Ly, (k + 0.5) / Lz
+    fx = (np.arange(nx, dtype=np.int64) + 0.5) / Lx
+    fy = (np.arange(ny, dtype=np.int64) + 0.5) / Ly
+    fz = (np.arange(nz, dtype=np.int64) + 0.5) / Lz
     ix, iy, iz = np.floor(fx).astype(np.int64), np.floor(fy).astype(np.int64), np.floor(fz).astype(np.int64)
     tx, ty, tz = fx - ix, fy - iy, fz - iz
-    out = np.zeros(nx * ny * nz)
+    out = np.zeros((nz, ny, nx))
     for a in (0, 1):
+        wx = tx if a else 1.0 - tx
         for b in (0, 1):
+            wxy = wx[None, :] * (ty if b else 1.0 - ty)[:, None]
             for c in (0, 1):
-                w = (tx if a else 1.0 - tx) * (ty if b else 1.0 - ty) * (tz if c else 1.0 - tz)
-                out += w * lat[iz + c, iy + b, ix + a]
-    return out
+                w = wxy[None, :, :] * (tz if c else 1.0 - tz)[:, None, None]
+                out += w * lat[np.ix_(iz + c, iy + b, ix + a)]
+    return out.reshape(-1)
 
 
 def _noisy_state(seed, nx, ny, nz, p=3000.0, sw=0.25, sg=0.05, rel=0.05, noise="smooth"):
@@ -234,17 +239,21 @@ def _sequence_state(base, nx, ny, nz, dx, dy, wells, t):
     falls near the producer, a water front grows from the injectors."""
     if t == 0.0:
         return base.copy()
-    i, j, _ = _cell_ijk(nx, ny, nz)
+    # every quantity below depends on the column (i, j) only: computed on the
+    # nx x ny columns and repeated over the layers
+    i = np.arange(nx, dtype=np.int64)[None, :]
+    j = np.arange(ny, dtype=np.int64)[:, None]
     xc, yc = (i + 0.5) * dx, (j + 0.5) * dy
     L = 0.2 * nx * dx
     inj = [w for w in wells if w.kind == "inj"]
     prod = [w for w in wells if w.kind == "prod"]
     d_inj = [np.hypot(xc - (w.i + 0.5) * dx, yc - (w.j + 0.5) * dy) for w in inj]
     d_prod = [np.hypot(xc - (w.i + 0.5) * dx, yc - (w.j + 0.5) * dy) for w in prod]
-    shape = sum(np.exp(-d / L) for d in d_inj) - sum(np.exp(-d / L) for d in d_prod)
+    layers = lambda a: np.broadcast_to(a, (nz, ny, nx)).reshape(-1)
+    shape = layers(sum(np.exp(-d / L) for d in d_inj) - sum(np.exp(-d / L) for d in d_prod))
     x = base.copy()
     x[0::3] = base[0::3] + 300.0 * (1.0 - math.exp(-t / 10.0)) * shape
-    dmin = np.min(np.stack(d_inj), axis=0)
+    dmin = layers(np.min(np.stack(d_inj), axis=0))
     R = 0.3 * nx * dx * math.sqrt(t / 30.0)
     sw0 = base[1::3]
     x[1::3] = sw0 + (0.75 - sw0) * 0.5 * (1.0 - np.tanh((dmin - R) / (3.0 * dx)))
@@ -346,11 +355,12 @@ def kazemi_sigma(lx=SHAPE_L, ly=SHAPE_L, lz=SHAPE_L) -> float:
     return 4.0 * (1.0 / lx ** 2 + 1.0 / ly ** 2 + 1.0 / lz ** 2)
 
 
-def _dual_state(seed, nx, ny, nz, xf_old, xf_new, wells):
+def _dual_state(seed, nx, ny, nz, xf_old, xf_new, wells, lag=None):
     """Matrix cells lag the fractures by one step, with their own correlated
     noise; fixed-rate wells start from the target BHP of their kind."""
     n = nx * ny * nz
-    lag = 1.0 + 0.02 * (smooth_noise(seed, _F_MSTATE, nx, ny, nz) - 0.5)
+    if lag is None:
+        lag = _matrix_lag(seed, nx, ny, nz)
     xm_new = xf_old.copy()
     xm_new[0::3] *= lag
     xm_old = xm_new.copy()
@@ -384,6 +394,24 @@ def line_drive_wells(seed, nx, ny, nz, lines, cols, jitter, rate=2000.0):
     return wells
 
 
+def _matrix_lag(seed, nx, ny, nz):
+    return 1.0 + 0.02 * (smooth_noise(seed, _F_MSTATE, nx, ny, nz) - 0.5)
+
+
+@functools.lru_cache(maxsize=1)
+def _dual_fields(nx, ny, nz, seed, kf_mean, km_mean, sigma_ln):
+    """The parts of a dual-porosity case that do not depend on the system of
+    the step sequence (kept for the next system of the same field; callers
+    must not modify the arrays)."""
+    n = nx * ny * nz
+    kx = _lognormal(seed, n, math.log(kf_mean), sigma_ln)
+    km = np.exp(math.log(km_mean) + sigma_ln * normal(seed, _F_KM, np.arange(n, dtype=np.uint64)))
+    phim = 0.15 + 0.10 * uniform(seed, _F_PHIM, np.arange(n, dtype=np.uint64))
+    base = _noisy_state(seed, nx, ny, nz)
+    lag = _matrix_lag(seed, nx, ny, nz)
+    return kx, km, phim, base, lag
+
+
 def make_dual_case(nx: int, ny: int, nz: int, seed: int, system: int = 1, wells=None,
                    kf_mean: float = 500.0, km_mean: float = 1.0, sigma_ln: float = 1.0, name=None) -> Case:
     """Dual-porosity case: fractures log-normal around kf_mean (kz = 0.1 kx),
@@ -391,15 +419,13 @@ def make_dual_case(nx: int, ny: int, nz: int, seed: int, system: int = 1, wells=
     the step sequence of the other workloads applied to the fractures."""
     dx, dy, dz, top = 50.0, 50.0, 10.0, 8000.0
     n = nx * ny * nz
-    kx = _lognormal(seed, n, math.log(kf_mean), sigma_ln)
-    km = np.exp(math.log(km_mean) + sigma_ln * normal(seed, _F_KM, np.arange(n, dtype=np.uint64)))
-    phim = 0.15 + 0.10 * uniform(seed, _F_PHIM, np.arange(n, dtype=np.uint64))
+    kx, km, phim, base, lag = _dual_fields(nx, ny, nz, seed, float(kf_mean), float(km_mean), float(sigma_ln))
+    kx, km, phim = kx.copy(), km.copy(), phim.copy()
     if wells is None:
         wells = _five_spot(nx, ny, nz)
-    base = _noisy_state(seed, nx, ny, nz)
     xf_old = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * (system - 1))
     xf_new = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * system)
-    x_old, x_new = _dual_state(seed, nx, ny, nz, xf_old, xf_new, wells)
+    x_old, x_new = _dual_state(seed, nx, ny, nz, xf_old, xf_new, wells, lag)
     return Case(name or f"dual{nx}x{ny}x{nz}.{system}", nx, ny, nz, dx, dy, dz, top, kx, kx.copy(), 0.1 * kx,
                 np.full(n, PHI_F), x_old, x_new, 3.0, wells, dict(FLUID), dual=True, km=km, phim=phim,
                 sigma=kazemi_sigma())
