@@ -260,12 +260,14 @@ def _sequence_state(base, nx, ny, nz, dx, dy, wells, t):
     return x
 
 
-def make_case(cfg: int, system: int = 1) -> Case:
+def make_case(cfg: int, system: int = 1, noise: str = "smooth") -> Case:
     """The synthetic Jacobian-producing state of workload ``cfg`` (0, 1 or 2).
 
     For cfg 0 the Jacobian is taken at the first Newton iterate
     (x_new == x_old, dt = 1 day).  For cfg 1 and 2, ``system`` k = 1..10 takes
     x_old = state(3(k-1) days) and x_new = state(3k days) with dt = 3 days.
+    ``noise``: "smooth" (the correlated state noise) or "iid" (independent
+    per cell; the case name then ends in "/iid").
     """
     dx, dy, dz, top = 50.0, 50.0, 10.0, 8000.0
     if cfg == 0:
@@ -275,8 +277,8 @@ def make_case(cfg: int, system: int = 1) -> Case:
         kx = _lognormal(seed, n, math.log(100.0), 1.0)
         wells = [Well(0, 0, 0, nz - 1, "inj", "bhp", 3500.0),
                  Well(nx - 1, ny - 1, 0, nz - 1, "prod", "bhp", 2500.0)]
-        x = _noisy_state(seed, nx, ny, nz)
-        return Case("cfg0", nx, ny, nz, dx, dy, dz, top, kx, kx.copy(), 0.1 * kx,
+        x = _noisy_state(seed, nx, ny, nz, noise=noise)
+        return Case("cfg0" + ("/iid" if noise == "iid" else ""), nx, ny, nz, dx, dy, dz, top, kx, kx.copy(), 0.1 * kx,
                     _porosity(seed, n), x, x.copy(), 1.0, wells, dict(FLUID))
     if cfg in (1, 2):
         if not 1 <= system <= N_SYSTEMS:
@@ -297,10 +299,11 @@ def make_case(cfg: int, system: int = 1) -> Case:
             kx[bar] = 0.01
             kz[bar] = 0.01
         wells = _five_spot(nx, ny, nz)
-        base = _noisy_state(seed, nx, ny, nz)
+        base = _noisy_state(seed, nx, ny, nz, noise=noise)
         x_old = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * (system - 1))
         x_new = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * system)
-        return Case(f"cfg{cfg}.{system}", nx, ny, nz, dx, dy, dz, top, kx, kx.copy(), kz,
+        return Case(f"cfg{cfg}.{system}" + ("/iid" if noise == "iid" else ""), nx, ny, nz, dx, dy, dz, top, kx,
+                    kx.copy(), kz,
                     _porosity(seed, n), x_old, x_new, 3.0, wells, dict(FLUID))
     raise ValueError(f"unknown workload {cfg}")
 

@@ -211,6 +211,20 @@ int or_fgmres(int n, const int32_t *rowptr, const int32_t *colind, const double 
 int or_arnoldi(int n, const int32_t *rowptr, const int32_t *colind, const double *val,
                or_cpr *pc, const double *b, int k, int orth, double *Z, double *V, double *H);
 
+/* The AMG setup rules on a caller-given scalar CSR matrix (for pins):
+ * or_amg_only builds the hierarchy alone (l1-Jacobi, no grid) into a handle
+ * that the level getters and or_cpr_vcycle accept (keep_singular: a singular
+ * coarsest matrix still returns the handle, with OR_ERR_SINGULAR_COARSE); or_amg_strength writes the
+ * symmetrised strength flag of every entry; or_amg_aggregate runs phase 1 and
+ * phase 2 of the aggregation from caller-chosen roots (root[i] = 1) and
+ * returns the number of aggregates. */
+int or_amg_only(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double theta,
+                int coarse_max, int max_levels, int keep_singular, or_cpr **out);
+int or_amg_strength(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double theta,
+                    uint8_t *sf);
+int or_amg_aggregate(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double theta,
+                     const uint8_t *root, int32_t *agg);
+
 /* ---- Exact elimination of the matrix cells (dual porosity) ------------- */
 /* For a dual-porosity system (rows: N fracture cells, N matrix cells, nw
  * fixed-rate well rows) the reduced system over the fracture cells and the

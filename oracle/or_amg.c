@@ -276,6 +276,27 @@ static void prolongator(const or_csr *A, const uint8_t *sf, const int32_t *agg, 
     free(aF); free(s); free(mark); free(cols);
 }
 
+/* ---- the setup rules on a caller-given matrix (pins) ----------------------- */
+void or_amg_strength_flags(const or_csr *A, double theta, uint8_t *sf) { strength(A, theta, sf); }
+
+/* Aggregates from caller-chosen roots (1 = root): phase 1 and phase 2 of the
+ * aggregation with the strength flags of theta; nodes without a strong
+ * neighbour stay unaggregated (-1).  Returns the number of aggregates. */
+int or_amg_aggregate_roots(const or_csr *A, double theta, const uint8_t *root, int32_t *agg)
+{
+    int n = A->n;
+    uint8_t *sf = malloc((size_t)(A->nnz > 0 ? A->nnz : 1)), *state = malloc((size_t)(n > 0 ? n : 1));
+    strength(A, theta, sf);
+    for (int i = 0; i < n; i++) {
+        int deg = 0;
+        for (int e = A->rp[i]; e < A->rp[i + 1]; e++) deg += sf[e];
+        state[i] = root[i] ? IN : (deg ? OUT : ISO);
+    }
+    int nc = aggregate(A, sf, state, agg);
+    free(sf); free(state);
+    return nc;
+}
+
 void or_amg_free(or_amg *h)
 {
     for (int l = 0; l < OR_MAXLEV; l++) {
@@ -362,12 +383,10 @@ int or_amg_setup(or_amg *h, const or_csr *A0, int nx, int ny, int nz, double the
         h->dense = calloc((size_t)nc * nc, sizeof(double));
         for (int i = 0; i < nc; i++)
             for (int e = C->rp[i]; e < C->rp[i + 1]; e++) h->dense[(size_t)i * nc + C->ci[e]] = C->v[e];
-        /* singularity check on a copy */
-        double *tmp = malloc(sizeof(double) * (size_t)nc * nc), *rhs = calloc((size_t)nc, sizeof(double));
-        memcpy(tmp, h->dense, sizeof(double) * (size_t)nc * nc);
-        int st = or_dense_solve(nc, tmp, rhs);
-        free(tmp); free(rhs);
-        if (st) return OR_ERR_SINGULAR_COARSE;
+        /* singular to working precision: a pivot (partial pivoting) at or
+         * below 1e-12 of the largest entry (a pure-Neumann pressure block
+         * gives about 1e-16 of it) */
+        if (!(or_dense_min_pivot_ratio(nc, h->dense) > 1e-12)) return OR_ERR_SINGULAR_COARSE;
     }
     return OR_OK;
 }

@@ -35,5 +35,7 @@ int or_amg_setup(or_amg *h, const or_csr *A0, int nx, int ny, int nz, double the
 void or_amg_vcycle(const or_amg *h, const double *b, double *x);
 void or_amg_free(or_amg *h);
 int or_amg_make_f32(or_amg *h);
+void or_amg_strength_flags(const or_csr *A, double theta, uint8_t *sf);
+int or_amg_aggregate_roots(const or_csr *A, double theta, const uint8_t *root, int32_t *agg);
 void or_amg_vcycle_f32(const or_amg *h, const float *b, float *x);
 #endif

@@ -340,6 +340,42 @@ int or_cpr_setup(const or_problem *p, int n, const int32_t *rowptr, const int32_
     return OR_OK;
 }
 
+/* A handle holding only the AMG hierarchy of a caller-given scalar CSR
+ * matrix (l1-Jacobi smoothing, no grid): the hierarchy getters and
+ * or_cpr_vcycle work on it. */
+int or_amg_only(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double theta,
+                int coarse_max, int max_levels, int keep_singular, or_cpr **out)
+{
+    *out = NULL;
+    or_cpr *c = calloc(1, sizeof *c);
+    if (!c) return OR_ERR_ALLOC;
+    c->n = n;
+    c->npr = n;
+    c->o.precision = OR_PREC_FP64;
+    or_csr A0 = { n, n, rowptr[n], (int32_t *)rowptr, (int32_t *)colind, (double *)val };
+    int st = or_amg_setup(&c->amg, &A0, 0, 0, 0, theta, coarse_max, max_levels, OR_SMOOTH_L1, 1, OR_CSMOOTH_L1);
+    c->has_amg = 1;
+    /* the hierarchy is complete when only the coarsest matrix is singular */
+    if (st && !(keep_singular && st == OR_ERR_SINGULAR_COARSE)) { or_cpr_free(c); return st; }
+    *out = c;
+    return st;
+}
+
+int or_amg_strength(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double theta,
+                    uint8_t *sf)
+{
+    or_csr A = { n, n, rowptr[n], (int32_t *)rowptr, (int32_t *)colind, (double *)val };
+    or_amg_strength_flags(&A, theta, sf);
+    return OR_OK;
+}
+
+int or_amg_aggregate(int n, const int32_t *rowptr, const int32_t *colind, const double *val, double theta,
+                     const uint8_t *root, int32_t *agg)
+{
+    or_csr A = { n, n, rowptr[n], (int32_t *)rowptr, (int32_t *)colind, (double *)val };
+    return or_amg_aggregate_roots(&A, theta, root, agg);
+}
+
 void or_cpr_free(or_cpr *c)
 {
     if (!c) return;

@@ -6,6 +6,8 @@
 int or_inv3(const double *A, double *Ainv);
 void or_mul3(const double *A, const double *B, double *C);
 void or_mv3(const double *A, const double *x, double *y);
+/* smallest |pivot| of partially pivoted LU over the largest |a_ij| */
+double or_dense_min_pivot_ratio(int n, const double *A);
 
 typedef struct {
     int n, m, nnz;              /* rows, columns, entries */

@@ -104,6 +104,31 @@ int or_inv3(const double *A, double *Ainv)
 }
 
 /* C = A * B for 3x3 blocks */
+/* Smallest |pivot| of LU with partial pivoting relative to the largest
+ * |a_ij| (A row-major n x n, not modified); 0 for a zero matrix. */
+double or_dense_min_pivot_ratio(int n, const double *A)
+{
+    double *M = malloc(sizeof(double) * (size_t)n * n);
+    memcpy(M, A, sizeof(double) * (size_t)n * n);
+    double amax = 0.0, pmin = INFINITY;
+    for (size_t e = 0; e < (size_t)n * n; e++) if (fabs(M[e]) > amax) amax = fabs(M[e]);
+    for (int k = 0; k < n; k++) {
+        int p = k;
+        for (int r = k + 1; r < n; r++) if (fabs(M[(size_t)r * n + k]) > fabs(M[(size_t)p * n + k])) p = r;
+        double pv = fabs(M[(size_t)p * n + k]);
+        if (pv < pmin) pmin = pv;
+        if (pv == 0.0) break;
+        if (p != k)
+            for (int c = 0; c < n; c++) { double t = M[(size_t)k * n + c]; M[(size_t)k * n + c] = M[(size_t)p * n + c]; M[(size_t)p * n + c] = t; }
+        for (int r = k + 1; r < n; r++) {
+            double f = M[(size_t)r * n + k] / M[(size_t)k * n + k];
+            for (int c = k; c < n; c++) M[(size_t)r * n + c] -= f * M[(size_t)k * n + c];
+        }
+    }
+    free(M);
+    return amax > 0.0 ? pmin / amax : 0.0;
+}
+
 void or_mul3(const double *A, const double *B, double *C)
 {
     for (int r = 0; r < 3; r++)

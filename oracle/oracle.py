@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 OR_OK, OR_NOT_CONVERGED = 0, 1
+OR_ERR_SINGULAR_BLOCK, OR_ERR_SINGULAR_COARSE = -5, -6
 F_BJ, F_ILU_NATURAL, F_ILU_RB, F_ILU_TILED = 0, 1, 2, 3
 QI_DIAG, QI_BLOCK = 0, 1
 SMOOTH_GS, SMOOTH_JACOBI, SMOOTH_L1 = 0, 1, 2
@@ -114,6 +115,10 @@ def lib():
                             C.POINTER(FgmresOpts), C.POINTER(FgmresStats), C.c_void_p]
     L.or_arnoldi.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _f64p, C.c_int, C.c_int,
                              _f64p, _f64p, _f64p]
+    L.or_amg_only.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_double, C.c_int, C.c_int, C.c_int,
+                              C.POINTER(C.c_void_p)]
+    L.or_amg_strength.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_double, C.c_void_p]
+    L.or_amg_aggregate.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_double, C.c_void_p, C.c_void_p]
     L.or_condense_pattern.argtypes = [C.c_int, C.c_int, _i32p, _i32p, C.c_void_p, C.c_void_p]
     L.or_condense_values.argtypes = [C.c_int, C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p]
     L.or_condense_rhs.argtypes = [C.c_int, C.c_int, _f64p, _f64p, _f64p]
@@ -499,3 +504,43 @@ def condensed_fgmres(rp, ci, val, b, cond: Condensed, x0=None, m=30, maxit=1500,
         info["passes"] += 1
         x += cond.back(r, d)
     return x, info
+
+
+class AmgOnly(Cpr):
+    """The oracle's AMG hierarchy of a scalar CSR matrix (l1-Jacobi, no grid);
+    level(), nlevels() and vcycle() as for a Cpr handle."""
+
+    def __init__(self, rp, ci, val, theta=0.08, coarse_max=192, max_levels=12, keep_singular=False):
+        """keep_singular: keep the hierarchy of an operator whose coarsest
+        matrix is singular (``status`` then reports it)."""
+        self.rp = np.ascontiguousarray(rp, np.int32)
+        self.ci = np.ascontiguousarray(ci, np.int32)
+        self.val = np.ascontiguousarray(val, np.float64)
+        self.n = self.npr = len(self.rp) - 1
+        h = C.c_void_p()
+        st = lib().or_amg_only(self.n, self.rp, self.ci, self.val, theta, coarse_max, max_levels,
+                               int(keep_singular), C.byref(h))
+        self.status = st
+        if not h.value:
+            raise RuntimeError(f"or_amg_only failed: {st}")
+        self.h = h
+
+
+def amg_strength(rp, ci, val, theta=0.08) -> np.ndarray:
+    """Symmetrised strength flag of every entry of a scalar CSR matrix."""
+    rp = np.ascontiguousarray(rp, np.int32); ci = np.ascontiguousarray(ci, np.int32)
+    sf = np.zeros(max(len(ci), 1), np.uint8)
+    lib().or_amg_strength(len(rp) - 1, rp, ci, np.ascontiguousarray(val, np.float64), theta, sf.ctypes.data)
+    return sf[:len(ci)].astype(bool)
+
+
+def amg_aggregate(rp, ci, val, roots, theta=0.08):
+    """Aggregates (phase 1 and 2) from the given roots; returns (agg, count)."""
+    rp = np.ascontiguousarray(rp, np.int32); ci = np.ascontiguousarray(ci, np.int32)
+    n = len(rp) - 1
+    root = np.zeros(n, np.uint8)
+    root[list(roots)] = 1
+    agg = np.zeros(n, np.int32)
+    nc = lib().or_amg_aggregate(n, rp, ci, np.ascontiguousarray(val, np.float64), theta, root.ctypes.data,
+                                agg.ctypes.data)
+    return agg, nc

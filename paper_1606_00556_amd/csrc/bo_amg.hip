@@ -984,6 +984,12 @@ __global__ void k_dense_from_csr(int n, const int32_t *__restrict__ rp, const in
     for (int e = rp[i]; e < rp[i + 1]; e++) M[(size_t)i * 2 * n + ci[e]] = v[e];
 }
 
+// Relative pivot bound of the coarsest level's elimination: a matrix whose
+// pivot (under partial pivoting) falls to 1e-12 of its largest entry is
+// singular to working precision (a pure-Neumann pressure block gives pivots
+// near 1e-16 of it; the workloads' coarsest matrices 1e-3 and more).
+constexpr double kCoarsePivotTol = 1e-12;
+
 // Gauss-Jordan with partial pivoting on [A | I] (n x 2n, row-major, n <=
 // 1024), one workgroup of 1024 threads; leaves A^{-1} in the right half.
 // Per column: pivot = largest |a_rk| (ties: smallest row), swap, scale the
@@ -994,8 +1000,23 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double *__restrict
     __shared__ double wv[16];
     __shared__ int wi[16];
     __shared__ int piv;
+    __shared__ double thr;
     int t = threadIdx.x, lane = t % 64, wave = t / 64;
     int w = 2 * n;
+    // a pivot at or below kCoarsePivotTol x max |a_ij| marks the matrix singular
+    {
+        double m = 0.0;
+        for (long long e = t; e < (long long)n * n; e += blockDim.x) m = fmax(m, fabs(M[(e / n) * w + e % n]));
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+        if (lane == 0) wv[wave] = m;
+        __syncthreads();
+        if (t == 0) {
+            double mm = wv[0];
+            for (int q = 1; q < 16; q++) mm = fmax(mm, wv[q]);
+            thr = kCoarsePivotTol * mm;
+        }
+        __syncthreads();
+    }
     for (int k = 0; k < n; k++) {
         int r = k + t;
         double bv = r < n ? fabs(M[(size_t)r * w + k]) : -1.0;
@@ -1013,7 +1034,7 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double *__restrict
             for (int q = 1; q < 16; q++)
                 if (wv[q] > best || (wv[q] == best && wi[q] < bidx)) { best = wv[q]; bidx = wi[q]; }
             piv = bidx;
-            if (!(best > 0.0)) *bad = 1;
+            if (!(best > thr)) *bad = 1;
         }
         __syncthreads();
         int p = piv;
@@ -1084,16 +1105,30 @@ __global__ void __launch_bounds__(1024) k_gj_regs(int n, const double *__restric
     __shared__ double colk[2][32 * G];  // column k before the step, rows before the swap
     __shared__ int piv[2];
     __shared__ int orig[32 * G];
+    __shared__ double wmax[16];
+    __shared__ double thr;
     int t = threadIdx.x, tr = t % 32, tc = t / 32;
     int w = 2 * n;
     double a[G][G];
+    double m = 0.0;
 #pragma unroll
     for (int i = 0; i < G; i++)
 #pragma unroll
         for (int j = 0; j < G; j++) {
             int r = tr + 32 * i, c = tc + 32 * j;
             a[i][j] = (r < n && c < n) ? M[(size_t)r * w + c] : 0.0;
+            m = fmax(m, fabs(a[i][j]));
         }
+    // a pivot at or below kCoarsePivotTol x max |a_ij| marks the matrix singular
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if (t % 64 == 0) wmax[t / 64] = m;
+    __syncthreads();
+    if (t == 0) {
+        double mm = wmax[0];
+        for (int q = 1; q < 16; q++) mm = fmax(mm, wmax[q]);
+        thr = kCoarsePivotTol * mm;
+    }
+    __syncthreads();
     for (int q = t; q < n; q += blockDim.x) orig[q] = q;
 #pragma unroll
     for (int kg = 0; kg < G; kg++) {
@@ -1125,7 +1160,7 @@ __global__ void __launch_bounds__(1024) k_gj_regs(int n, const double *__restric
                 if (nan) *bad = 1;
                 if (tr == 0) {
                     piv[h] = bi;
-                    if (!(bv > 0.0)) *bad = 1;
+                    if (!(bv > thr)) *bad = 1;
                 }
             }
             __syncthreads();

@@ -1,19 +1,22 @@
-"""GPU parity at the benchmark's full sizes: the 100x100x50 workload (500k
-cells, the one bench.py times) and the 200x200x50 one (2M cells), first
-system of each step sequence, through the same entry points and launch
-configurations as the benchmark.
+"""GPU parity at full sizes: the 100x100x50 workload (500k cells), the
+200x200x50 one (2M cells), and the 100x100x50-location twin of the
+dual-porosity workload (1M cells) in the condensed form bench.py times,
+through the same entry points and launch configurations as the benchmark.
 
 Jacobian and SpMV are compared with the oracle in full (1e-12, and bit for
-bit on integer data); the CPR application on the 500k-cell system in full
-(1e-10); the solves by their true FP64 residual (recomputed with the
-oracle's SpMV) and by the oracle's iteration count (within 10 %)."""
+bit on integer data); the CPR applications in full, each unknown (Po, Sw, Sg)
+separately (1e-10); the solves -- all 10 systems of the 500k-cell step
+sequence, the first 2M-cell system, an i.i.d.-noise 500k-cell system and the
+dual-porosity twin -- by their true FP64 residual (recomputed with the
+oracle's SpMV) and by the oracle's iteration count (within 10 %); the mixed
+forms report their solution error against the FP64 oracle's."""
 import math
 
 import numpy as np
 import pytest
 
 import bo_casegen as cg
-from tests.gpu_util import device_bsr, rel_err, run_stage, to_dev, to_host
+from tests.gpu_util import device_bsr, rel_err, rel_err_parts, run_stage, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -33,17 +36,22 @@ def O():
 
 
 _SYSTEMS = {}
-_ORACLE_ITS = {}  # the FP64 oracle's iteration count per workload
+_ORACLE = {}  # the FP64 oracle's (iterations, solution) per workload
 
 
-def system(O, cfg):
-    """The oracle's Jacobian of the first system of workload cfg (cached)."""
-    if cfg not in _SYSTEMS:
-        case = cg.make_case(cfg, 1)
-        P = O.Problem(case)
-        rp, ci, val, R = O.jacobian(P)
-        _SYSTEMS[cfg] = (case, P, rp, ci, val, -R)
-    return _SYSTEMS[cfg]
+def system(O, cfg, k=1, noise="smooth"):
+    """The oracle's Jacobian of system k of workload cfg (the first systems
+    cached: several tests use them)."""
+    key = (cfg, k, noise)
+    if key in _SYSTEMS:
+        return _SYSTEMS[key]
+    case = cg.make_case(cfg, k, noise=noise)
+    P = O.Problem(case)
+    rp, ci, val, R = O.jacobian(P)
+    out = (case, P, rp, ci, val, -R)
+    if k == 1 and noise == "smooth":
+        _SYSTEMS[key] = out
+    return out
 
 
 @pytest.mark.parametrize("cfg", [1, 2])
@@ -98,27 +106,23 @@ def test_fullsize_spmv(B, O, cfg):
     assert rel_err(to_host(y), ref) <= 1e-12
 
 
-def test_fullsize_cpr_apply(B, O):
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fullsize_cpr_apply(B, O, cfg):
     """The default CPR (quasi-IMPES, SA-AMG V-cycle with red-black Gauss-Seidel
-    on level 0, 8x8-tile block ILU(0)) on the 500k-cell system, whole
-    vectors against the oracle."""
-    case, P, rp, ci, val, b = system(O, 1)
+    on level 0, 8x8-tile block ILU(0)) on the 500k- and 2M-cell systems,
+    whole vectors against the oracle, each unknown separately."""
+    case, P, rp, ci, val, b = system(O, cfg)
     opc = O.Cpr(P, rp, ci, val)
     gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), B.bo_cpr_default_opts())
     assert B.bo_cpr_levels(gpc) == opc.nlevels()
     n = case.n
     v = np.random.default_rng(7).standard_normal(3 * n)
-    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= 1e-10
-    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, b, 3 * n), opc.apply(b)) <= 1e-10
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= 1e-10
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, b, 3 * n), opc.apply(b)) <= 1e-10
 
 
-@pytest.mark.parametrize("cfg", [1, 2])
-def test_fullsize_solve(B, O, cfg):
-    """bench.py's solve (default options) at full size: converged, a true FP64
-    residual <= 1e-6 recomputed with the oracle's SpMV, and the oracle's
-    iteration count within 10 %."""
+def _solve_and_compare(B, O, case, P, rp, ci, val, b, key=None):
     import torch
-    case, P, rp, ci, val, b = system(O, cfg)
     gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), B.bo_cpr_default_opts())
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
     info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
@@ -127,9 +131,60 @@ def test_fullsize_solve(B, O, cfg):
     true_rel = np.linalg.norm(r) / np.linalg.norm(b)
     assert true_rel <= 1e-6
     assert info["rel_residual"] == pytest.approx(true_rel, rel=1e-6, abs=1e-12)
-    _, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val))
+    xo, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val))
     io = oinfo["iterations"]
-    _ORACLE_ITS[cfg] = io
+    if key is not None:
+        _ORACLE[key] = (io, xo)
+    print(f"{case.name}: iterations gpu {info['iterations']} oracle {io}, true rel {true_rel:.2e}, "
+          f"|x - x_oracle| / |x_oracle| per unknown {rel_err_parts(to_host(x), xo):.2e}")
+    assert abs(info["iterations"] - io) <= max(1, math.ceil(0.1 * io))
+
+
+@pytest.mark.parametrize("k", range(1, 11))
+def test_fullsize_solve_500k_sequence(B, O, k):
+    """bench.py's solve (default options) on every system of the 500k-cell
+    step sequence: converged, a true FP64 residual <= 1e-6 recomputed with the
+    oracle's SpMV, and the oracle's iteration count within 10 %."""
+    case, P, rp, ci, val, b = system(O, 1, k)
+    _solve_and_compare(B, O, case, P, rp, ci, val, b)
+
+
+def test_fullsize_solve_2m(B, O):
+    case, P, rp, ci, val, b = system(O, 2)
+    _solve_and_compare(B, O, case, P, rp, ci, val, b, key=2)
+
+
+def test_fullsize_solve_iid_noise(B, O):
+    """The 500k-cell system with independent per-cell state noise (the
+    survey's reading of the +-5 % noise): a harder pressure block (the
+    decoupled A_pp is not an M-matrix on many rows), same bar."""
+    case, P, rp, ci, val, b = system(O, 1, 1, noise="iid")
+    _solve_and_compare(B, O, case, P, rp, ci, val, b)
+
+
+def test_fullsize_condensed_dual_twin(B, O):
+    """The dual-porosity workload's 100x100x50-location twin (1M cell rows and
+    its fixed-rate wells) in the condensed form bench.py times: the
+    full-length preconditioner application per unknown at 1e-10, and the
+    solve by true residual and the oracle's iteration count."""
+    import torch
+    case = cg.make_cfg4(1, scale=4)
+    P = O.Problem(case)
+    rp, ci, val, R = O.jacobian(P)
+    b = -R
+    cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, fpf=1)
+    opts = B.bo_cpr_default_opts(condense=1, fpf=1, smoother=B.BO_SMOOTH_L1)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz, 1), opts)
+    v = np.random.default_rng(9).standard_normal(3 * P.rows)
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * P.rows), cond.apply(v)) <= 1e-10
+    x = torch.zeros(3 * P.rows, dtype=torch.float64, device="cuda")
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
+    r = b - O.bsr_spmv(rp, ci, val, to_host(x))
+    true_rel = np.linalg.norm(r) / np.linalg.norm(b)
+    xo, oinfo = O.condensed_fgmres(rp, ci, val, b, cond)
+    io = oinfo["iterations"]
+    print(f"{case.name} condensed: iterations gpu {info['iterations']} oracle {io}, true rel {true_rel:.2e}")
+    assert info["converged"] and true_rel <= 1e-6
     assert abs(info["iterations"] - io) <= max(1, math.ceil(0.1 * io))
 
 
@@ -148,9 +203,15 @@ def test_fullsize_mixed_solve(B, O, prec):
     assert info["converged"] and info["status"] == B.BO_OK
     r = b - O.bsr_spmv(rp, ci, val, to_host(x))
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
-    if 2 not in _ORACLE_ITS:
-        _, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val))
-        _ORACLE_ITS[2] = oinfo["iterations"]
-    io = _ORACLE_ITS[2]
+    if 2 not in _ORACLE:
+        xo, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val))
+        _ORACLE[2] = (oinfo["iterations"], xo)
+    io, xo = _ORACLE[2]
+    err = rel_err_parts(to_host(x), xo)
+    print(f"2M cells {prec}: iterations {info['iterations']} (FP64 oracle {io}), "
+          f"|x - x_oracle| / |x_oracle| per unknown {err:.2e}")
+    # both solutions meet the 1e-6 residual; their difference is the
+    # conditioning of the system times that, far below a per cent
+    assert err <= 1e-2
     assert info["iterations"] <= io + max(1, math.ceil(0.1 * io))
 

@@ -11,8 +11,8 @@ import numpy as np
 import pytest
 
 import bo_casegen as cg
-from tests.gpu_util import (device_bsr, matching_opts, oracle_system, ragged_case, rel_err, run_stage, setup_both,
-                            solve_both, to_dev, to_host)
+from tests.gpu_util import (device_bsr, matching_opts, oracle_system, ragged_case, rel_err, rel_err_parts, run_stage,
+                            setup_both, solve_both, to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -103,11 +103,14 @@ def test_spmv_axpby_random(B, O):
     A = device_bsr(B, rp, ci, val)
     pc = B.bo_cpr_setup(A, (case.nx, case.ny, case.nz), B.bo_cpr_default_opts(use_amg=0, ftype=B.BO_F_BJ))
     y = to_dev(y0.copy())
+    # element-wise, each entry against the size of its own terms (sum of
+    # |alpha a_ij x_j| and |beta y_i|): no cancellation hides an error
+    mag = 0.75 * O.bsr_spmv(rp, ci, np.abs(val), np.abs(x)) + 1.5 * np.abs(y0)
     B.bo_cpr_spmv(pc, -0.75, to_dev(x), 1.5, y)
-    assert rel_err(to_host(y), ref) <= 1e-12
+    assert np.all(np.abs(to_host(y) - ref) <= 1e-14 * mag)
     y = to_dev(y0.copy())
     B.bo_bsr_spmv(A, -0.75, to_dev(x), 1.5, y)
-    assert rel_err(to_host(y), ref) <= 1e-12
+    assert np.all(np.abs(to_host(y) - ref) <= 1e-14 * mag)
 
 
 def test_decoupling_weights_bitwise(B, O):
@@ -146,9 +149,9 @@ def test_stages_match_oracle(B, O, name):
     assert rel_err(run_stage(B, gpc, B.bo_cpr_restrict, v, n), opc.restrict(v)) <= 1e-14
     rp = rng.standard_normal(n)
     assert rel_err(run_stage(B, gpc, B.bo_cpr_vcycle, rp, n), opc.vcycle(rp)) <= 1e-10
-    assert rel_err(run_stage(B, gpc, B.bo_cpr_fstage, v, 3 * n), opc.fstage(v)) <= 1e-10
-    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= 1e-10
-    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, b, 3 * n), opc.apply(b)) <= 1e-10
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_fstage, v, 3 * n), opc.fstage(v)) <= 1e-10
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= 1e-10
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, b, 3 * n), opc.apply(b)) <= 1e-10
 
 
 @pytest.mark.parametrize("kw", [dict(fpf=1), dict(ftype="bj"), dict(smoother="jacobi", sweeps=2),
@@ -158,7 +161,7 @@ def test_cpr_variants_match_oracle(B, O, kw):
     case = ragged_case(seed=31)
     _, _, _, _, b, opc, gpc = setup_both(B, O, case, coarse_max=40, **kw)
     v = np.random.default_rng(8).standard_normal(3 * case.n)
-    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * case.n), opc.apply(v)) <= 1e-10
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * case.n), opc.apply(v)) <= 1e-10
 
 
 @pytest.mark.parametrize("dims", [(9, 7, 5), (8, 7, 5), (7, 6, 5), (5, 5, 5)])
@@ -173,7 +176,7 @@ def test_gauss_seidel_colour_pairs(B, O, dims):
     r = np.random.default_rng(12).standard_normal(n)
     assert rel_err(run_stage(B, gpc, B.bo_cpr_vcycle, r, n), opc.vcycle(r)) <= 1e-10
     v = np.random.default_rng(13).standard_normal(3 * n)
-    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= 1e-10
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= 1e-10
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(precision="fp32"), dict(csmoother="jacobi", sweeps=2)])
@@ -189,20 +192,24 @@ def test_sliced_coarse_matrices_match_oracle(B, O, kw):
     r = np.random.default_rng(14).standard_normal(n)
     assert rel_err(run_stage(B, gpc, B.bo_cpr_vcycle, r, n), opc.vcycle(r)) <= tol
     v = np.random.default_rng(15).standard_normal(3 * n)
-    assert rel_err(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= tol
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * n), opc.apply(v)) <= tol
 
 
-def test_ilu_pivots_bitwise(B, O):
-    """The tiled block-ILU(0) pivots are produced by the same operations in the
-    same order on both sides: identical bits."""
+def test_ilu_unit_responses_match_oracle(B, O):
+    """The tiled block-ILU(0) factors seen through F applied to unit vectors
+    (the first cell of a tile and a cell in a tile's interior): element-wise
+    within 1e-13 of each entry's scale (the GPU forms the pivots in the
+    diagonal form of ILU(0), the oracle in the IKJ form: same values, other
+    rounding order)."""
     case = ragged_case(seed=41)
     _, _, _, _, _, opc, gpc = setup_both(B, O, case)
-    import torch
-    # the pivots are visible through F applied to unit vectors on a 1-cell tile
-    v = np.zeros(3 * case.n)
-    v[0] = 1.0
-    x = run_stage(B, gpc, B.bo_cpr_fstage, v, 3 * case.n)
-    assert rel_err(x, opc.fstage(v)) <= 1e-13
+    for cell, comp in ((0, 0), (0, 2), (3 + case.nx * (4 + case.ny * 2), 1)):
+        v = np.zeros(3 * case.n)
+        v[3 * cell + comp] = 1.0
+        x = run_stage(B, gpc, B.bo_cpr_fstage, v, 3 * case.n)
+        ref = opc.fstage(v)
+        assert np.all(np.abs(x - ref) <= 1e-13 * np.abs(ref).max())
+        assert rel_err_parts(x, ref) <= 1e-12
 
 
 @pytest.mark.parametrize("name", ["ragged", "cfg0"])
@@ -250,6 +257,30 @@ def test_delayed_request_falls_back_to_cgs2_exactly(B, O):
     assert np.array_equal(xs[0], xs[1])
     r = b - O.bsr_spmv(rp, ci, val, xs[0])
     assert np.linalg.norm(r) <= 1e-6 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("orth", [0, 1, 2])
+def test_gmres_minimal_residual_after_k_steps(B, O, orth):
+    """After k steps without restart, flexible GMRES with a fixed (linear)
+    preconditioner returns the minimal residual over x0 + span(Z_k): a
+    property of the Krylov space, not of the Gram-Schmidt form.  Each GPU form
+    (MGS, CGS2, CGS2 with the second projection delayed one step) must reach
+    the oracle's true residual after k steps; a wrong Hessenberg column or a
+    lost basis vector leaves a larger one."""
+    import torch
+    case = ragged_case(seed=43)
+    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
+    for k in (1, 2, 3, 5, 8, 10):
+        _, oi = O.fgmres(rp, ci, val, b, opc, maxit=k, rtol=1e-15)
+        # (steps whose residual is still far above rounding: near 1e-15 the
+        # minimal residual is no longer determined by the space alone)
+        assert oi["rel_residual"] > 1e-11
+        x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
+        gi = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x, B.bo_fgmres_default_opts(orth=orth, maxit=k, rtol=1e-15))
+        assert gi["iterations"] == oi["iterations"] == k
+        r = b - O.bsr_spmv(rp, ci, val, to_host(x))
+        rel = np.linalg.norm(r) / np.linalg.norm(b)
+        assert rel == pytest.approx(oi["rel_residual"], rel=1e-6), (k, rel, oi["rel_residual"])
 
 
 def test_fgmres_delayed_small_restart(B, O):
@@ -425,3 +456,54 @@ def test_failed_update_leaves_handle_unusable(B, O):
         B.bo_fgmres_solve(pc, pc.A, to_dev(b), x)
     B.bo_cpr_update(pc, device_bsr(B, rp, ci, val))
     assert B.bo_fgmres_solve(pc, pc.A, to_dev(b), x)["converged"]
+
+
+def _singular_pair_system():
+    """Two cells on a 2x1x1 grid with blocks [[I, -I], [-I, I]]: singular,
+    range {(y, -y)}; its decoupled pressure block is [[1, -1], [-1, 1]]."""
+    rp = np.array([0, 2, 4], np.int32)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    I = np.eye(3)
+    val = np.stack([I, -I, -I, I])
+    return rp, ci, val
+
+
+def test_singular_coarse_is_reported(B, O):
+    """A singular coarsest pressure matrix: the hand-built pair, and the
+    incompressible Jacobian without wells (a pure-Neumann pressure block,
+    singular to rounding), fail the setup with BO_ERR_SINGULAR_COARSE, as
+    the oracle's setup does."""
+    from tests.test_oracle_solver import incompressible_no_well_case
+    rp, ci, val = _singular_pair_system()
+    with pytest.raises(B.BoError) as e:
+        B.bo_cpr_setup(device_bsr(B, rp, ci, val), (2, 1, 1))
+    assert e.value.status == B.BO_ERR_SINGULAR_COARSE
+    c = incompressible_no_well_case()
+    P, rp, ci, val, b = oracle_system(O, c)
+    for cm in (192, 40, 10):
+        with pytest.raises(B.BoError) as e:
+            B.bo_cpr_setup(device_bsr(B, rp, ci, val), (c.nx, c.ny, c.nz), B.bo_cpr_default_opts(coarse_max=cm))
+        assert e.value.status == B.BO_ERR_SINGULAR_COARSE, cm
+
+
+@pytest.mark.parametrize("orth", [0, 1, 2])
+def test_arnoldi_breakdown_is_reported(B, O, orth):
+    """The singular pair with an inconsistent right-hand side (u, u) and an
+    exact block-Jacobi F stage (1x1 tiles, no pressure stage): z_1 = v_1 lies
+    in the null space, A z_1 = 0, the Hessenberg column is zero and the
+    least-squares problem singular: BO_ERR_BREAKDOWN, x left at the initial
+    guess."""
+    import torch
+    rp, ci, val = _singular_pair_system()
+    A = device_bsr(B, rp, ci, val)
+    pc = B.bo_cpr_setup(A, (2, 1, 1), B.bo_cpr_default_opts(use_amg=0, tile=(1, 1)))
+    b = to_dev(np.array([1.0, 2.0, 3.0, 1.0, 2.0, 3.0]))
+    x = torch.zeros(6, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.BoError) as e:
+        B.bo_fgmres_solve(pc, A, b, x, B.bo_fgmres_default_opts(orth=orth))
+    assert e.value.status == B.BO_ERR_BREAKDOWN
+    assert float(x.abs().max()) == 0.0
+    # a consistent right-hand side (y, -y) converges in one step (happy breakdown)
+    b2 = to_dev(np.array([1.0, 2.0, 3.0, -1.0, -2.0, -3.0]))
+    info = B.bo_fgmres_solve(pc, A, b2, x, B.bo_fgmres_default_opts(orth=orth))
+    assert info["converged"] and info["iterations"] == 1

@@ -326,3 +326,34 @@ def test_l1_smoother_keeps_high_contrast_cycle_convergent(oracle_lib):
             x = x + pc.vcycle(b - A @ x)
         out[cs] = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
     assert out[O.CSMOOTH_L1] < 0.2 and out[O.CSMOOTH_JACOBI] > 1.0
+
+
+def incompressible_no_well_case():
+    """No wells, rigid rock, constant formation-volume factors and solution
+    gas: accumulation has no pressure derivative, so every component's
+    pressure block has zero row sums and the decoupled pressure block (and
+    every Galerkin product of it) is singular: a pure-Neumann operator."""
+    import dataclasses
+    c = cg.tiny_case(6, 5, 4, seed=8, wells=[], step=0.0)
+    fl = dict(c.fluid)
+    fl.update(c_r=0.0, cw=0.0, co=0.0, cg=0.0, crs=0.0)
+    return dataclasses.replace(c, fluid=fl)
+
+
+def test_singular_pressure_block_is_reported(oracle_lib):
+    O = oracle_lib
+    import scipy.sparse as sp
+    c = incompressible_no_well_case()
+    P = O.Problem(c)
+    rp, ci, val, R = O.jacobian(P)
+    w, app = O.qi_decouple(rp, ci, val)
+    A = sp.csr_matrix((app, ci, rp), shape=(c.n, c.n))
+    assert np.abs(A @ np.ones(c.n)).max() <= 1e-13 * np.abs(app).max()
+    for cm in (192, 40, 10):
+        with pytest.raises(RuntimeError) as e:
+            O.Cpr(P, rp, ci, val, coarse_max=cm)
+        assert str(O.OR_ERR_SINGULAR_COARSE) in str(e.value)
+    # the same grid with its wells and compressibilities sets up (the bound is
+    # far from the workloads' coarsest pivots)
+    P2 = O.Problem(cg.tiny_case(6, 5, 4, seed=8, step=0.0))
+    O.Cpr(P2, *O.jacobian(P2)[:3])
