@@ -33,6 +33,7 @@
  */
 #ifndef BO_H
 #define BO_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -238,6 +239,22 @@ void bo_cpr_default_opts(bo_cpr_opts *o);
 
 typedef struct bo_cpr bo_cpr;
 
+/* A caller-supplied device allocator for a CPR handle's memory (hierarchy,
+ * factors, copies of the operator, Krylov basis, work vectors).  alloc
+ * returns `bytes` of device memory usable on the stream passed (NULL on
+ * failure); free releases a pointer alloc returned (stream: that of the
+ * entry point releasing it, NULL from bo_cpr_destroy, which synchronises the
+ * device first).  ctx is passed through.  The functions may be called from
+ * bo_cpr_setup, bo_cpr_update, bo_fgmres_solve, bo_cpr_attach_nn,
+ * bo_cpr_collect_pairs and bo_cpr_destroy of the handle, on the calling
+ * thread.  Library-wide scratch (a few small grow-only buffers per host
+ * thread) and pinned host staging buffers are not taken from it. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx, void *stream);
+    void (*free)(void *ptr, void *ctx, void *stream);
+    void *ctx;
+} bo_allocator;
+
 /* [host] grid of the matrix: the F stage tiles and the level-0 colours use it.
  * With nbrows == nx*ny*nz A's pattern must be the 7-point stencil of the grid.
  * Otherwise (the extended grid form) the first nx*ny*nz rows are the grid's
@@ -248,7 +265,9 @@ typedef struct { int32_t nx, ny, nz, dual; } bo_grid;
 /* Builds the CPR preconditioner of A (Section 3.2): quasi-IMPES weights and the
  * decoupled pressure block, the AMG hierarchy on it, and the F-stage factors.
  * Keeps a private copy of A's values in its own layout; A may be freed after
- * return.  Synchronises `stream` (the hierarchy sizes are decided on the host).
+ * return.  alloc [host, may be NULL: hipMalloc / hipFree] supplies the
+ * handle's device memory for its whole life (the struct is copied).
+ * Synchronises `stream` (the hierarchy sizes are decided on the host).
  * The F-stage factors are built on a second stream of the handle, forked from
  * `stream` and joined back before return, beside the AMG setup.
  * The general form, for a block pattern other than a grid's 7-point stencil,
@@ -259,7 +278,7 @@ typedef struct { int32_t nx, ny, nz, dual; } bo_grid;
  * tile: the tile's fracture cells, their matrix cells, and the remaining rows
  * as one block-Jacobi class of their own. */
 bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
-                       bo_cpr **out, void *stream);
+                       const bo_allocator *alloc, bo_cpr **out, void *stream);
 /* Rebuilds pc for new values of a matrix with the same grid, pattern and
  * options (a new Newton iterate): decoupling, AMG hierarchy and F-stage
  * factors are recomputed from scratch; device memory of pc is reused when

@@ -80,6 +80,14 @@ class BoCprOpts(C.Structure):
                 ("npr", C.c_int32), ("sell_rows", C.c_int32), ("condense", C.c_int32)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class BoAllocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
 class BoGrid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dual", C.c_int32)]
 
@@ -120,7 +128,8 @@ def lib():
     L.bo_bsr_spmv.argtypes = [C.POINTER(BoBsr), C.c_double, vp, C.c_double, vp, vp]
     L.bo_cpr_default_opts.argtypes = [C.POINTER(BoCprOpts)]
     L.bo_cpr_default_opts.restype = None
-    L.bo_cpr_setup.argtypes = [C.POINTER(BoBsr), C.POINTER(BoGrid), C.POINTER(BoCprOpts), C.POINTER(vp), vp]
+    L.bo_cpr_setup.argtypes = [C.POINTER(BoBsr), C.POINTER(BoGrid), C.POINTER(BoCprOpts), C.POINTER(BoAllocator),
+                               C.POINTER(vp), vp]
     L.bo_cpr_update.argtypes = [vp, C.POINTER(BoBsr), vp]
     L.bo_cpr_destroy.argtypes = [vp]
     L.bo_cpr_destroy.restype = None
@@ -295,11 +304,13 @@ class Cpr:
         self.h = C.c_void_p(h)
         self.n = n
         self.A = None
+        self.allocator = None
 
     def close(self):
         if self.h:
             lib().bo_cpr_destroy(self.h)
             self.h = None
+        self.allocator = None
 
     def __del__(self):
         try:
@@ -308,17 +319,25 @@ class Cpr:
             pass
 
 
-def bo_cpr_setup(A: DeviceBsr, grid, opts: Optional[BoCprOpts] = None, stream=None) -> Cpr:
+def bo_cpr_setup(A: DeviceBsr, grid, opts: Optional[BoCprOpts] = None, stream=None, allocator=None) -> Cpr:
     """grid: (nx, ny, nz) or (nx, ny, nz, dual), or None for the general form
-    (see include/bo.h)."""
+    (see include/bo.h).  allocator: None (the library's hipMalloc) or a pair
+    of callables (alloc(nbytes, stream) -> device address, free(address,
+    stream)) that supply the handle's device memory for its whole life."""
     o = opts if opts is not None else bo_cpr_default_opts()
     g = BoGrid(*grid) if grid is not None else None
+    al = None
+    if allocator is not None:
+        fa, ff = allocator
+        al = BoAllocator(ALLOC_FN(lambda nbytes, ctx, st: fa(int(nbytes), st)),
+                         FREE_FN(lambda ptr, ctx, st: ff(ptr, st)), None)
     h = C.c_void_p()
     s = A.s
-    _check(lib().bo_cpr_setup(C.byref(s), C.byref(g) if g is not None else None, C.byref(o), C.byref(h),
-                              _stream(stream)))
+    _check(lib().bo_cpr_setup(C.byref(s), C.byref(g) if g is not None else None, C.byref(o),
+                              C.byref(al) if al is not None else None, C.byref(h), _stream(stream)))
     pc = Cpr(h.value, s.nbrows)
     pc.A = A   # the matrix of the last setup or update (bo_fgmres_solve takes it)
+    pc.allocator = al   # the callbacks live as long as the handle
     return pc
 
 

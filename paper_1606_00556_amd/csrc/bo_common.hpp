@@ -27,24 +27,54 @@ bo_status fail(bo_status st, const std::string &msg);
     } while (0)
 
 // ---- device memory ----------------------------------------------------------
-// Owned device buffer (freed in the destructor).
+// The caller's allocator of the handle an entry point is working on (set for
+// the duration of that entry point by AllocScope; NULL: hipMalloc / hipFree),
+// and the stream of that entry point.
+extern thread_local const bo_allocator *t_alloc;
+extern thread_local void *t_alloc_stream;
+struct AllocScope {
+    const bo_allocator *prev_a;
+    void *prev_s;
+    AllocScope(const bo_allocator *a, void *stream) : prev_a(t_alloc), prev_s(t_alloc_stream) {
+        t_alloc = a;
+        t_alloc_stream = stream;
+    }
+    ~AllocScope() {
+        t_alloc = prev_a;
+        t_alloc_stream = prev_s;
+    }
+};
+
+// Owned device buffer (freed in the destructor).  Memory comes from the
+// allocator in scope when it is allocated and goes back to the same one.
 template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
+    void (*ufree)(void *, void *, void *) = nullptr;  // caller's free, or NULL for hipFree
+    void *uctx = nullptr;
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n), ufree(o.ufree), uctx(o.uctx) { o.p = nullptr; o.n = 0; }
     DBuf &operator=(DBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; ufree = o.ufree; uctx = o.uctx;
+            o.p = nullptr; o.n = 0;
+        }
         return *this;
     }
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (ufree) ufree(p, uctx, t_alloc_stream);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
+        ufree = nullptr;
+        uctx = nullptr;
     }
     // Grows only: a buffer that has to grow again (a rebuild for a system
     // with larger coarse levels) takes a quarter more than asked, so that a
@@ -56,6 +86,15 @@ struct DBuf {
         release();
         if (regrow) count = std::max(count, count + count / 4);
         size_t bytes = (count ? count : 1) * sizeof(T);
+        if (t_alloc && t_alloc->alloc) {
+            p = (T *)t_alloc->alloc(bytes, t_alloc->ctx, t_alloc_stream);
+            if (!p) return fail(BO_ERR_ALLOC, "the caller's allocator returned NULL for " + std::to_string(bytes) +
+                                                  " bytes");
+            ufree = t_alloc->free;
+            uctx = t_alloc->ctx;
+            n = count;
+            return BO_OK;
+        }
         hipError_t e = hipMalloc((void **)&p, bytes);
         if (e != hipSuccess) {
             p = nullptr;

@@ -78,6 +78,11 @@ struct Condensed;                 // exact elimination of dual-porosity matrix c
 }  // namespace bo
 
 struct bo_cpr {
+    // the caller's allocator of this handle's device memory (copied at
+    // setup; has_alloc false: hipMalloc / hipFree)
+    bool has_alloc = false;
+    bo_allocator alloc{};
+    const bo_allocator *allocator() const { return has_alloc ? &alloc : nullptr; }
     bool broken = false;          // a failed bo_cpr_update leaves the handle unusable
     // condensed dual-porosity form: the matrix cells eliminated exactly, the
     // CPR of the reduced system in cond->inner (every other member unused)

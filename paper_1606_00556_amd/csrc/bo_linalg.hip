@@ -19,6 +19,8 @@
 namespace bo {
 
 static thread_local std::string g_err = "no error";
+thread_local const bo_allocator *t_alloc = nullptr;
+thread_local void *t_alloc_stream = nullptr;
 
 void set_error(const std::string &msg) { g_err = msg; }
 bo_status fail(bo_status st, const std::string &msg) {

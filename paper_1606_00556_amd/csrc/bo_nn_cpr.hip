@@ -320,6 +320,7 @@ extern "C" bo_status bo_cpr_attach_nn(bo_cpr *pc, bo_nn *nn, const double *logk,
         return BO_OK;
     }
     if (!logk) return fail(BO_ERR_INVALID_ARG, "bo_cpr_attach_nn: logk is NULL");
+    AllocScope scope(pc->allocator(), stream);
     if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_attach_nn: the handle has no pressure stage");
     if (pc->general || pc->cond) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_attach_nn: the network needs the grid form");
     hipStream_t s = (hipStream_t)stream;
@@ -344,6 +345,7 @@ extern "C" bo_status bo_cpr_collect_pairs(bo_cpr *pc, const double *b, int32_t n
     if (ncalls < 1 || !(rtol_inner > 0.0)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: bad arguments");
     if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: the handle has no pressure stage");
     if (pc->general || pc->cond) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_collect_pairs: pairs need the grid form");
+    AllocScope scope(pc->allocator(), stream);
     hipStream_t s = (hipStream_t)stream;
     long long n = pc->n;
     *got = 0;

@@ -311,7 +311,7 @@ bo_status bo::cpr_check(int32_t nbrows, const bo_grid *grid, const bo_cpr_opts *
 }
 
 extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
-                                  bo_cpr **out, void *stream) {
+                                  const bo_allocator *alloc, bo_cpr **out, void *stream) {
     if (!out) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: out is NULL");
     *out = nullptr;
     if (!A || !opts || !A->rowptr || !A->colind || !A->val)
@@ -325,13 +325,20 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
     } else {
         BO_TRY(cpr_check(A->nbrows, grid, opts));
     }
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: an allocator needs both alloc and free");
     bo_cpr *pc = new (std::nothrow) bo_cpr();
     if (!pc) return fail(BO_ERR_ALLOC, "bo_cpr_setup: out of host memory");
+    if (alloc) {
+        pc->has_alloc = true;
+        pc->alloc = *alloc;
+    }
+    AllocScope scope(pc->allocator(), stream);
     bo_status st = opts->condense ? cond_setup(pc, A, grid, opts, (hipStream_t)stream)
                                    : cpr_setup_impl(A, grid, opts, pc, (hipStream_t)stream);
     if (st != BO_OK) {
         (void)hipStreamSynchronize((hipStream_t)stream);
-        delete pc;
+        bo_cpr_destroy(pc);
         return st;
     }
     *out = pc;
@@ -343,6 +350,7 @@ extern "C" bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream) {
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: NULL argument");
     if (A->nbrows != pc->n) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: matrix size differs from the setup");
     if (A->nnzb != pc->nnzb) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: block count differs from the setup");
+    AllocScope scope(pc->allocator(), stream);
     bo_grid g{pc->g.nx, pc->g.ny, pc->g.nz, pc->ncell > pc->g.n() ? 1 : 0};
     bo_cpr_opts o = pc->o;
     bo_status st = pc->cond ? cond_setup(pc, A, &g, &o, (hipStream_t)stream)
@@ -360,6 +368,7 @@ extern "C" bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream) {
 extern "C" void bo_cpr_destroy(bo_cpr *pc) {
     if (!pc) return;
     (void)hipDeviceSynchronize();
+    AllocScope scope(pc->allocator(), nullptr);
     cond_destroy(pc);
     for (hipEvent_t &e : pc->ev)
         if (e) (void)hipEventDestroy(e);
@@ -747,6 +756,7 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *
     if (opts->m < 1 || opts->m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || opts->orth < 0 ||
         opts->orth > 2 || (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1))
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
+    AllocScope scope(pc->allocator(), stream);
     if (pc->cond) return cond_solve(pc, A, b, x, opts, stats, (hipStream_t)stream);
     return fgmres_core(pc, A, b, x, opts, stats, (hipStream_t)stream);
 }

@@ -507,3 +507,45 @@ def test_arnoldi_breakdown_is_reported(B, O, orth):
     b2 = to_dev(np.array([1.0, 2.0, 3.0, -1.0, -2.0, -3.0]))
     info = B.bo_fgmres_solve(pc, A, b2, x, B.bo_fgmres_default_opts(orth=orth))
     assert info["converged"] and info["iterations"] == 1
+
+
+def test_caller_allocator_serves_the_handle(B, O):
+    """bo_cpr_setup with a caller allocator (here torch's caching allocator):
+    every device buffer of the handle -- hierarchy, factors, operator copies,
+    the Krylov basis allocated by the first solve, the condensed form's
+    reduced system and inner handle -- comes from it and goes back to it
+    by bo_cpr_destroy; results equal those of a handle on hipMalloc bit for
+    bit."""
+    import torch
+    live = {}
+
+    def alloc(nbytes, stream):
+        t = torch.empty(max(nbytes, 1), dtype=torch.uint8, device="cuda")
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def free(ptr, stream):
+        live.pop(ptr)
+
+    from tests.test_gpu_condensed import rate_case
+    for case, grid, opts in ((ragged_case(), None, None),
+                             (rate_case(), "dual", dict(condense=1, fpf=1, smoother=B.BO_SMOOTH_L1))):
+        P, rp, ci, val, b = oracle_system(O, case)
+        A = device_bsr(B, rp, ci, val)
+        g = (case.nx, case.ny, case.nz, 1) if grid == "dual" else (case.nx, case.ny, case.nz)
+        o = B.bo_cpr_default_opts(**(opts or {}))
+        ref = B.bo_cpr_setup(A, g, o)
+        pc = B.bo_cpr_setup(A, g, o, allocator=(alloc, free))
+        assert len(live) > 0
+        n_setup = len(live)
+        xs = []
+        for h in (ref, pc):
+            x = torch.zeros(3 * P.rows, dtype=torch.float64, device="cuda")
+            info = B.bo_fgmres_solve(h, A, to_dev(b), x)
+            assert info["converged"]
+            xs.append(to_host(x))
+        assert np.array_equal(xs[0], xs[1])
+        assert len(live) > n_setup          # the Krylov basis came from the caller too
+        B.bo_cpr_update(pc, A)
+        pc.close()
+        assert len(live) == 0
