@@ -220,15 +220,47 @@ __global__ void k_sell_fill(int n, const int32_t *__restrict__ rp, const int32_t
             sci[b] = ci[e0 + k];
             for (int z = 0; z < 9; z++) sv[((size_t)(k0 + k) * 9 + z) * 64 + lane] = v[9 * (size_t)(e0 + k) + z];
         } else {
-            sci[b] = -1;
+            // padding past the row's end: a zero block on the row's own column
+            // (its product adds +0 after the row's blocks, so the sum is
+            // unchanged, and the x load stays in bounds)
+            sci[b] = r;
+            for (int z = 0; z < 9; z++) sv[((size_t)(k0 + k) * 9 + z) * 64 + lane] = 0.0;
         }
+    }
+}
+
+// One row of the sliced layout, W blocks: every index and value load of the
+// row is issued before the first product (no load waits on a branch), then
+// the x gathers and the sums in block order.
+template <int W>
+__device__ __forceinline__ void sell_row(const int32_t *__restrict__ sci, const double *__restrict__ sv, int k0,
+                                         int lane, const double *__restrict__ x, double &s0, double &s1,
+                                         double &s2) {
+    int c[W];
+#pragma unroll
+    for (int k = 0; k < W; k++) c[k] = sci[(size_t)(k0 + k) * 64 + lane];
+    double e[W][9];
+#pragma unroll
+    for (int k = 0; k < W; k++)
+#pragma unroll
+        for (int z = 0; z < 9; z++) e[k][z] = __builtin_nontemporal_load(sv + ((size_t)(k0 + k) * 9 + z) * 64 + lane);
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+        const double *xj = x + 3 * (size_t)c[k];
+        double x0 = xj[0], x1 = xj[1], x2 = xj[2];
+        s0 = s0 + e[k][0] * x0; s0 = s0 + e[k][1] * x1; s0 = s0 + e[k][2] * x2;
+        s1 = s1 + e[k][3] * x0; s1 = s1 + e[k][4] * x1; s1 = s1 + e[k][5] * x2;
+        s2 = s2 + e[k][6] * x0; s2 = s2 + e[k][7] * x1; s2 = s2 + e[k][8] * x2;
     }
 }
 
 // y = alpha A x + beta y on the sliced layout: the blocks of a row in their
 // BSR order and each block's entries in order, as k_bsr_spmv; the 64 lanes of
 // a wavefront read each of a block column's 9 value arrays as one 512 B line
-// pair (non-temporal: read once per launch).
+// pair (non-temporal: read once per launch).  A wavefront is one slice, so the
+// slice width selects one path for all its lanes: widths 7 and 8 (the 7-point
+// stencil, and a row with a well block) unrolled, others in a loop.  Padding
+// blocks are zero blocks on the row's own column and add +0.
 __global__ void __launch_bounds__(kBlock) k_sell_spmv(int n, const int32_t *__restrict__ soff,
                                                       const int32_t *__restrict__ sci,
                                                       const double *__restrict__ sv, double alpha,
@@ -239,17 +271,22 @@ __global__ void __launch_bounds__(kBlock) k_sell_spmv(int n, const int32_t *__re
     int S = r >> 6, lane = r & 63;
     int k0 = soff[S], K = soff[S + 1] - k0;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int k = 0; k < K; k++) {
-        int c = sci[(size_t)(k0 + k) * 64 + lane];
-        if (c < 0) break;  // the rest of the row is padding
-        const double *blk = sv + (size_t)(k0 + k) * 9 * 64 + lane;
-        double e[9];
+    if (K == 7) {
+        sell_row<7>(sci, sv, k0, lane, x, s0, s1, s2);
+    } else if (K == 8) {
+        sell_row<8>(sci, sv, k0, lane, x, s0, s1, s2);
+    } else {
+        for (int k = 0; k < K; k++) {
+            int c = sci[(size_t)(k0 + k) * 64 + lane];
+            const double *blk = sv + (size_t)(k0 + k) * 9 * 64 + lane;
+            double e[9];
 #pragma unroll
-        for (int z = 0; z < 9; z++) e[z] = __builtin_nontemporal_load(blk + z * 64);
-        double x0 = x[3 * (size_t)c], x1 = x[3 * (size_t)c + 1], x2 = x[3 * (size_t)c + 2];
-        s0 = s0 + e[0] * x0; s0 = s0 + e[1] * x1; s0 = s0 + e[2] * x2;
-        s1 = s1 + e[3] * x0; s1 = s1 + e[4] * x1; s1 = s1 + e[5] * x2;
-        s2 = s2 + e[6] * x0; s2 = s2 + e[7] * x1; s2 = s2 + e[8] * x2;
+            for (int z = 0; z < 9; z++) e[z] = __builtin_nontemporal_load(blk + z * 64);
+            double x0 = x[3 * (size_t)c], x1 = x[3 * (size_t)c + 1], x2 = x[3 * (size_t)c + 2];
+            s0 = s0 + e[0] * x0; s0 = s0 + e[1] * x1; s0 = s0 + e[2] * x2;
+            s1 = s1 + e[3] * x0; s1 = s1 + e[4] * x1; s1 = s1 + e[5] * x2;
+            s2 = s2 + e[6] * x0; s2 = s2 + e[7] * x1; s2 = s2 + e[8] * x2;
+        }
     }
     double *yi = y + 3 * (size_t)r;
     double t0 = beta == 0.0 ? 0.0 : beta * yi[0];
