@@ -2,34 +2,41 @@
 // zero-padded 3x3x3 convolutions, channels 2 -> 16 -> 16 -> 16 -> 1, biases,
 // ReLU after the first three) trained on pairs of pressure residual and the
 // error one AMG V-cycle leaves.  Forward and backward passes run on the
-// matrix cores: BF16 operands, FP32 accumulation
-// (v_mfma_f32_16x16x16_bf16).
+// matrix cores: BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16,
+// lane l holding A[l % 16][8 (l / 16) + j], B[8 (l / 16) + j][l % 16] for
+// j < 8, and receiving C[4 (l / 16) + j][l % 16] for j < 4).
 //
 // Convolution as an implicit GEMM.  A workgroup owns an output tile of
 // 16 (x) by 4 (y) by 4 (z) voxels = 16 rows of 16 voxels; its four wavefronts
 // take four rows each.  The input halo (18 x 6 x 6 voxels, channel-last BF16)
 // and the layer's weights are staged in LDS.  For one row and one tap the
 // product is D[n][i] = sum_k W[t][n][k] X[i + off(t)][k] with n the output
-// channel, i the voxel of the row and k the input channel: one 16x16x16 MFMA
-// with the weights as the A operand and the shifted row as the B operand, so
-// that lane l ends with output channels 4(l/16)..4(l/16)+3 of voxel l%16 and
-// stores them as one 8-byte write.  The first layer has 2 input channels
-// (padded to 4): there one MFMA covers four taps, lane group l/16 reading its
-// own tap.
+// channel, i the voxel of the row and k the input channel, with the weights
+// as the A operand and the shifted row as the B operand, so that lane l ends
+// with output channels 4(l/16)..4(l/16)+3 of voxel l%16 and stores them as one
+// 8-byte write.  One 16x16x32 MFMA covers two taps of 16 input channels (lane
+// groups 0-1 the first tap, 2-3 the second; 27 taps padded to 28 with a zero
+// one): 14 per row.  The first layer has 2 input channels (padded to 4): one
+// MFMA covers eight taps, each lane group two of them (27 taps padded to 32).
 //
 // Backward: the input gradient of a layer is the same convolution with the
 // kernel flipped and transposed (dX[u][c] = sum_t sum_o dZ[u - off(t)][o]
 // W[t][c][o]), masked by the ReLU of the layer below; the weight gradient
 // dW[t][c][o] = sum_v X[v + off(t)][c] dZ[v][o] is an MFMA reduction over the
-// voxels of each tile, combined across workgroups in a fixed order.
+// voxels of each tile (32 voxels, two rows, per MFMA), combined across
+// workgroups in a fixed order.
 #include "bo_nn.hpp"
 #include "bo_cpr.hpp"
 
 namespace bo {
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// eight BF16 values (16 bytes) as an MFMA operand
+__device__ __forceinline__ v8bf bf8(uint4 u) { return __builtin_bit_cast(v8bf, u); }
+__device__ __forceinline__ v8bf lds8(const uint16_t *p) { return bf8(*(const uint4 *)p); }
 
 constexpr int TX = 16, TY = 4, TZ = 4;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
@@ -85,7 +92,7 @@ __device__ __forceinline__ void load_halo(const uint16_t *__restrict__ act, cons
 __device__ __forceinline__ int halo_index(int z, int y, int x) { return (z * HY + y) * HX + x; }
 
 // Convolution of a CIN-channel input to 16 output channels.  W: [taps][16][CIN]
-// BF16 (taps = 27, or 28 with a zero last tap when CIN = 4).
+// BF16 (27 taps and zero ones up to 28 (CIN = 16) or 32 (CIN = 4)).
 //   MODE_ACT:  out = BF16(ReLU(acc + bias))              -> act_out [v][16]
 //   MODE_OUT:  y = acc[channel 0] + bias[0]              -> y_out [v] (FP32)
 //   MODE_GRAD: out = BF16(acc) where mask[v][n] > 0, else 0 -> act_out [v][16]
@@ -94,7 +101,7 @@ __global__ void __launch_bounds__(256) k_nn_conv(Vol V, const uint16_t *__restri
                                                  const uint16_t *__restrict__ W, const float *__restrict__ bias,
                                                  const uint16_t *__restrict__ mask, uint16_t *__restrict__ act_out,
                                                  float *__restrict__ y_out) {
-    constexpr int NT = CIN == 4 ? 28 : 27;
+    constexpr int NT = CIN == 4 ? 32 : 28;
     __shared__ __align__(16) uint16_t xs[HV * CIN];
     __shared__ __align__(16) uint16_t ws[NT * 16 * CIN];
     const TileXY T = tile_of(V, blockIdx.x);
@@ -112,22 +119,33 @@ __global__ void __launch_bounds__(256) k_nn_conv(Vol V, const uint16_t *__restri
         const int ry = r % TY, rz = r / TY;
         v4f acc = {0.f, 0.f, 0.f, 0.f};
         if (CIN == 16) {
-#pragma unroll 3
-            for (int t = 0; t < 27; t++) {
-                const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                v4s a = *(const v4s *)(ws + (t * 16 + i) * 16 + 4 * g);
-                v4s b = *(const v4s *)(xs + halo_index(rz + 1 + dz, ry + 1 + dy, i + 1 + dx) * 16 + 4 * g);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < 7; q++) {
-                const int t = 4 * q + g;               // this lane group's tap
+            // k = 8g + j: tap 2 tp + g / 2, input channel 8 (g % 2) + j
+            const int ko = 8 * (g & 1);
+#pragma unroll 2
+            for (int tp = 0; tp < 14; tp++) {
+                const int t = 2 * tp + (g >> 1);
                 const int tt = t < 27 ? t : 26;        // tap 27 has zero weights
                 const int dz = tt / 9 - 1, dy = (tt / 3) % 3 - 1, dx = tt % 3 - 1;
-                v4s a = *(const v4s *)(ws + (t * 16 + i) * 4);
-                v4s b = *(const v4s *)(xs + halo_index(rz + 1 + dz, ry + 1 + dy, i + 1 + dx) * 4);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+                v8bf a = lds8(ws + (t * 16 + i) * 16 + ko);
+                v8bf b = lds8(xs + halo_index(rz + 1 + dz, ry + 1 + dy, i + 1 + dx) * 16 + ko);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+            }
+        } else {
+            // k = 8g + 4h + j: tap 8q + 2g + h, input channel j
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                uint2 wa[2], xb[2];
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int t = 8 * q + 2 * g + h;
+                    const int tt = t < 27 ? t : 26;    // taps 27..31 have zero weights
+                    const int dz = tt / 9 - 1, dy = (tt / 3) % 3 - 1, dx = tt % 3 - 1;
+                    wa[h] = *(const uint2 *)(ws + (t * 16 + i) * 4);
+                    xb[h] = *(const uint2 *)(xs + halo_index(rz + 1 + dz, ry + 1 + dy, i + 1 + dx) * 4);
+                }
+                v8bf a = bf8(make_uint4(wa[0].x, wa[0].y, wa[1].x, wa[1].y));
+                v8bf b = bf8(make_uint4(xb[0].x, xb[0].y, xb[1].x, xb[1].y));
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
             }
         }
         const int x = T.x0 + i, y = T.y0 + ry, z = T.z0 + rz;
@@ -179,26 +197,35 @@ __global__ void __launch_bounds__(256) k_nn_wgrad(Vol V, long long ntiles, const
             *(uint2 *)(ds + tv * COUT + 4 * c4) = val;
         }
         __syncthreads();
-        for (int rr = 0; rr < 4; rr++) {
-            const int r = wave * 4 + rr;
+        // two rows of 16 voxels per MFMA: k = 8g + j is voxel 8 (g % 2) + j of
+        // row r0 + g / 2
+        for (int rp = 0; rp < 2; rp++) {
+            const int r = wave * 4 + 2 * rp + (g >> 1);
             const int ry = r % TY, rz = r / TY;
-            // A[o = c][k = voxel 4g+j of the row]
-            v4s a;
-            for (int j = 0; j < 4; j++) {
-                uint16_t h = c < COUT ? ds[(r * TX + 4 * g + j) * COUT + c] : (uint16_t)0;
-                a[j] = (short)h;
+            const int vo = 8 * (g & 1);
+            // A[o = c][k]
+            uint16_t ha[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                uint16_t h = c < COUT ? ds[(r * TX + vo + j) * COUT + c] : (uint16_t)0;
+                ha[j] = h;
                 db += from_bf16(h);
             }
+            const v8bf a = bf8(make_uint4(ha[0] | ((uint32_t)ha[1] << 16), ha[2] | ((uint32_t)ha[3] << 16),
+                                          ha[4] | ((uint32_t)ha[5] << 16), ha[6] | ((uint32_t)ha[7] << 16)));
             // fully unrolled: the 27 accumulators stay in registers
 #pragma unroll
             for (int t = 0; t < 27; t++) {
                 const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                v4s b;
-                for (int j = 0; j < 4; j++) {
-                    int hv = halo_index(rz + 1 + dz, ry + 1 + dy, 4 * g + j + 1 + dx);
-                    b[j] = c < CIN ? (short)xs[hv * CIN + c] : (short)0;
+                uint16_t hb[8];
+#pragma unroll
+                for (int j = 0; j < 8; j++) {
+                    int hv = halo_index(rz + 1 + dz, ry + 1 + dy, vo + j + 1 + dx);
+                    hb[j] = c < CIN ? xs[hv * CIN + c] : (uint16_t)0;
                 }
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+                const v8bf b = bf8(make_uint4(hb[0] | ((uint32_t)hb[1] << 16), hb[2] | ((uint32_t)hb[3] << 16),
+                                              hb[4] | ((uint32_t)hb[5] << 16), hb[6] | ((uint32_t)hb[7] << 16)));
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
             }
         }
     }
@@ -315,13 +342,13 @@ int layer_off(int l) {
 bo_status nn_pack(bo_nn *nn, hipStream_t s) {
     for (int l = 0; l < kNnLayers; l++) {
         int ci = kNnChan[l], co = kNnChan[l + 1];
-        int kf = l == 0 ? 4 : 16, ntf = l == 0 ? 28 : 27;
+        int kf = l == 0 ? 4 : 16, ntf = l == 0 ? 32 : 28;
         BO_TRY(nn->wf[l].alloc((size_t)ntf * 16 * kf));
         uint16_t *wb = nullptr;
-        int kb = 16, ntb = 27;
+        int kb = 16, ntb = 28;
         if (l > 0) {
             kb = l == kNnLayers - 1 ? 4 : 16;
-            ntb = kb == 4 ? 28 : 27;
+            ntb = kb == 4 ? 32 : 28;
             BO_TRY(nn->wb[l].alloc((size_t)ntb * 16 * kb));
             wb = nn->wb[l].p;
         }
