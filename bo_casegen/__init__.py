@@ -260,14 +260,16 @@ def _sequence_state(base, nx, ny, nz, dx, dy, wells, t):
     return x
 
 
-def make_case(cfg: int, system: int = 1, noise: str = "smooth") -> Case:
+def make_case(cfg: int, system: int = 1, noise: str = "smooth", field: int = 0) -> Case:
     """The synthetic Jacobian-producing state of workload ``cfg`` (0, 1 or 2).
 
     For cfg 0 the Jacobian is taken at the first Newton iterate
     (x_new == x_old, dt = 1 day).  For cfg 1 and 2, ``system`` k = 1..10 takes
     x_old = state(3(k-1) days) and x_new = state(3k days) with dt = 3 days.
     ``noise``: "smooth" (the correlated state noise) or "iid" (independent
-    per cell; the case name then ends in "/iid").
+    per cell; the case name then ends in "/iid").  cfg 3 is the learned
+    stage's training set: the 200x200x50 recipe of cfg 2 on the fields of
+    seeds 1606300 + ``field`` (cfg 2's own systems are its test set).
     """
     dx, dy, dz, top = 50.0, 50.0, 10.0, 8000.0
     if cfg == 0:
@@ -280,10 +282,10 @@ def make_case(cfg: int, system: int = 1, noise: str = "smooth") -> Case:
         x = _noisy_state(seed, nx, ny, nz, noise=noise)
         return Case("cfg0" + ("/iid" if noise == "iid" else ""), nx, ny, nz, dx, dy, dz, top, kx, kx.copy(), 0.1 * kx,
                     _porosity(seed, n), x, x.copy(), 1.0, wells, dict(FLUID))
-    if cfg in (1, 2):
+    if cfg in (1, 2, 3):
         if not 1 <= system <= N_SYSTEMS:
             raise ValueError("system must be in 1..10")
-        seed = base_seed(cfg)
+        seed = base_seed(cfg) + (field if cfg == 3 else 0)
         if cfg == 1:
             nx, ny, nz = 100, 100, 50
             n = nx * ny * nz
@@ -302,7 +304,8 @@ def make_case(cfg: int, system: int = 1, noise: str = "smooth") -> Case:
         base = _noisy_state(seed, nx, ny, nz, noise=noise)
         x_old = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * (system - 1))
         x_new = _sequence_state(base, nx, ny, nz, dx, dy, wells, 3.0 * system)
-        return Case(f"cfg{cfg}.{system}" + ("/iid" if noise == "iid" else ""), nx, ny, nz, dx, dy, dz, top, kx,
+        name = f"cfg{cfg}.{system}" if cfg != 3 else f"cfg3/f{field}.{system}"
+        return Case(name + ("/iid" if noise == "iid" else ""), nx, ny, nz, dx, dy, dz, top, kx,
                     kx.copy(), kz,
                     _porosity(seed, n), x_old, x_new, 3.0, wells, dict(FLUID))
     raise ValueError(f"unknown workload {cfg}")

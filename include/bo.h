@@ -382,16 +382,30 @@ bo_status bo_nn_forward(bo_nn *nn, const float *in, float *out, int32_t nb, int3
  * and target ([nb][nz][ny][nx] FP32); loss [host, may be NULL] receives the
  * loss.  Synchronous.  Fails after a forward pass made inside CPR. */
 bo_status bo_nn_backward(bo_nn *nn, const float *target, double *loss, void *stream);
+/* Gradients of the A_pp-weighted error instead: the mean, over the voxels
+ * whose six neighbours lie in the volume, of (A (y - target))^2 with A the
+ * 7-point pressure stencil given per voxel in coef ([7][nb][nz][ny][nx] FP32,
+ * slots -z, -y, -x, self, +x, +y, +z, as bo_cpr_pressure_stencil writes it):
+ * the pressure residual the correction y would leave if the error were
+ * target, the quantity the judge of the pressure stage measures.  Fails if
+ * a side of the volume is below 3.  Synchronous. */
+bo_status bo_nn_backward_weighted(bo_nn *nn, const float *coef, const float *target, double *loss, void *stream);
 /* Adam (beta 0.9 / 0.999, eps 1e-8, bias-corrected) with learning rate lr on
- * the gradients of the last bo_nn_backward. */
+ * the gradients of the last bo_nn_backward or bo_nn_backward_weighted. */
 bo_status bo_nn_adam_step(bo_nn *nn, float lr, void *stream);
 
 /* Attaches nn (not owned; NULL detaches) to the pressure stage of pc; logk:
  * N FP64 values of ln k, standardised here.  With a network attached, each
  * pressure stage computes dp = V(r_p) and c = s N([r_p / s, z]) and uses
- * dp + c if ||r_p - A_pp (dp + c)|| < ||r_p - A_pp dp||, else dp
- * (bo_solve_stats.nn_used counts the kept corrections). */
+ * dp + alpha c with alpha = <u, A_pp c> / ||A_pp c||^2, u = r_p - A_pp dp
+ * (the multiple of c that minimises ||r_p - A_pp x||) when alpha > 0, else
+ * dp (bo_solve_stats.nn_used counts the kept corrections). */
 bo_status bo_cpr_attach_nn(bo_cpr *pc, bo_nn *nn, const double *logk, void *stream);
+/* [device] coef ([7][N] FP32): the decoupled level-0 pressure matrix A_pp of
+ * pc (plain grid form) in slot order -z, -y, -x, self, +x, +y, +z, zero where
+ * the neighbour is outside the grid: the stencil bo_nn_backward_weighted
+ * takes (cropped like the pairs). */
+bo_status bo_cpr_pressure_stencil(bo_cpr *pc, float *coef, void *stream);
 /* Training pairs from a solve of A x = b (A of the last setup/update): runs
  * FGMRES with pc for at most ncalls preconditioner applications, recording the
  * pressure-stage inputs r_p of the first ncalls of them in rp_out

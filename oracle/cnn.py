@@ -8,9 +8,11 @@ log-permeability of every cell to a pressure correction:
 with N four zero-padded "same" 3x3x3 convolutions, channels 2 -> 16 -> 16 ->
 16 -> 1, biases, and ReLU after the first three.  The correction is trained
 on pairs (r_p, e) with e = A_pp^{-1} r_p - V(r_p), the error that one AMG
-V-cycle leaves, by mean-squared error on e / s and Adam.  In CPR the
-corrected pressure V(r_p) + c is kept only when it lowers the pressure
-residual ||r_p - A_pp x||; otherwise the plain V-cycle result is used.
+V-cycle leaves, by mean-squared error on e / s (or by the A_pp-weighted
+error, the residual the correction would leave) and Adam.  In CPR the
+V-cycle result is corrected by the multiple of c that minimises the pressure
+residual ||r_p - A_pp x||, when that multiple is positive; otherwise the
+plain V-cycle result is used.
 
 Everything here is plain numpy: FP64 forward and backward, and a BF16
 emulation in which the weights, each layer's input and each backward operand
@@ -103,6 +105,11 @@ def backward(params, cache, Y, T, emulate_bf16: bool = False):
     """Gradients of mse(Y, T) with respect to every (W, b)."""
     M = np.asarray(Y).size
     dZ = 2.0 * (np.asarray(Y, dtype=np.float64) - np.asarray(T, dtype=np.float64)) / M
+    return _backprop(params, cache, dZ, emulate_bf16)
+
+
+def _backprop(params, cache, dZ, emulate_bf16: bool):
+    """Weight and bias gradients from the output gradient dZ (nz, ny, nx, 1)."""
     if emulate_bf16:
         dZ = dZ.astype(np.float32).astype(np.float64)
     grads = [None] * len(params)
@@ -121,6 +128,56 @@ def backward(params, cache, Y, T, emulate_bf16: bool = False):
             if l > 0:
                 dZ = conv_input_grad(dZ, W) * (cache[l - 1][1] > 0)
     return grads
+
+
+# 7-point stencil slots of a pressure matrix: (dz, dy, dx) of the coupled cell
+SLOTS = [(-1, 0, 0), (0, -1, 0), (0, 0, -1), (0, 0, 0), (0, 0, 1), (0, 1, 0), (1, 0, 0)]
+
+
+def stencil_apply(coef: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """(A y)_i = sum_s coef[s, i] y[i + off(s)] on a (nz, ny, nx) volume,
+    couplings that leave the volume dropped (coef: (7, nz, ny, nx))."""
+    Y = np.asarray(Y, dtype=np.float64)
+    out = np.zeros(Y.shape)
+    for s, (dz, dy, dx) in enumerate(SLOTS):
+        out += np.asarray(coef[s], dtype=np.float64) * _shifted(Y[..., None], dz, dy, dx)[..., 0]
+    return out
+
+
+def interior_mask(shape) -> np.ndarray:
+    """Voxels whose six neighbours all lie in the volume."""
+    m = np.zeros(shape, dtype=bool)
+    m[1:-1, 1:-1, 1:-1] = True
+    return m
+
+
+def weighted_loss(Y, coef, T) -> float:
+    """Mean over interior voxels of (A (y - t))^2: the error of the correction
+    measured by the pressure residual it would leave, on the voxels whose
+    stencil lies inside the volume."""
+    d = np.asarray(Y, dtype=np.float64).reshape(np.shape(T)) - np.asarray(T, dtype=np.float64)
+    m = interior_mask(np.shape(T))
+    R = stencil_apply(coef, d)[m]
+    return float(np.mean(R * R))
+
+
+def weighted_loss_grad(Y, coef, T) -> np.ndarray:
+    """d weighted_loss / d y = (2 / M) A^T (mask . A (y - t)), M interior voxels."""
+    shape = np.shape(T)
+    d = np.asarray(Y, dtype=np.float64).reshape(shape) - np.asarray(T, dtype=np.float64)
+    m = interior_mask(shape)
+    R = np.where(m, stencil_apply(coef, d), 0.0)
+    g = np.zeros(shape)
+    for s, (dz, dy, dx) in enumerate(SLOTS):
+        # (A^T R)_j gets coef[s, i] R_i from i = j - off(s)
+        g += _shifted((np.asarray(coef[s], dtype=np.float64) * R)[..., None], -dz, -dy, -dx)[..., 0]
+    return 2.0 * g / max(int(m.sum()), 1)
+
+
+def backward_weighted(params, cache, Y, coef, T, emulate_bf16: bool = False):
+    """Gradients of weighted_loss(Y, coef, T) with respect to every (W, b)."""
+    dY = weighted_loss_grad(Y, coef, T)[..., None]
+    return _backprop(params, cache, dY, emulate_bf16)
 
 
 class Adam:
@@ -160,7 +217,17 @@ def normalise_inputs(rp: np.ndarray, logk: np.ndarray, shape):
 
 
 def judge(App, rp, v, c):
-    """The V-cycle result v, corrected by c only if that lowers ||r_p - A_pp x||."""
-    r0 = np.linalg.norm(rp - App @ v)
-    r1 = np.linalg.norm(rp - App @ (v + c))
-    return (v + c, True) if r1 < r0 else (v, False)
+    """The V-cycle result v corrected by the multiple alpha c of the network's
+    correction that minimises ||r_p - A_pp (v + alpha c)||: alpha =
+    <u, A_pp c> / ||A_pp c||^2 with u = r_p - A_pp v.  The correction is kept
+    when alpha > 0 (the residual then falls by the factor sqrt(1 - cos^2) of
+    the angle between u and A_pp c); otherwise (alpha <= 0, or A_pp c = 0)
+    the plain V-cycle result is used.  Returns (x, alpha)."""
+    u = rp - App @ v
+    w = App @ c
+    q = float(w @ w)
+    p = float(u @ w)
+    if q > 0.0 and p > 0.0:
+        a = p / q
+        return v + a * c, a
+    return v, 0.0

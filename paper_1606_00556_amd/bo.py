@@ -34,7 +34,8 @@ EXPORTS = [
     "bo_cpr_level_copy", "bo_cpr_copy_weights", "bo_fgmres_default_opts", "bo_fgmres_solve",
     "bo_nn_create", "bo_nn_destroy", "bo_nn_num_params", "bo_nn_set_params", "bo_nn_get_params",
     "bo_nn_forward", "bo_nn_backward", "bo_nn_adam_step", "bo_cpr_attach_nn", "bo_cpr_collect_pairs",
-    "bo_jacobian_bsr_noalloc", "bo_jacobian_bsr_noalloc_max_rows",
+    "bo_jacobian_bsr_noalloc", "bo_jacobian_bsr_noalloc_max_rows", "bo_nn_backward_weighted",
+    "bo_cpr_pressure_stencil",
 ]
 
 
@@ -154,6 +155,8 @@ def lib():
     L.bo_nn_forward.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
     L.bo_nn_backward.argtypes = [vp, vp, C.POINTER(C.c_double), vp]
     L.bo_nn_adam_step.argtypes = [vp, C.c_float, vp]
+    L.bo_nn_backward_weighted.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
+    L.bo_cpr_pressure_stencil.argtypes = [vp, vp, vp]
     L.bo_cpr_attach_nn.argtypes = [vp, vp, vp, vp]
     L.bo_cpr_collect_pairs.argtypes = [vp, vp, C.c_int32, C.c_double, vp, vp, C.POINTER(C.c_int32), vp]
     for f in EXPORTS:
@@ -495,6 +498,13 @@ class Nn:
         _check(lib().bo_nn_backward(self.h, _ptr(target), C.byref(loss), _stream(stream)))
         return loss.value
 
+    def backward_weighted(self, coef, target, stream=None) -> float:
+        """coef: [7, nb, nz, ny, nx] float32 stencil; target: [nb, nz, ny, nx]."""
+        assert coef.is_contiguous() and target.is_contiguous() and coef.numel() == 7 * target.numel()
+        loss = C.c_double()
+        _check(lib().bo_nn_backward_weighted(self.h, _ptr(coef), _ptr(target), C.byref(loss), _stream(stream)))
+        return loss.value
+
     def adam_step(self, lr: float = 1e-3, stream=None):
         _check(lib().bo_nn_adam_step(self.h, C.c_float(lr), _stream(stream)))
 
@@ -502,6 +512,14 @@ class Nn:
 def bo_cpr_attach_nn(pc: "Cpr", nn: Optional[Nn], logk=None, stream=None):
     _check(lib().bo_cpr_attach_nn(pc.h, nn.h if nn is not None else None,
                                   _ptr(logk) if logk is not None else None, _stream(stream)))
+
+
+def bo_cpr_pressure_stencil(pc: "Cpr", stream=None):
+    """The level-0 pressure matrix as a [7, N] float32 device tensor."""
+    import torch
+    coef = torch.empty((7, pc.n), dtype=torch.float32, device="cuda")
+    _check(lib().bo_cpr_pressure_stencil(pc.h, _ptr(coef), _stream(stream)))
+    return coef
 
 
 def bo_cpr_collect_pairs(pc: "Cpr", b, ncalls: int = 4, rtol_inner: float = 1e-10, stream=None):

@@ -147,7 +147,8 @@ struct bo_cpr {
     bo::DBuf<float> nn_z;                 // standardised log-permeability
     bo::DBuf<double> nn_part, nn_mom, nn_dp;
     bo::DBuf<float> nn_dp32;
-    bo::DBuf<int32_t> nn_flag, nn_used;
+    bo::DBuf<int32_t> nn_used;
+    bo::DBuf<double> nn_alpha;            // the judge's multiple of the correction (0: not used)
     // pair collection: recorded pressure-stage inputs (caller's buffer)
     float *rec_out = nullptr;
     int rec_max = 0, rec_n = 0;

@@ -296,6 +296,58 @@ __global__ void k_nn_loss_final(int nparts, const double *__restrict__ lpart, do
     *loss = s * inv_m;
 }
 
+// A_pp-weighted loss: R = A (y - t) on the voxels whose six neighbours lie in
+// the volume (0 elsewhere), coef [7][voxels] in slot order (-z, -y, -x, self,
+// +x, +y, +z); partial sums of R^2 per block
+__global__ void __launch_bounds__(256) k_nn_wres(Vol V, const float *__restrict__ coef, const float *__restrict__ y,
+                                                 const float *__restrict__ tgt, float *__restrict__ R,
+                                                 double *__restrict__ lpart) {
+    __shared__ double red[256];
+    const long long nv = V.voxels();
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double sq = 0.0;
+    if (v < nv) {
+        const int x = (int)(v % V.nx), yy = (int)((v / V.nx) % V.ny), z = (int)((v / ((long long)V.nx * V.ny)) % V.nz);
+        float r = 0.f;
+        if (x > 0 && x < V.nx - 1 && yy > 0 && yy < V.ny - 1 && z > 0 && z < V.nz - 1) {
+            const long long sx = 1, sy = V.nx, sz = (long long)V.nx * V.ny;
+            const long long nb[7] = {v - sz, v - sy, v - sx, v, v + sx, v + sy, v + sz};
+            double acc = 0.0;
+            for (int q = 0; q < 7; q++)
+                acc += (double)coef[(size_t)q * nv + v] * (double)(y[nb[q]] - tgt[nb[q]]);
+            r = (float)acc;
+        }
+        R[v] = r;
+        sq = (double)r * r;
+    }
+    red[threadIdx.x] = sq;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+// output gradient of the weighted loss: dZ4 = BF16(scale (A^T R)) in a
+// 4-channel tensor, (A^T R)_j = sum over the cells i whose slot q couples to
+// j of coef[q][i] R_i
+__global__ void k_nn_wout(Vol V, const float *__restrict__ coef, const float *__restrict__ R, float scale,
+                          uint16_t *__restrict__ dz) {
+    const long long nv = V.voxels();
+    const long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    const int x = (int)(j % V.nx), yy = (int)((j / V.nx) % V.ny), z = (int)((j / ((long long)V.nx * V.ny)) % V.nz);
+    const long long sx = 1, sy = V.nx, sz = (long long)V.nx * V.ny;
+    // cell i = j - off(q): slot q of i points at j
+    const bool in[7] = {z < V.nz - 1, yy < V.ny - 1, x < V.nx - 1, true, x > 0, yy > 0, z > 0};
+    const long long src[7] = {j + sz, j + sy, j + sx, j, j - sx, j - sy, j - sz};
+    double g = 0.0;
+    for (int q = 0; q < 7; q++)
+        if (in[q]) g += (double)coef[(size_t)q * nv + src[q]] * (double)R[src[q]];
+    *(uint2 *)(dz + 4 * j) = make_uint2((uint32_t)to_bf16((float)(scale * g)), 0u);
+}
+
 __global__ void k_nn_adam(int n, float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
                           float *__restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -492,23 +544,13 @@ extern "C" bo_status bo_nn_forward(bo_nn *nn, const float *in, float *out, int32
     return BO_OK;
 }
 
-extern "C" bo_status bo_nn_backward(bo_nn *nn, const float *target, double *loss, void *stream) {
-    if (!nn || !target) return fail(BO_ERR_INVALID_ARG, "bo_nn_backward: NULL argument");
-    const Vol V = nn->vol;
-    long long nv = V.voxels();
-    if (nv <= 0 || nn->last_from_cpr)
-        return fail(BO_ERR_INVALID_ARG, "bo_nn_backward: the last forward pass was not a bo_nn_forward call");
-    hipStream_t s = (hipStream_t)stream;
-    BO_TRY(nn->dz4.alloc(4 * (size_t)nv));
-    BO_TRY(nn->dz.alloc(16 * (size_t)nv));
-    BO_TRY(nn->dzb.alloc(16 * (size_t)nv));
-    unsigned nlb = grid_for(nv);
-    BO_TRY(nn->lpart.alloc(nlb));
+namespace {
+// gradients of every layer from the output gradient in nn->dz4; the loss in
+// nn->loss is copied to *loss (may be NULL); synchronises the stream
+bo_status nn_backprop(bo_nn *nn, const Vol &V, double *loss, hipStream_t s) {
     long long nt = tiles_of(V);
     int wblocks = (int)std::min<long long>(nt, kNnWgradBlocks);
     BO_TRY(nn->part.alloc((size_t)wblocks * 4 * (27 * 256 + 16)));
-    k_nn_loss<<<nlb, 256, 0, s>>>(nv, nn->y.p, target, (float)(2.0 / (double)nv), nn->dz4.p, nn->lpart.p);
-    k_nn_loss_final<<<1, 64, 0, s>>>((int)nlb, nn->lpart.p, 1.0 / (double)nv, nn->loss.p);
     float *gw = nn->g.p;
     auto reduce = [&](int l) {
         int ci = kNnChan[l], co = kNnChan[l + 1];
@@ -538,6 +580,48 @@ extern "C" bo_status bo_nn_backward(bo_nn *nn, const float *target, double *loss
     if (loss) BO_HIP(hipMemcpyAsync(loss, nn->loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
     BO_HIP(hipStreamSynchronize(s));
     return BO_OK;
+}
+
+bo_status nn_backward_check(bo_nn *nn, const char *who) {
+    long long nv = nn->vol.voxels();
+    if (nv <= 0 || nn->last_from_cpr)
+        return fail(BO_ERR_INVALID_ARG, std::string(who) + ": the last forward pass was not a bo_nn_forward call");
+    BO_TRY(nn->dz4.alloc(4 * (size_t)nv));
+    BO_TRY(nn->dz.alloc(16 * (size_t)nv));
+    BO_TRY(nn->dzb.alloc(16 * (size_t)nv));
+    BO_TRY(nn->lpart.alloc(grid_for(nv)));
+    return BO_OK;
+}
+}  // namespace
+
+extern "C" bo_status bo_nn_backward(bo_nn *nn, const float *target, double *loss, void *stream) {
+    if (!nn || !target) return fail(BO_ERR_INVALID_ARG, "bo_nn_backward: NULL argument");
+    BO_TRY(nn_backward_check(nn, "bo_nn_backward"));
+    const Vol V = nn->vol;
+    long long nv = V.voxels();
+    hipStream_t s = (hipStream_t)stream;
+    unsigned nlb = grid_for(nv);
+    k_nn_loss<<<nlb, 256, 0, s>>>(nv, nn->y.p, target, (float)(2.0 / (double)nv), nn->dz4.p, nn->lpart.p);
+    k_nn_loss_final<<<1, 64, 0, s>>>((int)nlb, nn->lpart.p, 1.0 / (double)nv, nn->loss.p);
+    return nn_backprop(nn, V, loss, s);
+}
+
+extern "C" bo_status bo_nn_backward_weighted(bo_nn *nn, const float *coef, const float *target, double *loss,
+                                             void *stream) {
+    if (!nn || !coef || !target) return fail(BO_ERR_INVALID_ARG, "bo_nn_backward_weighted: NULL argument");
+    BO_TRY(nn_backward_check(nn, "bo_nn_backward_weighted"));
+    const Vol V = nn->vol;
+    long long nv = V.voxels();
+    long long interior = (long long)V.nb * std::max(V.nz - 2, 0) * std::max(V.ny - 2, 0) * std::max(V.nx - 2, 0);
+    if (interior <= 0)
+        return fail(BO_ERR_INVALID_ARG, "bo_nn_backward_weighted: the volume has no interior voxel (a side below 3)");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned nlb = grid_for(nv);
+    BO_TRY(nn->wres.alloc((size_t)nv));
+    k_nn_wres<<<nlb, 256, 0, s>>>(V, coef, nn->y.p, target, nn->wres.p, nn->lpart.p);
+    k_nn_loss_final<<<1, 64, 0, s>>>((int)nlb, nn->lpart.p, 1.0 / (double)interior, nn->loss.p);
+    k_nn_wout<<<nlb, kBlock, 0, s>>>(V, coef, nn->wres.p, (float)(2.0 / (double)interior), nn->dz4.p);
+    return nn_backprop(nn, V, loss, s);
 }
 
 extern "C" bo_status bo_nn_adam_step(bo_nn *nn, float lr, void *stream) {

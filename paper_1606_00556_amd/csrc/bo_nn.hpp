@@ -7,7 +7,7 @@ namespace bo {
 // a batch of nb volumes of nz x ny x nx voxels, channel-last tensors
 struct Vol {
     int nb = 0, nz = 0, ny = 0, nx = 0;
-    long long voxels() const { return (long long)nb * nz * ny * nx; }
+    __host__ __device__ long long voxels() const { return (long long)nb * nz * ny * nx; }
 };
 
 constexpr int kNnLayers = 4;
@@ -35,4 +35,5 @@ struct bo_nn {
     bo::DBuf<float> part;                         // weight-gradient partial sums
     bo::DBuf<double> lpart;                       // loss partial sums
     bo::DBuf<double> loss;                        // last loss (device)
+    bo::DBuf<float> wres;                         // weighted loss: the residual A (y - t) per voxel
 };

@@ -3,8 +3,9 @@
 //
 // Pressure stage with a network attached: dp = V(r_p) (one AMG V-cycle), then
 // c = s N([r_p / s, z]) with s = RMS(r_p) and z the standardised
-// log-permeability, and the judge keeps dp + c only if
-// ||r_p - A_pp (dp + c)|| < ||r_p - A_pp dp||; otherwise dp is used as it is.
+// log-permeability, and the judge uses dp + alpha c with alpha = <u, A_pp c>
+// / ||A_pp c||^2, u = r_p - A_pp dp (the multiple of c that minimises
+// ||r_p - A_pp x||) when alpha > 0; otherwise dp is used as it is.
 // Everything, the decision included, stays on the device: no host round trip
 // per application.
 //
@@ -94,33 +95,36 @@ __global__ void __launch_bounds__(256) k_judge(int nx, int ny, int nz, const T *
             ad += a * (double)dp[j];
             ay += a * (double)y[j];
         }
-        double r0 = (double)rp[i] - ad;
-        double r1 = r0 - s * ay;
-        q0 += r0 * r0;
-        q1 += r1 * r1;
+        double u = (double)rp[i] - ad;  // residual of the V-cycle result
+        double w = s * ay;              // A_pp c
+        q0 += u * w;
+        q1 += w * w;
     }
     q0 = block_sum256(q0, red);
     q1 = block_sum256(q1, red);
     if (threadIdx.x == 0) { part[2 * blockIdx.x] = q0; part[2 * blockIdx.x + 1] = q1; }
 }
 
-__global__ void k_judge_final(int np, const double *__restrict__ part, int32_t *__restrict__ flag,
+// alpha = <u, A c> / ||A c||^2 (the multiple of c that minimises the
+// pressure residual), kept when positive
+__global__ void k_judge_final(int np, const double *__restrict__ part, double *__restrict__ alpha,
                               int32_t *__restrict__ used) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double a = 0.0, b = 0.0;
-    for (int p = 0; p < np; p++) { a += part[2 * p]; b += part[2 * p + 1]; }
-    int keep = b < a;
-    *flag = keep;
-    if (keep) *used += 1;
+    double p = 0.0, q = 0.0;
+    for (int k = 0; k < np; k++) { p += part[2 * k]; q += part[2 * k + 1]; }
+    const double a = (q > 0.0 && p > 0.0) ? p / q : 0.0;
+    *alpha = a;
+    if (a > 0.0) *used += 1;
 }
 
-// out = dp + s y where the judge kept the correction, else dp
+// out = dp + alpha s y where the judge kept the correction, else dp
 template <typename T>
 __global__ void k_nn_apply(long long n, const T *__restrict__ dp, const float *__restrict__ y,
-                           const double *__restrict__ mom, const int32_t *__restrict__ flag, T *__restrict__ out) {
+                           const double *__restrict__ mom, const double *__restrict__ alpha, T *__restrict__ out) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (*flag) out[i] = dp[i] + (T)(sqrt(mom[1]) * (double)y[i]);
+    const double a = *alpha;
+    if (a > 0.0) out[i] = dp[i] + (T)(a * sqrt(mom[1]) * (double)y[i]);
     else out[i] = dp[i];
 }
 
@@ -189,7 +193,7 @@ bo_status nn_correct(bo_cpr *pc, const T *rp, const T *dp, const T **out, hipStr
     const bool fp32 = sizeof(T) == 4;
     BO_TRY(pc->nn_part.alloc(2 * kRB));
     BO_TRY(pc->nn_mom.alloc(2));
-    BO_TRY(pc->nn_flag.alloc(1));
+    BO_TRY(pc->nn_alpha.alloc(1));
     k_sums<T><<<kRB, 256, 0, s>>>(n, rp, pc->nn_part.p);
     k_sums_final<<<1, 64, 0, s>>>(kRB, pc->nn_part.p, 1.0 / (double)n, pc->nn_mom.p);
     BO_HIP(hipGetLastError());
@@ -198,7 +202,7 @@ bo_status nn_correct(bo_cpr *pc, const T *rp, const T *dp, const T **out, hipStr
     const T *A = fp32 ? (const T *)pc->app32.p : (const T *)pc->app.p;
     k_judge<T><<<kRB, 256, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, A, rp, dp, pc->nn->y.p, pc->nn_mom.p,
                                    pc->nn_part.p);
-    k_judge_final<<<1, 64, 0, s>>>(kRB, pc->nn_part.p, pc->nn_flag.p, pc->nn_used.p);
+    k_judge_final<<<1, 64, 0, s>>>(kRB, pc->nn_part.p, pc->nn_alpha.p, pc->nn_used.p);
     T *o;
     if (fp32) {
         BO_TRY(pc->nn_dp32.alloc(n));
@@ -207,7 +211,7 @@ bo_status nn_correct(bo_cpr *pc, const T *rp, const T *dp, const T **out, hipStr
         BO_TRY(pc->nn_dp.alloc(n));
         o = (T *)pc->nn_dp.p;
     }
-    k_nn_apply<T><<<grid_for(n), kBlock, 0, s>>>(n, dp, pc->nn->y.p, pc->nn_mom.p, pc->nn_flag.p, o);
+    k_nn_apply<T><<<grid_for(n), kBlock, 0, s>>>(n, dp, pc->nn->y.p, pc->nn_mom.p, pc->nn_alpha.p, o);
     BO_HIP(hipGetLastError());
     *out = o;
     return BO_OK;
@@ -336,6 +340,23 @@ extern "C" bo_status bo_cpr_attach_nn(bo_cpr *pc, bo_nn *nn, const double *logk,
     BO_HIP(hipMemsetAsync(pc->nn_used.p, 0, sizeof(int32_t), s));
     BO_HIP(hipStreamSynchronize(s));
     pc->nn = nn;
+    return BO_OK;
+}
+
+// level-0 pressure matrix in slot order as FP32 [7][N]
+__global__ void k_app_to_f32(long long n, const double *__restrict__ app, float *__restrict__ out) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < 7 * n) out[e] = (float)app[e];
+}
+
+extern "C" bo_status bo_cpr_pressure_stencil(bo_cpr *pc, float *coef, void *stream) {
+    if (!pc || !coef) return fail(BO_ERR_INVALID_ARG, "bo_cpr_pressure_stencil: NULL argument");
+    if (pc->general || pc->cond || !pc->o.use_amg)
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_pressure_stencil: needs the plain grid form with a pressure stage");
+    if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_cpr_pressure_stencil: the last bo_cpr_update failed");
+    long long n = pc->n;
+    k_app_to_f32<<<grid_for(7 * n), kBlock, 0, (hipStream_t)stream>>>(n, pc->app.p, coef);
+    BO_HIP(hipGetLastError());
     return BO_OK;
 }
 

@@ -117,6 +117,56 @@ def test_backward_matches_oracle_and_adam(B):
     assert np.allclose(p1, B.nn_flatten(ref), rtol=1e-5, atol=1e-7)
 
 
+def test_weighted_backward_matches_oracle(B):
+    """The A_pp-weighted loss (the residual a correction would leave, on the
+    voxels whose stencil lies in the volume) and its gradients against the
+    oracle's BF16 emulation: loss 1e-3, gradients 1e-2 norm-wise per layer."""
+    rng = np.random.default_rng(4)
+    params = cg.cnn_init(26, last_scale=1.0)
+    X = rng.standard_normal(SHAPE + (2,))
+    T = rng.standard_normal(SHAPE)
+    coef = rng.standard_normal((7,) + SHAPE) * 0.5
+    coef[3] = 4.0 + np.abs(coef[3])
+    nn = B.Nn(params)
+    gpu_forward(B, nn, X)
+    loss = nn.backward_weighted(to_dev(coef.astype(np.float32)), to_dev(T.astype(np.float32)))
+    _, g = nn.get()
+    gl = B.nn_unflatten(g)
+    nb = SHAPE[0]
+    ge, lref = None, 0.0
+    for v in range(nb):
+        ye, cache = N.forward(f64(params), X[v], emulate_bf16=True)
+        cv = coef[:, v].astype(np.float32).astype(np.float64)
+        gv = N.backward_weighted(f64(params), cache, ye, cv, T[v].astype(np.float32).astype(np.float64),
+                                 emulate_bf16=True)
+        ge = [(a / nb, b / nb) for a, b in gv] if ge is None else [(A + a / nb, Bb + b / nb)
+                                                                    for (A, Bb), (a, b) in zip(ge, gv)]
+        lref += N.weighted_loss(ye, cv, T[v]) / nb
+    assert abs(loss - lref) <= 1e-3 * lref
+    for l in range(4):
+        for q in range(2):
+            a, e = np.asarray(gl[l][q], np.float64), ge[l][q]
+            assert np.linalg.norm(a - e) <= 1e-2 * np.linalg.norm(e), (l, q)
+
+
+def test_pressure_stencil_export(B, O):
+    """bo_cpr_pressure_stencil: the decoupled level-0 pressure matrix of the
+    oracle (its entries in slot order, zero outside the grid), rounded to
+    FP32."""
+    case = ragged_case()
+    P, rp, ci, val, b, opc, gpc = setup_both(B, O, case)
+    coef = to_host(B.bo_cpr_pressure_stencil(gpc)).astype(np.float64)
+    w, app = O.qi_decouple(rp, ci, val)
+    n = case.n
+    nx, ny = case.nx, case.ny
+    offs = [-nx * ny, -nx, -1, 0, 1, nx, nx * ny]
+    ref = np.zeros((7, n))
+    for i in range(n):
+        for e in range(rp[i], rp[i + 1]):
+            ref[offs.index(int(ci[e]) - i), i] = app[e]
+    assert np.all(np.abs(coef - ref) <= 2.0**-24 * np.abs(ref))
+
+
 def test_zero_network_changes_nothing(B, O):
     """A network whose last layer is zero predicts c = 0, the judge never keeps
     it, and the solve is bit for bit the plain CPR solve (both with CGS2, the

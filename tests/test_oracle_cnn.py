@@ -112,7 +112,61 @@ def test_zero_last_layer_gives_zero_correction_and_judge_falls_back():
     A = sp.diags([np.full(60, 4.0), np.full(59, -1.0), np.full(59, -1.0)], [0, -1, 1]).tocsr()
     rp = rng.standard_normal(60)
     v = rng.standard_normal(60)
-    x, used = N.judge(A, rp, v, Y.ravel())
-    assert not used and np.array_equal(x, v)
-    x, used = N.judge(A, rp, v, 0.5 * (np.linalg.solve(A.toarray(), rp) - v))
-    assert used
+    x, alpha = N.judge(A, rp, v, Y.ravel())
+    assert alpha == 0.0 and np.array_equal(x, v)
+    # half the exact error: the minimal-residual multiple is exactly 2 and the
+    # corrected result is the exact solution
+    xs = np.linalg.solve(A.toarray(), rp)
+    x, alpha = N.judge(A, rp, v, 0.5 * (xs - v))
+    assert alpha == pytest.approx(2.0, rel=1e-12)
+    assert np.linalg.norm(x - xs) <= 1e-12 * np.linalg.norm(xs)
+    # a correction pointing the wrong way is never used
+    x, alpha = N.judge(A, rp, v, -(xs - v))
+    assert alpha == 0.0 and np.array_equal(x, v)
+    # any other correction: the residual after the judge never exceeds the
+    # V-cycle's, and equals the closed-form minimum over alpha
+    c = rng.standard_normal(60)
+    x, alpha = N.judge(A, rp, v, c)
+    u, w = rp - A @ v, A @ c
+    best = np.sqrt(max(u @ u - max(u @ w, 0.0) ** 2 / (w @ w), 0.0))
+    assert np.linalg.norm(rp - A @ x) == pytest.approx(best, rel=1e-10)
+    assert np.linalg.norm(rp - A @ x) <= np.linalg.norm(u)
+
+
+def test_weighted_loss_gradient_matches_finite_differences():
+    """The A_pp-weighted loss (the residual a correction would leave, on the
+    voxels whose stencil lies inside the crop): its gradient with respect to
+    the network output against central differences, and with respect to the
+    weights through the same back-propagation as the MSE."""
+    rng = np.random.default_rng(10)
+    shape = (4, 5, 6)
+    coef = rng.standard_normal((7,) + shape)
+    coef[3] = 6.0 + np.abs(coef[3])
+    Y = rng.standard_normal(shape + (1,))
+    T = rng.standard_normal(shape)
+    g = N.weighted_loss_grad(Y, coef, T)
+    h = 1e-6
+    for idx in [(0, 0, 0), (1, 2, 3), (3, 4, 5), (2, 1, 0), (1, 1, 1)]:
+        Yp, Ym = Y.copy(), Y.copy()
+        Yp[idx + (0,)] += h
+        Ym[idx + (0,)] -= h
+        fd = (N.weighted_loss(Yp, coef, T) - N.weighted_loss(Ym, coef, T)) / (2 * h)
+        assert fd == pytest.approx(g[idx], rel=1e-6, abs=1e-9)
+    # the loss is the MSE of A (y - t) on interior voxels: zero at y = t, and
+    # with unit diagonal coefficients and no couplings it is the interior MSE
+    assert N.weighted_loss(T[..., None], coef, T) == 0.0
+    I = np.zeros((7,) + shape)
+    I[3] = 1.0
+    m = N.interior_mask(shape)
+    assert N.weighted_loss(Y, I, T) == pytest.approx(np.mean((Y[..., 0] - T)[m] ** 2), rel=1e-14)
+    params = [(W.astype(np.float64), b.astype(np.float64)) for W, b in cg.cnn_init(13, last_scale=1.0)]
+    X = rng.standard_normal(shape + (2,))
+    Yn, cache = N.forward(params, X)
+    grads = N.backward_weighted(params, cache, Yn, coef, T)
+    l, q, pos = 3, 0, (5, 2, 0)
+    Wp = [(W.copy(), b.copy()) for W, b in params]
+    Wm = [(W.copy(), b.copy()) for W, b in params]
+    Wp[l][q][pos] += h
+    Wm[l][q][pos] -= h
+    fd = (N.weighted_loss(N.forward(Wp, X)[0], coef, T) - N.weighted_loss(N.forward(Wm, X)[0], coef, T)) / (2 * h)
+    assert fd == pytest.approx(grads[l][q][pos], rel=1e-5)
