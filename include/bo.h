@@ -350,6 +350,79 @@ typedef struct {
 bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
                           bo_solve_stats *stats, void *stream);
 
+/* ---- Inexact Newton and time steps (Section 3.1) ----------------------
+ * One time step solves R(x; x_old, dt) = 0 by the inexact Newton method of
+ * Section 3.1: iteration l assembles b(x^l) = -R(x^l) and its Jacobian
+ * (bo_jacobian_bsr), solves J dx = b with CPR-FGMRES to ||b - J dx|| <=
+ * theta_l ||b||, and steps x^{l+1} = x^l + omega dx with omega = min(1,
+ * ds_max / max |dS|) over the saturations of the cell rows (chopping).
+ * Forcing terms theta_l (r^{l-1} = b(x^{l-1}) - J_{l-1} omega dx, the linear
+ * model's residual of the step taken): BO_FORCING_EW1 ||b(x^l) - r^{l-1}|| /
+ * ||b(x^{l-1})||, BO_FORCING_EW2 | ||b(x^l)|| - ||r^{l-1}|| | / ||b(x^{l-1})||,
+ * BO_FORCING_EW3 gamma (||b(x^l)|| / ||b(x^{l-1})||)^beta, BO_FORCING_FIXED
+ * theta_fixed (the standard Newton method); theta_0 = theta0, every theta
+ * clipped to [theta_min, theta_max].  The loop stops when ||b(x^l)|| <=
+ * max(atol, rtol ||b(x^0)||) (2-norms). */
+enum { BO_FORCING_FIXED = 0, BO_FORCING_EW1 = 1, BO_FORCING_EW2 = 2, BO_FORCING_EW3 = 3 };
+#define BO_NEWTON_HIST 64
+#define BO_RUN_HIST 256
+
+typedef struct {
+    int32_t forcing;                    /* BO_FORCING_* */
+    double theta0, theta_fixed, gamma, beta, theta_min, theta_max;
+    double rtol, atol;                  /* nonlinear stopping test */
+    int32_t max_newton;                 /* <= BO_NEWTON_HIST */
+    double ds_max;                      /* largest saturation change per iteration */
+} bo_newton_opts;
+
+/* Defaults: EW1, theta0 1e-2, theta_fixed 1e-7, gamma 0.9, beta 2, theta in
+ * [1e-8, 0.1], rtol 1e-6, atol 0, 20 iterations, ds_max 0.2. */
+void bo_newton_default_opts(bo_newton_opts *o);
+
+typedef struct {
+    int32_t iterations;                 /* Newton iterations (linear solves) */
+    int32_t linear_iterations;          /* preconditioner applications, summed */
+    int32_t converged;
+    double res0, res;                   /* ||b(x^0)||, ||b(x^final)|| */
+    double res_hist[BO_NEWTON_HIST + 1];/* ||b(x^l)||, l = 0..iterations */
+    double theta_hist[BO_NEWTON_HIST];  /* theta_l */
+    double omega_hist[BO_NEWTON_HIST];  /* step lengths */
+    int32_t lin_hist[BO_NEWTON_HIST];   /* linear iterations of each solve */
+} bo_newton_stats;
+
+typedef struct {
+    int32_t steps, cuts;                /* accepted steps, halved steps */
+    int32_t newton_iterations, linear_iterations;   /* over every attempt */
+    double t;                           /* time reached, days */
+    double dt_hist[BO_RUN_HIST];        /* accepted step sizes (the first BO_RUN_HIST) */
+    int32_t newton_hist[BO_RUN_HIST];   /* their Newton iterations */
+} bo_run_stats;
+
+typedef struct bo_newton bo_newton;
+
+/* [host] A Newton driver for problem p (copied, wells included; the field
+ * pointers must stay valid): it owns the Jacobian, right-hand side and work
+ * vectors, and the CPR handle of its systems (set up with grid and copts on
+ * the first solve, updated for every later Jacobian). */
+bo_status bo_newton_create(const bo_problem *p, const bo_grid *grid, const bo_cpr_opts *copts, bo_newton **out,
+                           void *stream);
+void bo_newton_destroy(bo_newton *h);
+/* One time step: x (3 nbrows) holds the initial iterate on entry and the
+ * last iterate on exit; x_old the previous time level; dt in days; fo the
+ * linear solver's options (its rtol is replaced by theta_l).  Synchronous.
+ * Returns BO_OK (converged), BO_NOT_CONVERGED (max_newton reached) or an
+ * error. */
+bo_status bo_newton_solve(bo_newton *h, const double *x_old, double *x, double dt, const bo_newton_opts *o,
+                          const bo_fgmres_opts *fo, bo_newton_stats *st, void *stream);
+/* Time steps over [0, t_end] from the state x (updated in place): each step
+ * is bo_newton_solve from the previous state; a step that does not converge
+ * is repeated with half the step (BO_NOT_CONVERGED once it falls below
+ * dt_min); after a step of at most `easy` Newton iterations the next step is
+ * growth times longer, capped at dt_max and the remaining time. */
+bo_status bo_newton_run(bo_newton *h, double *x, double t_end, double dt0, double dt_max, double dt_min,
+                        double growth, int32_t easy, const bo_newton_opts *o, const bo_fgmres_opts *fo,
+                        bo_run_stats *rs, void *stream);
+
 /* ---- a9: learned pressure-stage correction ----------------------------
  * Not part of the paper, which stops at AMG for the pressure block (Section
  * 3.2); this stage adds to the V-cycle result a correction predicted by a

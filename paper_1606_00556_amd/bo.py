@@ -35,7 +35,8 @@ EXPORTS = [
     "bo_nn_create", "bo_nn_destroy", "bo_nn_num_params", "bo_nn_set_params", "bo_nn_get_params",
     "bo_nn_forward", "bo_nn_backward", "bo_nn_adam_step", "bo_cpr_attach_nn", "bo_cpr_collect_pairs",
     "bo_jacobian_bsr_noalloc", "bo_jacobian_bsr_noalloc_max_rows", "bo_nn_backward_weighted",
-    "bo_cpr_pressure_stencil",
+    "bo_cpr_pressure_stencil", "bo_newton_default_opts", "bo_newton_create", "bo_newton_destroy",
+    "bo_newton_solve", "bo_newton_run",
 ]
 
 
@@ -104,6 +105,29 @@ class BoSolveStats(C.Structure):
                 ("spmv_calls", C.c_int32), ("nn_used", C.c_int32)]
 
 
+BO_FORCING_FIXED, BO_FORCING_EW1, BO_FORCING_EW2, BO_FORCING_EW3 = 0, 1, 2, 3
+BO_NEWTON_HIST, BO_RUN_HIST = 64, 256
+
+
+class BoNewtonOpts(C.Structure):
+    _fields_ = [("forcing", C.c_int32), ("theta0", C.c_double), ("theta_fixed", C.c_double), ("gamma", C.c_double),
+                ("beta", C.c_double), ("theta_min", C.c_double), ("theta_max", C.c_double), ("rtol", C.c_double),
+                ("atol", C.c_double), ("max_newton", C.c_int32), ("ds_max", C.c_double)]
+
+
+class BoNewtonStats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("linear_iterations", C.c_int32), ("converged", C.c_int32),
+                ("res0", C.c_double), ("res", C.c_double), ("res_hist", C.c_double * (BO_NEWTON_HIST + 1)),
+                ("theta_hist", C.c_double * BO_NEWTON_HIST), ("omega_hist", C.c_double * BO_NEWTON_HIST),
+                ("lin_hist", C.c_int32 * BO_NEWTON_HIST)]
+
+
+class BoRunStats(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("cuts", C.c_int32), ("newton_iterations", C.c_int32),
+                ("linear_iterations", C.c_int32), ("t", C.c_double), ("dt_hist", C.c_double * BO_RUN_HIST),
+                ("newton_hist", C.c_int32 * BO_RUN_HIST)]
+
+
 _lib = None
 
 
@@ -159,10 +183,19 @@ def lib():
     L.bo_cpr_pressure_stencil.argtypes = [vp, vp, vp]
     L.bo_cpr_attach_nn.argtypes = [vp, vp, vp, vp]
     L.bo_cpr_collect_pairs.argtypes = [vp, vp, C.c_int32, C.c_double, vp, vp, C.POINTER(C.c_int32), vp]
+    L.bo_newton_default_opts.argtypes = [C.POINTER(BoNewtonOpts)]
+    L.bo_newton_default_opts.restype = None
+    L.bo_newton_create.argtypes = [C.POINTER(BoProblem), C.POINTER(BoGrid), C.POINTER(BoCprOpts), C.POINTER(vp), vp]
+    L.bo_newton_destroy.argtypes = [vp]
+    L.bo_newton_destroy.restype = None
+    L.bo_newton_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(BoNewtonOpts), C.POINTER(BoFgmresOpts),
+                                  C.POINTER(BoNewtonStats), vp]
+    L.bo_newton_run.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                C.POINTER(BoNewtonOpts), C.POINTER(BoFgmresOpts), C.POINTER(BoRunStats), vp]
     for f in EXPORTS:
         if f not in ("bo_last_error", "bo_version", "bo_cpr_default_opts", "bo_cpr_destroy",
                      "bo_fgmres_default_opts", "bo_nn_destroy", "bo_nn_num_params",
-                     "bo_jacobian_bsr_noalloc_max_rows"):
+                     "bo_jacobian_bsr_noalloc_max_rows", "bo_newton_default_opts", "bo_newton_destroy"):
             getattr(L, f).restype = st
     _lib = L
     return L
@@ -533,3 +566,62 @@ def bo_cpr_collect_pairs(pc: "Cpr", b, ncalls: int = 4, rtol_inner: float = 1e-1
     _check(lib().bo_cpr_collect_pairs(pc.h, _ptr(b), ncalls, rtol_inner, _ptr(rp), _ptr(e), C.byref(got),
                                       _stream(stream)))
     return rp, e, got.value
+
+
+# ---- inexact Newton and time steps ---------------------------------------------
+def bo_newton_default_opts(**overrides) -> BoNewtonOpts:
+    o = BoNewtonOpts()
+    lib().bo_newton_default_opts(C.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+class Newton:
+    """Owns a bo_newton handle for a DeviceProblem (kept alive here)."""
+
+    def __init__(self, p: DeviceProblem, grid, copts: Optional[BoCprOpts] = None, stream=None):
+        self.p = p
+        g = BoGrid(*grid)
+        o = copts if copts is not None else bo_cpr_default_opts()
+        h = C.c_void_p()
+        _check(lib().bo_newton_create(p.ref, C.byref(g), C.byref(o), C.byref(h), _stream(stream)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().bo_newton_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bo_newton_solve(h: Newton, x_old, x, dt: float, opts: Optional[BoNewtonOpts] = None,
+                    fopts: Optional[BoFgmresOpts] = None, stream=None) -> dict:
+    o = opts if opts is not None else bo_newton_default_opts()
+    fo = fopts if fopts is not None else bo_fgmres_default_opts()
+    st = BoNewtonStats()
+    rc = lib().bo_newton_solve(h.h, _ptr(x_old), _ptr(x), float(dt), C.byref(o), C.byref(fo), C.byref(st),
+                               _stream(stream))
+    _check(rc, allowed=(BO_OK, BO_NOT_CONVERGED))
+    k = st.iterations
+    return dict(status=rc, converged=bool(st.converged), iterations=k, linear_iterations=st.linear_iterations,
+                res0=st.res0, res=st.res, res_hist=list(st.res_hist[:k + 1]), theta=list(st.theta_hist[:k]),
+                omega=list(st.omega_hist[:k]), linear=list(st.lin_hist[:k]))
+
+
+def bo_newton_run(h: Newton, x, t_end: float, dt0: float, dt_max: float, dt_min: float = 1e-4,
+                  growth: float = 1.5, easy: int = 5, opts: Optional[BoNewtonOpts] = None,
+                  fopts: Optional[BoFgmresOpts] = None, stream=None) -> dict:
+    o = opts if opts is not None else bo_newton_default_opts()
+    fo = fopts if fopts is not None else bo_fgmres_default_opts()
+    rs = BoRunStats()
+    _check(lib().bo_newton_run(h.h, _ptr(x), float(t_end), float(dt0), float(dt_max), float(dt_min), float(growth),
+                               int(easy), C.byref(o), C.byref(fo), C.byref(rs), _stream(stream)))
+    n = min(rs.steps, BO_RUN_HIST)
+    return dict(steps=rs.steps, cuts=rs.cuts, newton_iterations=rs.newton_iterations,
+                linear_iterations=rs.linear_iterations, t=rs.t, dt=list(rs.dt_hist[:n]), newton=list(rs.newton_hist[:n]))
