@@ -245,7 +245,7 @@ typedef struct bo_cpr bo_cpr;
  * failure); free releases a pointer alloc returned (stream: that of the
  * entry point releasing it, NULL from bo_cpr_destroy, which synchronises the
  * device first).  ctx is passed through.  The functions may be called from
- * bo_cpr_setup, bo_cpr_update, bo_fgmres_solve, bo_cpr_attach_nn,
+ * bo_cpr_setup, bo_cpr_update, bo_fgmres_solve, bo_bicgstab_solve, bo_cpr_attach_nn,
  * bo_cpr_collect_pairs and bo_cpr_destroy of the handle, on the calling
  * thread.  Library-wide scratch (a few small grow-only buffers per host
  * thread) and pinned host staging buffers are not taken from it. */
@@ -349,6 +349,23 @@ typedef struct {
  * BO_ERR_BREAKDOWN or another error. */
 bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
                           bo_solve_stats *stats, void *stream);
+
+/* Right-preconditioned BiCGSTAB (Section 3.3 names it among the Krylov
+ * solvers; the scaling runs of Section 4.2 use it) on A x = b with the
+ * preconditioner of pc, which must be linear (no network attached:
+ * BO_ERR_UNSUPPORTED).  A and x as for bo_fgmres_solve; of opts only maxit
+ * (a cap on preconditioner applications, two per BiCGSTAB step) and rtol are
+ * read.  The recurrence residual stops the iteration; the true residual
+ * ||b - A x|| is then computed from A and the iteration restarts from it
+ * while it is above rtol ||b||.  A breakdown (a zero <rhat, r>, <rhat, v> or
+ * <t, t>) restarts once from the true residual; a second one returns
+ * BO_ERR_BREAKDOWN with x the last iterate.  With a condensed handle the
+ * reduced system is solved as for bo_fgmres_solve.  Synchronous (reads five
+ * scalars per step).  stats: iterations, restarts, converged, rel_residual
+ * (true, at exit) and est_residual (recurrence); the timing fields stay 0.
+ * Returns BO_OK, BO_NOT_CONVERGED, BO_ERR_BREAKDOWN or another error. */
+bo_status bo_bicgstab_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+                            bo_solve_stats *stats, void *stream);
 
 /* ---- Inexact Newton and time steps (Section 3.1) ----------------------
  * One time step solves R(x; x_old, dt) = 0 by the inexact Newton method of

@@ -36,7 +36,7 @@ EXPORTS = [
     "bo_nn_forward", "bo_nn_backward", "bo_nn_adam_step", "bo_cpr_attach_nn", "bo_cpr_collect_pairs",
     "bo_jacobian_bsr_noalloc", "bo_jacobian_bsr_noalloc_max_rows", "bo_nn_backward_weighted",
     "bo_cpr_pressure_stencil", "bo_newton_default_opts", "bo_newton_create", "bo_newton_destroy",
-    "bo_newton_solve", "bo_newton_run",
+    "bo_newton_solve", "bo_newton_run", "bo_bicgstab_solve",
 ]
 
 
@@ -169,6 +169,8 @@ def lib():
     L.bo_fgmres_default_opts.argtypes = [C.POINTER(BoFgmresOpts)]
     L.bo_fgmres_default_opts.restype = None
     L.bo_fgmres_solve.argtypes = [vp, C.POINTER(BoBsr), vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats), vp]
+    L.bo_bicgstab_solve.argtypes = [vp, C.POINTER(BoBsr), vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats),
+                                    vp]
     L.bo_nn_create.argtypes = [C.POINTER(vp)]
     L.bo_nn_destroy.argtypes = [vp]
     L.bo_nn_destroy.restype = None
@@ -459,6 +461,17 @@ def bo_fgmres_solve(pc: Cpr, A: DeviceBsr, b, x, opts: Optional[BoFgmresOpts] = 
     return dict(status=rc, iterations=st.iterations, restarts=st.restarts, converged=bool(st.converged),
                 rel_residual=st.rel_residual, est_residual=st.est_residual, spmv_ms=st.spmv_ms,
                 spmv_calls=st.spmv_calls, nn_used=st.nn_used)
+
+
+def bo_bicgstab_solve(pc: Cpr, A: DeviceBsr, b, x, opts: Optional[BoFgmresOpts] = None, stream=None,
+                      allowed=(BO_OK, BO_NOT_CONVERGED)) -> dict:
+    """BiCGSTAB with pc (maxit and rtol of opts); A as for bo_fgmres_solve."""
+    o = opts if opts is not None else bo_fgmres_default_opts()
+    st = BoSolveStats()
+    rc = lib().bo_bicgstab_solve(pc.h, C.byref(A.s), _ptr(b), _ptr(x), C.byref(o), C.byref(st), _stream(stream))
+    _check(rc, allowed=allowed)
+    return dict(status=rc, iterations=st.iterations, restarts=st.restarts, converged=bool(st.converged),
+                rel_residual=st.rel_residual, est_residual=st.est_residual)
 
 
 # ---- learned pressure-stage correction ---------------------------------------

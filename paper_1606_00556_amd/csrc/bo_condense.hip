@@ -275,13 +275,14 @@ bo_status cond_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     return BO_OK;
 }
 
-// The full system through the reduced one: r = b - A x (caller's A); FGMRES
-// on S d' = reduce(r) to ||reduce(r) - S d'|| <= rtol ||b||; x += back(r, d').
+// The full system through the reduced one: r = b - A x (caller's A); the
+// Krylov solver (FGMRES or BiCGSTAB) on S d' = reduce(r) to ||reduce(r) -
+// S d'|| <= rtol ||b||; x += back(r, d').
 // After the back-substitution the matrix rows hold exactly (up to rounding),
 // so the full residual is the reduced one; a further pass runs only if the
 // full residual still exceeds the tolerance.
 bo_status cond_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
-                     bo_solve_stats *stats, hipStream_t s) {
+                     bo_solve_stats *stats, hipStream_t s, KrylovCore core) {
     Condensed &C = *pc->cond;
     const long long len = 3 * C.nfull;
     bo_cpr *in = C.inner;
@@ -335,7 +336,7 @@ bo_status cond_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, co
         io.rtol = tol / rbn;
         io.maxit = opts->maxit - st.iterations;
         bo_solve_stats ist{};
-        bo_status rc = fgmres_core(in, nullptr, C.rb.p, C.rx.p, &io, &ist, s);
+        bo_status rc = core(in, nullptr, C.rb.p, C.rx.p, &io, &ist, s);
         st.iterations += ist.iterations;
         st.restarts += ist.restarts;
         st.spmv_ms += ist.spmv_ms;

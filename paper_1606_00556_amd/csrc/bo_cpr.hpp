@@ -136,6 +136,8 @@ struct bo_cpr {
     bo::SetupWork sw;
     bo::Reducer red;
     bo::Krylov kr;
+    bo::DBuf<double> bicg;        // BiCGSTAB work vectors: 7 x 3N (r, rhat, p, v, phat, shat, t)
+    bo::DBuf<double> bicg_sc;     // its device scalars
     hipEvent_t ev[4] = {};        // SpMV timing in bo_fgmres_solve (two Arnoldi steps in flight)
     hipEvent_t evf[2] = {};       // completion of an Arnoldi step's scalars
     // the preconditioner as a HIP graph (captured once per setup)
@@ -165,8 +167,15 @@ bo_status fgmres_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, c
 // condensed form (bo_condense.hip)
 bo_status cond_setup(bo_cpr *pc, const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, hipStream_t s);
 bo_status cond_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s);
+// a Krylov solver on pc's operator (A: the caller's matrix for the true
+// residual, or NULL for the handle's copy)
+typedef bo_status (*KrylovCore)(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+                                bo_solve_stats *stats, hipStream_t s);
+bo_status bicgstab_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+                        bo_solve_stats *stats, hipStream_t s);
+bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s);
 bo_status cond_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
-                     bo_solve_stats *stats, hipStream_t s);
+                     bo_solve_stats *stats, hipStream_t s, KrylovCore core);
 void cond_destroy(bo_cpr *pc);
 // the handle whose stages and hierarchy the entry points act on: the reduced
 // system's CPR for a condensed handle, pc itself otherwise (NULL stays NULL)

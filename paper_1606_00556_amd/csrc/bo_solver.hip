@@ -38,7 +38,7 @@ template <typename T>
 bo_status nn_record(bo_cpr *pc, const T *rp, hipStream_t s);
 
 // y = alpha A x + beta y with the handle's copy of A (slot or BSR form)
-static bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s) {
+bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s) {
     if (!pc->general) return slot_spmv(pc->g, pc->A.p, alpha, x, beta, y, s);
     return sell_spmv(pc->n, pc->Asoff.p, pc->Asci.p, pc->Asv.p, alpha, x, beta, y, s);
 }
@@ -757,6 +757,6 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *
         opts->orth > 2 || (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1))
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
     AllocScope scope(pc->allocator(), stream);
-    if (pc->cond) return cond_solve(pc, A, b, x, opts, stats, (hipStream_t)stream);
+    if (pc->cond) return cond_solve(pc, A, b, x, opts, stats, (hipStream_t)stream, fgmres_core);
     return fgmres_core(pc, A, b, x, opts, stats, (hipStream_t)stream);
 }
