@@ -26,6 +26,9 @@ noise amplitude, as in a Newton iterate of a real run.
 * ``cfg 2``  200x200x50, log-normal k with sigma 2 and five 0.01 mD barrier
   layers, five-spot wells, the same 10-system sequence.
 * ``tiny``   any small grid for pins and parity cases.
+* ``two_phase(case)``  the oil-water version of any single-porosity case with
+  fixed-BHP wells (Section 2.2): the same grid, rock, wells and oil / water
+  state, no gas (S_g = 0) and dead oil (R_s = 0).
 """
 from __future__ import annotations
 
@@ -37,7 +40,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = ["Well", "Case", "FLUID", "uniform", "normal", "make_case",
-           "tiny_case", "base_seed", "N_SYSTEMS"]
+           "tiny_case", "base_seed", "N_SYSTEMS", "two_phase", "state2"]
 
 N_SYSTEMS = 10
 
@@ -130,6 +133,9 @@ class Case:
     km: Optional[np.ndarray] = None
     phim: Optional[np.ndarray] = None
     sigma: float = 0.0
+    # two-phase oil-water case (see two_phase): x_old / x_new keep the
+    # three-slot layout with S_g = 0
+    two_phase: bool = False
 
     @property
     def n(self) -> int:
@@ -329,6 +335,25 @@ def tiny_case(nx: int, ny: int, nz: int, seed: int = 7, *, sigma: float = 1.0,
     return Case(f"tiny{nx}x{ny}x{nz}", nx, ny, nz, 50.0, 50.0, 10.0, 8000.0, kx, kx.copy(),
                 kz_ratio * kx, _porosity(seed, n), x_old, x_new, dt, wells, dict(FLUID),
                 gravity=gravity)
+
+
+def two_phase(case: Case) -> Case:
+    """The oil-water version of a single-porosity case with fixed-BHP wells:
+    S_g = 0 in both states (S_w kept), no dissolved gas (R_s = 0)."""
+    if case.dual or any(w.control != "bhp" for w in case.wells):
+        raise ValueError("two_phase needs a single-porosity case with fixed-BHP wells")
+    fl = dict(case.fluid)
+    fl["Rs0"] = 0.0
+    fl["crs"] = 0.0
+    xo, xn = case.x_old.copy(), case.x_new.copy()
+    xo[2::3] = 0.0
+    xn[2::3] = 0.0
+    return dataclasses.replace(case, name=case.name + "/2p", x_old=xo, x_new=xn, fluid=fl, two_phase=True)
+
+
+def state2(x: np.ndarray) -> np.ndarray:
+    """(Po, Sw) per cell from a three-slot state."""
+    return np.ascontiguousarray(np.asarray(x).reshape(-1, 3)[:, :2].reshape(-1))
 
 
 # ---- learned pressure-stage correction: seeded initial weights ---------------
