@@ -7,6 +7,8 @@
  *   - Section 2.1: three-phase, three-component black-oil model (Darcy's law,
  *     saturation and potential constraints, no-flow boundary, Stone II oil
  *     relative permeability) with unknowns (Po, Sw, Sg) per cell;
+ *   - Section 2.2: the two-phase oil-water model, unknowns (Po, Sw), with
+ *     2x2-block Jacobians (the bo_*2 entry points);
  *   - Section 2.3: Peaceman wells, fixed bottom-hole pressure control;
  *   - Section 3: finite differences on a structured hexahedral grid (7-point);
  *   - Section 3.2: block structure of the Jacobian, quasi-IMPES decoupling, and
@@ -71,6 +73,17 @@ typedef struct {
     int32_t *colind;    /* nnzb, ascending within each row */
     double *val;        /* 9*nnzb, row-major blocks */
 } bo_bsr;
+
+/* Block sparse row matrix with 2x2 blocks (the two-phase oil-water model,
+ * Section 2.2): block row = equation (oil, water), block column = unknown
+ * (Po, Sw), row-major; vectors interleave (Po, Sw) per cell (2N doubles). */
+typedef struct {
+    int32_t nbrows;     /* block rows (= cells) */
+    int32_t nnzb;       /* stored blocks */
+    int32_t *rowptr;    /* nbrows+1 */
+    int32_t *colind;    /* nnzb, ascending within each row */
+    double *val;        /* 4*nnzb, row-major blocks */
+} bo_bsr2;
 
 /* Fluid and rock description (field units: psi, ft, mD, cP, days). */
 typedef struct {
@@ -166,6 +179,28 @@ bo_status bo_jacobian_bsr_noalloc(const bo_problem *p, const double *x_old, cons
                                   bo_bsr *J, double *b, void *stream);
 /* Largest nbrows bo_jacobian_bsr_noalloc accepts (2^26). */
 int32_t bo_jacobian_bsr_noalloc_max_rows(void);
+
+/* ---- Two-phase oil-water model (Section 2.2) ----------------------------
+ * The black-oil model without the gas phase: oil and water mass balances,
+ * S_o + S_w = 1, unknowns (Po, Sw) per cell, zero capillary pressure, dead
+ * oil (fluid.Rs0, crs and the gas properties are not read), Corey relative
+ * permeabilities k_rw(S_w) and k_ro(1 - S_w) on [swc, 1 - sor] with
+ * exponents nw and no.  Fluxes, gravity, units and the Peaceman wells are
+ * those of bo_jacobian_bsr; only fixed-BHP wells and single porosity
+ * (dual == 0; otherwise BO_ERR_UNSUPPORTED).  The pattern is the grid's
+ * 7-point stencil, one block row per cell. */
+
+/* [host] sizes of the two-phase Jacobian of p. */
+bo_status bo_jacobian2_bsr_size(const bo_problem *p, int32_t *nbrows, int32_t *nnzb);
+
+/* J (2x2 blocks; rowptr, colind and val preallocated by the caller for the
+ * sizes above) and b = -R(x_new) of one implicit step from x_old to x_new
+ * (2N doubles each), dt in days.  Errors as for bo_jacobian_bsr. */
+bo_status bo_jacobian2_bsr(const bo_problem *p, const double *x_old, const double *x_new, double dt,
+                           bo_bsr2 *J, double *b, void *stream);
+
+/* y = alpha*A*x + beta*y on a 2x2-block BSR matrix (beta == 0: y is not read). */
+bo_status bo_bsr2_spmv(const bo_bsr2 *A, double alpha, const double *x, double beta, double *y, void *stream);
 
 /* ---- Basic operations (Section 3.3) ---------------------------------- */
 
@@ -349,6 +384,33 @@ typedef struct {
  * BO_ERR_BREAKDOWN or another error. */
 bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
                           bo_solve_stats *stats, void *stream);
+
+/* ---- CPR on 2x2-block (two-phase) Jacobians (Section 3.2) -------------
+ * bo_cpr2_setup builds the CPR preconditioner of a 2x2-block matrix on the
+ * grid's 7-point pattern (grid required, nbrows = nx*ny*nz, dual = 0):
+ * quasi-IMPES weights c_i = +-(1, -d_01/d_11) from the diagonal block (sign:
+ * a positive decoupled diagonal), the decoupled pressure block and the same
+ * SA-AMG hierarchy as the black-oil path, and an F stage of block Jacobi or
+ * the tiled block ILU(0) with 2x2 blocks; PF or FPF.  Options as for
+ * bo_cpr_setup, restricted to: precision BO_PREC_FP64, level-0 smoother
+ * BO_SMOOTH_GS or BO_SMOOTH_JACOBI, condense 0, npr 0 (BO_ERR_UNSUPPORTED or
+ * BO_ERR_INVALID_ARG otherwise).  The handle works with bo_cpr_apply,
+ * bo_cpr_spmv, bo_cpr_restrict, bo_cpr_vcycle, bo_cpr_fstage, the hierarchy
+ * introspection, bo_cpr_copy_weights (2N values) and bo_cpr_destroy, on
+ * vectors of 2N doubles; not with bo_cpr_update, bo_fgmres_solve,
+ * bo_bicgstab_solve or a network (BO_ERR_INVALID_ARG / BO_ERR_UNSUPPORTED).
+ * Synchronises `stream`. */
+bo_status bo_cpr2_setup(const bo_bsr2 *A, const bo_grid *grid, const bo_cpr_opts *opts, const bo_allocator *alloc,
+                        bo_cpr **pc, void *stream);
+/* Rebuilds a 2x2-block handle for new values of the same pattern (as bo_cpr_update). */
+bo_status bo_cpr2_update(bo_cpr *pc, const bo_bsr2 *A, void *stream);
+/* FGMRES(m) and BiCGSTAB with a 2x2-block handle: as bo_fgmres_solve and
+ * bo_bicgstab_solve, A the 2x2-block matrix of the last setup or update,
+ * vectors of 2N doubles. */
+bo_status bo_fgmres_solve2(bo_cpr *pc, const bo_bsr2 *A, const double *b, double *x, const bo_fgmres_opts *opts,
+                           bo_solve_stats *stats, void *stream);
+bo_status bo_bicgstab_solve2(bo_cpr *pc, const bo_bsr2 *A, const double *b, double *x, const bo_fgmres_opts *opts,
+                             bo_solve_stats *stats, void *stream);
 
 /* Right-preconditioned BiCGSTAB (Section 3.3 names it among the Krylov
  * solvers; the scaling runs of Section 4.2 use it) on A x = b with the

@@ -36,7 +36,8 @@ EXPORTS = [
     "bo_nn_forward", "bo_nn_backward", "bo_nn_adam_step", "bo_cpr_attach_nn", "bo_cpr_collect_pairs",
     "bo_jacobian_bsr_noalloc", "bo_jacobian_bsr_noalloc_max_rows", "bo_nn_backward_weighted",
     "bo_cpr_pressure_stencil", "bo_newton_default_opts", "bo_newton_create", "bo_newton_destroy",
-    "bo_newton_solve", "bo_newton_run", "bo_bicgstab_solve",
+    "bo_newton_solve", "bo_newton_run", "bo_bicgstab_solve", "bo_jacobian2_bsr_size", "bo_jacobian2_bsr",
+    "bo_bsr2_spmv", "bo_cpr2_setup", "bo_cpr2_update", "bo_fgmres_solve2", "bo_bicgstab_solve2",
 ]
 
 
@@ -171,6 +172,15 @@ def lib():
     L.bo_fgmres_solve.argtypes = [vp, C.POINTER(BoBsr), vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats), vp]
     L.bo_bicgstab_solve.argtypes = [vp, C.POINTER(BoBsr), vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats),
                                     vp]
+    # 2x2-block (two-phase) entry points; bo_bsr2 has bo_bsr's layout
+    L.bo_jacobian2_bsr_size.argtypes = [C.POINTER(BoProblem), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.bo_jacobian2_bsr.argtypes = [C.POINTER(BoProblem), vp, vp, C.c_double, C.POINTER(BoBsr), vp, vp]
+    L.bo_bsr2_spmv.argtypes = [C.POINTER(BoBsr), C.c_double, vp, C.c_double, vp, vp]
+    L.bo_cpr2_setup.argtypes = [C.POINTER(BoBsr), C.POINTER(BoGrid), C.POINTER(BoCprOpts), C.POINTER(BoAllocator),
+                                C.POINTER(vp), vp]
+    L.bo_cpr2_update.argtypes = [vp, C.POINTER(BoBsr), vp]
+    for f in ("bo_fgmres_solve2", "bo_bicgstab_solve2"):
+        getattr(L, f).argtypes = [vp, C.POINTER(BoBsr), vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats), vp]
     L.bo_nn_create.argtypes = [C.POINTER(vp)]
     L.bo_nn_destroy.argtypes = [vp]
     L.bo_nn_destroy.restype = None
@@ -336,11 +346,13 @@ def bo_fgmres_default_opts(**overrides) -> BoFgmresOpts:
 
 
 class Cpr:
-    """Owns a bo_cpr handle (bo_cpr_destroy on close / garbage collection)."""
+    """Owns a bo_cpr handle (bo_cpr_destroy on close / garbage collection).
+    bs: block size (3 black oil, 2 two-phase)."""
 
-    def __init__(self, h: int, n: int):
+    def __init__(self, h: int, n: int, bs: int = 3):
         self.h = C.c_void_p(h)
         self.n = n
+        self.bs = bs
         self.A = None
         self.allocator = None
 
@@ -445,7 +457,7 @@ def bo_cpr_level_copy(pc: Cpr, l: int) -> dict:
 
 def bo_cpr_copy_weights(pc: Cpr):
     import numpy as np
-    c = np.zeros(3 * pc.n)
+    c = np.zeros(pc.bs * pc.n)
     _check(lib().bo_cpr_copy_weights(pc.h, c.ctypes.data))
     return c
 
@@ -638,3 +650,77 @@ def bo_newton_run(h: Newton, x, t_end: float, dt0: float, dt_max: float, dt_min:
     n = min(rs.steps, BO_RUN_HIST)
     return dict(steps=rs.steps, cuts=rs.cuts, newton_iterations=rs.newton_iterations,
                 linear_iterations=rs.linear_iterations, t=rs.t, dt=list(rs.dt_hist[:n]), newton=list(rs.newton_hist[:n]))
+
+
+# ---- two-phase oil-water model: 2x2 blocks ----------------------------------------
+@dataclass
+class DeviceBsr2(DeviceBsr):
+    """A bo_bsr2 (2x2 blocks, val 4*nnzb) over device tensors."""
+
+
+def bo_jacobian2_bsr_size(p: DeviceProblem):
+    n, nnzb = C.c_int32(), C.c_int32()
+    _check(lib().bo_jacobian2_bsr_size(p.ref, C.byref(n), C.byref(nnzb)))
+    return n.value, nnzb.value
+
+
+def bo_jacobian2_bsr(p: DeviceProblem, x_old, x_new, dt: float, J: Optional[DeviceBsr2] = None, b=None,
+                     stream=None):
+    """Two-phase J (2x2 blocks) and b = -R for states of 2N doubles (Po, Sw).
+    Allocates J and b when they are not given."""
+    import torch
+    n, nnzb = bo_jacobian2_bsr_size(p)
+    dev = x_new.device
+    if J is None:
+        J = DeviceBsr2(torch.empty(n + 1, dtype=torch.int32, device=dev),
+                       torch.empty(nnzb, dtype=torch.int32, device=dev),
+                       torch.empty(4 * nnzb, dtype=torch.float64, device=dev))
+    if b is None:
+        b = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    s = J.s
+    _check(lib().bo_jacobian2_bsr(p.ref, _ptr(x_old), _ptr(x_new), float(dt), C.byref(s), _ptr(b),
+                                  _stream(stream)))
+    return J, b
+
+
+def bo_bsr2_spmv(A: DeviceBsr2, alpha: float, x, beta: float, y, stream=None):
+    s = A.s
+    _check(lib().bo_bsr2_spmv(C.byref(s), alpha, _ptr(x), beta, _ptr(y), _stream(stream)))
+    return y
+
+
+def bo_cpr2_setup(A: DeviceBsr2, grid, opts: Optional[BoCprOpts] = None, stream=None) -> Cpr:
+    """CPR of a 2x2-block matrix on the grid (nx, ny, nz)."""
+    o = opts if opts is not None else bo_cpr_default_opts()
+    g = BoGrid(*grid)
+    h = C.c_void_p()
+    s = A.s
+    _check(lib().bo_cpr2_setup(C.byref(s), C.byref(g), C.byref(o), None, C.byref(h), _stream(stream)))
+    pc = Cpr(h.value, s.nbrows, bs=2)
+    pc.A = A
+    return pc
+
+
+def bo_cpr2_update(pc: Cpr, A: DeviceBsr2, stream=None) -> Cpr:
+    s = A.s
+    _check(lib().bo_cpr2_update(pc.h, C.byref(s), _stream(stream)))
+    pc.A = A
+    return pc
+
+
+def _solve2(fn, pc: Cpr, A: DeviceBsr2, b, x, opts, stream):
+    o = opts if opts is not None else bo_fgmres_default_opts()
+    st = BoSolveStats()
+    rc = getattr(lib(), fn)(pc.h, C.byref(A.s), _ptr(b), _ptr(x), C.byref(o), C.byref(st), _stream(stream))
+    _check(rc, allowed=(BO_OK, BO_NOT_CONVERGED))
+    return dict(status=rc, iterations=st.iterations, restarts=st.restarts, converged=bool(st.converged),
+                rel_residual=st.rel_residual, est_residual=st.est_residual, spmv_ms=st.spmv_ms,
+                spmv_calls=st.spmv_calls)
+
+
+def bo_fgmres_solve2(pc: Cpr, A: DeviceBsr2, b, x, opts: Optional[BoFgmresOpts] = None, stream=None) -> dict:
+    return _solve2("bo_fgmres_solve2", pc, A, b, x, opts, stream)
+
+
+def bo_bicgstab_solve2(pc: Cpr, A: DeviceBsr2, b, x, opts: Optional[BoFgmresOpts] = None, stream=None) -> dict:
+    return _solve2("bo_bicgstab_solve2", pc, A, b, x, opts, stream)

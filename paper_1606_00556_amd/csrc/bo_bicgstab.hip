@@ -43,9 +43,9 @@ __global__ void k_bicg_update(long long n, double alpha, const double *__restric
 
 }  // namespace
 
-bo_status bicgstab_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+bo_status bicgstab_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_fgmres_opts *opts,
                         bo_solve_stats *stats, hipStream_t s) {
-    const long long len = 3LL * pc->n;
+    const long long len = (long long)pc->bs * pc->n;
     bo_solve_stats st{};
     BO_TRY(pc->bicg.alloc(7 * (size_t)len));
     BO_TRY(pc->bicg_sc.alloc(4));
@@ -59,8 +59,7 @@ bo_status bicgstab_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x,
     };
     auto true_residual = [&](double *out_norm) -> bo_status {
         BO_HIP(hipMemcpyAsync(r, b, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
-        if (A) BO_TRY(bo_bsr_spmv(A, -1.0, x, 1.0, r, s));
-        else BO_TRY(op_spmv(pc, -1.0, x, 1.0, r, s));
+        BO_TRY(user_spmv(pc, A, -1.0, x, 1.0, r, s));
         double q = 0.0;
         BO_TRY(dot(r, r, &q));
         *out_norm = std::sqrt(q);
@@ -162,6 +161,7 @@ extern "C" bo_status bo_bicgstab_solve(bo_cpr *pc, const bo_bsr *A, const double
                                        const bo_fgmres_opts *opts, bo_solve_stats *stats, void *stream) {
     if (!pc || !A || !b || !x || !opts || !A->rowptr || !A->colind || !A->val)
         return fail(BO_ERR_INVALID_ARG, "bo_bicgstab_solve: NULL argument");
+    if (pc->bs != 3) return fail(BO_ERR_INVALID_ARG, "bo_bicgstab_solve: a 2x2-block handle (bo_bicgstab_solve2)");
     if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_bicgstab_solve: the last bo_cpr_update failed");
     if (A->nbrows != pc->n || A->nnzb != pc->nnzb)
         return fail(BO_ERR_INVALID_ARG, "bo_bicgstab_solve: A is not the matrix of the last setup or update");
@@ -169,5 +169,5 @@ extern "C" bo_status bo_bicgstab_solve(bo_cpr *pc, const bo_bsr *A, const double
     if (pc->nn) return fail(BO_ERR_UNSUPPORTED, "bo_bicgstab_solve: needs a linear preconditioner (no network)");
     AllocScope scope(pc->allocator(), stream);
     if (pc->cond) return cond_solve(pc, A, b, x, opts, stats, (hipStream_t)stream, bicgstab_core);
-    return bicgstab_core(pc, A, b, x, opts, stats, (hipStream_t)stream);
+    return bicgstab_core(pc, UserA{A, nullptr}, b, x, opts, stats, (hipStream_t)stream);
 }

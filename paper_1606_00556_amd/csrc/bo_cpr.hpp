@@ -87,6 +87,7 @@ struct bo_cpr {
     // condensed dual-porosity form: the matrix cells eliminated exactly, the
     // CPR of the reduced system in cond->inner (every other member unused)
     bo::Condensed *cond = nullptr;
+    int bs = 3;                   // block size: 3 (black oil) or 2 (two-phase oil-water, bo_cpr2_setup)
     bo::Grid g{};
     int n = 0;                    // block rows (the cells of a grid)
     int npr = 0;                  // rows of the pressure system (the first npr block rows)
@@ -103,9 +104,9 @@ struct bo_cpr {
     bo::DBuf<int32_t> Asoff, Asci;  // sliced copy of A for the solver's SpMV (general form)
     bo::DBuf<double> Asv;
     bo_cpr_opts o{};
-    // operator (copy of A) in slot layout, 63 * N
+    // operator (copy of A) in slot layout, 7 bs^2 N (63 N, or 28 N for 2x2 blocks)
     bo::DBuf<double> A;
-    // decoupling rows, 3N
+    // decoupling rows, bs N
     bo::DBuf<double> cw;
     // level-0 pressure matrix in slot layout (7 * N) and the hierarchy
     bo::DBuf<double> app;
@@ -136,7 +137,7 @@ struct bo_cpr {
     bo::SetupWork sw;
     bo::Reducer red;
     bo::Krylov kr;
-    bo::DBuf<double> bicg;        // BiCGSTAB work vectors: 7 x 3N (r, rhat, p, v, phat, shat, t)
+    bo::DBuf<double> bicg;        // BiCGSTAB work vectors: 7 x bs N (r, rhat, p, v, phat, shat, t)
     bo::DBuf<double> bicg_sc;     // its device scalars
     hipEvent_t ev[4] = {};        // SpMV timing in bo_fgmres_solve (two Arnoldi steps in flight)
     hipEvent_t evf[2] = {};       // completion of an Arnoldi step's scalars
@@ -162,16 +163,24 @@ namespace bo {
 bo_status cpr_setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc, hipStream_t s);
 bo_status cpr_check(int32_t nbrows, const bo_grid *grid, const bo_cpr_opts *opts);
 bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s);
-bo_status fgmres_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+// The caller's matrix of a solve, for its true residual: a 3x3-block or a
+// 2x2-block BSR matrix (at most one of the two), or neither: the handle's own
+// copy of the operator.
+struct UserA {
+    const bo_bsr *a3;
+    const bo_bsr2 *a2;
+};
+bo_status user_spmv(bo_cpr *pc, const UserA &A, double alpha, const double *x, double beta, double *y,
+                    hipStream_t s);
+bo_status fgmres_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_fgmres_opts *opts,
                       bo_solve_stats *stats, hipStream_t s);
 // condensed form (bo_condense.hip)
 bo_status cond_setup(bo_cpr *pc, const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, hipStream_t s);
 bo_status cond_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s);
-// a Krylov solver on pc's operator (A: the caller's matrix for the true
-// residual, or NULL for the handle's copy)
-typedef bo_status (*KrylovCore)(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+// a Krylov solver on pc's operator
+typedef bo_status (*KrylovCore)(bo_cpr *pc, UserA A, const double *b, double *x, const bo_fgmres_opts *opts,
                                 bo_solve_stats *stats, hipStream_t s);
-bo_status bicgstab_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+bo_status bicgstab_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_fgmres_opts *opts,
                         bo_solve_stats *stats, hipStream_t s);
 bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s);
 bo_status cond_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
@@ -180,4 +189,9 @@ void cond_destroy(bo_cpr *pc);
 // the handle whose stages and hierarchy the entry points act on: the reduced
 // system's CPR for a condensed handle, pc itself otherwise (NULL stays NULL)
 bo_cpr *cond_inner(bo_cpr *pc);
+// 2x2-block handles (bo_cpr2.hip)
+bo_status cpr2_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s);
+bo_status slot2_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s);
+bo_status qi2_restrict(bo_cpr *pc, const double *v, double *rp, hipStream_t s);
+bo_status fstage2_apply(bo_cpr *pc, const double *r, const double *dp, double *out, hipStream_t s);
 }  // namespace bo

@@ -326,7 +326,8 @@ extern "C" bo_status bo_cpr_attach_nn(bo_cpr *pc, bo_nn *nn, const double *logk,
     if (!logk) return fail(BO_ERR_INVALID_ARG, "bo_cpr_attach_nn: logk is NULL");
     AllocScope scope(pc->allocator(), stream);
     if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_attach_nn: the handle has no pressure stage");
-    if (pc->general || pc->cond) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_attach_nn: the network needs the grid form");
+    if (pc->general || pc->cond || pc->bs != 3)
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_attach_nn: the network needs the black-oil grid form");
     hipStream_t s = (hipStream_t)stream;
     long long n = pc->n;
     BO_TRY(pc->nn_z.alloc(n));
@@ -365,7 +366,8 @@ extern "C" bo_status bo_cpr_collect_pairs(bo_cpr *pc, const double *b, int32_t n
     if (!pc || !b || !rp_out || !e_out || !got) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: NULL argument");
     if (ncalls < 1 || !(rtol_inner > 0.0)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: bad arguments");
     if (!pc->o.use_amg) return fail(BO_ERR_INVALID_ARG, "bo_cpr_collect_pairs: the handle has no pressure stage");
-    if (pc->general || pc->cond) return fail(BO_ERR_UNSUPPORTED, "bo_cpr_collect_pairs: pairs need the grid form");
+    if (pc->general || pc->cond || pc->bs != 3)
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_collect_pairs: pairs need the black-oil grid form");
     AllocScope scope(pc->allocator(), stream);
     hipStream_t s = (hipStream_t)stream;
     long long n = pc->n;
@@ -381,7 +383,7 @@ extern "C" bo_status bo_cpr_collect_pairs(bo_cpr *pc, const double *b, int32_t n
     bo_fgmres_default_opts(&o);
     o.maxit = ncalls;  // only the first ncalls applications are needed
     bo_solve_stats st;
-    bo_status rc = fgmres_core(pc, nullptr, b, pc->pg_x.p, &o, &st, s);
+    bo_status rc = fgmres_core(pc, UserA{nullptr, nullptr}, b, pc->pg_x.p, &o, &st, s);
     int rec = pc->rec_n;
     pc->rec_out = nullptr;
     pc->rec_max = pc->rec_n = 0;

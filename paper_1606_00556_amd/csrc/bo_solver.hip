@@ -39,6 +39,7 @@ bo_status nn_record(bo_cpr *pc, const T *rp, hipStream_t s);
 
 // y = alpha A x + beta y with the handle's copy of A (slot or BSR form)
 bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s) {
+    if (pc->bs == 2) return slot2_spmv(pc, alpha, x, beta, y, s);
     if (!pc->general) return slot_spmv(pc->g, pc->A.p, alpha, x, beta, y, s);
     return sell_spmv(pc->n, pc->Asoff.p, pc->Asci.p, pc->Asv.p, alpha, x, beta, y, s);
 }
@@ -83,6 +84,7 @@ static bo_status pressure_stage(bo_cpr *pc, const double *v, const void **dp, hi
 }
 
 bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
+    if (pc->bs == 2) return cpr2_apply(pc, v, z, s);
     long long n = pc->n, npr = pc->npr;
     const Grid &g = pc->g;
     const bool mixed = pc->o.precision != BO_PREC_FP64;
@@ -134,7 +136,7 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
 // z = M^{-1} v through a HIP graph of cpr_apply captured once per setup on a
 // private stream (input and output go through fixed buffers of the handle)
 bo_status cpr_apply_graph(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
-    size_t len = 3 * (size_t)pc->n;
+    size_t len = (size_t)pc->bs * pc->n;
     if (!pc->gexec) {
         BO_TRY(pc->g_in.alloc(len));
         BO_TRY(pc->g_out.alloc(len));
@@ -348,6 +350,7 @@ extern "C" bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo
 extern "C" bo_status bo_cpr_update(bo_cpr *pc, const bo_bsr *A, void *stream) {
     if (!pc || !A || !A->rowptr || !A->colind || !A->val)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: NULL argument");
+    if (pc->bs != 3) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: a 2x2-block handle (bo_cpr2_update)");
     if (A->nbrows != pc->n) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: matrix size differs from the setup");
     if (A->nnzb != pc->nnzb) return fail(BO_ERR_INVALID_ARG, "bo_cpr_update: block count differs from the setup");
     AllocScope scope(pc->allocator(), stream);
@@ -398,6 +401,7 @@ extern "C" bo_status bo_cpr_spmv(bo_cpr *pc, double alpha, const double *x, doub
 extern "C" bo_status bo_cpr_restrict(bo_cpr *pc, const double *v, double *rp, void *stream) {
     pc = cond_inner(pc);
     if (!pc || !v || !rp) return fail(BO_ERR_INVALID_ARG, "bo_cpr_restrict: NULL argument");
+    if (pc->bs == 2) return qi2_restrict(pc, v, rp, (hipStream_t)stream);
     return qi_restrict(pc, v, rp, (hipStream_t)stream);
 }
 
@@ -411,6 +415,7 @@ extern "C" bo_status bo_cpr_vcycle(bo_cpr *pc, const double *b, double *x, void 
 extern "C" bo_status bo_cpr_fstage(bo_cpr *pc, const double *r, double *x, void *stream) {
     pc = cond_inner(pc);
     if (!pc || !r || !x) return fail(BO_ERR_INVALID_ARG, "bo_cpr_fstage: NULL argument");
+    if (pc->bs == 2) return fstage2_apply(pc, r, nullptr, x, (hipStream_t)stream);
     return fstage_apply(pc, r, nullptr, x, (hipStream_t)stream);
 }
 
@@ -459,7 +464,7 @@ extern "C" bo_status bo_cpr_copy_weights(bo_cpr *pc, double *c) {
     pc = cond_inner(pc);
     if (!pc || !c) return fail(BO_ERR_INVALID_ARG, "bo_cpr_copy_weights: NULL argument");
     BO_HIP(hipDeviceSynchronize());
-    BO_HIP(hipMemcpy(c, pc->cw.p, sizeof(double) * 3 * pc->n, hipMemcpyDeviceToHost));
+    BO_HIP(hipMemcpy(c, pc->cw.p, sizeof(double) * pc->bs * pc->n, hipMemcpyDeviceToHost));
     return BO_OK;
 }
 
@@ -468,7 +473,7 @@ namespace {
 
 bo_status krylov_alloc(bo_cpr *pc, int m) {
     Krylov &K = pc->kr;
-    long long len = 3LL * pc->n;
+    long long len = (long long)pc->bs * pc->n;
     if (K.m == m && K.len == len) return BO_OK;
     K.m = 0;
     BO_TRY(K.V.alloc((size_t)(m + 1) * len));
@@ -498,8 +503,8 @@ namespace bo {
 
 // FGMRES(m) on pc's operator.  The residual at each restart and at exit (the
 // true residual) is b - A x with the caller's BSR matrix A, or with the
-// handle's own copy when A is NULL (internal callers).
-bo_status fgmres_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
+// handle's own copy when A names none (internal callers).
+bo_status fgmres_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_fgmres_opts *opts,
                       bo_solve_stats *stats, hipStream_t s) {
     int m = opts->m;
     bo_solve_stats st{};
@@ -560,8 +565,7 @@ bo_status fgmres_core(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, c
     for (;;) {
         // r = b - A x into V[0]
         BO_HIP(hipMemcpyAsync(V, b, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
-        if (A) BO_TRY(bo_bsr_spmv(A, -1.0, x, 1.0, V, s));
-        else BO_TRY(op_spmv(pc, -1.0, x, 1.0, V, s));
+        BO_TRY(user_spmv(pc, A, -1.0, x, 1.0, V, s));
         BO_TRY(pc->red.dot(len, V, V, hd, s));
         BO_TRY(fetch(1));
         double beta = std::sqrt(hh[0]);
@@ -750,6 +754,7 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *
                                      const bo_fgmres_opts *opts, bo_solve_stats *stats, void *stream) {
     if (!pc || !A || !b || !x || !opts || !A->rowptr || !A->colind || !A->val)
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: NULL argument");
+    if (pc->bs != 3) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: a 2x2-block handle (bo_fgmres_solve2)");
     if (pc->broken) return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: the last bo_cpr_update failed");
     if (A->nbrows != pc->n || A->nnzb != pc->nnzb)
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: A is not the matrix of the last setup or update");
@@ -758,5 +763,5 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
     AllocScope scope(pc->allocator(), stream);
     if (pc->cond) return cond_solve(pc, A, b, x, opts, stats, (hipStream_t)stream, fgmres_core);
-    return fgmres_core(pc, A, b, x, opts, stats, (hipStream_t)stream);
+    return fgmres_core(pc, UserA{A, nullptr}, b, x, opts, stats, (hipStream_t)stream);
 }
