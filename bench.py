@@ -58,6 +58,11 @@ def parse():
     ap.add_argument("--fpf", type=int, default=None, choices=(0, 1),
                     help="CPR form: 1 Algorithm CPR-FPF, 0 two-stage P then F (default: FPF on workload 4, "
                          "two-stage otherwise)")
+    ap.add_argument("--model", default="blackoil", choices=("blackoil", "twophase"),
+                    help="twophase: the oil-water model (2x2 blocks) on workloads 0-2, same grids, rock, "
+                         "wells and step sequence without the gas phase")
+    ap.add_argument("--krylov", default="fgmres", choices=("fgmres", "bicgstab"),
+                    help="outer Krylov solver (BiCGSTAB: no per-SpMV timing; use --spmv-isolated)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -82,6 +87,11 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     wl = args.workload
+    twop = args.model == "twophase"
+    if twop and wl == 4:
+        print(json.dumps({"error": "the two-phase model runs on workloads 0, 1 and 2"}))
+        sys.exit(2)
+    bs = 2 if twop else 3
     nsys = args.systems or cg.N_SYSTEMS
     systems = [0] if wl == 0 else list(range(1, nsys + 1))
     log(args, f"[bench] generating workload {wl} ({len(systems)} systems)")
@@ -91,17 +101,25 @@ def main():
     c0 = None
     for k in systems:
         c = cg.make_cfg4(k, scale=args.scale) if wl == 4 else (cg.make_case(wl, k) if wl else cg.make_case(0))
-        states.append((torch.from_numpy(c.x_old).to(dev), torch.from_numpy(c.x_new).to(dev), c.dt))
+        if twop:
+            c = cg.two_phase(c)
+            states.append((torch.from_numpy(cg.state2(c.x_old)).to(dev), torch.from_numpy(cg.state2(c.x_new)).to(dev),
+                           c.dt))
+        else:
+            states.append((torch.from_numpy(c.x_old).to(dev), torch.from_numpy(c.x_new).to(dev), c.dt))
         if c0 is None:
             c0 = c
         log(args, f"[bench] generated system {k}: {c.rows} block rows")
     prob = B.problem_from_case(c0, dev)
-    n, nnzb = B.bo_jacobian_bsr_size(prob)
-    J = B.DeviceBsr(torch.empty(n + 1, dtype=torch.int32, device=dev),
-                    torch.empty(nnzb, dtype=torch.int32, device=dev),
-                    torch.empty(9 * nnzb, dtype=torch.float64, device=dev))
-    b = torch.empty(3 * n, dtype=torch.float64, device=dev)
-    x = torch.empty(3 * n, dtype=torch.float64, device=dev)
+    n, nnzb = B.bo_jacobian2_bsr_size(prob) if twop else B.bo_jacobian_bsr_size(prob)
+    J = (B.DeviceBsr2 if twop else B.DeviceBsr)(torch.empty(n + 1, dtype=torch.int32, device=dev),
+                                                torch.empty(nnzb, dtype=torch.int32, device=dev),
+                                                torch.empty(bs * bs * nnzb, dtype=torch.float64, device=dev))
+    b = torch.empty(bs * n, dtype=torch.float64, device=dev)
+    x = torch.empty(bs * n, dtype=torch.float64, device=dev)
+    if twop and args.precision != "fp64":
+        print(json.dumps({"error": "the two-phase path is FP64 only"}))
+        sys.exit(2)
     prec = {"fp64": B.BO_PREC_FP64, "fp32": B.BO_PREC_FP32, "bf16": B.BO_PREC_FP32_BF16}[args.precision]
     condensed = wl == 4 and args.form == "condensed"
     if wl == 4:
@@ -129,20 +147,24 @@ def main():
     # the preconditioner handle lives across systems, as in a Newton loop:
     # bo_cpr_update rebuilds decoupling, AMG hierarchy and ILU factors from
     # scratch for each new Jacobian and only reuses device memory
+    assemble = B.bo_jacobian2_bsr if twop else B.bo_jacobian_bsr
+    update = B.bo_cpr2_update if twop else B.bo_cpr_update
+    solve = {("fgmres", False): B.bo_fgmres_solve, ("bicgstab", False): B.bo_bicgstab_solve,
+             ("fgmres", True): B.bo_fgmres_solve2, ("bicgstab", True): B.bo_bicgstab_solve2}[(args.krylov, twop)]
     xo, xn, dt = states[0]
-    B.bo_jacobian_bsr(prob, xo, xn, dt, J, b)
-    pc = B.bo_cpr_setup(J, grid, copts)
+    assemble(prob, xo, xn, dt, J, b)
+    pc = B.bo_cpr2_setup(J, grid, copts) if twop else B.bo_cpr_setup(J, grid, copts)
 
     def step(i, record=None):
         xo, xn, dt = states[i % len(states)]
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record is not None else None
         if e: e[0].record(stream)
-        B.bo_jacobian_bsr(prob, xo, xn, dt, J, b)
+        assemble(prob, xo, xn, dt, J, b)
         if e: e[1].record(stream)
-        B.bo_cpr_update(pc, J)
+        update(pc, J)
         if e: e[2].record(stream)
         x.zero_()
-        info = B.bo_fgmres_solve(pc, J, b, x, fopts if record is None else fopts_timed)
+        info = solve(pc, J, b, x, fopts if record is None else fopts_timed)
         if e: e[3].record(stream)
         if not info["converged"]:
             raise RuntimeError(f"system {i} did not converge: {info}")
@@ -176,15 +198,18 @@ def main():
     # launch).  The condensed form's solver multiplies by the reduced system:
     # N fracture rows and the wells, without the 3 blocks per location of the
     # fracture-matrix pairs.
-    spmv_calls = sum(inf["spmv_calls"] for _, inf in rec)
-    spmv_us = 1000.0 * sum(inf["spmv_ms"] for _, inf in rec) / max(spmv_calls, 1)
+    spmv_calls = sum(inf.get("spmv_calls", 0) for _, inf in rec)
+    spmv_us = 1000.0 * sum(inf.get("spmv_ms", 0.0) for _, inf in rec) / max(spmv_calls, 1)
     op_rows = c0.n + c0.nrate if condensed else n
     op_nnzb = nnzb - 3 * c0.n if condensed else nnzb
-    spmv_bytes = 72.0 * op_nnzb + 48.0 * op_rows
-    spmv_gbs = spmv_bytes / (spmv_us * 1e-6) / 1e9
+    spmv_bytes = 8.0 * bs * bs * op_nnzb + 16.0 * bs * op_rows
+    spmv_gbs = spmv_bytes / (spmv_us * 1e-6) / 1e9 if spmv_calls else None
     spmv = {"us": spmv_us, "GBs": spmv_gbs, "bytes": spmv_bytes, "launches": spmv_calls}
     if args.spmv_isolated:
-        spmv.update(isolated_spmv(args, B, pc, op_rows, dev, stream))
+        spmv.update(isolated_spmv(args, B, pc, op_rows, dev, stream, bs))
+        if spmv_gbs is None:
+            spmv_gbs = spmv_bytes / (spmv["isolated_cold_us"] * 1e-6) / 1e9
+            spmv["GBs"] = spmv_gbs
     if args.ceiling:
         spmv.update(stream_ceiling(args, dev, stream))
     # plain copy of known size: calibrates the HBM byte counters of a profile
@@ -195,12 +220,13 @@ def main():
     torch.cuda.synchronize()
     del src, cal
     pc.close()
-    log(args, f"[bench] SpMV in the solver: {spmv_us:.1f} us avg over {spmv_calls} launches = "
-              f"{spmv_gbs:.0f} GB/s algorithmic ({spmv_bytes / 1e6:.1f} MB)")
+    if spmv_calls:
+        log(args, f"[bench] SpMV in the solver: {spmv_us:.1f} us avg over {spmv_calls} launches = "
+                  f"{spmv_gbs:.0f} GB/s algorithmic ({spmv_bytes / 1e6:.1f} MB)")
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, c0 if wl != 4 else cg.make_cfg4(1, scale=8), wl, condensed)
+        cpu = cpu_baseline(args, c0 if wl != 4 else cg.make_cfg4(1, scale=8), wl, condensed, twop)
     out = {
         "metric": METRIC,
         "value": ms_per_step / 1000.0,
@@ -218,9 +244,11 @@ def main():
         "config": {
             "workload": (f"cfg{wl}: {c0.nx}x{c0.ny}x{c0.nz} "
                          + ("dual-porosity locations with fixed-rate wells, " if wl == 4 else "")
-                         + f"black-oil 3x3-block Jacobians ({n} block rows, {3 * n} unknowns, {nnzb} blocks), "
+                         + ("two-phase oil-water 2x2-block" if twop else "black-oil 3x3-block")
+                         + f" Jacobians ({n} block rows, {bs * n} unknowns, {nnzb} blocks), "
                          + (f"{len(systems)} systems of the synthetic 30-day step sequence" if wl else "one system")),
-            "solver": ("FGMRES(30), CPR-PF: block quasi-IMPES, SA-AMG V(1,1) RB-GS/l1-Jacobi, tiled BILU0 8x8"
+            "solver": (("BiCGSTAB" if args.krylov == "bicgstab" else "FGMRES(30)")
+                       + ", CPR-PF: block quasi-IMPES, SA-AMG V(1,1) RB-GS/l1-Jacobi, tiled BILU0 8x8"
                        if wl != 4 else
                        "matrix cells eliminated exactly; FGMRES(30) on the reduced system (fracture cells and "
                        "fixed-rate wells), CPR-FPF: block quasi-IMPES over all of its rows, SA-AMG V(1,1) "
@@ -230,46 +258,62 @@ def main():
                        "SA-AMG V(1,1) l1-Jacobi, tiled BILU0 8x8 (fracture tiles, matrix cells, wells)"),
             "precision": args.precision,
             "rtol": 1e-6,
-            "step": "bo_jacobian_bsr + bo_cpr_update (full rebuild, memory reused) + bo_fgmres_solve",
+            "step": (("bo_jacobian2_bsr + bo_cpr2_update" if twop else "bo_jacobian_bsr + bo_cpr_update")
+                     + " (full rebuild, memory reused) + "
+                     + {("fgmres", False): "bo_fgmres_solve", ("bicgstab", False): "bo_bicgstab_solve",
+                        ("fgmres", True): "bo_fgmres_solve2", ("bicgstab", True): "bo_bicgstab_solve2"}[
+                         (args.krylov, twop)]),
             "parallelism": "1 GPU",
         },
         "breakdown_ms": {"assembly": asm_ms, "setup": setup_ms, "solve": solve_ms},
         "iterations": its,
         "spmv": spmv,
         "roofline": {"bound": "hbm", "achieved": spmv_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": spmv_gbs / HBM_PEAK_GBS, "traffic": spmv_traffic(wl, condensed),
-                     "traffic_unit": "B per launch", "kernel": "k_slot_spmv" if wl != 4 else "k_sell_spmv"},
+                     "frac": spmv_gbs / HBM_PEAK_GBS if spmv_gbs else None,
+                     "traffic": None if twop else spmv_traffic(wl, condensed),
+                     "traffic_unit": "B per launch",
+                     "kernel": "k_slot2_spmv" if twop else ("k_slot_spmv" if wl != 4 else "k_sell_spmv")},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "slot_spmv_cfg1_500k_hbm_traffic.md")
+# HBM traffic summaries of the timed SpMV kernels (rocprofv3 FETCH_SIZE /
+# WRITE_SIZE scaled by a 256 MiB copy), per workload: (file, source file,
+# kernel, launcher)
+TRAFFIC = {
+    (1, False): ("slot_spmv_cfg1_500k_hbm_traffic.md", "bo_linalg.hip", "k_slot_spmv(int nx", "bo_status slot_spmv("),
+    (4, True): ("sell_spmv_cfg4_condensed_32m_hbm_traffic.md", "bo_linalg.hip", "k_sell_spmv(int n",
+                "bo_status sell_spmv("),
+}
 
 
-def spmv_source_hash():
-    """sha256 over the text of k_slot_spmv and its launcher."""
-    src = open(os.path.join(ROOT, "paper_1606_00556_amd", "csrc", "bo_linalg.hip")).read()
-    k0 = src.rindex("__global__", 0, src.index("k_slot_spmv(int nx"))
+def kernel_source_hash(src_file, kernel, launcher):
+    """sha256 over the text of a kernel and its launcher (the kernel's
+    template helpers are not included)."""
+    src = open(os.path.join(ROOT, "paper_1606_00556_amd", "csrc", src_file)).read()
+    k0 = src.rindex("__global__", 0, src.index(kernel))
     k1 = src.index("\n}\n", k0) + 3
-    w0 = src.index("bo_status slot_spmv(")
+    w0 = src.index(launcher)
     w1 = src.index("\n}\n", w0) + 3
     return hashlib.sha256((src[k0:k1] + src[w0:w1]).encode()).hexdigest()
 
 
 def spmv_traffic(wl, condensed):
-    """HBM bytes per SpMV launch from the committed counter summary (rocprofv3
-    FETCH_SIZE / WRITE_SIZE scaled by a 256 MiB copy), or None once the kernel
-    source differs from the one the counters were taken of."""
-    if wl != 1:
+    """HBM bytes per SpMV launch from the committed counter summary, or None
+    where there is none or once the kernel source differs from the one the
+    counters were taken of."""
+    key = (wl, bool(condensed))
+    if key not in TRAFFIC:
         return None
+    fname, src_file, kernel, launcher = TRAFFIC[key]
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(os.path.join(ROOT, "profiles", fname)).read()
     except OSError:
         return None
     m_t = re.search(r"traffic per launch \(bytes\): (\d+)", text)
     m_h = re.search(r"kernel source sha256: ([0-9a-f]{64})", text)
-    if not (m_t and m_h) or m_h.group(1) != spmv_source_hash():
+    if not (m_t and m_h) or m_h.group(1) != kernel_source_hash(src_file, kernel, launcher):
         return None
     return float(m_t.group(1))
 
@@ -306,12 +350,12 @@ def stream_ceiling(args, dev, stream):
     return out
 
 
-def isolated_spmv(args, B, pc, n, dev, stream):
+def isolated_spmv(args, B, pc, n, dev, stream, bs=3):
     """SpMV launches outside the solver: each after a 1 GiB read-only pass
     (clean lines, nothing to write back) that evicts L2 and the 256 MB
     Infinity Cache, and back to back (matrix partly cache-resident)."""
     import torch
-    xin = torch.randn(3 * n, dtype=torch.float64, device=dev)
+    xin = torch.randn(bs * n, dtype=torch.float64, device=dev)
     yout = torch.empty_like(xin)
     flush = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     sink = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -338,15 +382,23 @@ def isolated_spmv(args, B, pc, n, dev, stream):
     return {"isolated_cold_us": cold_us, "isolated_back_to_back_us": warm_us}
 
 
-def cpu_baseline(args, case, wl, condensed):
+def cpu_baseline(args, case, wl, condensed, twop=False):
     """The FP64 oracle on the host: one system (assembly + setup + solve); for
     the dual-porosity workload on its 50x50x25-location twin."""
     from oracle import oracle as O
     log(args, "[bench] cpu baseline: oracle on one system")
     t0 = time.perf_counter()
     P = O.Problem(case)
-    rp, ci, val, R = O.jacobian(P)
-    if wl == 4 and condensed:
+    if twop:
+        from oracle import twophase as T
+        rp, ci, val, R = T.jacobian(O, P)
+        x, info = T.fgmres(O, rp, ci, val, -R, T.Cpr2(O, P, rp, ci, val))
+        rp = None
+    else:
+        rp, ci, val, R = O.jacobian(P)
+    if rp is None:
+        pass
+    elif wl == 4 and condensed:
         cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, fpf=1)
         x, info = O.condensed_fgmres(rp, ci, val, -R, cond)
     elif wl == 4:

@@ -318,6 +318,17 @@ __global__ void __launch_bounds__(64) k_ilu2_factor(Tile2 T, const double *__res
     }
 }
 
+// The sweeps walk the steps with the next step's loads in flight: its
+// factors (1 KB per load instruction), and its r (forward) or u and dp
+// (backward), are fetched into the second of two register buffers before the
+// current step's arithmetic, which waits only for the shuffled neighbour
+// values of the previous step.  Lanes idle at a step load slot 0 of the tile
+// and cell 0 (all in bounds) so that no load is skipped on some paths.
+struct Step2 {
+    double f[16];
+    double v0, v1, d;
+};
+
 // forward sweep: u (slot order) from r (cell order)
 __global__ void __launch_bounds__(64) k_ilu2_forward(Tile2 T, const double2 *__restrict__ Ff,
                                                      const double *__restrict__ r, double2 *__restrict__ U) {
@@ -329,28 +340,46 @@ __global__ void __launch_bounds__(64) k_ilu2_forward(Tile2 T, const double2 *__r
     const bool active = t < T.tx * T.ty && i < T.nx && j < T.ny;
     const bool has_mx = a > 0, has_my = b > 0;
     double up[2] = {0.0, 0.0};  // this lane's u of the previous step (the -z neighbour)
-    for (int s = 0; s < T.ns; s++) {
+    auto fetch = [&](int s, Step2 &F) {
+        const int sc = min(s, T.ns - 1);
+        const int k = sc - a - b;
+        const bool act = active && k >= 0 && k < T.nz;
+        const int tl = act ? t : 0;
+#pragma unroll
+        for (int p2 = 0; p2 < kPk2; p2++) {
+            const double2 d = Ff[pk2(T, tile, sc, p2, tl)];
+            F.f[2 * p2] = d.x;
+            F.f[2 * p2 + 1] = d.y;
+        }
+        const size_t g = act ? (size_t)i + (size_t)T.nx * ((size_t)j + (size_t)T.ny * k) : 0;
+        F.v0 = r[2 * g];
+        F.v1 = r[2 * g + 1];
+    };
+    auto step = [&](int s, const Step2 &F) {
         double ux[2], uy[2];
         shfl_k<2>(up, ux, has_mx ? t - 1 : t);
         shfl_k<2>(up, uy, has_my ? t - T.tx : t);
         const int k = s - a - b;
-        if (!(active && k >= 0 && k < T.nz)) continue;
-        const int g = i + T.nx * (j + T.ny * k);
-        double f[16];
-#pragma unroll
-        for (int p2 = 0; p2 < kPk2; p2++) {
-            const double2 d = Ff[pk2(T, tile, s, p2, t)];
-            f[2 * p2] = d.x;
-            f[2 * p2 + 1] = d.y;
-        }
-        double y0 = r[2 * (size_t)g], y1 = r[2 * (size_t)g + 1], tmp[2];
+        if (!(active && k >= 0 && k < T.nz)) return;
+        const double *f = F.f;
+        double y0 = F.v0, y1 = F.v1, tmp[2];
         if (k > 0) { mv2(f + 4, up, tmp); y0 = y0 - tmp[0]; y1 = y1 - tmp[1]; }
         if (has_my) { mv2(f + 8, uy, tmp); y0 = y0 - tmp[0]; y1 = y1 - tmp[1]; }
         if (has_mx) { mv2(f + 12, ux, tmp); y0 = y0 - tmp[0]; y1 = y1 - tmp[1]; }
         const double yv[2] = {y0, y1};
         mv2(f, yv, up);
         U[slot2(T, tile, s, t)] = make_double2(up[0], up[1]);
+    };
+    Step2 R0, R1;
+    fetch(0, R0);
+    int s0 = 0;
+    for (; s0 + 2 <= T.ns; s0 += 2) {
+        fetch(s0 + 1, R1);
+        step(s0, R0);
+        fetch(s0 + 2, R0);
+        step(s0 + 1, R1);
     }
+    if (s0 < T.ns) step(s0, R0);
 }
 
 // backward sweep: x (cell order) from u (slot order), + Pi_p dp when given
@@ -365,20 +394,30 @@ __global__ void __launch_bounds__(64) k_ilu2_backward(Tile2 T, const double2 *__
     const bool active = t < T.tx * T.ty && i < T.nx && j < T.ny;
     const bool has_px = a + 1 < T.tx && i + 1 < T.nx, has_py = b + 1 < T.ty && j + 1 < T.ny;
     double xp[2] = {0.0, 0.0};  // this lane's x of the previous (later) step: the +z neighbour
-    for (int s = T.ns - 1; s >= 0; s--) {
+    auto fetch = [&](int s, Step2 &F) {
+        const int sc = max(s, 0);
+        const int k = sc - a - b;
+        const bool act = active && k >= 0 && k < T.nz;
+        const int tl = act ? t : 0;
+#pragma unroll
+        for (int p2 = 0; p2 < kPk2; p2++) {
+            const double2 d = Fb[pk2(T, tile, sc, p2, tl)];
+            F.f[2 * p2] = d.x;
+            F.f[2 * p2 + 1] = d.y;
+        }
+        const double2 u = U[slot2(T, tile, sc, tl)];
+        F.v0 = u.x;
+        F.v1 = u.y;
+        const size_t g = act ? (size_t)i + (size_t)T.nx * ((size_t)j + (size_t)T.ny * k) : 0;
+        F.d = dp ? dp[g] : 0.0;
+    };
+    auto step = [&](int s, const Step2 &F) {
         double xx[2], xy[2];
         shfl_k<2>(xp, xx, has_px ? t + 1 : t);
         shfl_k<2>(xp, xy, has_py ? t + T.tx : t);
         const int k = s - a - b;
-        if (!(active && k >= 0 && k < T.nz)) continue;
-        const int g = i + T.nx * (j + T.ny * k);
-        double f[16];
-#pragma unroll
-        for (int p2 = 0; p2 < kPk2; p2++) {
-            const double2 d = Fb[pk2(T, tile, s, p2, t)];
-            f[2 * p2] = d.x;
-            f[2 * p2 + 1] = d.y;
-        }
+        if (!(active && k >= 0 && k < T.nz)) return;
+        const double *f = F.f;
         // sum_{j>i} A_ij x_j in ascending column order: +x, +y, +z
         double s0 = 0.0, s1 = 0.0, tmp[2];
         if (has_px) { mv2(f + 8, xx, tmp); s0 = s0 + tmp[0]; s1 = s1 + tmp[1]; }
@@ -387,12 +426,22 @@ __global__ void __launch_bounds__(64) k_ilu2_backward(Tile2 T, const double2 *__
         const double sv[2] = {s0, s1};
         double c[2];
         mv2(f, sv, c);
-        const double2 u = U[slot2(T, tile, s, t)];
-        xp[0] = u.x - c[0];
-        xp[1] = u.y - c[1];
-        x[2 * (size_t)g] = dp ? xp[0] + dp[g] : xp[0];
-        x[2 * (size_t)g + 1] = xp[1];
+        xp[0] = F.v0 - c[0];
+        xp[1] = F.v1 - c[1];
+        const size_t g = (size_t)i + (size_t)T.nx * ((size_t)j + (size_t)T.ny * k);
+        x[2 * g] = dp ? xp[0] + F.d : xp[0];
+        x[2 * g + 1] = xp[1];
+    };
+    Step2 R0, R1;
+    fetch(T.ns - 1, R0);
+    int s0 = T.ns - 1;
+    for (; s0 - 2 >= -1; s0 -= 2) {
+        fetch(s0 - 1, R1);
+        step(s0, R0);
+        fetch(s0 - 2, R0);
+        step(s0 - 1, R1);
     }
+    if (s0 >= 0) step(s0, R0);
 }
 
 Tile2 tile_geom(const bo_cpr *pc) {
