@@ -29,6 +29,9 @@ noise amplitude, as in a Newton iterate of a real run.
 * ``two_phase(case)``  the oil-water version of any single-porosity case with
   fixed-BHP wells (Section 2.2): the same grid, rock, wells and oil / water
   state, no gas (S_g = 0) and dead oil (R_s = 0).
+* ``pressure_case(nx, ny, nz)``  one scalar pressure system on a grid (the
+  paper's pure linear-solver run solves such a system): a 7-point
+  diagonally dominant M-matrix with log-normal face coefficients.
 """
 from __future__ import annotations
 
@@ -40,7 +43,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = ["Well", "Case", "FLUID", "uniform", "normal", "make_case",
-           "tiny_case", "base_seed", "N_SYSTEMS", "two_phase", "state2"]
+           "tiny_case", "base_seed", "N_SYSTEMS", "two_phase", "state2", "PressureCase", "pressure_case"]
 
 N_SYSTEMS = 10
 
@@ -354,6 +357,85 @@ def two_phase(case: Case) -> Case:
 def state2(x: np.ndarray) -> np.ndarray:
     """(Po, Sw) per cell from a three-slot state."""
     return np.ascontiguousarray(np.asarray(x).reshape(-1, 3)[:, :2].reshape(-1))
+
+
+@dataclasses.dataclass
+class PressureCase:
+    """A scalar system on an nx x ny x nz grid: coef[s, g] is the coefficient
+    of row g on its neighbour through slot s (-z, -y, -x, diagonal, +x, +y,
+    +z; 0 where the neighbour lies outside the grid), b the right-hand side."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    coef: np.ndarray   # (7, N)
+    b: np.ndarray      # (N,)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+_F_PK, _F_PACC, _F_PP = 50, 51, 52
+
+
+def pressure_case(nx: int, ny: int, nz: int, seed: int = 1606700, sigma: float = 1.5, acc: float = 1e-3,
+                  well_index: float = 10.0, name: Optional[str] = None) -> PressureCase:
+    """Seeded scalar pressure system.  Each cell draws a log-coefficient
+    z_g = sigma N(0, 1); the face between cells a and b couples them by
+    t = t_dir exp((z_a + z_b) / 2) with t_x = t_y = 1, t_z = 2.5, giving the
+    off-diagonal entries -t; the diagonal is the sum of the cell's face
+    coefficients plus an accumulation term acc * U(0.5, 1.5) and, in the
+    five-spot columns (four corner injectors at 3500 psi, a central producer
+    at 2500 psi), a well term well_index.  b = accumulation * p_old + well
+    term * bhp with p_old = 3000 (1 + 0.05 U(-1, 1)).  Generated one layer
+    of cells at a time (large grids)."""
+    n = nx * ny * nz
+    nxy = nx * ny
+    coef = np.zeros((7, n))
+    b = np.zeros(n)
+    wells = [((0, 0), 3500.0), ((nx - 1, 0), 3500.0), ((0, ny - 1), 3500.0), ((nx - 1, ny - 1), 3500.0),
+             ((nx // 2, ny // 2), 2500.0)]
+    wcol = np.zeros(nxy)
+    wbhp = np.zeros(nxy)
+    for (i, j), p in wells:
+        wcol[i + nx * j] = well_index
+        wbhp[i + nx * j] = p
+    ii = np.arange(nxy) % nx
+    jj = np.arange(nxy) // nx
+
+    def logc(k):
+        return sigma * normal(seed, _F_PK, np.arange(k * nxy, (k + 1) * nxy, dtype=np.uint64))
+
+    z_prev, z_cur = None, logc(0)
+    for k in range(nz):
+        z_next = logc(k + 1) if k + 1 < nz else None
+        g0 = k * nxy
+        diag = np.zeros(nxy)
+        # x faces (slot 2: -x, slot 4: +x), y faces (1: -y, 5: +y), z faces (0: -z, 6: +z)
+        tx = np.exp(0.5 * (z_cur[:-1] + z_cur[1:]))
+        tx[(ii[:-1] == nx - 1)] = 0.0                  # no face across a row end
+        cm = np.zeros(nxy); cm[1:] = -tx
+        cp = np.zeros(nxy); cp[:-1] = -tx
+        coef[2, g0:g0 + nxy] = cm
+        coef[4, g0:g0 + nxy] = cp
+        ty = np.exp(0.5 * (z_cur[:-nx] + z_cur[nx:])) if ny > 1 else np.zeros(0)
+        cm = np.zeros(nxy); cm[nx:] = -ty
+        cp = np.zeros(nxy); cp[:-nx] = -ty
+        coef[1, g0:g0 + nxy] = cm
+        coef[5, g0:g0 + nxy] = cp
+        if z_prev is not None:
+            coef[0, g0:g0 + nxy] = -2.5 * np.exp(0.5 * (z_prev + z_cur))
+        if z_next is not None:
+            coef[6, g0:g0 + nxy] = -2.5 * np.exp(0.5 * (z_cur + z_next))
+        a = acc * (0.5 + uniform(seed, _F_PACC, np.arange(g0, g0 + nxy, dtype=np.uint64)))
+        p_old = 3000.0 * (1.0 + 0.05 * (2.0 * uniform(seed, _F_PP, np.arange(g0, g0 + nxy, dtype=np.uint64)) - 1.0))
+        off = coef[[0, 1, 2, 4, 5, 6], g0:g0 + nxy]
+        coef[3, g0:g0 + nxy] = -off.sum(axis=0) + a + wcol
+        b[g0:g0 + nxy] = a * p_old + wcol * wbhp
+        z_prev, z_cur = z_cur, z_next
+    del ii, jj
+    return PressureCase(name or f"pressure{nx}x{ny}x{nz}", nx, ny, nz, coef, b)
 
 
 # ---- learned pressure-stage correction: seeded initial weights ---------------

@@ -243,6 +243,17 @@ void or_condense_rhs(int N, int nw, const double *b, const double *wfm, double *
 void or_condense_back(int N, int nw, const double *b, const double *xr, const double *minv, const double *amf,
                       double *x);
 
+/* Restricted additive Schwarz with ILU(0) subdomain solves on a scalar
+ * 7-point system (or_ras.c): tiles of tx x ty columns extended by `overlap`
+ * columns; coef[s * N + g] in slot order -z, -y, -x, diagonal, +x, +y, +z. */
+typedef struct or_ras or_ras;
+int or_ras_setup(int nx, int ny, int nz, const double *coef, int tx, int ty, int overlap, or_ras **out);
+int or_ras_apply(const or_ras *h, const double *r, double *z);
+void or_ras_free(or_ras *h);
+int or_ras_tiles(const or_ras *h);
+int or_ras_tile_nnz(const or_ras *h, int t);
+int or_ras_tile(const or_ras *h, int t, int32_t *cell, uint8_t *own, int32_t *rp, int32_t *ci, double *lu);
+
 #ifdef __cplusplus
 }
 #endif

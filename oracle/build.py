@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["or_physics.c", "or_linalg.c", "or_amg.c", "or_cpr.c", "or_dual.c"]
+SOURCES = ["or_physics.c", "or_linalg.c", "or_amg.c", "or_cpr.c", "or_dual.c", "or_ras.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
