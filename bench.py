@@ -58,9 +58,14 @@ def parse():
     ap.add_argument("--fpf", type=int, default=None, choices=(0, 1),
                     help="CPR form: 1 Algorithm CPR-FPF, 0 two-stage P then F (default: FPF on workload 4, "
                          "two-stage otherwise)")
-    ap.add_argument("--model", default="blackoil", choices=("blackoil", "twophase"),
+    ap.add_argument("--model", default="blackoil", choices=("blackoil", "twophase", "pressure"),
                     help="twophase: the oil-water model (2x2 blocks) on workloads 0-2, same grids, rock, "
-                         "wells and step sequence without the gas phase")
+                         "wells and step sequence without the gas phase; pressure: one scalar pressure "
+                         "system, GMRES(30) with RAS-ILU(0) for a fixed 90 iterations (see --pressure-size)")
+    ap.add_argument("--pressure-size", default="node", choices=("share", "node"),
+                    help="pressure model: 'share' 125x125x47 (3e9 / 4096 unknowns, one process's share of "
+                         "the paper's largest run) or 'node' 1000x750x500 (3e9 / 8, one GPU's share on an "
+                         "8-GPU node)")
     ap.add_argument("--krylov", default="fgmres", choices=("fgmres", "bicgstab"),
                     help="outer Krylov solver (BiCGSTAB: no per-SpMV timing; use --spmv-isolated)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -79,6 +84,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.model == "pressure":
+        return pressure_main(args)
     import numpy as np
     import torch
     import bo_casegen as cg
@@ -412,6 +419,92 @@ def cpu_baseline(args, case, wl, condensed, twop=False):
     return {"value": t1 - t0, "unit": "s", "cores": 1, "kind": "oracle",
             "sample": f"{case.name}: one of the workload's systems, Jacobian + CPR setup + FGMRES solve, "
                       f"single-threaded C oracle, {info['iterations']} iterations"}
+
+
+def pressure_main(args):
+    """One scalar pressure system solved by GMRES(30) with RAS-ILU(0) (6x6
+    tiles, overlap 1) for a fixed 90 iterations, as in the paper's
+    linear-solver run; a step = RAS setup + the 90-iteration solve."""
+    import numpy as np
+    import torch
+    import bo_casegen as cg
+    from paper_1606_00556_amd import bo as B
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    dims = {"share": (125, 125, 47), "node": (1000, 750, 500)}[args.pressure_size]
+    log(args, f"[bench] generating the pressure system {dims}")
+    c = cg.pressure_case(*dims)
+    coef = torch.from_numpy(c.coef.reshape(-1)).to(dev)
+    b = torch.from_numpy(c.b).to(dev)
+    del c.coef
+    x = torch.zeros(c.n, dtype=torch.float64, device=dev)
+    fo = B.bo_fgmres_default_opts(flexible=0, maxit=90, rtol=1e-300, timing=1)
+    ro = B.bo_ras_default_opts()
+    torch.cuda.synchronize()
+    log(args, f"[bench] uploaded {c.n} cells")
+
+    # the handle lives across steps (as across the Newton iterations of a
+    # run): bo_ras_update refactors in its memory
+    pc = B.bo_ras_setup(dims, coef, ro)
+
+    def step(record=None):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        B.bo_ras_update(pc, coef)
+        e[1].record(stream)
+        x.zero_()
+        info = B.bo_scalar_solve(pc, coef, b, x, fo)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        if info["iterations"] != 90:
+            raise RuntimeError(f"expected 90 iterations: {info}")
+        if record is not None:
+            record.append((e, info))
+        return info
+
+    for w in range(args.warmup):
+        info = step()
+        log(args, f"[bench] warmup {w}: rel residual after 90 its {info['rel_residual']:.3e}")
+    rec = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    setup_ms = sum(e[0].elapsed_time(e[1]) for e, _ in rec) / len(rec)
+    solve_ms = sum(e[1].elapsed_time(e[2]) for e, _ in rec) / len(rec)
+    calls = sum(inf["spmv_calls"] for _, inf in rec)
+    spmv_us = 1000.0 * sum(inf["spmv_ms"] for _, inf in rec) / max(calls, 1)
+    spmv_bytes = 72.0 * c.n      # 7 coefficients, x and y, 8 B each, per row
+    gbs = spmv_bytes / (spmv_us * 1e-6) / 1e9
+    log(args, f"[bench] {args.steps} steps: {ms:.1f} ms/step, setup {setup_ms:.1f}, solve {solve_ms:.1f} ms; "
+              f"SpMV {spmv_us:.1f} us = {gbs:.0f} GB/s")
+    cpu = None
+    if not args.no_cpu_baseline and args.pressure_size == "share":
+        from oracle import pressure as PR
+        c2 = cg.pressure_case(*dims)
+        t = time.perf_counter()
+        _, oi = PR.solve(c2, tile=(6, 6), overlap=1, m=30, maxit=90)
+        cpu = {"value": time.perf_counter() - t, "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"the same system, RAS setup + 90 GMRES(30) iterations (C RAS, numpy GMRES)"}
+    out = {
+        "metric": "GMRES(30)+RAS-ILU(0) time for 90 iterations on one pressure system (s)",
+        "value": ms / 1000.0, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"scalar 7-point pressure system {dims[0]}x{dims[1]}x{dims[2]} ({c.n} unknowns)",
+                   "solver": "GMRES(30), right-preconditioned, CGS2 with the second projection delayed one "
+                             "step, 90 fixed iterations; RAS 6x6 tiles, overlap 1, ILU(0) subdomain solves",
+                   "step": "bo_ras_update (refactor in place) + bo_scalar_solve", "parallelism": "1 GPU"},
+        "breakdown_ms": {"setup": setup_ms, "solve": solve_ms},
+        "rel_residual_90": rec[-1][1]["rel_residual"],
+        "spmv": {"us": spmv_us, "GBs": gbs, "bytes": spmv_bytes, "launches": calls},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_scalar_spmv"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -358,9 +358,14 @@ typedef struct {
                            setup (same kernels, same results; fewer host launches, but
                            two copies through the graph's fixed buffers per
                            application); 0: launch the kernels directly */
+    int32_t flexible;   /* 1: flexible GMRES (the preconditioned basis is kept, m more
+                           vectors); 0: standard right-preconditioned GMRES for a fixed
+                           linear preconditioner (one work vector; each restart cycle
+                           ends with x += M^{-1} (V_k y), one more application that is
+                           not counted as an iteration; not with a network attached) */
 } bo_fgmres_opts;
 
-void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, delayed CGS2 (orth 2), no timing, direct launches (graph 0) */
+void bo_fgmres_default_opts(bo_fgmres_opts *o);   /* m 30, maxit 1500, rtol 1e-6, delayed CGS2 (orth 2), no timing, direct launches (graph 0), flexible 1 */
 
 typedef struct {
     int32_t iterations;     /* preconditioner applications */
@@ -428,6 +433,47 @@ bo_status bo_bicgstab_solve2(bo_cpr *pc, const bo_bsr2 *A, const double *b, doub
  * Returns BO_OK, BO_NOT_CONVERGED, BO_ERR_BREAKDOWN or another error. */
 bo_status bo_bicgstab_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, const bo_fgmres_opts *opts,
                             bo_solve_stats *stats, void *stream);
+
+/* ---- Scalar pressure systems: GMRES with RAS (Sections 3.2, 4.2) --------
+ * A scalar system on an nx x ny x nz grid's 7-point stencil is given by its
+ * slot coefficients coef[s * N + g] (7N doubles, N = nx*ny*nz): row g's
+ * coefficient on its neighbour through slot s in the order -z, -y, -x,
+ * diagonal, +x, +y, +z, zero where the neighbour lies outside the grid.
+ * The preconditioner is restricted additive Schwarz with ILU(0) subdomain
+ * solves (the paper's RAS): tiles of tile_x x tile_y grid columns over all
+ * layers, each extended by `overlap` columns on every side inside the grid;
+ * each extended tile's matrix (couplings leaving it dropped) is factored by
+ * ILU(0) in natural order, and each tile's solve writes its own cells only. */
+typedef struct {
+    int32_t tile_x, tile_y;   /* (tile_x + 2 overlap)(tile_y + 2 overlap) <= 64 */
+    int32_t overlap;          /* >= 0 */
+} bo_ras_opts;
+void bo_ras_default_opts(bo_ras_opts *o);   /* 6x6 tiles, overlap 1 */
+
+/* y = alpha A x + beta y for the slot coefficients coef on grid (beta == 0:
+ * y is not read). */
+bo_status bo_scalar_spmv(const bo_grid *grid, const double *coef, double alpha, const double *x, double beta,
+                         double *y, void *stream);
+
+/* Builds the RAS preconditioner of the scalar system coef on grid (dual 0):
+ * a handle of block size 1 that keeps a copy of coef.  It works with
+ * bo_cpr_apply (z = M^{-1} r, N doubles), bo_cpr_spmv (the copy),
+ * bo_scalar_solve and bo_cpr_destroy.  BO_ERR_SINGULAR_BLOCK for a zero
+ * ILU(0) pivot.  Synchronises `stream`. */
+bo_status bo_ras_setup(const bo_grid *grid, const double *coef, const bo_ras_opts *opts, const bo_allocator *alloc,
+                       bo_cpr **pc, void *stream);
+
+/* Rebuilds the factors of a RAS handle for new coefficients on the same
+ * grid and options, in the handle's memory. */
+bo_status bo_ras_update(bo_cpr *pc, const double *coef, void *stream);
+
+/* GMRES(m) with the RAS handle pc on the system coef x = b (coef: the
+ * matrix of the setup; the true residual is computed from it).  opts as for
+ * bo_fgmres_solve; flexible 0 gives the standard right-preconditioned
+ * GMRES(m) of the paper's run, and a fixed number of iterations is maxit
+ * with an rtol too small to be met. */
+bo_status bo_scalar_solve(bo_cpr *pc, const double *coef, const double *b, double *x, const bo_fgmres_opts *opts,
+                          bo_solve_stats *stats, void *stream);
 
 /* ---- Inexact Newton and time steps (Section 3.1) ----------------------
  * One time step solves R(x; x_old, dt) = 0 by the inexact Newton method of

@@ -38,6 +38,7 @@ EXPORTS = [
     "bo_cpr_pressure_stencil", "bo_newton_default_opts", "bo_newton_create", "bo_newton_destroy",
     "bo_newton_solve", "bo_newton_run", "bo_bicgstab_solve", "bo_jacobian2_bsr_size", "bo_jacobian2_bsr",
     "bo_bsr2_spmv", "bo_cpr2_setup", "bo_cpr2_update", "bo_fgmres_solve2", "bo_bicgstab_solve2",
+    "bo_ras_default_opts", "bo_scalar_spmv", "bo_ras_setup", "bo_scalar_solve", "bo_ras_update",
 ]
 
 
@@ -97,7 +98,11 @@ class BoGrid(C.Structure):
 
 class BoFgmresOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("maxit", C.c_int32), ("rtol", C.c_double), ("orth", C.c_int32),
-                ("timing", C.c_int32), ("graph", C.c_int32)]
+                ("timing", C.c_int32), ("graph", C.c_int32), ("flexible", C.c_int32)]
+
+
+class BoRasOpts(C.Structure):
+    _fields_ = [("tile_x", C.c_int32), ("tile_y", C.c_int32), ("overlap", C.c_int32)]
 
 
 class BoSolveStats(C.Structure):
@@ -181,6 +186,14 @@ def lib():
     L.bo_cpr2_update.argtypes = [vp, C.POINTER(BoBsr), vp]
     for f in ("bo_fgmres_solve2", "bo_bicgstab_solve2"):
         getattr(L, f).argtypes = [vp, C.POINTER(BoBsr), vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats), vp]
+    # scalar systems with RAS
+    L.bo_ras_default_opts.argtypes = [C.POINTER(BoRasOpts)]
+    L.bo_ras_default_opts.restype = None
+    L.bo_scalar_spmv.argtypes = [C.POINTER(BoGrid), vp, C.c_double, vp, C.c_double, vp, vp]
+    L.bo_ras_setup.argtypes = [C.POINTER(BoGrid), vp, C.POINTER(BoRasOpts), C.POINTER(BoAllocator),
+                               C.POINTER(vp), vp]
+    L.bo_scalar_solve.argtypes = [vp, vp, vp, vp, C.POINTER(BoFgmresOpts), C.POINTER(BoSolveStats), vp]
+    L.bo_ras_update.argtypes = [vp, vp, vp]
     L.bo_nn_create.argtypes = [C.POINTER(vp)]
     L.bo_nn_destroy.argtypes = [vp]
     L.bo_nn_destroy.restype = None
@@ -724,3 +737,45 @@ def bo_fgmres_solve2(pc: Cpr, A: DeviceBsr2, b, x, opts: Optional[BoFgmresOpts] 
 
 def bo_bicgstab_solve2(pc: Cpr, A: DeviceBsr2, b, x, opts: Optional[BoFgmresOpts] = None, stream=None) -> dict:
     return _solve2("bo_bicgstab_solve2", pc, A, b, x, opts, stream)
+
+
+# ---- scalar pressure systems: GMRES with RAS ------------------------------------
+def bo_ras_default_opts(**overrides) -> BoRasOpts:
+    o = BoRasOpts()
+    lib().bo_ras_default_opts(C.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def bo_scalar_spmv(grid, coef, alpha: float, x, beta: float, y, stream=None):
+    g = BoGrid(*grid)
+    _check(lib().bo_scalar_spmv(C.byref(g), _ptr(coef), alpha, _ptr(x), beta, _ptr(y), _stream(stream)))
+    return y
+
+
+def bo_ras_setup(grid, coef, opts: Optional[BoRasOpts] = None, stream=None) -> Cpr:
+    """RAS-ILU(0) handle of the scalar system coef (7N device doubles) on grid."""
+    o = opts if opts is not None else bo_ras_default_opts()
+    g = BoGrid(*grid)
+    h = C.c_void_p()
+    _check(lib().bo_ras_setup(C.byref(g), _ptr(coef), C.byref(o), None, C.byref(h), _stream(stream)))
+    pc = Cpr(h.value, grid[0] * grid[1] * grid[2], bs=1)
+    pc.A = coef
+    return pc
+
+
+def bo_ras_update(pc: Cpr, coef, stream=None) -> Cpr:
+    _check(lib().bo_ras_update(pc.h, _ptr(coef), _stream(stream)))
+    pc.A = coef
+    return pc
+
+
+def bo_scalar_solve(pc: Cpr, coef, b, x, opts: Optional[BoFgmresOpts] = None, stream=None) -> dict:
+    o = opts if opts is not None else bo_fgmres_default_opts(flexible=0)
+    st = BoSolveStats()
+    rc = lib().bo_scalar_solve(pc.h, _ptr(coef), _ptr(b), _ptr(x), C.byref(o), C.byref(st), _stream(stream))
+    _check(rc, allowed=(BO_OK, BO_NOT_CONVERGED))
+    return dict(status=rc, iterations=st.iterations, restarts=st.restarts, converged=bool(st.converged),
+                rel_residual=st.rel_residual, est_residual=st.est_residual, spmv_ms=st.spmv_ms,
+                spmv_calls=st.spmv_calls)

@@ -169,5 +169,5 @@ extern "C" bo_status bo_bicgstab_solve(bo_cpr *pc, const bo_bsr *A, const double
     if (pc->nn) return fail(BO_ERR_UNSUPPORTED, "bo_bicgstab_solve: needs a linear preconditioner (no network)");
     AllocScope scope(pc->allocator(), stream);
     if (pc->cond) return cond_solve(pc, A, b, x, opts, stats, (hipStream_t)stream, bicgstab_core);
-    return bicgstab_core(pc, UserA{A, nullptr}, b, x, opts, stats, (hipStream_t)stream);
+    return bicgstab_core(pc, UserA{A, nullptr, nullptr}, b, x, opts, stats, (hipStream_t)stream);
 }

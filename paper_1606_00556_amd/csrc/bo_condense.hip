@@ -336,7 +336,7 @@ bo_status cond_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, co
         io.rtol = tol / rbn;
         io.maxit = opts->maxit - st.iterations;
         bo_solve_stats ist{};
-        bo_status rc = core(in, UserA{nullptr, nullptr}, C.rb.p, C.rx.p, &io, &ist, s);
+        bo_status rc = core(in, UserA{nullptr, nullptr, nullptr}, C.rb.p, C.rx.p, &io, &ist, s);
         st.iterations += ist.iterations;
         st.restarts += ist.restarts;
         st.spmv_ms += ist.spmv_ms;

@@ -63,8 +63,9 @@ struct SetupWork {
 
 struct Krylov {
     int m = 0;
+    int nz = 0;                   // vectors in Z (m, or 1 for the standard form)
     long long len = 0;
-    DBuf<double> V, Z;            // (m+1) x len, m x len
+    DBuf<double> V, Z;            // (m+1) x len, nz x len
     std::vector<const double *> vptr, zptr;   // host lists of the basis vectors
     DBuf<double> h;               // device scalars of two Arnoldi steps, 2m+3 each
     DBuf<double> y;               // m coefficients for the update
@@ -87,7 +88,9 @@ struct bo_cpr {
     // condensed dual-porosity form: the matrix cells eliminated exactly, the
     // CPR of the reduced system in cond->inner (every other member unused)
     bo::Condensed *cond = nullptr;
-    int bs = 3;                   // block size: 3 (black oil) or 2 (two-phase oil-water, bo_cpr2_setup)
+    int bs = 3;                   // block size: 3 (black oil), 2 (two-phase oil-water, bo_cpr2_setup) or
+                                  // 1 (a scalar system with the RAS preconditioner, bo_ras_setup)
+    int ras_overlap = 0;          // bs 1: columns by which each RAS tile is extended
     bo::Grid g{};
     int n = 0;                    // block rows (the cells of a grid)
     int npr = 0;                  // rows of the pressure system (the first npr block rows)
@@ -164,11 +167,13 @@ bo_status cpr_setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts
 bo_status cpr_check(int32_t nbrows, const bo_grid *grid, const bo_cpr_opts *opts);
 bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s);
 // The caller's matrix of a solve, for its true residual: a 3x3-block or a
-// 2x2-block BSR matrix (at most one of the two), or neither: the handle's own
-// copy of the operator.
+// 2x2-block BSR matrix, or the slot coefficients of a scalar system on the
+// handle's grid (at most one of the three), or none: the handle's own copy
+// of the operator.
 struct UserA {
     const bo_bsr *a3;
     const bo_bsr2 *a2;
+    const double *c1;
 };
 bo_status user_spmv(bo_cpr *pc, const UserA &A, double alpha, const double *x, double beta, double *y,
                     hipStream_t s);
@@ -194,4 +199,8 @@ bo_status cpr2_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s);
 bo_status slot2_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s);
 bo_status qi2_restrict(bo_cpr *pc, const double *v, double *rp, hipStream_t s);
 bo_status fstage2_apply(bo_cpr *pc, const double *r, const double *dp, double *out, hipStream_t s);
+// scalar systems (bo_ras.hip)
+bo_status scalar_spmv(const Grid &g, const double *A, double alpha, const double *x, double beta, double *y,
+                      hipStream_t s);
+bo_status ras_apply(bo_cpr *pc, const double *r, double *z, hipStream_t s);
 }  // namespace bo

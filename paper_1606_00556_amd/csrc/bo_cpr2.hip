@@ -609,6 +609,7 @@ bo_status user_spmv(bo_cpr *pc, const UserA &A, double alpha, const double *x, d
                     hipStream_t s) {
     if (A.a3) return bo_bsr_spmv(A.a3, alpha, x, beta, y, s);
     if (A.a2) return bo_bsr2_spmv(A.a2, alpha, x, beta, y, s);
+    if (A.c1) return scalar_spmv(pc->g, A.c1, alpha, x, beta, y, s);
     return op_spmv(pc, alpha, x, beta, y, s);
 }
 
@@ -678,10 +679,11 @@ extern "C" bo_status bo_fgmres_solve2(bo_cpr *pc, const bo_bsr2 *A, const double
                                       const bo_fgmres_opts *opts, bo_solve_stats *stats, void *stream) {
     BO_TRY(solve2_check("bo_fgmres_solve2", pc, A, b, x, opts));
     if (opts->m < 1 || opts->m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || opts->orth < 0 ||
-        opts->orth > 2 || (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1))
+        opts->orth > 2 || (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1) ||
+        (opts->flexible != 0 && opts->flexible != 1))
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve2: options out of range");
     AllocScope scope(pc->allocator(), stream);
-    return fgmres_core(pc, UserA{nullptr, A}, b, x, opts, stats, (hipStream_t)stream);
+    return fgmres_core(pc, UserA{nullptr, A, nullptr}, b, x, opts, stats, (hipStream_t)stream);
 }
 
 extern "C" bo_status bo_bicgstab_solve2(bo_cpr *pc, const bo_bsr2 *A, const double *b, double *x,
@@ -690,5 +692,5 @@ extern "C" bo_status bo_bicgstab_solve2(bo_cpr *pc, const bo_bsr2 *A, const doub
     if (opts->maxit < 0 || !(opts->rtol > 0.0))
         return fail(BO_ERR_INVALID_ARG, "bo_bicgstab_solve2: options out of range");
     AllocScope scope(pc->allocator(), stream);
-    return bicgstab_core(pc, UserA{nullptr, A}, b, x, opts, stats, (hipStream_t)stream);
+    return bicgstab_core(pc, UserA{nullptr, A, nullptr}, b, x, opts, stats, (hipStream_t)stream);
 }

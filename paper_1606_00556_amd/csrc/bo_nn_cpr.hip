@@ -383,7 +383,7 @@ extern "C" bo_status bo_cpr_collect_pairs(bo_cpr *pc, const double *b, int32_t n
     bo_fgmres_default_opts(&o);
     o.maxit = ncalls;  // only the first ncalls applications are needed
     bo_solve_stats st;
-    bo_status rc = fgmres_core(pc, UserA{nullptr, nullptr}, b, pc->pg_x.p, &o, &st, s);
+    bo_status rc = fgmres_core(pc, UserA{nullptr, nullptr, nullptr}, b, pc->pg_x.p, &o, &st, s);
     int rec = pc->rec_n;
     pc->rec_out = nullptr;
     pc->rec_max = pc->rec_n = 0;

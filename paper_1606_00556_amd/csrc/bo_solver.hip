@@ -40,6 +40,7 @@ bo_status nn_record(bo_cpr *pc, const T *rp, hipStream_t s);
 // y = alpha A x + beta y with the handle's copy of A (slot or BSR form)
 bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double *y, hipStream_t s) {
     if (pc->bs == 2) return slot2_spmv(pc, alpha, x, beta, y, s);
+    if (pc->bs == 1) return scalar_spmv(pc->g, pc->A.p, alpha, x, beta, y, s);
     if (!pc->general) return slot_spmv(pc->g, pc->A.p, alpha, x, beta, y, s);
     return sell_spmv(pc->n, pc->Asoff.p, pc->Asci.p, pc->Asv.p, alpha, x, beta, y, s);
 }
@@ -85,6 +86,7 @@ static bo_status pressure_stage(bo_cpr *pc, const double *v, const void **dp, hi
 
 bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     if (pc->bs == 2) return cpr2_apply(pc, v, z, s);
+    if (pc->bs == 1) return ras_apply(pc, v, z, s);
     long long n = pc->n, npr = pc->npr;
     const Grid &g = pc->g;
     const bool mixed = pc->o.precision != BO_PREC_FP64;
@@ -198,6 +200,7 @@ extern "C" void bo_fgmres_default_opts(bo_fgmres_opts *o) {
     // direct launches: the host enqueues one Arnoldi step ahead, and the
     // replayed graph's copies in and out cost more than the launches it saves
     o->graph = 0;
+    o->flexible = 1;
 }
 
 // grid == NULL: the general form (A kept as BSR; block-Jacobi F stage; the
@@ -471,13 +474,16 @@ extern "C" bo_status bo_cpr_copy_weights(bo_cpr *pc, double *c) {
 // ---- FGMRES ---------------------------------------------------------------------
 namespace {
 
-bo_status krylov_alloc(bo_cpr *pc, int m) {
+// Z holds the m preconditioned basis vectors of the flexible form, or the one
+// work vector of the standard form (flexible 0).
+bo_status krylov_alloc(bo_cpr *pc, int m, bool flexible) {
     Krylov &K = pc->kr;
     long long len = (long long)pc->bs * pc->n;
-    if (K.m == m && K.len == len) return BO_OK;
+    const int nz = flexible ? m : 1;
+    if (K.m == m && K.len == len && K.nz == nz) return BO_OK;
     K.m = 0;
     BO_TRY(K.V.alloc((size_t)(m + 1) * len));
-    BO_TRY(K.Z.alloc((size_t)m * len));
+    BO_TRY(K.Z.alloc((size_t)nz * len));
     BO_TRY(K.h.alloc(2 * (2 * (m + 1) + 1)));
     BO_TRY(K.y.alloc(m + 1));
     if (K.host) (void)hipHostFree(K.host);
@@ -489,10 +495,11 @@ bo_status krylov_alloc(bo_cpr *pc, int m) {
                          hipHostMallocCoherent | hipHostMallocMapped));
     BO_HIP(hipHostGetDevicePointer((void **)&K.host_dev, K.host, 0));
     K.vptr.resize(m + 1);
-    K.zptr.resize(m);
+    K.zptr.resize(nz);
     for (int i = 0; i <= m; i++) K.vptr[i] = K.V.p + (size_t)i * len;
-    for (int i = 0; i < m; i++) K.zptr[i] = K.Z.p + (size_t)i * len;
+    for (int i = 0; i < nz; i++) K.zptr[i] = K.Z.p + (size_t)i * len;
     K.m = m;
+    K.nz = nz;
     K.len = len;
     return BO_OK;
 }
@@ -502,8 +509,14 @@ bo_status krylov_alloc(bo_cpr *pc, int m) {
 namespace bo {
 
 // FGMRES(m) on pc's operator.  The residual at each restart and at exit (the
-// true residual) is b - A x with the caller's BSR matrix A, or with the
-// handle's own copy when A names none (internal callers).
+// true residual) is b - A x with the caller's matrix A, or with the handle's
+// own copy when A names none (internal callers).  With opts->flexible 0 it is
+// the standard right-preconditioned GMRES(m) for a fixed linear
+// preconditioner: M^{-1} v_j goes to one work vector, and each cycle ends with
+// x += M^{-1} (V_k y) (one more application, not counted as an iteration).
+// In the delayed form the preconditioner acts on the pending vectors
+// u_j = S_jj v_j + sum_{i<j} S_ij v_i, so the update is M^{-1} (V_k (S y)) with
+// the upper triangular S of the re-orthogonalisation coefficients.
 bo_status fgmres_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_fgmres_opts *opts,
                       bo_solve_stats *stats, hipStream_t s) {
     int m = opts->m;
@@ -522,7 +535,8 @@ bo_status fgmres_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_
             if (!e) BO_HIP(hipEventCreate(&e));
     for (hipEvent_t &e : pc->evf)
         if (!e) BO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    BO_TRY(krylov_alloc(pc, m));
+    const bool flexible = opts->flexible != 0;
+    BO_TRY(krylov_alloc(pc, m, flexible));
     Krylov &K = pc->kr;
     const long long len = K.len;
     // the delayed form needs at most 32 vectors per pass and 32-bit offsets,
@@ -539,6 +553,8 @@ bo_status fgmres_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_
     double *yh = K.host + 2 * hs;       // pinned update coefficients
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1);
     std::vector<double> Hr(orth == 2 ? (size_t)(m + 1) * m : 0, 0.0);  // delayed form: unrotated H
+    // standard form with the delayed re-orthogonalisation: pending vectors U = V S
+    std::vector<double> S(orth == 2 && !flexible ? (size_t)m * m : 0, 0.0);
     auto fetch = [&](int count) -> bo_status {
         BO_HIP(hipMemcpyAsync(hh, hd, sizeof(double) * count, hipMemcpyDeviceToHost, s));
         BO_HIP(hipStreamSynchronize(s));
@@ -578,6 +594,7 @@ bo_status fgmres_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_
         std::fill(gv.begin(), gv.end(), 0.0);
         gv[0] = beta;
         if (orth == 2) std::fill(Hr.begin(), Hr.end(), 0.0);
+        std::fill(S.begin(), S.end(), 0.0);
         double g0 = beta;  // delayed form: |r| in the rescaled first basis vector
         int k = 0;
         // One Arnoldi step is enqueued as: preconditioner, SpMV, orthogonalisation
@@ -587,7 +604,8 @@ bo_status fgmres_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_
         // for this one's scalars, so the GPU does not idle during the Givens
         // update; a step enqueued past convergence is discarded.
         auto enqueue_step = [&](int j) -> bo_status {
-            double *vj = V + (size_t)j * len, *zj = Z + (size_t)j * len, *w = V + (size_t)(j + 1) * len;
+            double *vj = V + (size_t)j * len, *zj = flexible ? Z + (size_t)j * len : Z;
+            double *w = V + (size_t)(j + 1) * len;
             const int p = j & 1;
             double *hdp = hd + p * hs;
             if (use_graph) BO_TRY(cpr_apply_graph(pc, vj, zj, s));
@@ -659,6 +677,10 @@ bo_status fgmres_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_
                     // was invariant one step earlier
                     k = j;
                     break;
+                }
+                if (!flexible) {
+                    S[(size_t)j * m + j] = beta_u;
+                    for (int i = 0; i < j; i++) S[(size_t)i * m + j] = hq[i];
                 }
                 if (j == 0) {
                     g0 = beta * beta_u;  // V[0] was rescaled by 1 / beta_u
@@ -735,8 +757,24 @@ bo_status fgmres_core(bo_cpr *pc, UserA A, const double *b, double *x, const bo_
             for (int q = i + 1; q < k; q++) sum -= H[(size_t)i * m + q] * yh[q];
             yh[i] = sum / H[(size_t)i * m + i];
         }
+        if (!flexible && orth == 2)
+            for (int i = 0; i < k; i++) {  // S y, row by row (row i uses y[i..k))
+                double t = 0.0;
+                for (int q = i; q < k; q++) t += S[(size_t)i * m + q] * yh[q];
+                yh[i] = t;
+            }
         BO_HIP(hipMemcpyAsync(K.y.p, yh, sizeof(double) * k, hipMemcpyHostToDevice, s));
-        BO_TRY(multiaxpy(len, K.zptr.data(), k, K.y.p, 1.0, x, s));
+        if (flexible) {
+            BO_TRY(multiaxpy(len, K.zptr.data(), k, K.y.p, 1.0, x, s));
+        } else {
+            // u = V_k y in Z, M^{-1} u in V[k] (no longer needed), x += it
+            BO_TRY(fill(len, 0.0, Z, s));
+            BO_TRY(multiaxpy(len, K.vptr.data(), k, K.y.p, 1.0, Z, s));
+            double *mu = V + (size_t)k * len;
+            if (use_graph) BO_TRY(cpr_apply_graph(pc, Z, mu, s));
+            else BO_TRY(cpr_apply(pc, Z, mu, s));
+            BO_TRY(axpby(len, 1.0, mu, 1.0, x, s));
+        }
     }
 done:
     st.iterations = its;
@@ -759,9 +797,11 @@ extern "C" bo_status bo_fgmres_solve(bo_cpr *pc, const bo_bsr *A, const double *
     if (A->nbrows != pc->n || A->nnzb != pc->nnzb)
         return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: A is not the matrix of the last setup or update");
     if (opts->m < 1 || opts->m > 64 || opts->maxit < 0 || !(opts->rtol > 0.0) || opts->orth < 0 ||
-        opts->orth > 2 || (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1))
-        return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range");
+        opts->orth > 2 || (opts->timing != 0 && opts->timing != 1) || (opts->graph != 0 && opts->graph != 1) ||
+        (opts->flexible != 0 && opts->flexible != 1) || (opts->flexible == 0 && pc->nn))
+        return fail(BO_ERR_INVALID_ARG, "bo_fgmres_solve: options out of range (the standard form needs a linear "
+                                        "preconditioner)");
     AllocScope scope(pc->allocator(), stream);
     if (pc->cond) return cond_solve(pc, A, b, x, opts, stats, (hipStream_t)stream, fgmres_core);
-    return fgmres_core(pc, UserA{A, nullptr}, b, x, opts, stats, (hipStream_t)stream);
+    return fgmres_core(pc, UserA{A, nullptr, nullptr}, b, x, opts, stats, (hipStream_t)stream);
 }
