@@ -297,6 +297,62 @@ __global__ void __launch_bounds__(kBlock) k_sell_spmv(int n, const int32_t *__re
     yi[2] = alpha * s2 + t2;
 }
 
+// r -= A Pi_p dp on the sliced layout, in place: column 0 of each block (3
+// of its 9 value arrays), dp on the block columns below npr (0 elsewhere;
+// padding blocks sit on the row's own column with zero values).
+template <typename TD>
+__global__ void __launch_bounds__(kBlock) k_sell_col0_update(int n, int npr, const int32_t *__restrict__ soff,
+                                                             const int32_t *__restrict__ sci,
+                                                             const double *__restrict__ sv,
+                                                             const TD *__restrict__ dp, double *r) {
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    const int S = row >> 6, lane = row & 63;
+    const int k0 = soff[S], K = soff[S + 1] - k0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int k = 0; k < K; k++) {
+        const int c = sci[(size_t)(k0 + k) * 64 + lane];
+        const double *blk = sv + (size_t)(k0 + k) * 9 * 64 + lane;
+        const double p = c < npr ? (double)dp[c] : 0.0;
+        s0 = s0 + __builtin_nontemporal_load(blk) * p;
+        s1 = s1 + __builtin_nontemporal_load(blk + 3 * 64) * p;
+        s2 = s2 + __builtin_nontemporal_load(blk + 6 * 64) * p;
+    }
+    double *ri = r + 3 * (size_t)row;
+    ri[0] = ri[0] - s0;
+    ri[1] = ri[1] - s1;
+    ri[2] = ri[2] - s2;
+}
+
+// r -= A Pi_p dp on the slot layout, in place (column 0 of each block)
+template <typename TD>
+__global__ void __launch_bounds__(kBlock) k_slot_col0_update(int nx, int ny, int nz, const double *__restrict__ A,
+                                                             const TD *__restrict__ dp, double *r) {
+    const int n = nx * ny * nz;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t N = (size_t)n;
+    const int nxy = nx * ny;
+    const int ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    const int nb[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
+                       ix < nx - 1 ? i + 1 : -1, iy < ny - 1 ? i + nx : -1, iz < nz - 1 ? i + nxy : -1};
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < NSLOT; q++) {
+        const int j = nb[q];
+        if (j < 0) continue;
+        const double *a = A + (size_t)q * 9 * N + i;
+        const double p = (double)dp[j];
+        s0 = s0 + a[0 * N] * p;
+        s1 = s1 + a[3 * N] * p;
+        s2 = s2 + a[6 * N] * p;
+    }
+    double *ri = r + 3 * (size_t)i;
+    ri[0] = ri[0] - s0;
+    ri[1] = ri[1] - s1;
+    ri[2] = ri[2] - s2;
+}
+
 // ---- BSR -> slot layout -------------------------------------------------------
 __global__ void k_bsr_to_slots(int nx, int ny, int nz, const int32_t *__restrict__ rp,
                                const int32_t *__restrict__ ci, const double *__restrict__ v,
@@ -773,6 +829,28 @@ bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
+
+template <typename TD>
+bo_status sell_col0_update(int n, int npr, const int32_t *soff, const int32_t *sci, const double *sv, const TD *dp,
+                           double *r, hipStream_t s) {
+    if (n <= 0) return BO_OK;
+    k_sell_col0_update<TD><<<grid_for(n), kBlock, 0, s>>>(n, npr, soff, sci, sv, dp, r);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+template bo_status sell_col0_update<double>(int, int, const int32_t *, const int32_t *, const double *,
+                                            const double *, double *, hipStream_t);
+template bo_status sell_col0_update<float>(int, int, const int32_t *, const int32_t *, const double *,
+                                           const float *, double *, hipStream_t);
+
+template <typename TD>
+bo_status slot_col0_update(const Grid &g, const double *A, const TD *dp, double *r, hipStream_t s) {
+    k_slot_col0_update<TD><<<grid_for(g.n()), kBlock, 0, s>>>(g.nx, g.ny, g.nz, A, dp, r);
+    BO_HIP(hipGetLastError());
+    return BO_OK;
+}
+template bo_status slot_col0_update<double>(const Grid &, const double *, const double *, double *, hipStream_t);
+template bo_status slot_col0_update<float>(const Grid &, const double *, const float *, double *, hipStream_t);
 
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s) {

@@ -19,6 +19,13 @@ bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double
                     const double *x, double beta, double *y, hipStream_t s);
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s);
+// r -= A Pi_p dp in place (column 0 of each block; dp FP64 or FP32), on the
+// sliced layout (dp on the block columns below npr) and on the slot layout
+template <typename TD>
+bo_status sell_col0_update(int n, int npr, const int32_t *soff, const int32_t *sci, const double *sv, const TD *dp,
+                           double *r, hipStream_t s);
+template <typename TD>
+bo_status slot_col0_update(const Grid &g, const double *A, const TD *dp, double *r, hipStream_t s);
 bo_status axpby(long long n, double a, const double *x, double b, double *y, hipStream_t s);
 bo_status fill(long long n, double v, double *y, hipStream_t s);
 // w /= sqrt(*nrm2) on the device (left unchanged when that is <= 1e-300)

@@ -120,17 +120,26 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     }
     // FPF
     BO_TRY(fstage_apply(pc, v, nullptr, z, s));
+    BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    BO_TRY(op_spmv(pc, -1.0, z, 1.0, pc->t3a.p, s));
     if (pc->o.use_amg) {
-        BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-        BO_TRY(op_spmv(pc, -1.0, z, 1.0, pc->t3a.p, s));
         const void *dp;
         BO_TRY(pressure_stage(pc, pc->t3a.p, &dp, s));
         if (mixed) k_add_p<float><<<grid_for(npr), kBlock, 0, s>>>(npr, (const float *)dp, z);
         else k_add_p<double><<<grid_for(npr), kBlock, 0, s>>>(npr, (const double *)dp, z);
         BO_HIP(hipGetLastError());
+        // v - A z for the updated z: the residual above minus A Pi_p dp (column
+        // 0 of each block only, a third of the SpMV's coefficient bytes)
+        if (pc->general) {
+            if (mixed) BO_TRY(sell_col0_update(n, npr, pc->Asoff.p, pc->Asci.p, pc->Asv.p, (const float *)dp,
+                                               pc->t3a.p, s));
+            else BO_TRY(sell_col0_update(n, npr, pc->Asoff.p, pc->Asci.p, pc->Asv.p, (const double *)dp,
+                                         pc->t3a.p, s));
+        } else {
+            if (mixed) BO_TRY(slot_col0_update(g, pc->A.p, (const float *)dp, pc->t3a.p, s));
+            else BO_TRY(slot_col0_update(g, pc->A.p, (const double *)dp, pc->t3a.p, s));
+        }
     }
-    BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-    BO_TRY(op_spmv(pc, -1.0, z, 1.0, pc->t3a.p, s));
     BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, pc->t3b.p, s));
     return axpby(3 * n, 1.0, pc->t3b.p, 1.0, z, s);
 }
