@@ -28,6 +28,18 @@ METRIC = "CPR-FGMRES time-to-solution (s) at rel. residual 1e-6; BSR SpMV HBM GB
 HBM_PEAK_GBS = 8000.0
 
 
+# The CPR configuration timed per workload: the library's defaults with the
+# smoothing and tile choices measured fastest there (the full-size parity
+# tests run the same options on both sides).  Dual porosity (condensed):
+# V(3,3) cycles, ILU tiles of 16x4 columns, CPR-FPF; single porosity: V(2,2)
+# cycles, 8x8 tiles, two-stage PF.
+BENCH_CPR = {"dual": dict(sweeps=3, tile=(16, 4), fpf=1), "grid": dict(sweeps=2, tile=(8, 8), fpf=0)}
+
+
+def bench_cpr_kw(wl):
+    return dict(BENCH_CPR["dual" if wl == 4 else "grid"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +80,9 @@ def parse():
                          "8-GPU node)")
     ap.add_argument("--krylov", default="fgmres", choices=("fgmres", "bicgstab"),
                     help="outer Krylov solver (BiCGSTAB: no per-SpMV timing; use --spmv-isolated)")
+    ap.add_argument("--sweeps", type=int, default=None, help="AMG pre- and post-smoothing sweeps (default 1)")
+    ap.add_argument("--theta", type=float, default=None, help="AMG strength threshold (default 0.08)")
+    ap.add_argument("--tile", type=int, nargs=2, default=None, help="F-stage ILU tile (default 8 8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -139,11 +154,19 @@ def main():
         grid = (c0.nx, c0.ny, c0.nz, 1)
         ft = B.BO_F_ILU_TILED if prec == B.BO_PREC_FP64 else B.BO_F_BJ
         copts = B.bo_cpr_default_opts(precision=prec, ftype=ft, smoother=B.BO_SMOOTH_L1,
-                                      npr=0 if condensed else c0.rows, fpf=1 if args.fpf is None else args.fpf,
-                                      condense=int(condensed))
+                                      npr=0 if condensed else c0.rows, condense=int(condensed))
     else:
         grid = (c0.nx, c0.ny, c0.nz)
-        copts = B.bo_cpr_default_opts(precision=prec, fpf=args.fpf or 0)
+        copts = B.bo_cpr_default_opts(precision=prec)
+    kw = bench_cpr_kw(wl)
+    copts.sweeps = kw["sweeps"]
+    copts.tile_x, copts.tile_y = kw["tile"]
+    copts.fpf = kw["fpf"] if args.fpf is None else args.fpf
+    for k, v in (("sweeps", args.sweeps), ("theta", args.theta)):
+        if v is not None:
+            setattr(copts, k, v)
+    if args.tile is not None:
+        copts.tile_x, copts.tile_y = args.tile
     fo = {"graph": args.graph}
     if args.orth is not None:
         fo["orth"] = args.orth
@@ -255,14 +278,17 @@ def main():
                          + f" Jacobians ({n} block rows, {bs * n} unknowns, {nnzb} blocks), "
                          + (f"{len(systems)} systems of the synthetic 30-day step sequence" if wl else "one system")),
             "solver": (("BiCGSTAB" if args.krylov == "bicgstab" else "FGMRES(30)")
-                       + ", CPR-PF: block quasi-IMPES, SA-AMG V(1,1) RB-GS/l1-Jacobi, tiled BILU0 8x8"
+                       + f", CPR-{'FPF' if copts.fpf else 'PF'}: block quasi-IMPES, SA-AMG V({copts.sweeps},"
+                       f"{copts.sweeps}) RB-GS/l1-Jacobi, tiled BILU0 {copts.tile_x}x{copts.tile_y}"
                        if wl != 4 else
                        "matrix cells eliminated exactly; FGMRES(30) on the reduced system (fracture cells and "
-                       "fixed-rate wells), CPR-FPF: block quasi-IMPES over all of its rows, SA-AMG V(1,1) "
-                       "l1-Jacobi, tiled BILU0 8x8 (fracture tiles, wells); true residual of the full system"
+                       f"fixed-rate wells), CPR-{'FPF' if copts.fpf else 'PF'}: block quasi-IMPES over all of its "
+                       f"rows, SA-AMG V({copts.sweeps},{copts.sweeps}) l1-Jacobi, tiled BILU0 "
+                       f"{copts.tile_x}x{copts.tile_y} (fracture tiles, wells); true residual of the full system"
                        if condensed else
                        "FGMRES(30), CPR-FPF extended grid form: block quasi-IMPES over cell and well rows, "
-                       "SA-AMG V(1,1) l1-Jacobi, tiled BILU0 8x8 (fracture tiles, matrix cells, wells)"),
+                       f"SA-AMG V({copts.sweeps},{copts.sweeps}) l1-Jacobi, tiled BILU0 {copts.tile_x}x"
+                       f"{copts.tile_y} (fracture tiles, matrix cells, wells)"),
             "precision": args.precision,
             "rtol": 1e-6,
             "step": (("bo_jacobian2_bsr + bo_cpr2_update" if twop else "bo_jacobian_bsr + bo_cpr_update")
@@ -403,16 +429,17 @@ def cpu_baseline(args, case, wl, condensed, twop=False):
         rp = None
     else:
         rp, ci, val, R = O.jacobian(P)
+    kw = bench_cpr_kw(wl)
     if rp is None:
         pass
     elif wl == 4 and condensed:
-        cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, fpf=1)
+        cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, **kw)
         x, info = O.condensed_fgmres(rp, ci, val, -R, cond)
     elif wl == 4:
-        pc = O.Cpr(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, npr=P.rows, fpf=1)
+        pc = O.Cpr(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, npr=P.rows, **kw)
         x, info = O.fgmres(rp, ci, val, -R, pc)
     else:
-        pc = O.Cpr(P, rp, ci, val)
+        pc = O.Cpr(P, rp, ci, val, **kw)
         x, info = O.fgmres(rp, ci, val, -R, pc)
     t1 = time.perf_counter()
     log(args, f"[bench] cpu baseline: {t1 - t0:.2f} s, its={info['iterations']}")

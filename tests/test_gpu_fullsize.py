@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import bo_casegen as cg
+from bench import bench_cpr_kw
 from tests.gpu_util import device_bsr, rel_err, rel_err_parts, run_stage, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -106,14 +107,23 @@ def test_fullsize_spmv(B, O, cfg):
     assert rel_err(to_host(y), ref) <= 1e-12
 
 
+def bench_opts(B, O, wl):
+    """The oracle's and the library's CPR options of bench.py's run on
+    workload wl (plain grid form)."""
+    kw = bench_cpr_kw(wl)
+    bo_ = B.bo_cpr_default_opts(sweeps=kw["sweeps"], tile_x=kw["tile"][0], tile_y=kw["tile"][1], fpf=kw["fpf"])
+    return kw, bo_
+
+
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_fullsize_cpr_apply(B, O, cfg):
-    """The default CPR (quasi-IMPES, SA-AMG V-cycle with red-black Gauss-Seidel
-    on level 0, 8x8-tile block ILU(0)) on the 500k- and 2M-cell systems,
-    whole vectors against the oracle, each unknown separately."""
+    """bench.py's CPR (quasi-IMPES, SA-AMG V-cycle with red-black Gauss-Seidel
+    on level 0, tiled block ILU(0)) on the 500k- and 2M-cell systems, whole
+    vectors against the oracle, each unknown separately."""
     case, P, rp, ci, val, b = system(O, cfg)
-    opc = O.Cpr(P, rp, ci, val)
-    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), B.bo_cpr_default_opts())
+    kw, bo_ = bench_opts(B, O, cfg)
+    opc = O.Cpr(P, rp, ci, val, **kw)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), bo_)
     assert B.bo_cpr_levels(gpc) == opc.nlevels()
     n = case.n
     v = np.random.default_rng(7).standard_normal(3 * n)
@@ -121,9 +131,10 @@ def test_fullsize_cpr_apply(B, O, cfg):
     assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, b, 3 * n), opc.apply(b)) <= 1e-10
 
 
-def _solve_and_compare(B, O, case, P, rp, ci, val, b, key=None):
+def _solve_and_compare(B, O, case, P, rp, ci, val, b, key=None, wl=1):
     import torch
-    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), B.bo_cpr_default_opts())
+    kw, bo_ = bench_opts(B, O, wl)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), bo_)
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
     info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
     assert info["converged"] and info["status"] == B.BO_OK
@@ -131,7 +142,7 @@ def _solve_and_compare(B, O, case, P, rp, ci, val, b, key=None):
     true_rel = np.linalg.norm(r) / np.linalg.norm(b)
     assert true_rel <= 1e-6
     assert info["rel_residual"] == pytest.approx(true_rel, rel=1e-6, abs=1e-12)
-    xo, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val))
+    xo, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val, **kw))
     io = oinfo["iterations"]
     if key is not None:
         _ORACLE[key] = (io, xo)
@@ -142,7 +153,7 @@ def _solve_and_compare(B, O, case, P, rp, ci, val, b, key=None):
 
 @pytest.mark.parametrize("k", range(1, 11))
 def test_fullsize_solve_500k_sequence(B, O, k):
-    """bench.py's solve (default options) on every system of the 500k-cell
+    """bench.py's solve (its options) on every system of the 500k-cell
     step sequence: converged, a true FP64 residual <= 1e-6 recomputed with the
     oracle's SpMV, and the oracle's iteration count within 10 %."""
     case, P, rp, ci, val, b = system(O, 1, k)
@@ -151,7 +162,7 @@ def test_fullsize_solve_500k_sequence(B, O, k):
 
 def test_fullsize_solve_2m(B, O):
     case, P, rp, ci, val, b = system(O, 2)
-    _solve_and_compare(B, O, case, P, rp, ci, val, b, key=2)
+    _solve_and_compare(B, O, case, P, rp, ci, val, b, key=2, wl=2)
 
 
 def test_fullsize_solve_iid_noise(B, O):
@@ -172,8 +183,10 @@ def test_fullsize_condensed_dual_twin(B, O):
     P = O.Problem(case)
     rp, ci, val, R = O.jacobian(P)
     b = -R
-    cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, fpf=1)
-    opts = B.bo_cpr_default_opts(condense=1, fpf=1, smoother=B.BO_SMOOTH_L1)
+    kw = bench_cpr_kw(4)
+    cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, **kw)
+    opts = B.bo_cpr_default_opts(condense=1, fpf=kw["fpf"], smoother=B.BO_SMOOTH_L1, sweeps=kw["sweeps"],
+                                 tile_x=kw["tile"][0], tile_y=kw["tile"][1])
     gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz, 1), opts)
     v = np.random.default_rng(9).standard_normal(3 * P.rows)
     assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * P.rows), cond.apply(v)) <= 1e-10
@@ -196,15 +209,16 @@ def test_fullsize_mixed_solve(B, O, prec):
     import torch
     case, P, rp, ci, val, b = system(O, 2)
     bp = dict(fp32=B.BO_PREC_FP32, bf16=B.BO_PREC_FP32_BF16)[prec]
-    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz),
-                         B.bo_cpr_default_opts(precision=bp))
+    kw, bo_ = bench_opts(B, O, 2)
+    bo_.precision = bp
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), bo_)
     x = torch.zeros(3 * case.n, dtype=torch.float64, device="cuda")
     info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
     assert info["converged"] and info["status"] == B.BO_OK
     r = b - O.bsr_spmv(rp, ci, val, to_host(x))
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-6
     if 2 not in _ORACLE:
-        xo, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val))
+        xo, oinfo = O.fgmres(rp, ci, val, b, O.Cpr(P, rp, ci, val, **kw))
         _ORACLE[2] = (oinfo["iterations"], xo)
     io, xo = _ORACLE[2]
     err = rel_err_parts(to_host(x), xo)
