@@ -256,7 +256,24 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, c0 if wl != 4 else cg.make_cfg4(1, scale=8), wl, condensed, twop)
+        if wl == 4:
+            # a bounded sample: the 100x100x50-location twin (1/32 of the
+            # cell rows, the same recipe), scaled by the cell ratio and by the
+            # iteration ratio (the full-size iterations are the GPU's, which
+            # equal the oracle's wherever both were run)
+            twin = cg.make_cfg4(systems[0], scale=4)
+            cpu = cpu_baseline(args, twin, wl, condensed, twop)
+            its_full = sum(its) / len(its)
+            f_cells = c0.rows / twin.rows
+            f_its = its_full / max(cpu["iterations"], 1)
+            cpu["measured_s"] = cpu["value"]
+            cpu["value"] = cpu["value"] * f_cells * f_its
+            cpu["sample"] = (f"{twin.name} (the same recipe on 100x100x50 locations, {twin.rows} rows): Jacobian "
+                             f"+ CPR setup + FGMRES solve by the single-threaded oracle, {cpu['measured_s']:.2f} s "
+                             f"for {cpu['iterations']} iterations, scaled x{f_cells:.2f} (rows) "
+                             f"x{f_its:.2f} (the GPU's mean {its_full:.1f} iterations at full size)")
+        else:
+            cpu = cpu_baseline(args, c0, wl, condensed, twop)
     out = {
         "metric": METRIC,
         "value": ms_per_step / 1000.0,
@@ -416,8 +433,8 @@ def isolated_spmv(args, B, pc, n, dev, stream, bs=3):
 
 
 def cpu_baseline(args, case, wl, condensed, twop=False):
-    """The FP64 oracle on the host: one system (assembly + setup + solve); for
-    the dual-porosity workload on its 50x50x25-location twin."""
+    """The FP64 oracle on the host: one system (assembly + setup + solve) of
+    `case` with the benchmark's CPR options."""
     from oracle import oracle as O
     log(args, "[bench] cpu baseline: oracle on one system")
     t0 = time.perf_counter()
@@ -445,7 +462,18 @@ def cpu_baseline(args, case, wl, condensed, twop=False):
     log(args, f"[bench] cpu baseline: {t1 - t0:.2f} s, its={info['iterations']}")
     return {"value": t1 - t0, "unit": "s", "cores": 1, "kind": "oracle",
             "sample": f"{case.name}: one of the workload's systems, Jacobian + CPR setup + FGMRES solve, "
-                      f"single-threaded C oracle, {info['iterations']} iterations"}
+                      f"single-threaded C oracle, {info['iterations']} iterations",
+            "iterations": info["iterations"], "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def pressure_main(args):
