@@ -149,10 +149,11 @@ def main():
         # system (fracture cells and fixed-rate wells: pressure system over all
         # of its rows, l1-Jacobi level 0, tiled ILU over the fracture tiles with
         # the wells as a class of their own), Algorithm CPR-FPF.  full: the
-        # extended grid form over all 2N cells and the wells.  The tiled ILU of
-        # these forms is FP64; the mixed forms use block Jacobi.
+        # extended grid form over all 2N cells and the wells, whose mixed forms
+        # use block Jacobi.
         grid = (c0.nx, c0.ny, c0.nz, 1)
-        ft = B.BO_F_ILU_TILED if prec == B.BO_PREC_FP64 else B.BO_F_BJ
+        # the tiled ILU's FP32 / BF16 factors need a form without matrix cells
+        ft = B.BO_F_ILU_TILED if prec == B.BO_PREC_FP64 or condensed else B.BO_F_BJ
         copts = B.bo_cpr_default_opts(precision=prec, ftype=ft, smoother=B.BO_SMOOTH_L1,
                                       npr=0 if condensed else c0.rows, condense=int(condensed))
     else:

@@ -823,12 +823,16 @@ bo_status fstage_launch(bo_cpr *pc, hipStream_t s) {
         const long long N = pc->g.n();
         const bool ext = pc->general;  // the extended grid form (extra matrix / well rows)
         if (ext) {
-            if (st != ST_F64) return fail(BO_ERR_UNSUPPORTED, "F stage: the extended grid form's ILU is FP64 only");
+            // FP32 / BF16 factors: only without matrix cells (the tiles and the
+            // well rows; a matrix cell's pivot needs its fracture cell's E^-1 in
+            // natural order, which the FP64 chain writes)
+            if (st != ST_F64 && pc->ncell > N)
+                return fail(BO_ERR_UNSUPPORTED, "F stage: with matrix cells the extended form's ILU is FP64 only");
             BO_TRY(pc->A.alloc(63 * N));
             BO_HIP(hipMemsetAsync(ff, 0, sizeof(int32_t), s));
             k_bsr_stencil_slots<<<grid_for(N), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->Arp.p, pc->Aci.p,
                                                                pc->Aval.p, pc->A.p, ff);
-            BO_TRY(pc->x_einv_f.alloc(9 * N));
+            if (st == ST_F64) BO_TRY(pc->x_einv_f.alloc(9 * N));
         }
         // factor buffers sized for FP64; the FP32 and BF16 forms use a prefix
         BO_TRY(pc->ilu_f.alloc(S * kPairs));
@@ -896,12 +900,31 @@ bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, T *
 // out = F(r) (+ Pi_p dp when dp != NULL); r in natural order
 bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, hipStream_t s) {
     if (pc->general && pc->o.ftype == BO_F_ILU_TILED) {
-        // the extended grid form (FP64): tiles of fracture cells, then matrix
-        // cells, then well rows
+        // the extended grid form: tiles of fracture cells, then matrix cells,
+        // then well rows (FP64, or FP32 / BF16 tile factors without matrix
+        // cells; the well rows' inverses stay FP64)
         if (dp) return fail(BO_ERR_INVALID_ARG, "F stage: extended form takes no pressure correction");
         TileGeom G = geom(pc);
         size_t S = (size_t)G.slots();
         const long long N = pc->g.n();
+        const int st = store_of(pc);
+        if (st != ST_F64) {
+            if (st == ST_F32) k_ilu_forward<ST_F32, float><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, r,
+                                                                                          pc->ilu_w32.p);
+            else k_ilu_forward<ST_BF16, float><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, r, pc->ilu_w32.p);
+            if (pc->n > pc->ncell) {
+                int cnt = pc->n - pc->ncell;
+                k_rows_apply<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out);
+            }
+            if (st == ST_F32)
+                k_ilu_backward<ST_F32, float, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, pc->ilu_w32.p,
+                                                                                     nullptr, out);
+            else
+                k_ilu_backward<ST_BF16, float, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, pc->ilu_w32.p,
+                                                                                      nullptr, out);
+            BO_HIP(hipGetLastError());
+            return BO_OK;
+        }
         k_ilu_forward<ST_F64, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, r, pc->ilu_w.p);
         if (pc->ncell > N)
             k_dual_forward<<<grid_for(N), kBlock, 0, s>>>((int)N, pc->ilu_slot.p, S, r, pc->x_einv_m.p, pc->x_amf.p,

@@ -294,8 +294,9 @@ bo_status bo::cpr_check(int32_t nbrows, const bo_grid *grid, const bo_cpr_opts *
     const bool general = !grid || gn != nbrows;
     if (!grid && opts->ftype != BO_F_BJ)
         return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: without a grid the F stage must be BO_F_BJ");
-    if (general && opts->ftype == BO_F_ILU_TILED && opts->precision != BO_PREC_FP64)
-        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: the extended grid form's tiled ILU is FP64 only");
+    if (general && opts->ftype == BO_F_ILU_TILED && opts->precision != BO_PREC_FP64 && (!grid || grid->dual))
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: with matrix cells the extended grid form's tiled ILU is "
+                                        "FP64 only");
     if (general && opts->use_amg && opts->smoother == BO_SMOOTH_GS)
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: red-black Gauss-Seidel needs the plain grid form");
     if (!general && opts->smoother == BO_SMOOTH_L1)

@@ -128,3 +128,39 @@ def test_condensed_rejects_non_dual_input(B, O):
     with pytest.raises(B.BoError) as e:
         B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz), B.bo_cpr_default_opts(condense=1))
     assert e.value.status == B.BO_ERR_INVALID_ARG
+
+
+TOL = {"fp32": 1e-5, "bf16": 2.0**-7}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name", ["rate_wells", "cfg4_twin8"])
+def test_condensed_mixed_matches_emulation(B, O, name, prec):
+    """The condensed form's mixed-precision forms (FP32 hierarchy with FP32 or
+    BF16-stored tile factors, FP64 well rows): the full-length application per
+    unknown against the oracle's emulation of the same form, and the solve to
+    the true FP64 residual with no more iterations than the FP64 oracle's plus
+    10 %."""
+    import torch
+    case = CASES[name]()
+    P = O.Problem(case)
+    rp, ci, val, R = O.jacobian(P)
+    b = -R
+    op = dict(fp32=O.PREC_FP32, bf16=O.PREC_FP32_BF16)[prec]
+    bp = dict(fp32=B.BO_PREC_FP32, bf16=B.BO_PREC_FP32_BF16)[prec]
+    kw = dict(fpf=1, coarse_max=40, sweeps=3, tile=(16, 4))
+    cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, precision=op, **kw)
+    opts = B.bo_cpr_default_opts(condense=1, fpf=1, smoother=B.BO_SMOOTH_L1, coarse_max=40, sweeps=3,
+                                 tile_x=16, tile_y=4, precision=bp)
+    gpc = B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz, 1), opts)
+    v = np.random.default_rng(21).standard_normal(3 * P.rows)
+    assert rel_err_parts(run_stage(B, gpc, B.bo_cpr_apply, v, 3 * P.rows), cond.apply(v)) <= TOL[prec]
+    x = torch.zeros(3 * P.rows, dtype=torch.float64, device="cuda")
+    info = B.bo_fgmres_solve(gpc, gpc.A, to_dev(b), x)
+    true_rel = np.linalg.norm(b - O.bsr_spmv(rp, ci, val, to_host(x))) / np.linalg.norm(b)
+    cond64 = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, **kw)
+    _, oinfo = O.condensed_fgmres(rp, ci, val, b, cond64)
+    io = oinfo["iterations"]
+    print(f"{name} {prec}: iterations gpu {info['iterations']} FP64 oracle {io}, true rel {true_rel:.2e}")
+    assert info["converged"] and true_rel <= 1e-6
+    assert info["iterations"] <= io + max(1, math.ceil(0.1 * io))
