@@ -5,14 +5,17 @@
 // On the 7-point stencil the grid graph has no triangles, so block ILU(0)
 // only modifies the diagonal blocks: E_i = A_ii - sum_{k<i} A_ik E_k^{-1} A_ki
 // over the lower neighbours k inside the tile (natural order: -z, -y, -x).
-// The solve is w_i = E_i^{-1}(r_i - sum_{k<i} A_ik w_k) followed by
+// The FP64 solve takes the unit-lower factors L_ik = A_ik E_k^{-1}:
+// y_i = r_i - sum_{k<i} L_ik y_k, then x_i = E_i^{-1}(y_i - sum_{j>i} A_ij x_j)
+// (27 factor values per cell forward, 36 backward).  The FP32 / BF16 forms
+// keep the blocks of A: w_i = E_i^{-1}(r_i - sum_{k<i} A_ik w_k), then
 // x_i = w_i - E_i^{-1} sum_{j>i} A_ij x_j.
 //
 // Schedule: lane t = a + tile_x*b of the tile owns grid column (i0+a, j0+b)
 // and at step s handles layer k = s - a - b, so its -x, -y and -z neighbours
 // were handled one step earlier by lanes t-1, t-tile_x and t itself.  The
 // factors are stored in the same (tile, step, lane) order, packed in pairs, so
-// each step reads its 36 doubles with 18 contiguous 1 KB loads.  Two
+// each step reads its doubles with contiguous 1 KB loads (14 or 18 of them).  Two
 // wavefronts share a tile, each loading half of the factors several steps
 // ahead and exchanging partial products through LDS (see the sweeps below).
 // Block Jacobi (x_i = A_ii^{-1} r_i) is the alternative F stage.
@@ -35,7 +38,9 @@ struct TileGeom {
 // lower blocks (-z, -y, -x) for the forward sweep, E^{-1} and the three upper
 // blocks (+z, +x, +y) for the backward sweep.  They are packed as 18 double2
 // per slot in (tile, step, pair, lane) order, so one wavefront load of a
-// pair reads 1 KB contiguously and a step needs 18 load instructions.
+// pair reads 1 KB contiguously and a step needs 18 load instructions.  In the
+// FP64 form the forward slot holds the unit-lower factors in place of the
+// lower blocks and its sweep reads pairs 4..17 only (values 8..35).
 constexpr int kPairs = 18;
 __device__ __forceinline__ size_t pk_index(int tile, int ns, int s, int pair, int lane) {
     return (((size_t)tile * ns + s) * kPairs + pair) * 64 + lane;
@@ -261,19 +266,22 @@ __global__ void __launch_bounds__(64) k_ilu_chain(TileGeom T, double2 *__restric
         const bool act = active && k >= 0 && k < T.nz;
         const double *fw = S.fw, *uw = S.uw;
         if (act) {
-            double E[9], Lk[9], tmp[9];
+            // lw: E^{-1}[8] and the unit-lower factors L_ik = A_ik E_k^{-1}
+            // (-z, -y, -x) as values 8..35 of the forward slot
+            double E[9], lw[28], tmp[9];
+            for (int z = 0; z < 28; z++) lw[z] = 0.0;
             for (int z = 0; z < 9; z++) E[z] = fw[z];
             // -z, -y, -x in ascending order (zero blocks where missing)
             if (k > 0) {
-                mul3(fw + 9, Ep, Lk); mul3(Lk, Uzp, tmp);
+                mul3(fw + 9, Ep, lw + 1); mul3(lw + 1, Uzp, tmp);
                 for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
             }
             if (has_my) {
-                mul3(fw + 18, Ey, Lk); mul3(Lk, Uy, tmp);
+                mul3(fw + 18, Ey, lw + 10); mul3(lw + 10, Uy, tmp);
                 for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
             }
             if (has_mx) {
-                mul3(fw + 27, Ex, Lk); mul3(Lk, Ux, tmp);
+                mul3(fw + 27, Ex, lw + 19); mul3(lw + 19, Ux, tmp);
                 for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
             }
             double Ei[9];
@@ -286,15 +294,17 @@ __global__ void __launch_bounds__(64) k_ilu_chain(TileGeom T, double2 *__restric
                 const int g = i + T.nx * (j + T.ny * k);
                 for (int z = 0; z < 9; z++) einv_nat[(size_t)z * N + g] = Ei[z];
             }
-            // E^{-1} into values 0..8 of both slots
+            // E^{-1} into values 0..8 of the backward slot, the lower factors
+            // over the forward slot's blocks of A (its values 0..7, A_ii, are
+            // not read again)
 #pragma unroll
-            for (int p2 = 0; p2 < 4; p2++) {
-                const double2 e = make_double2(Ei[2 * p2], Ei[2 * p2 + 1]);
-                Ff[pk_index(tile, T.ns, s, p2, t)] = e;
-                Fb[pk_index(tile, T.ns, s, p2, t)] = e;
-            }
-            ((double *)&Ff[pk_index(tile, T.ns, s, 4, t)])[0] = Ei[8];
+            for (int p2 = 0; p2 < 4; p2++)
+                Fb[pk_index(tile, T.ns, s, p2, t)] = make_double2(Ei[2 * p2], Ei[2 * p2 + 1]);
             ((double *)&Fb[pk_index(tile, T.ns, s, 4, t)])[0] = Ei[8];
+            lw[0] = Ei[8];
+#pragma unroll
+            for (int p2 = 4; p2 < kPairs; p2++)
+                Ff[pk_index(tile, T.ns, s, p2, t)] = make_double2(lw[2 * p2 - 8], lw[2 * p2 - 7]);
             // this cell's upper blocks for the next step's neighbours
             for (int z = 0; z < 9; z++) { Uzp[z] = uw[z]; Uxp[z] = uw[9 + z]; Uyp[z] = uw[18 + z]; }
         }
@@ -350,6 +360,19 @@ __device__ __forceinline__ void load_half(const void *__restrict__ F, int tile, 
     }
 }
 
+// the FP64 forward slot's -z factor (values 9..17, with value 8) into
+// p.v[8..17]: pairs 4..8 only
+__device__ __forceinline__ void load_lz(const void *__restrict__ F, int tile, int ns, int s, int t,
+                                        Half<double> &p) {
+    const double2 *D = (const double2 *)F;
+#pragma unroll
+    for (int i = 4; i < 9; i++) {
+        double2 d = D[pk_index(tile, ns, s, i, t)];
+        p.v[2 * i] = d.x;
+        p.v[2 * i + 1] = d.y;
+    }
+}
+
 // the sweep's vector operand at one slot (three arrays S apart)
 template <typename T>
 __device__ __forceinline__ void load_vec(const T *__restrict__ vec, size_t S, size_t q, T *w) {
@@ -357,8 +380,9 @@ __device__ __forceinline__ void load_vec(const T *__restrict__ vec, size_t S, si
 }
 
 // Sweeps: two wavefronts per tile.  Wavefront 0 loads the first half of each
-// slot's factors (E^{-1} and the -z block forward; E^{-1} and the +z block
-// backward) with the vector operand, wavefront 1 the second half (the -y and
+// slot's factors (E^{-1} and the -z block forward, only the -z factor in the
+// FP64 form; E^{-1} and the +z block backward) with the vector operand,
+// wavefront 1 the second half (the -y and
 // -x blocks; the +x and +y blocks), so each keeps more steps of loads in
 // flight (three and four steps ahead).  Per step, wavefront 1 multiplies its
 // blocks with the neighbours' values of the previous step (read from LDS) and
@@ -398,8 +422,10 @@ struct SweepLane {
 constexpr int kAhead0 = 4;  // wavefront 0: 9 factor + 3 vector loads and 3 stores per step
 constexpr int kAhead1 = 6;  // wavefront 1: 9 factor loads per step
 
-// forward sweep: w = E^{-1}(r - L w_lower); r (FP64) in natural order, read at
-// the slot's cell and rounded to T; w in (tile, step, lane) order
+// forward sweep: FP64: y = r - sum_lower L y_lower with the unit-lower
+// factors L_ik = A_ik E_k^{-1}; FP32 / BF16: w = E^{-1}(r - sum_lower A w_lower)
+// (w = E^{-1} y).  r (FP64) in natural order, read at the slot's cell and
+// rounded to T; the result in (tile, step, lane) order
 template <int St, typename T>
 __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__restrict__ F,
                                                      const double *__restrict__ r,
@@ -452,7 +478,8 @@ __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__r
         auto fetch = [&](int s, Half<T> &h, T *w) {
             const int sc = min(s, ns - 1);
             const bool act = L.active(G, sc);
-            load_half<St, T, 0>(F, tile, ns, sc, act ? t : 0, h);
+            if constexpr (St == ST_F64) load_lz(F, tile, ns, sc, act ? t : 0, h);
+            else load_half<St, T, 0>(F, tile, ns, sc, act ? t : 0, h);
             const double *rg = r + 3 * (act ? L.cell(G, tile, sc) : 0);
             w[0] = (T)rg[0]; w[1] = (T)rg[1]; w[2] = (T)rg[2];
         };
@@ -465,7 +492,11 @@ __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__r
                 mv3(h.v + 9, wp, y); v[0] = v[0] - y[0]; v[1] = v[1] - y[1]; v[2] = v[2] - y[2];
                 v[0] = v[0] - ysh[s & 1][0][t]; v[1] = v[1] - ysh[s & 1][1][t]; v[2] = v[2] - ysh[s & 1][2][t];
                 v[0] = v[0] - ysh[s & 1][3][t]; v[1] = v[1] - ysh[s & 1][4][t]; v[2] = v[2] - ysh[s & 1][5][t];
-                mv3(h.v, v, wp);
+                if constexpr (St == ST_F64) {
+                    wp[0] = v[0]; wp[1] = v[1]; wp[2] = v[2];
+                } else {
+                    mv3(h.v, v, wp);
+                }
             } else {
                 wp[0] = wp[1] = wp[2] = 0;
             }
@@ -490,8 +521,9 @@ __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__r
     }
 }
 
-// backward sweep: x_i = w_i - E_i^{-1} sum_{upper} A_ij x_j, written in
-// natural order as out = x + (dp, 0, 0) in FP64 (dp may be NULL)
+// backward sweep: FP64: x_i = E_i^{-1}(y_i - sum_{upper} A_ij x_j); FP32 /
+// BF16: x_i = w_i - E_i^{-1} sum_{upper} A_ij x_j; written in natural order as
+// out = x + (dp, 0, 0) in FP64 (dp may be NULL)
 template <int St, typename T, typename TD>
 __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__restrict__ F,
                                                       const T *__restrict__ wq,
@@ -560,8 +592,13 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
                 T acc[3], y[3];
                 acc[0] = ash[s & 1][0][t]; acc[1] = ash[s & 1][1][t]; acc[2] = ash[s & 1][2][t];
                 mv3(h.v + 9, xp, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
-                mv3(h.v, acc, y);
-                xp[0] = w[0] - y[0]; xp[1] = w[1] - y[1]; xp[2] = w[2] - y[2];
+                if constexpr (St == ST_F64) {
+                    y[0] = w[0] - acc[0]; y[1] = w[1] - acc[1]; y[2] = w[2] - acc[2];
+                    mv3(h.v, y, xp);
+                } else {
+                    mv3(h.v, acc, y);
+                    xp[0] = w[0] - y[0]; xp[1] = w[1] - y[1]; xp[2] = w[2] - y[2];
+                }
             } else {
                 xp[0] = xp[1] = xp[2] = 0;
             }
@@ -662,10 +699,11 @@ int store_of(const bo_cpr *pc) {
 // as one class of their own after every tile (their couplings to the cells
 // dropped, like the couplings between tiles).  A matrix cell's only lower
 // neighbour is its fracture cell, so its pivot is E_m = A_mm - (A_mf E_f^{-1})
-// A_fm, and a fracture cell's only extra upper neighbour is its matrix cell:
-//   forward   w_f (tiles),  w_m = E_m^{-1} (r_m - A_mf w_f)
-//   backward  x_m = w_m,    x_f = w_f - E_f^{-1} (A_fm x_m + sum_stencil A x)
-// The term E_f^{-1} A_fm x_m is taken out of w_f before the tile sweep.
+// A_fm, and a fracture cell's only extra upper neighbour is its matrix cell
+// (matrix cells exist in the FP64 form only):
+//   forward   y_f (tiles),  y_m = r_m - (A_mf E_f^{-1}) y_f
+//   backward  x_m = E_m^{-1} y_m,  x_f = E_f^{-1} (y_f - A_fm x_m - sum_stencil A x)
+// The term A_fm x_m is taken out of y_f before the tile's backward sweep.
 
 // stencil blocks (columns < N) of the first N rows of a BSR matrix into the
 // slot layout
@@ -745,8 +783,11 @@ __global__ void k_rows_inv(int r0, int cnt, const int32_t *__restrict__ rp, cons
     for (int z = 0; z < 9; z++) out[(size_t)z * cnt + q] = Ei[z];
 }
 
-// forward step of the matrix cells and the fracture adjustment:
-// x_m = E_m^{-1}(r_m - A_mf w_f) into out, w_f -= E_f^{-1} A_fm x_m (slot order)
+// forward step of the matrix cells and the fracture adjustment, on the FP64
+// forward result y_f (slot order): x_m = E_m^{-1}(r_m - A_mf E_f^{-1} y_f)
+// into out (the matrix cell's lower factor is A_mf E_f^{-1} and it has no
+// upper neighbour), then y_f -= A_fm x_m (the fracture cell's coupling to its
+// matrix cell, taken out before the tile's backward sweep)
 __global__ void k_dual_forward(int n, const int32_t *__restrict__ slot_of, size_t S, const double *__restrict__ r,
                                const double *__restrict__ einv_m, const double *__restrict__ amf,
                                const double *__restrict__ afm, const double *__restrict__ einv_f,
@@ -755,8 +796,10 @@ __global__ void k_dual_forward(int n, const int32_t *__restrict__ slot_of, size_
     if (g >= n) return;
     size_t N = (size_t)n;
     size_t q = (size_t)slot_of[g];
-    double wf[3] = {wq[q], wq[S + q], wq[2 * S + q]};
-    double B[9], y[3], v3[3], xm[3];
+    double yf[3] = {wq[q], wq[S + q], wq[2 * S + q]};
+    double B[9], wf[3], y[3], v3[3], xm[3];
+    for (int z = 0; z < 9; z++) B[z] = einv_f[(size_t)z * N + g];
+    mv3(B, yf, wf);
     for (int z = 0; z < 9; z++) B[z] = amf[(size_t)z * N + g];
     mv3(B, wf, y);
     for (int c = 0; c < 3; c++) v3[c] = r[3 * (N + g) + c] - y[c];
@@ -765,11 +808,9 @@ __global__ void k_dual_forward(int n, const int32_t *__restrict__ slot_of, size_
     for (int c = 0; c < 3; c++) out[3 * (N + g) + c] = xm[c];
     for (int z = 0; z < 9; z++) B[z] = afm[(size_t)z * N + g];
     mv3(B, xm, y);
-    for (int z = 0; z < 9; z++) B[z] = einv_f[(size_t)z * N + g];
-    mv3(B, y, v3);
-    wq[q] = wf[0] - v3[0];
-    wq[S + q] = wf[1] - v3[1];
-    wq[2 * S + q] = wf[2] - v3[2];
+    wq[q] = yf[0] - y[0];
+    wq[S + q] = yf[1] - y[1];
+    wq[2 * S + q] = yf[2] - y[2];
 }
 
 // well rows: x_r = E_r^{-1} r_r
