@@ -523,13 +523,25 @@ __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__r
 
 // backward sweep: FP64: x_i = E_i^{-1}(y_i - sum_{upper} A_ij x_j); FP32 /
 // BF16: x_i = w_i - E_i^{-1} sum_{upper} A_ij x_j; written in natural order as
-// out = x + (dp, 0, 0) in FP64 (dp may be NULL)
+// out = x + (dp, 0, 0) in FP64 (dp may be NULL).
+// Output staging (D > 0, D = tile_x + tile_y - 1 layers of 64 x 3 doubles in
+// dynamic LDS): lane (a, b) finishes layer k at step k + a + b, so the layers
+// in flight at step s are s .. s + D - 1 and layer s is complete once step s
+// is.  Wavefront 0 puts each result into the layer's ring slot (k mod D);
+// wavefront 1, at the start of step s - 1 (after step s's last barrier),
+// writes layer s of the tile to HBM as tile_y rows of 3 tile_x contiguous
+// doubles, and layer 0 after the last step.  A slot is next written at step
+// s - 1 after that step's first barrier, which orders it after the write-out.
+// Without staging (D == 0) every lane writes its 24 bytes at its cell, and the
+// partial lines cost HBM writes of more than twice the output's size.
 template <int St, typename T, typename TD>
 __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__restrict__ F,
                                                       const T *__restrict__ wq,
-                                                      const TD *__restrict__ dp, double *__restrict__ out) {
+                                                      const TD *__restrict__ dp, double *__restrict__ out,
+                                                      int D) {
     __shared__ T xsh[2][3][64];  // x of a step, by step parity
     __shared__ T ash[2][3][64];  // wavefront 1's U_x x_x + U_y x_y
+    extern __shared__ double obuf[];  // D slots of [lane][3]
     const int wv = threadIdx.x / 64;
     const int tile = blockIdx.x;
     const SweepLane L(G, tile, threadIdx.x % 64);
@@ -544,7 +556,22 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
             const int sc = max(s, 0);
             load_half<St, T, 1>(F, tile, ns, sc, L.active(G, sc) ? t : 0, h);
         };
+        // layer k of the tile from its ring slot to HBM
+        const int i0 = (tile % G.ntx) * G.tx, j0 = (tile / G.ntx) * G.ty;
+        const int rowlen = 3 * G.tx, tot = rowlen * G.ty;
+        auto flush = [&](int k) {
+            if (D == 0 || k >= G.nz) return;
+            const double *ob = obuf + (size_t)(k % D) * 192;
+            for (int q = t; q < tot; q += 64) {
+                const int b = q / rowlen, rem = q - b * rowlen, a = rem / 3;
+                if (i0 + a < G.nx && j0 + b < G.ny) {
+                    const size_t g0 = (size_t)i0 + (size_t)G.nx * ((size_t)(j0 + b) + (size_t)G.ny * k);
+                    out[3 * g0 + rem] = ob[3 * (a + G.tx * b) + (rem - 3 * a)];
+                }
+            }
+        };
         auto step = [&](int s, Half<T> &h) {
+            flush(s + 1);
             T xx[3] = {0, 0, 0}, xy[3] = {0, 0, 0};
             if (s < e) {
                 const int p = (s + 1) & 1;
@@ -571,6 +598,7 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
 #pragma unroll
         for (int u = 0; u < kAhead1; u++)
             if (s0 - u >= 0) step(s0 - u, buf[u]);
+        flush(0);
     } else {
         T xp[3] = {0, 0, 0};
         Half<T> buf[kAhead0];
@@ -604,10 +632,18 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
             }
             for (int c = 0; c < 3; c++) xsh[s & 1][c][t] = xp[c];
             if (L.active(G, s)) {
-                size_t g = L.cell(G, tile, s);
-                out[3 * g] = dp ? (double)d + (double)xp[0] : (double)xp[0];
-                out[3 * g + 1] = (double)xp[1];
-                out[3 * g + 2] = (double)xp[2];
+                const double o0 = dp ? (double)d + (double)xp[0] : (double)xp[0];
+                if (D > 0) {
+                    double *ob = obuf + (size_t)((s - L.a - L.b) % D) * 192 + 3 * t;
+                    ob[0] = o0;
+                    ob[1] = (double)xp[1];
+                    ob[2] = (double)xp[2];
+                } else {
+                    size_t g = L.cell(G, tile, s);
+                    out[3 * g] = o0;
+                    out[3 * g + 1] = (double)xp[1];
+                    out[3 * g + 2] = (double)xp[2];
+                }
             }
             fetch(s - kAhead0, h, w, d);
             __syncthreads();  // x of step s published
@@ -825,6 +861,15 @@ __global__ void k_rows_apply(int r0, int cnt, const double *__restrict__ inv, co
     for (int c = 0; c < 3; c++) out[3 * R + c] = o[c];
 }
 
+// the backward sweep's output staging: tile_x + tile_y - 1 layers of 64
+// cells x 3 doubles when they fit in 32 KB of LDS (tiles of 16x4, 8x8 and
+// smaller), else direct writes
+constexpr int kStageBytes = 64 * 3 * (int)sizeof(double);
+inline int stage_layers(const TileGeom &G) {
+    const int D = G.tx + G.ty - 1;
+    return D * kStageBytes <= 32768 ? D : 0;
+}
+
 TileGeom geom(const bo_cpr *pc) {
     TileGeom T;
     T.nx = pc->g.nx; T.ny = pc->g.ny; T.nz = pc->g.nz;
@@ -931,7 +976,8 @@ bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, T *
     } else {
         TileGeom G = geom(pc);
         k_ilu_forward<St, T><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, r, wq);
-        k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, wq, dp, out);
+        const int D = stage_layers(G);
+        k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 128, D * kStageBytes, s>>>(G, pc->ilu_b.p, wq, dp, out, D);
     }
     BO_HIP(hipGetLastError());
     return BO_OK;
@@ -957,12 +1003,13 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
                 int cnt = pc->n - pc->ncell;
                 k_rows_apply<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out);
             }
+            const int D = stage_layers(G);
             if (st == ST_F32)
-                k_ilu_backward<ST_F32, float, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, pc->ilu_w32.p,
-                                                                                     nullptr, out);
+                k_ilu_backward<ST_F32, float, double><<<G.ntx * G.nty, 128, D * kStageBytes, s>>>(
+                    G, pc->ilu_b.p, pc->ilu_w32.p, nullptr, out, D);
             else
-                k_ilu_backward<ST_BF16, float, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p, pc->ilu_w32.p,
-                                                                                      nullptr, out);
+                k_ilu_backward<ST_BF16, float, double><<<G.ntx * G.nty, 128, D * kStageBytes, s>>>(
+                    G, pc->ilu_b.p, pc->ilu_w32.p, nullptr, out, D);
             BO_HIP(hipGetLastError());
             return BO_OK;
         }
@@ -974,8 +1021,9 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
             int cnt = pc->n - pc->ncell;
             k_rows_apply<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out);
         }
-        k_ilu_backward<ST_F64, double, double><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_b.p,
-                                                                             pc->ilu_w.p, nullptr, out);
+        const int D = stage_layers(G);
+        k_ilu_backward<ST_F64, double, double><<<G.ntx * G.nty, 128, D * kStageBytes, s>>>(
+            G, pc->ilu_b.p, pc->ilu_w.p, nullptr, out, D);
         BO_HIP(hipGetLastError());
         return BO_OK;
     }
