@@ -21,6 +21,7 @@
 // grid (or damped Jacobi), coarser levels damped Jacobi (omega 2/3), coarsest
 // level by the dense inverse.
 #include <cstring>
+#include <functional>
 #include "bo_cpr.hpp"
 
 namespace bo {
@@ -123,12 +124,26 @@ __global__ void k_app_fill(int npr, const int32_t *__restrict__ rp, const int32_
     if (i >= npr) return;
     double c0 = cw[3 * (size_t)i], c1 = cw[3 * (size_t)i + 1], c2 = cw[3 * (size_t)i + 2];
     int o = prp[i];
-    for (int e = rp[i]; e < rp[i + 1]; e++) {
-        if (ci[e] >= npr) continue;
-        const double *A = val + 9 * (size_t)e;
-        pci[o] = ci[e];
-        pv[o] = c0 * A[0] + c1 * A[3] + c2 * A[6];
-        o++;
+    // batches of kB blocks, all loads of a batch issued together
+    constexpr int kB = 8;
+    const int b0 = rp[i], b1 = rp[i + 1];
+    for (int e0 = b0; e0 < b1; e0 += kB) {
+        int cc[kB];
+        double a0[kB], a3[kB], a6[kB];
+#pragma unroll
+        for (int k = 0; k < kB; k++) {
+            const int e = min(e0 + k, b1 - 1);
+            const double *A = val + 9 * (size_t)e;
+            cc[k] = ci[e];
+            a0[k] = A[0]; a3[k] = A[3]; a6[k] = A[6];
+        }
+#pragma unroll
+        for (int k = 0; k < kB; k++)
+            if (e0 + k < b1 && cc[k] < npr) {
+                pci[o] = cc[k];
+                pv[o] = c0 * a0[k] + c1 * a3[k] + c2 * a6[k];
+                o++;
+            }
     }
 }
 
@@ -255,7 +270,16 @@ __global__ void k_mis_init(int n, const int32_t *__restrict__ rp, const uint8_t 
     if (i < kMisWords) words[i] = 0;
     if (i >= n) return;
     int deg = 0;
-    for (int e = rp[i]; e < rp[i + 1]; e++) deg += sf[e];
+    constexpr int kB = 8;
+    const int b0 = rp[i], b1 = rp[i + 1];
+    for (int e0 = b0; e0 < b1; e0 += kB) {
+        uint8_t f[kB];
+#pragma unroll
+        for (int k = 0; k < kB; k++) f[k] = sf[min(e0 + k, b1 - 1)];
+#pragma unroll
+        for (int k = 0; k < kB; k++)
+            if (e0 + k < b1) deg += f[k];
+    }
     state[i] = deg ? UND : ISO;
 }
 
@@ -1801,7 +1825,17 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     return BO_OK;
 }
 
-bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
+// after_l0 (may be NULL) is called once on the host when level 0's
+// aggregates have been enqueued (or when the hierarchy stops at level 0):
+// work that competes for HBM with level 0's strength and MIS-2 passes can be
+// started then, beside the products that follow.
+bo_status amg_setup(bo_cpr *pc, hipStream_t s, const std::function<bo_status()> &after_l0) {
+    bool forked = false;
+    auto fork = [&]() -> bo_status {
+        if (forked || !after_l0) return BO_OK;
+        forked = true;
+        return after_l0();
+    };
     const bo_cpr_opts &o = pc->o;
     int32_t *flag = pc->flag.p;
     // level 0: CSR with the stencil pattern (the general form built it with
@@ -1916,6 +1950,7 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
                                               W.dfl.p + 1);
         BO_HIP(hipGetLastError());
         L.nc = nc;
+        if (l == 0) BO_TRY(fork());
         // prolongator
         DBuf<double> &aF = W.aF;
         DBuf<unsigned long long> &rho = W.rho;
@@ -1971,6 +2006,7 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s) {
                       (double)apnnz / n));
     }
     pc->nlev = l + 1;
+    BO_TRY(fork());
     // sliced copies of the large matrices the cycle applies row by row
     const int sell_min = o.sell_rows > 0 ? o.sell_rows : kSellRows;
     for (int q = 0; q + 1 < pc->nlev; q++) {

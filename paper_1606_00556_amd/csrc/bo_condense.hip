@@ -28,8 +28,7 @@ struct Condensed {
     int N = 0, nw = 0, nr = 0;       // locations, fixed-rate wells, reduced rows (N + nw)
     long long nfull = 0;             // block rows of the full system (2N + nw)
     int nnz = 0;                     // blocks of the reduced system
-    DBuf<int32_t> srp, sci, src;     // reduced BSR pattern; src: the full block each reduced block copies
-    DBuf<double> sval;
+    DBuf<int32_t> src;               // the full block each reduced block copies
     DBuf<double> W, minv, amf;       // 9 x N each
     DBuf<double> rb, rx, rfull;      // reduced right-hand side and solution, full residual
     DBuf<int32_t> flag;
@@ -225,10 +224,19 @@ bo_status cond_setup(bo_cpr *pc, const bo_bsr *A, const bo_grid *grid, const bo_
     C.nr = nr;
     C.nfull = A->nbrows;
     C.nnz = A->nnzb - (int)(3 * N);
-    BO_TRY(C.srp.alloc((size_t)nr + 1));
-    BO_TRY(C.sci.alloc(C.nnz));
+    if (!C.inner) {
+        C.inner = new (std::nothrow) bo_cpr();
+        if (!C.inner) return fail(BO_ERR_ALLOC, "bo_cpr_setup: out of host memory");
+    }
+    // the reduced BSR matrix is built in the inner handle's own operator
+    // buffers (its setup then takes it without a copy)
+    bo_cpr *in = C.inner;
+    BO_TRY(in->Arp.alloc((size_t)nr + 1));
+    BO_TRY(in->Aci.alloc(C.nnz));
+    BO_TRY(in->Aval.alloc(9 * (size_t)C.nnz));
+    int32_t *const srp = in->Arp.p, *const sci = in->Aci.p;
+    double *const sval = in->Aval.p;
     BO_TRY(C.src.alloc(C.nnz));
-    BO_TRY(C.sval.alloc(9 * (size_t)C.nnz));
     BO_TRY(C.W.alloc(9 * (size_t)N));
     BO_TRY(C.minv.alloc(9 * (size_t)N));
     BO_TRY(C.amf.alloc(9 * (size_t)N));
@@ -238,28 +246,23 @@ bo_status cond_setup(bo_cpr *pc, const bo_bsr *A, const bo_grid *grid, const bo_
     BO_TRY(C.flag.alloc(1));
     BO_TRY(C.nrm.alloc(1));
     // pattern (its counts staged in sci before the column indices overwrite them)
-    k_cond_counts<<<grid_for(nr), kBlock, 0, s>>>(C.N, nr, A->rowptr, C.sci.p);
+    k_cond_counts<<<grid_for(nr), kBlock, 0, s>>>(C.N, nr, A->rowptr, sci);
     BO_HIP(hipGetLastError());
     int32_t total = 0;
-    BO_TRY(scan_counts(C.sci.p, C.srp.p, nr, &total, s));
+    BO_TRY(scan_counts(sci, srp, nr, &total, s));
     if (total != C.nnz) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: not a dual-porosity pattern (block count)");
     BO_HIP(hipMemsetAsync(C.flag.p, 0, sizeof(int32_t), s));
-    k_cond_pattern<<<grid_for(nr), kBlock, 0, s>>>(C.N, nr, A->rowptr, A->colind, C.srp.p, C.sci.p, C.src.p,
-                                                    C.flag.p);
-    k_cond_copy<<<grid_for(9LL * C.nnz), kBlock, 0, s>>>(9LL * C.nnz, C.src.p, A->val, C.sval.p);
-    k_cond_pivots<<<grid_for(N), kBlock, 0, s>>>(C.N, A->rowptr, A->colind, A->val, C.srp.p, C.sci.p, C.sval.p,
-                                                 C.W.p, C.minv.p, C.amf.p, C.flag.p);
+    k_cond_pattern<<<grid_for(nr), kBlock, 0, s>>>(C.N, nr, A->rowptr, A->colind, srp, sci, C.src.p, C.flag.p);
+    k_cond_copy<<<grid_for(9LL * C.nnz), kBlock, 0, s>>>(9LL * C.nnz, C.src.p, A->val, sval);
+    k_cond_pivots<<<grid_for(N), kBlock, 0, s>>>(C.N, A->rowptr, A->colind, A->val, srp, sci, sval, C.W.p,
+                                                 C.minv.p, C.amf.p, C.flag.p);
     BO_HIP(hipGetLastError());
     int32_t bad = 0;
     HostRead rd{C.flag.p, sizeof bad, &bad};
     BO_TRY(host_reads(&rd, 1, s));
     if (bad == 1) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: not a dual-porosity pattern");
     if (bad == 2) return fail(BO_ERR_SINGULAR_BLOCK, "bo_cpr_setup: a matrix cell's diagonal block is singular");
-    bo_bsr S{nr, C.nnz, C.srp.p, C.sci.p, C.sval.p};
-    if (!C.inner) {
-        C.inner = new (std::nothrow) bo_cpr();
-        if (!C.inner) return fail(BO_ERR_ALLOC, "bo_cpr_setup: out of host memory");
-    }
+    bo_bsr S{nr, C.nnz, srp, sci, sval};
     bo_status st = cpr_setup_impl(&S, &g0, &io, C.inner, s);
     C.inner->broken = st != BO_OK;
     return st;

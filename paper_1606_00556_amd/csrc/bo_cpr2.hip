@@ -29,10 +29,11 @@
 // CPR-FPF: x = F(v); x += Pi_p V(Pi_r (v - A x)); x += F(v - A x).
 // FP64 throughout.
 #include <cmath>
+#include <functional>
 #include "bo_cpr.hpp"
 
 namespace bo {
-bo_status amg_setup(bo_cpr *pc, hipStream_t s);
+bo_status amg_setup(bo_cpr *pc, hipStream_t s, const std::function<bo_status()> &after_l0);
 bo_status amg_vcycle_ptr(bo_cpr *pc, const double *b, const double **res, hipStream_t s);
 
 namespace {
@@ -593,7 +594,7 @@ static bo_status cpr2_setup_impl(const bo_bsr2 *A, const bo_grid *grid, const bo
     BO_HIP(hipGetLastError());
     BO_TRY(read_flag(pc, s, &bad));
     if (bad) return fail(BO_ERR_SINGULAR_BLOCK, "bo_cpr2_setup: a singular 2x2 pivot block in the F stage");
-    if (pc->o.use_amg) BO_TRY(amg_setup(pc, s));
+    if (pc->o.use_amg) BO_TRY(amg_setup(pc, s, nullptr));
     BO_TRY(pc->rp_.alloc(n));
     BO_TRY(pc->dp_.alloc(n));
     BO_TRY(pc->t3a.alloc(2 * n));

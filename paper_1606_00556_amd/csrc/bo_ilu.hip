@@ -217,6 +217,78 @@ __global__ void __launch_bounds__(kBlock) k_ilu_pack(TileGeom T, const double *_
     slot_of[g] = (int32_t)q;
 }
 
+// The same pack straight from a BSR matrix whose first N block rows are the
+// grid's cells, each row's stencil blocks first in ascending column order
+// (the extended grid form; later columns, matrix cells or wells, follow):
+// the thread reads its cell's row (contiguous blocks) instead of 63 slot
+// planes.  A stencil neighbour missing from the row raises *bad.
+__global__ void __launch_bounds__(kBlock) k_ilu_pack_bsr(TileGeom T, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci,
+                                                         const double *__restrict__ v, double2 *__restrict__ Ff,
+                                                         double2 *__restrict__ Fb, int32_t *__restrict__ slot_of,
+                                                         int32_t *__restrict__ bad) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= T.slots()) return;
+    const int t = (int)(q % 64);
+    const long long ts = q / 64;
+    const int s = (int)(ts % T.ns), tile = (int)(ts / T.ns);
+    const int a = t % T.tx, b = t / T.tx;
+    const int ti = tile % T.ntx, tj = tile / T.ntx;
+    const int i = ti * T.tx + a, j = tj * T.ty + b, k = s - a - b;
+    if (!(t < T.tx * T.ty && i < T.nx && j < T.ny && k >= 0 && k < T.nz)) return;  // idle slot
+    const int g = i + T.nx * (j + T.ny * k);
+    // grid neighbours present (slot order) and the blocks the tile keeps
+    const unsigned have = (k > 0 ? 1u << S_MZ : 0u) | (j > 0 ? 1u << S_MY : 0u) | (i > 0 ? 1u << S_MX : 0u) |
+                          (1u << S_D) | (i + 1 < T.nx ? 1u << S_PX : 0u) | (j + 1 < T.ny ? 1u << S_PY : 0u) |
+                          (k + 1 < T.nz ? 1u << S_PZ : 0u);
+    const unsigned keep = (k > 0 ? 1u << S_MZ : 0u) | (b > 0 ? 1u << S_MY : 0u) | (a > 0 ? 1u << S_MX : 0u) |
+                          (1u << S_D) | (a + 1 < T.tx && i + 1 < T.nx ? 1u << S_PX : 0u) |
+                          (b + 1 < T.ty && j + 1 < T.ny ? 1u << S_PY : 0u) | (k + 1 < T.nz ? 1u << S_PZ : 0u);
+    const int e0 = rp[g], e1 = rp[g + 1];
+    const int nxy = T.nx * T.ny;
+    const int nb[NSLOT] = {g - nxy, g - T.nx, g - 1, g, g + 1, g + T.nx, g + nxy};
+    int pos[NSLOT];
+    int c[NSLOT];
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; sl++) {
+        pos[sl] = e0 + __popc(have & ((1u << sl) - 1u));
+        c[sl] = (have >> sl) & 1u ? ci[min(pos[sl], e1 - 1)] : -1;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int sl = 0; sl < NSLOT; sl++)
+        if ((have >> sl) & 1u) ok = ok && pos[sl] < e1 && c[sl] == nb[sl];
+    if (!ok) {
+        *bad = 1;
+        return;
+    }
+    // fw = [A_ii | -z | -y | -x], bw[9..35] = [+z | +x | +y]; zero blocks outside the tile
+    const int fsl[4] = {S_D, S_MZ, S_MY, S_MX}, bsl[3] = {S_PZ, S_PX, S_PY};
+    double fw[36], bw[27];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const bool k_ = (keep >> fsl[u]) & 1u;
+        const double *src = v + 9 * (size_t)(k_ ? pos[fsl[u]] : e0);
+#pragma unroll
+        for (int z = 0; z < 9; z++) fw[9 * u + z] = k_ ? src[z] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+        const bool k_ = (keep >> bsl[u]) & 1u;
+        const double *src = v + 9 * (size_t)(k_ ? pos[bsl[u]] : e0);
+#pragma unroll
+        for (int z = 0; z < 9; z++) bw[9 * u + z] = k_ ? src[z] : 0.0;
+    }
+#pragma unroll
+    for (int p2 = 0; p2 < kPairs; p2++) {
+        Ff[pk_index(tile, T.ns, s, p2, t)] = make_double2(fw[2 * p2], fw[2 * p2 + 1]);
+        if (p2 >= 5) Fb[pk_index(tile, T.ns, s, p2, t)] = make_double2(bw[2 * p2 - 9], bw[2 * p2 - 8]);
+    }
+    // pair 4 of the backward slot: (E^{-1}[8], +z[0]); the chain writes E^{-1}
+    Fb[pk_index(tile, T.ns, s, 4, t)] = make_double2(0.0, bw[0]);
+    slot_of[g] = (int32_t)q;
+}
+
 __global__ void __launch_bounds__(64) k_ilu_chain(TileGeom T, double2 *__restrict__ Ff, double2 *__restrict__ Fb,
                                                   int32_t *__restrict__ bad, double *__restrict__ einv_nat) {
     int t = threadIdx.x;
@@ -914,10 +986,13 @@ bo_status fstage_launch(bo_cpr *pc, hipStream_t s) {
             // natural order, which the FP64 chain writes)
             if (st != ST_F64 && pc->ncell > N)
                 return fail(BO_ERR_UNSUPPORTED, "F stage: with matrix cells the extended form's ILU is FP64 only");
-            BO_TRY(pc->A.alloc(63 * N));
-            BO_HIP(hipMemsetAsync(ff, 0, sizeof(int32_t), s));
-            k_bsr_stencil_slots<<<grid_for(N), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->Arp.p, pc->Aci.p,
-                                                               pc->Aval.p, pc->A.p, ff);
+            // the FP64 pack reads the BSR rows itself; the FP32 / BF16
+            // factorisation takes the slot layout
+            if (st != ST_F64) {
+                BO_TRY(pc->A.alloc(63 * N));
+                k_bsr_stencil_slots<<<grid_for(N), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->Arp.p,
+                                                                   pc->Aci.p, pc->Aval.p, pc->A.p, ff);
+            }
             if (st == ST_F64) BO_TRY(pc->x_einv_f.alloc(9 * N));
         }
         // factor buffers sized for FP64; the FP32 and BF16 forms use a prefix
@@ -929,8 +1004,13 @@ bo_status fstage_launch(bo_cpr *pc, hipStream_t s) {
         // idle slots are never read by the sweeps: their factors stay unset
         int nb = T.ntx * T.nty;
         if (st == ST_F64) {
-            k_ilu_pack<<<grid_for(T.slots()), kBlock, 0, s>>>(T, pc->A.p, (double2 *)pc->ilu_f.p,
-                                                              (double2 *)pc->ilu_b.p, pc->ilu_slot.p);
+            if (ext)
+                k_ilu_pack_bsr<<<grid_for(T.slots()), kBlock, 0, s>>>(T, pc->Arp.p, pc->Aci.p, pc->Aval.p,
+                                                                      (double2 *)pc->ilu_f.p, (double2 *)pc->ilu_b.p,
+                                                                      pc->ilu_slot.p, ff);
+            else
+                k_ilu_pack<<<grid_for(T.slots()), kBlock, 0, s>>>(T, pc->A.p, (double2 *)pc->ilu_f.p,
+                                                                  (double2 *)pc->ilu_b.p, pc->ilu_slot.p);
             k_ilu_chain<<<nb, 64, 0, s>>>(T, (double2 *)pc->ilu_f.p, (double2 *)pc->ilu_b.p, ff,
                                           ext ? pc->x_einv_f.p : nullptr);
         } else if (st == ST_F32) {

@@ -17,12 +17,13 @@
 // solve run on the host.
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include "bo_cpr.hpp"
 
 namespace bo {
 bo_status qi_decouple(bo_cpr *pc, hipStream_t s);
 bo_status qi_restrict(bo_cpr *pc, const double *v, double *rp, hipStream_t s);
-bo_status amg_setup(bo_cpr *pc, hipStream_t s);
+bo_status amg_setup(bo_cpr *pc, hipStream_t s, const std::function<bo_status()> &after_l0);
 bo_status amg_vcycle(bo_cpr *pc, const double *b, double *x, hipStream_t s);
 bo_status amg_vcycle_ptr(bo_cpr *pc, const double *b, const double **res, hipStream_t s);
 bo_status amg_vcycle_ptr_f32(bo_cpr *pc, const float *b, const float **res, hipStream_t s);
@@ -243,27 +244,46 @@ bo_status bo::cpr_setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_
         BO_TRY(pc->Arp.alloc(n + 1));
         BO_TRY(pc->Aci.alloc(A->nnzb));
         BO_TRY(pc->Aval.alloc(9 * (size_t)A->nnzb));
-        BO_HIP(hipMemcpyAsync(pc->Arp.p, A->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
-        BO_HIP(hipMemcpyAsync(pc->Aci.p, A->colind, sizeof(int32_t) * A->nnzb, hipMemcpyDeviceToDevice, s));
-        BO_HIP(hipMemcpyAsync(pc->Aval.p, A->val, sizeof(double) * 9 * (size_t)A->nnzb, hipMemcpyDeviceToDevice, s));
+        // (a matrix already in these buffers, the condensed form's reduced
+        // system, is not copied)
+        if (A->rowptr != pc->Arp.p)
+            BO_HIP(hipMemcpyAsync(pc->Arp.p, A->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+        if (A->colind != pc->Aci.p)
+            BO_HIP(hipMemcpyAsync(pc->Aci.p, A->colind, sizeof(int32_t) * A->nnzb, hipMemcpyDeviceToDevice, s));
+        if (A->val != pc->Aval.p)
+            BO_HIP(hipMemcpyAsync(pc->Aval.p, A->val, sizeof(double) * 9 * (size_t)A->nnzb, hipMemcpyDeviceToDevice,
+                                  s));
         BO_TRY(sell_build(n, pc->Arp.p, pc->Aci.p, pc->Aval.p, pc->Asoff, pc->Asci, pc->Asv, s));
     } else {
         BO_TRY(bsr_to_slots(pc->g, A->rowptr, A->colind, A->val, pc->A.p, s));
     }
     BO_TRY(qi_decouple(pc, s));
     // The F stage's factors depend on A alone: they are built on a second
-    // stream, forked from s here and joined back below, while the AMG setup
-    // (many small launches and a few host reads) runs on s.
+    // stream, forked from s and joined back below, while the AMG setup (many
+    // small launches and a few host reads) runs on s.  The fork waits for
+    // level 0's aggregates: the factorisation's HBM traffic would otherwise
+    // slow level 0's strength and MIS-2 passes, and the Galerkin products that
+    // follow are bound by LDS hashing rather than HBM.
     if (!pc->side) BO_HIP(hipStreamCreateWithFlags(&pc->side, hipStreamNonBlocking));
     for (hipEvent_t &e : pc->evs)
         if (!e) BO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    BO_HIP(hipEventRecord(pc->evs[0], s));
-    BO_HIP(hipStreamWaitEvent(pc->side, pc->evs[0], 0));
-    bo_status fst = fstage_launch(pc, pc->side);
+    bool forked = false;
+    bo_status fst = BO_OK;
+    auto fork = [&]() -> bo_status {
+        forked = true;
+        BO_HIP(hipEventRecord(pc->evs[0], s));
+        BO_HIP(hipStreamWaitEvent(pc->side, pc->evs[0], 0));
+        fst = fstage_launch(pc, pc->side);
+        return fst;
+    };
     bo_status ast = BO_OK;
-    if (fst == BO_OK && pc->o.use_amg) {
-        ast = amg_setup(pc, s);
+    if (pc->o.use_amg) {
+        ast = amg_setup(pc, s, fork);
         if (ast == BO_OK && pc->o.precision != BO_PREC_FP64) ast = amg_make_f32(pc, s);
+    }
+    if (!forked) {
+        const bo_status e = fork();
+        if (ast == BO_OK && e != BO_OK && fst == BO_OK) fst = e;
     }
     // join on every path: nothing may still run on the side stream when this returns
     BO_HIP(hipEventRecord(pc->evs[1], pc->side));
