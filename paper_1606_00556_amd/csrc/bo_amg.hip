@@ -807,15 +807,19 @@ __global__ void __launch_bounds__(kBlock) k_sort_rows(int n, const int32_t *__re
 // accumulated in ascending k exactly as in a row-by-row Gustavson product.
 // The distinct columns are then compacted, ranked (sorted) and written.
 
-// products of each row (sum of the B row lengths it touches); their maximum
-// and the number of rows above kLongProducts go to the reduction words
-// stat[0..kRedSlots) and stat[kRedSlots..2 kRedSlots)
+// products of each row (sum of the B row lengths it touches) and five
+// reductions over the rows, kRedSlots words each (one atomic per workgroup):
+// [0] the largest product count, [1] rows above kLongProducts, [2] rows above
+// kVeryLongProducts, [3] the largest count at or below kLongProducts, [4] the
+// largest count at or below kVeryLongProducts
 constexpr int kLongProducts = 128;
+constexpr int kVeryLongProducts = 512;
+constexpr int kBoundWords = 5;
 __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *__restrict__ arp,
                                                          const int32_t *__restrict__ aci,
                                                          const int32_t *__restrict__ brp, int32_t *__restrict__ prod,
                                                          int32_t *__restrict__ stat) {
-    __shared__ int wmax[kBlock / 64], wlng[kBlock / 64];
+    __shared__ int wred[kBoundWords][kBlock / 64];
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int c = 0;
     if (i < n) {
@@ -835,18 +839,33 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *_
         }
         prod[i] = c;
     }
-    int lng = c > kLongProducts ? 1 : 0;
+    int r[kBoundWords] = {c, c > kLongProducts ? 1 : 0, c > kVeryLongProducts ? 1 : 0,
+                          c <= kLongProducts ? c : 0, c <= kVeryLongProducts ? c : 0};
     for (int off = 32; off > 0; off >>= 1) {
-        c = max(c, __shfl_xor(c, off, 64));
-        lng += __shfl_xor(lng, off, 64);
+        r[0] = max(r[0], __shfl_xor(r[0], off, 64));
+        r[1] += __shfl_xor(r[1], off, 64);
+        r[2] += __shfl_xor(r[2], off, 64);
+        r[3] = max(r[3], __shfl_xor(r[3], off, 64));
+        r[4] = max(r[4], __shfl_xor(r[4], off, 64));
     }
-    if (threadIdx.x % 64 == 0) { wmax[threadIdx.x / 64] = c; wlng[threadIdx.x / 64] = lng; }
+    if (threadIdx.x % 64 == 0)
+        for (int q = 0; q < kBoundWords; q++) wred[q][threadIdx.x / 64] = r[q];
     __syncthreads();
     if (threadIdx.x == 0) {
-        int m = 0, l = 0;
-        for (int w = 0; w < (int)(blockDim.x / 64); w++) { m = max(m, wmax[w]); l += wlng[w]; }
-        if (m > 0) atomicMax(&stat[blockIdx.x % kRedSlots], m);
-        if (l > 0) atomicAdd(&stat[kRedSlots + blockIdx.x % kRedSlots], l);
+        int m[kBoundWords] = {0, 0, 0, 0, 0};
+        for (int w = 0; w < (int)(blockDim.x / 64); w++) {
+            m[0] = max(m[0], wred[0][w]);
+            m[1] += wred[1][w];
+            m[2] += wred[2][w];
+            m[3] = max(m[3], wred[3][w]);
+            m[4] = max(m[4], wred[4][w]);
+        }
+        const int slot = blockIdx.x % kRedSlots;
+        if (m[0] > 0) atomicMax(&stat[slot], m[0]);
+        if (m[1] > 0) atomicAdd(&stat[kRedSlots + slot], m[1]);
+        if (m[2] > 0) atomicAdd(&stat[2 * kRedSlots + slot], m[2]);
+        if (m[3] > 0) atomicMax(&stat[3 * kRedSlots + slot], m[3]);
+        if (m[4] > 0) atomicMax(&stat[4 * kRedSlots + slot], m[4]);
     }
 }
 
@@ -1697,10 +1716,13 @@ __global__ void k_omega(const unsigned long long *__restrict__ rho_bits, double 
     }
 }
 
-// C = A B, counting pass, prefix sum, numeric pass.  The hash of a row must
-// hold twice its products: rows are sized by the longest row unless a few
-// rows (a well through many layers) are much longer than the rest; then the
-// others take the 256-slot hash and the long rows a launch of their own.
+// C = A B, counting pass, prefix sum, numeric pass.  The counting hash of a
+// row must hold twice its products: rows are sized by the longest row unless
+// a few rows (under 1 %: a well through many layers, the aggregates next to
+// it) have more than 512 or more than 128 products; then the others take a
+// hash sized for the longest of them and the long rows a launch of their
+// own.  Each launch's numeric pass sizes its hash from the largest distinct
+// count its own rows had.
 static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const double *av, const int32_t *brp,
                         const int32_t *bci, const double *bv, DBuf<int32_t> &crp, DBuf<int32_t> &cci,
                         DBuf<double> &cv, int *cnnz, SetupWork &W, hipStream_t s, double bavg) {
@@ -1711,40 +1733,51 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     BO_TRY(cnt.alloc(n));
     BO_TRY(crp.alloc(n + 1));
     BO_TRY(W.sg_prod.alloc(n));
-    // [0, 2 kRedSlots): reduction words of the product bound and the long-row
-    // count, then the long-row list position, the largest distinct count and
-    // the hash-capacity flag (one clear for all of them)
-    constexpr int kPos = 2 * kRedSlots, kMaxl = 2 * kRedSlots + 1, kBad = 2 * kRedSlots + 2;
+    // [0, kBoundWords kRedSlots): reduction words of k_spgemm_bound, then
+    // the long-row list position, the largest distinct counts of the rows
+    // launched together and of the long rows, and the hash-capacity flag
+    // (one clear for all of them)
+    constexpr int kPos = kBoundWords * kRedSlots, kMaxl = kPos + 1, kMaxlLong = kPos + 2, kBad = kPos + 3;
     BO_TRY(W.sg_stat.alloc(kBad + 1));
     BO_HIP(hipMemsetAsync(W.sg_stat.p, 0, sizeof(int32_t) * (kBad + 1), s));
     int32_t *const bflag = W.sg_stat.p + kBad;
     k_spgemm_bound<<<grid_for(n), kBlock, 0, s>>>(n, arp, aci, brp, W.sg_prod.p, W.sg_stat.p);
-    int32_t stat[2 * kRedSlots] = {};
+    int32_t stat[kBoundWords * kRedSlots] = {};
     HostRead rd{W.sg_stat.p, sizeof stat, stat};
     BO_TRY(host_reads(&rd, 1, s));
-    int bound = 0, nlong = 0;
+    int red[kBoundWords] = {0, 0, 0, 0, 0};
     for (int q = 0; q < kRedSlots; q++) {
-        bound = std::max(bound, stat[q]);
-        nlong += stat[kRedSlots + q];
+        red[0] = std::max(red[0], stat[q]);
+        red[1] += stat[kRedSlots + q];
+        red[2] += stat[2 * kRedSlots + q];
+        red[3] = std::max(red[3], stat[3 * kRedSlots + q]);
+        red[4] = std::max(red[4], stat[4 * kRedSlots + q]);
     }
+    const int bound = red[0];
     // counting pass: lanes per row and hash slots from the row's products
     auto pick = [](int b) { return b <= 32 ? 0 : b <= 64 ? 4 : b <= 128 ? 1 : b <= 512 ? 2 : 3; };
     auto count_slots = [](int sel) { return sel == 0 ? 64 : sel == 4 ? 128 : sel == 1 ? 256 : sel == 2 ? 1024 : 2048; };
-    // split when the long rows are few (below 1 %)
-    const bool split = bound > kLongProducts && (long long)nlong * 100 < n;
-    const int sel_all = split ? pick(kLongProducts) : pick(bound), sel_long = pick(bound);
+    // split when the long rows are few (below 1 %): at 128 products if
+    // possible, else at 512
+    int limit = 0, nlong = 0, bound_rest = bound;
+    if (bound > kLongProducts && (long long)red[1] * 100 < n) {
+        limit = kLongProducts; nlong = red[1]; bound_rest = red[3];
+    } else if (bound > kVeryLongProducts && (long long)red[2] * 100 < n) {
+        limit = kVeryLongProducts; nlong = red[2]; bound_rest = red[4];
+    }
+    const bool split = limit > 0;
+    const int sel_all = pick(bound_rest), sel_long = pick(bound);
     const int32_t *prod = split ? W.sg_prod.p : nullptr;
     if (split) {
         BO_TRY(W.sg_rows.alloc(nlong));
-        k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, W.sg_prod.p, kLongProducts, W.sg_rows.p,
-                                                           W.sg_stat.p + kPos);
+        k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, W.sg_prod.p, limit, W.sg_rows.p, W.sg_stat.p + kPos);
     }
-    auto count = [&](int sel, int rn, const int32_t *rows, const int32_t *pr) {
+    auto count = [&](int sel, int rn, const int32_t *rows, const int32_t *pr, int32_t *maxl) {
         if (rn <= 0) return;
 #define BO_SPGEMM_COUNT(G, H)                                                                                 \
     k_spgemm<G, H, false><<<grid_for((long long)rn * G), 256, 0, s>>>(rn, arp, aci, av, brp, bci, bv, cnt.p, \
                                                                       nullptr, nullptr, nullptr, bflag, rows, \
-                                                                      pr, W.sg_stat.p + kMaxl, kLongProducts)
+                                                                      pr, maxl, limit)
         switch (sel) {
         case 0: BO_SPGEMM_COUNT(8, 64); break;
         case 4: BO_SPGEMM_COUNT(8, 128); break;
@@ -1754,12 +1787,13 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         }
 #undef BO_SPGEMM_COUNT
     };
-    count(sel_all, n, nullptr, prod);
-    if (split) count(sel_long, nlong, W.sg_rows.p, nullptr);
+    count(sel_all, n, nullptr, prod, W.sg_stat.p + kMaxl);
+    if (split) count(sel_long, nlong, W.sg_rows.p, nullptr, W.sg_stat.p + kMaxlLong);
     BO_HIP(hipGetLastError());
-    int32_t bad = 0, total = 0, lmax = 0;
-    HostRead ex[2] = {{bflag, sizeof bad, &bad}, {W.sg_stat.p + kMaxl, sizeof lmax, &lmax}};
-    BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s, ex, 2));
+    int32_t bad = 0, total = 0, lmax = 0, lmax_long = 0;
+    HostRead ex[3] = {{bflag, sizeof bad, &bad}, {W.sg_stat.p + kMaxl, sizeof lmax, &lmax},
+                      {W.sg_stat.p + kMaxlLong, sizeof lmax_long, &lmax_long}};
+    BO_TRY(scan_counts(cnt.p, crp.p, n, &total, s, ex, 3));
     if (bad) return fail(BO_ERR_UNSUPPORTED, "AMG: Galerkin product row exceeds the LDS hash capacity");
     BO_TRY(cci.alloc(total));
     BO_TRY(cv.alloc(total));
@@ -1817,8 +1851,8 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         numeric(sel_all, n, nullptr, cnt.p, kFewDistinct, kFewDistinct);
         numeric(sel_all, nbig, W.sg_rows.p, nullptr, 0, lmax);
     } else {
-        numeric(sel_all, n, nullptr, prod, kLongProducts, lmax);
-        if (split) numeric(sel_long, nlong, W.sg_rows.p, nullptr, 0, lmax);
+        numeric(sel_all, n, nullptr, prod, limit, lmax);
+        if (split) numeric(sel_long, nlong, W.sg_rows.p, nullptr, 0, lmax_long);
     }
     BO_HIP(hipGetLastError());
     *cnnz = total;
