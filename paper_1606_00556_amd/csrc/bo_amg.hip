@@ -1467,22 +1467,54 @@ __global__ void __launch_bounds__(kBlock) k_csr_l1_resid(int n, const int32_t *_
 // row each (a level of 11M rows with 40 entries a row streamed at about 2
 // TB/s).  The row sums run in entry order.
 constexpr int kSellRows = 1 << 20;
-__global__ void k_csr_slice_width(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ w64) {
-    int S = blockIdx.x * blockDim.x + threadIdx.x;
-    int nsl = (n + 63) / 64;
-    if (S >= nsl) return;
-    int r0 = 64 * S, r1 = min(n, r0 + 64), w = 0;
-    for (int r = r0; r < r1; r++) w = max(w, rp[r + 1] - rp[r]);
-    w64[S] = 64 * w;
+// the width of each slice (times 64): its longest row, or in a stencil slice
+// (a grid's cell rows, see SellGrid) 7 + the most entries a row has beyond
+// its stencil neighbours
+// (a wavefront per slice: one lane per row, the maximum by shuffles)
+__global__ void k_csr_slice_width(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                  SellGrid G, int32_t *__restrict__ w64) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x, S = r / 64;
+    int len = 0;
+    if (r < n) {
+        len = rp[r + 1] - rp[r];
+        if (sell_stencil_slice(G, S)) {
+            int nb[NSLOT], extra = 0;
+            sell_stencil_nbrs(G, r, nb);
+            for (int e = rp[r]; e < rp[r + 1]; e++) extra += sell_slot_in(nb, ci[e]) < 0;
+            len = NSLOT + extra;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+    if (threadIdx.x % 64 == 0 && 64 * S < n) w64[S] = 64 * len;
 }
 __global__ void k_csr_sell_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                const double *__restrict__ v, const int32_t *__restrict__ off,
+                                const double *__restrict__ v, const int32_t *__restrict__ off, SellGrid G,
                                 int32_t *__restrict__ col, double *__restrict__ val) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const int S = r / 64, lane = r % 64;
     const int base = off[S] + lane, w = (off[S + 1] - off[S]) / 64;
     const int b = rp[r], len = rp[r + 1] - b;
+    if (sell_stencil_slice(G, S)) {
+        // stencil positions (zero where the row lacks the entry) on their
+        // implicit columns, then the other entries; padding on the row's own
+        // column
+        for (int p = 0; p < w; p++) {
+            col[base + 64 * p] = p < NSLOT ? sell_stencil_col(G, r, p, n) : r;
+            val[base + 64 * p] = 0.0;
+        }
+        int nb[NSLOT];
+        sell_stencil_nbrs(G, r, nb);
+        int next = NSLOT;
+        for (int q = 0; q < len; q++) {
+            const int c = ci[b + q];
+            int p = sell_slot_in(nb, c);
+            if (p < 0) p = next++;
+            col[base + 64 * p] = c;
+            val[base + 64 * p] = v[b + q];
+        }
+        return;
+    }
     // padding: the row's first column (a valid index of x for rectangular
     // P and R too; column 0 for an empty row) with value 0
     const int pad = len > 0 ? ci[b] : 0;
@@ -1495,15 +1527,28 @@ __global__ void k_csr_sell_fill(int n, const int32_t *__restrict__ rp, const int
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_sell_rowop(int n, const int32_t *__restrict__ off,
                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
-                                                       const T *__restrict__ x, int op, const T *__restrict__ b,
-                                                       const T *__restrict__ dl1, T *__restrict__ y) {
+                                                       SellGrid G, const T *__restrict__ x, int op,
+                                                       const T *__restrict__ b, const T *__restrict__ dl1,
+                                                       T *__restrict__ y) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const int S = r / 64, lane = r % 64;
     const int base = off[S] + lane, w = (off[S + 1] - off[S]) / 64;
     T s = 0;
+    int p0 = 0;
+    if (sell_stencil_slice(G, S)) {
+        // the stencil positions: columns from the row index, loads issued together
+        T a[NSLOT], xv[NSLOT];
+#pragma unroll
+        for (int p = 0; p < NSLOT; p++) a[p] = val[base + 64 * p];
+#pragma unroll
+        for (int p = 0; p < NSLOT; p++) xv[p] = x[sell_stencil_col(G, r, p, n)];
+#pragma unroll
+        for (int p = 0; p < NSLOT; p++) s = s + a[p] * xv[p];
+        p0 = NSLOT;
+    }
 #pragma unroll 4
-    for (int p = 0; p < w; p++) s = s + val[base + 64 * p] * x[col[base + 64 * p]];
+    for (int p = p0; p < w; p++) s = s + val[base + 64 * p] * x[col[base + 64 * p]];
     switch (op) {
     case OP_MV: y[r] = s; break;
     case OP_RESID: y[r] = b[r] - s; break;
@@ -1552,13 +1597,14 @@ bo_status read_flag(int32_t *dflag, hipStream_t s, int32_t *out) {
 
 // the sliced copy of a CSR matrix of n rows (M.on stays false below min_rows)
 static bo_status sell_from_csr(SellMat &M, int n, const int32_t *rp, const int32_t *ci, const double *v,
-                               int min_rows, DBuf<int32_t> &work, hipStream_t s) {
+                               int min_rows, DBuf<int32_t> &work, hipStream_t s, const SellGrid &G = SellGrid{}) {
     M.on = false;
+    M.grid = G;
     if (n < 1 || n < min_rows) return BO_OK;
     const int nsl = (n + 63) / 64;
     BO_TRY(work.alloc(nsl));
     BO_TRY(M.off.alloc(nsl + 1));
-    k_csr_slice_width<<<grid_for(nsl), kBlock, 0, s>>>(n, rp, work.p);
+    k_csr_slice_width<<<grid_for(64LL * nsl), kBlock, 0, s>>>(n, rp, ci, G, work.p);
     // the padded size in 64 bits first: the prefix sum is 32-bit
     std::vector<int32_t> w(nsl);
     BO_HIP(hipMemcpyAsync(w.data(), work.p, sizeof(int32_t) * nsl, hipMemcpyDeviceToHost, s));
@@ -1570,7 +1616,7 @@ static bo_status sell_from_csr(SellMat &M, int n, const int32_t *rp, const int32
     BO_TRY(scan_counts(work.p, M.off.p, nsl, &total, s));
     BO_TRY(M.col.alloc(total));
     BO_TRY(M.val.alloc(total));
-    k_csr_sell_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, M.off.p, M.col.p, M.val.p);
+    k_csr_sell_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, M.off.p, G, M.col.p, M.val.p);
     BO_HIP(hipGetLastError());
     M.len = total;
     M.on = true;
@@ -1587,8 +1633,8 @@ static bo_status csr_rowop(int n, int nnz, const int32_t *rp, const int32_t *ci,
                            const T *b, const int32_t *dpos, T *y, hipStream_t s, const T *dl1 = nullptr,
                            const SellMat *sm = nullptr) {
     if (sm && sm->on && (op == OP_MV || op == OP_RESID || op == OP_ADD || op == OP_L1)) {
-        k_sell_rowop<T><<<grid_for(n), kBlock, 0, s>>>(n, sm->off.p, sm->col.p, sell_val<T>(*sm), x, op, b, dl1,
-                                                      y);
+        k_sell_rowop<T><<<grid_for(n), kBlock, 0, s>>>(n, sm->off.p, sm->col.p, sell_val<T>(*sm), sm->grid, x, op,
+                                                      b, dl1, y);
         BO_HIP(hipGetLastError());
         return BO_OK;
     }
@@ -2045,7 +2091,11 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s, const std::function<bo_status()> 
     const int sell_min = o.sell_rows > 0 ? o.sell_rows : kSellRows;
     for (int q = 0; q + 1 < pc->nlev; q++) {
         Level &L = pc->lv[q], &C = pc->lv[q + 1];
-        if (q > 0 || pc->general) BO_TRY(sell_from_csr(L.sA, L.n, L.rp.p, L.ci.p, L.v.p, sell_min, W.cnt, s));
+        // level 0 of a grid with extra rows: the cells' stencil entries with
+        // implicit columns
+        SellGrid sg{};
+        if (q == 0 && pc->has_grid && pc->g.n() <= L.n) sg = SellGrid{(int)pc->g.n(), pc->g.nx, pc->g.ny, pc->g.nz};
+        if (q > 0 || pc->general) BO_TRY(sell_from_csr(L.sA, L.n, L.rp.p, L.ci.p, L.v.p, sell_min, W.cnt, s, sg));
         else L.sA.on = false;
         BO_TRY(sell_from_csr(L.sP, L.n, L.prp.p, L.pci.p, L.pv.p, sell_min, W.cnt, s));
         BO_TRY(sell_from_csr(L.sR, C.n, L.rrp.p, L.rci.p, L.rv.p, sell_min, W.cnt, s));

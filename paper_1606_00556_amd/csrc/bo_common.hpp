@@ -150,6 +150,52 @@ __device__ __forceinline__ int nbr_of(int g, int s, int nx, int ny, int nz) {
     }
 }
 
+// ---- sliced layouts over a grid's cells -----------------------------------------
+// A sliced (SELL-64) matrix whose first `rows` rows are the cells of an
+// nx x ny x nz grid: a slice of 64 rows all below `rows` keeps each row's
+// stencil entries at positions 0..6 in slot order (ascending column order;
+// zero values where the row has no such entry) and the row's other entries
+// (columns of extra rows: matrix cells, wells) from position 7 on.  Kernels
+// take the columns of positions 0..6 from the row index instead of reading
+// them; every other slice (and every matrix without a grid, rows == 0) keeps
+// explicit columns.  The same entries in the same order as the CSR row, with
+// +0 products where a neighbour is missing, so the same sums.
+struct SellGrid {
+    int rows = 0;
+    int nx = 0, ny = 0, nz = 0;
+};
+__host__ __device__ inline bool sell_stencil_slice(const SellGrid &G, int S) {
+    return 64LL * (S + 1) <= (long long)G.rows;
+}
+// the column of stencil position k of row r: its neighbour through slot k,
+// or r itself where that offset leaves 0..n-1 (the value there is zero)
+__device__ __forceinline__ int sell_stencil_col(const SellGrid &G, int r, int k, int n) {
+    const int nxy = G.nx * G.ny;
+    const int d = k == S_MZ ? -nxy : k == S_MY ? -G.nx : k == S_MX ? -1 : k == S_D ? 0 : k == S_PX ? 1
+                : k == S_PY ? G.nx : nxy;
+    const int c = r + d;
+    return c < 0 || c >= n ? r : c;
+}
+// the stencil neighbours of cell r in slot order (-1 outside the grid)
+__device__ __forceinline__ void sell_stencil_nbrs(const SellGrid &G, int r, int *nb) {
+    const int nxy = G.nx * G.ny;
+    const int i = r % G.nx, j = (r / G.nx) % G.ny, k = r / nxy;
+    nb[S_MZ] = k > 0 ? r - nxy : -1;
+    nb[S_MY] = j > 0 ? r - G.nx : -1;
+    nb[S_MX] = i > 0 ? r - 1 : -1;
+    nb[S_D] = r;
+    nb[S_PX] = i < G.nx - 1 ? r + 1 : -1;
+    nb[S_PY] = j < G.ny - 1 ? r + G.nx : -1;
+    nb[S_PZ] = k < G.nz - 1 ? r + nxy : -1;
+}
+// the slot of column c among the neighbours nb, or -1 (not a stencil neighbour)
+__device__ __forceinline__ int sell_slot_in(const int *nb, int c) {
+    int slot = -1;
+#pragma unroll
+    for (int k = 0; k < NSLOT; k++) slot = nb[k] == c ? k : slot;
+    return slot;
+}
+
 // ---- small dense blocks ------------------------------------------------------
 // Inverse of a 3x3 block by Gauss-Jordan elimination with partial pivoting;
 // returns false for a pivot that is zero relative to the block's largest entry.

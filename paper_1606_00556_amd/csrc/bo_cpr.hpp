@@ -18,6 +18,7 @@ constexpr int kCoarseMaxLimit = 1024;
 struct SellMat {
     bool on = false;
     long long len = 0;            // stored elements (padding included)
+    SellGrid grid{};              // level 0 of a grid: stencil slices with implicit columns
     DBuf<int32_t> off, col;
     DBuf<double> val;
     DBuf<float> val32;
@@ -106,6 +107,7 @@ struct bo_cpr {
     bo::DBuf<double> Aval;
     bo::DBuf<int32_t> Asoff, Asci;  // sliced copy of A for the solver's SpMV (general form)
     bo::DBuf<double> Asv;
+    bo::SellGrid Asg{};           // its grid rows (stencil slices with implicit columns)
     bo_cpr_opts o{};
     // operator (copy of A) in slot layout, 7 bs^2 N (63 N, or 28 N for 2x2 blocks)
     bo::DBuf<double> A;

@@ -197,48 +197,66 @@ __global__ void k_bsr_spmv(int n, const int32_t *__restrict__ rp, const int32_t 
 }
 
 // ---- sliced BSR (general operator of the solver) -------------------------------
-__global__ void k_sell_width(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ width) {
-    int S = blockIdx.x * blockDim.x + threadIdx.x;
-    int nsl = (n + 63) / 64;
-    if (S >= nsl) return;
-    int r0 = 64 * S, r1 = min(n, r0 + 64), w = 0;
-    for (int r = r0; r < r1; r++) w = max(w, rp[r + 1] - rp[r]);
-    width[S] = w;
+// the width of each slice: its longest row, or in a stencil slice 7 + the
+// most entries a row has beyond its stencil neighbours
+// (a wavefront per slice: one lane per row, the maximum by shuffles)
+__global__ void k_sell_width(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, SellGrid G,
+                             int32_t *__restrict__ width) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x, S = r >> 6;
+    int len = 0;
+    if (r < n) {
+        len = rp[r + 1] - rp[r];
+        if (sell_stencil_slice(G, S)) {
+            int nb[NSLOT], extra = 0;
+            sell_stencil_nbrs(G, r, nb);
+            for (int e = rp[r]; e < rp[r + 1]; e++) extra += sell_slot_in(nb, ci[e]) < 0;
+            len = NSLOT + extra;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+    if ((threadIdx.x & 63) == 0 && 64 * S < n) width[S] = len;
 }
 
 __global__ void k_sell_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                            const double *__restrict__ v, const int32_t *__restrict__ soff,
+                            const double *__restrict__ v, const int32_t *__restrict__ soff, SellGrid G,
                             int32_t *__restrict__ sci, double *__restrict__ sv) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     int S = r >> 6, lane = r & 63;
     int k0 = soff[S], K = soff[S + 1] - k0;
     int e0 = rp[r], len = rp[r + 1] - e0;
+    // padding (past the row's end, or a stencil position the row lacks): a
+    // zero block on the row's own column (in a stencil slice: the column the
+    // kernels derive), so its product adds +0 and the x load stays in bounds
     for (int k = 0; k < K; k++) {
         size_t b = (size_t)(k0 + k) * 64 + lane;
-        if (k < len) {
-            sci[b] = ci[e0 + k];
-            for (int z = 0; z < 9; z++) sv[((size_t)(k0 + k) * 9 + z) * 64 + lane] = v[9 * (size_t)(e0 + k) + z];
-        } else {
-            // padding past the row's end: a zero block on the row's own column
-            // (its product adds +0 after the row's blocks, so the sum is
-            // unchanged, and the x load stays in bounds)
-            sci[b] = r;
-            for (int z = 0; z < 9; z++) sv[((size_t)(k0 + k) * 9 + z) * 64 + lane] = 0.0;
-        }
+        sci[b] = sell_stencil_slice(G, S) && k < NSLOT ? sell_stencil_col(G, r, k, n) : r;
+        for (int z = 0; z < 9; z++) sv[((size_t)(k0 + k) * 9 + z) * 64 + lane] = 0.0;
+    }
+    const bool st = sell_stencil_slice(G, S);
+    int nb[NSLOT];
+    if (st) sell_stencil_nbrs(G, r, nb);
+    int next = st ? NSLOT : 0;
+    for (int q = 0; q < len; q++) {
+        const int c = ci[e0 + q];
+        int k = st ? sell_slot_in(nb, c) : -1;
+        if (k < 0) k = next++;
+        size_t b = (size_t)(k0 + k) * 64 + lane;
+        sci[b] = c;
+        for (int z = 0; z < 9; z++) sv[((size_t)(k0 + k) * 9 + z) * 64 + lane] = v[9 * (size_t)(e0 + q) + z];
     }
 }
 
 // One row of the sliced layout, W blocks: every index and value load of the
 // row is issued before the first product (no load waits on a branch), then
 // the x gathers and the sums in block order.
-template <int W>
+template <int W, bool ST>
 __device__ __forceinline__ void sell_row(const int32_t *__restrict__ sci, const double *__restrict__ sv, int k0,
-                                         int lane, const double *__restrict__ x, double &s0, double &s1,
-                                         double &s2) {
+                                         int lane, const SellGrid &G, int r, int n, const double *__restrict__ x,
+                                         double &s0, double &s1, double &s2) {
     int c[W];
 #pragma unroll
-    for (int k = 0; k < W; k++) c[k] = sci[(size_t)(k0 + k) * 64 + lane];
+    for (int k = 0; k < W; k++) c[k] = ST && k < NSLOT ? sell_stencil_col(G, r, k, n) : sci[(size_t)(k0 + k) * 64 + lane];
     double e[W][9];
 #pragma unroll
     for (int k = 0; k < W; k++)
@@ -263,21 +281,24 @@ __device__ __forceinline__ void sell_row(const int32_t *__restrict__ sci, const 
 // blocks are zero blocks on the row's own column and add +0.
 __global__ void __launch_bounds__(kBlock) k_sell_spmv(int n, const int32_t *__restrict__ soff,
                                                       const int32_t *__restrict__ sci,
-                                                      const double *__restrict__ sv, double alpha,
+                                                      const double *__restrict__ sv, SellGrid G, double alpha,
                                                       const double *__restrict__ x, double beta,
                                                       double *__restrict__ y) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     int S = r >> 6, lane = r & 63;
     int k0 = soff[S], K = soff[S + 1] - k0;
+    const bool st = sell_stencil_slice(G, S);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     if (K == 7) {
-        sell_row<7>(sci, sv, k0, lane, x, s0, s1, s2);
+        if (st) sell_row<7, true>(sci, sv, k0, lane, G, r, n, x, s0, s1, s2);
+        else sell_row<7, false>(sci, sv, k0, lane, G, r, n, x, s0, s1, s2);
     } else if (K == 8) {
-        sell_row<8>(sci, sv, k0, lane, x, s0, s1, s2);
+        if (st) sell_row<8, true>(sci, sv, k0, lane, G, r, n, x, s0, s1, s2);
+        else sell_row<8, false>(sci, sv, k0, lane, G, r, n, x, s0, s1, s2);
     } else {
         for (int k = 0; k < K; k++) {
-            int c = sci[(size_t)(k0 + k) * 64 + lane];
+            int c = st && k < NSLOT ? sell_stencil_col(G, r, k, n) : sci[(size_t)(k0 + k) * 64 + lane];
             const double *blk = sv + (size_t)(k0 + k) * 9 * 64 + lane;
             double e[9];
 #pragma unroll
@@ -303,15 +324,16 @@ __global__ void __launch_bounds__(kBlock) k_sell_spmv(int n, const int32_t *__re
 template <typename TD>
 __global__ void __launch_bounds__(kBlock) k_sell_col0_update(int n, int npr, const int32_t *__restrict__ soff,
                                                              const int32_t *__restrict__ sci,
-                                                             const double *__restrict__ sv,
+                                                             const double *__restrict__ sv, SellGrid G,
                                                              const TD *__restrict__ dp, double *r) {
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= n) return;
     const int S = row >> 6, lane = row & 63;
     const int k0 = soff[S], K = soff[S + 1] - k0;
+    const bool st = sell_stencil_slice(G, S);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int k = 0; k < K; k++) {
-        const int c = sci[(size_t)(k0 + k) * 64 + lane];
+        const int c = st && k < NSLOT ? sell_stencil_col(G, row, k, n) : sci[(size_t)(k0 + k) * 64 + lane];
         const double *blk = sv + (size_t)(k0 + k) * 9 * 64 + lane;
         const double p = c < npr ? (double)dp[c] : 0.0;
         s0 = s0 + __builtin_nontemporal_load(blk) * p;
@@ -805,43 +827,43 @@ template bo_status slot_col0_residual<double, double>(const Grid &, const double
 template bo_status slot_col0_residual<float, double>(const Grid &, const double *, const double *, const float *,
                                                      double *, hipStream_t);
 
-bo_status sell_build(int n, const int32_t *rp, const int32_t *ci, const double *v, DBuf<int32_t> &soff,
-                     DBuf<int32_t> &sci, DBuf<double> &sv, hipStream_t s) {
+bo_status sell_build(int n, const int32_t *rp, const int32_t *ci, const double *v, const SellGrid &G,
+                     DBuf<int32_t> &soff, DBuf<int32_t> &sci, DBuf<double> &sv, hipStream_t s) {
     int nsl = (n + 63) / 64;
     BO_TRY(soff.alloc((size_t)nsl + 1));
     int32_t *width = nullptr;
     BO_TRY(scratch_get(SC_SELL, sizeof(int32_t) * (size_t)std::max(nsl, 1), (void **)&width));
-    k_sell_width<<<grid_for(nsl), kBlock, 0, s>>>(n, rp, width);
+    k_sell_width<<<grid_for(64LL * nsl), kBlock, 0, s>>>(n, rp, ci, G, width);
     BO_HIP(hipGetLastError());
     int32_t cols = 0;
     BO_TRY(scan_counts(width, soff.p, nsl, &cols, s));
     BO_TRY(sci.alloc((size_t)cols * 64));
     BO_TRY(sv.alloc((size_t)cols * 64 * 9));
-    if (n > 0) k_sell_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, soff.p, sci.p, sv.p);
+    if (n > 0) k_sell_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, soff.p, G, sci.p, sv.p);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
 
-bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double *sv, double alpha,
-                    const double *x, double beta, double *y, hipStream_t s) {
+bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double *sv, const SellGrid &G,
+                    double alpha, const double *x, double beta, double *y, hipStream_t s) {
     if (n <= 0) return BO_OK;
-    k_sell_spmv<<<grid_for(n), kBlock, 0, s>>>(n, soff, sci, sv, alpha, x, beta, y);
+    k_sell_spmv<<<grid_for(n), kBlock, 0, s>>>(n, soff, sci, sv, G, alpha, x, beta, y);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
 
 template <typename TD>
-bo_status sell_col0_update(int n, int npr, const int32_t *soff, const int32_t *sci, const double *sv, const TD *dp,
-                           double *r, hipStream_t s) {
+bo_status sell_col0_update(int n, int npr, const int32_t *soff, const int32_t *sci, const double *sv,
+                           const SellGrid &G, const TD *dp, double *r, hipStream_t s) {
     if (n <= 0) return BO_OK;
-    k_sell_col0_update<TD><<<grid_for(n), kBlock, 0, s>>>(n, npr, soff, sci, sv, dp, r);
+    k_sell_col0_update<TD><<<grid_for(n), kBlock, 0, s>>>(n, npr, soff, sci, sv, G, dp, r);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }
 template bo_status sell_col0_update<double>(int, int, const int32_t *, const int32_t *, const double *,
-                                            const double *, double *, hipStream_t);
+                                            const SellGrid &, const double *, double *, hipStream_t);
 template bo_status sell_col0_update<float>(int, int, const int32_t *, const int32_t *, const double *,
-                                           const float *, double *, hipStream_t);
+                                           const SellGrid &, const float *, double *, hipStream_t);
 
 template <typename TD>
 bo_status slot_col0_update(const Grid &g, const double *A, const TD *dp, double *r, hipStream_t s) {

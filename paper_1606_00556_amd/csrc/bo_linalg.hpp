@@ -10,20 +10,22 @@ bo_status slot_spmv(const Grid &g, const double *A, double alpha, const double *
 template <typename TD, typename TO>
 bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, const TD *dp, TO *r, hipStream_t s);
 // Sliced layout of a BSR matrix for the solver's SpMV: slices of 64 rows; a
-// slice of width K (its longest row) stores, for k < K, the k-th block of each
-// of its rows as 9 arrays of 64 doubles and one array of 64 column indices
-// (-1 past the end of a row).  soff[S] = sum of the widths of slices < S.
-bo_status sell_build(int n, const int32_t *rp, const int32_t *ci, const double *v, DBuf<int32_t> &soff,
-                     DBuf<int32_t> &sci, DBuf<double> &sv, hipStream_t s);
-bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double *sv, double alpha,
-                    const double *x, double beta, double *y, hipStream_t s);
+// slice of width K stores, for k < K, the k-th block of each of its rows as 9
+// arrays of 64 doubles and one array of 64 column indices (zero blocks on the
+// row's own column past the end of a row).  soff[S] = sum of the widths of
+// slices < S.  With a grid (G.rows > 0) the slices of cell rows keep the
+// stencil blocks at positions 0..6 with implicit columns (see SellGrid).
+bo_status sell_build(int n, const int32_t *rp, const int32_t *ci, const double *v, const SellGrid &G,
+                     DBuf<int32_t> &soff, DBuf<int32_t> &sci, DBuf<double> &sv, hipStream_t s);
+bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double *sv, const SellGrid &G,
+                    double alpha, const double *x, double beta, double *y, hipStream_t s);
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s);
 // r -= A Pi_p dp in place (column 0 of each block; dp FP64 or FP32), on the
 // sliced layout (dp on the block columns below npr) and on the slot layout
 template <typename TD>
-bo_status sell_col0_update(int n, int npr, const int32_t *soff, const int32_t *sci, const double *sv, const TD *dp,
-                           double *r, hipStream_t s);
+bo_status sell_col0_update(int n, int npr, const int32_t *soff, const int32_t *sci, const double *sv,
+                           const SellGrid &G, const TD *dp, double *r, hipStream_t s);
 template <typename TD>
 bo_status slot_col0_update(const Grid &g, const double *A, const TD *dp, double *r, hipStream_t s);
 bo_status axpby(long long n, double a, const double *x, double b, double *y, hipStream_t s);

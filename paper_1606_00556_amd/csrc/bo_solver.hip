@@ -43,7 +43,7 @@ bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double
     if (pc->bs == 2) return slot2_spmv(pc, alpha, x, beta, y, s);
     if (pc->bs == 1) return scalar_spmv(pc->g, pc->A.p, alpha, x, beta, y, s);
     if (!pc->general) return slot_spmv(pc->g, pc->A.p, alpha, x, beta, y, s);
-    return sell_spmv(pc->n, pc->Asoff.p, pc->Asci.p, pc->Asv.p, alpha, x, beta, y, s);
+    return sell_spmv(pc->n, pc->Asoff.p, pc->Asci.p, pc->Asv.p, pc->Asg, alpha, x, beta, y, s);
 }
 
 namespace {
@@ -132,9 +132,9 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
         // v - A z for the updated z: the residual above minus A Pi_p dp (column
         // 0 of each block only, a third of the SpMV's coefficient bytes)
         if (pc->general) {
-            if (mixed) BO_TRY(sell_col0_update(n, npr, pc->Asoff.p, pc->Asci.p, pc->Asv.p, (const float *)dp,
-                                               pc->t3a.p, s));
-            else BO_TRY(sell_col0_update(n, npr, pc->Asoff.p, pc->Asci.p, pc->Asv.p, (const double *)dp,
+            if (mixed) BO_TRY(sell_col0_update(n, npr, pc->Asoff.p, pc->Asci.p, pc->Asv.p, pc->Asg,
+                                               (const float *)dp, pc->t3a.p, s));
+            else BO_TRY(sell_col0_update(n, npr, pc->Asoff.p, pc->Asci.p, pc->Asv.p, pc->Asg, (const double *)dp,
                                          pc->t3a.p, s));
         } else {
             if (mixed) BO_TRY(slot_col0_update(g, pc->A.p, (const float *)dp, pc->t3a.p, s));
@@ -253,7 +253,10 @@ bo_status bo::cpr_setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_
         if (A->val != pc->Aval.p)
             BO_HIP(hipMemcpyAsync(pc->Aval.p, A->val, sizeof(double) * 9 * (size_t)A->nnzb, hipMemcpyDeviceToDevice,
                                   s));
-        BO_TRY(sell_build(n, pc->Arp.p, pc->Aci.p, pc->Aval.p, pc->Asoff, pc->Asci, pc->Asv, s));
+        // a grid's cell rows (the first N rows) keep their stencil blocks at
+        // implicit columns
+        pc->Asg = grid && pc->g.n() <= n ? SellGrid{(int)pc->g.n(), pc->g.nx, pc->g.ny, pc->g.nz} : SellGrid{};
+        BO_TRY(sell_build(n, pc->Arp.p, pc->Aci.p, pc->Aval.p, pc->Asg, pc->Asoff, pc->Asci, pc->Asv, s));
     } else {
         BO_TRY(bsr_to_slots(pc->g, A->rowptr, A->colind, A->val, pc->A.p, s));
     }
