@@ -884,6 +884,26 @@ __global__ void k_spgemm_long_rows(int n, const int32_t *__restrict__ val, int l
     if (take) rows[base + __popcll(m & ((1ull << lane) - 1))] = i;
 }
 
+// After a split counting pass: key[i] = 1 for the rows the launch over all
+// rows leaves out (more than plimit products, or more than dlimit distinct
+// columns), and the rows of at most plimit products but more than dlimit
+// distinct columns listed (one atomic per wavefront)
+__global__ void k_spgemm_classify(int n, const int32_t *__restrict__ prod, int plimit,
+                                  const int32_t *__restrict__ cnt, int dlimit, int32_t *__restrict__ key,
+                                  int32_t *__restrict__ rows, int32_t *__restrict__ pos) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool longp = i < n && prod[i] > plimit;
+    const bool many = i < n && !longp && cnt[i] > dlimit;
+    if (i < n) key[i] = longp || many ? 1 : 0;
+    const uint64_t m = __ballot(many);
+    if (!m) return;
+    const int lane = threadIdx.x % 64, lead = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == lead) base = atomicAdd(pos, __popcll(m));
+    base = __shfl(base, lead, 64);
+    if (many) rows[base + __popcll(m & ((1ull << lane) - 1))] = i;
+}
+
 // Rows: with rows != NULL the kernel takes rows[0..n) (listed rows); with
 // prod != NULL it takes rows 0..n-1 except those with prod[i] > plimit (the
 // long rows by products, or in the numeric pass the rows of many distinct
@@ -1893,9 +1913,28 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         HostRead rb{pos, sizeof nbig, &nbig};
         BO_TRY(host_reads(&rb, 1, s));
     }
+    // The same after a split by products: the rows of few products whose
+    // distinct columns are many (next to a long row) take a launch of their
+    // own too.
+    int nbig2 = 0;
+    if (split && lmax > kFewDistinct) {
+        int32_t *pos = W.sg_stat.p + kPos;  // the long-row list is complete: its position word is free again
+        BO_TRY(W.sg_rows2.alloc(n));
+        BO_TRY(W.sg_key.alloc(n));
+        BO_HIP(hipMemsetAsync(pos, 0, sizeof(int32_t), s));
+        // (the products per row stay: the launch below may still need them)
+        k_spgemm_classify<<<grid_for(n), kBlock, 0, s>>>(n, W.sg_prod.p, limit, cnt.p, kFewDistinct, W.sg_key.p,
+                                                          W.sg_rows2.p, pos);
+        HostRead rb{pos, sizeof nbig2, &nbig2};
+        BO_TRY(host_reads(&rb, 1, s));
+    }
     if (nbig > 0 && (long long)nbig * 10 < n) {
         numeric(sel_all, n, nullptr, cnt.p, kFewDistinct, kFewDistinct);
         numeric(sel_all, nbig, W.sg_rows.p, nullptr, 0, lmax);
+    } else if (nbig2 > 0 && (long long)nbig2 * 10 < n) {
+        numeric(sel_all, n, nullptr, W.sg_key.p, 0, kFewDistinct);
+        numeric(sel_all, nbig2, W.sg_rows2.p, nullptr, 0, lmax);
+        numeric(sel_long, nlong, W.sg_rows.p, nullptr, 0, lmax_long);
     } else {
         numeric(sel_all, n, nullptr, prod, limit, lmax);
         if (split) numeric(sel_long, nlong, W.sg_rows.p, nullptr, 0, lmax_long);

@@ -57,6 +57,7 @@ struct SetupWork {
     DBuf<int32_t> aprp, apci;
     DBuf<double> apv, dense;
     DBuf<int32_t> sg_prod, sg_rows, sg_stat;  // sparse product: products per row, long rows, reduction words
+    DBuf<int32_t> sg_rows2, sg_key;           // rows of few products but many distinct columns, launch keys
     DBuf<int32_t> plong;          // prolongator rows longer than the register path: [count, rows...]
     DBuf<int32_t> misw;           // change words of the MIS-2 rounds, one per round
     DBuf<int32_t> scan_sums;      // block sums of the prefix sums that read nothing back

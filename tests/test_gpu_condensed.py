@@ -164,3 +164,43 @@ def test_condensed_mixed_matches_emulation(B, O, name, prec):
     print(f"{name} {prec}: iterations gpu {info['iterations']} FP64 oracle {io}, true rel {true_rel:.2e}")
     assert info["converged"] and true_rel <= 1e-6
     assert info["iterations"] <= io + max(1, math.ceil(0.1 * io))
+
+
+@pytest.mark.parametrize("scale", [4, 2])
+def test_hierarchy_is_galerkin_at_scale(B, scale):
+    """Every coarse operator of the reduced system's hierarchy equals P^T A P
+    of the level above it (host sparse products of the GPU's own level
+    matrices), on the dual-porosity workload's twins of 1M and 4M cells with
+    the benchmark's options: the sparse products there take the split
+    launches (rows of many products or many distinct columns, next to the
+    wells) that small cases never reach."""
+    import scipy.sparse as sp
+    import torch
+    from bench import bench_cpr_kw
+    case = cg.make_cfg4(1, scale=scale)
+    prob = B.problem_from_case(case, "cuda")
+    J, b = B.bo_jacobian_bsr(prob, torch.from_numpy(case.x_old).cuda(), torch.from_numpy(case.x_new).cuda(), case.dt)
+    kw = bench_cpr_kw(4)
+    opts = B.bo_cpr_default_opts(condense=1, fpf=kw["fpf"], smoother=B.BO_SMOOTH_L1, sweeps=kw["sweeps"])
+    opts.tile_x, opts.tile_y = kw["tile"]
+    pc = B.bo_cpr_setup(J, (case.nx, case.ny, case.nz, 1), opts)
+    nlev = B.bo_cpr_levels(pc)
+    assert nlev >= 3
+    lv = [B.bo_cpr_level_copy(pc, l) for l in range(nlev)]
+    for l in range(nlev - 1):
+        n, nc = lv[l]["n"], lv[l + 1]["n"]
+        A = sp.csr_matrix((lv[l]["val"], lv[l]["colind"], lv[l]["rowptr"]), shape=(n, n))
+        P = sp.csr_matrix((lv[l]["p_val"], lv[l]["p_colind"], lv[l]["p_rowptr"]), shape=(n, nc))
+        C = sp.csr_matrix((lv[l + 1]["val"], lv[l + 1]["colind"], lv[l + 1]["rowptr"]), shape=(nc, nc))
+        ref = (P.T @ (A @ P)).tocsr()
+        d = abs(C - ref)
+        scale_c = abs(C).max()
+        assert d.max() <= 1e-11 * scale_c, (l, d.max(), scale_c)
+        # every stored entry of the coarse operator is a product entry and no
+        # product entry is missing: the patterns agree wherever the value is
+        # not exactly zero
+        ref.eliminate_zeros()
+        Cz = C.copy()
+        Cz.eliminate_zeros()
+        assert Cz.nnz == ref.nnz, (l, Cz.nnz, ref.nnz)
+    pc.close()
