@@ -24,6 +24,7 @@
 // and stored rounded to FP32 (9 float4 per slot and sweep) or to BF16 (9 uint2
 // per slot and sweep, round to nearest even from the FP32 value); the sweeps
 // run in FP32 on FP32 vectors.
+#include <type_traits>
 #include "bo_cpr.hpp"
 
 namespace bo {
@@ -606,11 +607,13 @@ __global__ void __launch_bounds__(128) k_ilu_forward(TileGeom G, const void *__r
 // s - 1 after that step's first barrier, which orders it after the write-out.
 // Without staging (D == 0) every lane writes its 24 bytes at its cell, and the
 // partial lines cost HBM writes of more than twice the output's size.
+// With zin != NULL the result is added to it: out = zin + (x + (dp, 0, 0))
+// (zin may be out itself: each cell is read and written by one thread).
 template <int St, typename T, typename TD>
 __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__restrict__ F,
                                                       const T *__restrict__ wq,
-                                                      const TD *__restrict__ dp, double *__restrict__ out,
-                                                      int D) {
+                                                      const TD *__restrict__ dp, double *out,
+                                                      int D, const double *zin) {
     __shared__ T xsh[2][3][64];  // x of a step, by step parity
     __shared__ T ash[2][3][64];  // wavefront 1's U_x x_x + U_y x_y
     extern __shared__ double obuf[];  // D slots of [lane][3]
@@ -638,7 +641,8 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
                 const int b = q / rowlen, rem = q - b * rowlen, a = rem / 3;
                 if (i0 + a < G.nx && j0 + b < G.ny) {
                     const size_t g0 = (size_t)i0 + (size_t)G.nx * ((size_t)(j0 + b) + (size_t)G.ny * k);
-                    out[3 * g0 + rem] = ob[3 * (a + G.tx * b) + (rem - 3 * a)];
+                    const double o = ob[3 * (a + G.tx * b) + (rem - 3 * a)];
+                    out[3 * g0 + rem] = zin ? zin[3 * g0 + rem] + o : o;
                 }
             }
         };
@@ -712,9 +716,15 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
                     ob[2] = (double)xp[2];
                 } else {
                     size_t g = L.cell(G, tile, s);
-                    out[3 * g] = o0;
-                    out[3 * g + 1] = (double)xp[1];
-                    out[3 * g + 2] = (double)xp[2];
+                    if (zin) {
+                        out[3 * g] = zin[3 * g] + o0;
+                        out[3 * g + 1] = zin[3 * g + 1] + (double)xp[1];
+                        out[3 * g + 2] = zin[3 * g + 2] + (double)xp[2];
+                    } else {
+                        out[3 * g] = o0;
+                        out[3 * g + 1] = (double)xp[1];
+                        out[3 * g + 2] = (double)xp[2];
+                    }
                 }
             }
             fetch(s - kAhead0, h, w, d);
@@ -921,16 +931,19 @@ __global__ void k_dual_forward(int n, const int32_t *__restrict__ slot_of, size_
     wq[2 * S + q] = yf[2] - y[2];
 }
 
-// well rows: x_r = E_r^{-1} r_r
+// well rows: x_r = E_r^{-1} r_r; with zin != NULL out = zin + (x + (dp, 0, 0))
+// (dp on the row's own index; zin may be out)
+template <typename TD>
 __global__ void k_rows_apply(int r0, int cnt, const double *__restrict__ inv, const double *__restrict__ r,
-                             double *__restrict__ out) {
+                             double *out, const TD *__restrict__ dp, const double *zin) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= cnt) return;
     size_t R = (size_t)(r0 + q);
     double B[9], v3[3] = {r[3 * R], r[3 * R + 1], r[3 * R + 2]}, o[3];
     for (int z = 0; z < 9; z++) B[z] = inv[(size_t)z * cnt + q];
     mv3(B, v3, o);
-    for (int c = 0; c < 3; c++) out[3 * R + c] = o[c];
+    if (dp) o[0] = (double)dp[R] + o[0];
+    for (int c = 0; c < 3; c++) out[3 * R + c] = zin ? zin[3 * R + c] + o[c] : o[c];
 }
 
 // the backward sweep's output staging: tile_x + tile_y - 1 layers of 64
@@ -1049,15 +1062,18 @@ bo_status fstage_check(bo_cpr *pc, hipStream_t s) {
 
 namespace {
 template <int St, typename T, typename TD>
-bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, T *wq, hipStream_t s) {
+bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, T *wq, hipStream_t s,
+                     const double *zin = nullptr) {
     long long n = pc->n;
     if (pc->o.ftype == BO_F_BJ) {
+        if (zin) return fail(BO_ERR_UNSUPPORTED, "F stage: no accumulating block-Jacobi form");
         k_bj_apply<St, T, TD><<<grid_for(n), kBlock, 0, s>>>(n, pc->einv.p, r, dp, out);
     } else {
         TileGeom G = geom(pc);
         k_ilu_forward<St, T><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, r, wq);
         const int D = stage_layers(G);
-        k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 128, D * kStageBytes, s>>>(G, pc->ilu_b.p, wq, dp, out, D);
+        k_ilu_backward<St, T, TD><<<G.ntx * G.nty, 128, D * kStageBytes, s>>>(G, pc->ilu_b.p, wq, dp, out, D,
+                                                                                 zin);
     }
     BO_HIP(hipGetLastError());
     return BO_OK;
@@ -1081,15 +1097,16 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
             else k_ilu_forward<ST_BF16, float><<<G.ntx * G.nty, 128, 0, s>>>(G, pc->ilu_f.p, r, pc->ilu_w32.p);
             if (pc->n > pc->ncell) {
                 int cnt = pc->n - pc->ncell;
-                k_rows_apply<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out);
+                k_rows_apply<double><<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out, nullptr,
+                                                                      nullptr);
             }
             const int D = stage_layers(G);
             if (st == ST_F32)
                 k_ilu_backward<ST_F32, float, double><<<G.ntx * G.nty, 128, D * kStageBytes, s>>>(
-                    G, pc->ilu_b.p, pc->ilu_w32.p, nullptr, out, D);
+                    G, pc->ilu_b.p, pc->ilu_w32.p, nullptr, out, D, nullptr);
             else
                 k_ilu_backward<ST_BF16, float, double><<<G.ntx * G.nty, 128, D * kStageBytes, s>>>(
-                    G, pc->ilu_b.p, pc->ilu_w32.p, nullptr, out, D);
+                    G, pc->ilu_b.p, pc->ilu_w32.p, nullptr, out, D, nullptr);
             BO_HIP(hipGetLastError());
             return BO_OK;
         }
@@ -1099,11 +1116,12 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
                                                           pc->x_afm.p, pc->x_einv_f.p, pc->ilu_w.p, out);
         if (pc->n > pc->ncell) {
             int cnt = pc->n - pc->ncell;
-            k_rows_apply<<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out);
+            k_rows_apply<double><<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, out, nullptr,
+                                                                  nullptr);
         }
         const int D = stage_layers(G);
         k_ilu_backward<ST_F64, double, double><<<G.ntx * G.nty, 128, D * kStageBytes, s>>>(
-            G, pc->ilu_b.p, pc->ilu_w.p, nullptr, out, D);
+            G, pc->ilu_b.p, pc->ilu_w.p, nullptr, out, D, nullptr);
         BO_HIP(hipGetLastError());
         return BO_OK;
     }
@@ -1113,6 +1131,37 @@ bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *ou
     default: return fstage_run<ST_BF16, float, double>(pc, r, dp, out, pc->ilu_w32.p, s);
     }
 }
+
+// z += F(r) + Pi_p dp in one pass over z (dp may be NULL; FP64 dp with the
+// FP64 factors, FP32 dp with the FP32 / BF16 ones), for the tiled ILU of a
+// grid and of the extended form without matrix cells with the pressure system
+// over all rows; BO_ERR_UNSUPPORTED for the other forms (the caller then adds
+// the terms one by one)
+bool fstage_acc_ok(const bo_cpr *pc) {
+    if (pc->o.ftype != BO_F_ILU_TILED) return false;
+    if (!pc->general) return true;
+    return pc->has_grid && pc->ncell == pc->g.n() && pc->npr == pc->n;
+}
+template <typename TD>
+bo_status fstage_apply_acc(bo_cpr *pc, const double *r, const TD *dp, double *z, hipStream_t s) {
+    if (!fstage_acc_ok(pc)) return fail(BO_ERR_UNSUPPORTED, "F stage: no accumulating form here");
+    const int st = store_of(pc);
+    if ((st == ST_F64) != std::is_same<TD, double>::value)
+        return fail(BO_ERR_INVALID_ARG, "F stage: pressure correction precision does not match the factors");
+    TileGeom G = geom(pc);
+    if (pc->general && pc->n > pc->ncell) {
+        // the well rows first: they read r and write their own rows of z only
+        const int cnt = pc->n - pc->ncell;
+        k_rows_apply<TD><<<grid_for(cnt), kBlock, 0, s>>>(pc->ncell, cnt, pc->x_einv_w.p, r, z, dp, z);
+        BO_HIP(hipGetLastError());
+    }
+    if (st == ST_F64)
+        return fstage_run<ST_F64, double, TD>(pc, r, dp, z, pc->ilu_w.p, s, z);
+    if (st == ST_F32) return fstage_run<ST_F32, float, TD>(pc, r, dp, z, pc->ilu_w32.p, s, z);
+    return fstage_run<ST_BF16, float, TD>(pc, r, dp, z, pc->ilu_w32.p, s, z);
+}
+template bo_status fstage_apply_acc<double>(bo_cpr *, const double *, const double *, double *, hipStream_t);
+template bo_status fstage_apply_acc<float>(bo_cpr *, const double *, const float *, double *, hipStream_t);
 
 // mixed form with the FP32 pressure correction of the V-cycle
 bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, hipStream_t s) {

@@ -33,6 +33,9 @@ bo_status fstage_launch(bo_cpr *pc, hipStream_t s);
 bo_status fstage_check(bo_cpr *pc, hipStream_t s);
 bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, hipStream_t s);
 bo_status fstage_apply_f32dp(bo_cpr *pc, const double *r, const float *dp, double *out, hipStream_t s);
+bool fstage_acc_ok(const bo_cpr *pc);
+template <typename TD>
+bo_status fstage_apply_acc(bo_cpr *pc, const double *r, const TD *dp, double *z, hipStream_t s);
 template <typename T>
 bo_status nn_correct(bo_cpr *pc, const T *rp, const T *dp, const T **out, hipStream_t s);
 template <typename T>
@@ -123,11 +126,16 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     BO_TRY(fstage_apply(pc, v, nullptr, z, s));
     BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
     BO_TRY(op_spmv(pc, -1.0, z, 1.0, pc->t3a.p, s));
+    // where the F stage has an accumulating form, Pi_p dp and the last F
+    // stage go into z in one pass at the end
+    const bool acc = fstage_acc_ok(pc);
+    const void *dp = nullptr;
     if (pc->o.use_amg) {
-        const void *dp;
         BO_TRY(pressure_stage(pc, pc->t3a.p, &dp, s));
-        if (mixed) k_add_p<float><<<grid_for(npr), kBlock, 0, s>>>(npr, (const float *)dp, z);
-        else k_add_p<double><<<grid_for(npr), kBlock, 0, s>>>(npr, (const double *)dp, z);
+        if (!acc) {
+            if (mixed) k_add_p<float><<<grid_for(npr), kBlock, 0, s>>>(npr, (const float *)dp, z);
+            else k_add_p<double><<<grid_for(npr), kBlock, 0, s>>>(npr, (const double *)dp, z);
+        }
         BO_HIP(hipGetLastError());
         // v - A z for the updated z: the residual above minus A Pi_p dp (column
         // 0 of each block only, a third of the SpMV's coefficient bytes)
@@ -140,6 +148,10 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
             if (mixed) BO_TRY(slot_col0_update(g, pc->A.p, (const float *)dp, pc->t3a.p, s));
             else BO_TRY(slot_col0_update(g, pc->A.p, (const double *)dp, pc->t3a.p, s));
         }
+    }
+    if (acc) {
+        if (mixed) return fstage_apply_acc<float>(pc, pc->t3a.p, (const float *)dp, z, s);
+        return fstage_apply_acc<double>(pc, pc->t3a.p, (const double *)dp, z, s);
     }
     BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, pc->t3b.p, s));
     return axpby(3 * n, 1.0, pc->t3b.p, 1.0, z, s);
