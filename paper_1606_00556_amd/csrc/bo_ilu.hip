@@ -494,6 +494,10 @@ struct SweepLane {
 // all outstanding loads before using any of them.
 constexpr int kAhead0 = 4;  // wavefront 0: 9 factor + 3 vector loads and 3 stores per step
 constexpr int kAhead1 = 6;  // wavefront 1: 9 factor loads per step
+// the backward sweep's wavefront 1: one step fewer in flight, so that the
+// sweep fits two wavefronts per SIMD (its staging and accumulation take
+// registers of their own)
+constexpr int kAheadB1 = 5;
 
 // forward sweep: FP64: y = r - sum_lower L y_lower with the unit-lower
 // factors L_ik = A_ik E_k^{-1}; FP32 / BF16: w = E^{-1}(r - sum_lower A w_lower)
@@ -626,7 +630,7 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
     if (wv == 1) {
         const int px = L.a + 1 < G.tx && t + 1 < 64 ? t + 1 : t;
         const int py = L.b + 1 < G.ty && t + G.tx < 64 ? t + G.tx : t;
-        Half<T> buf[kAhead1];
+        Half<T> buf[kAheadB1];
         auto fetch = [&](int s, Half<T> &h) {
             const int sc = max(s, 0);
             load_half<St, T, 1>(F, tile, ns, sc, L.active(G, sc) ? t : 0, h);
@@ -659,20 +663,20 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
                 mv3(h.v, xx, acc);
                 mv3(h.v + 9, xy, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
             }
-            fetch(s - kAhead1, h);
+            fetch(s - kAheadB1, h);
             for (int c = 0; c < 3; c++) ash[s & 1][c][t] = acc[c];
             __syncthreads();  // products of step s published
             __syncthreads();  // x of step s published
         };
 #pragma unroll
-        for (int u = 0; u < kAhead1; u++) fetch(e - u, buf[u]);
+        for (int u = 0; u < kAheadB1; u++) fetch(e - u, buf[u]);
         int s0 = e;
-        for (; s0 - kAhead1 + 1 >= 0; s0 -= kAhead1) {
+        for (; s0 - kAheadB1 + 1 >= 0; s0 -= kAheadB1) {
 #pragma unroll
-            for (int u = 0; u < kAhead1; u++) step(s0 - u, buf[u]);
+            for (int u = 0; u < kAheadB1; u++) step(s0 - u, buf[u]);
         }
 #pragma unroll
-        for (int u = 0; u < kAhead1; u++)
+        for (int u = 0; u < kAheadB1; u++)
             if (s0 - u >= 0) step(s0 - u, buf[u]);
         flush(0);
     } else {
