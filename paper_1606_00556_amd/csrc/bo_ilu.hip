@@ -456,8 +456,8 @@ __device__ __forceinline__ void load_vec(const T *__restrict__ vec, size_t S, si
 // slot's factors (E^{-1} and the -z block forward, only the -z factor in the
 // FP64 form; E^{-1} and the +z block backward) with the vector operand,
 // wavefront 1 the second half (the -y and
-// -x blocks; the +x and +y blocks), so each keeps more steps of loads in
-// flight (three and four steps ahead).  Per step, wavefront 1 multiplies its
+// -x blocks; the +x and +y blocks), so each keeps its own steps of loads in
+// flight.  Per step, wavefront 1 multiplies its
 // blocks with the neighbours' values of the previous step (read from LDS) and
 // hands the products to wavefront 0 through LDS; wavefront 0 completes the
 // step and hands the new values back.  The products are combined in the
@@ -492,12 +492,13 @@ struct SweepLane {
 // valid step of the tile and ignore it, so the idle lanes of a load share one
 // cache line): loads that some paths skip would make the compiler wait for
 // all outstanding loads before using any of them.
-constexpr int kAhead0 = 4;  // wavefront 0: 9 factor + 3 vector loads and 3 stores per step
-constexpr int kAhead1 = 6;  // wavefront 1: 9 factor loads per step
-// the backward sweep's wavefront 1: one step fewer in flight, so that the
-// sweep fits two wavefronts per SIMD (its staging and accumulation take
-// registers of their own)
-constexpr int kAheadB1 = 5;
+// Two steps ahead in both wavefronts: the sweeps then take about 140
+// registers and three tiles' wavefronts share a SIMD (with rings of four and
+// six steps, 248 registers and two), and the extra tiles in flight hide the
+// latency better than longer rings (measured on the 32M-cell workload, same
+// on the 500k- and 2M-cell ones).
+constexpr int kAhead0 = 2;  // wavefront 0: its factor and vector loads per step
+constexpr int kAhead1 = 2;  // wavefront 1: 9 factor loads per step
 
 // forward sweep: FP64: y = r - sum_lower L y_lower with the unit-lower
 // factors L_ik = A_ik E_k^{-1}; FP32 / BF16: w = E^{-1}(r - sum_lower A w_lower)
@@ -630,7 +631,7 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
     if (wv == 1) {
         const int px = L.a + 1 < G.tx && t + 1 < 64 ? t + 1 : t;
         const int py = L.b + 1 < G.ty && t + G.tx < 64 ? t + G.tx : t;
-        Half<T> buf[kAheadB1];
+        Half<T> buf[kAhead1];
         auto fetch = [&](int s, Half<T> &h) {
             const int sc = max(s, 0);
             load_half<St, T, 1>(F, tile, ns, sc, L.active(G, sc) ? t : 0, h);
@@ -663,20 +664,20 @@ __global__ void __launch_bounds__(128) k_ilu_backward(TileGeom G, const void *__
                 mv3(h.v, xx, acc);
                 mv3(h.v + 9, xy, y); acc[0] = acc[0] + y[0]; acc[1] = acc[1] + y[1]; acc[2] = acc[2] + y[2];
             }
-            fetch(s - kAheadB1, h);
+            fetch(s - kAhead1, h);
             for (int c = 0; c < 3; c++) ash[s & 1][c][t] = acc[c];
             __syncthreads();  // products of step s published
             __syncthreads();  // x of step s published
         };
 #pragma unroll
-        for (int u = 0; u < kAheadB1; u++) fetch(e - u, buf[u]);
+        for (int u = 0; u < kAhead1; u++) fetch(e - u, buf[u]);
         int s0 = e;
-        for (; s0 - kAheadB1 + 1 >= 0; s0 -= kAheadB1) {
+        for (; s0 - kAhead1 + 1 >= 0; s0 -= kAhead1) {
 #pragma unroll
-            for (int u = 0; u < kAheadB1; u++) step(s0 - u, buf[u]);
+            for (int u = 0; u < kAhead1; u++) step(s0 - u, buf[u]);
         }
 #pragma unroll
-        for (int u = 0; u < kAheadB1; u++)
+        for (int u = 0; u < kAhead1; u++)
             if (s0 - u >= 0) step(s0 - u, buf[u]);
         flush(0);
     } else {
