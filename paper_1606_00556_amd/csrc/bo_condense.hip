@@ -312,12 +312,22 @@ bo_status cond_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, co
         return BO_OK;
     }
     const double tol = opts->rtol * bnorm;
+    // a zero initial guess leaves r = b: the first pass then takes b itself
+    // (no product with the full matrix, no copy, its norm known)
+    double xn = 0.0;
+    BO_TRY(norm(len, x, &xn));
     bo_status status = BO_NOT_CONVERGED;
     for (int pass = 0; pass < 4; pass++) {
-        BO_HIP(hipMemcpyAsync(C.rfull.p, b, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
-        BO_TRY(bo_bsr_spmv(A, -1.0, x, 1.0, C.rfull.p, s));
+        const double *rf = C.rfull.p;
         double rn = 0.0;
-        BO_TRY(norm(len, C.rfull.p, &rn));
+        if (pass == 0 && xn == 0.0) {
+            rf = b;
+            rn = bnorm;
+        } else {
+            BO_HIP(hipMemcpyAsync(C.rfull.p, b, sizeof(double) * len, hipMemcpyDeviceToDevice, s));
+            BO_TRY(bo_bsr_spmv(A, -1.0, x, 1.0, C.rfull.p, s));
+            BO_TRY(norm(len, C.rfull.p, &rn));
+        }
         st.rel_residual = rn / bnorm;
         if (!std::isfinite(rn)) {
             status = fail(BO_ERR_NONFINITE, "bo_fgmres_solve: residual is not finite");
@@ -329,7 +339,7 @@ bo_status cond_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, co
             break;
         }
         if (st.iterations >= opts->maxit) break;
-        k_cond_reduce<<<grid_for(C.nr), kBlock, 0, s>>>(C.N, C.nr, C.rfull.p, C.W.p, C.rb.p);
+        k_cond_reduce<<<grid_for(C.nr), kBlock, 0, s>>>(C.N, C.nr, rf, C.W.p, C.rb.p);
         BO_HIP(hipGetLastError());
         double rbn = 0.0;
         BO_TRY(norm(3LL * C.nr, C.rb.p, &rbn));
@@ -349,7 +359,7 @@ bo_status cond_solve(bo_cpr *pc, const bo_bsr *A, const double *b, double *x, co
             status = rc;
             break;
         }
-        k_cond_back<<<grid_for(C.nr), kBlock, 0, s>>>(C.N, C.nr, C.rfull.p, C.rx.p, C.minv.p, C.amf.p, 1, x);
+        k_cond_back<<<grid_for(C.nr), kBlock, 0, s>>>(C.N, C.nr, rf, C.rx.p, C.minv.p, C.amf.p, 1, x);
         BO_HIP(hipGetLastError());
     }
     BO_HIP(hipStreamSynchronize(s));
