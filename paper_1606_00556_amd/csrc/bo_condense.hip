@@ -109,10 +109,17 @@ __global__ void k_cond_pivots(int N, const int32_t *__restrict__ rp, const int32
     }
     const int m = N + g;
     double Afm[9], Amf[9], Amm[9], Mi[9], Wg[9], T[9];
+    bool fin = true;
     for (int z = 0; z < 9; z++) {
         Afm[z] = val[9 * (size_t)em + z];
         Amf[z] = val[9 * (size_t)rp[m] + z];
         Amm[z] = val[9 * (size_t)(rp[m] + 1) + z];
+        fin = fin && isfinite(Afm[z]) && isfinite(Amf[z]) && isfinite(Amm[z]);
+    }
+    // (the blocks the reduced system copies are checked by its own setup)
+    if (!fin) {
+        *bad = 3;
+        return;
     }
     if (!inv3_gj(Amm, Mi)) {
         *bad = 2;
@@ -262,6 +269,7 @@ bo_status cond_setup(bo_cpr *pc, const bo_bsr *A, const bo_grid *grid, const bo_
     BO_TRY(host_reads(&rd, 1, s));
     if (bad == 1) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: not a dual-porosity pattern");
     if (bad == 2) return fail(BO_ERR_SINGULAR_BLOCK, "bo_cpr_setup: a matrix cell's diagonal block is singular");
+    if (bad == 3) return fail(BO_ERR_NONFINITE, "bo_cpr_setup: the matrix holds NaN or Inf");
     bo_bsr S{nr, C.nnz, srp, sci, sval};
     bo_status st = cpr_setup_impl(&S, &g0, &io, C.inner, s);
     C.inner->broken = st != BO_OK;

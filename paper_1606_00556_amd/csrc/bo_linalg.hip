@@ -174,26 +174,28 @@ bo_status scan_counts(const int32_t *counts, int32_t *out, int n, int32_t *total
 }
 
 // ---- BSR SpMV on the ABI layout ---------------------------------------------
+// Three threads per block row, thread r forming component r: per block it
+// reads block row r (three contiguous doubles), so the three threads of a
+// row read the block's 72 contiguous bytes together and a wavefront's loads
+// touch three times fewer cache lines than with one thread per row; each
+// component sums in block order and, within a block, in column order.
 __global__ void k_bsr_spmv(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                            const double *__restrict__ v, double alpha, const double *__restrict__ x,
                            double beta, double *__restrict__ y) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int e = rp[i]; e < rp[i + 1]; e++) {
-        const double *blk = v + 9 * (size_t)e;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3LL * n) return;
+    const int i = (int)(t / 3), r = (int)(t - 3LL * i);
+    double s = 0.0;
+    const int e1 = rp[i + 1];
+    for (int e = rp[i]; e < e1; e++) {
+        const double *b3 = v + 9 * (size_t)e + 3 * r;
         const double *xj = x + 3 * (size_t)ci[e];
-        double x0 = xj[0], x1 = xj[1], x2 = xj[2];
-        for (int r = 0; r < 3; r++) {
-            s[r] = s[r] + blk[3 * r] * x0;
-            s[r] = s[r] + blk[3 * r + 1] * x1;
-            s[r] = s[r] + blk[3 * r + 2] * x2;
-        }
+        s = s + b3[0] * xj[0];
+        s = s + b3[1] * xj[1];
+        s = s + b3[2] * xj[2];
     }
-    for (int r = 0; r < 3; r++) {
-        double yi = beta == 0.0 ? 0.0 : beta * y[3 * (size_t)i + r];
-        y[3 * (size_t)i + r] = alpha * s[r] + yi;
-    }
+    const double yi = beta == 0.0 ? 0.0 : beta * y[t];
+    y[t] = alpha * s + yi;
 }
 
 // ---- sliced BSR (general operator of the solver) -------------------------------
@@ -1092,7 +1094,8 @@ extern "C" bo_status bo_bsr_spmv(const bo_bsr *A, double alpha, const double *x,
         return fail(BO_ERR_INVALID_ARG, "bo_bsr_spmv: NULL argument");
     if (A->nbrows == 0) return BO_OK;
     hipStream_t s = (hipStream_t)stream;
-    k_bsr_spmv<<<grid_for(A->nbrows), kBlock, 0, s>>>(A->nbrows, A->rowptr, A->colind, A->val, alpha, x, beta, y);
+    k_bsr_spmv<<<grid_for(3LL * A->nbrows), kBlock, 0, s>>>(A->nbrows, A->rowptr, A->colind, A->val, alpha, x, beta,
+                                                            y);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }

@@ -130,6 +130,32 @@ def test_condensed_rejects_non_dual_input(B, O):
     assert e.value.status == B.BO_ERR_INVALID_ARG
 
 
+@pytest.mark.parametrize("where", ["fracture_row", "matrix_row", "coupling"])
+def test_condensed_rejects_non_finite_values(B, O, where):
+    """A NaN anywhere in the full matrix is reported as BO_ERR_NONFINITE: in a
+    block the reduced system copies (a fracture row's stencil block, found by
+    the reduced system's own setup), in a matrix cell's diagonal block, or in
+    a fracture cell's coupling to its matrix cell (found by the condensation,
+    which reads those blocks and would otherwise report a singular pivot)."""
+    case = rate_case()
+    P = O.Problem(case)
+    rp, ci, val, R = O.jacobian(P)
+    val = np.array(val, copy=True).reshape(-1, 3, 3)
+    N = case.n
+    g = N // 2
+    if where == "fracture_row":
+        e = rp[g]                      # its first (stencil) block
+    elif where == "matrix_row":
+        e = rp[N + g] + 1              # A_mm of location g
+    else:
+        e = next(q for q in range(rp[g], rp[g + 1]) if ci[q] == N + g)   # A_fm
+    val[e, 1, 2] = np.nan
+    with pytest.raises(B.BoError) as err:
+        B.bo_cpr_setup(device_bsr(B, rp, ci, val), (case.nx, case.ny, case.nz, 1),
+                       B.bo_cpr_default_opts(condense=1, smoother=B.BO_SMOOTH_L1, fpf=1))
+    assert err.value.status == B.BO_ERR_NONFINITE
+
+
 TOL = {"fp32": 1e-5, "bf16": 2.0**-7}
 
 
