@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_sell_spmv(int n, const int32_t *__re
                                                       const int32_t *__restrict__ sci,
                                                       const double *__restrict__ sv, SellGrid G, double alpha,
                                                       const double *__restrict__ x, double beta,
-                                                      double *__restrict__ y) {
+                                                      const double *yin, double *y) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     int S = r >> 6, lane = r & 63;
@@ -311,10 +311,12 @@ __global__ void __launch_bounds__(kBlock) k_sell_spmv(int n, const int32_t *__re
             s2 = s2 + e[6] * x0; s2 = s2 + e[7] * x1; s2 = s2 + e[8] * x2;
         }
     }
+    // y = alpha A x + beta yin (yin is y itself, or another vector)
+    const double *wi = yin + 3 * (size_t)r;
+    double t0 = beta == 0.0 ? 0.0 : beta * wi[0];
+    double t1 = beta == 0.0 ? 0.0 : beta * wi[1];
+    double t2 = beta == 0.0 ? 0.0 : beta * wi[2];
     double *yi = y + 3 * (size_t)r;
-    double t0 = beta == 0.0 ? 0.0 : beta * yi[0];
-    double t1 = beta == 0.0 ? 0.0 : beta * yi[1];
-    double t2 = beta == 0.0 ? 0.0 : beta * yi[2];
     yi[0] = alpha * s0 + t0;
     yi[1] = alpha * s1 + t1;
     yi[2] = alpha * s2 + t2;
@@ -847,9 +849,9 @@ bo_status sell_build(int n, const int32_t *rp, const int32_t *ci, const double *
 }
 
 bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double *sv, const SellGrid &G,
-                    double alpha, const double *x, double beta, double *y, hipStream_t s) {
+                    double alpha, const double *x, double beta, double *y, hipStream_t s, const double *yin) {
     if (n <= 0) return BO_OK;
-    k_sell_spmv<<<grid_for(n), kBlock, 0, s>>>(n, soff, sci, sv, G, alpha, x, beta, y);
+    k_sell_spmv<<<grid_for(n), kBlock, 0, s>>>(n, soff, sci, sv, G, alpha, x, beta, yin ? yin : y, y);
     BO_HIP(hipGetLastError());
     return BO_OK;
 }

@@ -17,8 +17,10 @@ bo_status slot_col0_residual(const Grid &g, const double *A, const double *v, co
 // stencil blocks at positions 0..6 with implicit columns (see SellGrid).
 bo_status sell_build(int n, const int32_t *rp, const int32_t *ci, const double *v, const SellGrid &G,
                      DBuf<int32_t> &soff, DBuf<int32_t> &sci, DBuf<double> &sv, hipStream_t s);
+// (yin != NULL: y = alpha A x + beta yin, yin read instead of y)
 bo_status sell_spmv(int n, const int32_t *soff, const int32_t *sci, const double *sv, const SellGrid &G,
-                    double alpha, const double *x, double beta, double *y, hipStream_t s);
+                    double alpha, const double *x, double beta, double *y, hipStream_t s,
+                    const double *yin = nullptr);
 bo_status bsr_to_slots(const Grid &g, const int32_t *rp, const int32_t *ci, const double *v, double *slots,
                        hipStream_t s);
 // r -= A Pi_p dp in place (column 0 of each block; dp FP64 or FP32), on the

@@ -49,6 +49,15 @@ bo_status op_spmv(bo_cpr *pc, double alpha, const double *x, double beta, double
     return sell_spmv(pc->n, pc->Asoff.p, pc->Asci.p, pc->Asv.p, pc->Asg, alpha, x, beta, y, s);
 }
 
+// y = v - A x (3x3-block handles): the sliced form reads v in place of y,
+// the others copy v into y first
+static bo_status op_residual(bo_cpr *pc, const double *v, const double *x, double *y, hipStream_t s) {
+    if (pc->bs == 3 && pc->general)
+        return sell_spmv(pc->n, pc->Asoff.p, pc->Asci.p, pc->Asv.p, pc->Asg, -1.0, x, 1.0, y, s, v);
+    BO_HIP(hipMemcpyAsync(y, v, sizeof(double) * pc->bs * pc->n, hipMemcpyDeviceToDevice, s));
+    return op_spmv(pc, -1.0, x, 1.0, y, s);
+}
+
 namespace {
 
 __global__ void k_check_finite(long long n, const double *__restrict__ v, int32_t *__restrict__ bad) {
@@ -103,8 +112,7 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
         if (mixed) k_add_p<float><<<grid_for(npr), kBlock, 0, s>>>(npr, (const float *)dp, pc->t3b.p);
         else k_add_p<double><<<grid_for(npr), kBlock, 0, s>>>(npr, (const double *)dp, pc->t3b.p);
         BO_HIP(hipGetLastError());
-        BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-        BO_TRY(op_spmv(pc, -1.0, pc->t3b.p, 1.0, pc->t3a.p, s));
+        BO_TRY(op_residual(pc, v, pc->t3b.p, pc->t3a.p, s));
         BO_TRY(fstage_apply(pc, pc->t3a.p, nullptr, z, s));
         if (mixed) k_add_p<float><<<grid_for(npr), kBlock, 0, s>>>(npr, (const float *)dp, z);
         else k_add_p<double><<<grid_for(npr), kBlock, 0, s>>>(npr, (const double *)dp, z);
@@ -124,8 +132,7 @@ bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s) {
     }
     // FPF
     BO_TRY(fstage_apply(pc, v, nullptr, z, s));
-    BO_HIP(hipMemcpyAsync(pc->t3a.p, v, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-    BO_TRY(op_spmv(pc, -1.0, z, 1.0, pc->t3a.p, s));
+    BO_TRY(op_residual(pc, v, z, pc->t3a.p, s));
     // where the F stage has an accumulating form, Pi_p dp and the last F
     // stage go into z in one pass at the end
     const bool acc = fstage_acc_ok(pc);
