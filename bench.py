@@ -83,6 +83,9 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=None, help="AMG pre- and post-smoothing sweeps (default 1)")
     ap.add_argument("--theta", type=float, default=None, help="AMG strength threshold (default 0.08)")
     ap.add_argument("--tile", type=int, nargs=2, default=None, help="F-stage ILU tile (default 8 8)")
+    ap.add_argument("--fstage", default="tiled", choices=("tiled", "natural"),
+                    help="F stage: tiled block ILU(0) (default) or block ILU(0) of the whole system in natural "
+                         "order by level scheduling (FP64, plain and condensed forms)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
@@ -160,14 +163,20 @@ def main():
         grid = (c0.nx, c0.ny, c0.nz)
         copts = B.bo_cpr_default_opts(precision=prec)
     kw = bench_cpr_kw(wl)
-    copts.sweeps = kw["sweeps"]
-    copts.tile_x, copts.tile_y = kw["tile"]
-    copts.fpf = kw["fpf"] if args.fpf is None else args.fpf
+    for k, v in kw.items():
+        if k == "tile":
+            copts.tile_x, copts.tile_y = v
+        else:
+            setattr(copts, k, v)
+    if args.fpf is not None:
+        copts.fpf = args.fpf
     for k, v in (("sweeps", args.sweeps), ("theta", args.theta)):
         if v is not None:
             setattr(copts, k, v)
     if args.tile is not None:
         copts.tile_x, copts.tile_y = args.tile
+    if args.fstage == "natural":
+        copts.ftype = B.BO_F_ILU_NATURAL
     fo = {"graph": args.graph}
     if args.orth is not None:
         fo["orth"] = args.orth
@@ -275,6 +284,8 @@ def main():
                              f"x{f_its:.2f} (the GPU's mean {its_full:.1f} iterations at full size)")
         else:
             cpu = cpu_baseline(args, c0, wl, condensed, twop)
+    fdesc = ("natural-order BILU0 (level-scheduled)" if args.fstage == "natural"
+             else f"tiled BILU0 {copts.tile_x}x{copts.tile_y}")
     out = {
         "metric": METRIC,
         "value": ms_per_step / 1000.0,
@@ -297,12 +308,12 @@ def main():
                          + (f"{len(systems)} systems of the synthetic 30-day step sequence" if wl else "one system")),
             "solver": (("BiCGSTAB" if args.krylov == "bicgstab" else "FGMRES(30)")
                        + f", CPR-{'FPF' if copts.fpf else 'PF'}: block quasi-IMPES, SA-AMG V({copts.sweeps},"
-                       f"{copts.sweeps}) RB-GS/l1-Jacobi, tiled BILU0 {copts.tile_x}x{copts.tile_y}"
+                       f"{copts.sweeps}) RB-GS/l1-Jacobi, " + fdesc
                        if wl != 4 else
                        "matrix cells eliminated exactly; FGMRES(30) on the reduced system (fracture cells and "
                        f"fixed-rate wells), CPR-{'FPF' if copts.fpf else 'PF'}: block quasi-IMPES over all of its "
-                       f"rows, SA-AMG V({copts.sweeps},{copts.sweeps}) l1-Jacobi, tiled BILU0 "
-                       f"{copts.tile_x}x{copts.tile_y} (fracture tiles, wells); true residual of the full system"
+                       f"rows, SA-AMG V({copts.sweeps},{copts.sweeps}) l1-Jacobi, " + fdesc
+                       + " (fracture cells, wells); true residual of the full system"
                        if condensed else
                        "FGMRES(30), CPR-FPF extended grid form: block quasi-IMPES over cell and well rows, "
                        f"SA-AMG V({copts.sweeps},{copts.sweeps}) l1-Jacobi, tiled BILU0 {copts.tile_x}x"
@@ -448,16 +459,17 @@ def cpu_baseline(args, case, wl, condensed, twop=False):
     else:
         rp, ci, val, R = O.jacobian(P)
     kw = bench_cpr_kw(wl)
+    oft = O.F_ILU_NATURAL if args.fstage == "natural" else O.F_ILU_TILED
     if rp is None:
         pass
     elif wl == 4 and condensed:
-        cond = O.Condensed(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, **kw)
+        cond = O.Condensed(P, rp, ci, val, ftype=oft, smoother=O.SMOOTH_L1, **kw)
         x, info = O.condensed_fgmres(rp, ci, val, -R, cond)
     elif wl == 4:
-        pc = O.Cpr(P, rp, ci, val, ftype=O.F_ILU_TILED, smoother=O.SMOOTH_L1, npr=P.rows, **kw)
+        pc = O.Cpr(P, rp, ci, val, ftype=oft, smoother=O.SMOOTH_L1, npr=P.rows, **kw)
         x, info = O.fgmres(rp, ci, val, -R, pc)
     else:
-        pc = O.Cpr(P, rp, ci, val, **kw)
+        pc = O.Cpr(P, rp, ci, val, ftype=oft, **kw)
         x, info = O.fgmres(rp, ci, val, -R, pc)
     t1 = time.perf_counter()
     log(args, f"[bench] cpu baseline: {t1 - t0:.2f} s, its={info['iterations']}")

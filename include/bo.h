@@ -210,7 +210,15 @@ bo_status bo_bsr_spmv(const bo_bsr *A, double alpha, const double *x, double bet
 
 /* ---- a2-a6: CPR preconditioner --------------------------------------- */
 
-enum { BO_F_BJ = 0, BO_F_ILU_TILED = 3 };          /* F stage: block Jacobi / tiled block ILU(0) */
+/* F stage: block Jacobi; block ILU(0) of the whole system in natural order
+ * (Section 3.2's ILU(0), no coupling dropped), applied by level scheduling
+ * over the grid's hyperplanes i+j+k = const with the rows after the cells
+ * taken in order: FP64 only, on the plain grid form or on a grid with at
+ * most 4096 rows after its cells (fixed-rate wells; the condensed
+ * dual-porosity form's reduced system), nx+ny+nz-2 dependent launches per
+ * sweep; tiled block ILU(0) (couplings between tiles dropped, one wavefront
+ * per tile). */
+enum { BO_F_BJ = 0, BO_F_ILU_NATURAL = 1, BO_F_ILU_TILED = 3 };
 /* level-0 smoother: red-black Gauss-Seidel (needs the grid), damped Jacobi,
  * or l1-Jacobi (for the general form without a grid) */
 enum { BO_SMOOTH_GS = 0, BO_SMOOTH_JACOBI = 1, BO_SMOOTH_L1 = 2 };

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libbo.so")
 BO_OK, BO_NOT_CONVERGED, BO_NN_FALLBACK = 0, 1, 2
 BO_ERR_INVALID_ARG, BO_ERR_HIP, BO_ERR_ALLOC, BO_ERR_NONFINITE = -1, -2, -3, -4
 BO_ERR_SINGULAR_BLOCK, BO_ERR_SINGULAR_COARSE, BO_ERR_BREAKDOWN, BO_ERR_UNSUPPORTED = -5, -6, -7, -8
-BO_F_BJ, BO_F_ILU_TILED = 0, 3
+BO_F_BJ, BO_F_ILU_NATURAL, BO_F_ILU_TILED = 0, 1, 3
 BO_SMOOTH_GS, BO_SMOOTH_JACOBI, BO_SMOOTH_L1 = 0, 1, 2
 BO_QI_DIAG, BO_QI_BLOCK = 0, 1
 BO_PREC_FP64, BO_PREC_FP32, BO_PREC_FP32_BF16 = 0, 1, 2

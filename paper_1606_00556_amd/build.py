@@ -10,7 +10,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbo.so")
 SOURCES = ["bo_linalg.hip", "bo_jacobian.hip", "bo_amg.hip", "bo_ilu.hip", "bo_solver.hip", "bo_nn.hip",
            "bo_nn_cpr.hip", "bo_condense.hip", "bo_newton.hip", "bo_bicgstab.hip",
-           "bo_twophase.hip", "bo_cpr2.hip", "bo_ras.hip"]
+           "bo_twophase.hip", "bo_cpr2.hip", "bo_ras.hip", "bo_ilu_level.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

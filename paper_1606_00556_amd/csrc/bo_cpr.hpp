@@ -7,6 +7,8 @@ namespace bo {
 
 constexpr int kMaxLevels = 16;
 constexpr int kCoarseMaxLimit = 1024;
+// rows after a grid's cells that the natural-order ILU takes (one thread, in order)
+constexpr int kNatExtraRows = 4096;
 
 // One level of the aggregation hierarchy: CSR operator (ascending columns),
 // and for every level but the coarsest the transfer operators to the next.
@@ -134,6 +136,14 @@ struct bo_cpr {
     bo::DBuf<double> ilu_w;
     bo::DBuf<float> ilu_w32;           // mixed form
     bo::DBuf<int32_t> ilu_slot;
+    // natural-order block ILU(0) (BO_F_ILU_NATURAL): the factors over the
+    // pattern of Arp / Aci (unit-lower blocks L_ik at the lower entries, the
+    // updated blocks at the others), the pivots' inverses (9 per row), the
+    // grid's cells by hyperplane with the hyperplanes' offsets (host and
+    // device copies), the forward sweep's result
+    bo::DBuf<double> nat_lu, nat_inv, nat_y;
+    bo::DBuf<int32_t> nat_perm, nat_lptr_d;
+    std::vector<int32_t> nat_lptr;
     // work vectors
     bo::DBuf<double> rp_, dp_, t3a, t3b, t3c, wf;
     bo::DBuf<int32_t> flag;
@@ -169,6 +179,9 @@ namespace bo {
 bo_status cpr_setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts, bo_cpr *pc, hipStream_t s);
 bo_status cpr_check(int32_t nbrows, const bo_grid *grid, const bo_cpr_opts *opts);
 bo_status cpr_apply(bo_cpr *pc, const double *v, double *z, hipStream_t s);
+// natural-order block ILU(0) by level scheduling (BO_F_ILU_NATURAL)
+bo_status nat_launch(bo_cpr *pc, hipStream_t s);
+bo_status nat_apply(bo_cpr *pc, const double *r, const double *dp, double *out, hipStream_t s);
 // The caller's matrix of a solve, for its true residual: a 3x3-block or a
 // 2x2-block BSR matrix, or the slot coefficients of a scalar system on the
 // handle's grid (at most one of the three), or none: the handle's own copy

@@ -981,6 +981,7 @@ bo_status fstage_launch(bo_cpr *pc, hipStream_t s) {
     BO_TRY(pc->fflag.alloc(1));
     int32_t *ff = pc->fflag.p;
     BO_HIP(hipMemsetAsync(ff, 0, sizeof(int32_t), s));
+    if (pc->o.ftype == BO_F_ILU_NATURAL) return nat_launch(pc, s);
     if (pc->o.ftype == BO_F_BJ) {
         BO_TRY(pc->einv.alloc(9 * n));  // FP64 size: large enough for every format
         void *E = pc->einv.p;
@@ -1061,6 +1062,8 @@ bo_status fstage_check(bo_cpr *pc, hipStream_t s) {
     int32_t bad = 0;
     HostRead rd{pc->fflag.p, sizeof bad, &bad};
     BO_TRY(host_reads(&rd, 1, s));
+    if (bad & 2)
+        return fail(BO_ERR_UNSUPPORTED, "F stage: a cell row's lower blocks are not its -x, -y, -z neighbours");
     if (bad) return fail(BO_ERR_SINGULAR_BLOCK, "F stage: singular 3x3 pivot block");
     return BO_OK;
 }
@@ -1087,6 +1090,7 @@ bo_status fstage_run(bo_cpr *pc, const double *r, const TD *dp, double *out, T *
 
 // out = F(r) (+ Pi_p dp when dp != NULL); r in natural order
 bo_status fstage_apply(bo_cpr *pc, const double *r, const double *dp, double *out, hipStream_t s) {
+    if (pc->o.ftype == BO_F_ILU_NATURAL) return nat_apply(pc, r, dp, out, s);
     if (pc->general && pc->o.ftype == BO_F_ILU_TILED) {
         // the extended grid form: tiles of fracture cells, then matrix cells,
         // then well rows (FP64, or FP32 / BF16 tile factors without matrix

@@ -259,7 +259,8 @@ bo_status bo::cpr_setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_
     HostRead rd{pc->flag.p, sizeof bad, &bad};
     BO_TRY(host_reads(&rd, 1, s));
     if (bad) return fail(BO_ERR_NONFINITE, "bo_cpr_setup: the matrix holds NaN or Inf");
-    if (pc->general) {
+    // the BSR copy: the general form's operator, and the natural-order ILU's pattern
+    if (pc->general || pc->o.ftype == BO_F_ILU_NATURAL) {
         BO_TRY(pc->Arp.alloc(n + 1));
         BO_TRY(pc->Aci.alloc(A->nnzb));
         BO_TRY(pc->Aval.alloc(9 * (size_t)A->nnzb));
@@ -272,6 +273,8 @@ bo_status bo::cpr_setup_impl(const bo_bsr *A, const bo_grid *grid, const bo_cpr_
         if (A->val != pc->Aval.p)
             BO_HIP(hipMemcpyAsync(pc->Aval.p, A->val, sizeof(double) * 9 * (size_t)A->nnzb, hipMemcpyDeviceToDevice,
                                   s));
+    }
+    if (pc->general) {
         // a grid's cell rows (the first N rows) keep their stencil blocks at
         // implicit columns
         pc->Asg = grid && pc->g.n() <= n ? SellGrid{(int)pc->g.n(), pc->g.nx, pc->g.ny, pc->g.nz} : SellGrid{};
@@ -349,8 +352,18 @@ bo_status bo::cpr_check(int32_t nbrows, const bo_grid *grid, const bo_cpr_opts *
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: on a grid every row is a pressure row");
     if ((long long)nbrows * 7 >= (1LL << 31)) return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: matrix too large");
     const bo_cpr_opts &o = *opts;
-    if (o.ftype != BO_F_BJ && o.ftype != BO_F_ILU_TILED)
-        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: F stage must be BO_F_BJ or BO_F_ILU_TILED");
+    if (o.ftype != BO_F_BJ && o.ftype != BO_F_ILU_TILED && o.ftype != BO_F_ILU_NATURAL)
+        return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: F stage must be BO_F_BJ, BO_F_ILU_TILED or BO_F_ILU_NATURAL");
+    if (o.ftype == BO_F_ILU_NATURAL) {
+        if (o.precision != BO_PREC_FP64)
+            return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: the natural-order ILU is FP64 only");
+        if (grid->dual)
+            return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: the natural-order ILU needs a grid without matrix cells "
+                                            "(the plain or the condensed form)");
+        if (nbrows - gn > kNatExtraRows)
+            return fail(BO_ERR_UNSUPPORTED, "bo_cpr_setup: the natural-order ILU takes at most 4096 rows after the "
+                                            "grid's cells");
+    }
     if (o.ftype == BO_F_ILU_TILED && (o.tile_x < 1 || o.tile_y < 1 || o.tile_x * o.tile_y > 64))
         return fail(BO_ERR_INVALID_ARG, "bo_cpr_setup: tiles need 1 <= tile_x*tile_y <= 64");
     if (o.use_amg && (o.coarse_max < 1 || o.coarse_max > kCoarseMaxLimit || !(o.theta >= 0.0) ||
