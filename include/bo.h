@@ -319,7 +319,11 @@ typedef struct { int32_t nx, ny, nz, dual; } bo_grid;
  * its F stage must be block Jacobi; with the extended grid form (see bo_grid)
  * it may also be the tiled block ILU(0) (FP64 precision only), ordered tile by
  * tile: the tile's fracture cells, their matrix cells, and the remaining rows
- * as one block-Jacobi class of their own. */
+ * as one block-Jacobi class of their own.  BO_F_ILU_NATURAL takes a grid
+ * without matrix cells (the plain form, or at most 4096 rows after the cells,
+ * such as fixed-rate wells) and FP64 precision; BO_ERR_UNSUPPORTED otherwise,
+ * or when a cell row has a lower block other than its -x, -y, -z
+ * neighbours. */
 bo_status bo_cpr_setup(const bo_bsr *A, const bo_grid *grid, const bo_cpr_opts *opts,
                        const bo_allocator *alloc, bo_cpr **out, void *stream);
 /* Rebuilds pc for new values of a matrix with the same grid, pattern and
