@@ -133,6 +133,7 @@ struct bo_cpr {
     // buffers hold FP32 or BF16 values
     bo::DBuf<double> einv;
     bo::DBuf<double2> ilu_f, ilu_b;
+    bo::DBuf<double2> ilu_pf, ilu_pb;  // mixed form: the FP64 packed blocks its factorisation reads
     bo::DBuf<double> ilu_w;
     bo::DBuf<float> ilu_w32;           // mixed form
     bo::DBuf<int32_t> ilu_slot;

@@ -101,89 +101,17 @@ __device__ __forceinline__ void shfl_arr(const double *src, double *dst, int lan
     for (int z = 0; z < K; z++) dst[z] = __shfl(src[z], lane, 64);
 }
 
-// Factorisation: writes E^{-1}, the lower blocks (-z,-y,-x) and upper blocks
-// (+z,+x,+y) of each cell (zero where the neighbour lies outside the tile or
-// grid) into the (tile, step, lane) layout, and the slot of each cell.
-// E^{-1} by Gauss-Jordan with partial pivoting.
-template <int St>
-__global__ void __launch_bounds__(64) k_ilu_factor(TileGeom T, const double *__restrict__ A,
-                                                   void *__restrict__ Ff, void *__restrict__ Fb,
-                                                   int32_t *__restrict__ slot_of,
-                                                   int32_t *__restrict__ bad, double *__restrict__ einv_nat) {
-    int t = threadIdx.x;
-    int a = t % T.tx, b = t / T.tx;
-    int tile = blockIdx.x;
-    int ti = tile % T.ntx, tj = tile / T.ntx;
-    int i = ti * T.tx + a, j = tj * T.ty + b;
-    bool active = t < T.tx * T.ty && i < T.nx && j < T.ny;
-    bool has_mx = a > 0, has_my = b > 0;
-    bool has_px = a + 1 < T.tx && i + 1 < T.nx, has_py = b + 1 < T.ty && j + 1 < T.ny;
-    size_t N = (size_t)T.nx * T.ny * T.nz;
-    double Ep[9], Uxp[9], Uyp[9], Uzp[9];  // this lane's values from the previous step
-    for (int z = 0; z < 9; z++) Ep[z] = Uxp[z] = Uyp[z] = Uzp[z] = 0.0;
-    for (int s = 0; s < T.ns; s++) {
-        // neighbours' previous-step values (every lane takes part in the shuffles)
-        double Ex[9], Ey[9], Ux[9], Uy[9];
-        shfl_arr<9>(Ep, Ex, has_mx ? t - 1 : t);
-        shfl_arr<9>(Uxp, Ux, has_mx ? t - 1 : t);
-        shfl_arr<9>(Ep, Ey, has_my ? t - T.tx : t);
-        shfl_arr<9>(Uyp, Uy, has_my ? t - T.tx : t);
-        int k = s - a - b;
-        size_t q = ((size_t)tile * T.ns + s) * 64 + t;
-        if (active && k >= 0 && k < T.nz) {
-            int g = i + T.nx * (j + T.ny * k);
-            double E[9], L[9], Lk[9], tmp[9];
-            double fw[36], bw[36];  // packed slot data: [E^{-1} | Lz Ly Lx] and [E^{-1} | Uz Ux Uy]
-            for (int z = 0; z < 36; z++) fw[z] = bw[z] = 0.0;
-            load_blk(A, S_D, N, g, E);
-            // -z, -y, -x in ascending order
-            if (k > 0) {
-                load_blk(A, S_MZ, N, g, L);
-                mul3(L, Ep, Lk); mul3(Lk, Uzp, tmp);
-                for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
-                for (int z = 0; z < 9; z++) fw[9 + z] = L[z];
-            }
-            if (has_my) {
-                load_blk(A, S_MY, N, g, L);
-                mul3(L, Ey, Lk); mul3(Lk, Uy, tmp);
-                for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
-                for (int z = 0; z < 9; z++) fw[18 + z] = L[z];
-            }
-            if (has_mx) {
-                load_blk(A, S_MX, N, g, L);
-                mul3(L, Ex, Lk); mul3(Lk, Ux, tmp);
-                for (int z = 0; z < 9; z++) E[z] = E[z] - tmp[z];
-                for (int z = 0; z < 9; z++) fw[27 + z] = L[z];
-            }
-            double Ei[9];
-            if (!inv3_gj(E, Ei)) {
-                *bad = 1;
-                for (int z = 0; z < 9; z++) Ei[z] = 0.0;
-            }
-            for (int z = 0; z < 9; z++) { fw[z] = Ei[z]; bw[z] = Ei[z]; Ep[z] = Ei[z]; }
-            if (einv_nat)
-                for (int z = 0; z < 9; z++) einv_nat[(size_t)z * N + g] = Ei[z];
-            // upper blocks: this row's +x, +y, +z (zero outside the tile)
-            if (has_px) load_blk(A, S_PX, N, g, Uxp); else for (int z = 0; z < 9; z++) Uxp[z] = 0.0;
-            if (has_py) load_blk(A, S_PY, N, g, Uyp); else for (int z = 0; z < 9; z++) Uyp[z] = 0.0;
-            if (k + 1 < T.nz) load_blk(A, S_PZ, N, g, Uzp); else for (int z = 0; z < 9; z++) Uzp[z] = 0.0;
-            for (int z = 0; z < 9; z++) { bw[9 + z] = Uzp[z]; bw[18 + z] = Uxp[z]; bw[27 + z] = Uyp[z]; }
-            store_pack<St>(Ff, tile, T.ns, s, t, fw);
-            store_pack<St>(Fb, tile, T.ns, s, t, bw);
-            slot_of[g] = (int32_t)q;
-        }
-    }
-}
-
-// FP64 factorisation in two passes.  Pack: one thread per slot (tile, step,
-// lane), all slots at once, gathers its cell's blocks into the packed layout
-// (forward slot: [A_ii | Lz Ly Lx], backward slot: [- | Uz Ux Uy], zero where
-// the neighbour lies outside the tile or grid) and records the slot of each
-// cell.  Chain: one wavefront per tile walks the steps as k_ilu_factor does,
-// but reads each step's blocks from the packed layout (1 KB per load
-// instruction instead of one cache line per lane) and writes E^{-1} over
-// A_ii in the forward slot and into the backward slot.  Same operations in
-// the same order as k_ilu_factor, so the same bits.
+// Factorisation in two passes, in FP64 for every storage format.  Pack: one
+// thread per slot (tile, step, lane), all slots at once, gathers its cell's
+// blocks into the FP64 packed layout (forward slot: [A_ii | Az Ay Ax] with
+// the lower blocks -z, -y, -x; backward slot: [- | Uz Ux Uy] with the upper
+// blocks +z, +x, +y; zero where the neighbour lies outside the tile or grid)
+// and records the slot of each cell.  Chain: one wavefront per tile walks the
+// steps; lane t = a + tile_x*b at step s handles layer k = s - a - b and forms
+// E_i = A_ii - sum over -z, -y, -x of (A_ik E_k^{-1}) U_ki from the values its
+// neighbours held one step earlier (shuffled), reading each step's blocks
+// from the packed layout (1 KB per load instruction), and E_i^{-1} by
+// Gauss-Jordan with partial pivoting.
 __global__ void __launch_bounds__(kBlock) k_ilu_pack(TileGeom T, const double *__restrict__ A,
                                                      double2 *__restrict__ Ff, double2 *__restrict__ Fb,
                                                      int32_t *__restrict__ slot_of) {
@@ -290,8 +218,36 @@ __global__ void __launch_bounds__(kBlock) k_ilu_pack_bsr(TileGeom T, const int32
     slot_of[g] = (int32_t)q;
 }
 
+// one slot of the FP32 / BF16 forms: values 0..8 from e, 9..35 from r (the
+// three blocks of A), rounded to nearest
+template <int St>
+__device__ __forceinline__ void store_mixed(void *F, int tile, int ns, int s, int t, const double *e,
+                                            const double *r) {
+#pragma unroll
+    for (int qd = 0; qd < kQuads; qd++) {
+        float f[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int z = 4 * qd + u;
+            f[u] = (float)(z < 9 ? e[z] : r[z - 9]);
+        }
+        if constexpr (St == ST_F32) {
+            ((float4 *)F)[pq_index(tile, ns, s, qd, t)] = make_float4(f[0], f[1], f[2], f[3]);
+        } else {
+            ((uint2 *)F)[pq_index(tile, ns, s, qd, t)] =
+                make_uint2(bf16_bits(f[0]) | (bf16_bits(f[1]) << 16), bf16_bits(f[2]) | (bf16_bits(f[3]) << 16));
+        }
+    }
+}
+
+// FP64 form: E^{-1} and the unit-lower factors over the packed input (Ff,
+// Fb).  FP32 / BF16 forms: the packed input is left as it is and each slot
+// is stored rounded into Of ([E^{-1} | Az Ay Ax]) and Ob ([E^{-1} | Uz Ux
+// Uy]), the blocks of A as the sweeps of those forms take them.
+template <int St>
 __global__ void __launch_bounds__(64) k_ilu_chain(TileGeom T, double2 *__restrict__ Ff, double2 *__restrict__ Fb,
-                                                  int32_t *__restrict__ bad, double *__restrict__ einv_nat) {
+                                                  int32_t *__restrict__ bad, double *__restrict__ einv_nat,
+                                                  void *__restrict__ Of, void *__restrict__ Ob) {
     int t = threadIdx.x;
     int a = t % T.tx, b = t / T.tx;
     int tile = blockIdx.x;
@@ -366,6 +322,12 @@ __global__ void __launch_bounds__(64) k_ilu_chain(TileGeom T, double2 *__restric
             if (einv_nat) {
                 const int g = i + T.nx * (j + T.ny * k);
                 for (int z = 0; z < 9; z++) einv_nat[(size_t)z * N + g] = Ei[z];
+            }
+            if constexpr (St != ST_F64) {
+                store_mixed<St>(Of, tile, T.ns, s, t, Ei, fw + 9);
+                store_mixed<St>(Ob, tile, T.ns, s, t, Ei, uw);
+                for (int z = 0; z < 9; z++) { Uzp[z] = uw[z]; Uxp[z] = uw[9 + z]; Uyp[z] = uw[18 + z]; }
+                return;
             }
             // E^{-1} into values 0..8 of the backward slot, the lower factors
             // over the forward slot's blocks of A (its values 0..7, A_ii, are
@@ -828,25 +790,6 @@ int store_of(const bo_cpr *pc) {
 //   backward  x_m = E_m^{-1} y_m,  x_f = E_f^{-1} (y_f - A_fm x_m - sum_stencil A x)
 // The term A_fm x_m is taken out of y_f before the tile's backward sweep.
 
-// stencil blocks (columns < N) of the first N rows of a BSR matrix into the
-// slot layout
-__global__ void k_bsr_stencil_slots(int nx, int ny, int nz, const int32_t *__restrict__ rp,
-                                    const int32_t *__restrict__ ci, const double *__restrict__ v,
-                                    double *__restrict__ slots, int32_t *__restrict__ bad) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int n = nx * ny * nz;
-    if (i >= n) return;
-    size_t N = (size_t)n;
-    int e = rp[i], end = rp[i + 1];
-    for (int s = 0; s < NSLOT; s++) {
-        int nb = nbr_of(i, s, nx, ny, nz);
-        bool have = nb >= 0 && e < end && ci[e] == nb;
-        for (int z = 0; z < 9; z++) slots[((size_t)s * 9 + z) * N + i] = have ? v[9 * (size_t)e + z] : 0.0;
-        if (have) e++;
-        else if (nb >= 0) *bad = 1;
-    }
-}
-
 // matrix pivots E_m^{-1} and the coupling blocks A_mf (row N+g, col g) and
 // A_fm (row g, col N+g), SoA 9 x N
 __global__ void k_dual_pivots(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -1005,40 +948,35 @@ bo_status fstage_launch(bo_cpr *pc, hipStream_t s) {
             // natural order, which the FP64 chain writes)
             if (st != ST_F64 && pc->ncell > N)
                 return fail(BO_ERR_UNSUPPORTED, "F stage: with matrix cells the extended form's ILU is FP64 only");
-            // the FP64 pack reads the BSR rows itself; the FP32 / BF16
-            // factorisation takes the slot layout
-            if (st != ST_F64) {
-                BO_TRY(pc->A.alloc(63 * N));
-                k_bsr_stencil_slots<<<grid_for(N), kBlock, 0, s>>>(pc->g.nx, pc->g.ny, pc->g.nz, pc->Arp.p,
-                                                                   pc->Aci.p, pc->Aval.p, pc->A.p, ff);
-            }
             if (st == ST_F64) BO_TRY(pc->x_einv_f.alloc(9 * N));
         }
-        // factor buffers sized for FP64; the FP32 and BF16 forms use a prefix
-        BO_TRY(pc->ilu_f.alloc(S * kPairs));
-        BO_TRY(pc->ilu_b.alloc(S * kPairs));
+        // factor buffers: FP64 packed (the FP64 form factors in place), or
+        // the FP32 / BF16 layout (a float4 or uint2 per quad; sized for
+        // float4) beside an FP64 packed copy that the factorisation reads
+        const bool f64 = st == ST_F64;
+        BO_TRY(pc->ilu_f.alloc(f64 ? S * kPairs : S * kQuads));
+        BO_TRY(pc->ilu_b.alloc(f64 ? S * kPairs : S * kQuads));
+        if (!f64) {
+            BO_TRY(pc->ilu_pf.alloc(S * kPairs));
+            BO_TRY(pc->ilu_pb.alloc(S * kPairs));
+        }
+        double2 *Pf = f64 ? pc->ilu_f.p : pc->ilu_pf.p, *Pb = f64 ? pc->ilu_b.p : pc->ilu_pb.p;
         BO_TRY(pc->ilu_slot.alloc(n));
-        if (st == ST_F64) BO_TRY(pc->ilu_w.alloc(3 * S));
+        if (f64) BO_TRY(pc->ilu_w.alloc(3 * S));
         else BO_TRY(pc->ilu_w32.alloc(3 * S));
         // idle slots are never read by the sweeps: their factors stay unset
         int nb = T.ntx * T.nty;
-        if (st == ST_F64) {
-            if (ext)
-                k_ilu_pack_bsr<<<grid_for(T.slots()), kBlock, 0, s>>>(T, pc->Arp.p, pc->Aci.p, pc->Aval.p,
-                                                                      (double2 *)pc->ilu_f.p, (double2 *)pc->ilu_b.p,
-                                                                      pc->ilu_slot.p, ff);
-            else
-                k_ilu_pack<<<grid_for(T.slots()), kBlock, 0, s>>>(T, pc->A.p, (double2 *)pc->ilu_f.p,
-                                                                  (double2 *)pc->ilu_b.p, pc->ilu_slot.p);
-            k_ilu_chain<<<nb, 64, 0, s>>>(T, (double2 *)pc->ilu_f.p, (double2 *)pc->ilu_b.p, ff,
-                                          ext ? pc->x_einv_f.p : nullptr);
-        } else if (st == ST_F32) {
-            k_ilu_factor<ST_F32><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p,
-                                                   pc->ilu_slot.p, ff, nullptr);
-        } else {
-            k_ilu_factor<ST_BF16><<<nb, 64, 0, s>>>(T, pc->A.p, pc->ilu_f.p, pc->ilu_b.p,
-                                                    pc->ilu_slot.p, ff, nullptr);
-        }
+        if (ext)
+            k_ilu_pack_bsr<<<grid_for(T.slots()), kBlock, 0, s>>>(T, pc->Arp.p, pc->Aci.p, pc->Aval.p, Pf, Pb,
+                                                                  pc->ilu_slot.p, ff);
+        else
+            k_ilu_pack<<<grid_for(T.slots()), kBlock, 0, s>>>(T, pc->A.p, Pf, Pb, pc->ilu_slot.p);
+        if (f64)
+            k_ilu_chain<ST_F64><<<nb, 64, 0, s>>>(T, Pf, Pb, ff, ext ? pc->x_einv_f.p : nullptr, nullptr, nullptr);
+        else if (st == ST_F32)
+            k_ilu_chain<ST_F32><<<nb, 64, 0, s>>>(T, Pf, Pb, ff, nullptr, pc->ilu_f.p, pc->ilu_b.p);
+        else
+            k_ilu_chain<ST_BF16><<<nb, 64, 0, s>>>(T, Pf, Pb, ff, nullptr, pc->ilu_f.p, pc->ilu_b.p);
         if (ext && pc->ncell > N) {
             BO_TRY(pc->x_einv_m.alloc(9 * N));
             BO_TRY(pc->x_amf.alloc(9 * N));
