@@ -81,6 +81,32 @@ def test_ilu0_defining_property(oracle_lib, ftype):
                 assert np.abs(blk - val[e]).max() <= 1e-9 * scale
 
 
+def test_ilu0_defining_property_with_well_rows(oracle_lib):
+    """Natural order on a grid followed by two fixed-rate well rows: L U
+    equals A on the whole block pattern, the cell-well and well-cell blocks
+    included.  Each well perforates a whole column, so eliminating a
+    perforation updates the block of the perforation below it towards the
+    well, and the well row is eliminated against every perforation in turn; a
+    dropped or misplaced one of these updates breaks the equality there."""
+    import dataclasses
+    O = oracle_lib
+    c = cg.tiny_case(4, 3, 3, seed=5, wells=[cg.Well(0, 0, 0, 2, "inj", "wrat", 800.0),
+                                             cg.Well(3, 2, 0, 2, "prod", "lrat", 600.0)])
+    extra = np.tile(np.array([3000.0, 0.0, 0.0]), c.nrate)
+    c = dataclasses.replace(c, x_old=np.concatenate([c.x_old, extra]), x_new=np.concatenate([c.x_new, extra]))
+    P = O.Problem(c)
+    rp, ci, val, R = O.jacobian(P)
+    n = P.rows
+    assert n == c.n + 2 and any((ci[rp[i]:rp[i + 1]] >= c.n).any() for i in range(c.n))
+    pc = O.Cpr(P, rp, ci, val, ftype=O.F_ILU_NATURAL, use_amg=0)
+    M = dense_M_of_fstage(pc, 3 * n)
+    scale = np.abs(val).max()
+    for i in range(n):
+        for e in range(rp[i], rp[i + 1]):
+            j = ci[e]
+            assert np.abs(M[3 * i:3 * i + 3, 3 * j:3 * j + 3] - val[e]).max() <= 1e-9 * scale, (i, j)
+
+
 def test_ilu0_exact_on_a_line(oracle_lib):
     """On an nx x 1 x 1 grid the block pattern is tridiagonal, ILU(0) has no
     dropped fill and is the exact LU: F alone and CPR-PF both solve in one
