@@ -1481,47 +1481,49 @@ __global__ void __launch_bounds__(kBlock) k_csr_l1_resid(int n, const int32_t *_
 
 // ---- sliced copies of large CSR matrices --------------------------------------------
 // Matrices of at least kSellRows rows (bo_cpr_opts.sell_rows) are also kept
-// in SELL-64 form: one
-// thread per row then reads its entries with every load of a wavefront on
-// 64 consecutive words, where the lanes-per-row form reads short runs of a
-// row each (a level of 11M rows with 40 entries a row streamed at about 2
-// TB/s).  The row sums run in entry order.
+// in SELL-C form (C = 64 or 16 rows per slice, see SellMat): one thread per
+// row then reads its entries with every load of a wavefront on runs of C
+// consecutive words, where the lanes-per-row form reads short runs of a row
+// each (a level of 11M rows with 40 entries a row streamed at about 2 TB/s).
+// The row sums run in entry order.
 constexpr int kSellRows = 1 << 20;
-// the width of each slice (times 64): its longest row, or in a stencil slice
-// (a grid's cell rows, see SellGrid) 7 + the most entries a row has beyond
-// its stencil neighbours
-// (a wavefront per slice: one lane per row, the maximum by shuffles)
+// the width of each slice (times C): its longest row, or in a stencil slice
+// (a grid's cell rows, see SellGrid; C = 64) 7 + the most entries a row has
+// beyond its stencil neighbours (one lane per row, the maximum by shuffles
+// over the slice's C lanes)
+template <int C>
 __global__ void k_csr_slice_width(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                   SellGrid G, int32_t *__restrict__ w64) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x, S = r / 64;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x, S = r / C;
     int len = 0;
     if (r < n) {
         len = rp[r + 1] - rp[r];
-        if (sell_stencil_slice(G, S)) {
+        if (C == 64 && sell_stencil_slice(G, S)) {
             int nb[NSLOT], extra = 0;
             sell_stencil_nbrs(G, r, nb);
             for (int e = rp[r]; e < rp[r + 1]; e++) extra += sell_slot_in(nb, ci[e]) < 0;
             len = NSLOT + extra;
         }
     }
-    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
-    if (threadIdx.x % 64 == 0 && 64 * S < n) w64[S] = 64 * len;
+    for (int off = C / 2; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, C));
+    if (threadIdx.x % C == 0 && C * S < n) w64[S] = C * len;
 }
+template <int C>
 __global__ void k_csr_sell_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                 const double *__restrict__ v, const int32_t *__restrict__ off, SellGrid G,
                                 int32_t *__restrict__ col, double *__restrict__ val) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const int S = r / 64, lane = r % 64;
-    const int base = off[S] + lane, w = (off[S + 1] - off[S]) / 64;
+    const int S = r / C, lane = r % C;
+    const int base = off[S] + lane, w = (off[S + 1] - off[S]) / C;
     const int b = rp[r], len = rp[r + 1] - b;
-    if (sell_stencil_slice(G, S)) {
+    if (C == 64 && sell_stencil_slice(G, S)) {
         // stencil positions (zero where the row lacks the entry) on their
         // implicit columns, then the other entries; padding on the row's own
         // column
         for (int p = 0; p < w; p++) {
-            col[base + 64 * p] = p < NSLOT ? sell_stencil_col(G, r, p, n) : r;
-            val[base + 64 * p] = 0.0;
+            col[base + C * p] = p < NSLOT ? sell_stencil_col(G, r, p, n) : r;
+            val[base + C * p] = 0.0;
         }
         int nb[NSLOT];
         sell_stencil_nbrs(G, r, nb);
@@ -1530,8 +1532,8 @@ __global__ void k_csr_sell_fill(int n, const int32_t *__restrict__ rp, const int
             const int c = ci[b + q];
             int p = sell_slot_in(nb, c);
             if (p < 0) p = next++;
-            col[base + 64 * p] = c;
-            val[base + 64 * p] = v[b + q];
+            col[base + C * p] = c;
+            val[base + C * p] = v[b + q];
         }
         return;
     }
@@ -1539,12 +1541,12 @@ __global__ void k_csr_sell_fill(int n, const int32_t *__restrict__ rp, const int
     // P and R too; column 0 for an empty row) with value 0
     const int pad = len > 0 ? ci[b] : 0;
     for (int p = 0; p < w; p++) {
-        col[base + 64 * p] = p < len ? ci[b + p] : pad;
-        val[base + 64 * p] = p < len ? v[b + p] : 0.0;
+        col[base + C * p] = p < len ? ci[b + p] : pad;
+        val[base + C * p] = p < len ? v[b + p] : 0.0;
     }
 }
 // y = op(A x) as k_csr_rowop, for OP_MV, OP_RESID, OP_ADD and OP_L1
-template <typename T>
+template <typename T, int C>
 __global__ void __launch_bounds__(kBlock) k_sell_rowop(int n, const int32_t *__restrict__ off,
                                                        const int32_t *__restrict__ col, const T *__restrict__ val,
                                                        SellGrid G, const T *__restrict__ x, int op,
@@ -1552,15 +1554,15 @@ __global__ void __launch_bounds__(kBlock) k_sell_rowop(int n, const int32_t *__r
                                                        T *__restrict__ y) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const int S = r / 64, lane = r % 64;
-    const int base = off[S] + lane, w = (off[S + 1] - off[S]) / 64;
+    const int S = r / C, lane = r % C;
+    const int base = off[S] + lane, w = (off[S + 1] - off[S]) / C;
     T s = 0;
     int p0 = 0;
-    if (sell_stencil_slice(G, S)) {
+    if (C == 64 && sell_stencil_slice(G, S)) {
         // the stencil positions: columns from the row index, loads issued together
         T a[NSLOT], xv[NSLOT];
 #pragma unroll
-        for (int p = 0; p < NSLOT; p++) a[p] = val[base + 64 * p];
+        for (int p = 0; p < NSLOT; p++) a[p] = val[base + C * p];
 #pragma unroll
         for (int p = 0; p < NSLOT; p++) xv[p] = x[sell_stencil_col(G, r, p, n)];
 #pragma unroll
@@ -1568,7 +1570,7 @@ __global__ void __launch_bounds__(kBlock) k_sell_rowop(int n, const int32_t *__r
         p0 = NSLOT;
     }
 #pragma unroll 4
-    for (int p = p0; p < w; p++) s = s + val[base + 64 * p] * x[col[base + 64 * p]];
+    for (int p = p0; p < w; p++) s = s + val[base + C * p] * x[col[base + C * p]];
     switch (op) {
     case OP_MV: y[r] = s; break;
     case OP_RESID: y[r] = b[r] - s; break;
@@ -1620,11 +1622,13 @@ static bo_status sell_from_csr(SellMat &M, int n, const int32_t *rp, const int32
                                int min_rows, DBuf<int32_t> &work, hipStream_t s, const SellGrid &G = SellGrid{}) {
     M.on = false;
     M.grid = G;
+    M.c = G.rows > 0 ? 64 : 16;
     if (n < 1 || n < min_rows) return BO_OK;
-    const int nsl = (n + 63) / 64;
+    const int nsl = (n + M.c - 1) / M.c;
     BO_TRY(work.alloc(nsl));
     BO_TRY(M.off.alloc(nsl + 1));
-    k_csr_slice_width<<<grid_for(64LL * nsl), kBlock, 0, s>>>(n, rp, ci, G, work.p);
+    if (M.c == 64) k_csr_slice_width<64><<<grid_for(64LL * nsl), kBlock, 0, s>>>(n, rp, ci, G, work.p);
+    else k_csr_slice_width<16><<<grid_for(16LL * nsl), kBlock, 0, s>>>(n, rp, ci, G, work.p);
     // the padded size in 64 bits first: the prefix sum is 32-bit
     std::vector<int32_t> w(nsl);
     BO_HIP(hipMemcpyAsync(w.data(), work.p, sizeof(int32_t) * nsl, hipMemcpyDeviceToHost, s));
@@ -1636,7 +1640,8 @@ static bo_status sell_from_csr(SellMat &M, int n, const int32_t *rp, const int32
     BO_TRY(scan_counts(work.p, M.off.p, nsl, &total, s));
     BO_TRY(M.col.alloc(total));
     BO_TRY(M.val.alloc(total));
-    k_csr_sell_fill<<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, M.off.p, G, M.col.p, M.val.p);
+    if (M.c == 64) k_csr_sell_fill<64><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, M.off.p, G, M.col.p, M.val.p);
+    else k_csr_sell_fill<16><<<grid_for(n), kBlock, 0, s>>>(n, rp, ci, v, M.off.p, G, M.col.p, M.val.p);
     BO_HIP(hipGetLastError());
     M.len = total;
     M.on = true;
@@ -1653,8 +1658,12 @@ static bo_status csr_rowop(int n, int nnz, const int32_t *rp, const int32_t *ci,
                            const T *b, const int32_t *dpos, T *y, hipStream_t s, const T *dl1 = nullptr,
                            const SellMat *sm = nullptr) {
     if (sm && sm->on && (op == OP_MV || op == OP_RESID || op == OP_ADD || op == OP_L1)) {
-        k_sell_rowop<T><<<grid_for(n), kBlock, 0, s>>>(n, sm->off.p, sm->col.p, sell_val<T>(*sm), sm->grid, x, op,
-                                                      b, dl1, y);
+        if (sm->c == 64)
+            k_sell_rowop<T, 64><<<grid_for(n), kBlock, 0, s>>>(n, sm->off.p, sm->col.p, sell_val<T>(*sm), sm->grid,
+                                                               x, op, b, dl1, y);
+        else
+            k_sell_rowop<T, 16><<<grid_for(n), kBlock, 0, s>>>(n, sm->off.p, sm->col.p, sell_val<T>(*sm), sm->grid,
+                                                               x, op, b, dl1, y);
         BO_HIP(hipGetLastError());
         return BO_OK;
     }

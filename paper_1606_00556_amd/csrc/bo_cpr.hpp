@@ -12,13 +12,18 @@ constexpr int kNatExtraRows = 4096;
 
 // One level of the aggregation hierarchy: CSR operator (ascending columns),
 // and for every level but the coarsest the transfer operators to the next.
-// A CSR matrix of many rows also kept sliced (SELL-64): slices of 64 rows,
-// each entry position of a slice stored for its 64 rows together (column
+// A CSR matrix of many rows also kept sliced (SELL-C): slices of c rows,
+// each entry position of a slice stored for its c rows together (column
 // indices and values), rows shorter than the slice's longest padded with
-// (their first column, 0).  off[S] is slice S's first element (64 x the widths of
-// the slices before it).
+// (their first column, 0).  off[S] is slice S's first element (c x the widths of
+// the slices before it).  c = 64 (one wavefront per slice) for level 0 of a
+// grid, whose stencil slices keep implicit columns; c = 16 for the others,
+// whose rows vary in length (aggregates), so that a slice pads to the longest
+// of 16 rows rather than of 64 (a wavefront then reads four slices, each
+// position as four runs of 16 consecutive values).
 struct SellMat {
     bool on = false;
+    int c = 64;                   // rows per slice
     long long len = 0;            // stored elements (padding included)
     SellGrid grid{};              // level 0 of a grid: stencil slices with implicit columns
     DBuf<int32_t> off, col;
