@@ -529,8 +529,11 @@ __device__ __forceinline__ bool p_takes(int e, int i, const int32_t *ci, const u
 
 // Row data of the prolongator: the aggregate J of each entry that takes part
 // ({i} and the strong neighbours, aggregated) or -1, and its filtered value.
-constexpr int KP = 16;  // register fast path for rows of up to KP entries
-
+// Register fast path for rows of up to KP entries (8 on levels of at most 8
+// entries a row on average, else 16: the fully unrolled first-appearance
+// and rank loops grow with the cube of KP); longer rows go to k_p_long,
+// which forms the same sums in the same order.
+template <int KP>
 __global__ void k_p_count(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                           const uint8_t *__restrict__ sf, const int32_t *__restrict__ agg,
                           int32_t *__restrict__ cnt, int32_t *__restrict__ plong) {
@@ -573,6 +576,7 @@ __global__ void k_p_count(int n, const int32_t *__restrict__ rp, const int32_t *
 // P row i: for each distinct aggregate J among {i} and its strong neighbours,
 // (agg(i)==J) - omega/aF_ii * sum_{agg(j)=J} aF_ij (sums in ascending j),
 // stored in ascending J.
+template <int KP>
 __global__ void k_p_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                          const double *__restrict__ v, const uint8_t *__restrict__ sf,
                          const int32_t *__restrict__ agg, const double *__restrict__ aF,
@@ -2088,7 +2092,9 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s, const std::function<bo_status()> 
         const double *omega = W.omg.p + l;
         BO_TRY(W.plong.alloc(n + 1));
         k_omega<<<1, 1, 0, s>>>(rho.p, W.omg.p + l, W.dfl.p + 2, W.plong.p);
-        k_p_count<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, L.agg.p, cnt.p, W.plong.p);
+        const bool kp8 = L.nnz <= 8LL * n;
+        if (kp8) k_p_count<8><<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, L.agg.p, cnt.p, W.plong.p);
+        else k_p_count<16><<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.sf.p, L.agg.p, cnt.p, W.plong.p);
         // the listed long rows, a wavefront each up to 65536 of them
         const unsigned pgrid = (unsigned)std::min<long long>((n + kPWaves - 1) / kPWaves, 16384);
         k_p_long<<<pgrid, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega, nullptr,
@@ -2100,8 +2106,12 @@ bo_status amg_setup(bo_cpr *pc, hipStream_t s, const std::function<bo_status()> 
         BO_TRY(scan_counts(cnt.p, L.prp.p, n, &pnnz, s));
         L.pnnz = pnnz;
         BO_TRY(L.pci.alloc(pnnz)); BO_TRY(L.pv.alloc(pnnz));
-        k_p_fill<<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega,
-                                                L.prp.p, L.pci.p, L.pv.p);
+        if (kp8)
+            k_p_fill<8><<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega,
+                                                       L.prp.p, L.pci.p, L.pv.p);
+        else
+            k_p_fill<16><<<grid_for(n), kBlock, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega,
+                                                        L.prp.p, L.pci.p, L.pv.p);
         k_p_long<<<pgrid, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega, L.prp.p,
                                                 L.pci.p, L.pv.p, nullptr, flag, W.plong.p);
         k_p_vlong<<<pgrid, 64 * kPWaves, 0, s>>>(n, L.rp.p, L.ci.p, L.v.p, L.sf.p, L.agg.p, aF.p, omega, L.prp.p,
