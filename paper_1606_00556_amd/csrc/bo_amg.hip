@@ -816,11 +816,13 @@ __global__ void __launch_bounds__(kBlock) k_sort_rows(int n, const int32_t *__re
 // [0] the largest product count, [1] rows above kLongProducts, [2] rows above
 // kVeryLongProducts, [3] the largest count at or below kLongProducts, [4] the
 // largest count at or below kVeryLongProducts, [5] rows above
-// kShortProducts, [6] the largest count at or below kShortProducts
+// kShortProducts, [6] the largest count at or below kShortProducts, [7] rows
+// above kMidProducts, [8] the largest count at or below kMidProducts
 constexpr int kShortProducts = 32;
 constexpr int kLongProducts = 128;
+constexpr int kMidProducts = 256;
 constexpr int kVeryLongProducts = 512;
-constexpr int kBoundWords = 7;
+constexpr int kBoundWords = 9;
 __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *__restrict__ arp,
                                                          const int32_t *__restrict__ aci,
                                                          const int32_t *__restrict__ brp, int32_t *__restrict__ prod,
@@ -847,7 +849,8 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *_
     }
     int r[kBoundWords] = {c, c > kLongProducts ? 1 : 0, c > kVeryLongProducts ? 1 : 0,
                           c <= kLongProducts ? c : 0, c <= kVeryLongProducts ? c : 0,
-                          c > kShortProducts ? 1 : 0, c <= kShortProducts ? c : 0};
+                          c > kShortProducts ? 1 : 0, c <= kShortProducts ? c : 0,
+                          c > kMidProducts ? 1 : 0, c <= kMidProducts ? c : 0};
     for (int off = 32; off > 0; off >>= 1) {
         r[0] = max(r[0], __shfl_xor(r[0], off, 64));
         r[1] += __shfl_xor(r[1], off, 64);
@@ -856,12 +859,14 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *_
         r[4] = max(r[4], __shfl_xor(r[4], off, 64));
         r[5] += __shfl_xor(r[5], off, 64);
         r[6] = max(r[6], __shfl_xor(r[6], off, 64));
+        r[7] += __shfl_xor(r[7], off, 64);
+        r[8] = max(r[8], __shfl_xor(r[8], off, 64));
     }
     if (threadIdx.x % 64 == 0)
         for (int q = 0; q < kBoundWords; q++) wred[q][threadIdx.x / 64] = r[q];
     __syncthreads();
     if (threadIdx.x == 0) {
-        int m[kBoundWords] = {0, 0, 0, 0, 0, 0, 0};
+        int m[kBoundWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int w = 0; w < (int)(blockDim.x / 64); w++) {
             m[0] = max(m[0], wred[0][w]);
             m[1] += wred[1][w];
@@ -870,6 +875,8 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *_
             m[4] = max(m[4], wred[4][w]);
             m[5] += wred[5][w];
             m[6] = max(m[6], wred[6][w]);
+            m[7] += wred[7][w];
+            m[8] = max(m[8], wred[8][w]);
         }
         const int slot = blockIdx.x % kRedSlots;
         if (m[0] > 0) atomicMax(&stat[slot], m[0]);
@@ -879,6 +886,8 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_bound(int n, const int32_t *_
         if (m[4] > 0) atomicMax(&stat[4 * kRedSlots + slot], m[4]);
         if (m[5] > 0) atomicAdd(&stat[5 * kRedSlots + slot], m[5]);
         if (m[6] > 0) atomicMax(&stat[6 * kRedSlots + slot], m[6]);
+        if (m[7] > 0) atomicAdd(&stat[7 * kRedSlots + slot], m[7]);
+        if (m[8] > 0) atomicMax(&stat[8 * kRedSlots + slot], m[8]);
     }
 }
 
@@ -1833,7 +1842,7 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     int32_t stat[kBoundWords * kRedSlots] = {};
     HostRead rd{W.sg_stat.p, sizeof stat, stat};
     BO_TRY(host_reads(&rd, 1, s));
-    int red[kBoundWords] = {0, 0, 0, 0, 0, 0, 0};
+    int red[kBoundWords] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int q = 0; q < kRedSlots; q++) {
         red[0] = std::max(red[0], stat[q]);
         red[1] += stat[kRedSlots + q];
@@ -1842,20 +1851,26 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         red[4] = std::max(red[4], stat[4 * kRedSlots + q]);
         red[5] += stat[5 * kRedSlots + q];
         red[6] = std::max(red[6], stat[6 * kRedSlots + q]);
+        red[7] += stat[7 * kRedSlots + q];
+        red[8] = std::max(red[8], stat[8 * kRedSlots + q]);
     }
     const int bound = red[0];
     // counting pass: lanes per row and hash slots from the row's products
-    auto pick = [](int b) { return b <= 32 ? 0 : b <= 64 ? 4 : b <= 128 ? 1 : b <= 512 ? 2 : 3; };
-    auto count_slots = [](int sel) { return sel == 0 ? 64 : sel == 4 ? 128 : sel == 1 ? 256 : sel == 2 ? 1024 : 2048; };
+    auto pick = [](int b) { return b <= 32 ? 0 : b <= 64 ? 4 : b <= 128 ? 1 : b <= 256 ? 5 : b <= 512 ? 2 : 3; };
+    auto count_slots = [](int sel) {
+        return sel == 0 ? 64 : sel == 4 ? 128 : sel == 1 ? 256 : sel == 5 ? 512 : sel == 2 ? 1024 : 2048;
+    };
     // split when the long rows are few (below 1 %): at 32 products if the
     // longest row would otherwise take more than 8 lanes (a grid's level 0
     // next to long well rows: 8 lanes and a 64-slot hash for the others),
-    // else at 128, else at 512
+    // else at 128, else at 256, else at 512
     int limit = 0, nlong = 0, bound_rest = bound;
     if (bound > 2 * kShortProducts && (long long)red[5] * 100 < n) {
         limit = kShortProducts; nlong = red[5]; bound_rest = red[6];
     } else if (bound > kLongProducts && (long long)red[1] * 100 < n) {
         limit = kLongProducts; nlong = red[1]; bound_rest = red[3];
+    } else if (bound > kMidProducts && (long long)red[7] * 100 < n) {
+        limit = kMidProducts; nlong = red[7]; bound_rest = red[8];
     } else if (bound > kVeryLongProducts && (long long)red[2] * 100 < n) {
         limit = kVeryLongProducts; nlong = red[2]; bound_rest = red[4];
     }
@@ -1876,6 +1891,7 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         case 0: BO_SPGEMM_COUNT(8, 64); break;
         case 4: BO_SPGEMM_COUNT(8, 128); break;
         case 1: BO_SPGEMM_COUNT(16, 256); break;
+        case 5: BO_SPGEMM_COUNT(32, 512); break;
         case 2: if (g32) BO_SPGEMM_COUNT(32, 1024); else BO_SPGEMM_COUNT(64, 1024); break;
         default: if (g32) BO_SPGEMM_COUNT(32, 2048); else BO_SPGEMM_COUNT(64, 2048); break;
         }
