@@ -1948,14 +1948,25 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
     // A few rows of many distinct columns (a well's) would size every row's
     // hash: below 10 % of the rows they are listed and take a launch of their
     // own, the others a hash for kFewDistinct columns.
+    // Without a split by products the threshold is 64 distinct columns, or,
+    // on products of 2^17 rows and more, 128 where more than 10 % of the rows
+    // have over 64 (a coarse level's Galerkin product: a 256-slot hash for
+    // the others instead of one sized by the longest row; on fewer rows the
+    // extra list and read cost more than they save).
     constexpr int kFewDistinct = 64;
-    int nbig = 0;
+    int nbig = 0, dlim = kFewDistinct;
     if (!split && lmax > kFewDistinct) {
         int32_t *pos = W.sg_stat.p + kPos;  // unused without the products split
         BO_TRY(W.sg_rows.alloc(n));
-        k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, cnt.p, kFewDistinct, W.sg_rows.p, pos);
-        HostRead rb{pos, sizeof nbig, &nbig};
-        BO_TRY(host_reads(&rb, 1, s));
+        const int dmaxl = n >= (1 << 17) ? 2 * kFewDistinct : kFewDistinct;
+        for (int dl = kFewDistinct; dl <= dmaxl && lmax > dl; dl *= 2) {
+            BO_HIP(hipMemsetAsync(pos, 0, sizeof(int32_t), s));
+            k_spgemm_long_rows<<<grid_for(n), kBlock, 0, s>>>(n, cnt.p, dl, W.sg_rows.p, pos);
+            HostRead rb{pos, sizeof nbig, &nbig};
+            BO_TRY(host_reads(&rb, 1, s));
+            dlim = dl;
+            if ((long long)nbig * 10 < n) break;
+        }
     }
     // The same after a split by products: the rows of few products whose
     // distinct columns are many (next to a long row) take a launch of their
@@ -1973,7 +1984,7 @@ static bo_status spgemm(int n, const int32_t *arp, const int32_t *aci, const dou
         BO_TRY(host_reads(&rb, 1, s));
     }
     if (nbig > 0 && (long long)nbig * 10 < n) {
-        numeric(sel_all, n, nullptr, cnt.p, kFewDistinct, kFewDistinct);
+        numeric(sel_all, n, nullptr, cnt.p, dlim, dlim);
         numeric(sel_all, nbig, W.sg_rows.p, nullptr, 0, lmax);
     } else if (nbig2 > 0 && (long long)nbig2 * 10 < n) {
         numeric(sel_all, n, nullptr, W.sg_key.p, 0, kFewDistinct);
