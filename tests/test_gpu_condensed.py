@@ -200,6 +200,18 @@ def test_hierarchy_is_galerkin_at_scale(B, scale):
     the benchmark's options: the sparse products there take the split
     launches (rows of many products or many distinct columns, next to the
     wells) that small cases never reach."""
+    check_galerkin(B, scale)
+
+
+def test_coarse_hierarchy_is_galerkin_at_full_size(B):
+    """The same at the workload's full size (16M reduced rows) for the levels
+    below the finest: level 1's product R A P has over 2^17 rows, the size
+    from which rows of over 128 distinct columns take a launch of their own."""
+    check_galerkin(B, 1, first_level=1)
+
+
+def check_galerkin(B, scale, first_level=0):
+    """P^T A P against the GPU's coarse operators from level first_level on."""
     import scipy.sparse as sp
     import torch
     from bench import bench_cpr_kw
@@ -212,8 +224,8 @@ def test_hierarchy_is_galerkin_at_scale(B, scale):
     pc = B.bo_cpr_setup(J, (case.nx, case.ny, case.nz, 1), opts)
     nlev = B.bo_cpr_levels(pc)
     assert nlev >= 3
-    lv = [B.bo_cpr_level_copy(pc, l) for l in range(nlev)]
-    for l in range(nlev - 1):
+    lv = [B.bo_cpr_level_copy(pc, l) if l >= first_level else None for l in range(nlev)]
+    for l in range(first_level, nlev - 1):
         n, nc = lv[l]["n"], lv[l + 1]["n"]
         A = sp.csr_matrix((lv[l]["val"], lv[l]["colind"], lv[l]["rowptr"]), shape=(n, n))
         P = sp.csr_matrix((lv[l]["p_val"], lv[l]["p_colind"], lv[l]["p_rowptr"]), shape=(n, nc))
